@@ -1,0 +1,686 @@
+/*
+ * oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, FP64 CPU reference for supernodal selected inversion
+ * (Jacquelin, Lin, Yang: "PSelInv -- a distributed memory parallel algorithm
+ * for selected inversion: the symmetric case", ACM TOMS).  Only the tests,
+ * the smoke check and the CPU-baseline leg of the benchmark may load it; the
+ * product path never does.  It shares no code, header or table with the HIP
+ * library: both sides only read the same generated matrices.
+ *
+ * Tiers:
+ *   O1  orc_dense_inverse   -- A^{-1} by an LDL^T factorization and n
+ *                              triangular solves (Section 2.1, the
+ *                              "direct inversion" of equation (2.3)).
+ *   O2  orc_selinv_columns  -- dense LDL^T then the scalar (column)
+ *                              recurrence obtained from the 2x2 block form
+ *                              (Section 2.1, equations (2.5)-(2.8)).
+ *   O3  orc_factor_selinv   -- supernodal LDL^T, then Algorithm 1 with the
+ *                              symmetric simplifications of Section 2.1
+ *                              (U_hat = L_hat^T, LDL^T diagonal term,
+ *                              symmetrised diagonal block), root first.
+ *   sym orc_symbolic        -- nested-dissection order (geometric reading),
+ *                              column structures by definition, elimination
+ *                              tree (Section 2.2), fundamental supernodes
+ *                              capped in size (Section 2.1), priority
+ *                              levels of Algorithm 2 and block index maps.
+ *   grad orc_dense_grad     -- dense reference gradient of a weighted sum of
+ *                              selected entries: -(A^{-1} S A^{-1}).
+ *
+ * Everything is FP64, round to nearest; no blocking or reordering beyond the
+ * formulas.  OpenMP only splits independent loop iterations.
+ *
+ * Readings where the paper is silent:
+ *   - ordering: recursive coordinate bisection of the grid box (longest axis,
+ *     ties to the lowest axis, separator plane at lo + floor(ext/2); left
+ *     half, right half, then the plane in lexicographic order, x fastest);
+ *   - supernodes: fundamental (column j+1 joins j iff j is its only child and
+ *     struct(j) = {j+1} U struct(j+1)), split when a supernode reaches `cap`;
+ *   - D has 1x1 blocks, no pivoting (Section 4 uses none); a pivot that is
+ *     zero, not finite, or (when SPD is required) not positive is reported.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef int64_t i64;
+
+/* Planted-mistake switch used only by the tests that show the pins catch
+ * errors.  0 = correct code. */
+static int g_mut = 0;
+void orc_set_mutation(int m) { g_mut = m; }
+int orc_get_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------ */
+/* Nested dissection over a box of grid points                         */
+/* ------------------------------------------------------------------ */
+static void nd_box(const int lo[3], const int hi[3], const int full[3], int dofs,
+                   int* perm, i64* pos)
+{
+    int ext[3];
+    for (int k = 0; k < 3; k++) ext[k] = hi[k] - lo[k];
+    if (ext[0] <= 0 || ext[1] <= 0 || ext[2] <= 0) return;
+    int d = 0;
+    for (int k = 1; k < 3; k++)
+        if (ext[k] > ext[d]) d = k;
+    int mid = lo[d] + ext[d] / 2;
+    int l2[3], h2[3];
+    memcpy(l2, lo, sizeof l2);
+    memcpy(h2, hi, sizeof h2);
+    h2[d] = mid;
+    nd_box(l2, h2, full, dofs, perm, pos);
+    memcpy(h2, hi, sizeof h2);
+    l2[d] = mid + 1;
+    nd_box(l2, h2, full, dofs, perm, pos);
+    memcpy(l2, lo, sizeof l2);
+    l2[d] = mid;
+    h2[d] = mid + 1;
+    for (int z = l2[2]; z < h2[2]; z++)
+        for (int y = l2[1]; y < h2[1]; y++)
+            for (int x = l2[0]; x < h2[0]; x++) {
+                i64 pt = (i64)x + (i64)full[0] * ((i64)y + (i64)full[1] * z);
+                for (int b = 0; b < dofs; b++) perm[(*pos)++] = (int)(pt * dofs + b);
+            }
+}
+
+/* perm[new] = old.  Returns the number of unknowns. */
+i64 orc_nd_order(int ndim, const int* dims, int dofs, int* perm)
+{
+    int full[3] = {1, 1, 1};
+    for (int k = 0; k < ndim && k < 3; k++) full[k] = dims[k];
+    int lo[3] = {0, 0, 0};
+    i64 pos = 0;
+    nd_box(lo, full, full, dofs, perm, &pos);
+    return pos;
+}
+
+/* ------------------------------------------------------------------ */
+/* Symbolic analysis                                                   */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int n, N, cap;
+    int* perm;    /* new -> old */
+    int* iperm;   /* old -> new */
+    int* parent;  /* column elimination tree, -1 = root */
+    i64* sptr;    /* struct(j) = srow[sptr[j] .. sptr[j+1]), rows > j, sorted */
+    int* srow;
+    int* xsuper;  /* supernode K = columns xsuper[K] .. xsuper[K+1]-1 */
+    int* sn;      /* column -> supernode */
+    int* sparent; /* supernodal tree */
+    int* level;   /* priority number of Algorithm 2 (root = 1) */
+    i64* poff;    /* panel offsets, panel K is (s+c) x s column-major */
+    i64 arena;
+    /* block index maps: per supernode a flat list of segments
+     * [J, a, pos(C[a]), pos(C[a+1]), ..., pos(C[c-1])] */
+    i64* rptr;
+    int* rel;
+    int err;
+} orc_sym;
+
+static int cmp_int(const void* a, const void* b)
+{
+    int x = *(const int*)a, y = *(const int*)b;
+    return (x > y) - (x < y);
+}
+
+static inline int sn_s(const orc_sym* S, int K) { return S->xsuper[K + 1] - S->xsuper[K]; }
+static inline const int* sn_C(const orc_sym* S, int K) { return S->srow + S->sptr[S->xsuper[K + 1] - 1]; }
+static inline int sn_c(const orc_sym* S, int K)
+{
+    int j = S->xsuper[K + 1] - 1;
+    return (int)(S->sptr[j + 1] - S->sptr[j]);
+}
+
+/* position of global row r in rows(J) = cols(J) U C(J); -1 if absent */
+static int row_pos(const orc_sym* S, int J, int r)
+{
+    int f = S->xsuper[J], l = S->xsuper[J + 1];
+    if (r >= f && r < l) return r - f;
+    const int* C = sn_C(S, J);
+    int c = sn_c(S, J);
+    int lo = 0, hi = c;
+    while (lo < hi) {
+        int m = (lo + hi) / 2;
+        if (C[m] < r) lo = m + 1; else hi = m;
+    }
+    if (lo < c && C[lo] == r) return (l - f) + lo;
+    return -1;
+}
+
+void orc_sym_free(orc_sym* S)
+{
+    if (!S) return;
+    free(S->perm); free(S->iperm); free(S->parent); free(S->sptr); free(S->srow);
+    free(S->xsuper); free(S->sn); free(S->sparent); free(S->level); free(S->poff);
+    free(S->rptr); free(S->rel);
+    free(S);
+}
+
+/* Build the symbolic structure of L for the lower CSC pattern (colptr,
+ * rowind) of A in original numbering, under perm (new -> old; NULL =
+ * identity). */
+orc_sym* orc_symbolic(int n, const i64* colptr, const int* rowind, const int* perm, int cap)
+{
+    orc_sym* S = (orc_sym*)calloc(1, sizeof(orc_sym));
+    S->n = n;
+    S->cap = cap > 0 ? cap : n;
+    S->perm = (int*)malloc(sizeof(int) * (n > 0 ? n : 1));
+    S->iperm = (int*)malloc(sizeof(int) * (n > 0 ? n : 1));
+    for (int k = 0; k < n; k++) S->perm[k] = perm ? perm[k] : k;
+    for (int k = 0; k < n; k++) S->iperm[k] = -1;
+    for (int k = 0; k < n; k++) {
+        int o = S->perm[k];
+        if (o < 0 || o >= n || S->iperm[o] != -1) { S->err = 1; return S; }
+        S->iperm[o] = k;
+    }
+    /* permuted off-diagonal lower pattern: adj[j] = {i > j : B_ij != 0} */
+    i64 nnz = colptr[n];
+    i64* acnt = (i64*)calloc((size_t)n + 1, sizeof(i64));
+    for (int j = 0; j < n; j++)
+        for (i64 p = colptr[j]; p < colptr[j + 1]; p++) {
+            int i = rowind[p];
+            if (i < j || i >= n) { S->err = 2; free(acnt); return S; }
+            int a = S->iperm[i], b = S->iperm[j];
+            if (a == b) continue;
+            acnt[(a < b ? a : b) + 1]++;
+        }
+    for (int j = 0; j < n; j++) acnt[j + 1] += acnt[j];
+    int* adj = (int*)malloc(sizeof(int) * (size_t)(acnt[n] + 1));
+    i64* fill = (i64*)malloc(sizeof(i64) * ((size_t)n + 1));
+    memcpy(fill, acnt, sizeof(i64) * ((size_t)n + 1));
+    for (int j = 0; j < n; j++)
+        for (i64 p = colptr[j]; p < colptr[j + 1]; p++) {
+            int a = S->iperm[rowind[p]], b = S->iperm[j];
+            if (a == b) continue;
+            int lo = a < b ? a : b, hi = a < b ? b : a;
+            adj[fill[lo]++] = hi;
+        }
+    free(fill);
+    (void)nnz;
+
+    /* column structures by definition (Section 2.2):
+     * struct(j) = {i>j : B_ij != 0}  U  (U over children c of struct(c) \ {j}),
+     * parent(j) = min struct(j). */
+    S->parent = (int*)malloc(sizeof(int) * (n > 0 ? n : 1));
+    S->sptr = (i64*)malloc(sizeof(i64) * ((size_t)n + 1));
+    i64 capw = (i64)acnt[n] * 2 + 16;
+    S->srow = (int*)malloc(sizeof(int) * (size_t)capw);
+    int* mark = (int*)malloc(sizeof(int) * (n > 0 ? n : 1));
+    int* buf = (int*)malloc(sizeof(int) * (n > 0 ? n : 1));
+    int* chead = (int*)malloc(sizeof(int) * (n > 0 ? n : 1));
+    int* cnext = (int*)malloc(sizeof(int) * (n > 0 ? n : 1));
+    for (int j = 0; j < n; j++) { mark[j] = -1; chead[j] = -1; }
+    S->sptr[0] = 0;
+    for (int j = 0; j < n; j++) {
+        int m = 0;
+        for (i64 p = acnt[j]; p < acnt[j + 1]; p++) {
+            int i = adj[p];
+            if (mark[i] != j) { mark[i] = j; buf[m++] = i; }
+        }
+        if (g_mut != 7) {
+            for (int ch = chead[j]; ch >= 0; ch = cnext[ch])
+                for (i64 p = S->sptr[ch]; p < S->sptr[ch + 1]; p++) {
+                    int i = S->srow[p];
+                    if (i != j && mark[i] != j) { mark[i] = j; buf[m++] = i; }
+                }
+        }
+        qsort(buf, (size_t)m, sizeof(int), cmp_int);
+        if (S->sptr[j] + m > capw) {
+            while (S->sptr[j] + m > capw) capw *= 2;
+            S->srow = (int*)realloc(S->srow, sizeof(int) * (size_t)capw);
+        }
+        memcpy(S->srow + S->sptr[j], buf, sizeof(int) * (size_t)m);
+        S->sptr[j + 1] = S->sptr[j] + m;
+        S->parent[j] = m > 0 ? buf[0] : -1;
+        if (m > 0) { cnext[j] = chead[buf[0]]; chead[buf[0]] = j; }
+    }
+    free(adj); free(acnt); free(mark); free(buf);
+
+    /* fundamental supernodes, split at `cap` columns */
+    int* nchild = (int*)calloc((size_t)n + 1, sizeof(int));
+    for (int j = 0; j < n; j++)
+        if (S->parent[j] >= 0) nchild[S->parent[j]]++;
+    S->xsuper = (int*)malloc(sizeof(int) * ((size_t)n + 1));
+    S->sn = (int*)malloc(sizeof(int) * (n > 0 ? n : 1));
+    int N = 0, start = 0;
+    if (n > 0) S->xsuper[N++] = 0;
+    for (int j = 0; j + 1 < n; j++) {
+        int join = S->parent[j] == j + 1 && nchild[j + 1] == 1;
+        if (join) {
+            i64 cj = S->sptr[j + 1] - S->sptr[j], cn = S->sptr[j + 2] - S->sptr[j + 1];
+            join = (cj == cn + 1) && S->srow[S->sptr[j]] == j + 1;
+            for (i64 k = 1; join && k < cj; k++)
+                if (S->srow[S->sptr[j] + k] != S->srow[S->sptr[j + 1] + k - 1]) join = 0;
+        }
+        if (join && (j + 1 - start) >= S->cap) join = 0;
+        if (!join) { S->xsuper[N++] = j + 1; start = j + 1; }
+    }
+    S->xsuper[N] = n;
+    S->N = N;
+    free(nchild);
+    for (int K = 0; K < N; K++)
+        for (int j = S->xsuper[K]; j < S->xsuper[K + 1]; j++) S->sn[j] = K;
+    S->sparent = (int*)malloc(sizeof(int) * (N > 0 ? N : 1));
+    S->level = (int*)malloc(sizeof(int) * (N > 0 ? N : 1));
+    for (int K = 0; K < N; K++) {
+        int p = S->parent[S->xsuper[K + 1] - 1];
+        S->sparent[K] = p >= 0 ? S->sn[p] : -1;
+    }
+    /* Algorithm 2: sigma(root) = 1, sigma(I) = sigma(parent(I)) + 1 */
+    for (int K = N - 1; K >= 0; K--)
+        S->level[K] = S->sparent[K] < 0 ? 1 : S->level[S->sparent[K]] + 1;
+    /* panel layout */
+    S->poff = (i64*)malloc(sizeof(i64) * ((size_t)N + 1));
+    S->poff[0] = 0;
+    for (int K = 0; K < N; K++) {
+        i64 s = sn_s(S, K), c = sn_c(S, K);
+        S->poff[K + 1] = S->poff[K] + (s + c) * s;
+    }
+    S->arena = S->poff[N];
+    /* block index maps */
+    S->rptr = (i64*)malloc(sizeof(i64) * ((size_t)N + 1));
+    S->rptr[0] = 0;
+    for (int K = 0; K < N; K++) {
+        const int* C = sn_C(S, K);
+        int c = sn_c(S, K);
+        i64 tot = 0;
+        for (int r = 0; r < c;) {
+            int J = S->sn[C[r]];
+            tot += 2 + (c - r);
+            while (r < c && S->sn[C[r]] == J) r++;
+        }
+        S->rptr[K + 1] = S->rptr[K] + tot;
+    }
+    S->rel = (int*)malloc(sizeof(int) * (size_t)(S->rptr[N] + 1));
+    for (int K = 0; K < N; K++) {
+        const int* C = sn_C(S, K);
+        int c = sn_c(S, K);
+        i64 q = S->rptr[K];
+        for (int r = 0; r < c;) {
+            int J = S->sn[C[r]];
+            S->rel[q++] = J;
+            S->rel[q++] = r;
+            for (int t = r; t < c; t++) {
+                int p = row_pos(S, J, C[t]);
+                if (p < 0) S->err = 3;
+                S->rel[q++] = p;
+            }
+            while (r < c && S->sn[C[r]] == J) r++;
+        }
+    }
+    return S;
+}
+
+int orc_sym_error(const orc_sym* S) { return S->err; }
+int orc_sym_nsuper(const orc_sym* S) { return S->N; }
+i64 orc_sym_nnzL(const orc_sym* S) { return S->sptr[S->n] + S->n; }
+i64 orc_sym_relsize(const orc_sym* S) { return S->rptr[S->N]; }
+i64 orc_sym_arena(const orc_sym* S) { return S->arena; }
+
+void orc_sym_get(const orc_sym* S, int* perm, int* parent, int* xsuper, int* sparent, int* level,
+                 i64* cptr, int* crows)
+{
+    int n = S->n, N = S->N;
+    if (perm) memcpy(perm, S->perm, sizeof(int) * (size_t)n);
+    if (parent) memcpy(parent, S->parent, sizeof(int) * (size_t)n);
+    if (xsuper) memcpy(xsuper, S->xsuper, sizeof(int) * ((size_t)N + 1));
+    if (sparent) memcpy(sparent, S->sparent, sizeof(int) * (size_t)N);
+    if (level) memcpy(level, S->level, sizeof(int) * (size_t)N);
+    if (cptr) {
+        cptr[0] = 0;
+        for (int K = 0; K < N; K++) cptr[K + 1] = cptr[K] + sn_c(S, K);
+        if (crows)
+            for (int K = 0; K < N; K++) memcpy(crows + cptr[K], sn_C(S, K), sizeof(int) * (size_t)sn_c(S, K));
+    }
+}
+
+void orc_sym_rel(const orc_sym* S, i64* rptr, int* rel)
+{
+    memcpy(rptr, S->rptr, sizeof(i64) * ((size_t)S->N + 1));
+    memcpy(rel, S->rel, sizeof(int) * (size_t)S->rptr[S->N]);
+}
+
+/* canonical lower pattern of L in permuted numbering: column j holds j then
+ * struct(j), ascending */
+void orc_sym_pattern(const orc_sym* S, i64* colptrL, int* rowindL)
+{
+    i64 q = 0;
+    for (int j = 0; j < S->n; j++) {
+        colptrL[j] = q;
+        rowindL[q++] = j;
+        for (i64 p = S->sptr[j]; p < S->sptr[j + 1]; p++) rowindL[q++] = S->srow[p];
+    }
+    colptrL[S->n] = q;
+}
+
+/* work per supernode: gemm = 2c^2 s + 2 c s^2, factor = c^2 s + c s^2 + s^3/3 */
+void orc_sym_flops(const orc_sym* S, double* gemm, double* factor)
+{
+    double g = 0, f = 0;
+    for (int K = 0; K < S->N; K++) {
+        double s = sn_s(S, K), c = sn_c(S, K);
+        g += 2 * c * c * s + 2 * c * s * s;
+        f += c * c * s + c * s * s + s * s * s / 3.0;
+    }
+    *gemm = g;
+    *factor = f;
+}
+
+/* ------------------------------------------------------------------ */
+/* O3: supernodal LDL^T and selected inversion                         */
+/* ------------------------------------------------------------------ */
+
+/* segment lookup: for supernode K, pointer to the block index map of the
+ * segment containing position r of C(K), and that segment's start a */
+static const int* seg_of(const orc_sym* S, int K, int r, int* J, int* a)
+{
+    int c = sn_c(S, K);
+    i64 q = S->rptr[K];
+    for (;;) {
+        int JJ = S->rel[q], aa = S->rel[q + 1];
+        int len = c - aa;
+        /* the segment covers positions aa .. (next segment start - 1) */
+        i64 nq = q + 2 + len;
+        int nexta = nq < S->rptr[K + 1] ? S->rel[nq + 1] : c;
+        if (r >= aa && r < nexta) { *J = JJ; *a = aa; return S->rel + q + 2; }
+        q = nq;
+    }
+}
+
+/* Numerical supernodal LDL^T (leaves first), then Algorithm 1 (root first).
+ * valsA: values in the original CSC order given to orc_symbolic.
+ * sel:   nnz(L) values of A^{-1} on the canonical pattern (may be NULL).
+ * Lout:  nnz(L) values of L on the canonical pattern, D on the diagonal
+ *        (may be NULL).
+ * Returns 0, or -3 on a bad pivot with *bad_col = original column index. */
+int orc_factor_selinv(const orc_sym* S, const i64* colptr, const int* rowind, const double* valsA,
+                      int require_spd, double* sel, double* Lout, i64* bad_col, double* t_factor,
+                      double* t_selinv)
+{
+    int n = S->n, N = S->N;
+    double* Lp = (double*)calloc((size_t)S->arena + 1, sizeof(double));
+    double* Ai = (double*)calloc((size_t)S->arena + 1, sizeof(double));
+    if (!Lp || !Ai) { free(Lp); free(Ai); return -4; }
+    int bad = -1;
+    double t0 = 0;
+#ifdef _OPENMP
+    t0 = omp_get_wtime();
+#endif
+    /* assemble the permuted lower triangle into the panels */
+    for (int j = 0; j < n; j++)
+        for (i64 p = colptr[j]; p < colptr[j + 1]; p++) {
+            int a = S->iperm[rowind[p]], b = S->iperm[j];
+            int lo = a > b ? a : b, hi = a > b ? b : a;
+            int K = S->sn[hi];
+            i64 ld = sn_s(S, K) + sn_c(S, K);
+            int r = row_pos(S, K, lo);
+            Lp[S->poff[K] + r + (i64)(hi - S->xsuper[K]) * ld] += valsA[p];
+        }
+    /* factor, supernodes in increasing order (children before parents) */
+    for (int K = 0; K < N && bad < 0; K++) {
+        int s = sn_s(S, K), c = sn_c(S, K);
+        i64 ld = s + c;
+        double* F = Lp + S->poff[K];
+        /* column LDL^T of the whole panel: for j, d_j = F(j,j) - sum_k L(j,k)^2 d_k
+         * and L(i,j) = (F(i,j) - sum_k L(i,k) d_k L(j,k)) / d_j for rows i > j
+         * (diagonal block and C(K) rows alike; the C rows give
+         * L(C,K) = F(C,K) L_KK^{-T} D_K^{-1}). */
+        for (int j = 0; j < s; j++) {
+            double dj = F[j + j * ld];
+            for (int k = 0; k < j; k++) dj -= F[j + k * ld] * F[j + k * ld] * F[k + k * ld];
+            int ok = isfinite(dj) && dj != 0.0 && (!require_spd || dj > 0.0);
+            if (!ok) { bad = S->xsuper[K] + j; break; }
+            F[j + j * ld] = dj;
+#pragma omp parallel for schedule(static) if (ld > 512)
+            for (i64 i = j + 1; i < ld; i++) {
+                double v = F[i + j * ld];
+                for (int k = 0; k < j; k++) v -= F[i + k * ld] * F[k + k * ld] * F[j + k * ld];
+                F[i + j * ld] = v / dj;
+            }
+        }
+        if (bad >= 0) break;
+        if (c == 0) continue;
+        /* Schur complement update of the ancestors:
+         * F(C,C) -= L(C,K) D_K L(C,K)^T, added into the owning panels. */
+        const int* C = sn_C(S, K);
+#pragma omp parallel for schedule(dynamic, 4) if (c > 64)
+        for (int kk = 0; kk < c; kk++) {
+            int J, a;
+            const int* pos = seg_of(S, K, kk, &J, &a);
+            i64 ldJ = sn_s(S, J) + sn_c(S, J);
+            double* FJ = Lp + S->poff[J] + (i64)(C[kk] - S->xsuper[J]) * ldJ;
+            int i0 = (g_mut == 5) ? kk + 1 : kk;
+            for (int ii = i0; ii < c; ii++) {
+                double u = 0;
+                for (int t = 0; t < s; t++) u += F[s + ii + t * ld] * F[t + t * ld] * F[s + kk + t * ld];
+                FJ[pos[ii - a]] -= u;
+            }
+        }
+    }
+    double t1 = 0;
+#ifdef _OPENMP
+    t1 = omp_get_wtime();
+#endif
+    if (bad >= 0) {
+        if (bad_col) *bad_col = S->perm[bad];
+        free(Lp); free(Ai);
+        return -3;
+    }
+    /* Algorithm 1, K = N .. 1 (root first; parents have larger indices) */
+    for (int K = N - 1; K >= 0; K--) {
+        int s = sn_s(S, K), c = sn_c(S, K);
+        i64 ld = s + c;
+        const double* F = Lp + S->poff[K];
+        double* X = Ai + S->poff[K];
+        const int* C = sn_C(S, K);
+        double* Lh = (double*)malloc(sizeof(double) * ((size_t)c * s + 1));
+        /* step 2: L_hat(C,K) = L(C,K) L_KK^{-1}  (row-wise x L_KK = L(r,:)) */
+        for (int r = 0; r < c; r++)
+            for (int j = s - 1; j >= 0; j--) {
+                double v = F[s + r + (i64)j * ld];
+                if (g_mut != 3)
+                    for (int k = j + 1; k < s; k++) v -= Lh[r + (i64)k * c] * F[k + (i64)j * ld];
+                Lh[r + (i64)j * c] = v;
+            }
+        if (c > 0) {
+            /* step 1 + gather: G = Ainv(C,C) from the stored lower entries */
+            double* G = (double*)malloc(sizeof(double) * (size_t)c * c);
+#pragma omp parallel for schedule(dynamic, 4) if (c > 64)
+            for (int kk = 0; kk < c; kk++) {
+                int J, a;
+                const int* pos = seg_of(S, K, kk, &J, &a);
+                i64 ldJ = sn_s(S, J) + sn_c(S, J);
+                const double* AJ = Ai + S->poff[J] + (i64)(C[kk] - S->xsuper[J]) * ldJ;
+                for (int ii = kk; ii < c; ii++) {
+                    double g = AJ[pos[ii - a]];
+                    G[ii + (i64)kk * c] = g;
+                    G[kk + (i64)ii * c] = (g_mut == 4 && ii != kk) ? 0.0 : g;
+                }
+            }
+            /* step 3: Ainv(C,K) = -Ainv(C,C) L_hat(C,K) */
+#pragma omp parallel for schedule(static) if (c > 64)
+            for (int r = 0; r < c; r++)
+                for (int j = 0; j < s; j++) {
+                    double v = 0;
+                    for (int k = 0; k < c; k++) v += G[r + (i64)k * c] * Lh[k + (i64)j * c];
+                    X[s + r + (i64)j * ld] = (g_mut == 1) ? v : -v;
+                }
+            free(G);
+        }
+        /* step 4: Ainv(K,K) = U_KK^{-1} L_KK^{-1} - U_hat(K,C) Ainv(C,K),
+         * with U = D L^T and U_hat = L_hat^T.  T(:,j) solves L D L^T x = e_j. */
+        double* Y = (double*)malloc(sizeof(double) * (size_t)s * s);
+        double* y = (double*)malloc(sizeof(double) * (size_t)s);
+        for (int j = 0; j < s; j++) {
+            for (int i = 0; i < s; i++) y[i] = (i == j) ? 1.0 : 0.0;
+            for (int i = 0; i < s; i++)
+                for (int k = 0; k < i; k++) y[i] -= F[i + (i64)k * ld] * y[k];
+            for (int i = 0; i < s; i++) y[i] = (g_mut == 6) ? y[i] * F[i + (i64)i * ld] : y[i] / F[i + (i64)i * ld];
+            for (int i = s - 1; i >= 0; i--)
+                for (int k = i + 1; k < s; k++) y[i] -= F[k + (i64)i * ld] * y[k];
+            for (int i = 0; i < s; i++) Y[i + (i64)j * s] = (g_mut == 2) ? 0.0 : y[i];
+        }
+        for (int j = 0; j < s; j++)
+            for (int i = 0; i < s; i++) {
+                double v = 0;
+                for (int r = 0; r < c; r++) v += Lh[r + (i64)i * c] * X[s + r + (i64)j * ld];
+                Y[i + (i64)j * s] -= v;
+            }
+        /* symmetrise the diagonal block */
+        for (int j = 0; j < s; j++)
+            for (int i = 0; i < s; i++)
+                X[i + (i64)j * ld] = 0.5 * (Y[i + (i64)j * s] + Y[j + (i64)i * s]);
+        free(Y); free(y); free(Lh);
+    }
+    double t2 = 0;
+#ifdef _OPENMP
+    t2 = omp_get_wtime();
+#endif
+    if (t_factor) *t_factor = t1 - t0;
+    if (t_selinv) *t_selinv = t2 - t1;
+    /* export on the canonical pattern */
+    i64 q = 0;
+    for (int K = 0; K < N; K++) {
+        int s = sn_s(S, K), c = sn_c(S, K);
+        i64 ld = s + c;
+        for (int j = 0; j < s; j++)
+            for (i64 i = j; i < ld; i++) {
+                i64 o = S->poff[K] + i + (i64)j * ld;
+                if (sel) sel[q] = Ai[o];
+                if (Lout) Lout[q] = Lp[o];
+                q++;
+            }
+    }
+    free(Lp); free(Ai);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Dense tiers                                                          */
+/* ------------------------------------------------------------------ */
+
+/* in-place dense LDL^T of a symmetric n x n column-major matrix: on exit the
+ * strict lower triangle holds L (unit diagonal implied), the diagonal holds D.
+ * Returns the first bad column or -1. */
+static int dense_ldlt(int n, double* A)
+{
+    for (int j = 0; j < n; j++) {
+        double dj = A[j + (i64)j * n];
+        for (int k = 0; k < j; k++) dj -= A[j + (i64)k * n] * A[j + (i64)k * n] * A[k + (i64)k * n];
+        if (!isfinite(dj) || dj == 0.0) return j;
+        A[j + (i64)j * n] = dj;
+#pragma omp parallel for schedule(static) if (n > 256)
+        for (int i = j + 1; i < n; i++) {
+            double v = A[i + (i64)j * n];
+            for (int k = 0; k < j; k++) v -= A[i + (i64)k * n] * A[k + (i64)k * n] * A[j + (i64)k * n];
+            A[i + (i64)j * n] = v / dj;
+        }
+    }
+    return -1;
+}
+
+/* O1: A^{-1} by LDL^T and n triangular solves L y = e_j, D z = y, L^T x = z. */
+int orc_dense_inverse(int n, const double* A, double* Ainv)
+{
+    double* F = (double*)malloc(sizeof(double) * (size_t)n * n);
+    memcpy(F, A, sizeof(double) * (size_t)n * n);
+    int bad = dense_ldlt(n, F);
+    if (bad >= 0) { free(F); return -3; }
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int j = 0; j < n; j++) {
+        double* x = Ainv + (i64)j * n;
+        for (int i = 0; i < n; i++) x[i] = (i == j) ? 1.0 : 0.0;
+        for (int i = 0; i < n; i++)
+            for (int k = 0; k < i; k++) x[i] -= F[i + (i64)k * n] * x[k];
+        for (int i = 0; i < n; i++) x[i] /= F[i + (i64)i * n];
+        for (int i = n - 1; i >= 0; i--)
+            for (int k = i + 1; k < n; k++) x[i] -= F[k + (i64)i * n] * x[k];
+    }
+    free(F);
+    return 0;
+}
+
+/* O2: scalar recurrence on the pattern of L (canonical lower CSC, rows
+ * sorted, diagonal first) for a dense, already permuted A:
+ *   Ainv(C,j) = -Ainv(C,C) L(C,j),   Ainv(j,j) = 1/d_j - L(C,j)^T Ainv(C,j),
+ * for j = n-1 .. 0, C = struct(L(:,j)). */
+int orc_selinv_columns(int n, const double* A, const i64* colptrL, const int* rowindL, double* sel)
+{
+    double* F = (double*)malloc(sizeof(double) * (size_t)n * n);
+    memcpy(F, A, sizeof(double) * (size_t)n * n);
+    int bad = dense_ldlt(n, F);
+    if (bad >= 0) { free(F); return -3; }
+    double* Z = (double*)calloc((size_t)n * n, sizeof(double));
+    double* tmp = (double*)malloc(sizeof(double) * (size_t)n);
+    for (int j = n - 1; j >= 0; j--) {
+        i64 p0 = colptrL[j] + 1, p1 = colptrL[j + 1];
+        for (i64 p = p0; p < p1; p++) {
+            int i = rowindL[p];
+            double v = 0;
+            for (i64 q = p0; q < p1; q++) {
+                int k = rowindL[q];
+                v += Z[i + (i64)k * n] * F[k + (i64)j * n];
+            }
+            tmp[p - p0] = -v;
+        }
+        double d = 1.0 / F[j + (i64)j * n];
+        for (i64 p = p0; p < p1; p++) {
+            int i = rowindL[p];
+            Z[i + (i64)j * n] = tmp[p - p0];
+            Z[j + (i64)i * n] = tmp[p - p0];
+            d -= F[i + (i64)j * n] * tmp[p - p0];
+        }
+        Z[j + (i64)j * n] = d;
+    }
+    for (int j = 0; j < n; j++)
+        for (i64 p = colptrL[j]; p < colptrL[j + 1]; p++) sel[p] = Z[rowindL[p] + (i64)j * n];
+    free(F); free(Z); free(tmp);
+    return 0;
+}
+
+/* Dense reference gradient.  f = sum over the lower pattern of L of
+ * w_ij Ainv_ij; S = W + W^T (so S_ii = 2 w_ii).  An off-diagonal parameter
+ * a_ij drives A_ij and A_ji, so df/da_ij = -(Ainv S Ainv)_ij for i != j and
+ * -(1/2)(Ainv S Ainv)_ii on the diagonal.  Ainv: dense n x n (permuted
+ * numbering), W on (colptrL, rowindL); g on A's lower pattern given in the
+ * same numbering as (colptrA, rowindA). */
+void orc_dense_grad(int n, const double* Ainv, const i64* colptrL, const int* rowindL, const double* w,
+                    const i64* colptrA, const int* rowindA, double* g)
+{
+    double* Sm = (double*)calloc((size_t)n * n, sizeof(double));
+    for (int j = 0; j < n; j++)
+        for (i64 p = colptrL[j]; p < colptrL[j + 1]; p++) {
+            int i = rowindL[p];
+            Sm[i + (i64)j * n] += w[p];
+            Sm[j + (i64)i * n] += w[p];
+        }
+    double* T = (double*)calloc((size_t)n * n, sizeof(double));
+    /* T = S Ainv */
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < n; j++)
+        for (int k = 0; k < n; k++) {
+            double b = Ainv[k + (i64)j * n];
+            if (b == 0.0) continue;
+            for (int i = 0; i < n; i++) T[i + (i64)j * n] += Sm[i + (i64)k * n] * b;
+        }
+    for (int j = 0; j < n; j++)
+        for (i64 p = colptrA[j]; p < colptrA[j + 1]; p++) {
+            int i = rowindA[p];
+            double m = 0;
+            for (int k = 0; k < n; k++) m += Ainv[i + (i64)k * n] * T[k + (i64)j * n];
+            g[p] = (i == j) ? -0.5 * m : -m;
+        }
+    free(Sm); free(T);
+}

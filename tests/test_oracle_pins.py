@@ -1,0 +1,304 @@
+"""Pins for the CPU oracle: each check comes from outside the oracle itself
+(closed forms, the paper's worked example, brute force, invariants), and a
+planted mistake in any part of the oracle fails at least one of them."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1404_0447_amd import workloads as W
+from tests import helpers as H
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(autouse=True)
+def _no_mutation():
+    O.set_mutation(0)
+    yield
+    O.set_mutation(0)
+
+
+# ---------------------------------------------------------------- ordering
+def test_nd_order_hand_examples():
+    # 1D, 7 points: halves {0,1,2} and {4,5,6} split at 1 and 5, root plane 3
+    assert list(O.nd_order(1, (7,))) == [0, 2, 1, 4, 6, 5, 3]
+    # 3x3 grid: x is split first (tie goes to the lowest axis)
+    assert list(O.nd_order(2, (3, 3))) == [0, 6, 3, 2, 8, 5, 1, 4, 7]
+    # dofs stay contiguous per point
+    assert list(O.nd_order(1, (3,), dofs=2)) == [0, 1, 4, 5, 2, 3]
+
+
+@pytest.mark.parametrize("dims", [(5,), (6, 4), (7, 3, 5), (16, 16), (9, 9, 9)])
+def test_nd_order_is_a_separating_permutation(dims):
+    p = O.nd_order(len(dims), dims)
+    n = int(np.prod(dims))
+    assert sorted(p) == list(range(n))
+    # the last vertex eliminated is on a plane that splits the longest axis
+    m = W.laplacian(dims)
+    s = O.symbolic(m, cap=10 ** 9).sym
+    # a separator ordered last: the root supernode's columns disconnect the rest
+    assert s.parent[-1] == -1
+
+
+# ---------------------------------------------------------------- Fig. 1
+def test_fig1_structure():
+    g = json.load(open(os.path.join(GOLD, "fig1.json")))
+    m = W.fig1_pattern()
+    s = O.symbolic(m, cap=6, perm="natural").sym
+    assert s.nnzL == g["nnzL"]
+    assert list(s.parent) == g["column_parent"]
+    # the fill is exactly the "+" block of the figure
+    A = set()
+    for j in range(m.n):
+        for p in range(m.colptr[j], m.colptr[j + 1]):
+            A.add((int(m.rowind[p]), j))
+    Lset = set()
+    for j in range(m.n):
+        for p in range(s.colptrL[j], s.colptrL[j + 1]):
+            Lset.add((int(s.rowindL[p]), j))
+    fill = Lset - A
+    exp = {(r, c) for r in g["fill"]["rows"] for c in g["fill"]["cols"]}
+    assert fill == exp
+    got = [[int(s.xsuper[k]), int(s.xsuper[k + 1])] for k in range(s.N)]
+    assert got == g["fundamental_supernodes_cap6"]
+
+
+def test_fig1_block_tree_and_priorities():
+    """Block etree and Algorithm 2 priorities for the paper's own partition,
+    derived from the oracle's column tree."""
+    g = json.load(open(os.path.join(GOLD, "fig1.json")))
+    m = W.fig1_pattern()
+    s = O.symbolic(m, cap=6, perm="natural").sym
+    part = g["paper_supernodes"]
+    sn = np.empty(m.n, dtype=int)
+    for k, (a, b) in enumerate(part):
+        sn[a:b] = k
+    bpar = {}
+    for k, (a, b) in enumerate(part):
+        p = s.parent[b - 1]
+        bpar[str(k + 1)] = None if p < 0 else int(sn[p]) + 1
+    assert bpar == g["paper_block_parent"]
+    sigma = {}
+    for k in range(len(part), 0, -1):
+        sigma[str(k)] = 1 if bpar[str(k)] is None else sigma[str(bpar[str(k)])] + 1
+    assert sigma == g["paper_priority"]
+
+
+def test_fig1_priority_levels_fundamental():
+    m = W.fig1_pattern()
+    s = O.symbolic(m, cap=6, perm="natural").sym
+    # root = merged {23..28} -> 1; {10..15},{20..22} -> 2; four -> 3; two -> 4
+    assert list(s.level) == [4, 3, 4, 3, 2, 3, 3, 2, 1]
+
+
+# ---------------------------------------------------------------- brute force symbolic
+def _brute_pattern(m, perm):
+    n = m.n
+    ip = np.empty(n, dtype=int)
+    ip[perm] = np.arange(n)
+    B = np.zeros((n, n), dtype=bool)
+    r, c, _ = m.coo_full()
+    B[ip[r], ip[c]] = True
+    for k in range(n):  # Gaussian elimination on the pattern
+        nz = np.nonzero(B[k + 1:, k])[0] + k + 1
+        B[np.ix_(nz, nz)] = True
+    return B
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_symbolic_vs_brute_force_elimination(seed):
+    m = W.random_spd_pattern(40, 0.08, seed)
+    perm = np.random.default_rng(seed).permutation(m.n).astype(np.int32)
+    cap = 4 + seed
+    s = O.symbolic(m, cap=cap, perm=perm).sym
+    B = _brute_pattern(m, perm)
+    for j in range(m.n):
+        rows = [int(x) for x in s.rowindL[s.colptrL[j]:s.colptrL[j + 1]]]
+        exp = [j] + [int(i) for i in np.nonzero(B[j + 1:, j])[0] + j + 1]
+        assert rows == exp
+        assert s.parent[j] == (exp[1] if len(exp) > 1 else -1)
+    # supernodes: contiguous, dense diagonal block, same structure below, <= cap
+    for k in range(s.N):
+        a, b = int(s.xsuper[k]), int(s.xsuper[k + 1])
+        assert 1 <= b - a <= cap
+        below = set(np.nonzero(B[b:, a])[0] + b)
+        for j in range(a, b):
+            assert set(np.nonzero(B[j + 1:, j])[0] + j + 1) == set(range(j + 1, b)) | below
+    # maximality: neighbours could not have been merged
+    for k in range(s.N - 1):
+        a, b = int(s.xsuper[k]), int(s.xsuper[k + 1])
+        j = b - 1
+        only_child = s.parent[j] == j + 1 and int(np.sum(s.parent == j + 1)) == 1
+        same = set(np.nonzero(B[j + 1:, j])[0] + j + 1) == {j + 1} | set(np.nonzero(B[j + 2:, j + 1])[0] + j + 2)
+        assert (b - a == cap) or not (only_child and same)
+
+
+# ---------------------------------------------------------------- 1D closed form
+@pytest.mark.parametrize("n,shift,perm", [(50, 0.0, "natural"), (63, 0.3, "nd"), (200, 1e-2, "nd")])
+def test_tridiagonal_closed_form(n, shift, perm):
+    m = W.tridiag_1d(n, shift)
+    osym = O.symbolic(m, cap=8, perm=perm)
+    s = osym.sym
+    sel, _, st, _, _, _ = osym.factor_selinv(m.vals)
+    assert st == 0
+    exp = np.array([H.tridiag_inverse_entry(int(s.perm[i]) + 1, int(s.perm[j]) + 1, n, shift)
+                    for j in range(n) for i in s.rowindL[s.colptrL[j]:s.colptrL[j + 1]]])
+    assert H.err_c8(sel, exp, s.colptrL, s.rowindL) < 1e-12
+    if perm == "natural":  # natural order: pattern = diagonal + subdiagonal (linear work)
+        assert s.nnzL == 2 * n - 1
+
+
+def test_tridiagonal_dense_tiers():
+    n, shift = 40, 0.5
+    m = W.tridiag_1d(n, shift)
+    a = m.dense()
+    inv = O.dense_inverse(a)
+    exp = np.array([[H.tridiag_inverse_entry(i + 1, j + 1, n, shift) for j in range(n)] for i in range(n)])
+    assert np.max(np.abs(inv - exp)) < 1e-13
+    s = O.symbolic(m, cap=4, perm="nd").sym
+    ap = a[np.ix_(s.perm, s.perm)]
+    sel2 = O.selinv_columns(ap, s.colptrL, s.rowindL)
+    assert H.err_c8(sel2, H.sel_from_dense(exp, s.colptrL, s.rowindL, s.perm), s.colptrL, s.rowindL) < 1e-13
+
+
+# ---------------------------------------------------------------- 2D/3D closed form
+@pytest.mark.parametrize("dims,shift,cap", [((8, 8), 0.0, 128), ((32, 32), 0.1, 128), ((5, 4, 3), 0.2, 4),
+                                           ((9, 9, 9), 1e-2, 16)])
+def test_grid_spectral_closed_form(dims, shift, cap):
+    m = W.laplacian(dims, shift=shift)
+    osym = O.symbolic(m, cap=cap)
+    s = osym.sym
+    sel, _, st, _, _, _ = osym.factor_selinv(m.vals)
+    assert st == 0
+    exact = H.laplacian_inverse_dense(dims, shift)
+    exp = H.sel_from_dense(exact, s.colptrL, s.rowindL, s.perm)
+    assert H.err_c8(sel, exp, s.colptrL, s.rowindL) < 1e-11
+    # strict positivity (irreducible Stieltjes matrix)
+    assert np.all(sel > 0)
+
+
+def test_cfg1_sizes():
+    m = W.make("lap2d_32")
+    s = O.symbolic(m, cap=128).sym
+    assert (m.n, m.nnz) == (1024, 3008)
+    # symbolic sizes of the 32x32 grid under the bisection order
+    assert s.nnzL == 15836 and s.N == 663 and int(s.level.max()) == 19
+
+
+# ---------------------------------------------------------------- tiers agree
+@pytest.mark.parametrize("seed", range(4))
+def test_o3_o2_o1_random(seed):
+    m = W.random_spd_pattern(120, 0.04, seed + 10)
+    perm = np.random.default_rng(seed).permutation(m.n).astype(np.int32)
+    osym = O.symbolic(m, cap=3 + 5 * seed, perm=perm)
+    s = osym.sym
+    sel3, _, st, _, _, _ = osym.factor_selinv(m.vals)
+    assert st == 0
+    a = m.dense()
+    inv = O.dense_inverse(a)
+    exp = H.sel_from_dense(inv, s.colptrL, s.rowindL, s.perm)
+    sel2 = O.selinv_columns(a[np.ix_(s.perm, s.perm)], s.colptrL, s.rowindL)
+    assert H.err_c8(sel3, exp, s.colptrL, s.rowindL) < 1e-12
+    assert H.err_c8(sel2, exp, s.colptrL, s.rowindL) < 1e-12
+    # O1 itself: A @ Ainv = I
+    assert np.max(np.abs(a @ inv - np.eye(m.n))) < 1e-12
+
+
+def test_molecular_small_tiers():
+    m = W.molecular(side=3, dofs=4, seed=1)
+    osym = O.symbolic(m, cap=16)
+    s = osym.sym
+    sel3, _, st, _, _, _ = osym.factor_selinv(m.vals)
+    assert st == 0
+    a = m.dense()
+    inv = O.dense_inverse(a)
+    exp = H.sel_from_dense(inv, s.colptrL, s.rowindL, s.perm)
+    assert H.err_c8(sel3, exp, s.colptrL, s.rowindL) < 1e-11
+    assert np.min(np.linalg.eigvalsh(a)) >= 0.5 - 1e-6  # shift recipe: lambda_min >= 0.5
+
+
+# ---------------------------------------------------------------- invariants
+def test_invariants_cfg1():
+    m = W.make("lap2d_32")
+    osym = O.symbolic(m, cap=128)
+    s = osym.sym
+    sel, _, st, _, _, _ = osym.factor_selinv(m.vals)
+    r = H.row_identity_fast(sel, m, s.colptrL, s.rowindL, s.perm)
+    assert np.max(np.abs(r)) < 1e-12
+    d = sel[s.colptrL[:-1]]
+    cols = np.repeat(np.arange(m.n), np.diff(s.colptrL))
+    assert np.all(np.abs(sel) <= np.sqrt(d[s.rowindL] * d[cols]) * (1 + 1e-12))
+    assert np.all(sel > 0)
+
+
+def test_ordering_invariance():
+    m = W.laplacian((12, 10), coeff="uniform", lo=0.5, hi=2.0, shift=0.05, seed=7)
+    a = O.symbolic(m, cap=8, perm="nd")
+    b = O.symbolic(m, cap=8, perm="natural")
+    sa = a.factor_selinv(m.vals)[0]
+    sb = b.factor_selinv(m.vals)[0]
+    da = H.sel_to_dict(sa, a.sym.colptrL, a.sym.rowindL, a.sym.perm)
+    db = H.sel_to_dict(sb, b.sym.colptrL, b.sym.rowindL, b.sym.perm)
+    common = set(da) & set(db)
+    assert len(common) > m.nnz
+    assert max(abs(da[k] - db[k]) for k in common) < 1e-12
+
+
+def test_pivot_failure_reported():
+    m = W.laplacian((6, 6), shift=-10.0)
+    osym = O.symbolic(m, cap=8)
+    _, _, st, bad, _, _ = osym.factor_selinv(m.vals, require_spd=True)
+    assert st == -3 and bad == int(osym.sym.perm[0])
+
+
+# ---------------------------------------------------------------- gradient reference
+def test_dense_gradient_vs_finite_differences():
+    m = W.laplacian((4, 4), coeff="uniform", lo=0.5, hi=2.0, shift=0.3, seed=3)
+    s = O.symbolic(m, cap=4, perm="natural").sym
+    rng = np.random.default_rng(0)
+    w = rng.standard_normal(s.nnzL)
+    a = m.dense()
+    inv = O.dense_inverse(a)
+    g = O.dense_grad(inv, s.colptrL, s.rowindL, w, m.colptr, m.rowind)
+
+    def f(mat):
+        return float(np.dot(w, H.sel_from_dense(O.dense_inverse(mat), s.colptrL, s.rowindL)))
+
+    cols = np.repeat(np.arange(m.n), np.diff(m.colptr))
+    h = 1e-5
+    for p in range(m.nnz):
+        i, j = int(m.rowind[p]), int(cols[p])
+        e = np.zeros_like(a)
+        e[i, j] = 1.0
+        e[j, i] = 1.0
+        fd = (f(a + h * e) - f(a - h * e)) / (2 * h)
+        assert abs(fd - g[p]) <= 1e-6 * max(1.0, abs(g[p]))
+
+
+# ---------------------------------------------------------------- planted mistakes
+def _pin_suite_fails():
+    """True if one of the numeric pins fails under the current mutation."""
+    try:
+        test_tridiagonal_closed_form(63, 0.3, "nd")
+        test_grid_spectral_closed_form((8, 8), 0.0, 128)
+        test_grid_spectral_closed_form((5, 4, 3), 0.2, 4)
+        test_o3_o2_o1_random(1)
+    except (AssertionError, ValueError):
+        return True
+    return False
+
+
+@pytest.mark.parametrize("mutation", [1, 2, 3, 4, 5, 6, 7])
+def test_planted_mistakes_are_caught(mutation):
+    """1 sign of X, 2 dropped diagonal term, 3 L used for L_hat, 4 upper part
+    of the gathered block dropped, 5 Schur update misses its diagonal,
+    6 D instead of D^{-1}, 7 children's structures not merged."""
+    O.set_mutation(mutation)
+    try:
+        assert _pin_suite_fails()
+    finally:
+        O.set_mutation(0)
+    assert not _pin_suite_fails()
