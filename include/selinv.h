@@ -1,0 +1,147 @@
+/*
+ * selinv.h -- C ABI of the MI355X supernodal selected-inversion library.
+ *
+ * Given a sparse symmetric matrix A, the library computes every entry of
+ * A^{-1} that lies in the sparsity pattern of its LDL^T factor L (the
+ * "selected elements", Section 2 of Jacquelin, Lin and Yang, PSelInv, ACM
+ * TOMS; Algorithm 1 with the symmetric simplifications of Section 2.1).
+ *
+ * Pipeline: selinv_analyze (host: ordering, elimination tree, supernodes,
+ * block index maps) -> selinv_bind_workspace (device memory owned by the
+ * caller) -> selinv_factor (device supernodal LDL^T) -> selinv_invert
+ * (device root-to-leaf selected inversion, written as values on the pattern
+ * of L).
+ *
+ * Conventions for every call:
+ *  - Status codes are returned, never thrown.  selinv_last_error() gives a
+ *    thread-local message for the last failing call.
+ *  - Device pointers ("d_" prefix) are HIP device memory owned by the
+ *    caller; host pointers are read during the call only.
+ *  - Device work is asynchronous and ordered on the given stream; a zero
+ *    pivot found on the device is latched and reported by
+ *    selinv_sync_status.
+ *  - A plan is not thread-safe; distinct plans are independent.
+ *  - Numbering: "original" indices are those of the input CSC; L, the
+ *    selected values and the pattern use the permuted numbering, with
+ *    perm[new] = original.
+ */
+#ifndef SELINV_H
+#define SELINV_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct selinv_plan_s* selinv_plan;
+
+typedef enum {
+    SELINV_OK = 0,
+    SELINV_EINVAL = -1,       /* bad argument or malformed input pattern      */
+    SELINV_ESTATE = -2,       /* call out of order (e.g. invert before factor) */
+    SELINV_EPIVOT = -3,       /* zero / non-finite / non-positive pivot        */
+    SELINV_ENOMEM = -4,       /* host allocation failed or workspace too small */
+    SELINV_EHIP = -5,         /* a HIP runtime call failed                     */
+    SELINV_EUNSUPPORTED = -6  /* option not supported                          */
+} selinv_status;
+
+/* Geometry used by the nested-dissection ordering: a box grid of
+ * dims[0] x dims[1] x dims[2] points (x fastest), dofs_per_point unknowns
+ * per point stored contiguously (unknown = dofs*point + k).  ndim = 0 means
+ * no geometry: natural order unless a permutation is given. */
+typedef struct {
+    int32_t ndim;
+    int32_t dims[3];
+    int32_t dofs_per_point;
+} selinv_geom;
+
+typedef struct {
+    int32_t max_super;    /* cap on supernode width (columns), e.g. 128      */
+    int32_t fuse_chains;  /* 1: run chains of single-child supernodes as one
+                             amalgamated block (explicit zeros; results on the
+                             fundamental pattern are unchanged up to rounding) */
+    int32_t require_spd;  /* 1: a pivot <= 0 is an error (SELINV_EPIVOT)     */
+    int32_t exec_cap;     /* cap on an amalgamated block's width; 0 = max_super */
+} selinv_opts;
+
+typedef struct {
+    int64_t n, nnzA, nnzL;      /* order, lower nonzeros of A and of L          */
+    int64_t nsuper, depth;      /* fundamental supernodes, tree depth (levels)   */
+    int64_t nblocks, exec_depth;/* execution blocks and their tree depth         */
+    int64_t workspace_bytes;
+    double flops_factor;        /* sum c^2 s + c s^2 + s^3/3 (fundamental)       */
+    double flops_gemm;          /* sum 2 c^2 s + 2 c s^2      (fundamental)      */
+    double flops_selinv;        /* sum 2 c^2 s + 3 c s^2 + 2/3 s^3 (fundamental) */
+    double gather_bytes;        /* sum 8 c (c+1) / 2          (fundamental)      */
+    double exec_flops_gemm;     /* same GEMM count on the execution blocks       */
+} selinv_info;
+
+/* Symbolic analysis (Sections 2.1-2.2 and Algorithm 2).
+ * colptr[n+1], rowind[nnz]: lower triangle of A in CSC, diagonal included,
+ * rows strictly increasing within a column, rowind[p] >= column.
+ * geom: may be NULL (= ndim 0).  perm_or_null: perm[new] = original; when
+ * given it overrides the geometric ordering.  opts: may be NULL (defaults
+ * max_super 128, fuse_chains 1, require_spd 1).  On success *out owns a
+ * copy of everything it needs; no device memory is touched. */
+selinv_status selinv_analyze(int64_t n, const int64_t* colptr, const int32_t* rowind,
+                             const selinv_geom* geom, const int32_t* perm_or_null,
+                             const selinv_opts* opts, selinv_plan* out);
+
+/* Bytes of device workspace the plan needs (factor, inverse, index maps). */
+selinv_status selinv_workspace_size(selinv_plan p, size_t* bytes);
+
+/* Bind caller-owned device memory (>= selinv_workspace_size bytes, 256-byte
+ * aligned) and upload the index maps on stream s.  The plan never allocates
+ * device memory itself. */
+selinv_status selinv_bind_workspace(selinv_plan p, void* d_ws, size_t bytes, hipStream_t s);
+
+/* Supernodal LDL^T of A (Section 2.1, LDL^T form; no pivoting, Section 4).
+ * d_valsA: nnzA doubles in the CSC order given to selinv_analyze. */
+selinv_status selinv_factor(selinv_plan p, const double* d_valsA, hipStream_t s);
+
+/* Selected inversion (Algorithm 1, root first by the priority levels of
+ * Algorithm 2): writes nnzL doubles of A^{-1} to d_sel in the canonical
+ * order of selinv_get_pattern. */
+selinv_status selinv_invert(selinv_plan p, double* d_sel, hipStream_t s);
+
+/* Copy L (unit lower, D on the diagonal) on the canonical pattern to d_L. */
+selinv_status selinv_get_factor(selinv_plan p, double* d_L, hipStream_t s);
+
+/* Synchronise s and report a latched pivot failure: returns SELINV_EPIVOT
+ * with *bad_col = original index of the first failing column (else -1). */
+selinv_status selinv_sync_status(selinv_plan p, hipStream_t s, int64_t* bad_col);
+
+selinv_status selinv_get_info(selinv_plan p, selinv_info* out);
+
+/* Canonical pattern of L in permuted numbering: colptrL[n+1], rowindL[nnzL]
+ * (rows ascending, diagonal first), perm[n] (new -> original).  Any pointer
+ * may be NULL. */
+selinv_status selinv_get_pattern(selinv_plan p, int64_t* colptrL, int32_t* rowindL, int32_t* perm);
+
+/* Sizes of the arrays returned by selinv_get_symbolic. */
+selinv_status selinv_symbolic_sizes(selinv_plan p, int64_t* nsuper, int64_t* ncrows, int64_t* nrel);
+
+/* Fundamental-supernode symbolic data for parity checks (host copies):
+ * parent[n] column elimination tree (-1 root); xsuper[N+1]; sparent[N];
+ * level[N] (Algorithm 2 priority, root = 1); cptr[N+1], crows[] the row
+ * structure C(K) below each supernode; rptr[N+1], rel[] the block index
+ * maps: per supernode K, for each ancestor J met in C(K) in ascending order,
+ * the record [J, a, pos(C[a]), ..., pos(C[c-1])] where a is the first
+ * position of C(K) inside J's columns and pos(x) is the row of x within
+ * rows(J) = cols(J) U C(J).  Any pointer may be NULL. */
+selinv_status selinv_get_symbolic(selinv_plan p, int32_t* parent, int32_t* xsuper, int32_t* sparent,
+                                  int32_t* level, int64_t* cptr, int32_t* crows, int64_t* rptr,
+                                  int32_t* rel);
+
+/* Message for the last failing call on this thread. */
+const char* selinv_last_error(void);
+
+void selinv_destroy(selinv_plan p);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SELINV_H */

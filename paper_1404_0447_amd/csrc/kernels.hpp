@@ -1,0 +1,32 @@
+// Launch wrappers for the device kernels (kernels.hip).
+#pragma once
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+
+#include "plan.hpp"
+
+namespace selinv {
+
+// Device views of the workspace sub-arrays.
+struct DevPtrs {
+    double *Lp, *Ap, *Hp, *Wp, *Tp;
+    unsigned long long* status;
+    const BlockDesc* blocks;
+    const int32_t* crow;
+    const int64_t *cbase, *rbase;
+    const int32_t* rel;
+    const int64_t *asm_off, *exp_off;
+    const Task *t_diag, *t_panel, *t_schur, *t_gemm, *t_sdiag;
+};
+
+hipError_t launch_status_reset(unsigned long long* status, hipStream_t s);
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
+hipError_t launch_scatter_set(const double* src, const int64_t* off, int64_t n, double* dst, hipStream_t s);
+hipError_t launch_gather(const double* src, const int64_t* off, int64_t n, double* dst, hipStream_t s);
+hipError_t launch_factor_level(const DevPtrs& D, int64_t diag0, int64_t ndiag, int64_t panel0, int64_t npanel,
+                               int64_t schur0, int64_t nschur, int require_spd, hipStream_t s);
+hipError_t launch_invert_level(const DevPtrs& D, int64_t gemm0, int64_t ngemm, int64_t sdiag0, int64_t nsdiag,
+                               hipStream_t s);
+
+}  // namespace selinv

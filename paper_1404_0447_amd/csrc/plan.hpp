@@ -1,0 +1,93 @@
+// Internal plan structures shared by the host analysis, the scheduler and
+// the C ABI.  Not part of the public interface.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "selinv.h"
+
+namespace selinv {
+
+// A partition of the (permuted) columns into contiguous supernodes/blocks.
+struct Partition {
+    std::vector<int32_t> xs;     // block K = columns xs[K] .. xs[K+1]-1
+    std::vector<int32_t> of;     // column -> block
+    std::vector<int32_t> par;    // block tree parent, -1 for roots
+    std::vector<int32_t> lev;    // Algorithm 2 priority (root = 1)
+    std::vector<int64_t> cptr;   // C(K) = crows[cptr[K] .. cptr[K+1])
+    std::vector<int32_t> crows;  // sorted row indices below each block
+    int32_t depth = 0;
+
+    int32_t nblocks() const { return (int32_t)xs.size() - 1; }
+    int32_t first(int K) const { return xs[K]; }
+    int32_t width(int K) const { return xs[K + 1] - xs[K]; }
+    int32_t clen(int K) const { return (int32_t)(cptr[K + 1] - cptr[K]); }
+    const int32_t* C(int K) const { return crows.data() + cptr[K]; }
+};
+
+// Device descriptor of one execution block (all offsets in doubles).
+struct BlockDesc {
+    int64_t poff;   // panel (s+c) x s, column-major, ld = s + c  (L and Ainv arenas)
+    int64_t hoff;   // L_hat(C,K), c x s column-major, ld = c
+    int64_t woff;   // s x s blocks: W = L_KK^{-1} and T = L_KK^{-T} D^{-1} L_KK^{-1}
+    int64_t coff;   // offset into the per-position arrays (crow, cbase, rbase)
+    int32_t first, s, c, level;
+};
+static_assert(sizeof(BlockDesc) == 48, "BlockDesc layout");
+
+// One unit of device work; meaning of the fields depends on the kernel.
+struct Task {
+    int32_t b, i0, j0, k0;
+};
+
+struct LevelTasks {
+    std::vector<Task> tasks;
+    std::vector<int64_t> off;  // per level (index = level-1): tasks[off[l] .. off[l+1])
+};
+
+struct DeviceLayout {
+    // byte offsets into the workspace
+    size_t lp, ap, hp, wp, tp, status, blocks, crow, cbase, rbase, rel, asm_off, exp_off;
+    size_t t_diag, t_panel, t_schur, t_gemm, t_sdiag, total;
+};
+
+}  // namespace selinv
+
+struct selinv_plan_s {
+    int64_t n = 0, nnzA = 0;
+    selinv_opts opts{};
+    std::vector<int64_t> colptr;
+    std::vector<int32_t> rowind;
+    std::vector<int32_t> perm, iperm;  // perm[new] = original
+    std::vector<int32_t> parent;       // column elimination tree
+    std::vector<int32_t> cnt;          // |struct(j)| (below the diagonal)
+    selinv::Partition fund;            // fundamental supernodes (reported)
+    selinv::Partition exec;            // execution blocks (amalgamated chains)
+    std::vector<int64_t> colptrL;      // canonical pattern of L
+    std::vector<int32_t> rowindL;
+    // execution-block device tables (host copies)
+    std::vector<selinv::BlockDesc> blocks;
+    std::vector<int32_t> crow;         // = exec.crows
+    std::vector<int64_t> cbase, rbase;
+    std::vector<int32_t> rel;
+    std::vector<int64_t> asm_off, exp_off;
+    int64_t arena = 0, harena = 0, warena = 0;
+    selinv::LevelTasks t_diag, t_panel, t_schur, t_gemm, t_sdiag;
+    selinv::DeviceLayout lay{};
+    selinv_info info{};
+    // binding state
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    bool factored = false;
+};
+
+namespace selinv {
+// analyze.cpp
+selinv_status analyze(selinv_plan_s* P, const selinv_geom* geom, const int32_t* perm_or_null,
+                      std::string& err);
+void nd_order_box(int ndim, const int32_t dims[3], int dofs, std::vector<int32_t>& perm);
+void block_index_maps(const Partition& part, std::vector<int64_t>& rptr, std::vector<int32_t>& rel);
+// schedule.cpp
+void build_schedule(selinv_plan_s* P);
+}  // namespace selinv

@@ -1,0 +1,222 @@
+"""Python binding of libselinv.so (argument marshalling only).
+
+Every numerical step runs in the library's HIP kernels; torch only provides
+device memory (the workspace and the value/output tensors) and the stream.
+If the library is missing the import fails loudly: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "libselinv.so")
+
+SELINV_OK, SELINV_EINVAL, SELINV_ESTATE, SELINV_EPIVOT = 0, -1, -2, -3
+SELINV_ENOMEM, SELINV_EHIP, SELINV_EUNSUPPORTED = -4, -5, -6
+_NAMES = {0: "OK", -1: "EINVAL", -2: "ESTATE", -3: "EPIVOT", -4: "ENOMEM", -5: "EHIP", -6: "EUNSUPPORTED"}
+
+# every symbol include/selinv.h declares
+EXPORTS = ["selinv_analyze", "selinv_workspace_size", "selinv_bind_workspace", "selinv_factor", "selinv_invert",
+           "selinv_get_factor", "selinv_sync_status", "selinv_get_info", "selinv_get_pattern",
+           "selinv_symbolic_sizes", "selinv_get_symbolic", "selinv_last_error", "selinv_destroy"]
+
+
+class SelinvError(RuntimeError):
+    def __init__(self, status, msg, bad_col=-1):
+        super().__init__(f"selinv {_NAMES.get(status, status)}: {msg}")
+        self.status = status
+        self.bad_col = bad_col
+
+
+class Geom(ct.Structure):
+    _fields_ = [("ndim", ct.c_int32), ("dims", ct.c_int32 * 3), ("dofs_per_point", ct.c_int32)]
+
+
+class Opts(ct.Structure):
+    _fields_ = [("max_super", ct.c_int32), ("fuse_chains", ct.c_int32), ("require_spd", ct.c_int32),
+                ("exec_cap", ct.c_int32)]
+
+
+class Info(ct.Structure):
+    _fields_ = [("n", ct.c_int64), ("nnzA", ct.c_int64), ("nnzL", ct.c_int64), ("nsuper", ct.c_int64),
+                ("depth", ct.c_int64), ("nblocks", ct.c_int64), ("exec_depth", ct.c_int64),
+                ("workspace_bytes", ct.c_int64), ("flops_factor", ct.c_double), ("flops_gemm", ct.c_double),
+                ("flops_selinv", ct.c_double), ("gather_bytes", ct.c_double), ("exec_flops_gemm", ct.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            raise ImportError(f"{LIB} is not built; run __graft_entry__.build() (no fallback exists)")
+        L = ct.CDLL(LIB)
+        vp, i64, i32 = ct.c_void_p, ct.c_int64, ct.c_int32
+        L.selinv_analyze.argtypes = [i64, vp, vp, vp, vp, vp, ct.POINTER(vp)]
+        L.selinv_workspace_size.argtypes = [vp, ct.POINTER(ct.c_size_t)]
+        L.selinv_bind_workspace.argtypes = [vp, vp, ct.c_size_t, vp]
+        L.selinv_factor.argtypes = [vp, vp, vp]
+        L.selinv_invert.argtypes = [vp, vp, vp]
+        L.selinv_get_factor.argtypes = [vp, vp, vp]
+        L.selinv_sync_status.argtypes = [vp, vp, ct.POINTER(i64)]
+        L.selinv_get_info.argtypes = [vp, ct.POINTER(Info)]
+        L.selinv_get_pattern.argtypes = [vp, vp, vp, vp]
+        L.selinv_symbolic_sizes.argtypes = [vp, ct.POINTER(i64), ct.POINTER(i64), ct.POINTER(i64)]
+        L.selinv_get_symbolic.argtypes = [vp] + [vp] * 8
+        L.selinv_last_error.restype = ct.c_char_p
+        L.selinv_destroy.argtypes = [vp]
+        for f in EXPORTS:
+            if f not in ("selinv_last_error", "selinv_destroy"):
+                getattr(L, f).restype = ct.c_int
+        _ = i32
+        _lib = L
+    return _lib
+
+
+def _check(st, bad=-1):
+    if st != SELINV_OK:
+        msg = lib().selinv_last_error().decode(errors="replace")
+        raise SelinvError(st, msg, bad)
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ct.c_void_p)
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ct.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """Symbolic analysis + bound device workspace for one sparsity pattern."""
+
+    def __init__(self, n, colptr, rowind, geom=None, perm=None, max_super=128, fuse_chains=True,
+                 require_spd=True, exec_cap=0):
+        L = lib()
+        self.n = int(n)
+        self._colptr = np.ascontiguousarray(colptr, dtype=np.int64)
+        self._rowind = np.ascontiguousarray(rowind, dtype=np.int32)
+        g = None
+        if geom is not None:
+            ndim, dims, dofs = geom
+            d3 = list(dims) + [1] * (3 - len(dims))
+            g = Geom(int(ndim), (ct.c_int32 * 3)(*[int(x) for x in d3[:3]]), int(dofs))
+        pm = None if perm is None else np.ascontiguousarray(perm, dtype=np.int32)
+        o = Opts(int(max_super), int(bool(fuse_chains)), int(bool(require_spd)), int(exec_cap))
+        h = ct.c_void_p()
+        st = L.selinv_analyze(self.n, _p(self._colptr), _p(self._rowind), ct.byref(g) if g is not None else None,
+                              _p(pm), ct.byref(o), ct.byref(h))
+        _check(st)
+        self._h = h
+        self._ws = None
+        self._bound = False
+        inf = Info()
+        _check(L.selinv_get_info(self._h, ct.byref(inf)))
+        self.info = {k: getattr(inf, k) for k, _ in Info._fields_}
+
+    @classmethod
+    def from_matrix(cls, m, **kw):
+        geom = (m.ndim, m.dims, m.dofs) if m.ndim > 0 else None
+        return cls(m.n, m.colptr, m.rowind, geom=geom, **kw)
+
+    # ------------------------------------------------------------ host queries
+    def pattern(self):
+        nnzL = int(self.info["nnzL"])
+        cp = np.empty(self.n + 1, np.int64)
+        ri = np.empty(max(nnzL, 1), np.int32)
+        pm = np.empty(max(self.n, 1), np.int32)
+        _check(lib().selinv_get_pattern(self._h, _p(cp), _p(ri), _p(pm)))
+        return cp, ri[:nnzL], pm[: self.n]
+
+    def symbolic(self):
+        L = lib()
+        N, nc, nr = ct.c_int64(), ct.c_int64(), ct.c_int64()
+        _check(L.selinv_symbolic_sizes(self._h, ct.byref(N), ct.byref(nc), ct.byref(nr)))
+        N, nc, nr = N.value, nc.value, nr.value
+        out = dict(parent=np.empty(max(self.n, 1), np.int32), xsuper=np.empty(N + 1, np.int32),
+                   sparent=np.empty(max(N, 1), np.int32), level=np.empty(max(N, 1), np.int32),
+                   cptr=np.empty(N + 1, np.int64), crows=np.empty(max(nc, 1), np.int32),
+                   rptr=np.empty(N + 1, np.int64), rel=np.empty(max(nr, 1), np.int32))
+        _check(L.selinv_get_symbolic(self._h, *[_p(out[k]) for k in
+                                                ("parent", "xsuper", "sparent", "level", "cptr", "crows", "rptr",
+                                                 "rel")]))
+        out["parent"] = out["parent"][: self.n]
+        out["sparent"] = out["sparent"][:N]
+        out["level"] = out["level"][:N]
+        out["crows"] = out["crows"][:nc]
+        out["rel"] = out["rel"][:nr]
+        return out
+
+    # ------------------------------------------------------------ device calls
+    def bind(self, device="cuda", stream=None):
+        import torch
+        nb = ct.c_size_t()
+        _check(lib().selinv_workspace_size(self._h, ct.byref(nb)))
+        self._ws = torch.empty(int(nb.value), dtype=torch.uint8, device=device)
+        _check(lib().selinv_bind_workspace(self._h, ct.c_void_p(self._ws.data_ptr()), int(nb.value),
+                                           _stream(stream)))
+        self._bound = True
+        return self
+
+    def _need(self, t, n, name):
+        import torch
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+                and t.numel() == n):
+            raise ValueError(f"{name}: expected a contiguous float64 CUDA tensor with {n} entries")
+
+    def factor(self, vals, stream=None):
+        if not self._bound:
+            self.bind(device=vals.device)
+        self._need(vals, int(self.info["nnzA"]), "vals")
+        _check(lib().selinv_factor(self._h, ct.c_void_p(vals.data_ptr()), _stream(stream)))
+
+    def invert(self, out=None, stream=None):
+        import torch
+        nnzL = int(self.info["nnzL"])
+        if out is None:
+            out = torch.empty(nnzL, dtype=torch.float64, device=self._ws.device)
+        self._need(out, nnzL, "out")
+        _check(lib().selinv_invert(self._h, ct.c_void_p(out.data_ptr()), _stream(stream)))
+        return out
+
+    def factor_values(self, out=None, stream=None):
+        import torch
+        nnzL = int(self.info["nnzL"])
+        if out is None:
+            out = torch.empty(nnzL, dtype=torch.float64, device=self._ws.device)
+        self._need(out, nnzL, "out")
+        _check(lib().selinv_get_factor(self._h, ct.c_void_p(out.data_ptr()), _stream(stream)))
+        return out
+
+    def sync_status(self, stream=None):
+        bad = ct.c_int64(-1)
+        st = lib().selinv_sync_status(self._h, _stream(stream), ct.byref(bad))
+        _check(st, bad.value)
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                lib().selinv_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+
+def selected_inverse(m, vals=None, **kw):
+    """One-shot helper: analyze, factor and invert a workloads.Matrix on the
+    current CUDA device. Returns (plan, selected values tensor)."""
+    import torch
+    plan = Plan.from_matrix(m, **kw).bind()
+    v = torch.as_tensor(m.vals if vals is None else vals, dtype=torch.float64).cuda()
+    plan.factor(v)
+    sel = plan.invert()
+    plan.sync_status()
+    return plan, sel

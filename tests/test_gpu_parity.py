@@ -1,0 +1,164 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bar: max |x - o| / sqrt(o_ii o_jj) <= 1e-10 over the pattern of L (FP64),
+factor values within 1e-12 of the oracle's (relative to the pivot scale)."""
+import numpy as np
+import pytest
+
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _run(m, cap=128, fuse=True, perm="nd", vals=None, exec_cap=0):
+    torch = _torch()
+    from paper_1404_0447_amd import selinv as S
+    if isinstance(perm, str) and perm == "nd":
+        p = S.Plan.from_matrix(m, max_super=cap, fuse_chains=fuse, exec_cap=exec_cap)
+    elif isinstance(perm, str):
+        p = S.Plan(m.n, m.colptr, m.rowind, max_super=cap, fuse_chains=fuse, exec_cap=exec_cap)
+    else:
+        p = S.Plan(m.n, m.colptr, m.rowind, perm=perm, max_super=cap, fuse_chains=fuse, exec_cap=exec_cap)
+    p.bind()
+    v = torch.as_tensor(m.vals if vals is None else vals, dtype=torch.float64, device="cuda")
+    p.factor(v)
+    sel = p.invert()
+    Lv = p.factor_values()
+    p.sync_status()
+    return p, sel.cpu().numpy(), Lv.cpu().numpy()
+
+
+def _oracle(m, cap, perm="nd"):
+    from oracle import oracle as O
+    o = O.symbolic(m, cap=cap, perm=perm)
+    sel, Lv, st, _, _, _ = o.factor_selinv(m.vals, want_L=True)
+    assert st == 0
+    return o.sym, sel, Lv
+
+
+def _check(m, cap=128, fuse=True, perm="nd", exec_cap=0):
+    p, sel, Lv = _run(m, cap, fuse, perm, exec_cap=exec_cap)
+    s, osel, oL = _oracle(m, cap, perm)
+    cp, ri, pm = p.pattern()
+    assert np.array_equal(cp, s.colptrL) and np.array_equal(ri, s.rowindL) and np.array_equal(pm, s.perm)
+    e = H.err_c8(sel, osel, cp, ri)
+    assert e <= TOL, f"selected inverse error {e:.3e}"
+    # L: D on the diagonal; compare with the pivot scale sqrt(d_i d_j)
+    eL = H.err_c8(Lv, oL, cp, ri)
+    assert eL <= 1e-12, f"factor error {eL:.3e}"
+    return p, sel, s
+
+
+@pytest.mark.parametrize("fuse", [True, False])
+def test_lap2d_32(fuse):
+    from paper_1404_0447_amd import workloads as W
+    m = W.make("lap2d_32")
+    p, sel, s = _check(m, 128, fuse)
+    exact = H.laplacian_inverse_dense((32, 32), 0.1)
+    assert H.err_c8(sel, H.sel_from_dense(exact, s.colptrL, s.rowindL, s.perm), s.colptrL, s.rowindL) <= TOL
+    r = H.row_identity_fast(sel, m, s.colptrL, s.rowindL, s.perm)
+    assert np.max(np.abs(r)) <= 1e-10
+    assert np.all(sel > 0)
+
+
+@pytest.mark.parametrize("n,shift", [(1, 0.5), (2, 0.0), (37, 0.3), (300, 1e-2)])
+def test_tridiagonal_closed_form(n, shift):
+    from paper_1404_0447_amd import workloads as W
+    m = W.tridiag_1d(n, shift)
+    p, sel, s = _check(m, 8)
+    exp = np.array([H.tridiag_inverse_entry(int(s.perm[i]) + 1, int(s.perm[j]) + 1, n, shift)
+                    for j in range(n) for i in s.rowindL[s.colptrL[j]:s.colptrL[j + 1]]])
+    assert H.err_c8(sel, exp, s.colptrL, s.rowindL) <= TOL
+
+
+@pytest.mark.parametrize("seed,cap", [(0, 1), (1, 3), (2, 7), (3, 33), (4, 64)])
+def test_random_patterns(seed, cap):
+    from paper_1404_0447_amd import workloads as W
+    m = W.random_spd_pattern(150, 0.05, seed)
+    perm = np.random.default_rng(seed).permutation(m.n).astype(np.int32)
+    _check(m, cap, True, perm)
+
+
+@pytest.mark.parametrize("dims,cap,exec_cap", [((12, 11, 10), 16, 0), ((16, 16, 16), 128, 0),
+                                               ((16, 16, 16), 64, 256), ((48, 40), 32, 0)])
+def test_grids_variable_coefficients(dims, cap, exec_cap):
+    from paper_1404_0447_amd import workloads as W
+    m = W.laplacian(dims, coeff="loguniform", lo=0.1, hi=10.0, shift=1e-3, seed=5)
+    _check(m, cap, True, "nd", exec_cap)
+
+
+def test_molecular_small():
+    from paper_1404_0447_amd import workloads as W
+    m = W.molecular(side=5, dofs=8, seed=4)
+    _check(m, 128)
+
+
+def test_fig1_natural_order():
+    from paper_1404_0447_amd import workloads as W
+    _check(W.fig1_pattern(), 6, True, "natural")
+
+
+def test_diagonal_only_and_single():
+    torch = _torch()
+    from paper_1404_0447_amd import selinv as S
+    n = 7
+    d = np.arange(1, n + 1, dtype=np.float64)
+    p = S.Plan(n, np.arange(n + 1), np.arange(n, dtype=np.int32)).bind()
+    p.factor(torch.as_tensor(d, device="cuda"))
+    sel = p.invert().cpu().numpy()
+    assert np.allclose(sel, 1.0 / d, rtol=1e-15)
+
+
+def test_pivot_failure_reported():
+    torch = _torch()
+    from paper_1404_0447_amd import selinv as S
+    from paper_1404_0447_amd import workloads as W
+    m = W.laplacian((6, 6), shift=-10.0)
+    p = S.Plan.from_matrix(m).bind()
+    p.factor(torch.as_tensor(m.vals, device="cuda"))
+    with pytest.raises(S.SelinvError) as e:
+        p.sync_status()
+    assert e.value.status == S.SELINV_EPIVOT
+    cp, ri, pm = p.pattern()
+    assert e.value.bad_col == int(pm[0])
+    # the same plan recovers on a good matrix
+    good = W.laplacian((6, 6), shift=0.5)
+    p.factor(torch.as_tensor(good.vals, device="cuda"))
+    p.invert()
+    p.sync_status()
+
+
+def test_repeat_calls_identical():
+    torch = _torch()
+    from paper_1404_0447_amd import selinv as S
+    from paper_1404_0447_amd import workloads as W
+    m = W.laplacian((20, 20, 20), coeff="uniform", lo=0.5, hi=2.0, shift=1e-2, seed=2)
+    p = S.Plan.from_matrix(m).bind()
+    v = torch.as_tensor(m.vals, device="cuda")
+    p.factor(v)
+    a = p.invert().clone()
+    p.factor(v)
+    b = p.invert()
+    torch.cuda.synchronize()
+    # the Schur update uses atomics, so only rounding may differ
+    cp, ri, _ = p.pattern()
+    assert H.err_c8(a.cpu().numpy(), b.cpu().numpy(), cp, ri) <= 1e-13
+
+
+@pytest.mark.slow
+def test_lap3d_40_full():
+    """40^3 grid, U[0.5,2] conductivities, shift 1e-2, cap 128 (full size)."""
+    from paper_1404_0447_amd import workloads as W
+    m = W.make("lap3d_40")
+    p, sel, s = _check(m, 128, True)
+    r = H.row_identity_fast(sel, m, s.colptrL, s.rowindL, s.perm)
+    assert np.max(np.abs(r)) <= 1e-10

@@ -1,0 +1,123 @@
+"""Host side of the library (no GPU needed): the library loads and exports
+every declared symbol, its symbolic analysis equals the oracle's bit for bit,
+and malformed inputs are rejected with a status code."""
+import ctypes as ct
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1404_0447_amd import selinv as S
+from paper_1404_0447_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "selinv.h")).read()
+    declared = set(re.findall(r"\b(selinv_[a-z_]+)\s*\(", hdr))
+    assert declared == set(S.EXPORTS)
+    L = ct.CDLL(S.LIB)
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def _compare(m, cap, perm="nd", fuse=True):
+    o = O.symbolic(m, cap=cap, perm=perm).sym
+    if isinstance(perm, str):
+        p = S.Plan.from_matrix(m, max_super=cap, fuse_chains=fuse) if perm == "nd" else \
+            S.Plan(m.n, m.colptr, m.rowind, max_super=cap, fuse_chains=fuse)
+    else:
+        p = S.Plan(m.n, m.colptr, m.rowind, perm=perm, max_super=cap, fuse_chains=fuse)
+    cp, ri, pm = p.pattern()
+    sy = p.symbolic()
+    assert np.array_equal(pm, o.perm)
+    assert np.array_equal(cp, o.colptrL) and np.array_equal(ri, o.rowindL)
+    assert np.array_equal(sy["parent"], o.parent)
+    assert np.array_equal(sy["xsuper"], o.xsuper)
+    assert np.array_equal(sy["sparent"], o.sparent)
+    assert np.array_equal(sy["level"], o.level)
+    assert np.array_equal(sy["cptr"], o.cptr) and np.array_equal(sy["crows"], o.crows)
+    assert np.array_equal(sy["rptr"], o.rptr) and np.array_equal(sy["rel"], o.rel)
+    inf = p.info
+    assert inf["nnzL"] == o.nnzL and inf["nsuper"] == o.N and inf["depth"] == o.level.max()
+    assert inf["flops_gemm"] == pytest.approx(o.gemm_flops, rel=1e-12)
+    return p, o
+
+
+def test_fig1_parity():
+    _compare(W.fig1_pattern(), 6, perm="natural")
+
+
+@pytest.mark.parametrize("dims,cap", [((32, 32), 128), ((7, 5), 3), ((9, 8, 7), 16), ((12, 12, 12), 128),
+                                      ((1,), 4), ((50,), 8)])
+def test_grid_parity(dims, cap):
+    _compare(W.laplacian(dims, shift=0.1), cap)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_random_pattern_parity(seed):
+    m = W.random_spd_pattern(80, 0.05, seed)
+    perm = np.random.default_rng(seed).permutation(m.n).astype(np.int32)
+    _compare(m, 2 + 3 * seed, perm=perm)
+
+
+def test_molecular_parity():
+    _compare(W.molecular(side=4, dofs=8, seed=4, shift=30.0), 128)
+
+
+@pytest.mark.slow
+def test_lap3d_40_parity():
+    p, o = _compare(W.make("lap3d_40"), 128)
+    assert o.N == 42178 and o.level.max() == 311 and o.nnzL == 21285841
+
+
+def test_exec_blocks_reduce_depth():
+    m = W.laplacian((16, 16, 16), shift=0.1)
+    a = S.Plan.from_matrix(m, fuse_chains=False).info
+    b = S.Plan.from_matrix(m, fuse_chains=True).info
+    assert a["nblocks"] == a["nsuper"] and a["exec_depth"] == a["depth"]
+    assert b["nblocks"] < a["nblocks"] and b["exec_depth"] < a["depth"]
+    assert b["exec_flops_gemm"] >= b["flops_gemm"]
+
+
+def test_malformed_inputs_rejected():
+    m = W.laplacian((4, 4))
+    bad = m.rowind.copy()
+    bad[1], bad[2] = bad[2], bad[1]  # unsorted rows in column 0
+    with pytest.raises(S.SelinvError) as e:
+        S.Plan(m.n, m.colptr, bad)
+    assert e.value.status == S.SELINV_EINVAL
+    up = m.rowind.copy()
+    up[m.colptr[3]] = 1  # row above the diagonal in column 3
+    with pytest.raises(S.SelinvError):
+        S.Plan(m.n, m.colptr, up)
+    with pytest.raises(S.SelinvError):
+        S.Plan(m.n, m.colptr, m.rowind, perm=np.zeros(m.n, np.int32))  # not a permutation
+    with pytest.raises(S.SelinvError) as e:
+        S.Plan(m.n, m.colptr, m.rowind, geom=(2, (5, 5), 1))  # geometry mismatch
+    assert e.value.status == S.SELINV_EINVAL
+    with pytest.raises(S.SelinvError) as e:
+        S.Plan(m.n, m.colptr, m.rowind, max_super=512)
+    assert e.value.status == S.SELINV_EUNSUPPORTED
+
+
+def test_degenerate_sizes():
+    p = S.Plan(0, np.zeros(1, np.int64), np.zeros(0, np.int32))
+    assert p.info["nnzL"] == 0 and p.info["nsuper"] == 0
+    p = S.Plan(1, np.array([0, 1]), np.array([0], np.int32))
+    assert p.info["nnzL"] == 1 and p.info["nsuper"] == 1
+    # a matrix with an empty off-diagonal column structure (diagonal only)
+    n = 5
+    p = S.Plan(n, np.arange(n + 1), np.arange(n, dtype=np.int32))
+    assert p.info["nnzL"] == n and p.info["depth"] == 1
+
+
+def test_device_calls_need_a_workspace():
+    m = W.laplacian((4, 4))
+    p = S.Plan.from_matrix(m)
+    L = S.lib()
+    st = L.selinv_invert(p._h, None, None)
+    assert st == S.SELINV_ESTATE
