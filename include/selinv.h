@@ -136,6 +136,50 @@ selinv_status selinv_get_symbolic(selinv_plan p, int32_t* parent, int32_t* xsupe
                                   int32_t* level, int64_t* cptr, int32_t* crows, int64_t* rptr,
                                   int32_t* rel);
 
+/* Kernel kinds reported by the timing calls below. */
+enum {
+    SELINV_K_ASSEMBLE = 0, /* zero the factor arena, scatter A into it            */
+    SELINV_K_LDLT = 1,     /* diagonal block LDL^T, W = L_KK^{-1}, T_K           */
+    SELINV_K_PANEL = 2,    /* L(C,K) and the normalised L_hat(C,K)               */
+    SELINV_K_SCHUR = 3,    /* Schur update added into ancestor panels            */
+    SELINV_K_GEMM = 4,     /* Ainv(C,K) = -Ainv(C,C) L_hat(C,K), gathered        */
+    SELINV_K_SDIAG = 5,    /* Ainv(K,K) = T_K - L_hat^T Ainv(C,K), symmetrised   */
+    SELINV_K_EXPORT = 6,   /* panels -> canonical values                         */
+    SELINV_NKINDS = 7
+};
+
+/* Enable (1) or disable (0) per-launch timing: every later kernel launch of
+ * this plan is stamped with HIP start/stop events in its dispatch. */
+selinv_status selinv_profile(selinv_plan p, int32_t enable);
+
+/* Wait for the recorded launches and return, per kernel kind, the summed
+ * duration in ms and the launch count (arrays of SELINV_NKINDS); clears the
+ * record.  Either pointer may be NULL. */
+selinv_status selinv_profile_read(selinv_plan p, double* ms, int64_t* launches);
+
+/* Algorithmic flops and bytes of one selinv_factor (kinds ASSEMBLE..SCHUR)
+ * and one selinv_invert (GEMM, SDIAG, EXPORT) call, per kernel kind, on the
+ * execution blocks (arrays of SELINV_NKINDS). */
+selinv_status selinv_kernel_work(selinv_plan p, double* flops, double* bytes);
+
+/* Raw device arenas, for kernel-level checks: which = 0 factor panels
+ * (L_KK with D on the diagonal; F(C,K) in the C rows), 1 inverse panels,
+ * 2 L_hat(C,K) blocks, 3 W = L_KK^{-1} blocks, 4 T_K blocks.  The layout of
+ * each execution block is given by selinv_get_blocks.  *count = number of
+ * doubles; d_out (device, may be NULL) receives a copy on stream s. */
+selinv_status selinv_get_arena(selinv_plan p, int32_t which, double* d_out, int64_t* count, hipStream_t s);
+
+/* Execution blocks (host copies, nblocks entries each; any may be NULL):
+ * first column, width s, |C|, priority level, and the offsets (in doubles)
+ * of the block's (s+c) x s panel, its c x s L_hat block and its s x s
+ * W / T blocks; crow_off[b] indexes the rows C(b) in the order returned by
+ * selinv_get_exec_rows. */
+selinv_status selinv_get_blocks(selinv_plan p, int32_t* first, int32_t* s, int32_t* c, int32_t* level,
+                                int64_t* poff, int64_t* hoff, int64_t* woff, int64_t* crow_off);
+
+/* Row structures C(b) of the execution blocks, concatenated (host copy). */
+selinv_status selinv_get_exec_rows(selinv_plan p, int32_t* rows);
+
 /* Message for the last failing call on this thread. */
 const char* selinv_last_error(void);
 

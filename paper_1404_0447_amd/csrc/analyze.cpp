@@ -409,6 +409,7 @@ selinv_status analyze(selinv_plan_s* P, const selinv_geom* geom, const int32_t* 
             const BlockDesc& d = P->blocks[B];
             P->asm_off[p] = d.poff + r + (int64_t)(hi - d.first) * (d.s + d.c);
         }
+    P->colblk = E.of;
     // ---- export map: canonical entry of L -> arena offset
     P->exp_off.resize(P->rowindL.size());
     for (int64_t j = 0; j < n; j++) {

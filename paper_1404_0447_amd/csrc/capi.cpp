@@ -51,6 +51,8 @@ void compute_layout(selinv_plan_s* P)
     L.rel = take(sizeof(int32_t) * P->rel.size());
     L.asm_off = take(sizeof(int64_t) * P->asm_off.size());
     L.exp_off = take(sizeof(int64_t) * P->exp_off.size());
+    L.colblk = take(sizeof(int32_t) * P->colblk.size());
+    L.colptrL = take(sizeof(int64_t) * P->colptrL.size());
     L.t_diag = take(sizeof(Task) * P->t_diag.tasks.size());
     L.t_panel = take(sizeof(Task) * P->t_panel.tasks.size());
     L.t_schur = take(sizeof(Task) * P->t_schur.tasks.size());
@@ -78,6 +80,8 @@ DevPtrs dev_ptrs(const selinv_plan_s* P)
     D.rel = (const int32_t*)(w + L.rel);
     D.asm_off = (const int64_t*)(w + L.asm_off);
     D.exp_off = (const int64_t*)(w + L.exp_off);
+    D.colblk = (const int32_t*)(w + L.colblk);
+    D.colptrL = (const int64_t*)(w + L.colptrL);
     D.t_diag = (const Task*)(w + L.t_diag);
     D.t_panel = (const Task*)(w + L.t_panel);
     D.t_schur = (const Task*)(w + L.t_schur);
@@ -174,8 +178,9 @@ selinv_status selinv_bind_workspace(selinv_plan P, void* d_ws, size_t bytes, hip
     P->ws_bytes = bytes;
     P->factored = false;
     const DeviceLayout& L = P->lay;
+    static hipError_t init = kernels_init();
+    if (init != hipSuccess) return hip_fail(init, "kernel attributes");
     hipError_t e = hipSuccess;
-    std::vector<Task> empty;
     if (!e) e = upload(P->ws, L.blocks, P->blocks, s);
     if (!e) e = upload(P->ws, L.crow, P->crow, s);
     if (!e) e = upload(P->ws, L.cbase, P->cbase, s);
@@ -183,6 +188,8 @@ selinv_status selinv_bind_workspace(selinv_plan P, void* d_ws, size_t bytes, hip
     if (!e) e = upload(P->ws, L.rel, P->rel, s);
     if (!e) e = upload(P->ws, L.asm_off, P->asm_off, s);
     if (!e) e = upload(P->ws, L.exp_off, P->exp_off, s);
+    if (!e) e = upload(P->ws, L.colblk, P->colblk, s);
+    if (!e) e = upload(P->ws, L.colptrL, P->colptrL, s);
     if (!e) e = upload(P->ws, L.t_diag, P->t_diag.tasks, s);
     if (!e) e = upload(P->ws, L.t_panel, P->t_panel.tasks, s);
     if (!e) e = upload(P->ws, L.t_schur, P->t_schur.tasks, s);
@@ -204,15 +211,15 @@ selinv_status selinv_factor(selinv_plan P, const double* d_valsA, hipStream_t s)
     DevPtrs D = dev_ptrs(P);
     // status word := "no failure"; zero the factor arena; assemble A
     hipError_t e = launch_status_reset(D.status, s);
-    if (!e) e = launch_fill(D.Lp, P->arena, 0.0, s);
-    if (!e) e = launch_scatter_set(d_valsA, D.asm_off, P->nnzA, D.Lp, s);
+    if (!e) e = launch_fill(&P->prof, kAssemble, D.Lp, P->arena, 0.0, s);
+    if (!e) e = launch_scatter_set(&P->prof, kAssemble, d_valsA, D.asm_off, P->nnzA, D.Lp, s);
     if (e) return hip_fail(e, "factor setup");
     const int depth = P->exec.depth;
     for (int l = depth - 1; l >= 0; l--) {
         const auto& a = P->t_diag.off;
         const auto& b = P->t_panel.off;
         const auto& c = P->t_schur.off;
-        e = launch_factor_level(D, a[l], a[l + 1] - a[l], b[l], b[l + 1] - b[l], c[l], c[l + 1] - c[l],
+        e = launch_factor_level(&P->prof, D, a[l], a[l + 1] - a[l], b[l], b[l + 1] - b[l], c[l], c[l + 1] - c[l],
                                 P->opts.require_spd, s);
         if (e) return hip_fail(e, "factor level launch");
     }
@@ -232,10 +239,10 @@ selinv_status selinv_invert(selinv_plan P, double* d_sel, hipStream_t s)
     for (int l = 0; l < depth; l++) {
         const auto& g = P->t_gemm.off;
         const auto& d = P->t_sdiag.off;
-        e = launch_invert_level(D, g[l], g[l + 1] - g[l], d[l], d[l + 1] - d[l], s);
+        e = launch_invert_level(&P->prof, D, g[l], g[l + 1] - g[l], d[l], d[l + 1] - d[l], s);
         if (e) return hip_fail(e, "invert level launch");
     }
-    e = launch_gather(D.Ap, D.exp_off, P->colptrL.back(), d_sel, s);
+    e = launch_gather(&P->prof, kExport, D.Ap, D.exp_off, P->colptrL.back(), d_sel, s);
     if (e) return hip_fail(e, "export launch");
     return SELINV_OK;
 }
@@ -246,7 +253,7 @@ selinv_status selinv_get_factor(selinv_plan P, double* d_L, hipStream_t s)
     if (!P->ws) return fail(SELINV_ESTATE, "no workspace bound");
     if (!P->factored) return fail(SELINV_ESTATE, "no factor computed");
     DevPtrs D = dev_ptrs(P);
-    hipError_t e = launch_gather(D.Lp, D.exp_off, P->colptrL.back(), d_L, s);
+    hipError_t e = launch_export_L(&P->prof, D, P->n, d_L, s);
     if (e) return hip_fail(e, "export launch");
     return SELINV_OK;
 }
@@ -318,6 +325,93 @@ selinv_status selinv_get_symbolic(selinv_plan P, int32_t* parent, int32_t* xsupe
         if (rptr) std::copy(rp.begin(), rp.end(), rptr);
         if (rel) std::copy(rl.begin(), rl.end(), rel);
     }
+    return SELINV_OK;
+}
+
+selinv_status selinv_profile(selinv_plan P, int32_t enable)
+{
+    if (!P) return fail(SELINV_EINVAL, "NULL plan");
+    P->prof.on = enable != 0;
+    return SELINV_OK;
+}
+
+selinv_status selinv_profile_read(selinv_plan P, double* ms, int64_t* launches)
+{
+    if (!P) return fail(SELINV_EINVAL, "NULL plan");
+    Prof& R = P->prof;
+    for (int k = 0; k < kNumKinds; k++) {
+        if (ms) ms[k] = 0.0;
+        if (launches) launches[k] = 0;
+    }
+    hipError_t e = hipSuccess;
+    for (size_t i = 0; i < R.kinds.size() && !e; i++) {
+        e = hipEventSynchronize(R.pool[2 * i + 1]);
+        float t = 0.f;
+        if (!e) e = hipEventElapsedTime(&t, R.pool[2 * i], R.pool[2 * i + 1]);
+        if (!e) {
+            if (ms) ms[R.kinds[i]] += t;
+            if (launches) launches[R.kinds[i]] += 1;
+        }
+    }
+    R.kinds.clear();
+    R.used = 0;
+    if (e) return hip_fail(e, "profile_read");
+    return SELINV_OK;
+}
+
+selinv_status selinv_kernel_work(selinv_plan P, double* flops, double* bytes)
+{
+    if (!P) return fail(SELINV_EINVAL, "NULL plan");
+    for (int k = 0; k < kNumKinds; k++) {
+        if (flops) flops[k] = P->work_flops[k];
+        if (bytes) bytes[k] = P->work_bytes[k];
+    }
+    return SELINV_OK;
+}
+
+selinv_status selinv_get_arena(selinv_plan P, int32_t which, double* d_out, int64_t* count, hipStream_t s)
+{
+    if (!P) return fail(SELINV_EINVAL, "NULL plan");
+    size_t off;
+    int64_t n;
+    switch (which) {
+        case 0: off = P->lay.lp; n = P->arena; break;
+        case 1: off = P->lay.ap; n = P->arena; break;
+        case 2: off = P->lay.hp; n = P->harena; break;
+        case 3: off = P->lay.wp; n = P->warena; break;
+        case 4: off = P->lay.tp; n = P->warena; break;
+        default: return fail(SELINV_EINVAL, "unknown arena");
+    }
+    if (count) *count = n;
+    if (!d_out || n == 0) return SELINV_OK;
+    if (!P->ws) return fail(SELINV_ESTATE, "no workspace bound");
+    hipError_t e = hipMemcpyAsync(d_out, P->ws + off, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
+    if (e) return hip_fail(e, "get_arena");
+    return SELINV_OK;
+}
+
+selinv_status selinv_get_blocks(selinv_plan P, int32_t* first, int32_t* s, int32_t* c, int32_t* level,
+                                int64_t* poff, int64_t* hoff, int64_t* woff, int64_t* crow_off)
+{
+    if (!P) return fail(SELINV_EINVAL, "NULL plan");
+    for (size_t b = 0; b < P->blocks.size(); b++) {
+        const BlockDesc& d = P->blocks[b];
+        if (first) first[b] = d.first;
+        if (s) s[b] = d.s;
+        if (c) c[b] = d.c;
+        if (level) level[b] = d.level;
+        if (poff) poff[b] = d.poff;
+        if (hoff) hoff[b] = d.hoff;
+        if (woff) woff[b] = d.woff;
+        if (crow_off) crow_off[b] = d.coff;
+    }
+    return SELINV_OK;
+}
+
+selinv_status selinv_get_exec_rows(selinv_plan P, int32_t* rows)
+{
+    if (!P) return fail(SELINV_EINVAL, "NULL plan");
+    if (rows) std::copy(P->crow.begin(), P->crow.end(), rows);
     return SELINV_OK;
 }
 

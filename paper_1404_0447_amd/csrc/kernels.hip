@@ -2,15 +2,22 @@
 //
 // Data layout (all FP64, in one caller-bound workspace):
 //   Lp  panels of the factor: block B is an (s+c) x s column-major panel,
-//       ld = s+c; rows = cols(B) then C(B).  Holds A, then L (D on the
-//       diagonal of the s x s block).
+//       ld = s+c; rows = cols(B) then C(B).  The s x s block holds L_BB
+//       (unit diagonal implied, D on the diagonal); the C rows hold
+//       F(C,B), the assembled and updated entries of A (L(C,B) is
+//       F(C,B) L_BB^{-T} D^{-1} and is formed only on export).
 //   Ap  same layout, holds the selected entries of A^{-1}.
-//   Hp  L_hat(C,B) = L(C,B) L_BB^{-1}, c x s column-major (ld = c).
+//   Hp  L_hat(C,B) = L(C,B) L_BB^{-1} = F(C,B) T, c x s column-major (ld c).
 //   Wp  W = L_BB^{-1} (s x s); Tp  T = L_BB^{-T} D_B^{-1} L_BB^{-1} (s x s).
 // Block index maps: for position r of C(B), cbase[r] is the arena offset of
 // column C[r] inside its owning block J, and rel[rbase[r] + i] the row of
 // C[i] (i >= r's segment start) inside rows(J).  So the entry
 // A^{-1}(C[i], C[k]), i >= k, lives at cbase[k] + rel[rbase[k] + i].
+//
+// Dense products use v_mfma_f64_16x16x4f64: lane l holds A[l%16][l/16] and
+// B[l/16][l%16]; the 16x16 result element (l/16 + 4v, l%16) sits in
+// register v of lane l.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -20,6 +27,23 @@
 #include "tiles.hpp"
 
 namespace selinv {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Wait states after the last MFMA of a loop, before its accumulators are
+// read by ordinary vector instructions (the scheduler may not move anything
+// across the barrier).
+__device__ __forceinline__ void mfma_drain()
+{
+    __builtin_amdgcn_sched_barrier(0);
+    asm volatile("s_nop 15\n\ts_nop 15\n\ts_nop 15\n\ts_nop 15" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+}
 
 __global__ void k_fill(double* __restrict__ p, int64_t n, double v)
 {
@@ -46,19 +70,345 @@ __global__ void k_gather(const double* __restrict__ src, const int64_t* __restri
         dst[i] = src[off[i]];
 }
 
-// ---------------------------------------------------------------------------
-// Factor, diagonal block: F_BB = L_BB D_B L_BB^T in place (right-looking, no
-// pivoting), then W = L_BB^{-1} and T = W^T D^{-1} W.  One work-group per
-// block.  A pivot that is zero, not finite, or (require_spd) not positive is
-// latched as the smallest failing permuted column.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_ldlt_diag(const Task* __restrict__ tasks,
-                                                        const BlockDesc* __restrict__ blk, double* __restrict__ Lp,
-                                                        double* __restrict__ Wp, double* __restrict__ Tp,
-                                                        unsigned long long* __restrict__ status, int require_spd)
+// L on the canonical pattern: diagonal-block entries are stored; an entry in
+// C(B) rows is L(r,j) = sum_{k>=j} L_hat(r,k) L_BB(k,j).  One thread per column.
+__global__ void k_export_L(const BlockDesc* __restrict__ blk, const int32_t* __restrict__ colblk,
+                           const int64_t* __restrict__ colptrL, const int64_t* __restrict__ off, int64_t n,
+                           const double* __restrict__ Lp, const double* __restrict__ Hp, double* __restrict__ out)
 {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+        const BlockDesc d = blk[colblk[j]];
+        const int64_t ld = (int64_t)d.s + d.c;
+        for (int64_t q = colptrL[j]; q < colptrL[j + 1]; ++q) {
+            const int64_t o = off[q] - d.poff;
+            const int row = (int)(o % ld), col = (int)(o / ld);
+            double v;
+            if (row < d.s) {
+                v = Lp[off[q]];
+            } else {
+                const int r = row - d.s;
+                v = Hp[d.hoff + r + (int64_t)col * d.c];
+                for (int k = col + 1; k < d.s; ++k)
+                    v += Hp[d.hoff + r + (int64_t)k * d.c] * Lp[d.poff + k + (int64_t)col * ld];
+            }
+            out[q] = v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Generic 64 x BN MFMA tile: acc += A(64 x K) B(K x BN), K streamed in
+// chunks of 16 through LDS.  loadA(k0, kk, i) -> A(i, k0+kk) and
+// loadB(k0, kk, j) -> B(k0+kk, j).  The A loads run with consecutive threads
+// along i, or along kk for chunks where chunkAlongK(k0) holds (contiguous
+// in k).  Four waves: BN >= 64 -> 2 x 2 waves of 32 x BN/2, else 4 x 1 waves
+// of 16 x BN.
+// ---------------------------------------------------------------------------
+constexpr int TBM = 64, TBK = 16, TPAD = 4;
+
+struct TileLds {
+    double A[TBK][TBM + TPAD];
+    double B[TBK][128 + TPAD];
+};
+
+template <int BN>
+struct TileShape {
+    static constexpr int WM = BN >= 64 ? 2 : 4;
+    static constexpr int WN = 4 / WM;
+    static constexpr int MT = TBM / WM / 16;
+    static constexpr int NT = BN / WN / 16;
+};
+
+template <int BN, class FA, class FB, class FAK>
+__device__ __forceinline__ void tile_mma(TileLds& L, int K, d4 (&acc)[2][4], FA loadA, FB loadB, FAK chunkAlongK)
+{
+    using SH = TileShape<BN>;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm0 = (wave % SH::WM) * (TBM / SH::WM), wn0 = (wave / SH::WM) * (BN / SH::WN);
+    for (int k0 = 0; k0 < K; k0 += TBK) {
+        if (chunkAlongK(k0)) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int e = threadIdx.x + q * kThreads;
+                const int kk = e & 15, i = e >> 4;
+                L.A[kk][i] = loadA(k0, kk, i);
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int e = threadIdx.x + q * kThreads;
+                const int i = e & 63, kk = e >> 6;
+                L.A[kk][i] = loadA(k0, kk, i);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < BN / 16; ++q) {
+            const int e = threadIdx.x + q * kThreads;
+            const int kk = e & 15, j = e >> 4;
+            L.B[kk][j] = loadB(k0, kk, j);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < TBK / 4; ++ks) {
+            const int kr = ks * 4 + (lane >> 4);
+            double a[SH::MT], b[SH::NT];
+#pragma unroll
+            for (int mt = 0; mt < SH::MT; ++mt) a[mt] = L.A[kr][wm0 + mt * 16 + (lane & 15)];
+#pragma unroll
+            for (int nt = 0; nt < SH::NT; ++nt) b[nt] = L.B[kr][wn0 + nt * 16 + (lane & 15)];
+#pragma unroll
+            for (int mt = 0; mt < SH::MT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < SH::NT; ++nt) acc[mt][nt] = mfma(a[mt], b[nt], acc[mt][nt]);
+        }
+        __syncthreads();
+    }
+    mfma_drain();
+}
+
+// visit every accumulator element: f(i, j, value) with tile-local i, j
+template <int BN, class F>
+__device__ __forceinline__ void tile_epilogue(const d4 (&acc)[2][4], F f)
+{
+    using SH = TileShape<BN>;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm0 = (wave % SH::WM) * (TBM / SH::WM), wn0 = (wave / SH::WM) * (BN / SH::WN);
+#pragma unroll
+    for (int mt = 0; mt < SH::MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < SH::NT; ++nt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                f(wm0 + mt * 16 + (lane >> 4) + 4 * v, wn0 + nt * 16 + (lane & 15), acc[mt][nt][v]);
+}
+
+#define SELINV_BN_DISPATCH(bn, CALL) \
+    switch (bn) {                    \
+        case 16: CALL(16); break;    \
+        case 32: CALL(32); break;    \
+        case 64: CALL(64); break;    \
+        default: CALL(128); break;   \
+    }
+
+// ---------------------------------------------------------------------------
+// Selected inversion, step 3: X = Ainv(C,B) = -Ainv(C,C) L_hat(C,B) for rows
+// [i0, i0+64) and columns [j0, j0+BN) of X.  Ainv(C,C) is gathered from the
+// ancestors' panels: entries with i >= k directly, the others by symmetry.
+// ---------------------------------------------------------------------------
+template <int BN>
+__device__ void gemm_task(TileLds& L, const Task t, const BlockDesc d, double* __restrict__ Ap,
+                          const double* __restrict__ Hp, const int64_t* __restrict__ cbase,
+                          const int64_t* __restrict__ rbase, const int32_t* __restrict__ rel)
+{
+    const int s = d.s, c = d.c;
+    const int64_t ld = (int64_t)s + c;
+    const int r0 = t.i0, n0 = t.j0;
+    d4 acc[2][4] = {};
+    auto loadA = [&](int k0, int kk, int ii) -> double {
+        const int i = r0 + ii, k = k0 + kk;
+        if (i >= c || k >= c) return 0.0;
+        if (i >= k) {
+            const int64_t pk = d.coff + k;
+            return Ap[cbase[pk] + rel[rbase[pk] + i]];
+        }
+        const int64_t pi = d.coff + i;
+        return Ap[cbase[pi] + rel[rbase[pi] + k]];
+    };
+    auto loadB = [&](int k0, int kk, int j) -> double {
+        const int k = k0 + kk, jj = n0 + j;
+        return (k < c && jj < s) ? Hp[d.hoff + k + (int64_t)jj * c] : 0.0;
+    };
+    // chunks entirely above the diagonal band are read along k (contiguous)
+    auto alongK = [&](int k0) { return k0 >= r0 + TBM; };
+    tile_mma<BN>(L, c, acc, loadA, loadB, alongK);
+    tile_epilogue<BN>(acc, [&](int i, int j, double v) {
+        const int ii = r0 + i, jj = n0 + j;
+        if (ii < c && jj < s) Ap[d.poff + s + ii + (int64_t)jj * ld] = -v;
+    });
+}
+
+__global__ __launch_bounds__(kThreads) void k_gemm(const Task* __restrict__ tasks, const BlockDesc* __restrict__ blk,
+                                                   double* __restrict__ Ap, const double* __restrict__ Hp,
+                                                   const int64_t* __restrict__ cbase,
+                                                   const int64_t* __restrict__ rbase,
+                                                   const int32_t* __restrict__ rel)
+{
+    __shared__ TileLds L;
     const Task t = tasks[blockIdx.x];
     const BlockDesc d = blk[t.b];
+#define SELINV_CALL(BN) gemm_task<BN>(L, t, d, Ap, Hp, cbase, rbase, rel)
+    SELINV_BN_DISPATCH(t.k0, SELINV_CALL)
+#undef SELINV_CALL
+}
+
+// ---------------------------------------------------------------------------
+// Factor panel (Algorithm 1 step 2, fused into the factorization):
+// L_hat(C,B) = F(C,B) T for rows [i0, i0+64), columns [j0, j0+BN).
+// ---------------------------------------------------------------------------
+template <int BN>
+__device__ void panel_task(TileLds& L, const Task t, const BlockDesc d, const double* __restrict__ Lp,
+                           double* __restrict__ Hp, const double* __restrict__ Tp)
+{
+    const int s = d.s, c = d.c;
+    const int64_t ld = (int64_t)s + c;
+    const int r0 = t.i0, n0 = t.j0;
+    d4 acc[2][4] = {};
+    const double* F = Lp + d.poff + s;
+    const double* T = Tp + d.woff;
+    auto loadA = [&](int k0, int kk, int ii) -> double {
+        const int i = r0 + ii, k = k0 + kk;
+        return (i < c && k < s) ? F[i + k * ld] : 0.0;
+    };
+    auto loadB = [&](int k0, int kk, int j) -> double {
+        const int k = k0 + kk, jj = n0 + j;
+        return (k < s && jj < s) ? T[k + jj * s] : 0.0;
+    };
+    tile_mma<BN>(L, s, acc, loadA, loadB, [](int) { return false; });
+    tile_epilogue<BN>(acc, [&](int i, int j, double v) {
+        const int ii = r0 + i, jj = n0 + j;
+        if (ii < c && jj < s) Hp[d.hoff + ii + (int64_t)jj * c] = v;
+    });
+}
+
+__global__ __launch_bounds__(kThreads) void k_panel(const Task* __restrict__ tasks,
+                                                    const BlockDesc* __restrict__ blk, const double* __restrict__ Lp,
+                                                    double* __restrict__ Hp, const double* __restrict__ Tp)
+{
+    __shared__ TileLds L;
+    const Task t = tasks[blockIdx.x];
+    const BlockDesc d = blk[t.b];
+#define SELINV_CALL(BN) panel_task<BN>(L, t, d, Lp, Hp, Tp)
+    SELINV_BN_DISPATCH(t.k0, SELINV_CALL)
+#undef SELINV_CALL
+}
+
+// ---------------------------------------------------------------------------
+// Factor, Schur update: F(C,C) -= L(C,B) D_B L(C,B)^T = L_hat(C,B) F(C,B)^T,
+// lower half, tile rows [i0, i0+64) x columns [k0, k0+64), added into the
+// ancestor panels through the block index maps.  FP64 atomics: sibling
+// blocks of one level may update the same ancestor entry.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_schur(const Task* __restrict__ tasks,
+                                                    const BlockDesc* __restrict__ blk, double* __restrict__ Lp,
+                                                    const double* __restrict__ Hp,
+                                                    const int64_t* __restrict__ cbase,
+                                                    const int64_t* __restrict__ rbase,
+                                                    const int32_t* __restrict__ rel)
+{
+    __shared__ TileLds L;
+    const Task t = tasks[blockIdx.x];
+    const BlockDesc d = blk[t.b];
+    const int s = d.s, c = d.c;
+    const int64_t ld = (int64_t)s + c;
+    const int i0 = t.i0, k0c = t.j0;
+    const double* H = Hp + d.hoff;
+    const double* F = Lp + d.poff + s;
+    d4 acc[2][4] = {};
+    auto loadA = [&](int t0, int tt, int ii) -> double {
+        const int i = i0 + ii, k = t0 + tt;
+        return (i < c && k < s) ? H[i + (int64_t)k * c] : 0.0;
+    };
+    auto loadB = [&](int t0, int tt, int j) -> double {
+        const int k = k0c + j, col = t0 + tt;
+        return (k < c && col < s) ? F[k + col * ld] : 0.0;
+    };
+    tile_mma<64>(L, s, acc, loadA, loadB, [](int) { return false; });
+    tile_epilogue<64>(acc, [&](int i, int j, double v) {
+        const int ii = i0 + i, kk = k0c + j;
+        if (ii < c && kk < c && ii >= kk) {
+            const int64_t pk = d.coff + kk;
+            unsafeAtomicAdd(Lp + cbase[pk] + rel[rbase[pk] + ii], -v);
+        }
+    });
+}
+
+// ---------------------------------------------------------------------------
+// Selected inversion, step 4 + symmetrisation, one pair of 32 x 32 tiles
+// (I, J), I >= J, of the diagonal block per work-group:
+//   Y(I,J) = T(I,J) - L_hat(:,I)^T X(:,J),  Y(J,I) = T(J,I) - L_hat(:,J)^T X(:,I)
+//   Ainv(I,J) = Ainv(J,I)^T = (Y(I,J) + Y(J,I)^T) / 2.
+// ---------------------------------------------------------------------------
+constexpr int SDT = 32;
+
+__global__ __launch_bounds__(kThreads) void k_sdiag(const Task* __restrict__ tasks, const BlockDesc* __restrict__ blk,
+                                                    double* __restrict__ Ap, const double* __restrict__ Hp,
+                                                    const double* __restrict__ Tp)
+{
+    __shared__ double LI[16][SDT + 1], LJ[16][SDT + 1], XI[16][SDT + 1], XJ[16][SDT + 1];
+    __shared__ double Sx[SDT][SDT + 1];
+    const Task t = tasks[blockIdx.x];
+    const BlockDesc d = blk[t.b];
+    const int s = d.s, c = d.c;
+    const int64_t ld = (int64_t)s + c;
+    const int I0 = t.i0, J0 = t.j0;
+    double* A = Ap + d.poff;
+    const double* H = Hp + d.hoff;
+    const double* T = Tp + d.woff;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int fm = (wave & 1) * 16, fn = (wave >> 1) * 16;
+    d4 accIJ = {0, 0, 0, 0}, accJI = {0, 0, 0, 0};
+    // Branch-free body: a diagonal tile (I == J) simply recomputes its own
+    // product as the partner.  Control flow between an FP64 MFMA and a read
+    // of its accumulator let the compiler place the read too early.
+    for (int r0 = 0; r0 < c; r0 += 16) {
+#pragma unroll
+        for (int q = 0; q < (16 * SDT) / kThreads; ++q) {
+            const int e = threadIdx.x + q * kThreads;
+            const int kk = e & 15, col = e >> 4;
+            const int r = r0 + kk;
+            const bool okr = r < c;
+            const int ci = I0 + col, cj = J0 + col;
+            const double li = (okr && ci < s) ? H[r + (int64_t)ci * c] : 0.0;
+            const double lj = (okr && cj < s) ? H[r + (int64_t)cj * c] : 0.0;
+            const double xi = (okr && ci < s) ? A[s + r + ci * ld] : 0.0;
+            const double xj = (okr && cj < s) ? A[s + r + cj * ld] : 0.0;
+            LI[kk][col] = li;
+            LJ[kk][col] = lj;
+            XI[kk][col] = xi;
+            XJ[kk][col] = xj;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int kr = ks * 4 + (lane >> 4);
+            accIJ = mfma(LI[kr][fm + (lane & 15)], XJ[kr][fn + (lane & 15)], accIJ);
+            accJI = mfma(LJ[kr][fm + (lane & 15)], XI[kr][fn + (lane & 15)], accJI);
+        }
+        __syncthreads();
+    }
+    mfma_drain();
+    // Sx[b][a] = Y(J,I)(a, b): element (a, b) of the transposed partner tile
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int i = fm + (lane >> 4) + 4 * v, j = fn + (lane & 15);
+        Sx[j][i] = (J0 + i < s && I0 + j < s) ? T[(J0 + i) + (I0 + j) * s] - accJI[v] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int i = fm + (lane >> 4) + 4 * v, j = fn + (lane & 15);
+        const int gi = I0 + i, gj = J0 + j;
+        if (gi < s && gj < s) {
+            const double yij = T[gi + gj * s] - accIJ[v];
+            const double m = 0.5 * (yij + Sx[i][j]);
+            A[gi + gj * ld] = m;
+            A[gj + gi * ld] = m;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Factor, diagonal block, s <= kLdsDiagMax: the s x s block lives in LDS.
+// Right-looking LDL^T without pivoting; the same row operations applied to
+// the identity build W = L_BB^{-1}, kept in the (otherwise unused) upper
+// triangle: W(i,k), i > k, at S[k][i].  Then T = W^T D^{-1} W on MFMA (lower
+// 16 x 16 tiles, mirrored).  A pivot that is zero, not finite, or
+// (require_spd) not positive is latched as the smallest failing column.
+// Larger blocks take the same steps on global memory.
+// ---------------------------------------------------------------------------
+__device__ void ldlt_global(const BlockDesc d, double* __restrict__ Lp, double* __restrict__ Wp,
+                            double* __restrict__ Tp, unsigned long long* __restrict__ status, int require_spd)
+{
     const int s = d.s;
     const int64_t ld = (int64_t)d.s + d.c;
     double* F = Lp + d.poff;
@@ -71,7 +421,6 @@ __global__ __launch_bounds__(kThreads) void k_ldlt_diag(const Task* __restrict__
         const bool ok = isfinite(dj) && dj != 0.0 && (!require_spd || dj > 0.0);
         if (!ok && tid == 0) atomicMin(status, (unsigned long long)(d.first + j));
         const int m = s - j - 1;
-        // L(i,j) for i > j inside the block: keep F(i,j) for the update first
         for (int e = tid; e < m * m; e += kThreads) {
             const int ii = e % m, kk = e / m;
             if (ii >= kk) {
@@ -83,7 +432,6 @@ __global__ __launch_bounds__(kThreads) void k_ldlt_diag(const Task* __restrict__
         for (int i = j + 1 + tid; i < s; i += kThreads) F[i + j * ld] /= dj;
     }
     __syncthreads();
-    // W = L^{-1}: column j by forward substitution (one thread per column)
     for (int j = tid; j < s; j += kThreads) {
         for (int i = 0; i < j; ++i) W[i + j * s] = 0.0;
         W[j + j * s] = 1.0;
@@ -94,7 +442,6 @@ __global__ __launch_bounds__(kThreads) void k_ldlt_diag(const Task* __restrict__
         }
     }
     __syncthreads();
-    // T(i,j) = sum_{k >= max(i,j)} W(k,i) W(k,j) / d_k
     for (int e = tid; e < s * s; e += kThreads) {
         const int i = e % s, j = e / s;
         const int m = i > j ? i : j;
@@ -104,188 +451,84 @@ __global__ __launch_bounds__(kThreads) void k_ldlt_diag(const Task* __restrict__
     }
 }
 
-// ---------------------------------------------------------------------------
-// Factor, panel: L(C,B) = F(C,B) W^T D^{-1} (in place) and, fused,
-// the normalised panel L_hat(C,B) = L(C,B) W = F(C,B) T (Algorithm 1 step 2).
-// One work-group per kPanelRows rows of C(B).
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_panel(const Task* __restrict__ tasks,
-                                                    const BlockDesc* __restrict__ blk, double* __restrict__ Lp,
-                                                    double* __restrict__ Hp, const double* __restrict__ Wp,
-                                                    const double* __restrict__ Tp)
+__global__ __launch_bounds__(kThreads) void k_ldlt_diag(const Task* __restrict__ tasks,
+                                                        const BlockDesc* __restrict__ blk, double* __restrict__ Lp,
+                                                        double* __restrict__ Wp, double* __restrict__ Tp,
+                                                        unsigned long long* __restrict__ status, int require_spd)
 {
-    __shared__ double Fs[kPanelRows][kMaxS + 1];
+    extern __shared__ double S[];
     const Task t = tasks[blockIdx.x];
     const BlockDesc d = blk[t.b];
-    const int s = d.s, c = d.c;
-    const int64_t ld = (int64_t)s + c;
+    const int s = d.s;
+    if (s > kLdsDiagMax) {
+        ldlt_global(d, Lp, Wp, Tp, status, require_spd);
+        return;
+    }
+    const int64_t ld = (int64_t)d.s + d.c;
     double* F = Lp + d.poff;
-    const double* W = Wp + d.woff;
-    const double* T = Tp + d.woff;
-    const int r0 = t.i0;
-    const int nr = min(kPanelRows, c - r0);
-    for (int e = threadIdx.x; e < kPanelRows * s; e += kThreads) {
-        const int rr = e % kPanelRows, k = e / kPanelRows;
-        Fs[rr][k] = rr < nr ? F[s + r0 + rr + k * ld] : 0.0;
+    const int ls = s + 1;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < s * s; e += kThreads) {
+        const int i = e % s, k = e / s;
+        S[i * ls + k] = (k <= i) ? F[i + k * ld] : 0.0;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < kPanelRows * s; e += kThreads) {
-        const int rr = e % kPanelRows, j = e / kPanelRows;
-        if (rr >= nr) continue;
-        double v = 0.0;
-        for (int k = 0; k <= j; ++k) v += Fs[rr][k] * W[j + k * s];
-        double h = 0.0;
-        for (int k = 0; k < s; ++k) h += Fs[rr][k] * T[k + j * s];
-        F[s + r0 + rr + j * ld] = v / F[j + j * ld];
-        Hp[d.hoff + r0 + rr + (int64_t)j * c] = h;
+    for (int j = 0; j < s; ++j) {
+        const double dj = S[j * ls + j];
+        if (tid == 0) {
+            const bool ok = isfinite(dj) && dj != 0.0 && (!require_spd || dj > 0.0);
+            if (!ok) atomicMin(status, (unsigned long long)(d.first + j));
+        }
+        const int rows = s - j - 1;
+        for (int e = tid; e < rows * s; e += kThreads) {
+            const int i = j + 1 + e / s, k = e % s;
+            if (k == j || k > i) continue;
+            const double lraw = S[i * ls + j];
+            if (k > j) S[i * ls + k] -= lraw * S[k * ls + j] / dj;  // trailing update of F
+            else S[k * ls + i] -= (lraw / dj) * S[k * ls + j];      // W(i,k) -= l_ij W(j,k)
+        }
+        __syncthreads();
+        for (int i = j + 1 + tid; i < s; i += kThreads) {
+            const double l = S[i * ls + j] / dj;
+            S[i * ls + j] = l;
+            S[j * ls + i] = -l;  // W(i,j) = -l_ij
+        }
+        __syncthreads();
     }
-}
-
-// ---------------------------------------------------------------------------
-// Factor, Schur update: F(C,C) -= L(C,B) D_B L(C,B)^T, lower half, added into
-// the ancestor panels through the block index maps (FP64 atomics: sibling
-// blocks of one level may update the same ancestor entry).
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_schur(const Task* __restrict__ tasks,
-                                                    const BlockDesc* __restrict__ blk, double* __restrict__ Lp,
-                                                    const int64_t* __restrict__ cbase,
-                                                    const int64_t* __restrict__ rbase,
-                                                    const int32_t* __restrict__ rel)
-{
-    constexpr int TS = kSchurTile;
-    __shared__ double As[TS][TS + 1];
-    __shared__ double Bs[TS][TS + 1];
-    const Task t = tasks[blockIdx.x];
-    const BlockDesc d = blk[t.b];
-    const int s = d.s, c = d.c;
-    const int64_t ld = (int64_t)s + c;
-    const double* F = Lp + d.poff;
-    const int i0 = t.i0, k0 = t.j0;
-    const int ii = threadIdx.x % TS, kq = threadIdx.x / TS;  // kq in 0..7, 4 columns each
-    double acc[4] = {0, 0, 0, 0};
-    for (int t0 = 0; t0 < s; t0 += TS) {
-        for (int e = threadIdx.x; e < TS * TS; e += kThreads) {
-            const int r = e % TS, tt = e / TS;
-            const int col = t0 + tt;
-            double a = 0.0, b = 0.0;
-            if (col < s) {
-                const double dc = F[col + col * ld];
-                if (i0 + r < c) a = F[s + i0 + r + col * ld] * dc;
-                if (k0 + r < c) b = F[s + k0 + r + col * ld];
+    // write L_BB (with D) back and W = L^{-1}
+    double* W = Wp + d.woff;
+    for (int e = tid; e < s * s; e += kThreads) {
+        const int i = e % s, k = e / s;
+        if (k <= i) F[i + k * ld] = S[i * ls + k];
+        W[e] = (i == k) ? 1.0 : (i > k ? S[k * ls + i] : 0.0);
+    }
+    // T = W^T D^{-1} W on the lower 16 x 16 tiles, mirrored
+    double* T = Tp + d.woff;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int nt = (s + 15) / 16;
+    auto Wv = [&](int k, int i) -> double {  // W(k, i)
+        if (k >= s || i >= s) return 0.0;
+        return k == i ? 1.0 : (k > i ? S[i * ls + k] : 0.0);
+    };
+    for (int p = wave; p < nt * (nt + 1) / 2; p += kThreads / 64) {
+        int I = 0;
+        while ((I + 1) * (I + 2) / 2 <= p) ++I;
+        const int J = p - I * (I + 1) / 2;
+        const int i0 = I * 16, j0 = J * 16;
+        d4 acc = {0, 0, 0, 0};
+        for (int k4 = i0; k4 < s; k4 += 4) {  // W(k, i) = 0 for k < i, and i >= j
+            const int k = k4 + (lane >> 4);
+            const double dk = k < s ? S[k * ls + k] : 1.0;
+            acc = mfma(Wv(k, i0 + (lane & 15)), Wv(k, j0 + (lane & 15)) / dk, acc);
+        }
+        mfma_drain();
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = i0 + (lane >> 4) + 4 * v, j = j0 + (lane & 15);
+            if (i < s && j < s) {
+                T[i + j * s] = acc[v];
+                T[j + i * s] = acc[v];
             }
-            As[r][tt] = a;
-            Bs[r][tt] = b;
-        }
-        __syncthreads();
-#pragma unroll 4
-        for (int tt = 0; tt < TS; ++tt) {
-            const double a = As[ii][tt];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) acc[q] += a * Bs[kq * 4 + q][tt];
-        }
-        __syncthreads();
-    }
-    const int i = i0 + ii;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int k = k0 + kq * 4 + q;
-        if (i < c && k < c && i >= k) {
-            const int64_t pk = d.coff + k;
-            unsafeAtomicAdd(Lp + cbase[pk] + rel[rbase[pk] + i], -acc[q]);
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Selected inversion, step 3: X = Ainv(C,B) = -Ainv(C,C) L_hat(C,B).
-// Ainv(C,C) is gathered from the ancestors' panels (lower entries directly,
-// upper entries through symmetry) into LDS tiles.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_gemm(const Task* __restrict__ tasks, const BlockDesc* __restrict__ blk,
-                                                   double* __restrict__ Ap, const double* __restrict__ Hp,
-                                                   const int64_t* __restrict__ cbase,
-                                                   const int64_t* __restrict__ rbase,
-                                                   const int32_t* __restrict__ rel)
-{
-    constexpr int BM = kGemmBM, BN = kGemmBN, BK = kGemmBK;
-    __shared__ double Gs[BK][BM + 1];
-    __shared__ double Ls[BK][BN + 1];
-    const Task t = tasks[blockIdx.x];
-    const BlockDesc d = blk[t.b];
-    const int s = d.s, c = d.c;
-    const int64_t ld = (int64_t)s + c;
-    const int r0 = t.i0, n0 = t.j0;
-    const int rr = threadIdx.x % BM, nq = threadIdx.x / BM;  // 8 groups of 4 columns
-    const double* H = Hp + d.hoff;
-    double acc[4] = {0, 0, 0, 0};
-    for (int k0 = 0; k0 < c; k0 += BK) {
-        for (int e = threadIdx.x; e < BM * BK; e += kThreads) {
-            const int r = e % BM, kk = e / BM;
-            const int i = r0 + r, k = k0 + kk;
-            double g = 0.0;
-            if (i < c && k < c) {
-                if (i >= k) {
-                    const int64_t pk = d.coff + k;
-                    g = Ap[cbase[pk] + rel[rbase[pk] + i]];
-                } else {
-                    const int64_t pi = d.coff + i;
-                    g = Ap[cbase[pi] + rel[rbase[pi] + k]];
-                }
-            }
-            Gs[kk][r] = g;
-        }
-        for (int e = threadIdx.x; e < BK * BN; e += kThreads) {
-            const int kk = e % BK, nn = e / BK;
-            const int k = k0 + kk, j = n0 + nn;
-            Ls[kk][nn] = (k < c && j < s) ? H[k + (int64_t)j * c] : 0.0;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < BK; ++kk) {
-            const double g = Gs[kk][rr];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) acc[q] += g * Ls[kk][nq * 4 + q];
-        }
-        __syncthreads();
-    }
-    const int i = r0 + rr;
-    if (i < c) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int j = n0 + nq * 4 + q;
-            if (j < s) Ap[d.poff + s + i + (int64_t)j * ld] = -acc[q];
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Selected inversion, step 4 + symmetrisation:
-// Y = T - L_hat^T X, Ainv(B,B) = (Y + Y^T)/2.  One work-group per block.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_sdiag(const Task* __restrict__ tasks, const BlockDesc* __restrict__ blk,
-                                                    double* __restrict__ Ap, const double* __restrict__ Hp,
-                                                    const double* __restrict__ Tp)
-{
-    const Task t = tasks[blockIdx.x];
-    const BlockDesc d = blk[t.b];
-    const int s = d.s, c = d.c;
-    const int64_t ld = (int64_t)s + c;
-    double* A = Ap + d.poff;
-    const double* H = Hp + d.hoff;
-    const double* T = Tp + d.woff;
-    for (int e = threadIdx.x; e < s * s; e += kThreads) {
-        const int i = e % s, j = e / s;
-        double v = 0.0;
-        for (int r = 0; r < c; ++r) v += H[r + (int64_t)i * c] * A[s + r + j * ld];
-        A[i + j * ld] = T[e] - v;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < s * s; e += kThreads) {
-        const int i = e % s, j = e / s;
-        if (i > j) {
-            const double m = 0.5 * (A[i + j * ld] + A[j + i * ld]);
-            A[i + j * ld] = m;
-            A[j + i * ld] = m;
         }
     }
 }
@@ -293,6 +536,35 @@ __global__ __launch_bounds__(kThreads) void k_sdiag(const Task* __restrict__ tas
 // ---------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------
+hipEvent_t Prof::next()
+{
+    if (used == pool.size()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        pool.push_back(e);
+    }
+    return pool[used++];
+}
+
+Prof::~Prof()
+{
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+}
+
+template <class Kern, class... Args>
+static void launch(Prof* P, int kind, Kern kern, dim3 grid, size_t shmem, hipStream_t s, Args... args)
+{
+    if (P && P->on) {
+        hipEvent_t a = P->next(), z = P->next();
+        if (a && z) {
+            hipExtLaunchKernelGGL(kern, grid, dim3(kThreads), (uint32_t)shmem, s, a, z, 0, args...);
+            P->kinds.push_back(kind);
+            return;
+        }
+    }
+    hipLaunchKernelGGL(kern, grid, dim3(kThreads), shmem, s, args...);
+}
+
 static inline unsigned grid_for(int64_t n)
 {
     int64_t g = (n + kThreads - 1) / kThreads;
@@ -301,57 +573,74 @@ static inline unsigned grid_for(int64_t n)
     return (unsigned)g;
 }
 
+hipError_t kernels_init()
+{
+    // the LDS diagonal factorization needs more than the default 64 KB
+    return hipFuncSetAttribute((const void*)k_ldlt_diag, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)kLdsDiagBytes);
+}
+
 hipError_t launch_status_reset(unsigned long long* status, hipStream_t s)
 {
     hipLaunchKernelGGL(k_status_reset, dim3(1), dim3(64), 0, s, status);
     return hipGetLastError();
 }
 
-hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s)
+hipError_t launch_fill(Prof* P, int kind, double* p, int64_t n, double v, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(kThreads), 0, s, p, n, v);
+    launch(P, kind, k_fill, dim3(grid_for(n)), 0, s, p, n, v);
     return hipGetLastError();
 }
 
-hipError_t launch_scatter_set(const double* src, const int64_t* off, int64_t n, double* dst, hipStream_t s)
+hipError_t launch_scatter_set(Prof* P, int kind, const double* src, const int64_t* off, int64_t n, double* dst,
+                              hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_scatter_set, dim3(grid_for(n)), dim3(kThreads), 0, s, src, off, n, dst);
+    launch(P, kind, k_scatter_set, dim3(grid_for(n)), 0, s, src, off, n, dst);
     return hipGetLastError();
 }
 
-hipError_t launch_gather(const double* src, const int64_t* off, int64_t n, double* dst, hipStream_t s)
+hipError_t launch_gather(Prof* P, int kind, const double* src, const int64_t* off, int64_t n, double* dst,
+                         hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gather, dim3(grid_for(n)), dim3(kThreads), 0, s, src, off, n, dst);
+    launch(P, kind, k_gather, dim3(grid_for(n)), 0, s, src, off, n, dst);
     return hipGetLastError();
 }
 
-hipError_t launch_factor_level(const DevPtrs& D, int64_t diag0, int64_t ndiag, int64_t panel0, int64_t npanel,
-                               int64_t schur0, int64_t nschur, int require_spd, hipStream_t s)
+hipError_t launch_export_L(Prof* P, const DevPtrs& D, int64_t n, double* out, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    launch(P, kExport, k_export_L, dim3(grid_for(n)), 0, s, D.blocks, D.colblk, D.colptrL, D.exp_off, n,
+           (const double*)D.Lp, (const double*)D.Hp, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_factor_level(Prof* P, const DevPtrs& D, int64_t diag0, int64_t ndiag, int64_t panel0,
+                               int64_t npanel, int64_t schur0, int64_t nschur, int require_spd, hipStream_t s)
 {
     if (ndiag > 0)
-        hipLaunchKernelGGL(k_ldlt_diag, dim3((unsigned)ndiag), dim3(kThreads), 0, s, D.t_diag + diag0, D.blocks,
-                           D.Lp, D.Wp, D.Tp, D.status, require_spd);
+        launch(P, kLdlt, k_ldlt_diag, dim3((unsigned)ndiag), kLdsDiagBytes, s, D.t_diag + diag0, D.blocks, D.Lp,
+               D.Wp, D.Tp, D.status, require_spd);
     if (npanel > 0)
-        hipLaunchKernelGGL(k_panel, dim3((unsigned)npanel), dim3(kThreads), 0, s, D.t_panel + panel0, D.blocks,
-                           D.Lp, D.Hp, D.Wp, D.Tp);
+        launch(P, kPanel, k_panel, dim3((unsigned)npanel), 0, s, D.t_panel + panel0, D.blocks,
+               (const double*)D.Lp, D.Hp, (const double*)D.Tp);
     if (nschur > 0)
-        hipLaunchKernelGGL(k_schur, dim3((unsigned)nschur), dim3(kThreads), 0, s, D.t_schur + schur0, D.blocks,
-                           D.Lp, D.cbase, D.rbase, D.rel);
+        launch(P, kSchur, k_schur, dim3((unsigned)nschur), 0, s, D.t_schur + schur0, D.blocks, D.Lp,
+               (const double*)D.Hp, D.cbase, D.rbase, D.rel);
     return hipGetLastError();
 }
 
-hipError_t launch_invert_level(const DevPtrs& D, int64_t gemm0, int64_t ngemm, int64_t sdiag0, int64_t nsdiag,
-                               hipStream_t s)
+hipError_t launch_invert_level(Prof* P, const DevPtrs& D, int64_t gemm0, int64_t ngemm, int64_t sdiag0,
+                               int64_t nsdiag, hipStream_t s)
 {
     if (ngemm > 0)
-        hipLaunchKernelGGL(k_gemm, dim3((unsigned)ngemm), dim3(kThreads), 0, s, D.t_gemm + gemm0, D.blocks, D.Ap,
-                           D.Hp, D.cbase, D.rbase, D.rel);
+        launch(P, kGemm, k_gemm, dim3((unsigned)ngemm), 0, s, D.t_gemm + gemm0, D.blocks, D.Ap,
+               (const double*)D.Hp, D.cbase, D.rbase, D.rel);
     if (nsdiag > 0)
-        hipLaunchKernelGGL(k_sdiag, dim3((unsigned)nsdiag), dim3(kThreads), 0, s, D.t_sdiag + sdiag0, D.blocks,
-                           D.Ap, D.Hp, D.Tp);
+        launch(P, kSdiag, k_sdiag, dim3((unsigned)nsdiag), 0, s, D.t_sdiag + sdiag0, D.blocks, D.Ap,
+               (const double*)D.Hp, (const double*)D.Tp);
     return hipGetLastError();
 }
 

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <cstdint>
+#include <vector>
 
 #include "plan.hpp"
 
@@ -17,16 +18,22 @@ struct DevPtrs {
     const int64_t *cbase, *rbase;
     const int32_t* rel;
     const int64_t *asm_off, *exp_off;
+    const int32_t* colblk;     // column -> execution block
+    const int64_t* colptrL;    // canonical column pointers of L
     const Task *t_diag, *t_panel, *t_schur, *t_gemm, *t_sdiag;
 };
 
+hipError_t kernels_init();
+hipError_t launch_export_L(Prof* P, const DevPtrs& D, int64_t n, double* out, hipStream_t s);
 hipError_t launch_status_reset(unsigned long long* status, hipStream_t s);
-hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
-hipError_t launch_scatter_set(const double* src, const int64_t* off, int64_t n, double* dst, hipStream_t s);
-hipError_t launch_gather(const double* src, const int64_t* off, int64_t n, double* dst, hipStream_t s);
-hipError_t launch_factor_level(const DevPtrs& D, int64_t diag0, int64_t ndiag, int64_t panel0, int64_t npanel,
-                               int64_t schur0, int64_t nschur, int require_spd, hipStream_t s);
-hipError_t launch_invert_level(const DevPtrs& D, int64_t gemm0, int64_t ngemm, int64_t sdiag0, int64_t nsdiag,
-                               hipStream_t s);
+hipError_t launch_fill(Prof* P, int kind, double* p, int64_t n, double v, hipStream_t s);
+hipError_t launch_scatter_set(Prof* P, int kind, const double* src, const int64_t* off, int64_t n, double* dst,
+                              hipStream_t s);
+hipError_t launch_gather(Prof* P, int kind, const double* src, const int64_t* off, int64_t n, double* dst,
+                         hipStream_t s);
+hipError_t launch_factor_level(Prof* P, const DevPtrs& D, int64_t diag0, int64_t ndiag, int64_t panel0,
+                               int64_t npanel, int64_t schur0, int64_t nschur, int require_spd, hipStream_t s);
+hipError_t launch_invert_level(Prof* P, const DevPtrs& D, int64_t gemm0, int64_t ngemm, int64_t sdiag0,
+                               int64_t nsdiag, hipStream_t s);
 
 }  // namespace selinv

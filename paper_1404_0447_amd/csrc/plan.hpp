@@ -46,9 +46,23 @@ struct LevelTasks {
     std::vector<int64_t> off;  // per level (index = level-1): tasks[off[l] .. off[l+1])
 };
 
+// Kernel kinds (same numbering as SELINV_K_* in selinv.h).
+enum Kind { kAssemble = 0, kLdlt, kPanel, kSchur, kGemm, kSdiag, kExport, kNumKinds };
+
+// Optional per-launch timing: start/stop events are stamped by the dispatch
+// itself (hipExtLaunchKernelGGL), so no marker packets are added.
+struct Prof {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    std::vector<int> kinds;  // launch i used events 2i, 2i+1
+    hipEvent_t next();
+    ~Prof();
+};
+
 struct DeviceLayout {
     // byte offsets into the workspace
-    size_t lp, ap, hp, wp, tp, status, blocks, crow, cbase, rbase, rel, asm_off, exp_off;
+    size_t lp, ap, hp, wp, tp, status, blocks, crow, cbase, rbase, rel, asm_off, exp_off, colblk, colptrL;
     size_t t_diag, t_panel, t_schur, t_gemm, t_sdiag, total;
 };
 
@@ -72,6 +86,7 @@ struct selinv_plan_s {
     std::vector<int64_t> cbase, rbase;
     std::vector<int32_t> rel;
     std::vector<int64_t> asm_off, exp_off;
+    std::vector<int32_t> colblk;       // column -> execution block
     int64_t arena = 0, harena = 0, warena = 0;
     selinv::LevelTasks t_diag, t_panel, t_schur, t_gemm, t_sdiag;
     selinv::DeviceLayout lay{};
@@ -80,6 +95,8 @@ struct selinv_plan_s {
     char* ws = nullptr;
     size_t ws_bytes = 0;
     bool factored = false;
+    selinv::Prof prof;
+    std::vector<double> work_flops, work_bytes;  // per kernel kind, per call
 };
 
 namespace selinv {

@@ -2,6 +2,7 @@
 // levels from the leaves up, the inversion from the root down; all blocks of
 // one level are independent (Section 2.2), so each level is one launch per
 // kernel kind with one work-group per task.
+#include "kernels.hpp"
 #include "plan.hpp"
 #include "tiles.hpp"
 
@@ -26,16 +27,40 @@ void build_schedule(selinv_plan_s* P)
     for (int l = 0; l < D; l++) {
         for (int B : lv[l]) {
             const BlockDesc& d = P->blocks[B];
+            const int bn = tile_bn(d.s);
             P->t_diag.tasks.push_back({B, 0, 0, 0});
-            P->t_sdiag.tasks.push_back({B, 0, 0, 0});
-            for (int r = 0; r < d.c; r += kPanelRows) P->t_panel.tasks.push_back({B, r, 0, 0});
+            const int nd = (d.s + kDiagTile - 1) / kDiagTile;
+            for (int I = 0; I < nd; I++)
+                for (int J = 0; J <= I; J++) P->t_sdiag.tasks.push_back({B, I * kDiagTile, J * kDiagTile, 0});
+            for (int j = 0; j < d.s; j += bn)
+                for (int r = 0; r < d.c; r += kTileM) {
+                    P->t_panel.tasks.push_back({B, r, j, bn});
+                    P->t_gemm.tasks.push_back({B, r, j, bn});
+                }
             for (int k = 0; k < d.c; k += kSchurTile)
-                for (int i = k; i < d.c; i += kSchurTile) P->t_schur.tasks.push_back({B, i, k, 0});
-            for (int j = 0; j < d.s; j += kGemmBN)
-                for (int r = 0; r < d.c; r += kGemmBM) P->t_gemm.tasks.push_back({B, r, j, 0});
+                for (int i = k; i < d.c; i += kSchurTile) P->t_schur.tasks.push_back({B, i, k, kSchurTile});
         }
         for (LevelTasks* t : all) t->off[l + 1] = (int64_t)t->tasks.size();
     }
+    // algorithmic work of one factor / one invert call, per kernel kind
+    P->work_flops.assign(kNumKinds, 0.0);
+    P->work_bytes.assign(kNumKinds, 0.0);
+    for (const BlockDesc& d : P->blocks) {
+        const double s = d.s, c = d.c;
+        P->work_flops[kLdlt] += s * s * s;              // LDL^T s^3/3, W s^3/3, T s^3/3
+        P->work_bytes[kLdlt] += 8.0 * 3 * s * s;
+        P->work_flops[kPanel] += 2.0 * c * s * s;       // L_hat = F(C,B) T
+        P->work_bytes[kPanel] += 8.0 * (2 * c * s + s * s);
+        P->work_flops[kSchur] += c * c * s;             // lower half of L D L^T
+        P->work_bytes[kSchur] += 8.0 * (c * s + c * (c + 1) / 2);
+        P->work_flops[kGemm] += 2.0 * c * c * s;        // X = -G L_hat
+        P->work_bytes[kGemm] += 8.0 * (c * (c + 1) / 2 + 2 * c * s);
+        P->work_flops[kSdiag] += 2.0 * c * s * s;       // Y = T - L_hat^T X
+        P->work_bytes[kSdiag] += 8.0 * (2 * c * s + 2 * s * s);
+    }
+    const double nnzL = (double)P->colptrL.back(), nnzA = (double)P->nnzA;
+    P->work_bytes[kAssemble] = 8.0 * P->arena + 24.0 * nnzA;
+    P->work_bytes[kExport] = 24.0 * nnzL;
 }
 
 }  // namespace selinv

@@ -1,12 +1,16 @@
 // Tile shapes shared by the scheduler (task lists) and the kernels.
 #pragma once
+#include <cstddef>
 
 namespace selinv {
-constexpr int kThreads = 256;   // work-group size of every tiled kernel
-constexpr int kMaxS = 256;      // widest supported block (cap)
-constexpr int kPanelRows = 16;  // rows of C(K) per factor panel task
-constexpr int kSchurTile = 32;  // edge of a Schur-update tile (lower c x c)
-constexpr int kGemmBM = 32;     // rows of X per gather-GEMM task
-constexpr int kGemmBN = 32;     // columns of X per gather-GEMM task
-constexpr int kGemmBK = 16;     // contraction chunk staged in LDS
+constexpr int kThreads = 256;    // work-group size of every tiled kernel (4 waves)
+constexpr int kMaxS = 256;       // widest supported block (cap)
+constexpr int kTileM = 64;       // rows of an MFMA output tile (gather-GEMM, panel, Schur)
+constexpr int kSchurTile = 64;   // edge of a Schur-update tile (lower c x c)
+constexpr int kDiagTile = 32;    // edge of a diagonal-block tile (pairs (I,J), I >= J)
+constexpr int kLdsDiagMax = 128; // diagonal factorization in LDS up to this width
+constexpr size_t kLdsDiagBytes = sizeof(double) * kLdsDiagMax * (kLdsDiagMax + 1);
+
+// output-column tile of a block of width s: 16, 32, 64 or 128
+inline int tile_bn(int s) { return s <= 16 ? 16 : s <= 32 ? 32 : s <= 64 ? 64 : 128; }
 }  // namespace selinv

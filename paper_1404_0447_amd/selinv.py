@@ -21,7 +21,11 @@ _NAMES = {0: "OK", -1: "EINVAL", -2: "ESTATE", -3: "EPIVOT", -4: "ENOMEM", -5: "
 # every symbol include/selinv.h declares
 EXPORTS = ["selinv_analyze", "selinv_workspace_size", "selinv_bind_workspace", "selinv_factor", "selinv_invert",
            "selinv_get_factor", "selinv_sync_status", "selinv_get_info", "selinv_get_pattern",
-           "selinv_symbolic_sizes", "selinv_get_symbolic", "selinv_last_error", "selinv_destroy"]
+           "selinv_symbolic_sizes", "selinv_get_symbolic", "selinv_profile", "selinv_profile_read",
+           "selinv_kernel_work", "selinv_get_arena", "selinv_get_blocks", "selinv_get_exec_rows",
+           "selinv_last_error", "selinv_destroy"]
+ARENAS = {"L": 0, "Ainv": 1, "Lhat": 2, "W": 3, "T": 4}
+KINDS = ["assemble", "ldlt", "panel", "schur", "gemm", "sdiag", "export"]
 
 
 class SelinvError(RuntimeError):
@@ -68,6 +72,12 @@ def lib():
         L.selinv_get_pattern.argtypes = [vp, vp, vp, vp]
         L.selinv_symbolic_sizes.argtypes = [vp, ct.POINTER(i64), ct.POINTER(i64), ct.POINTER(i64)]
         L.selinv_get_symbolic.argtypes = [vp] + [vp] * 8
+        L.selinv_profile.argtypes = [vp, ct.c_int32]
+        L.selinv_profile_read.argtypes = [vp, vp, vp]
+        L.selinv_kernel_work.argtypes = [vp, vp, vp]
+        L.selinv_get_arena.argtypes = [vp, ct.c_int32, vp, ct.POINTER(i64), vp]
+        L.selinv_get_blocks.argtypes = [vp] + [vp] * 8
+        L.selinv_get_exec_rows.argtypes = [vp, vp]
         L.selinv_last_error.restype = ct.c_char_p
         L.selinv_destroy.argtypes = [vp]
         for f in EXPORTS:
@@ -200,6 +210,46 @@ class Plan:
         bad = ct.c_int64(-1)
         st = lib().selinv_sync_status(self._h, _stream(stream), ct.byref(bad))
         _check(st, bad.value)
+
+    def profile(self, enable=True):
+        _check(lib().selinv_profile(self._h, int(bool(enable))))
+
+    def profile_read(self):
+        """{kind: (ms, launches)} for the launches recorded since the last read."""
+        ms = np.zeros(len(KINDS))
+        nl = np.zeros(len(KINDS), np.int64)
+        _check(lib().selinv_profile_read(self._h, _p(ms), _p(nl)))
+        return {k: (float(ms[i]), int(nl[i])) for i, k in enumerate(KINDS)}
+
+    def kernel_work(self):
+        """{kind: (flops, bytes)} of one factor (assemble..schur) / invert (gemm..export) call."""
+        f = np.zeros(len(KINDS))
+        b = np.zeros(len(KINDS))
+        _check(lib().selinv_kernel_work(self._h, _p(f), _p(b)))
+        return {k: (float(f[i]), float(b[i])) for i, k in enumerate(KINDS)}
+
+    def blocks(self):
+        """Execution blocks: dict of arrays (first, s, c, level, poff, hoff, woff, crow_off, rows)."""
+        nb = int(self.info["nblocks"])
+        out = {k: np.empty(max(nb, 1), np.int32) for k in ("first", "s", "c", "level")}
+        out.update({k: np.empty(max(nb, 1), np.int64) for k in ("poff", "hoff", "woff", "crow_off")})
+        _check(lib().selinv_get_blocks(self._h, *[_p(out[k]) for k in ("first", "s", "c", "level", "poff", "hoff",
+                                                                         "woff", "crow_off")]))
+        out = {k: v[:nb] for k, v in out.items()}
+        rows = np.empty(max(int(out["c"].sum()) if nb else 0, 1), np.int32)
+        _check(lib().selinv_get_exec_rows(self._h, _p(rows)))
+        out["rows"] = rows[: int(out["c"].sum()) if nb else 0]
+        return out
+
+    def arena(self, which, stream=None):
+        """Copy of a device arena ("L", "Ainv", "Lhat", "W", "T") as a CUDA tensor."""
+        import torch
+        n = ct.c_int64()
+        _check(lib().selinv_get_arena(self._h, ARENAS[which], None, ct.byref(n), None))
+        out = torch.empty(max(n.value, 1), dtype=torch.float64, device=self._ws.device)
+        _check(lib().selinv_get_arena(self._h, ARENAS[which], ct.c_void_p(out.data_ptr()), ct.byref(n),
+                                      _stream(stream)))
+        return out[: n.value]
 
     def __del__(self):
         try:
