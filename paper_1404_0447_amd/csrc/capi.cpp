@@ -58,6 +58,7 @@ void compute_layout(selinv_plan_s* P)
     L.t_schur = take(sizeof(Task) * P->t_schur.tasks.size());
     L.t_gemm = take(sizeof(Task) * P->t_gemm.tasks.size());
     L.t_sdiag = take(sizeof(Task) * P->t_sdiag.tasks.size());
+    L.t_zero = take(sizeof(Task) * P->t_zero.size());
     L.total = o;
     P->info.workspace_bytes = (int64_t)o;
 }
@@ -87,6 +88,7 @@ DevPtrs dev_ptrs(const selinv_plan_s* P)
     D.t_schur = (const Task*)(w + L.t_schur);
     D.t_gemm = (const Task*)(w + L.t_gemm);
     D.t_sdiag = (const Task*)(w + L.t_sdiag);
+    D.t_zero = (const Task*)(w + L.t_zero);
     return D;
 }
 
@@ -195,6 +197,7 @@ selinv_status selinv_bind_workspace(selinv_plan P, void* d_ws, size_t bytes, hip
     if (!e) e = upload(P->ws, L.t_schur, P->t_schur.tasks, s);
     if (!e) e = upload(P->ws, L.t_gemm, P->t_gemm.tasks, s);
     if (!e) e = upload(P->ws, L.t_sdiag, P->t_sdiag.tasks, s);
+    if (!e) e = upload(P->ws, L.t_zero, P->t_zero, s);
     if (!e) e = hipStreamSynchronize(s);
     if (e) {
         P->ws = nullptr;
@@ -234,7 +237,8 @@ selinv_status selinv_invert(selinv_plan P, double* d_sel, hipStream_t s)
     if (!P->factored) return fail(SELINV_ESTATE, "invert called before factor");
     if (P->colptrL.back() > 0 && !d_sel) return fail(SELINV_EINVAL, "d_sel is NULL");
     DevPtrs D = dev_ptrs(P);
-    hipError_t e = hipSuccess;
+    hipError_t e = launch_zero_x(&P->prof, D, (int64_t)P->t_zero.size(), s);
+    if (e) return hip_fail(e, "invert setup");
     const int depth = P->exec.depth;
     for (int l = 0; l < depth; l++) {
         const auto& g = P->t_gemm.off;

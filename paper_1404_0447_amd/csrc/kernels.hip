@@ -70,6 +70,15 @@ __global__ void k_gather(const double* __restrict__ src, const int64_t* __restri
         dst[i] = src[off[i]];
 }
 
+// X = Ainv(C,B) := 0 for blocks whose gather-GEMM accumulates split pieces.
+__global__ void k_zero_x(const Task* __restrict__ tasks, const BlockDesc* __restrict__ blk, double* __restrict__ Ap)
+{
+    const BlockDesc d = blk[tasks[blockIdx.x].b];
+    const int64_t ld = (int64_t)d.s + d.c;
+    for (int64_t e = threadIdx.x; e < (int64_t)d.c * d.s; e += blockDim.x)
+        Ap[d.poff + d.s + e % d.c + (e / d.c) * ld] = 0.0;
+}
+
 // L on the canonical pattern: diagonal-block entries are stored; an entry in
 // C(B) rows is L(r,j) = sum_{k>=j} L_hat(r,k) L_BB(k,j).  One thread per column.
 __global__ void k_export_L(const BlockDesc* __restrict__ blk, const int32_t* __restrict__ colblk,
@@ -120,34 +129,60 @@ struct TileShape {
 };
 
 template <int BN, class FA, class FB, class FAK>
-__device__ __forceinline__ void tile_mma(TileLds& L, int K, d4 (&acc)[2][4], FA loadA, FB loadB, FAK chunkAlongK)
+__device__ __forceinline__ void tile_mma(TileLds& L, int Kb, int Ke, d4 (&acc)[2][4], FA loadA, FB loadB,
+                                         FAK chunkAlongK)
 {
     using SH = TileShape<BN>;
+    constexpr int NB = BN / 16;  // B elements per thread per chunk
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm0 = (wave % SH::WM) * (TBM / SH::WM), wn0 = (wave / SH::WM) * (BN / SH::WN);
-    for (int k0 = 0; k0 < K; k0 += TBK) {
-        if (chunkAlongK(k0)) {
+    // the next chunk is fetched into registers while the current one feeds
+    // the MFMAs, so gather latency overlaps the products
+    double ra[4], rb[NB];
+    bool along = false;
+    auto fetch = [&](int k0) {
+        along = chunkAlongK(k0);
+        if (along) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int e = threadIdx.x + q * kThreads;
-                const int kk = e & 15, i = e >> 4;
-                L.A[kk][i] = loadA(k0, kk, i);
+                ra[q] = loadA(k0, e & 15, e >> 4);
             }
         } else {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int e = threadIdx.x + q * kThreads;
-                const int i = e & 63, kk = e >> 6;
-                L.A[kk][i] = loadA(k0, kk, i);
+                ra[q] = loadA(k0, e >> 6, e & 63);
             }
         }
 #pragma unroll
-        for (int q = 0; q < BN / 16; ++q) {
+        for (int q = 0; q < NB; ++q) {
             const int e = threadIdx.x + q * kThreads;
-            const int kk = e & 15, j = e >> 4;
-            L.B[kk][j] = loadB(k0, kk, j);
+            rb[q] = loadB(k0, e & 15, e >> 4);
+        }
+    };
+    if (Kb < Ke) fetch(Kb);
+    for (int k0 = Kb; k0 < Ke; k0 += TBK) {
+        if (along) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int e = threadIdx.x + q * kThreads;
+                L.A[e & 15][e >> 4] = ra[q];
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int e = threadIdx.x + q * kThreads;
+                L.A[e >> 6][e & 63] = ra[q];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const int e = threadIdx.x + q * kThreads;
+            L.B[e & 15][e >> 4] = rb[q];
         }
         __syncthreads();
+        if (k0 + TBK < Ke) fetch(k0 + TBK);
 #pragma unroll
         for (int ks = 0; ks < TBK / 4; ++ks) {
             const int kr = ks * 4 + (lane >> 4);
@@ -220,10 +255,13 @@ __device__ void gemm_task(TileLds& L, const Task t, const BlockDesc d, double* _
     };
     // chunks entirely above the diagonal band are read along k (contiguous)
     auto alongK = [&](int k0) { return k0 >= r0 + TBM; };
-    tile_mma<BN>(L, c, acc, loadA, loadB, alongK);
+    tile_mma<BN>(L, t.kb, t.ke, acc, loadA, loadB, alongK);
     tile_epilogue<BN>(acc, [&](int i, int j, double v) {
         const int ii = r0 + i, jj = n0 + j;
-        if (ii < c && jj < s) Ap[d.poff + s + ii + (int64_t)jj * ld] = -v;
+        if (ii < c && jj < s) {
+            double* x = Ap + d.poff + s + ii + (int64_t)jj * ld;
+            if (t.flags & 1) unsafeAtomicAdd(x, -v); else *x = -v;
+        }
     });
 }
 
@@ -237,7 +275,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm(const Task* __restrict__ task
     const Task t = tasks[blockIdx.x];
     const BlockDesc d = blk[t.b];
 #define SELINV_CALL(BN) gemm_task<BN>(L, t, d, Ap, Hp, cbase, rbase, rel)
-    SELINV_BN_DISPATCH(t.k0, SELINV_CALL)
+    SELINV_BN_DISPATCH(t.bn, SELINV_CALL)
 #undef SELINV_CALL
 }
 
@@ -263,7 +301,7 @@ __device__ void panel_task(TileLds& L, const Task t, const BlockDesc d, const do
         const int k = k0 + kk, jj = n0 + j;
         return (k < s && jj < s) ? T[k + jj * s] : 0.0;
     };
-    tile_mma<BN>(L, s, acc, loadA, loadB, [](int) { return false; });
+    tile_mma<BN>(L, 0, s, acc, loadA, loadB, [](int) { return false; });
     tile_epilogue<BN>(acc, [&](int i, int j, double v) {
         const int ii = r0 + i, jj = n0 + j;
         if (ii < c && jj < s) Hp[d.hoff + ii + (int64_t)jj * c] = v;
@@ -278,7 +316,7 @@ __global__ __launch_bounds__(kThreads) void k_panel(const Task* __restrict__ tas
     const Task t = tasks[blockIdx.x];
     const BlockDesc d = blk[t.b];
 #define SELINV_CALL(BN) panel_task<BN>(L, t, d, Lp, Hp, Tp)
-    SELINV_BN_DISPATCH(t.k0, SELINV_CALL)
+    SELINV_BN_DISPATCH(t.bn, SELINV_CALL)
 #undef SELINV_CALL
 }
 
@@ -312,7 +350,7 @@ __global__ __launch_bounds__(kThreads) void k_schur(const Task* __restrict__ tas
         const int k = k0c + j, col = t0 + tt;
         return (k < c && col < s) ? F[k + col * ld] : 0.0;
     };
-    tile_mma<64>(L, s, acc, loadA, loadB, [](int) { return false; });
+    tile_mma<64>(L, 0, s, acc, loadA, loadB, [](int) { return false; });
     tile_epilogue<64>(acc, [&](int i, int j, double v) {
         const int ii = i0 + i, kk = k0c + j;
         if (ii < c && kk < c && ii >= kk) {
@@ -451,6 +489,91 @@ __device__ void ldlt_global(const BlockDesc d, double* __restrict__ Lp, double* 
     }
 }
 
+// Diagonal block, s <= 128, by symmetric Gauss-Jordan sweeps held in
+// registers.  Thread (tx, ty) = (tid % 16, tid / 16) owns M(tx + 16a,
+// ty + 16b), a, b < 8.  Sweeping pivot j (M(j,j) = d_j, c = M(:,j)):
+//   M(i,k) -= c_i c_k / d_j  (i, k != j),  M(i,j) = M(j,i) = c_i / d_j,
+//   M(j,j) = -1 / d_j.
+// After all pivots M = -F_BB^{-1} = -T.  Before its own sweep, column j
+// below the diagonal holds the Schur-complement column, so the multipliers
+// c_i / d_j (i > j) are L_BB(i,j) and d_j is D's entry: both are written
+// out as they appear.  One LDS broadcast of column j and one barrier per
+// pivot (the column buffer alternates between two slots).
+__device__ void ldlt_sweep(const BlockDesc d, double* __restrict__ Lp, double* __restrict__ Tp,
+                           unsigned long long* __restrict__ status, int require_spd, double (*colbuf)[kLdsDiagMax])
+{
+    const int s = d.s;
+    const int64_t ld = (int64_t)d.s + d.c;
+    double* F = Lp + d.poff;
+    double* T = Tp + d.woff;
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    double M[8][8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const int i = tx + 16 * a, k = ty + 16 * b;
+            double v = 0.0;
+            if (i < s && k < s) v = i >= k ? F[i + k * ld] : F[k + i * ld];
+            M[a][b] = v;
+        }
+    for (int j = 0; j < s; ++j) {
+        double* buf = colbuf[j & 1];
+        const int jb = j >> 4;
+        if (ty == (j & 15)) {
+#pragma unroll
+            for (int a = 0; a < 8; ++a) {
+                double v = M[a][0];
+#pragma unroll
+                for (int b = 1; b < 8; ++b) v = (b == jb) ? M[a][b] : v;
+                buf[tx + 16 * a] = v;
+            }
+        }
+        __syncthreads();
+        const double dj = buf[j];
+        const double inv = 1.0 / dj;
+        if (tid == 0) {
+            const bool ok = isfinite(dj) && dj != 0.0 && (!require_spd || dj > 0.0);
+            if (!ok) atomicMin(status, (unsigned long long)(d.first + j));
+        }
+        double ci[8], ck[8];
+#pragma unroll
+        for (int a = 0; a < 8; ++a) ci[a] = buf[tx + 16 * a] * inv;  // c_i / d_j
+#pragma unroll
+        for (int b = 0; b < 8; ++b) ck[b] = buf[ty + 16 * b];
+        if (ty == (j & 15)) {  // column j of L_BB and D
+#pragma unroll
+            for (int a = 0; a < 8; ++a) {
+                const int i = tx + 16 * a;
+                if (i > j && i < s) F[i + (int64_t)j * ld] = ci[a];
+            }
+            if (tx == 0) F[j + (int64_t)j * ld] = dj;
+        }
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            const bool ri = (tx + 16 * a) == j;
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const bool rk = (ty + 16 * b) == j;
+                const double upd = M[a][b] - ci[a] * ck[b];
+                const double edge = ri ? ck[b] * inv : ci[a];
+                M[a][b] = (ri && rk) ? -inv : ((ri || rk) ? edge : upd);
+            }
+        }
+    }
+    // T = -M, made exactly symmetric from the lower triangle
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const int i = tx + 16 * a, k = ty + 16 * b;
+            if (i < s && k < s && i >= k) {
+                T[i + (int64_t)k * s] = -M[a][b];
+                T[k + (int64_t)i * s] = -M[a][b];
+            }
+        }
+}
+
 __global__ __launch_bounds__(kThreads) void k_ldlt_diag(const Task* __restrict__ tasks,
                                                         const BlockDesc* __restrict__ blk, double* __restrict__ Lp,
                                                         double* __restrict__ Wp, double* __restrict__ Tp,
@@ -462,6 +585,10 @@ __global__ __launch_bounds__(kThreads) void k_ldlt_diag(const Task* __restrict__
     const int s = d.s;
     if (s > kLdsDiagMax) {
         ldlt_global(d, Lp, Wp, Tp, status, require_spd);
+        return;
+    }
+    if (kUseSweep) {
+        ldlt_sweep(d, Lp, Tp, status, require_spd, reinterpret_cast<double(*)[kLdsDiagMax]>(S));
         return;
     }
     const int64_t ld = (int64_t)d.s + d.c;
@@ -609,6 +736,13 @@ hipError_t launch_gather(Prof* P, int kind, const double* src, const int64_t* of
     return hipGetLastError();
 }
 
+hipError_t launch_zero_x(Prof* P, const DevPtrs& D, int64_t nblocks, hipStream_t s)
+{
+    if (nblocks <= 0) return hipSuccess;
+    launch(P, kGemm, k_zero_x, dim3((unsigned)nblocks), 0, s, D.t_zero, D.blocks, D.Ap);
+    return hipGetLastError();
+}
+
 hipError_t launch_export_L(Prof* P, const DevPtrs& D, int64_t n, double* out, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
@@ -621,7 +755,7 @@ hipError_t launch_factor_level(Prof* P, const DevPtrs& D, int64_t diag0, int64_t
                                int64_t npanel, int64_t schur0, int64_t nschur, int require_spd, hipStream_t s)
 {
     if (ndiag > 0)
-        launch(P, kLdlt, k_ldlt_diag, dim3((unsigned)ndiag), kLdsDiagBytes, s, D.t_diag + diag0, D.blocks, D.Lp,
+        launch(P, kLdlt, k_ldlt_diag, dim3((unsigned)ndiag), kDiagShmem, s, D.t_diag + diag0, D.blocks, D.Lp,
                D.Wp, D.Tp, D.status, require_spd);
     if (npanel > 0)
         launch(P, kPanel, k_panel, dim3((unsigned)npanel), 0, s, D.t_panel + panel0, D.blocks,

@@ -20,10 +20,11 @@ struct DevPtrs {
     const int64_t *asm_off, *exp_off;
     const int32_t* colblk;     // column -> execution block
     const int64_t* colptrL;    // canonical column pointers of L
-    const Task *t_diag, *t_panel, *t_schur, *t_gemm, *t_sdiag;
+    const Task *t_diag, *t_panel, *t_schur, *t_gemm, *t_sdiag, *t_zero;
 };
 
 hipError_t kernels_init();
+hipError_t launch_zero_x(Prof* P, const DevPtrs& D, int64_t nblocks, hipStream_t s);
 hipError_t launch_export_L(Prof* P, const DevPtrs& D, int64_t n, double* out, hipStream_t s);
 hipError_t launch_status_reset(unsigned long long* status, hipStream_t s);
 hipError_t launch_fill(Prof* P, int kind, double* p, int64_t n, double v, hipStream_t s);

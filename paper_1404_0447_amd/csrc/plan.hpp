@@ -38,7 +38,12 @@ static_assert(sizeof(BlockDesc) == 48, "BlockDesc layout");
 
 // One unit of device work; meaning of the fields depends on the kernel.
 struct Task {
-    int32_t b, i0, j0, k0;
+    int32_t b;       // execution block
+    int32_t i0, j0;  // tile origin (rows, columns)
+    int32_t bn;      // tile width (16, 32, 64, 128)
+    int32_t kb, ke;  // contraction range [kb, ke)
+    int32_t flags;   // bit 0: accumulate atomically (split contraction)
+    int32_t pad;
 };
 
 struct LevelTasks {
@@ -63,7 +68,7 @@ struct Prof {
 struct DeviceLayout {
     // byte offsets into the workspace
     size_t lp, ap, hp, wp, tp, status, blocks, crow, cbase, rbase, rel, asm_off, exp_off, colblk, colptrL;
-    size_t t_diag, t_panel, t_schur, t_gemm, t_sdiag, total;
+    size_t t_diag, t_panel, t_schur, t_gemm, t_sdiag, t_zero, total;
 };
 
 }  // namespace selinv
@@ -89,6 +94,7 @@ struct selinv_plan_s {
     std::vector<int32_t> colblk;       // column -> execution block
     int64_t arena = 0, harena = 0, warena = 0;
     selinv::LevelTasks t_diag, t_panel, t_schur, t_gemm, t_sdiag;
+    std::vector<selinv::Task> t_zero;  // blocks whose X accumulates over split contractions
     selinv::DeviceLayout lay{};
     selinv_info info{};
     // binding state

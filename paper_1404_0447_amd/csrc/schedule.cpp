@@ -2,6 +2,8 @@
 // levels from the leaves up, the inversion from the root down; all blocks of
 // one level are independent (Section 2.2), so each level is one launch per
 // kernel kind with one work-group per task.
+#include <algorithm>
+
 #include "kernels.hpp"
 #include "plan.hpp"
 #include "tiles.hpp"
@@ -24,21 +26,39 @@ void build_schedule(selinv_plan_s* P)
         t->tasks.clear();
         t->off.assign(D + 1, 0);
     }
+    P->t_zero.clear();
     for (int l = 0; l < D; l++) {
+        // tiles of X this level has without splitting the contraction over C
+        int64_t base = 0;
+        for (int B : lv[l]) {
+            const BlockDesc& d = P->blocks[B];
+            base += (int64_t)((d.c + kTileM - 1) / kTileM) * ((d.s + tile_bn(d.s) - 1) / tile_bn(d.s));
+        }
+        const int64_t want = base > 0 && base < kFillTiles ? (kFillTiles + base - 1) / base : 1;
         for (int B : lv[l]) {
             const BlockDesc& d = P->blocks[B];
             const int bn = tile_bn(d.s);
-            P->t_diag.tasks.push_back({B, 0, 0, 0});
+            P->t_diag.tasks.push_back({B, 0, 0, 0, 0, 0, 0, 0});
             const int nd = (d.s + kDiagTile - 1) / kDiagTile;
             for (int I = 0; I < nd; I++)
-                for (int J = 0; J <= I; J++) P->t_sdiag.tasks.push_back({B, I * kDiagTile, J * kDiagTile, 0});
+                for (int J = 0; J <= I; J++)
+                    P->t_sdiag.tasks.push_back({B, I * kDiagTile, J * kDiagTile, 0, 0, d.c, 0, 0});
+            // split the contraction into pieces of >= kMinSplitK rows of C
+            const int nchunk = (d.c + 15) / 16;
+            int split = (int)std::min<int64_t>(want, std::max(1, nchunk / (kMinSplitK / 16)));
+            if (split > 1) P->t_zero.push_back({B, 0, 0, 0, 0, 0, 0, 0});
             for (int j = 0; j < d.s; j += bn)
                 for (int r = 0; r < d.c; r += kTileM) {
-                    P->t_panel.tasks.push_back({B, r, j, bn});
-                    P->t_gemm.tasks.push_back({B, r, j, bn});
+                    P->t_panel.tasks.push_back({B, r, j, bn, 0, d.s, 0, 0});
+                    for (int q = 0; q < split; q++) {
+                        const int kb = (int)((int64_t)nchunk * q / split) * 16;
+                        const int ke = std::min(d.c, (int)((int64_t)nchunk * (q + 1) / split) * 16);
+                        P->t_gemm.tasks.push_back({B, r, j, bn, kb, ke, split > 1 ? 1 : 0, 0});
+                    }
                 }
             for (int k = 0; k < d.c; k += kSchurTile)
-                for (int i = k; i < d.c; i += kSchurTile) P->t_schur.tasks.push_back({B, i, k, kSchurTile});
+                for (int i = k; i < d.c; i += kSchurTile)
+                    P->t_schur.tasks.push_back({B, i, k, kSchurTile, 0, d.s, 0, 0});
         }
         for (LevelTasks* t : all) t->off[l + 1] = (int64_t)t->tasks.size();
     }

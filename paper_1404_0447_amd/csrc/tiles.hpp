@@ -10,6 +10,11 @@ constexpr int kSchurTile = 64;   // edge of a Schur-update tile (lower c x c)
 constexpr int kDiagTile = 32;    // edge of a diagonal-block tile (pairs (I,J), I >= J)
 constexpr int kLdsDiagMax = 128; // diagonal factorization in LDS up to this width
 constexpr size_t kLdsDiagBytes = sizeof(double) * kLdsDiagMax * (kLdsDiagMax + 1);
+constexpr bool kUseSweep = true;  // register Gauss-Jordan sweep for s <= kLdsDiagMax
+constexpr size_t kDiagShmem = kUseSweep ? sizeof(double) * 2 * kLdsDiagMax : kLdsDiagBytes;
+
+constexpr int kFillTiles = 512;  // split the contraction when a level has fewer X tiles
+constexpr int kMinSplitK = 256;  // rows of C per split piece, at least
 
 // output-column tile of a block of width s: 16, 32, 64 or 128
 inline int tile_bn(int s) { return s <= 16 ? 16 : s <= 32 ? 32 : s <= 64 ? 64 : 128; }
