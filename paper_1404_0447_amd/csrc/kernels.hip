@@ -70,13 +70,19 @@ __global__ void k_gather(const double* __restrict__ src, const int64_t* __restri
         dst[i] = src[off[i]];
 }
 
-// X = Ainv(C,B) := 0 for blocks whose gather-GEMM accumulates split pieces.
-__global__ void k_zero_x(const Task* __restrict__ tasks, const BlockDesc* __restrict__ blk, double* __restrict__ Ap)
+// Blocks whose contractions are split over several work-groups accumulate:
+// X = Ainv(C,B) := 0 and the lower triangle of Ainv(B,B) := T.
+__global__ void k_zero_x(const Task* __restrict__ tasks, const BlockDesc* __restrict__ blk, double* __restrict__ Ap,
+                         const double* __restrict__ Tp)
 {
     const BlockDesc d = blk[tasks[blockIdx.x].b];
     const int64_t ld = (int64_t)d.s + d.c;
     for (int64_t e = threadIdx.x; e < (int64_t)d.c * d.s; e += blockDim.x)
         Ap[d.poff + d.s + e % d.c + (e / d.c) * ld] = 0.0;
+    for (int64_t e = threadIdx.x; e < (int64_t)d.s * d.s; e += blockDim.x) {
+        const int i = (int)(e % d.s), j = (int)(e / d.s);
+        if (i >= j) Ap[d.poff + i + j * ld] = Tp[d.woff + e];
+    }
 }
 
 // L on the canonical pattern: diagonal-block entries are stored; an entry in
@@ -388,13 +394,14 @@ __global__ __launch_bounds__(kThreads) void k_sdiag(const Task* __restrict__ tas
     // Branch-free body: a diagonal tile (I == J) simply recomputes its own
     // product as the partner.  Control flow between an FP64 MFMA and a read
     // of its accumulator let the compiler place the read too early.
-    for (int r0 = 0; r0 < c; r0 += 16) {
+    const int rend = min(c, t.ke);
+    for (int r0 = t.kb; r0 < rend; r0 += 16) {
 #pragma unroll
         for (int q = 0; q < (16 * SDT) / kThreads; ++q) {
             const int e = threadIdx.x + q * kThreads;
             const int kk = e & 15, col = e >> 4;
             const int r = r0 + kk;
-            const bool okr = r < c;
+            const bool okr = r < rend;
             const int ci = I0 + col, cj = J0 + col;
             const double li = (okr && ci < s) ? H[r + (int64_t)ci * c] : 0.0;
             const double lj = (okr && cj < s) ? H[r + (int64_t)cj * c] : 0.0;
@@ -415,22 +422,30 @@ __global__ __launch_bounds__(kThreads) void k_sdiag(const Task* __restrict__ tas
         __syncthreads();
     }
     mfma_drain();
-    // Sx[b][a] = Y(J,I)(a, b): element (a, b) of the transposed partner tile
+    // Only the lower triangle of Ainv(B,B) is kept (it is all that the
+    // gathers and the export read).  A whole contraction writes
+    // (Y(I,J) + Y(J,I)^T)/2 there; a split piece adds its share
+    // -(P(I,J) + P(J,I)^T)/2 to the T written beforehand (the average is
+    // linear, so the pieces may arrive in any order).
+    const bool split = t.flags & 1;
+    // Sx[b][a] = element (a, b) of the partner tile
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int i = fm + (lane >> 4) + 4 * v, j = fn + (lane & 15);
-        Sx[j][i] = (J0 + i < s && I0 + j < s) ? T[(J0 + i) + (I0 + j) * s] - accJI[v] : 0.0;
+        const double tji = (!split && J0 + i < s && I0 + j < s) ? T[(J0 + i) + (I0 + j) * s] : 0.0;
+        Sx[j][i] = tji - accJI[v];
     }
     __syncthreads();
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int i = fm + (lane >> 4) + 4 * v, j = fn + (lane & 15);
         const int gi = I0 + i, gj = J0 + j;
-        if (gi < s && gj < s) {
-            const double yij = T[gi + gj * s] - accIJ[v];
-            const double m = 0.5 * (yij + Sx[i][j]);
-            A[gi + gj * ld] = m;
-            A[gj + gi * ld] = m;
+        if (gi < s && gj < s && gi >= gj) {
+            if (split) {
+                unsafeAtomicAdd(A + gi + gj * ld, 0.5 * (Sx[i][j] - accIJ[v]));
+            } else {
+                A[gi + gj * ld] = 0.5 * ((T[gi + gj * s] - accIJ[v]) + Sx[i][j]);
+            }
         }
     }
 }
@@ -517,48 +532,54 @@ __device__ void ldlt_sweep(const BlockDesc d, double* __restrict__ Lp, double* _
             if (i < s && k < s) v = i >= k ? F[i + k * ld] : F[k + i * ld];
             M[a][b] = v;
         }
-    for (int j = 0; j < s; ++j) {
-        double* buf = colbuf[j & 1];
-        const int jb = j >> 4;
-        if (ty == (j & 15)) {
+    // pivots j = 16 jb + jt: jb is unrolled, so the pivot's register row
+    // (a == jb) and column (b == jb) are known at compile time
 #pragma unroll
-            for (int a = 0; a < 8; ++a) {
-                double v = M[a][0];
+    for (int jb = 0; jb < 8; ++jb) {
+        const int jt_end = min(16, s - 16 * jb);
+        for (int jt = 0; jt < jt_end; ++jt) {
+            const int j = 16 * jb + jt;
+            double* buf = colbuf[j & 1];
+            if (ty == jt) {
 #pragma unroll
-                for (int b = 1; b < 8; ++b) v = (b == jb) ? M[a][b] : v;
-                buf[tx + 16 * a] = v;
+                for (int a = 0; a < 8; ++a) buf[tx + 16 * a] = M[a][jb];
             }
-        }
-        __syncthreads();
-        const double dj = buf[j];
-        const double inv = 1.0 / dj;
-        if (tid == 0) {
-            const bool ok = isfinite(dj) && dj != 0.0 && (!require_spd || dj > 0.0);
-            if (!ok) atomicMin(status, (unsigned long long)(d.first + j));
-        }
-        double ci[8], ck[8];
-#pragma unroll
-        for (int a = 0; a < 8; ++a) ci[a] = buf[tx + 16 * a] * inv;  // c_i / d_j
-#pragma unroll
-        for (int b = 0; b < 8; ++b) ck[b] = buf[ty + 16 * b];
-        if (ty == (j & 15)) {  // column j of L_BB and D
-#pragma unroll
-            for (int a = 0; a < 8; ++a) {
-                const int i = tx + 16 * a;
-                if (i > j && i < s) F[i + (int64_t)j * ld] = ci[a];
+            __syncthreads();
+            const double dj = buf[j];
+            const double inv = 1.0 / dj;
+            if (tid == 0) {
+                const bool ok = isfinite(dj) && dj != 0.0 && (!require_spd || dj > 0.0);
+                if (!ok) atomicMin(status, (unsigned long long)(d.first + j));
             }
-            if (tx == 0) F[j + (int64_t)j * ld] = dj;
-        }
+            double ci[8], ck[8];
 #pragma unroll
-        for (int a = 0; a < 8; ++a) {
-            const bool ri = (tx + 16 * a) == j;
+            for (int a = 0; a < 8; ++a) ci[a] = buf[tx + 16 * a] * inv;  // c_i / d_j
 #pragma unroll
-            for (int b = 0; b < 8; ++b) {
-                const bool rk = (ty + 16 * b) == j;
-                const double upd = M[a][b] - ci[a] * ck[b];
-                const double edge = ri ? ck[b] * inv : ci[a];
-                M[a][b] = (ri && rk) ? -inv : ((ri || rk) ? edge : upd);
+            for (int b = 0; b < 8; ++b) ck[b] = buf[ty + 16 * b];
+            if (ty == jt) {  // column j of L_BB and D
+#pragma unroll
+                for (int a = 0; a < 8; ++a) {
+                    const int i = tx + 16 * a;
+                    if (i > j && i < s) F[i + (int64_t)j * ld] = ci[a];
+                }
+                if (tx == 0) F[j + (int64_t)j * ld] = dj;
             }
+            const bool ri = tx == jt, rk = ty == jt;  // this lane holds row j / column j
+#pragma unroll
+            for (int a = 0; a < 8; ++a)
+#pragma unroll
+                for (int b = 0; b < 8; ++b) {
+                    const double upd = M[a][b] - ci[a] * ck[b];
+                    if (a == jb && b == jb) {
+                        M[a][b] = (ri && rk) ? -inv : (ri ? ck[b] * inv : (rk ? ci[a] : upd));
+                    } else if (a == jb) {
+                        M[a][b] = ri ? ck[b] * inv : upd;
+                    } else if (b == jb) {
+                        M[a][b] = rk ? ci[a] : upd;
+                    } else {
+                        M[a][b] = upd;
+                    }
+                }
         }
     }
     // T = -M, made exactly symmetric from the lower triangle
@@ -739,7 +760,7 @@ hipError_t launch_gather(Prof* P, int kind, const double* src, const int64_t* of
 hipError_t launch_zero_x(Prof* P, const DevPtrs& D, int64_t nblocks, hipStream_t s)
 {
     if (nblocks <= 0) return hipSuccess;
-    launch(P, kGemm, k_zero_x, dim3((unsigned)nblocks), 0, s, D.t_zero, D.blocks, D.Ap);
+    launch(P, kGemm, k_zero_x, dim3((unsigned)nblocks), 0, s, D.t_zero, D.blocks, D.Ap, (const double*)D.Tp);
     return hipGetLastError();
 }
 

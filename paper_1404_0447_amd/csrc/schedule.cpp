@@ -29,24 +29,34 @@ void build_schedule(selinv_plan_s* P)
     P->t_zero.clear();
     for (int l = 0; l < D; l++) {
         // tiles of X this level has without splitting the contraction over C
-        int64_t base = 0;
+        int64_t base = 0, dbase = 0;
         for (int B : lv[l]) {
             const BlockDesc& d = P->blocks[B];
             base += (int64_t)((d.c + kTileM - 1) / kTileM) * ((d.s + tile_bn(d.s) - 1) / tile_bn(d.s));
+            const int nd = (d.s + kDiagTile - 1) / kDiagTile;
+            dbase += nd * (nd + 1) / 2;
         }
         const int64_t want = base > 0 && base < kFillTiles ? (kFillTiles + base - 1) / base : 1;
+        const int64_t dwant = dbase > 0 && dbase < kFillTiles ? (kFillTiles + dbase - 1) / dbase : 1;
         for (int B : lv[l]) {
             const BlockDesc& d = P->blocks[B];
             const int bn = tile_bn(d.s);
             P->t_diag.tasks.push_back({B, 0, 0, 0, 0, 0, 0, 0});
+            // contractions over C are split into pieces of >= kMinSplitK rows
+            // when a level has too few tiles to fill the device
+            const int nchunk = (d.c + 15) / 16;
+            const int maxsplit = std::max(1, nchunk / (kMinSplitK / 16));
+            const int split = (int)std::min<int64_t>(want, maxsplit);
+            const int dsplit = (int)std::min<int64_t>(dwant, maxsplit);
+            if (split > 1 || dsplit > 1) P->t_zero.push_back({B, 0, 0, 0, 0, 0, 0, 0});
             const int nd = (d.s + kDiagTile - 1) / kDiagTile;
             for (int I = 0; I < nd; I++)
                 for (int J = 0; J <= I; J++)
-                    P->t_sdiag.tasks.push_back({B, I * kDiagTile, J * kDiagTile, 0, 0, d.c, 0, 0});
-            // split the contraction into pieces of >= kMinSplitK rows of C
-            const int nchunk = (d.c + 15) / 16;
-            int split = (int)std::min<int64_t>(want, std::max(1, nchunk / (kMinSplitK / 16)));
-            if (split > 1) P->t_zero.push_back({B, 0, 0, 0, 0, 0, 0, 0});
+                    for (int q = 0; q < dsplit; q++) {
+                        const int kb = (int)((int64_t)nchunk * q / dsplit) * 16;
+                        const int ke = std::min(d.c, (int)((int64_t)nchunk * (q + 1) / dsplit) * 16);
+                        P->t_sdiag.tasks.push_back({B, I * kDiagTile, J * kDiagTile, 0, kb, ke, dsplit > 1, 0});
+                    }
             for (int j = 0; j < d.s; j += bn)
                 for (int r = 0; r < d.c; r += kTileM) {
                     P->t_panel.tasks.push_back({B, r, j, bn, 0, d.s, 0, 0});
