@@ -64,7 +64,9 @@ typedef struct {
                              amalgamated block (explicit zeros; results on the
                              fundamental pattern are unchanged up to rounding) */
     int32_t require_spd;  /* 1: a pivot <= 0 is an error (SELINV_EPIVOT)     */
-    int32_t exec_cap;     /* cap on an amalgamated block's width; 0 = max_super */
+    int32_t exec_cap;     /* cap on an execution block's width (<= 256); 0 =
+                             min(max_super, 128).  Blocks wider than 128 take
+                             a slow diagonal-factorization path.           */
 } selinv_opts;
 
 typedef struct {

@@ -297,19 +297,34 @@ selinv_status analyze(selinv_plan_s* P, const selinv_geom* geom, const int32_t* 
             std::copy(buf.begin(), buf.end(), F.crows.begin() + F.cptr[K]);
         }
     }
-    // ---- execution blocks: chains of single-child supernodes run as one
-    //      amalgamated block (rows(B) = cols(B) U C(top of the chain)).
+    // ---- execution blocks.  Fundamental supernodes wider than ecap are cut
+    //      into pieces of at most ecap columns (a piece is a supernode whose
+    //      rows below are the rest of its supernode plus C(K)); then chains
+    //      of single-child pieces run as one amalgamated block with
+    //      rows(B) = cols(B) U C(top piece of the chain).
     Partition& E = P->exec;
     std::vector<int32_t> nsch(N, 0);
     for (int K = 0; K < N; K++)
         if (F.par[K] >= 0) nsch[F.par[K]]++;
-    std::vector<int32_t> topOf;  // exec block -> fundamental supernode at its top
+    std::vector<int32_t> topK, topEnd;  // exec block -> top supernode, end column of its top piece
     E.xs.clear();
     for (int K = 0; K < N; K++) {
-        bool join = K > 0 && P->opts.fuse_chains && F.par[K - 1] == K && nsch[K] == 1 &&
-                    (F.xs[K + 1] - E.xs.back()) <= ecap;
-        if (!join) E.xs.push_back(F.xs[K]);
-        if (join) topOf.back() = K; else topOf.push_back(K);
+        const int32_t f = F.xs[K], l = F.xs[K + 1];
+        for (int32_t a = f; a < l; a += ecap) {
+            const int32_t b = std::min(l, a + ecap);
+            // the previous piece is this piece's only child: within K always,
+            // at K's first piece when K-1 is K's only child
+            bool chain = a > f || (K > 0 && F.par[K - 1] == K && nsch[K] == 1);
+            bool join = !E.xs.empty() && P->opts.fuse_chains && chain && (b - E.xs.back()) <= ecap;
+            if (join) {
+                topK.back() = K;
+                topEnd.back() = b;
+            } else {
+                E.xs.push_back(a);
+                topK.push_back(K);
+                topEnd.push_back(b);
+            }
+        }
     }
     E.xs.push_back((int32_t)n);
     int32_t NB = E.nblocks();
@@ -319,12 +334,19 @@ selinv_status analyze(selinv_plan_s* P, const selinv_geom* geom, const int32_t* 
     E.par.assign(NB, -1);
     E.cptr.assign(NB + 1, 0);
     for (int B = 0; B < NB; B++) {
-        int T = topOf[B];
-        E.par[B] = F.par[T] >= 0 ? E.of[F.xs[F.par[T]]] : -1;
-        E.cptr[B + 1] = E.cptr[B] + F.clen(T);
+        const int K = topK[B];
+        const int32_t e = topEnd[B], l = F.xs[K + 1];
+        if (e < l) E.par[B] = E.of[e];                          // next piece of the same supernode
+        else E.par[B] = F.par[K] >= 0 ? E.of[F.xs[F.par[K]]] : -1;
+        E.cptr[B + 1] = E.cptr[B] + (l - e) + F.clen(K);
     }
     E.crows.resize((size_t)E.cptr[NB]);
-    for (int B = 0; B < NB; B++) std::copy(F.C(topOf[B]), F.C(topOf[B]) + F.clen(topOf[B]), E.crows.begin() + E.cptr[B]);
+    for (int B = 0; B < NB; B++) {
+        const int K = topK[B];
+        int64_t q = E.cptr[B];
+        for (int32_t x = topEnd[B]; x < F.xs[K + 1]; x++) E.crows[q++] = x;
+        std::copy(F.C(K), F.C(K) + F.clen(K), E.crows.begin() + q);
+    }
     priority_levels(E);
     // ---- canonical pattern of L (fundamental)
     P->colptrL.assign(n + 1, 0);

@@ -9,6 +9,7 @@
 
 #include "kernels.hpp"
 #include "plan.hpp"
+#include "tiles.hpp"
 
 using namespace selinv;
 
@@ -114,7 +115,10 @@ selinv_status selinv_analyze(int64_t n, const int64_t* colptr, const int32_t* ro
     selinv_opts o{128, 1, 1, 0};
     if (opts) o = *opts;
     if (o.max_super <= 0) o.max_super = 128;
-    if (o.exec_cap <= 0) o.exec_cap = o.max_super;
+    // execution blocks default to <= 128 columns (the width the register
+    // sweep of the diagonal block holds); the L pattern does not depend on
+    // the partition, only the reported fundamental supernodes use max_super
+    if (o.exec_cap <= 0) o.exec_cap = std::min(o.max_super, (int32_t)kLdsDiagMax);
     if (o.max_super > 256 || o.exec_cap > 256)
         return fail(SELINV_EUNSUPPORTED, "supernode width cap above 256 is not supported");
     if (n > 0) {
