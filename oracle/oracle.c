@@ -11,10 +11,11 @@
  * Tiers:
  *   O1  orc_dense_inverse   -- A^{-1} by an LDL^T factorization and n
  *                              triangular solves (Section 2.1, the
- *                              "direct inversion" of equation (2.3)).
+ *                              "direct inversion" by triangular solves).
  *   O2  orc_selinv_columns  -- dense LDL^T then the scalar (column)
  *                              recurrence obtained from the 2x2 block form
- *                              (Section 2.1, equations (2.5)-(2.8)).
+ *                              (Section 2.1, the 2x2 block form of A^{-1}
+ *                              with normalised factors).
  *   O3  orc_factor_selinv   -- supernodal LDL^T, then Algorithm 1 with the
  *                              symmetric simplifications of Section 2.1
  *                              (U_hat = L_hat^T, LDL^T diagonal term,

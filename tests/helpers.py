@@ -32,7 +32,7 @@ def err_c8(x, o, colptrL, rowindL):
 
 def colwise_rel(x, o, colptrL, rowindL, n):
     """Column-wise relative difference max_j ||x(:,j)-o(:,j)|| / ||o(:,j)||
-    (the paper's accuracy metric, Section 4.3), on the symmetric pattern."""
+    (the paper's accuracy metric, Section 4.2), on the symmetric pattern."""
     cols = np.repeat(np.arange(n), np.diff(colptrL))
     num = np.zeros(n)
     den = np.zeros(n)
