@@ -109,6 +109,18 @@ selinv_status selinv_factor(selinv_plan p, const double* d_valsA, hipStream_t s)
  * order of selinv_get_pattern. */
 selinv_status selinv_invert(selinv_plan p, double* d_sel, hipStream_t s);
 
+/* Reverse sweep (adjoint).  For f = sum over the pattern of L of
+ * gsel_q * Ainv_q (d_gsel: nnzL doubles, canonical order), writes
+ * d_gA[p] = df/da_p for every stored entry p of A (nnzA doubles, the CSC
+ * order given to selinv_analyze); an off-diagonal entry stands for A_ij and
+ * A_ji, so d_gA = -(A^{-1} S A^{-1}) off the diagonal and half of it on the
+ * diagonal, S = G + G^T.  Runs the selected inversion in reverse (leaves
+ * first, Algorithm 1 backwards) and then the factorization in reverse (root
+ * first).  Needs selinv_factor and selinv_invert of the same values first;
+ * uses only the workspace (no allocation).  SELINV_EUNSUPPORTED if an
+ * execution block is wider than 128 columns. */
+selinv_status selinv_backward(selinv_plan p, const double* d_gsel, double* d_gA, hipStream_t s);
+
 /* Copy L (unit lower, D on the diagonal) on the canonical pattern to d_L. */
 selinv_status selinv_get_factor(selinv_plan p, double* d_L, hipStream_t s);
 
@@ -147,7 +159,9 @@ enum {
     SELINV_K_GEMM = 4,     /* Ainv(C,K) = -Ainv(C,C) L_hat(C,K), gathered        */
     SELINV_K_SDIAG = 5,    /* Ainv(K,K) = T_K - L_hat^T Ainv(C,K), symmetrised   */
     SELINV_K_EXPORT = 6,   /* panels -> canonical values                         */
-    SELINV_NKINDS = 7
+    SELINV_K_REVSEL = 7,   /* reverse selected inversion (adjoint), leaves first */
+    SELINV_K_REVFAC = 8,   /* reverse factorization (adjoint), root first        */
+    SELINV_NKINDS = 9
 };
 
 /* Enable (1) or disable (0) per-launch timing: every later kernel launch of
@@ -166,7 +180,8 @@ selinv_status selinv_kernel_work(selinv_plan p, double* flops, double* bytes);
 
 /* Raw device arenas, for kernel-level checks: which = 0 factor panels
  * (L_KK with D on the diagonal; F(C,K) in the C rows), 1 inverse panels,
- * 2 L_hat(C,K) blocks, 3 W = L_KK^{-1} blocks, 4 T_K blocks.  The layout of
+ * 2 L_hat(C,K) blocks, 3 scratch, 4 T_K blocks; after selinv_backward:
+ * 5 the adjoint of the factor panels, 6 that of L_hat, 7 that of T_K.  The layout of
  * each execution block is given by selinv_get_blocks.  *count = number of
  * doubles; d_out (device, may be NULL) receives a copy on stream s. */
 selinv_status selinv_get_arena(selinv_plan p, int32_t which, double* d_out, int64_t* count, hipStream_t s);

@@ -60,6 +60,15 @@ void compute_layout(selinv_plan_s* P)
     L.t_gemm = take(sizeof(Task) * P->t_gemm.tasks.size());
     L.t_sdiag = take(sizeof(Task) * P->t_sdiag.tasks.size());
     L.t_zero = take(sizeof(Task) * P->t_zero.size());
+    L.zb = take(sizeof(double) * P->arena);
+    L.hb = take(sizeof(double) * P->harena);
+    L.tb = take(sizeof(double) * P->warena);
+    L.t_rs1 = take(sizeof(Task) * P->t_rs1.tasks.size());
+    L.t_rs2 = take(sizeof(Task) * P->t_rs2.tasks.size());
+    L.t_rs3 = take(sizeof(Task) * P->t_rs3.tasks.size());
+    L.t_rf1a = take(sizeof(Task) * P->t_rf1a.tasks.size());
+    L.t_rf1b = take(sizeof(Task) * P->t_rf1b.tasks.size());
+    L.t_rf2 = take(sizeof(Task) * P->t_rf2.tasks.size());
     L.total = o;
     P->info.workspace_bytes = (int64_t)o;
 }
@@ -90,6 +99,15 @@ DevPtrs dev_ptrs(const selinv_plan_s* P)
     D.t_gemm = (const Task*)(w + L.t_gemm);
     D.t_sdiag = (const Task*)(w + L.t_sdiag);
     D.t_zero = (const Task*)(w + L.t_zero);
+    D.Zb = (double*)(w + L.zb);
+    D.Hb = (double*)(w + L.hb);
+    D.Tb = (double*)(w + L.tb);
+    D.t_rs1 = (const Task*)(w + L.t_rs1);
+    D.t_rs2 = (const Task*)(w + L.t_rs2);
+    D.t_rs3 = (const Task*)(w + L.t_rs3);
+    D.t_rf1a = (const Task*)(w + L.t_rf1a);
+    D.t_rf1b = (const Task*)(w + L.t_rf1b);
+    D.t_rf2 = (const Task*)(w + L.t_rf2);
     return D;
 }
 
@@ -202,6 +220,12 @@ selinv_status selinv_bind_workspace(selinv_plan P, void* d_ws, size_t bytes, hip
     if (!e) e = upload(P->ws, L.t_gemm, P->t_gemm.tasks, s);
     if (!e) e = upload(P->ws, L.t_sdiag, P->t_sdiag.tasks, s);
     if (!e) e = upload(P->ws, L.t_zero, P->t_zero, s);
+    if (!e) e = upload(P->ws, L.t_rs1, P->t_rs1.tasks, s);
+    if (!e) e = upload(P->ws, L.t_rs2, P->t_rs2.tasks, s);
+    if (!e) e = upload(P->ws, L.t_rs3, P->t_rs3.tasks, s);
+    if (!e) e = upload(P->ws, L.t_rf1a, P->t_rf1a.tasks, s);
+    if (!e) e = upload(P->ws, L.t_rf1b, P->t_rf1b.tasks, s);
+    if (!e) e = upload(P->ws, L.t_rf2, P->t_rf2.tasks, s);
     if (!e) e = hipStreamSynchronize(s);
     if (e) {
         P->ws = nullptr;
@@ -231,6 +255,45 @@ selinv_status selinv_factor(selinv_plan P, const double* d_valsA, hipStream_t s)
         if (e) return hip_fail(e, "factor level launch");
     }
     P->factored = true;
+    P->inverted = false;
+    return SELINV_OK;
+}
+
+selinv_status selinv_backward(selinv_plan P, const double* d_gsel, double* d_gA, hipStream_t s)
+{
+    if (!P) return fail(SELINV_EINVAL, "NULL plan");
+    if (!P->ws) return fail(SELINV_ESTATE, "no workspace bound");
+    if (!P->inverted) return fail(SELINV_ESTATE, "backward needs factor and invert of the same values first");
+    if ((P->colptrL.back() > 0 && !d_gsel) || (P->nnzA > 0 && !d_gA)) return fail(SELINV_EINVAL, "NULL buffer");
+    for (const BlockDesc& d : P->blocks)
+        if (d.s > kLdsDiagMax)
+            return fail(SELINV_EUNSUPPORTED, "backward supports execution blocks of at most 128 columns");
+    DevPtrs D = dev_ptrs(P);
+    hipError_t e = launch_backward_init(&P->prof, D, P->arena, P->harena, d_gsel, P->colptrL.back(), s);
+    if (e) return hip_fail(e, "backward setup");
+    const int depth = P->exec.depth;
+    // reverse selected inversion: leaves first
+    for (int l = depth - 1; l >= 0; l--) {
+        const auto& a = P->t_rs1.off;
+        const auto& b = P->t_rs2.off;
+        const auto& c = P->t_rs3.off;
+        e = launch_revsel_level(&P->prof, D, a[l], a[l + 1] - a[l], b[l], b[l + 1] - b[l], c[l], c[l + 1] - c[l], s);
+        if (e) return hip_fail(e, "reverse inversion launch");
+    }
+    e = launch_revfac_init(&P->prof, D, (int64_t)P->t_diag.tasks.size(), P->arena, s);
+    if (e) return hip_fail(e, "reverse factor setup");
+    // reverse factorization: root first
+    for (int l = 0; l < depth; l++) {
+        const auto& a = P->t_rf1a.off;
+        const auto& b = P->t_rf1b.off;
+        const auto& c = P->t_rf2.off;
+        const auto& d = P->t_diag.off;
+        e = launch_revfac_level(&P->prof, D, a[l], a[l + 1] - a[l], b[l], b[l + 1] - b[l], c[l], c[l + 1] - c[l],
+                                d[l], d[l + 1] - d[l], s);
+        if (e) return hip_fail(e, "reverse factor launch");
+    }
+    e = launch_gather(&P->prof, kRevFac, D.Zb, D.asm_off, P->nnzA, d_gA, s);
+    if (e) return hip_fail(e, "gradient export");
     return SELINV_OK;
 }
 
@@ -252,6 +315,7 @@ selinv_status selinv_invert(selinv_plan P, double* d_sel, hipStream_t s)
     }
     e = launch_gather(&P->prof, kExport, D.Ap, D.exp_off, P->colptrL.back(), d_sel, s);
     if (e) return hip_fail(e, "export launch");
+    P->inverted = true;
     return SELINV_OK;
 }
 
@@ -388,6 +452,9 @@ selinv_status selinv_get_arena(selinv_plan P, int32_t which, double* d_out, int6
         case 2: off = P->lay.hp; n = P->harena; break;
         case 3: off = P->lay.wp; n = P->warena; break;
         case 4: off = P->lay.tp; n = P->warena; break;
+        case 5: off = P->lay.zb; n = P->arena; break;
+        case 6: off = P->lay.hb; n = P->harena; break;
+        case 7: off = P->lay.tb; n = P->warena; break;
         default: return fail(SELINV_EINVAL, "unknown arena");
     }
     if (count) *count = n;

@@ -681,6 +681,371 @@ __global__ __launch_bounds__(kThreads) void k_ldlt_diag(const Task* __restrict__
     }
 }
 
+// ===========================================================================
+// Reverse sweep: adjoint of the factorization and of the selected inversion.
+// Adjoints are those of the stored values: an entry of a diagonal block's
+// lower triangle stands for both (i,j) and (j,i), an entry of the C rows for
+// itself.  Zb holds the adjoint of Ainv during the reverse selected
+// inversion (leaves first) and the adjoint of F during the reverse
+// factorization (root first), in the panel layout; Hb is the adjoint of
+// L_hat and Tb that of T.  Per block, with Zbar the adjoint of its panel:
+//   Ybar = (Zbar_BB + Zbar_BB^T)/2,  Xbar = Zbar(C,B) - L_hat Ybar,
+//   Lhat_bar = -X Ybar - G Xbar,  Tbar = Ybar,
+//   ancestors' Zbar(C,C) += -(Xbar L_hat^T + L_hat Xbar^T)  (stored lower);
+// then, root first, with Ubar(i,k) = -Fbar(C[i],C[k]) (i >= k) from the
+// ancestors: Lhat_bar += Ubar F(C,B), Fbar(C,B) = Ubar^T L_hat + Lhat_bar T,
+// Tbar += F(C,B)^T Lhat_bar, Fbar_BB = -T (Tbar + Tbar^T) T (stored lower).
+// The gradient of A's entries is Fbar at their positions.
+// ===========================================================================
+__device__ __forceinline__ double ybar_at(const double* __restrict__ Zd, int64_t ld, int t, int j)
+{
+    if (t == j) return Zd[t + (int64_t)t * ld];
+    const int a = t > j ? t : j, b = t > j ? j : t;
+    return 0.5 * Zd[a + (int64_t)b * ld];
+}
+
+template <int BN>
+__device__ void rs1_task(TileLds& L, const Task t, const BlockDesc d, double* __restrict__ Zb,
+                         const double* __restrict__ Hp)
+{
+    const int s = d.s, c = d.c;
+    const int64_t ld = (int64_t)s + c;
+    const int r0 = t.i0, n0 = t.j0;
+    const double* Zd = Zb + d.poff;
+    d4 acc[2][4] = {};
+    auto loadA = [&](int k0, int kk, int ii) -> double {
+        const int i = r0 + ii, k = k0 + kk;
+        return (i < c && k < s) ? Hp[d.hoff + i + (int64_t)k * c] : 0.0;
+    };
+    auto loadB = [&](int k0, int kk, int j) -> double {
+        const int k = k0 + kk, jj = n0 + j;
+        return (k < s && jj < s) ? ybar_at(Zd, ld, k, jj) : 0.0;
+    };
+    tile_mma<BN>(L, 0, s, acc, loadA, loadB, [](int) { return false; });
+    tile_epilogue<BN>(acc, [&](int i, int j, double v) {
+        const int ii = r0 + i, jj = n0 + j;
+        if (ii < c && jj < s) Zb[d.poff + s + ii + (int64_t)jj * ld] -= v;
+    });
+}
+
+__global__ __launch_bounds__(kThreads) void k_rs1(const Task* __restrict__ tasks, const BlockDesc* __restrict__ blk,
+                                                  double* __restrict__ Zb, const double* __restrict__ Hp)
+{
+    __shared__ TileLds L;
+    const Task t = tasks[blockIdx.x];
+    const BlockDesc d = blk[t.b];
+#define SELINV_CALL(BN) rs1_task<BN>(L, t, d, Zb, Hp)
+    SELINV_BN_DISPATCH(t.bn, SELINV_CALL)
+#undef SELINV_CALL
+}
+
+template <int BN>
+__device__ void rs2_task(TileLds& L, const Task t, const BlockDesc d, const double* __restrict__ Ap,
+                         const double* __restrict__ Zb, double* __restrict__ Hb, const int64_t* __restrict__ cbase,
+                         const int64_t* __restrict__ rbase, const int32_t* __restrict__ rel)
+{
+    const int s = d.s, c = d.c;
+    const int64_t ld = (int64_t)s + c;
+    const int r0 = t.i0, n0 = t.j0;
+    const double* Zd = Zb + d.poff;
+    d4 acc[2][4] = {};
+    auto loadG = [&](int k0, int kk, int ii) -> double {
+        const int i = r0 + ii, k = k0 + kk;
+        if (i >= c || k >= c) return 0.0;
+        if (i >= k) {
+            const int64_t pk = d.coff + k;
+            return Ap[cbase[pk] + rel[rbase[pk] + i]];
+        }
+        const int64_t pi = d.coff + i;
+        return Ap[cbase[pi] + rel[rbase[pi] + k]];
+    };
+    auto loadXb = [&](int k0, int kk, int j) -> double {
+        const int k = k0 + kk, jj = n0 + j;
+        return (k < c && jj < s) ? Zb[d.poff + s + k + (int64_t)jj * ld] : 0.0;
+    };
+    tile_mma<BN>(L, t.kb, t.ke, acc, loadG, loadXb, [&](int k0) { return k0 >= r0 + TBM; });
+    if (t.kb == 0) {  // -X Ybar, once per tile
+        auto loadX = [&](int k0, int kk, int ii) -> double {
+            const int i = r0 + ii, k = k0 + kk;
+            return (i < c && k < s) ? Ap[d.poff + s + i + (int64_t)k * ld] : 0.0;
+        };
+        auto loadY = [&](int k0, int kk, int j) -> double {
+            const int k = k0 + kk, jj = n0 + j;
+            return (k < s && jj < s) ? ybar_at(Zd, ld, k, jj) : 0.0;
+        };
+        tile_mma<BN>(L, 0, s, acc, loadX, loadY, [](int) { return false; });
+    }
+    tile_epilogue<BN>(acc, [&](int i, int j, double v) {
+        const int ii = r0 + i, jj = n0 + j;
+        if (ii < c && jj < s) {
+            double* p = Hb + d.hoff + ii + (int64_t)jj * c;
+            if (t.flags & 1) unsafeAtomicAdd(p, -v); else *p = -v;
+        }
+    });
+}
+
+__global__ __launch_bounds__(kThreads) void k_rs2(const Task* __restrict__ tasks, const BlockDesc* __restrict__ blk,
+                                                  const double* __restrict__ Ap, const double* __restrict__ Zb,
+                                                  double* __restrict__ Hb, const int64_t* __restrict__ cbase,
+                                                  const int64_t* __restrict__ rbase, const int32_t* __restrict__ rel)
+{
+    __shared__ TileLds L;
+    const Task t = tasks[blockIdx.x];
+    const BlockDesc d = blk[t.b];
+#define SELINV_CALL(BN) rs2_task<BN>(L, t, d, Ap, Zb, Hb, cbase, rbase, rel)
+    SELINV_BN_DISPATCH(t.bn, SELINV_CALL)
+#undef SELINV_CALL
+}
+
+// ancestors' Zbar += -(Xbar L_hat^T + L_hat Xbar^T): lower tile rows
+// [i0, i0+64) x columns [k0, k0+64), contraction over [Xbar | L_hat]
+__global__ __launch_bounds__(kThreads) void k_rs3(const Task* __restrict__ tasks, const BlockDesc* __restrict__ blk,
+                                                  double* __restrict__ Zb, const double* __restrict__ Hp,
+                                                  const int64_t* __restrict__ cbase,
+                                                  const int64_t* __restrict__ rbase, const int32_t* __restrict__ rel)
+{
+    __shared__ TileLds L;
+    const Task t = tasks[blockIdx.x];
+    const BlockDesc d = blk[t.b];
+    const int s = d.s, c = d.c;
+    const int64_t ld = (int64_t)s + c;
+    const int i0 = t.i0, k0c = t.j0;
+    const double* Xb = Zb + d.poff + s;
+    const double* H = Hp + d.hoff;
+    d4 acc[2][4] = {};
+    auto loadA = [&](int q0, int qq, int ii) -> double {
+        const int i = i0 + ii, q = q0 + qq;
+        if (i >= c || q >= 2 * s) return 0.0;
+        return q < s ? Xb[i + (int64_t)q * ld] : H[i + (int64_t)(q - s) * c];
+    };
+    auto loadB = [&](int q0, int qq, int j) -> double {
+        const int k = k0c + j, q = q0 + qq;
+        if (k >= c || q >= 2 * s) return 0.0;
+        return q < s ? H[k + (int64_t)q * c] : Xb[k + (int64_t)(q - s) * ld];
+    };
+    tile_mma<64>(L, 0, 2 * s, acc, loadA, loadB, [](int) { return false; });
+    tile_epilogue<64>(acc, [&](int i, int j, double v) {
+        const int ii = i0 + i, kk = k0c + j;
+        if (ii < c && kk < c && ii >= kk) {
+            const int64_t pk = d.coff + kk;
+            unsafeAtomicAdd(Zb + cbase[pk] + rel[rbase[pk] + ii], ii == kk ? -0.5 * v : -v);
+        }
+    });
+}
+
+// Tbar := Ybar for every block, once the reverse selected inversion is done
+__global__ void k_tbar_init(const Task* __restrict__ tasks, const BlockDesc* __restrict__ blk,
+                            const double* __restrict__ Zb, double* __restrict__ Tb)
+{
+    const BlockDesc d = blk[tasks[blockIdx.x].b];
+    const int64_t ld = (int64_t)d.s + d.c;
+    for (int e = threadIdx.x; e < d.s * d.s; e += blockDim.x)
+        Tb[d.woff + e] = ybar_at(Zb + d.poff, ld, e % d.s, e / d.s);
+}
+
+// Lhat_bar += Ubar F(C,B), Ubar(i,k) = -Fbar(C[i],C[k]) for i >= k
+template <int BN>
+__device__ void rf1a_task(TileLds& L, const Task t, const BlockDesc d, const double* __restrict__ Zb,
+                          const double* __restrict__ Lp, double* __restrict__ Hb, const int64_t* __restrict__ cbase,
+                          const int64_t* __restrict__ rbase, const int32_t* __restrict__ rel)
+{
+    const int s = d.s, c = d.c;
+    const int64_t ld = (int64_t)s + c;
+    const int r0 = t.i0, n0 = t.j0;
+    d4 acc[2][4] = {};
+    auto loadA = [&](int k0, int kk, int ii) -> double {
+        const int i = r0 + ii, k = k0 + kk;
+        if (i >= c || k > i) return 0.0;
+        const int64_t pk = d.coff + k;
+        return -Zb[cbase[pk] + rel[rbase[pk] + i]];
+    };
+    auto loadB = [&](int k0, int kk, int j) -> double {
+        const int k = k0 + kk, jj = n0 + j;
+        return (k < c && jj < s) ? Lp[d.poff + s + k + (int64_t)jj * ld] : 0.0;
+    };
+    tile_mma<BN>(L, t.kb, t.ke, acc, loadA, loadB, [](int) { return false; });
+    tile_epilogue<BN>(acc, [&](int i, int j, double v) {
+        const int ii = r0 + i, jj = n0 + j;
+        if (ii < c && jj < s) {
+            double* p = Hb + d.hoff + ii + (int64_t)jj * c;
+            if (t.flags & 1) unsafeAtomicAdd(p, v); else *p += v;
+        }
+    });
+}
+
+__global__ __launch_bounds__(kThreads) void k_rf1a(const Task* __restrict__ tasks, const BlockDesc* __restrict__ blk,
+                                                   const double* __restrict__ Zb, const double* __restrict__ Lp,
+                                                   double* __restrict__ Hb, const int64_t* __restrict__ cbase,
+                                                   const int64_t* __restrict__ rbase,
+                                                   const int32_t* __restrict__ rel)
+{
+    __shared__ TileLds L;
+    const Task t = tasks[blockIdx.x];
+    const BlockDesc d = blk[t.b];
+#define SELINV_CALL(BN) rf1a_task<BN>(L, t, d, Zb, Lp, Hb, cbase, rbase, rel)
+    SELINV_BN_DISPATCH(t.bn, SELINV_CALL)
+#undef SELINV_CALL
+}
+
+// Fbar(C,B) = Ubar^T L_hat (+ Lhat_bar T on piece 0), Ubar^T(i,k) = -Fbar(C[k],C[i]) for k >= i
+template <int BN>
+__device__ void rf1b_task(TileLds& L, const Task t, const BlockDesc d, double* __restrict__ Zb,
+                          const double* __restrict__ Hp, const double* __restrict__ Hb, const double* __restrict__ Tp,
+                          const int64_t* __restrict__ cbase, const int64_t* __restrict__ rbase,
+                          const int32_t* __restrict__ rel)
+{
+    const int s = d.s, c = d.c;
+    const int64_t ld = (int64_t)s + c;
+    const int r0 = t.i0, n0 = t.j0;
+    d4 acc[2][4] = {};
+    auto loadA = [&](int k0, int kk, int ii) -> double {
+        const int i = r0 + ii, k = k0 + kk;
+        if (i >= c || k >= c || k < i) return 0.0;
+        const int64_t pi = d.coff + i;
+        return -Zb[cbase[pi] + rel[rbase[pi] + k]];
+    };
+    auto loadB = [&](int k0, int kk, int j) -> double {
+        const int k = k0 + kk, jj = n0 + j;
+        return (k < c && jj < s) ? Hp[d.hoff + k + (int64_t)jj * c] : 0.0;
+    };
+    tile_mma<BN>(L, t.kb, t.ke, acc, loadA, loadB, [&](int k0) { return k0 >= r0 + TBM; });
+    if (t.flags & 2) {
+        auto loadA2 = [&](int k0, int kk, int ii) -> double {
+            const int i = r0 + ii, k = k0 + kk;
+            return (i < c && k < s) ? Hb[d.hoff + i + (int64_t)k * c] : 0.0;
+        };
+        auto loadB2 = [&](int k0, int kk, int j) -> double {
+            const int k = k0 + kk, jj = n0 + j;
+            return (k < s && jj < s) ? Tp[d.woff + k + (int64_t)jj * s] : 0.0;
+        };
+        tile_mma<BN>(L, 0, s, acc, loadA2, loadB2, [](int) { return false; });
+    }
+    tile_epilogue<BN>(acc, [&](int i, int j, double v) {
+        const int ii = r0 + i, jj = n0 + j;
+        if (ii < c && jj < s) {
+            double* p = Zb + d.poff + s + ii + (int64_t)jj * ld;
+            if (t.flags & 1) unsafeAtomicAdd(p, v); else *p = v;
+        }
+    });
+}
+
+__global__ __launch_bounds__(kThreads) void k_rf1b(const Task* __restrict__ tasks, const BlockDesc* __restrict__ blk,
+                                                   double* __restrict__ Zb, const double* __restrict__ Hp,
+                                                   const double* __restrict__ Hb, const double* __restrict__ Tp,
+                                                   const int64_t* __restrict__ cbase,
+                                                   const int64_t* __restrict__ rbase,
+                                                   const int32_t* __restrict__ rel)
+{
+    __shared__ TileLds L;
+    const Task t = tasks[blockIdx.x];
+    const BlockDesc d = blk[t.b];
+#define SELINV_CALL(BN) rf1b_task<BN>(L, t, d, Zb, Hp, Hb, Tp, cbase, rbase, rel)
+    SELINV_BN_DISPATCH(t.bn, SELINV_CALL)
+#undef SELINV_CALL
+}
+
+// Tbar(I,J) += F(C,B)^T Lhat_bar over rows [kb, ke) of C, one 32 x 32 tile
+__global__ __launch_bounds__(kThreads) void k_rf2(const Task* __restrict__ tasks, const BlockDesc* __restrict__ blk,
+                                                  const double* __restrict__ Lp, const double* __restrict__ Hb,
+                                                  double* __restrict__ Tb)
+{
+    __shared__ double FI[16][SDT + 1], HJ[16][SDT + 1];
+    const Task t = tasks[blockIdx.x];
+    const BlockDesc d = blk[t.b];
+    const int s = d.s, c = d.c;
+    const int64_t ld = (int64_t)s + c;
+    const int I0 = t.i0, J0 = t.j0;
+    const double* F = Lp + d.poff + s;
+    const double* H = Hb + d.hoff;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int fm = (wave & 1) * 16, fn = (wave >> 1) * 16;
+    d4 acc = {0, 0, 0, 0};
+    const int rend = min(c, t.ke);
+    for (int r0 = t.kb; r0 < rend; r0 += 16) {
+#pragma unroll
+        for (int q = 0; q < (16 * SDT) / kThreads; ++q) {
+            const int e = threadIdx.x + q * kThreads;
+            const int kk = e & 15, col = e >> 4;
+            const int r = r0 + kk;
+            const bool okr = r < rend;
+            const int ci = I0 + col, cj = J0 + col;
+            const double f = (okr && ci < s) ? F[r + (int64_t)ci * ld] : 0.0;
+            const double h = (okr && cj < s) ? H[r + (int64_t)cj * c] : 0.0;
+            FI[kk][col] = f;
+            HJ[kk][col] = h;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int kr = ks * 4 + (lane >> 4);
+            acc = mfma(FI[kr][fm + (lane & 15)], HJ[kr][fn + (lane & 15)], acc);
+        }
+        __syncthreads();
+    }
+    mfma_drain();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int gi = I0 + fm + (lane >> 4) + 4 * v, gj = J0 + fn + (lane & 15);
+        if (gi < s && gj < s) {
+            double* p = Tb + d.woff + gi + (int64_t)gj * s;
+            if (t.flags & 1) unsafeAtomicAdd(p, acc[v]); else *p += acc[v];
+        }
+    }
+}
+
+// Fbar(B,B) stored lower = -T (Tbar + Tbar^T) T with the diagonal halved; one
+// work-group per block, Q = (Tbar + Tbar^T) T held in LDS (s <= 128).
+__global__ __launch_bounds__(kThreads) void k_rf3(const Task* __restrict__ tasks, const BlockDesc* __restrict__ blk,
+                                                  const double* __restrict__ Tp, const double* __restrict__ Tb,
+                                                  double* __restrict__ Zb)
+{
+    extern __shared__ double Q[];
+    const BlockDesc d = blk[tasks[blockIdx.x].b];
+    const int s = d.s;
+    const int64_t ld = (int64_t)d.s + d.c;
+    const int ls = s + 1;
+    const double* T = Tp + d.woff;
+    const double* Tbar = Tb + d.woff;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nt = (s + 15) / 16;
+    for (int p = wave; p < nt * nt; p += kThreads / 64) {
+        const int i0 = (p / nt) * 16, j0 = (p % nt) * 16;
+        d4 acc = {0, 0, 0, 0};
+        for (int k4 = 0; k4 < s; k4 += 4) {
+            const int k = k4 + (lane >> 4), i = i0 + (lane & 15), j = j0 + (lane & 15);
+            const double a = (i < s && k < s) ? Tbar[i + (int64_t)k * s] + Tbar[k + (int64_t)i * s] : 0.0;
+            const double b = (k < s && j < s) ? T[k + (int64_t)j * s] : 0.0;
+            acc = mfma(a, b, acc);
+        }
+        mfma_drain();
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int ii = i0 + (lane >> 4) + 4 * v, jj = j0 + (lane & 15);
+            if (ii < s && jj < s) Q[ii * ls + jj] = acc[v];
+        }
+    }
+    __syncthreads();
+    for (int p = wave; p < nt * (nt + 1) / 2; p += kThreads / 64) {
+        int I = 0;
+        while ((I + 1) * (I + 2) / 2 <= p) ++I;
+        const int J = p - I * (I + 1) / 2;
+        const int i0 = I * 16, j0 = J * 16;
+        d4 acc = {0, 0, 0, 0};
+        for (int k4 = 0; k4 < s; k4 += 4) {
+            const int k = k4 + (lane >> 4), i = i0 + (lane & 15), j = j0 + (lane & 15);
+            const double a = (i < s && k < s) ? T[i + (int64_t)k * s] : 0.0;
+            const double b = (k < s && j < s) ? Q[k * ls + j] : 0.0;
+            acc = mfma(a, b, acc);
+        }
+        mfma_drain();
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int ii = i0 + (lane >> 4) + 4 * v, jj = j0 + (lane & 15);
+            if (ii < s && jj < s && ii >= jj) Zb[d.poff + ii + (int64_t)jj * ld] = ii == jj ? -0.5 * acc[v] : -acc[v];
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------
@@ -723,9 +1088,60 @@ static inline unsigned grid_for(int64_t n)
 
 hipError_t kernels_init()
 {
-    // the LDS diagonal factorization needs more than the default 64 KB
-    return hipFuncSetAttribute((const void*)k_ldlt_diag, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)kLdsDiagBytes);
+    // the LDS diagonal factorization and the reverse diagonal step need more
+    // than the default 64 KB of LDS
+    hipError_t e = hipFuncSetAttribute((const void*)k_ldlt_diag, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)kLdsDiagBytes);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)k_rf3, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsDiagBytes);
+    return e;
+}
+
+hipError_t launch_backward_init(Prof* P, const DevPtrs& D, int64_t arena, int64_t harena, const double* gsel,
+                                int64_t nnzL, hipStream_t s)
+{
+    hipError_t e = launch_fill(P, kRevSel, D.Zb, arena, 0.0, s);
+    if (!e) e = launch_fill(P, kRevSel, D.Hb, harena, 0.0, s);
+    if (!e) e = launch_scatter_set(P, kRevSel, gsel, D.exp_off, nnzL, D.Zb, s);
+    return e;
+}
+
+hipError_t launch_revsel_level(Prof* P, const DevPtrs& D, int64_t a0, int64_t na, int64_t b0, int64_t nb, int64_t c0,
+                               int64_t nc, hipStream_t s)
+{
+    if (na > 0) launch(P, kRevSel, k_rs1, dim3((unsigned)na), 0, s, D.t_rs1 + a0, D.blocks, D.Zb, (const double*)D.Hp);
+    if (nb > 0)
+        launch(P, kRevSel, k_rs2, dim3((unsigned)nb), 0, s, D.t_rs2 + b0, D.blocks, (const double*)D.Ap,
+               (const double*)D.Zb, D.Hb, D.cbase, D.rbase, D.rel);
+    if (nc > 0)
+        launch(P, kRevSel, k_rs3, dim3((unsigned)nc), 0, s, D.t_rs3 + c0, D.blocks, D.Zb, (const double*)D.Hp,
+               D.cbase, D.rbase, D.rel);
+    return hipGetLastError();
+}
+
+hipError_t launch_revfac_init(Prof* P, const DevPtrs& D, int64_t nblocks, int64_t arena, hipStream_t s)
+{
+    if (nblocks > 0)
+        launch(P, kRevFac, k_tbar_init, dim3((unsigned)nblocks), 0, s, D.t_diag, D.blocks, (const double*)D.Zb, D.Tb);
+    return launch_fill(P, kRevFac, D.Zb, arena, 0.0, s);
+}
+
+hipError_t launch_revfac_level(Prof* P, const DevPtrs& D, int64_t a0, int64_t na, int64_t b0, int64_t nb, int64_t c0,
+                               int64_t nc, int64_t d0, int64_t nd, hipStream_t s)
+{
+    if (na > 0)
+        launch(P, kRevFac, k_rf1a, dim3((unsigned)na), 0, s, D.t_rf1a + a0, D.blocks, (const double*)D.Zb,
+               (const double*)D.Lp, D.Hb, D.cbase, D.rbase, D.rel);
+    if (nb > 0)
+        launch(P, kRevFac, k_rf1b, dim3((unsigned)nb), 0, s, D.t_rf1b + b0, D.blocks, D.Zb, (const double*)D.Hp,
+               (const double*)D.Hb, (const double*)D.Tp, D.cbase, D.rbase, D.rel);
+    if (nc > 0)
+        launch(P, kRevFac, k_rf2, dim3((unsigned)nc), 0, s, D.t_rf2 + c0, D.blocks, (const double*)D.Lp,
+               (const double*)D.Hb, D.Tb);
+    if (nd > 0)
+        launch(P, kRevFac, k_rf3, dim3((unsigned)nd), kLdsDiagBytes, s, D.t_diag + d0, D.blocks, (const double*)D.Tp,
+               (const double*)D.Tb, D.Zb);
+    return hipGetLastError();
 }
 
 hipError_t launch_status_reset(unsigned long long* status, hipStream_t s)

@@ -12,6 +12,7 @@ namespace selinv {
 // Device views of the workspace sub-arrays.
 struct DevPtrs {
     double *Lp, *Ap, *Hp, *Wp, *Tp;
+    double *Zb, *Hb, *Tb;  // adjoint arenas
     unsigned long long* status;
     const BlockDesc* blocks;
     const int32_t* crow;
@@ -21,9 +22,17 @@ struct DevPtrs {
     const int32_t* colblk;     // column -> execution block
     const int64_t* colptrL;    // canonical column pointers of L
     const Task *t_diag, *t_panel, *t_schur, *t_gemm, *t_sdiag, *t_zero;
+    const Task *t_rs1, *t_rs2, *t_rs3, *t_rf1a, *t_rf1b, *t_rf2;
 };
 
 hipError_t kernels_init();
+hipError_t launch_backward_init(Prof* P, const DevPtrs& D, int64_t arena, int64_t harena, const double* gsel,
+                                int64_t nnzL, hipStream_t s);
+hipError_t launch_revsel_level(Prof* P, const DevPtrs& D, int64_t a0, int64_t na, int64_t b0, int64_t nb, int64_t c0,
+                               int64_t nc, hipStream_t s);
+hipError_t launch_revfac_init(Prof* P, const DevPtrs& D, int64_t nblocks, int64_t arena, hipStream_t s);
+hipError_t launch_revfac_level(Prof* P, const DevPtrs& D, int64_t a0, int64_t na, int64_t b0, int64_t nb, int64_t c0,
+                               int64_t nc, int64_t d0, int64_t nd, hipStream_t s);
 hipError_t launch_zero_x(Prof* P, const DevPtrs& D, int64_t nblocks, hipStream_t s);
 hipError_t launch_export_L(Prof* P, const DevPtrs& D, int64_t n, double* out, hipStream_t s);
 hipError_t launch_status_reset(unsigned long long* status, hipStream_t s);

@@ -52,7 +52,7 @@ struct LevelTasks {
 };
 
 // Kernel kinds (same numbering as SELINV_K_* in selinv.h).
-enum Kind { kAssemble = 0, kLdlt, kPanel, kSchur, kGemm, kSdiag, kExport, kNumKinds };
+enum Kind { kAssemble = 0, kLdlt, kPanel, kSchur, kGemm, kSdiag, kExport, kRevSel, kRevFac, kNumKinds };
 
 // Optional per-launch timing: start/stop events are stamped by the dispatch
 // itself (hipExtLaunchKernelGGL), so no marker packets are added.
@@ -68,7 +68,9 @@ struct Prof {
 struct DeviceLayout {
     // byte offsets into the workspace
     size_t lp, ap, hp, wp, tp, status, blocks, crow, cbase, rbase, rel, asm_off, exp_off, colblk, colptrL;
-    size_t t_diag, t_panel, t_schur, t_gemm, t_sdiag, t_zero, total;
+    size_t t_diag, t_panel, t_schur, t_gemm, t_sdiag, t_zero;
+    size_t zb, hb, tb;  // adjoint arenas (backward)
+    size_t t_rs1, t_rs2, t_rs3, t_rf1a, t_rf1b, t_rf2, total;
 };
 
 }  // namespace selinv
@@ -94,6 +96,8 @@ struct selinv_plan_s {
     std::vector<int32_t> colblk;       // column -> execution block
     int64_t arena = 0, harena = 0, warena = 0;
     selinv::LevelTasks t_diag, t_panel, t_schur, t_gemm, t_sdiag;
+    // reverse sweep: selected inversion (leaves first) and factorization (root first)
+    selinv::LevelTasks t_rs1, t_rs2, t_rs3, t_rf1a, t_rf1b, t_rf2;
     std::vector<selinv::Task> t_zero;  // blocks whose X accumulates over split contractions
     selinv::DeviceLayout lay{};
     selinv_info info{};
@@ -101,6 +105,7 @@ struct selinv_plan_s {
     char* ws = nullptr;
     size_t ws_bytes = 0;
     bool factored = false;
+    bool inverted = false;
     selinv::Prof prof;
     std::vector<double> work_flops, work_bytes;  // per kernel kind, per call
 };

@@ -1,7 +1,8 @@
 // Per-level task lists (Algorithm 2 priority levels): the factor runs the
 // levels from the leaves up, the inversion from the root down; all blocks of
 // one level are independent (Section 2.2), so each level is one launch per
-// kernel kind with one work-group per task.
+// kernel kind with one work-group per task.  The reverse sweep uses the same
+// levels in the opposite orders.
 #include <algorithm>
 
 #include "kernels.hpp"
@@ -16,19 +17,44 @@ static void by_level(const selinv_plan_s* P, std::vector<std::vector<int>>& lv)
     for (int B = 0; B < P->exec.nblocks(); B++) lv[P->exec.lev[B] - 1].push_back(B);
 }
 
+// contraction range [lo, hi) cut into `split` pieces aligned to 16 rows; an
+// empty range still yields one (empty) piece, e.g. the diagonal block of a
+// root (c = 0) whose inverse is T alone
+template <class F>
+static void pieces(int lo, int hi, int split, F emit)
+{
+    if (hi <= lo) {
+        emit(lo, lo, 0);
+        return;
+    }
+    const int n16 = (hi - lo + 15) / 16;
+    for (int q = 0; q < split; q++) {
+        const int kb = lo + (int)((int64_t)n16 * q / split) * 16;
+        const int ke = std::min(hi, lo + (int)((int64_t)n16 * (q + 1) / split) * 16);
+        if (kb < ke) emit(kb, ke, q);
+    }
+}
+
+static int split_for(int64_t want, int len)
+{
+    const int maxsplit = std::max(1, ((len + 15) / 16) / (kMinSplitK / 16));
+    return (int)std::min<int64_t>(want, maxsplit);
+}
+
 void build_schedule(selinv_plan_s* P)
 {
     std::vector<std::vector<int>> lv;
     by_level(P, lv);
     const int D = (int)lv.size();
-    LevelTasks* all[] = {&P->t_diag, &P->t_panel, &P->t_schur, &P->t_gemm, &P->t_sdiag};
+    LevelTasks* all[] = {&P->t_diag, &P->t_panel, &P->t_schur, &P->t_gemm, &P->t_sdiag, &P->t_rs1,
+                         &P->t_rs2,  &P->t_rs3,   &P->t_rf1a,  &P->t_rf1b, &P->t_rf2};
     for (LevelTasks* t : all) {
         t->tasks.clear();
         t->off.assign(D + 1, 0);
     }
     P->t_zero.clear();
     for (int l = 0; l < D; l++) {
-        // tiles of X this level has without splitting the contraction over C
+        // tiles this level has without splitting contractions over C
         int64_t base = 0, dbase = 0;
         for (int B : lv[l]) {
             const BlockDesc& d = P->blocks[B];
@@ -41,52 +67,76 @@ void build_schedule(selinv_plan_s* P)
         for (int B : lv[l]) {
             const BlockDesc& d = P->blocks[B];
             const int bn = tile_bn(d.s);
+            const int s = d.s, c = d.c;
             P->t_diag.tasks.push_back({B, 0, 0, 0, 0, 0, 0, 0});
             // contractions over C are split into pieces of >= kMinSplitK rows
             // when a level has too few tiles to fill the device
-            const int nchunk = (d.c + 15) / 16;
-            const int maxsplit = std::max(1, nchunk / (kMinSplitK / 16));
-            const int split = (int)std::min<int64_t>(want, maxsplit);
-            const int dsplit = (int)std::min<int64_t>(dwant, maxsplit);
+            const int split = split_for(want, c);
+            const int dsplit = split_for(dwant, c);
             if (split > 1 || dsplit > 1) P->t_zero.push_back({B, 0, 0, 0, 0, 0, 0, 0});
-            const int nd = (d.s + kDiagTile - 1) / kDiagTile;
+            const int nd = (s + kDiagTile - 1) / kDiagTile;
             for (int I = 0; I < nd; I++)
                 for (int J = 0; J <= I; J++)
-                    for (int q = 0; q < dsplit; q++) {
-                        const int kb = (int)((int64_t)nchunk * q / dsplit) * 16;
-                        const int ke = std::min(d.c, (int)((int64_t)nchunk * (q + 1) / dsplit) * 16);
+                    pieces(0, c, dsplit, [&](int kb, int ke, int) {
                         P->t_sdiag.tasks.push_back({B, I * kDiagTile, J * kDiagTile, 0, kb, ke, dsplit > 1, 0});
-                    }
-            for (int j = 0; j < d.s; j += bn)
-                for (int r = 0; r < d.c; r += kTileM) {
-                    P->t_panel.tasks.push_back({B, r, j, bn, 0, d.s, 0, 0});
-                    for (int q = 0; q < split; q++) {
-                        const int kb = (int)((int64_t)nchunk * q / split) * 16;
-                        const int ke = std::min(d.c, (int)((int64_t)nchunk * (q + 1) / split) * 16);
-                        P->t_gemm.tasks.push_back({B, r, j, bn, kb, ke, split > 1 ? 1 : 0, 0});
-                    }
+                    });
+            for (int I = 0; I < nd; I++)
+                for (int J = 0; J < nd; J++)
+                    pieces(0, c, dsplit, [&](int kb, int ke, int) {
+                        P->t_rf2.tasks.push_back({B, I * kDiagTile, J * kDiagTile, 0, kb, ke, dsplit > 1, 0});
+                    });
+            for (int j = 0; j < s; j += bn)
+                for (int r = 0; r < c; r += kTileM) {
+                    P->t_panel.tasks.push_back({B, r, j, bn, 0, s, 0, 0});
+                    P->t_rs1.tasks.push_back({B, r, j, bn, 0, s, 0, 0});
+                    pieces(0, c, split, [&](int kb, int ke, int) {
+                        P->t_gemm.tasks.push_back({B, r, j, bn, kb, ke, split > 1, 0});
+                        P->t_rs2.tasks.push_back({B, r, j, bn, kb, ke, split > 1, 0});
+                    });
+                    // reverse factor: Ubar is lower triangular, so row tile r
+                    // contracts over [0, r+64) with Ubar and over [r, c) with Ubar^T
+                    const int hi = std::min(c, r + kTileM);
+                    const int sa = split_for(want, hi);
+                    pieces(0, hi, sa, [&](int kb, int ke, int) {
+                        P->t_rf1a.tasks.push_back({B, r, j, bn, kb, ke, sa > 1, 0});
+                    });
+                    const int sb = split_for(want, c - r);
+                    pieces(r, c, sb, [&](int kb, int ke, int q) {
+                        // piece 0 also adds L_hat_bar T
+                        P->t_rf1b.tasks.push_back({B, r, j, bn, kb, ke, (sb > 1) | (q == 0 ? 2 : 0), 0});
+                    });
                 }
-            for (int k = 0; k < d.c; k += kSchurTile)
-                for (int i = k; i < d.c; i += kSchurTile)
-                    P->t_schur.tasks.push_back({B, i, k, kSchurTile, 0, d.s, 0, 0});
+            for (int k = 0; k < c; k += kSchurTile)
+                for (int i = k; i < c; i += kSchurTile) {
+                    P->t_schur.tasks.push_back({B, i, k, kSchurTile, 0, s, 0, 0});
+                    P->t_rs3.tasks.push_back({B, i, k, kSchurTile, 0, 2 * s, 0, 0});
+                }
         }
         for (LevelTasks* t : all) t->off[l + 1] = (int64_t)t->tasks.size();
     }
-    // algorithmic work of one factor / one invert call, per kernel kind
+    // algorithmic work of one factor / invert / backward call, per kernel kind
     P->work_flops.assign(kNumKinds, 0.0);
     P->work_bytes.assign(kNumKinds, 0.0);
     for (const BlockDesc& d : P->blocks) {
         const double s = d.s, c = d.c;
-        P->work_flops[kLdlt] += s * s * s;              // LDL^T s^3/3, W s^3/3, T s^3/3
+        P->work_flops[kLdlt] += s * s * s;              // sweep: s pivots x s^2 updates
         P->work_bytes[kLdlt] += 8.0 * 3 * s * s;
         P->work_flops[kPanel] += 2.0 * c * s * s;       // L_hat = F(C,B) T
         P->work_bytes[kPanel] += 8.0 * (2 * c * s + s * s);
-        P->work_flops[kSchur] += c * c * s;             // lower half of L D L^T
+        P->work_flops[kSchur] += c * c * s;             // lower half of L_hat F^T
         P->work_bytes[kSchur] += 8.0 * (c * s + c * (c + 1) / 2);
         P->work_flops[kGemm] += 2.0 * c * c * s;        // X = -G L_hat
         P->work_bytes[kGemm] += 8.0 * (c * (c + 1) / 2 + 2 * c * s);
         P->work_flops[kSdiag] += 2.0 * c * s * s;       // Y = T - L_hat^T X
         P->work_bytes[kSdiag] += 8.0 * (2 * c * s + 2 * s * s);
+        // reverse selected inversion: Xbar (2cs^2), Lhat_bar (2c^2 s + 2cs^2),
+        // symmetric scatter of -(Xbar L_hat^T + L_hat Xbar^T) (2c^2 s, lower half)
+        P->work_flops[kRevSel] += 4.0 * c * c * s + 4.0 * c * s * s;
+        P->work_bytes[kRevSel] += 8.0 * (c * (c + 1) + 6 * c * s + s * s);
+        // reverse factor: Ubar F (c^2 s), Ubar^T L_hat + Lhat_bar T (c^2 s + 2cs^2),
+        // F^T Lhat_bar (2cs^2), -T (Tbar + Tbar^T) T (4 s^3)
+        P->work_flops[kRevFac] += 2.0 * c * c * s + 4.0 * c * s * s + 4.0 * s * s * s;
+        P->work_bytes[kRevFac] += 8.0 * (c * (c + 1) + 6 * c * s + 4 * s * s);
     }
     const double nnzL = (double)P->colptrL.back(), nnzA = (double)P->nnzA;
     P->work_bytes[kAssemble] = 8.0 * P->arena + 24.0 * nnzA;

@@ -20,12 +20,13 @@ _NAMES = {0: "OK", -1: "EINVAL", -2: "ESTATE", -3: "EPIVOT", -4: "ENOMEM", -5: "
 
 # every symbol include/selinv.h declares
 EXPORTS = ["selinv_analyze", "selinv_workspace_size", "selinv_bind_workspace", "selinv_factor", "selinv_invert",
+           "selinv_backward",
            "selinv_get_factor", "selinv_sync_status", "selinv_get_info", "selinv_get_pattern",
            "selinv_symbolic_sizes", "selinv_get_symbolic", "selinv_profile", "selinv_profile_read",
            "selinv_kernel_work", "selinv_get_arena", "selinv_get_blocks", "selinv_get_exec_rows",
            "selinv_last_error", "selinv_destroy"]
-ARENAS = {"L": 0, "Ainv": 1, "Lhat": 2, "W": 3, "T": 4}
-KINDS = ["assemble", "ldlt", "panel", "schur", "gemm", "sdiag", "export"]
+ARENAS = {"L": 0, "Ainv": 1, "Lhat": 2, "W": 3, "T": 4, "Fbar": 5, "Lhat_bar": 6, "T_bar": 7}
+KINDS = ["assemble", "ldlt", "panel", "schur", "gemm", "sdiag", "export", "revsel", "revfac"]
 
 
 class SelinvError(RuntimeError):
@@ -67,6 +68,7 @@ def lib():
         L.selinv_factor.argtypes = [vp, vp, vp]
         L.selinv_invert.argtypes = [vp, vp, vp]
         L.selinv_get_factor.argtypes = [vp, vp, vp]
+        L.selinv_backward.argtypes = [vp, vp, vp, vp]
         L.selinv_sync_status.argtypes = [vp, vp, ct.POINTER(i64)]
         L.selinv_get_info.argtypes = [vp, ct.POINTER(Info)]
         L.selinv_get_pattern.argtypes = [vp, vp, vp, vp]
@@ -197,6 +199,17 @@ class Plan:
         _check(lib().selinv_invert(self._h, ct.c_void_p(out.data_ptr()), _stream(stream)))
         return out
 
+    def backward(self, gsel, out=None, stream=None):
+        """d(sum gsel * Ainv on L's pattern)/d(A's stored entries), on the device."""
+        import torch
+        self._need(gsel, int(self.info["nnzL"]), "gsel")
+        if out is None:
+            out = torch.empty(int(self.info["nnzA"]), dtype=torch.float64, device=self._ws.device)
+        self._need(out, int(self.info["nnzA"]), "out")
+        _check(lib().selinv_backward(self._h, ct.c_void_p(gsel.data_ptr()), ct.c_void_p(out.data_ptr()),
+                                     _stream(stream)))
+        return out
+
     def factor_values(self, out=None, stream=None):
         import torch
         nnzL = int(self.info["nnzL"])
@@ -258,6 +271,41 @@ class Plan:
                 self._h = None
         except Exception:
             pass
+
+
+def _autograd_function():
+    import torch
+
+    class SelInv(torch.autograd.Function):
+        """vals (A's stored lower entries, nnzA) -> selected entries of A^{-1}
+        on the pattern of L (nnzL).  The backward is the library's reverse
+        sweep; an off-diagonal entry of A stands for A_ij and A_ji."""
+
+        @staticmethod
+        def forward(ctx, vals, plan):
+            plan.factor(vals.contiguous())
+            sel = plan.invert()
+            ctx.plan = plan
+            return sel
+
+        @staticmethod
+        def backward(ctx, gsel):
+            g = ctx.plan.backward(gsel.contiguous().to(torch.float64))
+            return g, None
+
+    return SelInv
+
+
+_SelInv = None
+
+
+def selinv(vals, plan):
+    """Differentiable selected inversion: ``selinv(vals, plan)`` with ``vals``
+    a float64 CUDA tensor of A's stored lower entries."""
+    global _SelInv
+    if _SelInv is None:
+        _SelInv = _autograd_function()
+    return _SelInv.apply(vals, plan)
 
 
 def selected_inverse(m, vals=None, **kw):
