@@ -11,7 +11,11 @@ Prints ONE JSON line.  `value` is algorithmic FP64 GFLOP/s of the step
 the step time).  `roofline` covers the kernel kind with the largest share of
 device time, timed live with HIP events stamped in each dispatch.
 `cpu_baseline` times the CPU oracle (test infrastructure, untuned) on the
-same matrix.
+same matrix.  Two more parts of the metric ride on the same line:
+`backward` (the reverse sweep's time over the forward step's, same matrix)
+and `batched` (256 independent 2D grids: the batch on the persistent
+per-level kernels replayed from a HIP graph, against a loop of per-matrix
+runs with per-level launches, same kernels, same GPU).
 """
 from __future__ import annotations
 
@@ -48,6 +52,9 @@ def main():
     ap.add_argument("--workload", default="lap3d_40", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fuse", action="store_true", help="run fundamental supernodes unamalgamated")
+    ap.add_argument("--no-bwd", action="store_true", help="skip the backward (adjoint) timing")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-speedup measurement")
+    ap.add_argument("--batch-reps", type=int, default=10, help="timed replays of the batched graph")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the multi-GPU "
@@ -143,6 +150,11 @@ def main():
         "cpu_baseline": None,
     }
 
+    if not args.no_bwd:
+        result["backward"] = measure_backward(plan, vals, out, ms_step, args, dev)
+    if not args.no_batch:
+        result["batched"] = measure_batched(args, dev)
+
     if not args.no_cpu:
         from oracle import oracle as O
         log("[bench] cpu baseline: oracle symbolic ...")
@@ -165,6 +177,123 @@ def main():
         result["max_err_vs_oracle"] = err
         log(f"[bench] oracle {tf + ts:.2f}s ({wall:.1f}s wall), max err vs oracle {err:.2e}")
     print(json.dumps(result), flush=True)
+
+
+def _time(fn, reps, stream):
+    import torch
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(reps):
+        fn()
+    stop.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / reps
+
+
+def measure_backward(plan, vals, out, fwd_ms, args, dev):
+    """Reverse sweep (adjoint of factor + selected inversion) on the bench
+    matrix for a seeded weight vector, timed against the forward step."""
+    import numpy as np
+    import torch
+    from paper_1404_0447_amd import selinv as S
+    if plan.blocks()["s"].max() > 128:
+        return {"skipped": "execution blocks wider than 128 columns"}
+    rng = np.random.default_rng(0)
+    g = torch.as_tensor(rng.standard_normal(int(plan.info["nnzL"])), device=dev)
+    gA = torch.empty(int(plan.info["nnzA"]), dtype=torch.float64, device=dev)
+    plan.factor(vals)
+    plan.invert(out)
+    stream = torch.cuda.current_stream()
+    for _ in range(max(1, args.warmup)):
+        plan.backward(g, out=gA)
+    plan.profile(True)
+    bwd_ms = _time(lambda: plan.backward(g, out=gA), args.steps, stream)
+    plan.profile(False)
+    prof = plan.profile_read()
+    plan.sync_status()
+    log(f"[bench] backward {bwd_ms:.3f} ms/step ({bwd_ms / fwd_ms:.2f}x forward)")
+    return {"fwd_ms": round(fwd_ms, 4), "bwd_ms": round(bwd_ms, 4), "bwd_over_fwd": round(bwd_ms / fwd_ms, 3),
+            "kernels_ms": {k: round(prof[k][0] / args.steps, 4) for k in ("revsel", "revfac")},
+            "target": "<= 3"}
+
+
+def measure_batched(args, dev):
+    """256 2D 5-point grids, sides U{32..96}, shifts U[0.01,1] (seed 3):
+    batched persistent kernels replayed from a graph vs a loop of per-matrix
+    plans launching per level.  Every matrix is checked against the oracle."""
+    import numpy as np
+    import torch
+    from paper_1404_0447_amd import selinv as S
+    from paper_1404_0447_amd import workloads as W
+    stream = torch.cuda.current_stream()
+    t0 = time.time()
+    ms = W.batch_2d()
+    batch = S.Plan.batch(ms).bind(device=dev)
+    vals = torch.as_tensor(np.concatenate([m.vals for m in ms]), device=dev)
+    out = torch.empty(int(batch.info["nnzL"]), dtype=torch.float64, device=dev)
+    log(f"[bench] batch: {len(ms)} matrices n={batch.info['n']} nnzL={batch.info['nnzL']} "
+        f"blocks={batch.info['nblocks']} levels={batch.info['exec_depth']} ({time.time() - t0:.1f}s)")
+    sched, tune_ms, _ = batch.tune(vals, out=out)
+    log(f"[bench] batch tuned: {sched} {tune_ms:.3f} ms")
+    for _ in range(max(1, args.warmup)):
+        batch.run(vals, out=out, graph=True)
+    batch.sync_status()
+    reps = args.batch_reps
+    ms_graph = _time(lambda: batch.run(vals, out=out, graph=True), reps, stream)
+    ms_direct = _time(lambda: batch.run(vals, out=out), reps, stream)
+    def union_levels():
+        batch.factor(vals)
+        batch.invert(out)
+    union_levels()
+    ms_union = _time(union_levels, reps, stream)
+    batch.run(vals, out=out, graph=True)
+    batch.sync_status()
+    got = out.cpu().numpy()
+    # per-matrix plans, per-level launches: the loop the batch replaces
+    t0 = time.time()
+    plans = [S.Plan.from_matrix(m).bind(device=dev) for m in ms]
+    pv = [vals[int(batch.nnzA_off[k]):int(batch.nnzA_off[k + 1])] for k in range(len(ms))]
+    po = [torch.empty(int(p.info["nnzL"]), dtype=torch.float64, device=dev) for p in plans]
+    log(f"[bench] per-matrix plans ready ({time.time() - t0:.1f}s)")
+
+    def loop():
+        for p, v, o in zip(plans, pv, po):
+            p.factor(v)
+            p.invert(o)
+    loop()
+    for p in plans:
+        p.sync_status()
+    ms_loop = _time(loop, max(1, reps // 5), stream)
+    flops = batch.info["flops_factor"] + batch.info["flops_selinv"]
+    res = {"workload": "256 2D 5-point grids, side U{32..96}, shift U[0.01,1], seed 3",
+           "count": len(ms), "n": batch.info["n"], "nnzL": batch.info["nnzL"], "blocks": batch.info["nblocks"],
+           "levels": batch.info["exec_depth"], "schedule": sched,
+           "ms_graph": round(ms_graph, 4), "ms_persistent_direct": round(ms_direct, 4),
+           "ms_union_per_level_launches": round(ms_union, 4), "ms_loop_per_matrix": round(ms_loop, 4),
+           "speedup_vs_loop": round(ms_loop / ms_graph, 2),
+           "gflops_graph": round(flops / (ms_graph * 1e-3) / 1e9, 3)}
+    log(f"[bench] batched graph {ms_graph:.3f} ms, direct {ms_direct:.3f} ms, union per-level {ms_union:.3f} ms, "
+        f"loop {ms_loop:.3f} ms: speedup {ms_loop / ms_graph:.1f}x")
+    if not args.no_cpu:
+        from oracle import oracle as O
+        worst, cpu_s = 0.0, 0.0
+        for k, m in enumerate(ms):
+            o = O.symbolic(m, cap=128)
+            ref, _, st, _, tf, ts = o.factor_selinv(m.vals)
+            cpu_s += tf + ts
+            l0, l1 = int(batch.nnzL_off[k]), int(batch.nnzL_off[k + 1])
+            cp, ri = o.sym.colptrL, o.sym.rowindL
+            d = ref[cp[:-1]]
+            cols = np.repeat(np.arange(m.n), np.diff(cp))
+            worst = max(worst, float(np.max(np.abs(got[l0:l1] - ref) / np.sqrt(np.abs(d[ri] * d[cols])))))
+        res["max_err_vs_oracle"] = worst
+        res["cpu_oracle_ms"] = round(cpu_s * 1e3, 2)
+        res["cpu_oracle_cores"] = O.threads()
+        log(f"[bench] batch vs oracle: max err {worst:.2e}; oracle {cpu_s:.2f}s")
+    del plans
+    return res
 
 
 if __name__ == "__main__":

@@ -10,7 +10,11 @@
  * block index maps) -> selinv_bind_workspace (device memory owned by the
  * caller) -> selinv_factor (device supernodal LDL^T) -> selinv_invert
  * (device root-to-leaf selected inversion, written as values on the pattern
- * of L).
+ * of L).  selinv_backward runs the adjoint of both.  selinv_analyze_batch
+ * builds one plan for many independent matrices, and selinv_run executes
+ * factor + inversion with one persistent work-queue launch per tree level
+ * (optionally replayed from a captured HIP graph), with the schedule chosen
+ * by selinv_tune.
  *
  * Conventions for every call:
  *  - Status codes are returned, never thrown.  selinv_last_error() gives a
@@ -45,7 +49,9 @@ typedef enum {
     SELINV_EPIVOT = -3,       /* zero / non-finite / non-positive pivot        */
     SELINV_ENOMEM = -4,       /* host allocation failed or workspace too small */
     SELINV_EHIP = -5,         /* a HIP runtime call failed                     */
-    SELINV_EUNSUPPORTED = -6  /* option not supported                          */
+    SELINV_EUNSUPPORTED = -6, /* option not supported                          */
+    SELINV_EQUEUE = -7        /* a persistent-kernel dependency wait gave up
+                                 (poll limit reached); the results are invalid */
 } selinv_status;
 
 /* Geometry used by the nested-dissection ordering: a box grid of
@@ -161,7 +167,9 @@ enum {
     SELINV_K_EXPORT = 6,   /* panels -> canonical values                         */
     SELINV_K_REVSEL = 7,   /* reverse selected inversion (adjoint), leaves first */
     SELINV_K_REVFAC = 8,   /* reverse factorization (adjoint), root first        */
-    SELINV_NKINDS = 9
+    SELINV_K_QFACTOR = 9,  /* persistent factor level (LDLT, PANEL, SCHUR tasks)  */
+    SELINV_K_QINVERT = 10, /* persistent inversion level (GEMM, SDIAG tasks)      */
+    SELINV_NKINDS = 11
 };
 
 /* Enable (1) or disable (0) per-launch timing: every later kernel launch of
@@ -196,6 +204,91 @@ selinv_status selinv_get_blocks(selinv_plan p, int32_t* first, int32_t* s, int32
 
 /* Row structures C(b) of the execution blocks, concatenated (host copy). */
 selinv_status selinv_get_exec_rows(selinv_plan p, int32_t* rows);
+
+/* ------------------------------------------------------------------------
+ * Batched form and persistent execution.
+ *
+ * A batch of independent matrices is analysed as the block-diagonal matrix
+ * they form: its elimination tree is the forest of their trees, and the
+ * priority levels of Algorithm 2 (root = 1 in every tree) line up across the
+ * batch (Section 3.4), so one launch per level serves every matrix; the
+ * matrices are independent problems, like the pole matrices of the
+ * electronic-structure application (Section 4.3).  The result
+ * is an ordinary plan: every call above works on it, with the matrices'
+ * unknowns, A entries and L entries concatenated in batch order.
+ * ------------------------------------------------------------------------ */
+
+/* Analyse `count` matrices (each as in selinv_analyze, with geoms[m] its
+ * geometry; geoms may be NULL) into one plan.  Per matrix m: ns[m] order,
+ * colptrs[m][ns[m]+1], rowinds[m][...] host arrays read during the call.
+ * Columns of matrix m are ns[0] + ... + ns[m-1] + its own (permuted)
+ * indices; perm maps within each matrix.  A failing matrix is named in the
+ * error message.  The total order must stay below 2^31 - 1. */
+selinv_status selinv_analyze_batch(int32_t count, const int64_t* ns, const int64_t* const* colptrs,
+                                   const int32_t* const* rowinds, const selinv_geom* geoms, const selinv_opts* opts,
+                                   selinv_plan* out);
+
+/* Offsets of the matrices of a batch (count + 1 entries each; any pointer may
+ * be NULL): columns, A's entries (the d_valsA layout) and L's entries (the
+ * d_sel layout).  A plan from selinv_analyze is a batch of one. */
+selinv_status selinv_batch_offsets(selinv_plan p, int32_t* count, int64_t* n_off, int64_t* nnzA_off,
+                                   int64_t* nnzL_off);
+
+/* Schedule of the persistent path.  Each level's queue lists its tasks phase
+ * by phase (factor: diagonal block, L_hat tiles, Schur tiles; inversion:
+ * zeroing of split blocks, gather-GEMM tiles, diagonal tiles) and, within a
+ * phase, in `order`: 0 plan order (matrix by matrix), 1 largest block first,
+ * 2 round robin over the matrices, 3 largest tile first.  bn_cap: widest
+ * output tile of the gather-GEMM and panel products (16, 32, 64, 128).
+ * split_fill (0..4096): contractions are split over work-groups while a
+ * level has fewer output tiles than this (0 = never).  grid_mult: resident
+ * work-groups per compute unit (capped by the kernel's occupancy). */
+typedef struct {
+    int32_t order;
+    int32_t bn_cap;
+    int32_t split_fill;
+    int32_t grid_mult;
+} selinv_sched;
+
+/* Rebuild the work queues for schedule *sc and upload them on stream s
+ * (synchronises s; s is unused before selinv_bind_workspace); drops a
+ * captured graph.  SELINV_EINVAL for a field out of range.  The workspace
+ * reserves queue space for every valid schedule. */
+selinv_status selinv_set_schedule(selinv_plan p, const selinv_sched* sc, hipStream_t s);
+selinv_status selinv_get_schedule(selinv_plan p, selinv_sched* sc);
+
+/* Host copy of one level's queue (sweep 0 factor, 1 inversion; level 1 =
+ * roots) as 8 int32 per task: block, row origin, column origin, tile width,
+ * contraction begin, end, flags (bit 0 atomic accumulation, bits 8..15 the
+ * operation: 0 LDLT, 1 PANEL, 2 SCHUR, 3 ZERO, 4 GEMM, 5 SDIAG) and the number
+ * of earlier tasks of the same block it waits for.  *count = tasks; tasks may
+ * be NULL. */
+selinv_status selinv_get_queue(selinv_plan p, int32_t sweep, int32_t level, int32_t* tasks, int64_t* count);
+
+/* Polls a dependency wait makes before it gives up and latches
+ * SELINV_EQUEUE (default 2^22, far beyond any legitimate wait); the kernel
+ * still runs every task, so it always finishes.  A small value forces the
+ * error path for tests.  Drops a captured graph. */
+selinv_status selinv_set_spin_limit(selinv_plan p, uint32_t polls);
+
+/* Factor and invert (same results as selinv_factor + selinv_invert, up to
+ * the order of floating-point atomic additions) with one persistent
+ * work-queue launch per level and sweep.  d_valsA / d_sel as in
+ * selinv_factor / selinv_invert.  use_graph = 1: the launch sequence is
+ * captured into a HIP graph on the first call (and again whenever d_valsA,
+ * d_sel, the schedule or the workspace change) and replayed on stream s.
+ * Errors found on the device are reported by selinv_sync_status. */
+selinv_status selinv_run(selinv_plan p, const double* d_valsA, double* d_sel, int32_t use_graph, hipStream_t s);
+
+/* Autotuner: times selinv_run (no graph) on the given buffers for schedules
+ * along each axis in turn (order, bn_cap, split_fill 0/512/4096, grid_mult
+ * 1/2/4), keeps the fastest and leaves it set.  cache_path (may be NULL):
+ * a JSON file of earlier choices keyed by device and block structure; a hit
+ * skips the timing, a miss adds the choice.  On return d_sel holds the
+ * selected inverse of d_valsA; *chosen and *best_ms (may be NULL) the
+ * schedule and its time in ms.  Synchronises s. */
+selinv_status selinv_tune(selinv_plan p, const double* d_valsA, double* d_sel, const char* cache_path,
+                          selinv_sched* chosen, double* best_ms, hipStream_t s);
 
 /* Message for the last failing call on this thread. */
 const char* selinv_last_error(void);

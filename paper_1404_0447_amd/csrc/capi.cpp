@@ -3,8 +3,11 @@
 
 #include <algorithm>
 #include <climits>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <new>
+#include <sstream>
 #include <string>
 
 #include "kernels.hpp"
@@ -44,7 +47,7 @@ void compute_layout(selinv_plan_s* P)
     L.hp = take(sizeof(double) * P->harena);
     L.wp = take(sizeof(double) * P->warena);
     L.tp = take(sizeof(double) * P->warena);
-    L.status = take(sizeof(unsigned long long));
+    L.status = take(2 * sizeof(unsigned long long));
     L.blocks = take(sizeof(BlockDesc) * P->blocks.size());
     L.crow = take(sizeof(int32_t) * P->crow.size());
     L.cbase = take(sizeof(int64_t) * P->cbase.size());
@@ -69,6 +72,13 @@ void compute_layout(selinv_plan_s* P)
     L.t_rf1a = take(sizeof(Task) * P->t_rf1a.tasks.size());
     L.t_rf1b = take(sizeof(Task) * P->t_rf1b.tasks.size());
     L.t_rf2 = take(sizeof(Task) * P->t_rf2.tasks.size());
+    L.q_fac = take(sizeof(Task) * P->q_cap_fac);
+    L.q_inv = take(sizeof(Task) * P->q_cap_inv);
+    // completion counters (factor, inversion) per block, then the queue
+    // heads (factor, inversion) per level
+    const size_t nb = P->blocks.size(), nl = (size_t)std::max(P->exec.depth, 0);
+    L.q_done = take(sizeof(unsigned) * 2 * (nb + nl));
+    L.q_head = L.q_done + sizeof(unsigned) * 2 * nb;
     L.total = o;
     P->info.workspace_bytes = (int64_t)o;
 }
@@ -123,14 +133,49 @@ extern "C" {
 
 const char* selinv_last_error(void) { return g_err.c_str(); }
 
-selinv_status selinv_analyze(int64_t n, const int64_t* colptr, const int32_t* rowind, const selinv_geom* geom,
-                             const int32_t* perm_or_null, const selinv_opts* opts, selinv_plan* out)
+}  // extern "C"
+
+namespace {
+// Validate one matrix and run the host analysis into P (no schedule yet).
+selinv_status analyze_one(int64_t n, const int64_t* colptr, const int32_t* rowind, const selinv_geom* geom,
+                          const int32_t* perm_or_null, const selinv_opts& o, selinv_plan_s* P, std::string& err)
 {
-    if (!out) return fail(SELINV_EINVAL, "out is NULL");
-    *out = nullptr;
-    if (n < 0 || n > INT32_MAX - 1) return fail(SELINV_EINVAL, "n out of range");
-    if (n > 0 && (!colptr || !rowind)) return fail(SELINV_EINVAL, "colptr/rowind is NULL");
-    selinv_opts o{128, 1, 1, 0};
+    if (n < 0 || n > INT32_MAX - 1) return err = "n out of range", SELINV_EINVAL;
+    if (n > 0 && (!colptr || !rowind)) return err = "colptr/rowind is NULL", SELINV_EINVAL;
+    if (n > 0) {
+        if (colptr[0] != 0) return err = "colptr[0] must be 0", SELINV_EINVAL;
+        for (int64_t j = 0; j < n; j++) {
+            if (colptr[j + 1] < colptr[j]) return err = "colptr is not monotone", SELINV_EINVAL;
+            for (int64_t p = colptr[j]; p < colptr[j + 1]; p++) {
+                if (rowind[p] < j || rowind[p] >= n)
+                    return err = "row index outside the lower triangle at column " + std::to_string(j), SELINV_EINVAL;
+                if (p > colptr[j] && rowind[p] <= rowind[p - 1])
+                    return err = "rows not strictly increasing in column " + std::to_string(j), SELINV_EINVAL;
+            }
+        }
+    }
+    if (geom && geom->ndim > 0) {
+        if (geom->ndim > 3) return err = "geom.ndim must be 0..3", SELINV_EINVAL;
+        int64_t pts = 1;
+        for (int d = 0; d < geom->ndim; d++) {
+            if (geom->dims[d] <= 0) return err = "geom.dims must be positive", SELINV_EINVAL;
+            pts *= geom->dims[d];
+        }
+        int dofs = geom->dofs_per_point > 0 ? geom->dofs_per_point : 1;
+        if (pts * dofs != n) return err = "geometry does not match n", SELINV_EINVAL;
+    }
+    P->n = n;
+    P->opts = o;
+    P->nnzA = n > 0 ? colptr[n] : 0;
+    P->colptr.assign(colptr, colptr + (n > 0 ? n + 1 : 1));
+    if (n == 0) P->colptr.assign(1, 0);
+    if (P->nnzA > 0) P->rowind.assign(rowind, rowind + P->nnzA);
+    return analyze(P, geom, perm_or_null, err);
+}
+
+selinv_status resolve_opts(const selinv_opts* opts, selinv_opts& o)
+{
+    o = selinv_opts{128, 1, 1, 0};
     if (opts) o = *opts;
     if (o.max_super <= 0) o.max_super = 128;
     // execution blocks default to <= 128 columns (the width the register
@@ -139,50 +184,142 @@ selinv_status selinv_analyze(int64_t n, const int64_t* colptr, const int32_t* ro
     if (o.exec_cap <= 0) o.exec_cap = std::min(o.max_super, (int32_t)kLdsDiagMax);
     if (o.max_super > 256 || o.exec_cap > 256)
         return fail(SELINV_EUNSUPPORTED, "supernode width cap above 256 is not supported");
-    if (n > 0) {
-        if (colptr[0] != 0) return fail(SELINV_EINVAL, "colptr[0] must be 0");
-        for (int64_t j = 0; j < n; j++) {
-            if (colptr[j + 1] < colptr[j]) return fail(SELINV_EINVAL, "colptr is not monotone");
-            for (int64_t p = colptr[j]; p < colptr[j + 1]; p++) {
-                if (rowind[p] < j || rowind[p] >= n)
-                    return fail(SELINV_EINVAL, "row index outside the lower triangle at column " + std::to_string(j));
-                if (p > colptr[j] && rowind[p] <= rowind[p - 1])
-                    return fail(SELINV_EINVAL, "rows not strictly increasing in column " + std::to_string(j));
-            }
-        }
+    return SELINV_OK;
+}
+
+// queue-tile widths and split fills the schedule may take; the workspace
+// reserves queue entries for the largest of them
+constexpr int32_t kTuneOrders[] = {qoPlan, qoLpt, qoRoundRobin, qoTileLpt};
+constexpr int32_t kTuneBn[] = {32, 64, 128};
+constexpr int32_t kTuneFill[] = {0, 512, 4096};
+constexpr int32_t kTuneGrid[] = {1, 2, 4};
+constexpr int32_t kCapBn[] = {16, 32, 64, 128};
+
+// per-level task lists, persistent queues for the default schedule, and
+// the device layout
+void finish_plan(selinv_plan_s* P)
+{
+    if (P->b_noff.empty()) {  // a single matrix: a batch of one
+        P->blk_matrix.assign(P->blocks.size(), 0);
+        P->b_noff = {0, P->n};
+        P->b_aoff = {0, P->nnzA};
+        P->b_loff = {0, P->colptrL.back()};
     }
-    if (geom && geom->ndim > 0) {
-        if (geom->ndim > 3) return fail(SELINV_EINVAL, "geom.ndim must be 0..3");
-        int64_t pts = 1;
-        for (int d = 0; d < geom->ndim; d++) {
-            if (geom->dims[d] <= 0) return fail(SELINV_EINVAL, "geom.dims must be positive");
-            pts *= geom->dims[d];
+    build_schedule(P);
+    for (int32_t bn : kCapBn)
+        for (int32_t fill : kTuneFill) {
+            Sched sc = P->sched;
+            sc.bn_cap = bn;
+            sc.split_fill = fill;
+            int64_t nf = 0, ni = 0;
+            queue_sizes(P, sc, nf, ni);
+            P->q_cap_fac = std::max(P->q_cap_fac, nf);
+            P->q_cap_inv = std::max(P->q_cap_inv, ni);
         }
-        int dofs = geom->dofs_per_point > 0 ? geom->dofs_per_point : 1;
-        if (pts * dofs != n) return fail(SELINV_EINVAL, "geometry does not match n");
-    }
+    build_queues(P, P->sched, P->q_fac, P->q_fac_off, P->q_inv, P->q_inv_off);
+    compute_layout(P);
+}
+
+void drop_graph(selinv_plan_s* P)
+{
+    if (P->graph_exec) (void)hipGraphExecDestroy(P->graph_exec);
+    if (P->graph) (void)hipGraphDestroy(P->graph);
+    P->graph_exec = nullptr;
+    P->graph = nullptr;
+    P->graph_in = nullptr;
+    P->graph_out = nullptr;
+}
+}  // namespace
+
+selinv_plan_s::~selinv_plan_s()
+{
+    drop_graph(this);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+}
+
+extern "C" {
+
+selinv_status selinv_analyze(int64_t n, const int64_t* colptr, const int32_t* rowind, const selinv_geom* geom,
+                             const int32_t* perm_or_null, const selinv_opts* opts, selinv_plan* out)
+{
+    if (!out) return fail(SELINV_EINVAL, "out is NULL");
+    *out = nullptr;
+    selinv_opts o;
+    if (selinv_status st = resolve_opts(opts, o)) return st;
     selinv_plan_s* P = new (std::nothrow) selinv_plan_s();
     if (!P) return fail(SELINV_ENOMEM, "out of host memory");
     try {
-        P->n = n;
-        P->opts = o;
-        P->nnzA = n > 0 ? colptr[n] : 0;
-        P->colptr.assign(colptr, colptr + (n > 0 ? n + 1 : 1));
-        if (n == 0) P->colptr.assign(1, 0);
-        if (P->nnzA > 0) P->rowind.assign(rowind, rowind + P->nnzA);
         std::string err;
-        selinv_status st = analyze(P, geom, perm_or_null, err);
+        selinv_status st = analyze_one(n, colptr, rowind, geom, perm_or_null, o, P, err);
         if (st != SELINV_OK) {
             delete P;
             return fail(st, err);
         }
-        build_schedule(P);
-        compute_layout(P);
+        finish_plan(P);
     } catch (const std::bad_alloc&) {
         delete P;
         return fail(SELINV_ENOMEM, "out of host memory during analysis");
     }
     *out = P;
+    return SELINV_OK;
+}
+
+selinv_status selinv_analyze_batch(int32_t count, const int64_t* ns, const int64_t* const* colptrs,
+                                   const int32_t* const* rowinds, const selinv_geom* geoms, const selinv_opts* opts,
+                                   selinv_plan* out)
+{
+    if (!out) return fail(SELINV_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (count < 0) return fail(SELINV_EINVAL, "count must be >= 0");
+    if (count > 0 && (!ns || !colptrs || !rowinds)) return fail(SELINV_EINVAL, "ns/colptrs/rowinds is NULL");
+    selinv_opts o;
+    if (selinv_status st = resolve_opts(opts, o)) return st;
+    int64_t total = 0;
+    for (int32_t m = 0; m < count; m++) {
+        if (ns[m] < 0) return fail(SELINV_EINVAL, "matrix " + std::to_string(m) + ": n out of range");
+        total += ns[m];
+    }
+    if (total > INT32_MAX - 1) return fail(SELINV_EINVAL, "batch too large: total order exceeds 2^31 - 2");
+    std::vector<selinv_plan_s*> parts;
+    selinv_plan_s* U = nullptr;
+    auto cleanup = [&]() {
+        for (selinv_plan_s* p : parts) delete p;
+        parts.clear();
+    };
+    try {
+        for (int32_t m = 0; m < count; m++) {
+            selinv_plan_s* P = new selinv_plan_s();
+            parts.push_back(P);
+            std::string err;
+            selinv_status st = analyze_one(ns[m], colptrs[m], rowinds[m], geoms ? geoms + m : nullptr, nullptr, o,
+                                           P, err);
+            if (st != SELINV_OK) {
+                cleanup();
+                return fail(st, "matrix " + std::to_string(m) + ": " + err);
+            }
+        }
+        U = new selinv_plan_s();
+        U->opts = o;
+        merge_plans(parts, U);
+        cleanup();
+        finish_plan(U);
+    } catch (const std::bad_alloc&) {
+        cleanup();
+        delete U;
+        return fail(SELINV_ENOMEM, "out of host memory during batch analysis");
+    }
+    *out = U;
+    return SELINV_OK;
+}
+
+selinv_status selinv_batch_offsets(selinv_plan P, int32_t* count, int64_t* n_off, int64_t* nnzA_off,
+                                   int64_t* nnzL_off)
+{
+    if (!P) return fail(SELINV_EINVAL, "NULL plan");
+    if (count) *count = (int32_t)P->b_noff.size() - 1;
+    if (n_off) std::copy(P->b_noff.begin(), P->b_noff.end(), n_off);
+    if (nnzA_off) std::copy(P->b_aoff.begin(), P->b_aoff.end(), nnzA_off);
+    if (nnzL_off) std::copy(P->b_loff.begin(), P->b_loff.end(), nnzL_off);
     return SELINV_OK;
 }
 
@@ -198,13 +335,27 @@ selinv_status selinv_bind_workspace(selinv_plan P, void* d_ws, size_t bytes, hip
     if (!P || !d_ws) return fail(SELINV_EINVAL, "NULL argument");
     if (bytes < P->lay.total) return fail(SELINV_ENOMEM, "workspace too small");
     if (((uintptr_t)d_ws & 255) != 0) return fail(SELINV_EINVAL, "workspace must be 256-byte aligned");
+    drop_graph(P);
     P->ws = (char*)d_ws;
     P->ws_bytes = bytes;
     P->factored = false;
+    P->inverted = false;
+    P->queues_on_device = false;
     const DeviceLayout& L = P->lay;
     static hipError_t init = kernels_init();
     if (init != hipSuccess) return hip_fail(init, "kernel attributes");
     hipError_t e = hipSuccess;
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (!e) e = hipGetDevice(&dev);
+    if (!e) e = hipGetDeviceProperties(&prop, dev);
+    if (!e) e = persist_occupancy(&P->occ_fac, &P->occ_inv);
+    if (e) {
+        P->ws = nullptr;
+        return hip_fail(e, "device query");
+    }
+    P->n_cu = prop.multiProcessorCount;
+    P->dev_arch = prop.gcnArchName;
     if (!e) e = upload(P->ws, L.blocks, P->blocks, s);
     if (!e) e = upload(P->ws, L.crow, P->crow, s);
     if (!e) e = upload(P->ws, L.cbase, P->cbase, s);
@@ -226,11 +377,14 @@ selinv_status selinv_bind_workspace(selinv_plan P, void* d_ws, size_t bytes, hip
     if (!e) e = upload(P->ws, L.t_rf1a, P->t_rf1a.tasks, s);
     if (!e) e = upload(P->ws, L.t_rf1b, P->t_rf1b.tasks, s);
     if (!e) e = upload(P->ws, L.t_rf2, P->t_rf2.tasks, s);
+    if (!e) e = upload(P->ws, L.q_fac, P->q_fac, s);
+    if (!e) e = upload(P->ws, L.q_inv, P->q_inv, s);
     if (!e) e = hipStreamSynchronize(s);
     if (e) {
         P->ws = nullptr;
         return hip_fail(e, "bind_workspace upload");
     }
+    P->queues_on_device = true;
     return SELINV_OK;
 }
 
@@ -335,10 +489,13 @@ selinv_status selinv_sync_status(selinv_plan P, hipStream_t s, int64_t* bad_col)
     if (!P) return fail(SELINV_EINVAL, "NULL plan");
     if (bad_col) *bad_col = -1;
     if (!P->ws) return fail(SELINV_ESTATE, "no workspace bound");
-    unsigned long long v = ~0ull;
-    hipError_t e = hipMemcpyAsync(&v, P->ws + P->lay.status, sizeof v, hipMemcpyDeviceToHost, s);
+    unsigned long long w[2] = {~0ull, 0ull};
+    hipError_t e = hipMemcpyAsync(w, P->ws + P->lay.status, sizeof w, hipMemcpyDeviceToHost, s);
     if (!e) e = hipStreamSynchronize(s);
     if (e) return hip_fail(e, "sync_status");
+    if (w[1] != 0)
+        return fail(SELINV_EQUEUE, "a work-queue dependency wait exceeded its poll limit; results are invalid");
+    const unsigned long long v = w[0];
     if (v != ~0ull) {
         int64_t col = (int64_t)v;
         int64_t orig = (col >= 0 && col < P->n) ? P->perm[col] : -1;
@@ -487,6 +644,316 @@ selinv_status selinv_get_exec_rows(selinv_plan P, int32_t* rows)
 {
     if (!P) return fail(SELINV_EINVAL, "NULL plan");
     if (rows) std::copy(P->crow.begin(), P->crow.end(), rows);
+    return SELINV_OK;
+}
+
+}  // extern "C"
+
+namespace {
+// One factor + inversion on the persistent kernels: assemble, one launch per
+// level of the factor (leaves first) and of the inversion (root first),
+// export.  Kernels only (fill kernels clear memory), so the sequence can be
+// captured into a graph.
+selinv_status run_persistent(selinv_plan_s* P, const double* d_valsA, double* d_sel, hipStream_t s, Prof* prof)
+{
+    DevPtrs D = dev_ptrs(P);
+    const int64_t nb = (int64_t)P->blocks.size();
+    const int depth = P->exec.depth;
+    unsigned* done_f = (unsigned*)(P->ws + P->lay.q_done);
+    unsigned* done_i = done_f + nb;
+    unsigned* head_f = (unsigned*)(P->ws + P->lay.q_head);
+    unsigned* head_i = head_f + depth;
+    const Task* qf = (const Task*)(P->ws + P->lay.q_fac);
+    const Task* qi = (const Task*)(P->ws + P->lay.q_inv);
+    const int gf = std::max(1, P->n_cu * std::min(P->sched.grid_mult, P->occ_fac));
+    const int gi = std::max(1, P->n_cu * std::min(P->sched.grid_mult, P->occ_inv));
+    hipError_t e = launch_status_reset(D.status, s);
+    if (!e) e = launch_fill(prof, kAssemble, D.Lp, P->arena, 0.0, s);
+    if (!e) e = launch_scatter_set(prof, kAssemble, d_valsA, D.asm_off, P->nnzA, D.Lp, s);
+    if (!e) e = launch_fill_u32(prof, kAssemble, done_f, 2 * (nb + depth), s);
+    for (int l = depth - 1; l >= 0 && !e; l--) {
+        const int64_t a = P->q_fac_off[l], z = P->q_fac_off[l + 1];
+        e = launch_persist_factor(prof, D, qf + a, z - a, head_f + l, done_f, gf, P->opts.require_spd,
+                                  P->spin_limit, s);
+    }
+    for (int l = 0; l < depth && !e; l++) {
+        const int64_t a = P->q_inv_off[l], z = P->q_inv_off[l + 1];
+        e = launch_persist_invert(prof, D, qi + a, z - a, head_i + l, done_i, gi, P->spin_limit, s);
+    }
+    if (!e) e = launch_gather(prof, kExport, D.Ap, D.exp_off, P->colptrL.back(), d_sel, s);
+    if (e) return hip_fail(e, "persistent launch");
+    return SELINV_OK;
+}
+
+selinv_status check_sched(const selinv_sched* sc)
+{
+    if (!sc) return fail(SELINV_EINVAL, "NULL schedule");
+    if (sc->order < 0 || sc->order >= qoNumOrders) return fail(SELINV_EINVAL, "schedule order out of range");
+    if (sc->bn_cap != 16 && sc->bn_cap != 32 && sc->bn_cap != 64 && sc->bn_cap != 128)
+        return fail(SELINV_EINVAL, "bn_cap must be 16, 32, 64 or 128");
+    // queue lengths grow with split_fill, so the capacity reserved for 4096
+    // covers every accepted value
+    if (sc->split_fill < 0 || sc->split_fill > 4096) return fail(SELINV_EINVAL, "split_fill must be 0..4096");
+    if (sc->grid_mult < 1 || sc->grid_mult > 16) return fail(SELINV_EINVAL, "grid_mult must be 1..16");
+    return SELINV_OK;
+}
+
+// 64-bit FNV-1a over the block structure: the autotuner cache key
+struct Fnv {
+    uint64_t h = 1469598103934665603ull;
+    void add(uint64_t v)
+    {
+        for (int b = 0; b < 8; b++) {
+            h ^= (v >> (8 * b)) & 0xff;
+            h *= 1099511628211ull;
+        }
+    }
+};
+
+std::string tune_key(const selinv_plan_s* P)
+{
+    Fnv f;
+    f.add((uint64_t)P->n);
+    f.add((uint64_t)P->colptrL.back());
+    f.add((uint64_t)P->blocks.size());
+    f.add((uint64_t)P->exec.depth);
+    f.add((uint64_t)P->opts.require_spd);
+    for (const BlockDesc& d : P->blocks) {
+        f.add((uint64_t)d.s);
+        f.add((uint64_t)d.c);
+        f.add((uint64_t)d.level);
+    }
+    char buf[64];
+    std::snprintf(buf, sizeof buf, "%016llx", (unsigned long long)f.h);
+    return "selinv/" + P->dev_arch + "/" + std::to_string(P->n_cu) + "cu/" + buf;
+}
+
+// Cache file: a JSON object with one entry per line,
+//   "key": {"order": 1, "bn_cap": 128, "split_fill": 512, "grid_mult": 2, "ms": 1.5},
+bool cache_lookup(const char* path, const std::string& key, selinv_sched& sc, double& ms)
+{
+    std::ifstream in(path);
+    if (!in) return false;
+    std::string line;
+    const std::string tag = "\"" + key + "\":";
+    while (std::getline(in, line)) {
+        const size_t at = line.find(tag);
+        if (at == std::string::npos) continue;
+        auto num = [&](const char* name, double& v) {
+            const std::string f = std::string("\"") + name + "\":";
+            const size_t q = line.find(f, at + tag.size());
+            if (q == std::string::npos) return false;
+            v = std::strtod(line.c_str() + q + f.size(), nullptr);
+            return true;
+        };
+        double o, b, fl, g;
+        if (!num("order", o) || !num("bn_cap", b) || !num("split_fill", fl) || !num("grid_mult", g)) return false;
+        if (!num("ms", ms)) ms = 0.0;
+        sc = selinv_sched{(int32_t)o, (int32_t)b, (int32_t)fl, (int32_t)g};
+        return check_sched(&sc) == SELINV_OK;
+    }
+    return false;
+}
+
+bool cache_store(const char* path, const std::string& key, const selinv_sched& sc, double ms)
+{
+    std::vector<std::string> keep;
+    {
+        std::ifstream in(path);
+        std::string line;
+        const std::string tag = "\"" + key + "\":";
+        while (in && std::getline(in, line)) {
+            if (line.find("\": {") == std::string::npos || line.find(tag) != std::string::npos) continue;
+            while (!line.empty() && (line.back() == ',' || line.back() == ' ')) line.pop_back();
+            keep.push_back(line);
+        }
+    }
+    char buf[256];
+    std::snprintf(buf, sizeof buf,
+                  "  \"%s\": {\"order\": %d, \"bn_cap\": %d, \"split_fill\": %d, \"grid_mult\": %d, \"ms\": %.6f}",
+                  key.c_str(), sc.order, sc.bn_cap, sc.split_fill, sc.grid_mult, ms);
+    keep.push_back(buf);
+    std::ofstream out(path, std::ios::trunc);
+    if (!out) return false;
+    out << "{\n";
+    for (size_t i = 0; i < keep.size(); i++) out << keep[i] << (i + 1 < keep.size() ? ",\n" : "\n");
+    out << "}\n";
+    return (bool)out;
+}
+}  // namespace
+
+extern "C" {
+
+selinv_status selinv_set_schedule(selinv_plan P, const selinv_sched* sc, hipStream_t s)
+{
+    if (!P) return fail(SELINV_EINVAL, "NULL plan");
+    if (selinv_status st = check_sched(sc)) return st;
+    Sched next{sc->order, sc->bn_cap, sc->split_fill, sc->grid_mult};
+    std::vector<Task> qf, qi;
+    std::vector<int64_t> of, oi;
+    try {
+        build_queues(P, next, qf, of, qi, oi);
+    } catch (const std::bad_alloc&) {
+        return fail(SELINV_ENOMEM, "out of host memory building the queues");
+    }
+    if ((int64_t)qf.size() > P->q_cap_fac || (int64_t)qi.size() > P->q_cap_inv)
+        return fail(SELINV_EINVAL, "schedule needs more queue entries than the workspace reserves");
+    if (P->ws) {
+        hipError_t e = upload(P->ws, P->lay.q_fac, qf, s);
+        if (!e) e = upload(P->ws, P->lay.q_inv, qi, s);
+        if (!e) e = hipStreamSynchronize(s);
+        if (e) {
+            P->queues_on_device = false;
+            return hip_fail(e, "queue upload");
+        }
+    }
+    drop_graph(P);
+    P->sched = next;
+    P->q_fac.swap(qf);
+    P->q_inv.swap(qi);
+    P->q_fac_off.swap(of);
+    P->q_inv_off.swap(oi);
+    return SELINV_OK;
+}
+
+selinv_status selinv_get_schedule(selinv_plan P, selinv_sched* sc)
+{
+    if (!P || !sc) return fail(SELINV_EINVAL, "NULL argument");
+    *sc = selinv_sched{P->sched.order, P->sched.bn_cap, P->sched.split_fill, P->sched.grid_mult};
+    return SELINV_OK;
+}
+
+selinv_status selinv_get_queue(selinv_plan P, int32_t sweep, int32_t level, int32_t* tasks, int64_t* count)
+{
+    if (!P) return fail(SELINV_EINVAL, "NULL plan");
+    if (sweep != 0 && sweep != 1) return fail(SELINV_EINVAL, "sweep must be 0 (factor) or 1 (inversion)");
+    if (level < 1 || level > P->exec.depth) return fail(SELINV_EINVAL, "level out of range");
+    const std::vector<Task>& q = sweep == 0 ? P->q_fac : P->q_inv;
+    const std::vector<int64_t>& off = sweep == 0 ? P->q_fac_off : P->q_inv_off;
+    const int64_t a = off[level - 1], z = off[level];
+    if (count) *count = z - a;
+    if (tasks) std::memcpy(tasks, q.data() + a, sizeof(Task) * (size_t)(z - a));
+    return SELINV_OK;
+}
+
+selinv_status selinv_set_spin_limit(selinv_plan P, uint32_t polls)
+{
+    if (!P) return fail(SELINV_EINVAL, "NULL plan");
+    P->spin_limit = polls;
+    drop_graph(P);
+    return SELINV_OK;
+}
+
+selinv_status selinv_run(selinv_plan P, const double* d_valsA, double* d_sel, int32_t use_graph, hipStream_t s)
+{
+    if (!P) return fail(SELINV_EINVAL, "NULL plan");
+    if (!P->ws || !P->queues_on_device) return fail(SELINV_ESTATE, "no workspace bound");
+    if ((P->nnzA > 0 && !d_valsA) || (P->colptrL.back() > 0 && !d_sel)) return fail(SELINV_EINVAL, "NULL buffer");
+    if (!use_graph) {
+        if (selinv_status st = run_persistent(P, d_valsA, d_sel, s, &P->prof)) return st;
+    } else {
+        if (!P->graph_exec || P->graph_in != (const void*)d_valsA || P->graph_out != (void*)d_sel) {
+            drop_graph(P);
+            hipError_t e = hipSuccess;
+            if (!P->cap_stream) e = hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking);
+            if (e) return hip_fail(e, "capture stream");
+            e = hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal);
+            if (e) return hip_fail(e, "begin capture");
+            selinv_status st = run_persistent(P, d_valsA, d_sel, P->cap_stream, nullptr);
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(P->cap_stream, &g);
+            if (st != SELINV_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return st;
+            }
+            if (e) return hip_fail(e, "end capture");
+            P->graph = g;
+            e = hipGraphInstantiate(&P->graph_exec, g, nullptr, nullptr, 0);
+            if (e) {
+                drop_graph(P);
+                return hip_fail(e, "graph instantiate");
+            }
+            P->graph_in = d_valsA;
+            P->graph_out = d_sel;
+        }
+        hipError_t e = hipGraphLaunch(P->graph_exec, s);
+        if (e) return hip_fail(e, "graph launch");
+    }
+    P->factored = true;
+    P->inverted = true;
+    return SELINV_OK;
+}
+
+selinv_status selinv_tune(selinv_plan P, const double* d_valsA, double* d_sel, const char* cache_path,
+                          selinv_sched* chosen, double* best_ms, hipStream_t s)
+{
+    if (!P) return fail(SELINV_EINVAL, "NULL plan");
+    if (!P->ws) return fail(SELINV_ESTATE, "no workspace bound");
+    const std::string key = tune_key(P);
+    selinv_sched best{};
+    double ms = 0.0;
+    if (cache_path && cache_lookup(cache_path, key, best, ms)) {
+        if (selinv_status st = selinv_set_schedule(P, &best, s)) return st;
+        if (chosen) *chosen = best;
+        if (best_ms) *best_ms = ms;
+        return SELINV_OK;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t he = hipEventCreate(&e0);
+    if (!he) he = hipEventCreate(&e1);
+    if (he) return hip_fail(he, "tune events");
+    auto destroy = [&]() {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    };
+    const bool prof_was = P->prof.on;
+    P->prof.on = false;
+    // time one schedule: a warm-up run, then the best of three
+    auto evaluate = [&](const selinv_sched& sc, double& t) -> selinv_status {
+        if (selinv_status st = selinv_set_schedule(P, &sc, s)) return st;
+        if (selinv_status st = run_persistent(P, d_valsA, d_sel, s, nullptr)) return st;
+        t = 1e30;
+        for (int r = 0; r < 3; r++) {
+            hipError_t e = hipEventRecord(e0, s);
+            if (!e && run_persistent(P, d_valsA, d_sel, s, nullptr) != SELINV_OK) return SELINV_EHIP;
+            if (!e) e = hipEventRecord(e1, s);
+            if (!e) e = hipEventSynchronize(e1);
+            float dt = 0.f;
+            if (!e) e = hipEventElapsedTime(&dt, e0, e1);
+            if (e) return hip_fail(e, "tune timing");
+            t = std::min(t, (double)dt);
+        }
+        int64_t bad = -1;
+        return selinv_sync_status(P, s, &bad);
+    };
+    // coordinate descent over queue order, tile cap, split fill, grid size
+    best = selinv_sched{P->sched.order, P->sched.bn_cap, P->sched.split_fill, P->sched.grid_mult};
+    double tbest = 0.0;
+    selinv_status st = evaluate(best, tbest);
+    for (int dim = 0; dim < 4 && st == SELINV_OK; dim++) {
+        const int32_t* vals = dim == 0 ? kTuneOrders : dim == 1 ? kTuneBn : dim == 2 ? kTuneFill : kTuneGrid;
+        const int nv = dim == 0 ? 4 : 3;
+        for (int v = 0; v < nv && st == SELINV_OK; v++) {
+            selinv_sched c = best;
+            int32_t* field = dim == 0 ? &c.order : dim == 1 ? &c.bn_cap : dim == 2 ? &c.split_fill : &c.grid_mult;
+            if (*field == vals[v]) continue;
+            *field = vals[v];
+            double t = 0.0;
+            st = evaluate(c, t);
+            if (st == SELINV_OK && t < tbest) {
+                tbest = t;
+                best = c;
+            }
+        }
+    }
+    destroy();
+    P->prof.on = prof_was;
+    if (st != SELINV_OK) return st;
+    if ((st = selinv_set_schedule(P, &best, s))) return st;
+    if (cache_path && !cache_store(cache_path, key, best, tbest))
+        return fail(SELINV_EINVAL, std::string("cannot write the tuning cache ") + cache_path);
+    if (chosen) *chosen = best;
+    if (best_ms) *best_ms = tbest;
     return SELINV_OK;
 }
 

@@ -20,6 +20,7 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "kernels.hpp"
@@ -51,9 +52,14 @@ __global__ void k_fill(double* __restrict__ p, int64_t n, double v)
         p[i] = v;
 }
 
+// status[0]: smallest failing pivot column (~0 = none); status[1]: error
+// flags of the persistent work queues (0 = none)
 __global__ void k_status_reset(unsigned long long* status)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *status = ~0ull;
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        status[0] = ~0ull;
+        status[1] = 0ull;
+    }
 }
 
 __global__ void k_scatter_set(const double* __restrict__ src, const int64_t* __restrict__ off, int64_t n,
@@ -71,18 +77,25 @@ __global__ void k_gather(const double* __restrict__ src, const int64_t* __restri
 }
 
 // Blocks whose contractions are split over several work-groups accumulate:
-// X = Ainv(C,B) := 0 and the lower triangle of Ainv(B,B) := T.
-__global__ void k_zero_x(const Task* __restrict__ tasks, const BlockDesc* __restrict__ blk, double* __restrict__ Ap,
-                         const double* __restrict__ Tp)
+// X = Ainv(C,B) := 0 and the lower triangle of Ainv(B,B) := T.  One wave per
+// column, lanes along its rows.
+__device__ void zero_task(const BlockDesc d, double* __restrict__ Ap, const double* __restrict__ Tp)
 {
-    const BlockDesc d = blk[tasks[blockIdx.x].b];
     const int64_t ld = (int64_t)d.s + d.c;
-    for (int64_t e = threadIdx.x; e < (int64_t)d.c * d.s; e += blockDim.x)
-        Ap[d.poff + d.s + e % d.c + (e / d.c) * ld] = 0.0;
-    for (int64_t e = threadIdx.x; e < (int64_t)d.s * d.s; e += blockDim.x) {
-        const int i = (int)(e % d.s), j = (int)(e / d.s);
-        if (i >= j) Ap[d.poff + i + j * ld] = Tp[d.woff + e];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int j = wave; j < d.s; j += kThreads / 64) {
+        double* col = Ap + d.poff + (int64_t)j * ld;
+        const double* tcol = Tp + d.woff + (int64_t)j * d.s;
+        for (int i = j + lane; i < d.s; i += 64) col[i] = tcol[i];
+        for (int i = lane; i < d.c; i += 64) col[d.s + i] = 0.0;
     }
+}
+
+__global__ __launch_bounds__(kThreads) void k_zero_x(const Task* __restrict__ tasks,
+                                                     const BlockDesc* __restrict__ blk, double* __restrict__ Ap,
+                                                     const double* __restrict__ Tp)
+{
+    zero_task(blk[tasks[blockIdx.x].b], Ap, Tp);
 }
 
 // L on the canonical pattern: diagonal-block entries are stored; an entry in
@@ -332,16 +345,10 @@ __global__ __launch_bounds__(kThreads) void k_panel(const Task* __restrict__ tas
 // ancestor panels through the block index maps.  FP64 atomics: sibling
 // blocks of one level may update the same ancestor entry.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_schur(const Task* __restrict__ tasks,
-                                                    const BlockDesc* __restrict__ blk, double* __restrict__ Lp,
-                                                    const double* __restrict__ Hp,
-                                                    const int64_t* __restrict__ cbase,
-                                                    const int64_t* __restrict__ rbase,
-                                                    const int32_t* __restrict__ rel)
+__device__ void schur_task(TileLds& L, const Task t, const BlockDesc d, double* __restrict__ Lp,
+                           const double* __restrict__ Hp, const int64_t* __restrict__ cbase,
+                           const int64_t* __restrict__ rbase, const int32_t* __restrict__ rel)
 {
-    __shared__ TileLds L;
-    const Task t = tasks[blockIdx.x];
-    const BlockDesc d = blk[t.b];
     const int s = d.s, c = d.c;
     const int64_t ld = (int64_t)s + c;
     const int i0 = t.i0, k0c = t.j0;
@@ -366,6 +373,18 @@ __global__ __launch_bounds__(kThreads) void k_schur(const Task* __restrict__ tas
     });
 }
 
+__global__ __launch_bounds__(kThreads) void k_schur(const Task* __restrict__ tasks,
+                                                    const BlockDesc* __restrict__ blk, double* __restrict__ Lp,
+                                                    const double* __restrict__ Hp,
+                                                    const int64_t* __restrict__ cbase,
+                                                    const int64_t* __restrict__ rbase,
+                                                    const int32_t* __restrict__ rel)
+{
+    __shared__ TileLds L;
+    const Task t = tasks[blockIdx.x];
+    schur_task(L, t, blk[t.b], Lp, Hp, cbase, rbase, rel);
+}
+
 // ---------------------------------------------------------------------------
 // Selected inversion, step 4 + symmetrisation, one pair of 32 x 32 tiles
 // (I, J), I >= J, of the diagonal block per work-group:
@@ -374,14 +393,19 @@ __global__ __launch_bounds__(kThreads) void k_schur(const Task* __restrict__ tas
 // ---------------------------------------------------------------------------
 constexpr int SDT = 32;
 
-__global__ __launch_bounds__(kThreads) void k_sdiag(const Task* __restrict__ tasks, const BlockDesc* __restrict__ blk,
-                                                    double* __restrict__ Ap, const double* __restrict__ Hp,
-                                                    const double* __restrict__ Tp)
+struct SdiagLds {
+    double LI[16][SDT + 1], LJ[16][SDT + 1], XI[16][SDT + 1], XJ[16][SDT + 1];
+    double Sx[SDT][SDT + 1];
+};
+
+__device__ void sdiag_task(SdiagLds& S, const Task t, const BlockDesc d, double* __restrict__ Ap,
+                           const double* __restrict__ Hp, const double* __restrict__ Tp)
 {
-    __shared__ double LI[16][SDT + 1], LJ[16][SDT + 1], XI[16][SDT + 1], XJ[16][SDT + 1];
-    __shared__ double Sx[SDT][SDT + 1];
-    const Task t = tasks[blockIdx.x];
-    const BlockDesc d = blk[t.b];
+    auto& LI = S.LI;
+    auto& LJ = S.LJ;
+    auto& XI = S.XI;
+    auto& XJ = S.XJ;
+    auto& Sx = S.Sx;
     const int s = d.s, c = d.c;
     const int64_t ld = (int64_t)s + c;
     const int I0 = t.i0, J0 = t.j0;
@@ -448,6 +472,15 @@ __global__ __launch_bounds__(kThreads) void k_sdiag(const Task* __restrict__ tas
             }
         }
     }
+}
+
+__global__ __launch_bounds__(kThreads) void k_sdiag(const Task* __restrict__ tasks, const BlockDesc* __restrict__ blk,
+                                                    double* __restrict__ Ap, const double* __restrict__ Hp,
+                                                    const double* __restrict__ Tp)
+{
+    __shared__ SdiagLds S;
+    const Task t = tasks[blockIdx.x];
+    sdiag_task(S, t, blk[t.b], Ap, Hp, Tp);
 }
 
 // ---------------------------------------------------------------------------
@@ -679,6 +712,165 @@ __global__ __launch_bounds__(kThreads) void k_ldlt_diag(const Task* __restrict__
             }
         }
     }
+}
+
+// ===========================================================================
+// Persistent level kernels (batched form).  One launch per tree level runs
+// every task of the level, across all blocks of all matrices of a batch,
+// from a work queue: a work-group claims the next index with an atomic add
+// on the level's queue head until the queue is empty.  Tasks of one block
+// depend on the block's earlier phases (factor: diagonal block -> L_hat
+// tiles -> Schur tiles; inversion: zero X -> X tiles -> diagonal tiles); a
+// task waits until its block's completion counter reaches task.pad.  Waits
+// are on smaller queue indices only, which running work-groups hold, so
+// every wait ends; a wait that exceeds spin_limit polls latches status[1]
+// and the task proceeds, so the kernel always drains.
+// ===========================================================================
+union PersistLds {
+    TileLds tile;
+    SdiagLds sd;
+    double colbuf[2][kLdsDiagMax];
+};
+
+struct QueueArgs {
+    const Task* q;
+    int64_t ntasks;
+    unsigned* head;   // this level's queue head
+    unsigned* done;   // per-block completion counters of this sweep
+    unsigned long long* status;
+    int require_spd;
+    unsigned spin_limit;
+};
+
+// The claimed index is the same in every thread; readfirstlane makes it a
+// wave-uniform (scalar) value, so the compiler sees a uniform loop whose
+// barriers every thread reaches together.
+__device__ __forceinline__ int claim(const QueueArgs& a, int* s_idx)
+{
+    if (threadIdx.x == 0) *s_idx = (int)__hip_atomic_fetch_add(a.head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int idx = __builtin_amdgcn_readfirstlane(*s_idx);
+    __syncthreads();
+    return idx;
+}
+
+__device__ __forceinline__ Task uniform_task(const Task* q, int idx)
+{
+    const Task r = q[idx];
+    Task t;
+    t.b = __builtin_amdgcn_readfirstlane(r.b);
+    t.i0 = __builtin_amdgcn_readfirstlane(r.i0);
+    t.j0 = __builtin_amdgcn_readfirstlane(r.j0);
+    t.bn = __builtin_amdgcn_readfirstlane(r.bn);
+    t.kb = __builtin_amdgcn_readfirstlane(r.kb);
+    t.ke = __builtin_amdgcn_readfirstlane(r.ke);
+    t.flags = __builtin_amdgcn_readfirstlane(r.flags);
+    t.pad = __builtin_amdgcn_readfirstlane(r.pad);
+    return t;
+}
+
+// Thread 0 polls the block's counter (relaxed loads; one acquire fence for
+// the whole work-group once the count is reached).  A wait gives up after
+// spin_limit polls, or at once when another wait has already given up, so
+// a run ends within about one poll limit whatever happens.
+__device__ __forceinline__ void wait_deps(const QueueArgs& a, const Task& t)
+{
+    if (t.pad > 0 && threadIdx.x == 0) {
+        unsigned spins = 0;
+        while (__hip_atomic_load(a.done + t.b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (unsigned)t.pad) {
+            const bool gave_up =
+                (spins & 255u) == 0 && __hip_atomic_load(a.status + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+            if (gave_up || ++spins > a.spin_limit) {
+                atomicOr(a.status + 1, 1ull);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+__device__ __forceinline__ void signal_done(const QueueArgs& a, const Task& t)
+{
+    __threadfence();  // every thread's results reach device scope first
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(a.done + t.b, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ __launch_bounds__(kThreads) void k_persist_factor(const QueueArgs a, const BlockDesc* __restrict__ blk,
+                                                             double* __restrict__ Lp, double* __restrict__ Wp,
+                                                             double* __restrict__ Hp, double* __restrict__ Tp,
+                                                             const int64_t* __restrict__ cbase,
+                                                             const int64_t* __restrict__ rbase,
+                                                             const int32_t* __restrict__ rel)
+{
+    __shared__ PersistLds sm;
+    __shared__ int s_idx;
+    // a work-group cannot claim more than ntasks entries: the bound only
+    // makes termination evident
+    for (int64_t it = 0; it < a.ntasks; ++it) {
+        const int idx = claim(a, &s_idx);
+        if (idx >= a.ntasks) break;
+        const Task t = uniform_task(a.q, idx);
+        const BlockDesc d = blk[t.b];
+        wait_deps(a, t);
+        switch (t.flags >> 8) {
+            case qLdlt:
+                if (d.s > kLdsDiagMax) ldlt_global(d, Lp, Wp, Tp, a.status, a.require_spd);
+                else ldlt_sweep(d, Lp, Tp, a.status, a.require_spd, sm.colbuf);
+                break;
+            case qPanel:
+#define SELINV_CALL(BN) panel_task<BN>(sm.tile, t, d, Lp, Hp, Tp)
+                SELINV_BN_DISPATCH(t.bn, SELINV_CALL)
+#undef SELINV_CALL
+                break;
+            default:
+                schur_task(sm.tile, t, d, Lp, Hp, cbase, rbase, rel);
+                break;
+        }
+        signal_done(a, t);
+    }
+}
+
+__global__ __launch_bounds__(kThreads, 2) void k_persist_invert(const QueueArgs a, const BlockDesc* __restrict__ blk,
+                                                             double* __restrict__ Ap, const double* __restrict__ Hp,
+                                                             const double* __restrict__ Tp,
+                                                             const int64_t* __restrict__ cbase,
+                                                             const int64_t* __restrict__ rbase,
+                                                             const int32_t* __restrict__ rel)
+{
+    __shared__ PersistLds sm;
+    __shared__ int s_idx;
+    // a work-group cannot claim more than ntasks entries: the bound only
+    // makes termination evident
+    for (int64_t it = 0; it < a.ntasks; ++it) {
+        const int idx = claim(a, &s_idx);
+        if (idx >= a.ntasks) break;
+        const Task t = uniform_task(a.q, idx);
+        const BlockDesc d = blk[t.b];
+        wait_deps(a, t);
+        switch (t.flags >> 8) {
+            case qZero:
+                zero_task(d, Ap, Tp);
+                break;
+            case qGemm:
+#define SELINV_CALL(BN) gemm_task<BN>(sm.tile, t, d, Ap, Hp, cbase, rbase, rel)
+                SELINV_BN_DISPATCH(t.bn, SELINV_CALL)
+#undef SELINV_CALL
+                break;
+            default:
+                sdiag_task(sm.sd, t, d, Ap, Hp, Tp);
+                break;
+        }
+        signal_done(a, t);
+    }
+}
+
+__global__ void k_fill_u32(unsigned* __restrict__ p, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
 }
 
 // ===========================================================================
@@ -1212,6 +1404,42 @@ hipError_t launch_invert_level(Prof* P, const DevPtrs& D, int64_t gemm0, int64_t
     if (nsdiag > 0)
         launch(P, kSdiag, k_sdiag, dim3((unsigned)nsdiag), 0, s, D.t_sdiag + sdiag0, D.blocks, D.Ap,
                (const double*)D.Hp, (const double*)D.Tp);
+    return hipGetLastError();
+}
+
+
+hipError_t persist_occupancy(int* occ_factor, int* occ_invert)
+{
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(occ_factor, k_persist_factor, kThreads, 0);
+    if (!e) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(occ_invert, k_persist_invert, kThreads, 0);
+    return e;
+}
+
+hipError_t launch_fill_u32(Prof* P, int kind, unsigned* p, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    launch(P, kind, k_fill_u32, dim3(grid_for(n)), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_persist_factor(Prof* P, const DevPtrs& D, const Task* q, int64_t ntasks, unsigned* head,
+                                 unsigned* done, int grid, int require_spd, unsigned spin_limit, hipStream_t s)
+{
+    if (ntasks <= 0) return hipSuccess;
+    const QueueArgs a{q, ntasks, head, done, D.status, require_spd, spin_limit};
+    const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(grid, ntasks));
+    launch(P, kQFactor, k_persist_factor, dim3(g), 0, s, a, D.blocks, D.Lp, D.Wp, D.Hp, D.Tp, D.cbase, D.rbase, D.rel);
+    return hipGetLastError();
+}
+
+hipError_t launch_persist_invert(Prof* P, const DevPtrs& D, const Task* q, int64_t ntasks, unsigned* head,
+                                 unsigned* done, int grid, unsigned spin_limit, hipStream_t s)
+{
+    if (ntasks <= 0) return hipSuccess;
+    const QueueArgs a{q, ntasks, head, done, D.status, 0, spin_limit};
+    const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(grid, ntasks));
+    launch(P, kQInvert, k_persist_invert, dim3(g), 0, s, a, D.blocks, D.Ap, (const double*)D.Hp, (const double*)D.Tp,
+           D.cbase, D.rbase, D.rel);
     return hipGetLastError();
 }
 

@@ -45,5 +45,13 @@ hipError_t launch_factor_level(Prof* P, const DevPtrs& D, int64_t diag0, int64_t
                                int64_t npanel, int64_t schur0, int64_t nschur, int require_spd, hipStream_t s);
 hipError_t launch_invert_level(Prof* P, const DevPtrs& D, int64_t gemm0, int64_t ngemm, int64_t sdiag0,
                                int64_t nsdiag, hipStream_t s);
+// persistent work-queue kernels: resident work-groups per CU, and one
+// level's launch over ntasks queue entries at q
+hipError_t persist_occupancy(int* occ_factor, int* occ_invert);
+hipError_t launch_fill_u32(Prof* P, int kind, unsigned* p, int64_t n, hipStream_t s);
+hipError_t launch_persist_factor(Prof* P, const DevPtrs& D, const Task* q, int64_t ntasks, unsigned* head,
+                                 unsigned* done, int grid, int require_spd, unsigned spin_limit, hipStream_t s);
+hipError_t launch_persist_invert(Prof* P, const DevPtrs& D, const Task* q, int64_t ntasks, unsigned* head,
+                                 unsigned* done, int grid, unsigned spin_limit, hipStream_t s);
 
 }  // namespace selinv

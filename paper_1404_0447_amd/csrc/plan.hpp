@@ -51,8 +51,26 @@ struct LevelTasks {
     std::vector<int64_t> off;  // per level (index = level-1): tasks[off[l] .. off[l+1])
 };
 
+// Work-queue tasks of the persistent level kernels reuse Task: the operation
+// sits in bits 8..15 of flags and `pad` holds the number of earlier tasks of
+// the same block that must have finished first (its dependencies: the
+// phases of one block run in the order below).
+enum QOp { qLdlt = 0, qPanel, qSchur, qZero, qGemm, qSdiag };
+inline int32_t q_flags(int op, int f) { return (op << 8) | f; }
+
+// Schedule of the persistent path (chosen by the autotuner).
+struct Sched {
+    int32_t order = 1;        // queue order within a phase, see QOrder
+    int32_t bn_cap = 128;     // widest output tile of the gather-GEMM / panel
+    int32_t split_fill = 512; // split contractions when a level has fewer tiles (0: never)
+    int32_t grid_mult = 2;    // resident work-groups per CU
+};
+enum QOrder { qoPlan = 0, qoLpt = 1, qoRoundRobin = 2, qoTileLpt = 3, qoNumOrders };
+
 // Kernel kinds (same numbering as SELINV_K_* in selinv.h).
-enum Kind { kAssemble = 0, kLdlt, kPanel, kSchur, kGemm, kSdiag, kExport, kRevSel, kRevFac, kNumKinds };
+enum Kind {
+    kAssemble = 0, kLdlt, kPanel, kSchur, kGemm, kSdiag, kExport, kRevSel, kRevFac, kQFactor, kQInvert, kNumKinds
+};
 
 // Optional per-launch timing: start/stop events are stamped by the dispatch
 // itself (hipExtLaunchKernelGGL), so no marker packets are added.
@@ -70,7 +88,9 @@ struct DeviceLayout {
     size_t lp, ap, hp, wp, tp, status, blocks, crow, cbase, rbase, rel, asm_off, exp_off, colblk, colptrL;
     size_t t_diag, t_panel, t_schur, t_gemm, t_sdiag, t_zero;
     size_t zb, hb, tb;  // adjoint arenas (backward)
-    size_t t_rs1, t_rs2, t_rs3, t_rf1a, t_rf1b, t_rf2, total;
+    size_t t_rs1, t_rs2, t_rs3, t_rf1a, t_rf1b, t_rf2;
+    size_t q_fac, q_inv, q_done, q_head;  // persistent path: queues, counters
+    size_t total;
 };
 
 }  // namespace selinv
@@ -101,6 +121,26 @@ struct selinv_plan_s {
     std::vector<selinv::Task> t_zero;  // blocks whose X accumulates over split contractions
     selinv::DeviceLayout lay{};
     selinv_info info{};
+    // batch (block-diagonal union of independent matrices): per-matrix
+    // offsets of columns, of A's entries and of L's entries (count + 1 each),
+    // and the matrix of every execution block; a single matrix is a batch of 1
+    std::vector<int64_t> b_noff, b_aoff, b_loff;
+    std::vector<int32_t> blk_matrix;
+    // persistent path: per-level work queues (factor leaves first, inversion
+    // root first), their capacity in the workspace and the schedule
+    selinv::Sched sched{};
+    std::vector<selinv::Task> q_fac, q_inv;
+    std::vector<int64_t> q_fac_off, q_inv_off;
+    int64_t q_cap_fac = 0, q_cap_inv = 0;
+    bool queues_on_device = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    const void* graph_in = nullptr;
+    void* graph_out = nullptr;
+    hipStream_t cap_stream = nullptr;
+    int n_cu = 0, occ_fac = 1, occ_inv = 1;  // device of the bound workspace
+    std::string dev_arch;
+    unsigned spin_limit = 1u << 22;         // polls of a dependency wait before it is abandoned
     // binding state
     char* ws = nullptr;
     size_t ws_bytes = 0;
@@ -108,6 +148,7 @@ struct selinv_plan_s {
     bool inverted = false;
     selinv::Prof prof;
     std::vector<double> work_flops, work_bytes;  // per kernel kind, per call
+    ~selinv_plan_s();
 };
 
 namespace selinv {
@@ -118,4 +159,13 @@ void nd_order_box(int ndim, const int32_t dims[3], int dofs, std::vector<int32_t
 void block_index_maps(const Partition& part, std::vector<int64_t>& rptr, std::vector<int32_t>& rel);
 // schedule.cpp
 void build_schedule(selinv_plan_s* P);
+// Work queues of the persistent path for schedule `sc`: per level (index =
+// level-1) the factor tasks qf[qf_off[l] .. qf_off[l+1]) and the inversion
+// tasks qi[...], each level's tasks in phase order.
+void build_queues(const selinv_plan_s* P, const Sched& sc, std::vector<Task>& qf, std::vector<int64_t>& qf_off,
+                  std::vector<Task>& qi, std::vector<int64_t>& qi_off);
+// number of factor / inversion queue entries build_queues makes for `sc`
+void queue_sizes(const selinv_plan_s* P, const Sched& sc, int64_t& nfac, int64_t& ninv);
+// batch.cpp: merge independently analysed plans into their block-diagonal union
+void merge_plans(const std::vector<selinv_plan_s*>& parts, selinv_plan_s* U);
 }  // namespace selinv

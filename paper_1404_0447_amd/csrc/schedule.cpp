@@ -143,4 +143,174 @@ void build_schedule(selinv_plan_s* P)
     P->work_bytes[kExport] = 24.0 * nnzL;
 }
 
+
+// ---------------------------------------------------------------------------
+// Work queues of the persistent level kernels.  One queue per level and
+// sweep holds the level's tasks of every block (and, in a batch, of every
+// matrix) in phase order; `pad` counts the earlier tasks of the same block
+// that must have finished.  A work-group only ever waits on tasks with a
+// smaller queue index, which were claimed before it by running work-groups,
+// so the queue drains whatever the residency.
+// ---------------------------------------------------------------------------
+static double block_cost(const BlockDesc& d)
+{
+    const double s = d.s, c = d.c;
+    return 2 * c * c * s + 2 * c * s * s + s * s * s;
+}
+
+// blocks of one level in the queue order of `order`
+static void order_blocks(const selinv_plan_s* P, int order, std::vector<int>& bl)
+{
+    if (order == qoLpt || order == qoTileLpt) {
+        std::stable_sort(bl.begin(), bl.end(),
+                         [&](int a, int b) { return block_cost(P->blocks[a]) > block_cost(P->blocks[b]); });
+    } else if (order == qoRoundRobin && !P->blk_matrix.empty()) {
+        // i-th block of every matrix in turn
+        std::vector<int> rank(bl.size());
+        int last = -1, r = 0;
+        for (size_t q = 0; q < bl.size(); q++) {  // bl is ascending, so matrix-major
+            const int m = P->blk_matrix[bl[q]];
+            r = (m == last) ? r + 1 : 0;
+            last = m;
+            rank[q] = r;
+        }
+        std::vector<size_t> idx(bl.size());
+        for (size_t q = 0; q < idx.size(); q++) idx[q] = q;
+        std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return rank[a] < rank[b]; });
+        std::vector<int> out(bl.size());
+        for (size_t q = 0; q < idx.size(); q++) out[q] = bl[idx[q]];
+        bl.swap(out);
+    }
+}
+
+static double task_cost(const Task& t)
+{
+    const int op = t.flags >> 8;
+    if (op == qSchur) return (double)t.ke * kSchurTile * kSchurTile;
+    if (op == qSdiag) return 2.0 * (t.ke - t.kb) * kDiagTile * kDiagTile;
+    return (double)(t.ke - t.kb) * t.bn * kTileM;
+}
+
+void build_queues(const selinv_plan_s* P, const Sched& sc, std::vector<Task>& qf, std::vector<int64_t>& qf_off,
+                  std::vector<Task>& qi, std::vector<int64_t>& qi_off)
+{
+    std::vector<std::vector<int>> lv;
+    by_level(P, lv);
+    const int D = (int)lv.size();
+    qf.clear();
+    qi.clear();
+    qf_off.assign(D + 1, 0);
+    qi_off.assign(D + 1, 0);
+    const int cap = std::max(16, std::min(128, sc.bn_cap));
+    auto bn_of = [&](int s) { return std::min(tile_bn(s), cap); };
+    std::vector<Task> ph[3];
+    auto flush = [&](std::vector<Task>& q) {
+        for (auto& p : ph) {
+            if (sc.order == qoTileLpt)
+                std::stable_sort(p.begin(), p.end(), [](const Task& a, const Task& b) { return task_cost(a) > task_cost(b); });
+            q.insert(q.end(), p.begin(), p.end());
+            p.clear();
+        }
+    };
+    for (int l = 0; l < D; l++) {
+        std::vector<int> bl = lv[l];
+        order_blocks(P, sc.order, bl);
+        // factor: diagonal block, then L_hat tiles, then Schur tiles
+        for (int B : bl) {
+            const BlockDesc& d = P->blocks[B];
+            const int bn = bn_of(d.s);
+            const int npanel = ((d.c + kTileM - 1) / kTileM) * ((d.s + bn - 1) / bn);
+            ph[0].push_back({B, 0, 0, 0, 0, 0, q_flags(qLdlt, 0), 0});
+            for (int j = 0; j < d.s; j += bn)
+                for (int r = 0; r < d.c; r += kTileM) ph[1].push_back({B, r, j, bn, 0, d.s, q_flags(qPanel, 0), 1});
+            for (int k = 0; k < d.c; k += kSchurTile)
+                for (int i = k; i < d.c; i += kSchurTile)
+                    ph[2].push_back({B, i, k, kSchurTile, 0, d.s, q_flags(qSchur, 0), 1 + npanel});
+        }
+        flush(qf);
+        qf_off[l + 1] = (int64_t)qf.size();
+        // inversion: zero X (split blocks), then X tiles, then diagonal tiles
+        int64_t base = 0, dbase = 0;
+        for (int B : bl) {
+            const BlockDesc& d = P->blocks[B];
+            base += (int64_t)((d.c + kTileM - 1) / kTileM) * ((d.s + bn_of(d.s) - 1) / bn_of(d.s));
+            const int nd = (d.s + kDiagTile - 1) / kDiagTile;
+            dbase += nd * (nd + 1) / 2;
+        }
+        const int64_t fill = sc.split_fill;
+        const int64_t want = fill > 0 && base > 0 && base < fill ? (fill + base - 1) / base : 1;
+        const int64_t dwant = fill > 0 && dbase > 0 && dbase < fill ? (fill + dbase - 1) / dbase : 1;
+        for (int B : bl) {
+            const BlockDesc& d = P->blocks[B];
+            const int bn = bn_of(d.s);
+            const int split = split_for(want, d.c);
+            const int dsplit = split_for(dwant, d.c);
+            const int nz = (split > 1 || dsplit > 1) ? 1 : 0;
+            if (nz) ph[0].push_back({B, 0, 0, 0, 0, 0, q_flags(qZero, 0), 0});
+            int ng = 0;
+            for (int j = 0; j < d.s; j += bn)
+                for (int r = 0; r < d.c; r += kTileM)
+                    pieces(0, d.c, split, [&](int kb, int ke, int) {
+                        ph[1].push_back({B, r, j, bn, kb, ke, q_flags(qGemm, split > 1), nz});
+                        ng++;
+                    });
+            const int nd = (d.s + kDiagTile - 1) / kDiagTile;
+            for (int I = 0; I < nd; I++)
+                for (int J = 0; J <= I; J++)
+                    pieces(0, d.c, dsplit, [&](int kb, int ke, int) {
+                        ph[2].push_back({B, I * kDiagTile, J * kDiagTile, 0, kb, ke, q_flags(qSdiag, dsplit > 1), nz + ng});
+                    });
+        }
+        flush(qi);
+        qi_off[l + 1] = (int64_t)qi.size();
+    }
+}
+
+
+void queue_sizes(const selinv_plan_s* P, const Sched& sc, int64_t& nfac, int64_t& ninv)
+{
+    std::vector<std::vector<int>> lv;
+    by_level(P, lv);
+    const int cap = std::max(16, std::min(128, sc.bn_cap));
+    auto bn_of = [&](int s) { return std::min(tile_bn(s), cap); };
+    auto npieces = [](int len, int split) {  // what pieces() emits for [0, len)
+        if (len <= 0) return 1;
+        const int n16 = (len + 15) / 16;
+        int k = 0;
+        for (int q = 0; q < split; q++) {
+            const int kb = (int)((int64_t)n16 * q / split) * 16;
+            const int ke = std::min(len, (int)((int64_t)n16 * (q + 1) / split) * 16);
+            if (kb < ke) k++;
+        }
+        return k;
+    };
+    nfac = ninv = 0;
+    for (const std::vector<int>& bl : lv) {
+        int64_t base = 0, dbase = 0;
+        for (int B : bl) {
+            const BlockDesc& d = P->blocks[B];
+            const int bn = bn_of(d.s);
+            const int64_t tiles = (int64_t)((d.c + kTileM - 1) / kTileM) * ((d.s + bn - 1) / bn);
+            const int64_t nsc = (d.c + kSchurTile - 1) / kSchurTile;
+            nfac += 1 + tiles + nsc * (nsc + 1) / 2;
+            base += tiles;
+            const int nd = (d.s + kDiagTile - 1) / kDiagTile;
+            dbase += nd * (nd + 1) / 2;
+        }
+        const int64_t fill = sc.split_fill;
+        const int64_t want = fill > 0 && base > 0 && base < fill ? (fill + base - 1) / base : 1;
+        const int64_t dwant = fill > 0 && dbase > 0 && dbase < fill ? (fill + dbase - 1) / dbase : 1;
+        for (int B : bl) {
+            const BlockDesc& d = P->blocks[B];
+            const int bn = bn_of(d.s);
+            const int split = split_for(want, d.c), dsplit = split_for(dwant, d.c);
+            const int64_t tiles = (int64_t)((d.c + kTileM - 1) / kTileM) * ((d.s + bn - 1) / bn);
+            const int nd = (d.s + kDiagTile - 1) / kDiagTile;
+            ninv += (split > 1 || dsplit > 1) ? 1 : 0;
+            ninv += tiles * npieces(d.c, split);
+            ninv += (int64_t)nd * (nd + 1) / 2 * npieces(d.c, dsplit);
+        }
+    }
+}
+
 }  // namespace selinv

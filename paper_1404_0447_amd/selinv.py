@@ -15,8 +15,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libselinv.so")
 
 SELINV_OK, SELINV_EINVAL, SELINV_ESTATE, SELINV_EPIVOT = 0, -1, -2, -3
-SELINV_ENOMEM, SELINV_EHIP, SELINV_EUNSUPPORTED = -4, -5, -6
-_NAMES = {0: "OK", -1: "EINVAL", -2: "ESTATE", -3: "EPIVOT", -4: "ENOMEM", -5: "EHIP", -6: "EUNSUPPORTED"}
+SELINV_ENOMEM, SELINV_EHIP, SELINV_EUNSUPPORTED, SELINV_EQUEUE = -4, -5, -6, -7
+_NAMES = {0: "OK", -1: "EINVAL", -2: "ESTATE", -3: "EPIVOT", -4: "ENOMEM", -5: "EHIP", -6: "EUNSUPPORTED",
+          -7: "EQUEUE"}
 
 # every symbol include/selinv.h declares
 EXPORTS = ["selinv_analyze", "selinv_workspace_size", "selinv_bind_workspace", "selinv_factor", "selinv_invert",
@@ -24,9 +25,13 @@ EXPORTS = ["selinv_analyze", "selinv_workspace_size", "selinv_bind_workspace", "
            "selinv_get_factor", "selinv_sync_status", "selinv_get_info", "selinv_get_pattern",
            "selinv_symbolic_sizes", "selinv_get_symbolic", "selinv_profile", "selinv_profile_read",
            "selinv_kernel_work", "selinv_get_arena", "selinv_get_blocks", "selinv_get_exec_rows",
+           "selinv_analyze_batch", "selinv_batch_offsets", "selinv_set_schedule", "selinv_get_schedule",
+           "selinv_get_queue", "selinv_set_spin_limit", "selinv_run", "selinv_tune",
            "selinv_last_error", "selinv_destroy"]
 ARENAS = {"L": 0, "Ainv": 1, "Lhat": 2, "W": 3, "T": 4, "Fbar": 5, "Lhat_bar": 6, "T_bar": 7}
-KINDS = ["assemble", "ldlt", "panel", "schur", "gemm", "sdiag", "export", "revsel", "revfac"]
+KINDS = ["assemble", "ldlt", "panel", "schur", "gemm", "sdiag", "export", "revsel", "revfac", "qfactor", "qinvert"]
+QOPS = ["ldlt", "panel", "schur", "zero", "gemm", "sdiag"]
+ORDERS = ["plan", "lpt", "round_robin", "tile_lpt"]
 
 
 class SelinvError(RuntimeError):
@@ -43,6 +48,13 @@ class Geom(ct.Structure):
 class Opts(ct.Structure):
     _fields_ = [("max_super", ct.c_int32), ("fuse_chains", ct.c_int32), ("require_spd", ct.c_int32),
                 ("exec_cap", ct.c_int32)]
+
+
+class Sched(ct.Structure):
+    _fields_ = [("order", ct.c_int32), ("bn_cap", ct.c_int32), ("split_fill", ct.c_int32), ("grid_mult", ct.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
 class Info(ct.Structure):
@@ -80,12 +92,19 @@ def lib():
         L.selinv_get_arena.argtypes = [vp, ct.c_int32, vp, ct.POINTER(i64), vp]
         L.selinv_get_blocks.argtypes = [vp] + [vp] * 8
         L.selinv_get_exec_rows.argtypes = [vp, vp]
+        L.selinv_analyze_batch.argtypes = [i32, vp, vp, vp, vp, vp, ct.POINTER(vp)]
+        L.selinv_batch_offsets.argtypes = [vp, ct.POINTER(i32), vp, vp, vp]
+        L.selinv_set_schedule.argtypes = [vp, ct.POINTER(Sched), vp]
+        L.selinv_get_schedule.argtypes = [vp, ct.POINTER(Sched)]
+        L.selinv_get_queue.argtypes = [vp, i32, i32, vp, ct.POINTER(i64)]
+        L.selinv_set_spin_limit.argtypes = [vp, ct.c_uint32]
+        L.selinv_run.argtypes = [vp, vp, vp, i32, vp]
+        L.selinv_tune.argtypes = [vp, vp, vp, ct.c_char_p, ct.POINTER(Sched), ct.POINTER(ct.c_double), vp]
         L.selinv_last_error.restype = ct.c_char_p
         L.selinv_destroy.argtypes = [vp]
         for f in EXPORTS:
             if f not in ("selinv_last_error", "selinv_destroy"):
                 getattr(L, f).restype = ct.c_int
-        _ = i32
         _lib = L
     return _lib
 
@@ -111,9 +130,12 @@ class Plan:
     """Symbolic analysis + bound device workspace for one sparsity pattern."""
 
     def __init__(self, n, colptr, rowind, geom=None, perm=None, max_super=128, fuse_chains=True,
-                 require_spd=True, exec_cap=0):
+                 require_spd=True, exec_cap=0, _handle=None):
         L = lib()
         self.n = int(n)
+        if _handle is not None:
+            self._adopt(_handle)
+            return
         self._colptr = np.ascontiguousarray(colptr, dtype=np.int64)
         self._rowind = np.ascontiguousarray(rowind, dtype=np.int32)
         g = None
@@ -127,12 +149,43 @@ class Plan:
         st = L.selinv_analyze(self.n, _p(self._colptr), _p(self._rowind), ct.byref(g) if g is not None else None,
                               _p(pm), ct.byref(o), ct.byref(h))
         _check(st)
+        self._adopt(h)
+
+    def _adopt(self, h):
+        L = lib()
         self._h = h
         self._ws = None
         self._bound = False
         inf = Info()
         _check(L.selinv_get_info(self._h, ct.byref(inf)))
         self.info = {k: getattr(inf, k) for k, _ in Info._fields_}
+        cnt = ct.c_int32()
+        _check(L.selinv_batch_offsets(self._h, ct.byref(cnt), None, None, None))
+        self.count = int(cnt.value)
+        offs = [np.empty(self.count + 1, np.int64) for _ in range(3)]
+        _check(L.selinv_batch_offsets(self._h, None, *[_p(o) for o in offs]))
+        self.n_off, self.nnzA_off, self.nnzL_off = offs
+
+    @classmethod
+    def batch(cls, matrices, max_super=128, fuse_chains=True, require_spd=True, exec_cap=0):
+        """One plan for a list of independent workloads.Matrix (their
+        block-diagonal union); values and results concatenate in list order."""
+        L = lib()
+        cnt = len(matrices)
+        cps = [np.ascontiguousarray(m.colptr, dtype=np.int64) for m in matrices]
+        ris = [np.ascontiguousarray(m.rowind, dtype=np.int32) for m in matrices]
+        ns = np.array([m.n for m in matrices], dtype=np.int64)
+        cp_arr = (ct.c_void_p * max(cnt, 1))(*[c.ctypes.data for c in cps])
+        ri_arr = (ct.c_void_p * max(cnt, 1))(*[r.ctypes.data if r.size else None for r in ris])
+        geoms = (Geom * max(cnt, 1))()
+        for i, m in enumerate(matrices):
+            d3 = list(m.dims) + [1] * (3 - len(m.dims))
+            geoms[i] = Geom(int(m.ndim), (ct.c_int32 * 3)(*[int(x) for x in d3[:3]]), int(m.dofs))
+        o = Opts(int(max_super), int(bool(fuse_chains)), int(bool(require_spd)), int(exec_cap))
+        h = ct.c_void_p()
+        st = L.selinv_analyze_batch(cnt, _p(ns), cp_arr, ri_arr, geoms, ct.byref(o), ct.byref(h))
+        _check(st)
+        return cls(int(ns.sum()), None, None, _handle=h)
 
     @classmethod
     def from_matrix(cls, m, **kw):
@@ -209,6 +262,69 @@ class Plan:
         _check(lib().selinv_backward(self._h, ct.c_void_p(gsel.data_ptr()), ct.c_void_p(out.data_ptr()),
                                      _stream(stream)))
         return out
+
+    # ------------------------------------------------------------ persistent path
+    def schedule(self):
+        sc = Sched()
+        _check(lib().selinv_get_schedule(self._h, ct.byref(sc)))
+        return sc.as_dict()
+
+    def set_schedule(self, order=None, bn_cap=None, split_fill=None, grid_mult=None, stream=None):
+        cur = self.schedule()
+        for k, v in (("order", order), ("bn_cap", bn_cap), ("split_fill", split_fill), ("grid_mult", grid_mult)):
+            if v is not None:
+                cur[k] = ORDERS.index(v) if (k == "order" and isinstance(v, str)) else int(v)
+        sc = Sched(**cur)
+        _check(lib().selinv_set_schedule(self._h, ct.byref(sc), _stream(stream) if self._bound else None))
+        return self.schedule()
+
+    def queue(self, sweep, level):
+        """Host copy of one level's work queue: int32 array (tasks, 8)."""
+        cnt = ct.c_int64()
+        _check(lib().selinv_get_queue(self._h, int(sweep), int(level), None, ct.byref(cnt)))
+        out = np.empty((max(cnt.value, 1), 8), np.int32)
+        _check(lib().selinv_get_queue(self._h, int(sweep), int(level), _p(out), ct.byref(cnt)))
+        return out[: cnt.value]
+
+    def set_spin_limit(self, polls):
+        _check(lib().selinv_set_spin_limit(self._h, int(polls)))
+
+    def run(self, vals, out=None, graph=False, stream=None):
+        """Factor + invert on the persistent level kernels (graph=True:
+        replayed from a captured HIP graph)."""
+        import torch
+        if not self._bound:
+            self.bind(device=vals.device)
+        self._need(vals, int(self.info["nnzA"]), "vals")
+        nnzL = int(self.info["nnzL"])
+        if out is None:
+            out = torch.empty(nnzL, dtype=torch.float64, device=self._ws.device)
+        self._need(out, nnzL, "out")
+        _check(lib().selinv_run(self._h, ct.c_void_p(vals.data_ptr()), ct.c_void_p(out.data_ptr()),
+                                int(bool(graph)), _stream(stream)))
+        return out
+
+    def tune(self, vals, out=None, cache_path=None, stream=None):
+        """Autotune the persistent schedule on these values; returns
+        (schedule dict, best ms, selected inverse)."""
+        import torch
+        if not self._bound:
+            self.bind(device=vals.device)
+        self._need(vals, int(self.info["nnzA"]), "vals")
+        nnzL = int(self.info["nnzL"])
+        if out is None:
+            out = torch.empty(nnzL, dtype=torch.float64, device=self._ws.device)
+        self._need(out, nnzL, "out")
+        sc = Sched()
+        ms = ct.c_double()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        _check(lib().selinv_tune(self._h, ct.c_void_p(vals.data_ptr()), ct.c_void_p(out.data_ptr()), path,
+                                 ct.byref(sc), ct.byref(ms), _stream(stream)))
+        return sc.as_dict(), float(ms.value), out
+
+    def split(self, sel):
+        """Per-matrix views of a batch's concatenated selected values."""
+        return [sel[int(self.nnzL_off[m]):int(self.nnzL_off[m + 1])] for m in range(self.count)]
 
     def factor_values(self, out=None, stream=None):
         import torch
