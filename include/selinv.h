@@ -169,7 +169,9 @@ enum {
     SELINV_K_REVFAC = 8,   /* reverse factorization (adjoint), root first        */
     SELINV_K_QFACTOR = 9,  /* persistent factor level (LDLT, PANEL, SCHUR tasks)  */
     SELINV_K_QINVERT = 10, /* persistent inversion level (GEMM, SDIAG tasks)      */
-    SELINV_NKINDS = 11
+    SELINV_K_SBFACTOR = 11, /* small blocks, whole factor step, one wave each      */
+    SELINV_K_SBINVERT = 12, /* small blocks, whole inversion step, one wave each   */
+    SELINV_NKINDS = 13
 };
 
 /* Enable (1) or disable (0) per-launch timing: every later kernel launch of
@@ -181,9 +183,12 @@ selinv_status selinv_profile(selinv_plan p, int32_t enable);
  * record.  Either pointer may be NULL. */
 selinv_status selinv_profile_read(selinv_plan p, double* ms, int64_t* launches);
 
-/* Algorithmic flops and bytes of one selinv_factor (kinds ASSEMBLE..SCHUR)
- * and one selinv_invert (GEMM, SDIAG, EXPORT) call, per kernel kind, on the
- * execution blocks (arrays of SELINV_NKINDS). */
+/* Algorithmic flops and bytes per kernel kind (arrays of SELINV_NKINDS) on
+ * the execution blocks: of one selinv_factor (ASSEMBLE..SCHUR and SBFACTOR),
+ * one selinv_invert (GEMM, SDIAG, EXPORT, SBINVERT), one selinv_backward
+ * (REVSEL, REVFAC) and, for selinv_run, of its factor and inversion levels
+ * (QFACTOR, QINVERT).  Blocks of at most 16 columns and 256 rows below take
+ * the small-block kinds in selinv_factor / selinv_invert. */
 selinv_status selinv_kernel_work(selinv_plan p, double* flops, double* bytes);
 
 /* Raw device arenas, for kernel-level checks: which = 0 factor panels
@@ -242,27 +247,42 @@ selinv_status selinv_batch_offsets(selinv_plan p, int32_t* count, int64_t* n_off
  * output tile of the gather-GEMM and panel products (16, 32, 64, 128).
  * split_fill (0..4096): contractions are split over work-groups while a
  * level has fewer output tiles than this (0 = never).  grid_mult: resident
- * work-groups per compute unit (capped by the kernel's occupancy). */
+ * work-groups per compute unit (capped by the kernel's occupancy).
+ * small_s (0, 1, 2, 4, 8, 16): blocks of at most small_s columns and at most
+ * 256 rows below run whole on one wave each, four to a task (0 = none); a
+ * level with only such blocks runs a lighter kernel variant with as many
+ * resident work-groups as it allows, each wave taking a fixed share.
+ * mb_tiles (0..4096): other blocks with at most this many gather-GEMM output
+ * tiles run whole on one work-group, phase after phase, so they wait for no
+ * other work-group; larger blocks are split into tile tasks that wait for
+ * their block's earlier phases. */
 typedef struct {
     int32_t order;
     int32_t bn_cap;
     int32_t split_fill;
     int32_t grid_mult;
+    int32_t small_s;
+    int32_t mb_tiles;
 } selinv_sched;
 
 /* Rebuild the work queues for schedule *sc and upload them on stream s
  * (synchronises s; s is unused before selinv_bind_workspace); drops a
  * captured graph.  SELINV_EINVAL for a field out of range.  The workspace
- * reserves queue space for every valid schedule. */
+ * reserves queue space for every valid schedule (a bound that holds for
+ * any of them). */
 selinv_status selinv_set_schedule(selinv_plan p, const selinv_sched* sc, hipStream_t s);
 selinv_status selinv_get_schedule(selinv_plan p, selinv_sched* sc);
 
 /* Host copy of one level's queue (sweep 0 factor, 1 inversion; level 1 =
  * roots) as 8 int32 per task: block, row origin, column origin, tile width,
- * contraction begin, end, flags (bit 0 atomic accumulation, bits 8..15 the
- * operation: 0 LDLT, 1 PANEL, 2 SCHUR, 3 ZERO, 4 GEMM, 5 SDIAG) and the number
- * of earlier tasks of the same block it waits for.  *count = tasks; tasks may
- * be NULL. */
+ * contraction begin, end, flags (bit 0 atomic accumulation, bit 1 others
+ * wait for it, bits 8..15 the operation: 0 LDLT, 1 PANEL, 2 SCHUR, 3 ZERO,
+ * 4 GEMM, 5 SDIAG, 6 small-block factor, 7 small-block inversion, 8
+ * medium-block factor, 9 medium-block inversion) and the number of earlier
+ * tasks of the same block it waits for.  A small-block task lists up to four
+ * block ids in its first four fields (-1 = none); a medium-block task names
+ * its block and its tile width.
+ * *count = tasks; tasks may be NULL. */
 selinv_status selinv_get_queue(selinv_plan p, int32_t sweep, int32_t level, int32_t* tasks, int64_t* count);
 
 /* Polls a dependency wait makes before it gives up and latches
@@ -281,8 +301,9 @@ selinv_status selinv_set_spin_limit(selinv_plan p, uint32_t polls);
 selinv_status selinv_run(selinv_plan p, const double* d_valsA, double* d_sel, int32_t use_graph, hipStream_t s);
 
 /* Autotuner: times selinv_run (no graph) on the given buffers for schedules
- * along each axis in turn (order, bn_cap, split_fill 0/512/4096, grid_mult
- * 1/2/4), keeps the fastest and leaves it set.  cache_path (may be NULL):
+ * along each axis in turn (small_s 0/4/16, mb_tiles 0/8/64, order, bn_cap
+ * 32/64/128, split_fill 0/512/4096, grid_mult 1/2/4), keeps the fastest and
+ * leaves it set.  cache_path (may be NULL):
  * a JSON file of earlier choices keyed by device and block structure; a hit
  * skips the timing, a miss adds the choice.  On return d_sel holds the
  * selected inverse of d_valsA; *chosen and *best_ms (may be NULL) the

@@ -58,6 +58,8 @@ void compute_layout(selinv_plan_s* P)
     L.colblk = take(sizeof(int32_t) * P->colblk.size());
     L.colptrL = take(sizeof(int64_t) * P->colptrL.size());
     L.t_diag = take(sizeof(Task) * P->t_diag.tasks.size());
+    L.t_ldlt = take(sizeof(Task) * P->t_ldlt.tasks.size());
+    L.t_sb = take(sizeof(Task) * P->t_sb.tasks.size());
     L.t_panel = take(sizeof(Task) * P->t_panel.tasks.size());
     L.t_schur = take(sizeof(Task) * P->t_schur.tasks.size());
     L.t_gemm = take(sizeof(Task) * P->t_gemm.tasks.size());
@@ -104,6 +106,8 @@ DevPtrs dev_ptrs(const selinv_plan_s* P)
     D.colblk = (const int32_t*)(w + L.colblk);
     D.colptrL = (const int64_t*)(w + L.colptrL);
     D.t_diag = (const Task*)(w + L.t_diag);
+    D.t_ldlt = (const Task*)(w + L.t_ldlt);
+    D.t_sb = (const Task*)(w + L.t_sb);
     D.t_panel = (const Task*)(w + L.t_panel);
     D.t_schur = (const Task*)(w + L.t_schur);
     D.t_gemm = (const Task*)(w + L.t_gemm);
@@ -193,7 +197,32 @@ constexpr int32_t kTuneOrders[] = {qoPlan, qoLpt, qoRoundRobin, qoTileLpt};
 constexpr int32_t kTuneBn[] = {32, 64, 128};
 constexpr int32_t kTuneFill[] = {0, 512, 4096};
 constexpr int32_t kTuneGrid[] = {1, 2, 4};
-constexpr int32_t kCapBn[] = {16, 32, 64, 128};
+constexpr int32_t kTuneSmall[] = {0, 4, 16};
+constexpr int32_t kTuneMb[] = {0, 8, 64};
+constexpr int32_t kSmallValues[] = {0, 1, 2, 4, 8, 16};  // the accepted small_s values
+
+// per level: the persistent variant its queue needs (light when it holds
+// only small-block tasks, else the class of its widest diagonal block or
+// output tile)
+void level_variants(const selinv_plan_s* P, const std::vector<Task>& q, const std::vector<int64_t>& off,
+                    bool factor, std::vector<uint8_t>& var)
+{
+    const int sb_op = factor ? qSbFactor : qSbInvert;
+    var.assign(off.empty() ? 0 : off.size() - 1, 0);
+    for (size_t l = 0; l + 1 < off.size(); l++) {
+        bool tiled = false;
+        int widest = 0;
+        for (int64_t k = off[l]; k < off[l + 1]; k++) {
+            const int op = q[k].flags >> 8;
+            if (op == sb_op) continue;
+            tiled = true;
+            if (op == qLdlt || op == qMbFactor) widest = std::max(widest, P->blocks[q[k].b].s);
+            if (op == qGemm || op == qMbInvert) widest = std::max(widest, q[k].bn);
+        }
+        if (factor) var[l] = !tiled ? kLightFactor : widest <= 32 ? kFactor32 : widest <= 64 ? kFactor64 : kFactor128;
+        else var[l] = !tiled ? kLightInvert : widest <= 32 ? kInvert32 : widest <= 64 ? kInvert64 : kInvert128;
+    }
+}
 
 // per-level task lists, persistent queues for the default schedule, and
 // the device layout
@@ -206,17 +235,10 @@ void finish_plan(selinv_plan_s* P)
         P->b_loff = {0, P->colptrL.back()};
     }
     build_schedule(P);
-    for (int32_t bn : kCapBn)
-        for (int32_t fill : kTuneFill) {
-            Sched sc = P->sched;
-            sc.bn_cap = bn;
-            sc.split_fill = fill;
-            int64_t nf = 0, ni = 0;
-            queue_sizes(P, sc, nf, ni);
-            P->q_cap_fac = std::max(P->q_cap_fac, nf);
-            P->q_cap_inv = std::max(P->q_cap_inv, ni);
-        }
+    queue_bound(P, P->q_cap_fac, P->q_cap_inv);
     build_queues(P, P->sched, P->q_fac, P->q_fac_off, P->q_inv, P->q_inv_off);
+    level_variants(P, P->q_fac, P->q_fac_off, true, P->q_var_fac);
+    level_variants(P, P->q_inv, P->q_inv_off, false, P->q_var_inv);
     compute_layout(P);
 }
 
@@ -349,7 +371,7 @@ selinv_status selinv_bind_workspace(selinv_plan P, void* d_ws, size_t bytes, hip
     hipDeviceProp_t prop;
     if (!e) e = hipGetDevice(&dev);
     if (!e) e = hipGetDeviceProperties(&prop, dev);
-    if (!e) e = persist_occupancy(&P->occ_fac, &P->occ_inv);
+    if (!e) e = persist_occupancy(P->occ);
     if (e) {
         P->ws = nullptr;
         return hip_fail(e, "device query");
@@ -366,6 +388,8 @@ selinv_status selinv_bind_workspace(selinv_plan P, void* d_ws, size_t bytes, hip
     if (!e) e = upload(P->ws, L.colblk, P->colblk, s);
     if (!e) e = upload(P->ws, L.colptrL, P->colptrL, s);
     if (!e) e = upload(P->ws, L.t_diag, P->t_diag.tasks, s);
+    if (!e) e = upload(P->ws, L.t_ldlt, P->t_ldlt.tasks, s);
+    if (!e) e = upload(P->ws, L.t_sb, P->t_sb.tasks, s);
     if (!e) e = upload(P->ws, L.t_panel, P->t_panel.tasks, s);
     if (!e) e = upload(P->ws, L.t_schur, P->t_schur.tasks, s);
     if (!e) e = upload(P->ws, L.t_gemm, P->t_gemm.tasks, s);
@@ -401,11 +425,15 @@ selinv_status selinv_factor(selinv_plan P, const double* d_valsA, hipStream_t s)
     if (e) return hip_fail(e, "factor setup");
     const int depth = P->exec.depth;
     for (int l = depth - 1; l >= 0; l--) {
-        const auto& a = P->t_diag.off;
+        const auto& q = P->t_sb.off;
+        const auto& a = P->t_ldlt.off;
         const auto& b = P->t_panel.off;
         const auto& c = P->t_schur.off;
-        e = launch_factor_level(&P->prof, D, a[l], a[l + 1] - a[l], b[l], b[l + 1] - b[l], c[l], c[l + 1] - c[l],
-                                P->opts.require_spd, s);
+        const int64_t diag[4] = {a[l], P->ldlt_cut[2 * l], P->ldlt_cut[2 * l + 1], a[l + 1]};
+        e = launch_sb_factor(&P->prof, D, q[l], q[l + 1] - q[l], P->opts.require_spd, s);
+        if (!e)
+            e = launch_factor_level(&P->prof, D, diag, b[l], b[l + 1] - b[l], c[l], c[l + 1] - c[l],
+                                    P->opts.require_spd, s);
         if (e) return hip_fail(e, "factor level launch");
     }
     P->factored = true;
@@ -462,9 +490,11 @@ selinv_status selinv_invert(selinv_plan P, double* d_sel, hipStream_t s)
     if (e) return hip_fail(e, "invert setup");
     const int depth = P->exec.depth;
     for (int l = 0; l < depth; l++) {
+        const auto& q = P->t_sb.off;
         const auto& g = P->t_gemm.off;
         const auto& d = P->t_sdiag.off;
-        e = launch_invert_level(&P->prof, D, g[l], g[l + 1] - g[l], d[l], d[l + 1] - d[l], s);
+        e = launch_sb_invert(&P->prof, D, q[l], q[l + 1] - q[l], s);
+        if (!e) e = launch_invert_level(&P->prof, D, g[l], g[l + 1] - g[l], d[l], d[l + 1] - d[l], s);
         if (e) return hip_fail(e, "invert level launch");
     }
     e = launch_gather(&P->prof, kExport, D.Ap, D.exp_off, P->colptrL.back(), d_sel, s);
@@ -665,20 +695,27 @@ selinv_status run_persistent(selinv_plan_s* P, const double* d_valsA, double* d_
     unsigned* head_i = head_f + depth;
     const Task* qf = (const Task*)(P->ws + P->lay.q_fac);
     const Task* qi = (const Task*)(P->ws + P->lay.q_inv);
-    const int gf = std::max(1, P->n_cu * std::min(P->sched.grid_mult, P->occ_fac));
-    const int gi = std::max(1, P->n_cu * std::min(P->sched.grid_mult, P->occ_inv));
+    auto grid = [&](int variant) {
+        // light (wave-granular) levels fill the occupancy; tiled levels take
+        // grid_mult work-groups per CU, capped by it
+        const int occ = std::max(1, P->occ[variant]);
+        const bool light = variant == kLightFactor || variant == kLightInvert;
+        return P->n_cu * (light ? occ : std::min(P->sched.grid_mult, occ));
+    };
     hipError_t e = launch_status_reset(D.status, s);
     if (!e) e = launch_fill(prof, kAssemble, D.Lp, P->arena, 0.0, s);
     if (!e) e = launch_scatter_set(prof, kAssemble, d_valsA, D.asm_off, P->nnzA, D.Lp, s);
     if (!e) e = launch_fill_u32(prof, kAssemble, done_f, 2 * (nb + depth), s);
     for (int l = depth - 1; l >= 0 && !e; l--) {
         const int64_t a = P->q_fac_off[l], z = P->q_fac_off[l + 1];
-        e = launch_persist_factor(prof, D, qf + a, z - a, head_f + l, done_f, gf, P->opts.require_spd,
+        const int var = P->q_var_fac[l];
+        e = launch_persist_factor(prof, D, qf + a, z - a, head_f + l, done_f, grid(var), var, P->opts.require_spd,
                                   P->spin_limit, s);
     }
     for (int l = 0; l < depth && !e; l++) {
         const int64_t a = P->q_inv_off[l], z = P->q_inv_off[l + 1];
-        e = launch_persist_invert(prof, D, qi + a, z - a, head_i + l, done_i, gi, P->spin_limit, s);
+        const int var = P->q_var_inv[l];
+        e = launch_persist_invert(prof, D, qi + a, z - a, head_i + l, done_i, grid(var), var, P->spin_limit, s);
     }
     if (!e) e = launch_gather(prof, kExport, D.Ap, D.exp_off, P->colptrL.back(), d_sel, s);
     if (e) return hip_fail(e, "persistent launch");
@@ -691,10 +728,11 @@ selinv_status check_sched(const selinv_sched* sc)
     if (sc->order < 0 || sc->order >= qoNumOrders) return fail(SELINV_EINVAL, "schedule order out of range");
     if (sc->bn_cap != 16 && sc->bn_cap != 32 && sc->bn_cap != 64 && sc->bn_cap != 128)
         return fail(SELINV_EINVAL, "bn_cap must be 16, 32, 64 or 128");
-    // queue lengths grow with split_fill, so the capacity reserved for 4096
-    // covers every accepted value
     if (sc->split_fill < 0 || sc->split_fill > 4096) return fail(SELINV_EINVAL, "split_fill must be 0..4096");
     if (sc->grid_mult < 1 || sc->grid_mult > 16) return fail(SELINV_EINVAL, "grid_mult must be 1..16");
+    if (std::find(std::begin(kSmallValues), std::end(kSmallValues), sc->small_s) == std::end(kSmallValues))
+        return fail(SELINV_EINVAL, "small_s must be 0, 1, 2, 4, 8 or 16");
+    if (sc->mb_tiles < 0 || sc->mb_tiles > 4096) return fail(SELINV_EINVAL, "mb_tiles must be 0..4096");
     return SELINV_OK;
 }
 
@@ -729,7 +767,8 @@ std::string tune_key(const selinv_plan_s* P)
 }
 
 // Cache file: a JSON object with one entry per line,
-//   "key": {"order": 1, "bn_cap": 128, "split_fill": 512, "grid_mult": 2, "ms": 1.5},
+//   "key": {"order": 1, "bn_cap": 128, "split_fill": 512, "grid_mult": 2, "small_s": 16, "mb_tiles": 8,
+//           "ms": 1.5},   (one line per entry)
 bool cache_lookup(const char* path, const std::string& key, selinv_sched& sc, double& ms)
 {
     std::ifstream in(path);
@@ -746,10 +785,12 @@ bool cache_lookup(const char* path, const std::string& key, selinv_sched& sc, do
             v = std::strtod(line.c_str() + q + f.size(), nullptr);
             return true;
         };
-        double o, b, fl, g;
-        if (!num("order", o) || !num("bn_cap", b) || !num("split_fill", fl) || !num("grid_mult", g)) return false;
+        double o, b, fl, g, sm, mb;
+        if (!num("order", o) || !num("bn_cap", b) || !num("split_fill", fl) || !num("grid_mult", g) ||
+            !num("small_s", sm) || !num("mb_tiles", mb))
+            return false;
         if (!num("ms", ms)) ms = 0.0;
-        sc = selinv_sched{(int32_t)o, (int32_t)b, (int32_t)fl, (int32_t)g};
+        sc = selinv_sched{(int32_t)o, (int32_t)b, (int32_t)fl, (int32_t)g, (int32_t)sm, (int32_t)mb};
         return check_sched(&sc) == SELINV_OK;
     }
     return false;
@@ -770,8 +811,9 @@ bool cache_store(const char* path, const std::string& key, const selinv_sched& s
     }
     char buf[256];
     std::snprintf(buf, sizeof buf,
-                  "  \"%s\": {\"order\": %d, \"bn_cap\": %d, \"split_fill\": %d, \"grid_mult\": %d, \"ms\": %.6f}",
-                  key.c_str(), sc.order, sc.bn_cap, sc.split_fill, sc.grid_mult, ms);
+                  "  \"%s\": {\"order\": %d, \"bn_cap\": %d, \"split_fill\": %d, \"grid_mult\": %d, "
+                  "\"small_s\": %d, \"mb_tiles\": %d, \"ms\": %.6f}",
+                  key.c_str(), sc.order, sc.bn_cap, sc.split_fill, sc.grid_mult, sc.small_s, sc.mb_tiles, ms);
     keep.push_back(buf);
     std::ofstream out(path, std::ios::trunc);
     if (!out) return false;
@@ -788,7 +830,7 @@ selinv_status selinv_set_schedule(selinv_plan P, const selinv_sched* sc, hipStre
 {
     if (!P) return fail(SELINV_EINVAL, "NULL plan");
     if (selinv_status st = check_sched(sc)) return st;
-    Sched next{sc->order, sc->bn_cap, sc->split_fill, sc->grid_mult};
+    Sched next{sc->order, sc->bn_cap, sc->split_fill, sc->grid_mult, sc->small_s, sc->mb_tiles};
     std::vector<Task> qf, qi;
     std::vector<int64_t> of, oi;
     try {
@@ -797,7 +839,7 @@ selinv_status selinv_set_schedule(selinv_plan P, const selinv_sched* sc, hipStre
         return fail(SELINV_ENOMEM, "out of host memory building the queues");
     }
     if ((int64_t)qf.size() > P->q_cap_fac || (int64_t)qi.size() > P->q_cap_inv)
-        return fail(SELINV_EINVAL, "schedule needs more queue entries than the workspace reserves");
+        return fail(SELINV_EINVAL, "internal: queue longer than its bound");
     if (P->ws) {
         hipError_t e = upload(P->ws, P->lay.q_fac, qf, s);
         if (!e) e = upload(P->ws, P->lay.q_inv, qi, s);
@@ -813,13 +855,16 @@ selinv_status selinv_set_schedule(selinv_plan P, const selinv_sched* sc, hipStre
     P->q_inv.swap(qi);
     P->q_fac_off.swap(of);
     P->q_inv_off.swap(oi);
+    level_variants(P, P->q_fac, P->q_fac_off, true, P->q_var_fac);
+    level_variants(P, P->q_inv, P->q_inv_off, false, P->q_var_inv);
     return SELINV_OK;
 }
 
 selinv_status selinv_get_schedule(selinv_plan P, selinv_sched* sc)
 {
     if (!P || !sc) return fail(SELINV_EINVAL, "NULL argument");
-    *sc = selinv_sched{P->sched.order, P->sched.bn_cap, P->sched.split_fill, P->sched.grid_mult};
+    *sc = selinv_sched{P->sched.order,     P->sched.bn_cap,  P->sched.split_fill,
+                       P->sched.grid_mult, P->sched.small_s, P->sched.mb_tiles};
     return SELINV_OK;
 }
 
@@ -926,16 +971,20 @@ selinv_status selinv_tune(selinv_plan P, const double* d_valsA, double* d_sel, c
         int64_t bad = -1;
         return selinv_sync_status(P, s, &bad);
     };
-    // coordinate descent over queue order, tile cap, split fill, grid size
-    best = selinv_sched{P->sched.order, P->sched.bn_cap, P->sched.split_fill, P->sched.grid_mult};
+    // coordinate descent over small-block width, medium-block size, queue
+    // order, tile cap, split fill, grid size
+    best = selinv_sched{P->sched.order,     P->sched.bn_cap,  P->sched.split_fill,
+                        P->sched.grid_mult, P->sched.small_s, P->sched.mb_tiles};
     double tbest = 0.0;
     selinv_status st = evaluate(best, tbest);
-    for (int dim = 0; dim < 4 && st == SELINV_OK; dim++) {
-        const int32_t* vals = dim == 0 ? kTuneOrders : dim == 1 ? kTuneBn : dim == 2 ? kTuneFill : kTuneGrid;
-        const int nv = dim == 0 ? 4 : 3;
+    for (int dim = 0; dim < 6 && st == SELINV_OK; dim++) {
+        const int32_t* axes[] = {kTuneSmall, kTuneMb, kTuneOrders, kTuneBn, kTuneFill, kTuneGrid};
+        const int32_t* vals = axes[dim];
+        const int nv = dim == 2 ? 4 : 3;
         for (int v = 0; v < nv && st == SELINV_OK; v++) {
             selinv_sched c = best;
-            int32_t* field = dim == 0 ? &c.order : dim == 1 ? &c.bn_cap : dim == 2 ? &c.split_fill : &c.grid_mult;
+            int32_t* fields[] = {&c.small_s, &c.mb_tiles, &c.order, &c.bn_cap, &c.split_fill, &c.grid_mult};
+            int32_t* field = fields[dim];
             if (*field == vals[v]) continue;
             *field = vals[v];
             double t = 0.0;

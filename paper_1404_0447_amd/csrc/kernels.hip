@@ -22,6 +22,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <type_traits>
 
 #include "kernels.hpp"
 #include "plan.hpp"
@@ -537,9 +538,9 @@ __device__ void ldlt_global(const BlockDesc d, double* __restrict__ Lp, double* 
     }
 }
 
-// Diagonal block, s <= 128, by symmetric Gauss-Jordan sweeps held in
-// registers.  Thread (tx, ty) = (tid % 16, tid / 16) owns M(tx + 16a,
-// ty + 16b), a, b < 8.  Sweeping pivot j (M(j,j) = d_j, c = M(:,j)):
+// Diagonal block, s <= 16 NB (NB = 2, 4, 8), by symmetric Gauss-Jordan
+// sweeps held in registers.  Thread (tx, ty) = (tid % 16, tid / 16) owns
+// M(tx + 16a, ty + 16b), a, b < NB (the kernel's registers follow NB).  Sweeping pivot j (M(j,j) = d_j, c = M(:,j)):
 //   M(i,k) -= c_i c_k / d_j  (i, k != j),  M(i,j) = M(j,i) = c_i / d_j,
 //   M(j,j) = -1 / d_j.
 // After all pivots M = -F_BB^{-1} = -T.  Before its own sweep, column j
@@ -547,6 +548,7 @@ __device__ void ldlt_global(const BlockDesc d, double* __restrict__ Lp, double* 
 // c_i / d_j (i > j) are L_BB(i,j) and d_j is D's entry: both are written
 // out as they appear.  One LDS broadcast of column j and one barrier per
 // pivot (the column buffer alternates between two slots).
+template <int NB>
 __device__ void ldlt_sweep(const BlockDesc d, double* __restrict__ Lp, double* __restrict__ Tp,
                            unsigned long long* __restrict__ status, int require_spd, double (*colbuf)[kLdsDiagMax])
 {
@@ -555,11 +557,11 @@ __device__ void ldlt_sweep(const BlockDesc d, double* __restrict__ Lp, double* _
     double* F = Lp + d.poff;
     double* T = Tp + d.woff;
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-    double M[8][8];
+    double M[NB][NB];
 #pragma unroll
-    for (int a = 0; a < 8; ++a)
+    for (int a = 0; a < NB; ++a)
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
+        for (int b = 0; b < NB; ++b) {
             const int i = tx + 16 * a, k = ty + 16 * b;
             double v = 0.0;
             if (i < s && k < s) v = i >= k ? F[i + k * ld] : F[k + i * ld];
@@ -568,14 +570,14 @@ __device__ void ldlt_sweep(const BlockDesc d, double* __restrict__ Lp, double* _
     // pivots j = 16 jb + jt: jb is unrolled, so the pivot's register row
     // (a == jb) and column (b == jb) are known at compile time
 #pragma unroll
-    for (int jb = 0; jb < 8; ++jb) {
+    for (int jb = 0; jb < NB; ++jb) {
         const int jt_end = min(16, s - 16 * jb);
         for (int jt = 0; jt < jt_end; ++jt) {
             const int j = 16 * jb + jt;
             double* buf = colbuf[j & 1];
             if (ty == jt) {
 #pragma unroll
-                for (int a = 0; a < 8; ++a) buf[tx + 16 * a] = M[a][jb];
+                for (int a = 0; a < NB; ++a) buf[tx + 16 * a] = M[a][jb];
             }
             __syncthreads();
             const double dj = buf[j];
@@ -584,14 +586,14 @@ __device__ void ldlt_sweep(const BlockDesc d, double* __restrict__ Lp, double* _
                 const bool ok = isfinite(dj) && dj != 0.0 && (!require_spd || dj > 0.0);
                 if (!ok) atomicMin(status, (unsigned long long)(d.first + j));
             }
-            double ci[8], ck[8];
+            double ci[NB], ck[NB];
 #pragma unroll
-            for (int a = 0; a < 8; ++a) ci[a] = buf[tx + 16 * a] * inv;  // c_i / d_j
+            for (int a = 0; a < NB; ++a) ci[a] = buf[tx + 16 * a] * inv;  // c_i / d_j
 #pragma unroll
-            for (int b = 0; b < 8; ++b) ck[b] = buf[ty + 16 * b];
+            for (int b = 0; b < NB; ++b) ck[b] = buf[ty + 16 * b];
             if (ty == jt) {  // column j of L_BB and D
 #pragma unroll
-                for (int a = 0; a < 8; ++a) {
+                for (int a = 0; a < NB; ++a) {
                     const int i = tx + 16 * a;
                     if (i > j && i < s) F[i + (int64_t)j * ld] = ci[a];
                 }
@@ -599,9 +601,9 @@ __device__ void ldlt_sweep(const BlockDesc d, double* __restrict__ Lp, double* _
             }
             const bool ri = tx == jt, rk = ty == jt;  // this lane holds row j / column j
 #pragma unroll
-            for (int a = 0; a < 8; ++a)
+            for (int a = 0; a < NB; ++a)
 #pragma unroll
-                for (int b = 0; b < 8; ++b) {
+                for (int b = 0; b < NB; ++b) {
                     const double upd = M[a][b] - ci[a] * ck[b];
                     if (a == jb && b == jb) {
                         M[a][b] = (ri && rk) ? -inv : (ri ? ck[b] * inv : (rk ? ci[a] : upd));
@@ -617,9 +619,9 @@ __device__ void ldlt_sweep(const BlockDesc d, double* __restrict__ Lp, double* _
     }
     // T = -M, made exactly symmetric from the lower triangle
 #pragma unroll
-    for (int a = 0; a < 8; ++a)
+    for (int a = 0; a < NB; ++a)
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
+        for (int b = 0; b < NB; ++b) {
             const int i = tx + 16 * a, k = ty + 16 * b;
             if (i < s && k < s && i >= k) {
                 T[i + (int64_t)k * s] = -M[a][b];
@@ -628,90 +630,221 @@ __device__ void ldlt_sweep(const BlockDesc d, double* __restrict__ Lp, double* _
         }
 }
 
+// one launch per width class: NB = 2, 4, 8 for s <= 32, 64, 128; wider
+// blocks take ldlt_global
+template <int NB>
 __global__ __launch_bounds__(kThreads) void k_ldlt_diag(const Task* __restrict__ tasks,
                                                         const BlockDesc* __restrict__ blk, double* __restrict__ Lp,
                                                         double* __restrict__ Wp, double* __restrict__ Tp,
                                                         unsigned long long* __restrict__ status, int require_spd)
 {
-    extern __shared__ double S[];
+    __shared__ double colbuf[2][kLdsDiagMax];
     const Task t = tasks[blockIdx.x];
     const BlockDesc d = blk[t.b];
-    const int s = d.s;
-    if (s > kLdsDiagMax) {
-        ldlt_global(d, Lp, Wp, Tp, status, require_spd);
-        return;
-    }
-    if (kUseSweep) {
-        ldlt_sweep(d, Lp, Tp, status, require_spd, reinterpret_cast<double(*)[kLdsDiagMax]>(S));
-        return;
-    }
-    const int64_t ld = (int64_t)d.s + d.c;
+    if (d.s > 16 * NB) ldlt_global(d, Lp, Wp, Tp, status, require_spd);
+    else ldlt_sweep<NB>(d, Lp, Tp, status, require_spd, colbuf);
+}
+
+// ===========================================================================
+// Small blocks (s <= 16, c <= 256): one wave runs a whole block, every phase
+// in turn, on 16 x 16 FP64 MFMA tiles (output rows in groups of 16, the
+// contraction in steps of 4), so a block needs no other wave and no
+// work-group barrier.  Per wave, LDS holds the s x s diagonal block during
+// its sweep (then T = -M) and one 16 x 16 tile for transposition.
+//   factor:  sweep F_BB -> L_BB, D, T;  per row group I of C: L_hat(I,:) =
+//            F(I,B) T, then for every row group K <= I the Schur tile
+//            -L_hat(I,:) F(K,:)^T added into the ancestors (lower part);
+//   invert:  per row group I: X(I,:) = -G(I,:) L_hat, written to Ainv(C,B),
+//            and P += L_hat(I,:)^T X(I,:) straight from the accumulators;
+//            then Ainv(B,B) = ((T - P) + (T - P)^T) / 2 on the lower triangle.
+// ===========================================================================
+struct SbLds {
+    double M[16][17];
+    double L[16][17];
+};
+
+// LDS written by some lanes of a wave, then read by others
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__device__ void sb_factor(const BlockDesc d, double* __restrict__ Lp, double* __restrict__ Hp,
+                          double* __restrict__ Tp, const int64_t* __restrict__ cbase,
+                          const int64_t* __restrict__ rbase, const int32_t* __restrict__ rel,
+                          unsigned long long* __restrict__ status, int require_spd, SbLds& S)
+{
+    const int lane = threadIdx.x & 63;
+    const int s = d.s, c = d.c;
+    const int64_t ld = (int64_t)s + c;
     double* F = Lp + d.poff;
-    const int ls = s + 1;
-    const int tid = threadIdx.x;
-    for (int e = tid; e < s * s; e += kThreads) {
-        const int i = e % s, k = e / s;
-        S[i * ls + k] = (k <= i) ? F[i + k * ld] : 0.0;
+    // diagonal block: symmetric Gauss-Jordan sweep (as in ldlt_sweep), lane
+    // holds entries (e & 15, e >> 4) for e = lane + 64 q
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int e = lane + 64 * q, i = e & 15, k = e >> 4;
+        S.M[i][k] = (i < s && k < s) ? (i >= k ? F[i + k * ld] : F[k + i * ld]) : 0.0;
     }
-    __syncthreads();
+    wave_sync();
     for (int j = 0; j < s; ++j) {
-        const double dj = S[j * ls + j];
-        if (tid == 0) {
-            const bool ok = isfinite(dj) && dj != 0.0 && (!require_spd || dj > 0.0);
-            if (!ok) atomicMin(status, (unsigned long long)(d.first + j));
+        const double dj = S.M[j][j];
+        const double inv = 1.0 / dj;
+        double nv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = lane + 64 * q, i = e & 15, k = e >> 4;
+            const double ci = S.M[i][j], ck = S.M[k][j], m = S.M[i][k];
+            nv[q] = (i == j && k == j) ? -inv : (i == j ? ck * inv : (k == j ? ci * inv : m - ci * ck * inv));
         }
-        const int rows = s - j - 1;
-        for (int e = tid; e < rows * s; e += kThreads) {
-            const int i = j + 1 + e / s, k = e % s;
-            if (k == j || k > i) continue;
-            const double lraw = S[i * ls + j];
-            if (k > j) S[i * ls + k] -= lraw * S[k * ls + j] / dj;  // trailing update of F
-            else S[k * ls + i] -= (lraw / dj) * S[k * ls + j];      // W(i,k) -= l_ij W(j,k)
+        const double cl = S.M[lane & 15][j];  // Schur-complement column j
+        wave_sync();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = lane + 64 * q, i = e & 15, k = e >> 4;
+            if (i < s && k < s) S.M[i][k] = nv[q];
         }
-        __syncthreads();
-        for (int i = j + 1 + tid; i < s; i += kThreads) {
-            const double l = S[i * ls + j] / dj;
-            S[i * ls + j] = l;
-            S[j * ls + i] = -l;  // W(i,j) = -l_ij
-        }
-        __syncthreads();
+        if (lane < s && lane > j) F[lane + j * ld] = cl * inv;  // L_BB(i, j)
+        if (lane == j) F[j + j * ld] = dj;                      // D_j
+        if (lane == 0 && !(isfinite(dj) && dj != 0.0 && (!require_spd || dj > 0.0)))
+            atomicMin(status, (unsigned long long)(d.first + j));
+        wave_sync();
     }
-    // write L_BB (with D) back and W = L^{-1}
-    double* W = Wp + d.woff;
-    for (int e = tid; e < s * s; e += kThreads) {
-        const int i = e % s, k = e / s;
-        if (k <= i) F[i + k * ld] = S[i * ls + k];
-        W[e] = (i == k) ? 1.0 : (i > k ? S[k * ls + i] : 0.0);
-    }
-    // T = W^T D^{-1} W on the lower 16 x 16 tiles, mirrored
+    // T = -M (the sweep keeps M exactly symmetric)
     double* T = Tp + d.woff;
-    const int lane = tid & 63, wave = tid >> 6;
-    const int nt = (s + 15) / 16;
-    auto Wv = [&](int k, int i) -> double {  // W(k, i)
-        if (k >= s || i >= s) return 0.0;
-        return k == i ? 1.0 : (k > i ? S[i * ls + k] : 0.0);
-    };
-    for (int p = wave; p < nt * (nt + 1) / 2; p += kThreads / 64) {
-        int I = 0;
-        while ((I + 1) * (I + 2) / 2 <= p) ++I;
-        const int J = p - I * (I + 1) / 2;
-        const int i0 = I * 16, j0 = J * 16;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int e = lane + 64 * q, i = e & 15, k = e >> 4;
+        if (i < s && k < s) T[i + (int64_t)k * s] = -S.M[i][k];
+    }
+    const double* FC = F + s;  // F(C,B)(i, k) = FC[i + k ld]
+    double* H = Hp + d.hoff;
+    const int m16 = lane & 15, q4 = lane >> 4;
+    for (int r0 = 0; r0 < c; r0 += 16) {
+        // L_hat(I,:) = F(I,B) T
         d4 acc = {0, 0, 0, 0};
-        for (int k4 = i0; k4 < s; k4 += 4) {  // W(k, i) = 0 for k < i, and i >= j
-            const int k = k4 + (lane >> 4);
-            const double dk = k < s ? S[k * ls + k] : 1.0;
-            acc = mfma(Wv(k, i0 + (lane & 15)), Wv(k, j0 + (lane & 15)) / dk, acc);
+        for (int k0 = 0; k0 < s; k0 += 4) {
+            const int kk = k0 + q4;
+            const double a = (r0 + m16 < c && kk < s) ? FC[(r0 + m16) + (int64_t)kk * ld] : 0.0;
+            const double b = (kk < s && m16 < s) ? -S.M[kk][m16] : 0.0;
+            acc = mfma(a, b, acc);
         }
         mfma_drain();
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int i = i0 + (lane >> 4) + 4 * v, j = j0 + (lane & 15);
-            if (i < s && j < s) {
-                T[i + j * s] = acc[v];
-                T[j + i * s] = acc[v];
+            const int row = r0 + q4 + 4 * v;
+            if (row < c && m16 < s) H[row + (int64_t)m16 * c] = acc[v];
+            S.L[q4 + 4 * v][m16] = acc[v];
+        }
+        wave_sync();
+        // Schur tiles (I, K), K <= I: F(C,C) -= L_hat(I,:) F(K,:)^T, lower part
+        for (int k0c = 0; k0c <= r0; k0c += 16) {
+            d4 u = {0, 0, 0, 0};
+            for (int t0 = 0; t0 < s; t0 += 4) {
+                const int kk = t0 + q4;
+                const double a = kk < s ? S.L[m16][kk] : 0.0;
+                const double b = (k0c + m16 < c && kk < s) ? FC[(k0c + m16) + (int64_t)kk * ld] : 0.0;
+                u = mfma(a, b, u);
+            }
+            mfma_drain();
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int ii = r0 + q4 + 4 * v, kk = k0c + m16;
+                if (ii < c && kk < c && ii >= kk) {
+                    const int64_t pk = d.coff + kk;
+                    unsafeAtomicAdd(Lp + cbase[pk] + rel[rbase[pk] + ii], -u[v]);
+                }
             }
         }
+        wave_sync();
     }
+}
+
+__device__ void sb_invert(const BlockDesc d, double* __restrict__ Ap, const double* __restrict__ Hp,
+                          const double* __restrict__ Tp, const int64_t* __restrict__ cbase,
+                          const int64_t* __restrict__ rbase, const int32_t* __restrict__ rel, SbLds& S)
+{
+    const int lane = threadIdx.x & 63;
+    const int s = d.s, c = d.c;
+    const int64_t ld = (int64_t)s + c;
+    const double* H = Hp + d.hoff;
+    const double* T = Tp + d.woff;
+    double* A = Ap + d.poff;
+    const int m16 = lane & 15, q4 = lane >> 4;
+    d4 p = {0, 0, 0, 0};  // P = L_hat^T X
+    for (int r0 = 0; r0 < c; r0 += 16) {
+        const int i = r0 + m16;
+        d4 acc = {0, 0, 0, 0};
+        for (int k0 = 0; k0 < c; k0 += 4) {
+            const int kk = k0 + q4;
+            double g = 0.0;
+            if (i < c && kk < c) {
+                const int64_t pc = d.coff + (i >= kk ? kk : i);
+                g = Ap[cbase[pc] + rel[rbase[pc] + (i >= kk ? i : kk)]];
+            }
+            const double b = (kk < c && m16 < s) ? H[kk + (int64_t)m16 * c] : 0.0;
+            acc = mfma(g, b, acc);
+        }
+        mfma_drain();
+        // acc[v] = (G L_hat)(r0 + q4 + 4v, m16): X = -acc
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = r0 + q4 + 4 * v;
+            if (row < c && m16 < s) A[s + row + (int64_t)m16 * ld] = -acc[v];
+        }
+        // P += L_hat(I,:)^T X(I,:): B(kk, n) = X(r0 + 4t + kk, n) is -acc[t] of this lane
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int row = r0 + 4 * t + q4;
+            const double a = (row < c && m16 < s) ? H[row + (int64_t)m16 * c] : 0.0;
+            p = mfma(a, -acc[t], p);
+        }
+    }
+    mfma_drain();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) S.M[q4 + 4 * v][m16] = p[v];
+    wave_sync();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int e = lane + 64 * q, ii = e & 15, jj = e >> 4;
+        if (ii < s && jj < s && ii >= jj)
+            A[ii + (int64_t)jj * ld] = 0.5 * ((T[ii + (int64_t)jj * s] - S.M[ii][jj]) + (T[jj + (int64_t)ii * s] - S.M[jj][ii]));
+    }
+    wave_sync();
+}
+
+// Per-level launches of the small-block path: task q holds up to four block
+// ids (b, i0, j0, bn; -1 = none), one per wave.
+__device__ __forceinline__ int sb_block_of(const Task& t)
+{
+    const int w = threadIdx.x >> 6;
+    return w == 0 ? t.b : w == 1 ? t.i0 : w == 2 ? t.j0 : t.bn;
+}
+
+__global__ __launch_bounds__(kThreads) void k_sb_factor(const Task* __restrict__ tasks,
+                                                        const BlockDesc* __restrict__ blk, double* __restrict__ Lp,
+                                                        double* __restrict__ Hp, double* __restrict__ Tp,
+                                                        const int64_t* __restrict__ cbase,
+                                                        const int64_t* __restrict__ rbase,
+                                                        const int32_t* __restrict__ rel,
+                                                        unsigned long long* __restrict__ status, int require_spd)
+{
+    __shared__ SbLds S[kThreads / 64];
+    const int b = sb_block_of(tasks[blockIdx.x]);
+    if (b >= 0) sb_factor(blk[b], Lp, Hp, Tp, cbase, rbase, rel, status, require_spd, S[threadIdx.x >> 6]);
+}
+
+__global__ __launch_bounds__(kThreads) void k_sb_invert(const Task* __restrict__ tasks,
+                                                        const BlockDesc* __restrict__ blk, double* __restrict__ Ap,
+                                                        const double* __restrict__ Hp, const double* __restrict__ Tp,
+                                                        const int64_t* __restrict__ cbase,
+                                                        const int64_t* __restrict__ rbase,
+                                                        const int32_t* __restrict__ rel)
+{
+    __shared__ SbLds S[kThreads / 64];
+    const int b = sb_block_of(tasks[blockIdx.x]);
+    if (b >= 0) sb_invert(blk[b], Ap, Hp, Tp, cbase, rbase, rel, S[threadIdx.x >> 6]);
 }
 
 // ===========================================================================
@@ -730,7 +863,9 @@ union PersistLds {
     TileLds tile;
     SdiagLds sd;
     double colbuf[2][kLdsDiagMax];
+    SbLds sb[kThreads / 64];
 };
+
 
 struct QueueArgs {
     const Task* q;
@@ -798,6 +933,54 @@ __device__ __forceinline__ void signal_done(const QueueArgs& a, const Task& t)
     if (threadIdx.x == 0) __hip_atomic_fetch_add(a.done + t.b, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// diagonal block of a tiled level: the host keeps s <= 16 NB, or NB = 8
+template <int NB>
+__device__ __forceinline__ void diag_block(const BlockDesc& d, double* Lp, double* Wp, double* Tp,
+                                           unsigned long long* status, int require_spd, double (*colbuf)[kLdsDiagMax])
+{
+    if constexpr (NB == 8) {
+        if (d.s > kLdsDiagMax) {
+            ldlt_global(d, Lp, Wp, Tp, status, require_spd);
+            return;
+        }
+    }
+    ldlt_sweep<NB>(d, Lp, Tp, status, require_spd, colbuf);
+}
+
+// L_hat tile; tiles are at most as wide as the level's widest block
+template <int NB>
+__device__ __forceinline__ void panel_bounded(TileLds& L, const Task& t, const BlockDesc& d, const double* Lp,
+                                              double* Hp, const double* Tp)
+{
+    if (t.bn <= 16) {
+        panel_task<16>(L, t, d, Lp, Hp, Tp);
+    } else if (t.bn <= 32) {
+        panel_task<32>(L, t, d, Lp, Hp, Tp);
+    } else if constexpr (NB >= 4) {
+        if (t.bn <= 64) panel_task<64>(L, t, d, Lp, Hp, Tp);
+        else if constexpr (NB >= 8) panel_task<128>(L, t, d, Lp, Hp, Tp);
+    }
+}
+
+// gather-GEMM tile; the host keeps t.bn <= BNMAX in this variant's levels
+template <int BNMAX>
+__device__ __forceinline__ void gemm_bounded(TileLds& L, const Task& t, const BlockDesc& d, double* Ap,
+                                             const double* Hp, const int64_t* cbase, const int64_t* rbase,
+                                             const int32_t* rel)
+{
+    if (t.bn <= 16) {
+        gemm_task<16>(L, t, d, Ap, Hp, cbase, rbase, rel);
+    } else if (t.bn <= 32) {
+        gemm_task<32>(L, t, d, Ap, Hp, cbase, rbase, rel);
+    } else if constexpr (BNMAX >= 64) {
+        if (t.bn <= 64) gemm_task<64>(L, t, d, Ap, Hp, cbase, rbase, rel);
+        else if constexpr (BNMAX >= 128) gemm_task<128>(L, t, d, Ap, Hp, cbase, rbase, rel);
+    }
+}
+
+// Levels with tiled blocks; NB bounds the diagonal sweep (s <= 16 NB, wider
+// blocks take ldlt_global) and so the kernel's registers.
+template <int NB>
 __global__ __launch_bounds__(kThreads) void k_persist_factor(const QueueArgs a, const BlockDesc* __restrict__ blk,
                                                              double* __restrict__ Lp, double* __restrict__ Wp,
                                                              double* __restrict__ Hp, double* __restrict__ Tp,
@@ -813,57 +996,159 @@ __global__ __launch_bounds__(kThreads) void k_persist_factor(const QueueArgs a, 
         const int idx = claim(a, &s_idx);
         if (idx >= a.ntasks) break;
         const Task t = uniform_task(a.q, idx);
-        const BlockDesc d = blk[t.b];
-        wait_deps(a, t);
-        switch (t.flags >> 8) {
-            case qLdlt:
-                if (d.s > kLdsDiagMax) ldlt_global(d, Lp, Wp, Tp, a.status, a.require_spd);
-                else ldlt_sweep(d, Lp, Tp, a.status, a.require_spd, sm.colbuf);
-                break;
-            case qPanel:
-#define SELINV_CALL(BN) panel_task<BN>(sm.tile, t, d, Lp, Hp, Tp)
-                SELINV_BN_DISPATCH(t.bn, SELINV_CALL)
-#undef SELINV_CALL
-                break;
-            default:
-                schur_task(sm.tile, t, d, Lp, Hp, cbase, rbase, rel);
-                break;
+        const int op = t.flags >> 8;
+        if (op == qSbFactor) {
+            const int b = sb_block_of(t);
+            if (b >= 0)
+                sb_factor(blk[b], Lp, Hp, Tp, cbase, rbase, rel, a.status, a.require_spd, sm.sb[threadIdx.x >> 6]);
+            __syncthreads();  // the LDS union is reused by the next task
+            continue;
         }
-        signal_done(a, t);
+        const BlockDesc d = blk[t.b];
+        // a medium block runs its diagonal block, L_hat tiles and Schur tiles
+        // here in turn (one call site per routine keeps registers down)
+        const bool whole = op == qMbFactor;
+        if (!whole) wait_deps(a, t);
+        const int nrow = (d.c + kTileM - 1) / kTileM, ncol = whole ? (d.s + t.bn - 1) / t.bn : 0;
+        const int nsc = (d.c + kSchurTile - 1) / kSchurTile;
+        const int steps = whole ? 1 + nrow * ncol + nsc * (nsc + 1) / 2 : 1;
+        int pr = 0, pj = 0, si = 0, sk = 0;  // next panel tile (row, column), Schur tile (row, column)
+        for (int st = 0; st < steps; ++st) {
+            int o = op;
+            Task u = t;
+            if (whole) {
+                if (st == 0) {
+                    o = qLdlt;
+                } else if (st <= nrow * ncol) {
+                    o = qPanel;
+                    u = Task{t.b, pr * kTileM, pj * t.bn, t.bn, 0, d.s, 0, 0};
+                    if (++pr == nrow) pr = 0, ++pj;
+                } else {
+                    o = qSchur;
+                    u = Task{t.b, si * kSchurTile, sk * kSchurTile, kSchurTile, 0, d.s, 0, 0};
+                    if (++si == nsc) si = ++sk;
+                }
+            }
+            switch (o) {
+                case qLdlt:
+                    diag_block<NB>(d, Lp, Wp, Tp, a.status, a.require_spd, sm.colbuf);
+                    break;
+                case qPanel:
+                    panel_bounded<NB>(sm.tile, u, d, Lp, Hp, Tp);
+                    break;
+                default:
+                    schur_task(sm.tile, u, d, Lp, Hp, cbase, rbase, rel);
+                    break;
+            }
+            if (whole) __syncthreads();
+        }
+        if (!whole && (t.flags & 2)) signal_done(a, t);
+        else __syncthreads();
     }
 }
 
+// Levels with tiled blocks; BNMAX bounds the gather-GEMM tile width and so
+// the kernel's registers.
+template <int BNMAX>
 __global__ __launch_bounds__(kThreads, 2) void k_persist_invert(const QueueArgs a, const BlockDesc* __restrict__ blk,
-                                                             double* __restrict__ Ap, const double* __restrict__ Hp,
-                                                             const double* __restrict__ Tp,
-                                                             const int64_t* __restrict__ cbase,
-                                                             const int64_t* __restrict__ rbase,
-                                                             const int32_t* __restrict__ rel)
+                                                                double* __restrict__ Ap, const double* __restrict__ Hp,
+                                                                const double* __restrict__ Tp,
+                                                                const int64_t* __restrict__ cbase,
+                                                                const int64_t* __restrict__ rbase,
+                                                                const int32_t* __restrict__ rel)
 {
     __shared__ PersistLds sm;
     __shared__ int s_idx;
-    // a work-group cannot claim more than ntasks entries: the bound only
-    // makes termination evident
     for (int64_t it = 0; it < a.ntasks; ++it) {
         const int idx = claim(a, &s_idx);
         if (idx >= a.ntasks) break;
         const Task t = uniform_task(a.q, idx);
-        const BlockDesc d = blk[t.b];
-        wait_deps(a, t);
-        switch (t.flags >> 8) {
-            case qZero:
-                zero_task(d, Ap, Tp);
-                break;
-            case qGemm:
-#define SELINV_CALL(BN) gemm_task<BN>(sm.tile, t, d, Ap, Hp, cbase, rbase, rel)
-                SELINV_BN_DISPATCH(t.bn, SELINV_CALL)
-#undef SELINV_CALL
-                break;
-            default:
-                sdiag_task(sm.sd, t, d, Ap, Hp, Tp);
-                break;
+        const int op = t.flags >> 8;
+        if (op == qSbInvert) {
+            const int b = sb_block_of(t);
+            if (b >= 0) sb_invert(blk[b], Ap, Hp, Tp, cbase, rbase, rel, sm.sb[threadIdx.x >> 6]);
+            __syncthreads();
+            continue;
         }
-        signal_done(a, t);
+        const BlockDesc d = blk[t.b];
+        // a medium block runs its X tiles (whole contractions) and then its
+        // diagonal tiles here in turn
+        const bool whole = op == qMbInvert;
+        if (!whole) wait_deps(a, t);
+        const int nrow = (d.c + kTileM - 1) / kTileM, ncol = whole ? (d.s + t.bn - 1) / t.bn : 0;
+        const int nd = (d.s + kDiagTile - 1) / kDiagTile;
+        const int steps = whole ? nrow * ncol + nd * (nd + 1) / 2 : 1;
+        int gr = 0, gj = 0, di = 0, dj = 0;  // next X tile (row, column), diagonal tile pair (I, J)
+        for (int st = 0; st < steps; ++st) {
+            int o = op;
+            Task u = t;
+            if (whole) {
+                if (st < nrow * ncol) {
+                    o = qGemm;
+                    u = Task{t.b, gr * kTileM, gj * t.bn, t.bn, 0, d.c, 0, 0};
+                    if (++gr == nrow) gr = 0, ++gj;
+                } else {
+                    o = qSdiag;
+                    u = Task{t.b, di * kDiagTile, dj * kDiagTile, 0, 0, d.c, 0, 0};
+                    if (++dj > di) dj = 0, ++di;
+                }
+            }
+            switch (o) {
+                case qZero:
+                    zero_task(d, Ap, Tp);
+                    break;
+                case qGemm:
+                    gemm_bounded<BNMAX>(sm.tile, u, d, Ap, Hp, cbase, rbase, rel);
+                    break;
+                default:
+                    sdiag_task(sm.sd, u, d, Ap, Hp, Tp);
+                    break;
+            }
+            if (whole) __syncthreads();
+        }
+        if (!whole && (t.flags & 2)) signal_done(a, t);
+        else __syncthreads();
+    }
+}
+
+// Levels made only of small blocks: no dependencies, so no queue head
+// either.  Wave g of W takes slots g, g + W, g + 2W, ... (slot = 4 task +
+// wave field) of the level's cost-ordered list, so every wave gets a like
+// mix; no atomics, no work-group barrier.
+__device__ __forceinline__ int slot_block(const QueueArgs& a, int64_t slot)
+{
+    const int32_t* ids = reinterpret_cast<const int32_t*>(a.q + slot / kSbPerTask);
+    return __builtin_amdgcn_readfirstlane(ids[slot % kSbPerTask]);
+}
+
+__global__ __launch_bounds__(kThreads) void k_light_factor(const QueueArgs a, const BlockDesc* __restrict__ blk,
+                                                           double* __restrict__ Lp, double* __restrict__ Hp,
+                                                           double* __restrict__ Tp, const int64_t* __restrict__ cbase,
+                                                           const int64_t* __restrict__ rbase,
+                                                           const int32_t* __restrict__ rel)
+{
+    __shared__ SbLds S[kThreads / 64];
+    const int64_t nslots = a.ntasks * kSbPerTask;
+    const int64_t nw = (int64_t)gridDim.x * (kThreads / 64);
+    for (int64_t slot = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); slot < nslots; slot += nw) {
+        const int b = slot_block(a, slot);
+        if (b >= 0) sb_factor(blk[b], Lp, Hp, Tp, cbase, rbase, rel, a.status, a.require_spd, S[threadIdx.x >> 6]);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_light_invert(const QueueArgs a, const BlockDesc* __restrict__ blk,
+                                                           double* __restrict__ Ap, const double* __restrict__ Hp,
+                                                           const double* __restrict__ Tp,
+                                                           const int64_t* __restrict__ cbase,
+                                                           const int64_t* __restrict__ rbase,
+                                                           const int32_t* __restrict__ rel)
+{
+    __shared__ SbLds S[kThreads / 64];
+    const int64_t nslots = a.ntasks * kSbPerTask;
+    const int64_t nw = (int64_t)gridDim.x * (kThreads / 64);
+    for (int64_t slot = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); slot < nslots; slot += nw) {
+        const int b = slot_block(a, slot);
+        if (b >= 0) sb_invert(blk[b], Ap, Hp, Tp, cbase, rbase, rel, S[threadIdx.x >> 6]);
     }
 }
 
@@ -1280,13 +1565,8 @@ static inline unsigned grid_for(int64_t n)
 
 hipError_t kernels_init()
 {
-    // the LDS diagonal factorization and the reverse diagonal step need more
-    // than the default 64 KB of LDS
-    hipError_t e = hipFuncSetAttribute((const void*)k_ldlt_diag, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)kLdsDiagBytes);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void*)k_rf3, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsDiagBytes);
-    return e;
+    // the reverse diagonal step needs more than the default 64 KB of LDS
+    return hipFuncSetAttribute((const void*)k_rf3, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsDiagBytes);
 }
 
 hipError_t launch_backward_init(Prof* P, const DevPtrs& D, int64_t arena, int64_t harena, const double* gsel,
@@ -1380,12 +1660,36 @@ hipError_t launch_export_L(Prof* P, const DevPtrs& D, int64_t n, double* out, hi
     return hipGetLastError();
 }
 
-hipError_t launch_factor_level(Prof* P, const DevPtrs& D, int64_t diag0, int64_t ndiag, int64_t panel0,
-                               int64_t npanel, int64_t schur0, int64_t nschur, int require_spd, hipStream_t s)
+hipError_t launch_sb_factor(Prof* P, const DevPtrs& D, int64_t sb0, int64_t nsb, int require_spd, hipStream_t s)
 {
-    if (ndiag > 0)
-        launch(P, kLdlt, k_ldlt_diag, dim3((unsigned)ndiag), kDiagShmem, s, D.t_diag + diag0, D.blocks, D.Lp,
-               D.Wp, D.Tp, D.status, require_spd);
+    if (nsb > 0)
+        launch(P, kSbFactor, k_sb_factor, dim3((unsigned)nsb), 0, s, D.t_sb + sb0, D.blocks, D.Lp, D.Hp, D.Tp, D.cbase,
+               D.rbase, D.rel, D.status, require_spd);
+    return hipGetLastError();
+}
+
+hipError_t launch_sb_invert(Prof* P, const DevPtrs& D, int64_t sb0, int64_t nsb, hipStream_t s)
+{
+    if (nsb > 0)
+        launch(P, kSbInvert, k_sb_invert, dim3((unsigned)nsb), 0, s, D.t_sb + sb0, D.blocks, D.Ap, (const double*)D.Hp,
+               (const double*)D.Tp, D.cbase, D.rbase, D.rel);
+    return hipGetLastError();
+}
+
+hipError_t launch_factor_level(Prof* P, const DevPtrs& D, const int64_t diag[4], int64_t panel0, int64_t npanel,
+                               int64_t schur0, int64_t nschur, int require_spd, hipStream_t s)
+{
+    // diagonal blocks by width class: [diag[0], diag[1]) s <= 32, then <= 64,
+    // then wider
+    if (diag[1] > diag[0])
+        launch(P, kLdlt, k_ldlt_diag<2>, dim3((unsigned)(diag[1] - diag[0])), 0, s, D.t_ldlt + diag[0], D.blocks,
+               D.Lp, D.Wp, D.Tp, D.status, require_spd);
+    if (diag[2] > diag[1])
+        launch(P, kLdlt, k_ldlt_diag<4>, dim3((unsigned)(diag[2] - diag[1])), 0, s, D.t_ldlt + diag[1], D.blocks,
+               D.Lp, D.Wp, D.Tp, D.status, require_spd);
+    if (diag[3] > diag[2])
+        launch(P, kLdlt, k_ldlt_diag<8>, dim3((unsigned)(diag[3] - diag[2])), 0, s, D.t_ldlt + diag[2], D.blocks,
+               D.Lp, D.Wp, D.Tp, D.status, require_spd);
     if (npanel > 0)
         launch(P, kPanel, k_panel, dim3((unsigned)npanel), 0, s, D.t_panel + panel0, D.blocks,
                (const double*)D.Lp, D.Hp, (const double*)D.Tp);
@@ -1408,10 +1712,16 @@ hipError_t launch_invert_level(Prof* P, const DevPtrs& D, int64_t gemm0, int64_t
 }
 
 
-hipError_t persist_occupancy(int* occ_factor, int* occ_invert)
+// resident work-groups per CU of each persistent variant, in the order of
+// selinv::PersistVariant
+hipError_t persist_occupancy(int occ[kNumVariants])
 {
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(occ_factor, k_persist_factor, kThreads, 0);
-    if (!e) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(occ_invert, k_persist_invert, kThreads, 0);
+    const void* k[kNumVariants] = {(const void*)k_light_factor,       (const void*)k_persist_factor<2>,
+                                   (const void*)k_persist_factor<4>,  (const void*)k_persist_factor<8>,
+                                   (const void*)k_light_invert,       (const void*)k_persist_invert<32>,
+                                   (const void*)k_persist_invert<64>, (const void*)k_persist_invert<128>};
+    hipError_t e = hipSuccess;
+    for (int v = 0; v < kNumVariants && !e; v++) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(occ + v, k[v], kThreads, 0);
     return e;
 }
 
@@ -1423,23 +1733,41 @@ hipError_t launch_fill_u32(Prof* P, int kind, unsigned* p, int64_t n, hipStream_
 }
 
 hipError_t launch_persist_factor(Prof* P, const DevPtrs& D, const Task* q, int64_t ntasks, unsigned* head,
-                                 unsigned* done, int grid, int require_spd, unsigned spin_limit, hipStream_t s)
+                                 unsigned* done, int grid, int variant, int require_spd, unsigned spin_limit,
+                                 hipStream_t s)
 {
     if (ntasks <= 0) return hipSuccess;
     const QueueArgs a{q, ntasks, head, done, D.status, require_spd, spin_limit};
     const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(grid, ntasks));
-    launch(P, kQFactor, k_persist_factor, dim3(g), 0, s, a, D.blocks, D.Lp, D.Wp, D.Hp, D.Tp, D.cbase, D.rbase, D.rel);
+#define SELINV_PF(K) launch(P, kQFactor, K, dim3(g), 0, s, a, D.blocks, D.Lp, D.Wp, D.Hp, D.Tp, D.cbase, D.rbase, D.rel)
+    switch (variant) {
+        case kLightFactor:
+            launch(P, kQFactor, k_light_factor, dim3(g), 0, s, a, D.blocks, D.Lp, D.Hp, D.Tp, D.cbase, D.rbase, D.rel);
+            break;
+        case kFactor32: SELINV_PF(k_persist_factor<2>); break;
+        case kFactor64: SELINV_PF(k_persist_factor<4>); break;
+        default: SELINV_PF(k_persist_factor<8>); break;
+    }
+#undef SELINV_PF
     return hipGetLastError();
 }
 
 hipError_t launch_persist_invert(Prof* P, const DevPtrs& D, const Task* q, int64_t ntasks, unsigned* head,
-                                 unsigned* done, int grid, unsigned spin_limit, hipStream_t s)
+                                 unsigned* done, int grid, int variant, unsigned spin_limit, hipStream_t s)
 {
     if (ntasks <= 0) return hipSuccess;
     const QueueArgs a{q, ntasks, head, done, D.status, 0, spin_limit};
     const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(grid, ntasks));
-    launch(P, kQInvert, k_persist_invert, dim3(g), 0, s, a, D.blocks, D.Ap, (const double*)D.Hp, (const double*)D.Tp,
-           D.cbase, D.rbase, D.rel);
+#define SELINV_PI(K)                                                                                              \
+    launch(P, kQInvert, K, dim3(g), 0, s, a, D.blocks, D.Ap, (const double*)D.Hp, (const double*)D.Tp, D.cbase, \
+           D.rbase, D.rel)
+    switch (variant) {
+        case kLightInvert: SELINV_PI(k_light_invert); break;
+        case kInvert32: SELINV_PI(k_persist_invert<32>); break;
+        case kInvert64: SELINV_PI(k_persist_invert<64>); break;
+        default: SELINV_PI(k_persist_invert<128>); break;
+    }
+#undef SELINV_PI
     return hipGetLastError();
 }
 

@@ -21,7 +21,7 @@ struct DevPtrs {
     const int64_t *asm_off, *exp_off;
     const int32_t* colblk;     // column -> execution block
     const int64_t* colptrL;    // canonical column pointers of L
-    const Task *t_diag, *t_panel, *t_schur, *t_gemm, *t_sdiag, *t_zero;
+    const Task *t_diag, *t_ldlt, *t_panel, *t_schur, *t_gemm, *t_sdiag, *t_zero, *t_sb;
     const Task *t_rs1, *t_rs2, *t_rs3, *t_rf1a, *t_rf1b, *t_rf2;
 };
 
@@ -41,17 +41,22 @@ hipError_t launch_scatter_set(Prof* P, int kind, const double* src, const int64_
                               hipStream_t s);
 hipError_t launch_gather(Prof* P, int kind, const double* src, const int64_t* off, int64_t n, double* dst,
                          hipStream_t s);
-hipError_t launch_factor_level(Prof* P, const DevPtrs& D, int64_t diag0, int64_t ndiag, int64_t panel0,
-                               int64_t npanel, int64_t schur0, int64_t nschur, int require_spd, hipStream_t s);
+// diag[0..3]: the level's diagonal-block tasks for s <= 32, <= 64 and wider
+hipError_t launch_factor_level(Prof* P, const DevPtrs& D, const int64_t diag[4], int64_t panel0, int64_t npanel,
+                               int64_t schur0, int64_t nschur, int require_spd, hipStream_t s);
 hipError_t launch_invert_level(Prof* P, const DevPtrs& D, int64_t gemm0, int64_t ngemm, int64_t sdiag0,
                                int64_t nsdiag, hipStream_t s);
 // persistent work-queue kernels: resident work-groups per CU, and one
 // level's launch over ntasks queue entries at q
-hipError_t persist_occupancy(int* occ_factor, int* occ_invert);
+hipError_t persist_occupancy(int occ[kNumVariants]);
 hipError_t launch_fill_u32(Prof* P, int kind, unsigned* p, int64_t n, hipStream_t s);
 hipError_t launch_persist_factor(Prof* P, const DevPtrs& D, const Task* q, int64_t ntasks, unsigned* head,
-                                 unsigned* done, int grid, int require_spd, unsigned spin_limit, hipStream_t s);
+                                 unsigned* done, int grid, int variant, int require_spd, unsigned spin_limit,
+                                 hipStream_t s);
 hipError_t launch_persist_invert(Prof* P, const DevPtrs& D, const Task* q, int64_t ntasks, unsigned* head,
-                                 unsigned* done, int grid, unsigned spin_limit, hipStream_t s);
+                                 unsigned* done, int grid, int variant, unsigned spin_limit, hipStream_t s);
+// small-block path of one level (per-level launches)
+hipError_t launch_sb_factor(Prof* P, const DevPtrs& D, int64_t sb0, int64_t nsb, int require_spd, hipStream_t s);
+hipError_t launch_sb_invert(Prof* P, const DevPtrs& D, int64_t sb0, int64_t nsb, hipStream_t s);
 
 }  // namespace selinv

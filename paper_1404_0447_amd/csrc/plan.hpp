@@ -55,7 +55,12 @@ struct LevelTasks {
 // sits in bits 8..15 of flags and `pad` holds the number of earlier tasks of
 // the same block that must have finished first (its dependencies: the
 // phases of one block run in the order below).
-enum QOp { qLdlt = 0, qPanel, qSchur, qZero, qGemm, qSdiag };
+// Flags bit 1: other tasks of the level wait for this one (it signals its
+// block's counter).  Small-block tasks (qSbFactor, qSbInvert) carry up to
+// four block ids in b, i0, j0, bn (-1 = none), one per wave; medium-block
+// tasks (qMbFactor, qMbInvert) run one block's every phase on one
+// work-group, tile after tile.  Neither kind waits nor signals.
+enum QOp { qLdlt = 0, qPanel, qSchur, qZero, qGemm, qSdiag, qSbFactor, qSbInvert, qMbFactor, qMbInvert };
 inline int32_t q_flags(int op, int f) { return (op << 8) | f; }
 
 // Schedule of the persistent path (chosen by the autotuner).
@@ -64,12 +69,23 @@ struct Sched {
     int32_t bn_cap = 128;     // widest output tile of the gather-GEMM / panel
     int32_t split_fill = 512; // split contractions when a level has fewer tiles (0: never)
     int32_t grid_mult = 2;    // resident work-groups per CU
+    int32_t small_s = 16;     // blocks with s <= small_s (and |C| <= kSbC) run whole on one wave (0: none)
+    int32_t mb_tiles = 8;     // other blocks with at most this many X tiles run whole on one work-group
 };
 enum QOrder { qoPlan = 0, qoLpt = 1, qoRoundRobin = 2, qoTileLpt = 3, qoNumOrders };
 
+// Persistent kernel variants, chosen per level: only small blocks (light,
+// wave-granular), else bounded by the widest diagonal block (factor) or
+// output tile (inversion) of the level.
+enum PersistVariant {
+    kLightFactor = 0, kFactor32, kFactor64, kFactor128,
+    kLightInvert, kInvert32, kInvert64, kInvert128, kNumVariants
+};
+
 // Kernel kinds (same numbering as SELINV_K_* in selinv.h).
 enum Kind {
-    kAssemble = 0, kLdlt, kPanel, kSchur, kGemm, kSdiag, kExport, kRevSel, kRevFac, kQFactor, kQInvert, kNumKinds
+    kAssemble = 0, kLdlt, kPanel, kSchur, kGemm, kSdiag, kExport, kRevSel, kRevFac, kQFactor, kQInvert, kSbFactor,
+    kSbInvert, kNumKinds
 };
 
 // Optional per-launch timing: start/stop events are stamped by the dispatch
@@ -86,7 +102,7 @@ struct Prof {
 struct DeviceLayout {
     // byte offsets into the workspace
     size_t lp, ap, hp, wp, tp, status, blocks, crow, cbase, rbase, rel, asm_off, exp_off, colblk, colptrL;
-    size_t t_diag, t_panel, t_schur, t_gemm, t_sdiag, t_zero;
+    size_t t_diag, t_ldlt, t_panel, t_schur, t_gemm, t_sdiag, t_zero, t_sb;
     size_t zb, hb, tb;  // adjoint arenas (backward)
     size_t t_rs1, t_rs2, t_rs3, t_rf1a, t_rf1b, t_rf2;
     size_t q_fac, q_inv, q_done, q_head;  // persistent path: queues, counters
@@ -115,7 +131,11 @@ struct selinv_plan_s {
     std::vector<int64_t> asm_off, exp_off;
     std::vector<int32_t> colblk;       // column -> execution block
     int64_t arena = 0, harena = 0, warena = 0;
-    selinv::LevelTasks t_diag, t_panel, t_schur, t_gemm, t_sdiag;
+    // forward, per level: small blocks (t_sb, four per task), and the tiled
+    // path of the others (t_ldlt, t_panel, t_schur, t_gemm, t_sdiag, t_zero);
+    // t_diag lists every block (used by the reverse sweep)
+    selinv::LevelTasks t_diag, t_ldlt, t_panel, t_schur, t_gemm, t_sdiag, t_sb;
+    std::vector<int64_t> ldlt_cut;     // per level: t_ldlt splits into s <= 32 | <= 64 | wider at 2l, 2l+1
     // reverse sweep: selected inversion (leaves first) and factorization (root first)
     selinv::LevelTasks t_rs1, t_rs2, t_rs3, t_rf1a, t_rf1b, t_rf2;
     std::vector<selinv::Task> t_zero;  // blocks whose X accumulates over split contractions
@@ -138,7 +158,9 @@ struct selinv_plan_s {
     const void* graph_in = nullptr;
     void* graph_out = nullptr;
     hipStream_t cap_stream = nullptr;
-    int n_cu = 0, occ_fac = 1, occ_inv = 1;  // device of the bound workspace
+    int n_cu = 0;                           // device of the bound workspace
+    int occ[selinv::kNumVariants] = {1, 1, 1, 1, 1, 1, 1, 1};  // resident work-groups per CU, per variant
+    std::vector<uint8_t> q_var_fac, q_var_inv;                  // per level: the PersistVariant to launch
     std::string dev_arch;
     unsigned spin_limit = 1u << 22;         // polls of a dependency wait before it is abandoned
     // binding state
@@ -164,8 +186,8 @@ void build_schedule(selinv_plan_s* P);
 // tasks qi[...], each level's tasks in phase order.
 void build_queues(const selinv_plan_s* P, const Sched& sc, std::vector<Task>& qf, std::vector<int64_t>& qf_off,
                   std::vector<Task>& qi, std::vector<int64_t>& qi_off);
-// number of factor / inversion queue entries build_queues makes for `sc`
-void queue_sizes(const selinv_plan_s* P, const Sched& sc, int64_t& nfac, int64_t& ninv);
+// upper bound on the factor / inversion queue entries of any schedule
+void queue_bound(const selinv_plan_s* P, int64_t& nfac, int64_t& ninv);
 // batch.cpp: merge independently analysed plans into their block-diagonal union
 void merge_plans(const std::vector<selinv_plan_s*>& parts, selinv_plan_s* U);
 }  // namespace selinv

@@ -41,76 +41,118 @@ static int split_for(int64_t want, int len)
     return (int)std::min<int64_t>(want, maxsplit);
 }
 
+// small blocks of a level in groups of four (one per wave of a work-group)
+static void push_sb_groups(const std::vector<int>& small, int op, std::vector<Task>& out)
+{
+    for (size_t q = 0; q < small.size(); q += kSbPerTask) {
+        int id[kSbPerTask];
+        for (int w = 0; w < kSbPerTask; w++) id[w] = q + w < small.size() ? small[q + w] : -1;
+        out.push_back({id[0], id[1], id[2], id[3], 0, 0, q_flags(op, 0), 0});
+    }
+}
+
 void build_schedule(selinv_plan_s* P)
 {
     std::vector<std::vector<int>> lv;
     by_level(P, lv);
     const int D = (int)lv.size();
-    LevelTasks* all[] = {&P->t_diag, &P->t_panel, &P->t_schur, &P->t_gemm, &P->t_sdiag, &P->t_rs1,
-                         &P->t_rs2,  &P->t_rs3,   &P->t_rf1a,  &P->t_rf1b, &P->t_rf2};
+    LevelTasks* all[] = {&P->t_diag, &P->t_ldlt, &P->t_panel, &P->t_schur, &P->t_gemm, &P->t_sdiag, &P->t_sb,
+                         &P->t_rs1,  &P->t_rs2,  &P->t_rs3,   &P->t_rf1a,  &P->t_rf1b, &P->t_rf2};
     for (LevelTasks* t : all) {
         t->tasks.clear();
         t->off.assign(D + 1, 0);
     }
     P->t_zero.clear();
+    P->ldlt_cut.assign(2 * D, 0);
     for (int l = 0; l < D; l++) {
-        // tiles this level has without splitting contractions over C
-        int64_t base = 0, dbase = 0;
+        // tiles this level has without splitting contractions over C: of the
+        // tiled forward path, and of the reverse sweep (every block)
+        int64_t base = 0, dbase = 0, rbase_ = 0, rdbase = 0;
+        std::vector<int> small;
         for (int B : lv[l]) {
             const BlockDesc& d = P->blocks[B];
-            base += (int64_t)((d.c + kTileM - 1) / kTileM) * ((d.s + tile_bn(d.s) - 1) / tile_bn(d.s));
+            const int64_t tiles = (int64_t)((d.c + kTileM - 1) / kTileM) * ((d.s + tile_bn(d.s) - 1) / tile_bn(d.s));
             const int nd = (d.s + kDiagTile - 1) / kDiagTile;
+            rbase_ += tiles;
+            rdbase += nd * (nd + 1) / 2;
+            if (is_small(d.s, d.c, kSbS)) {
+                small.push_back(B);
+                continue;
+            }
+            base += tiles;
             dbase += nd * (nd + 1) / 2;
         }
-        const int64_t want = base > 0 && base < kFillTiles ? (kFillTiles + base - 1) / base : 1;
-        const int64_t dwant = dbase > 0 && dbase < kFillTiles ? (kFillTiles + dbase - 1) / dbase : 1;
+        push_sb_groups(small, qSbFactor, P->t_sb.tasks);
+        auto fill_for = [](int64_t tiles) { return tiles > 0 && tiles < kFillTiles ? (kFillTiles + tiles - 1) / tiles : 1; };
+        const int64_t want = fill_for(base), dwant = fill_for(dbase);
+        const int64_t rwant = fill_for(rbase_), rdwant = fill_for(rdbase);
         for (int B : lv[l]) {
             const BlockDesc& d = P->blocks[B];
             const int bn = tile_bn(d.s);
             const int s = d.s, c = d.c;
             P->t_diag.tasks.push_back({B, 0, 0, 0, 0, 0, 0, 0});
-            // contractions over C are split into pieces of >= kMinSplitK rows
-            // when a level has too few tiles to fill the device
-            const int split = split_for(want, c);
-            const int dsplit = split_for(dwant, c);
-            if (split > 1 || dsplit > 1) P->t_zero.push_back({B, 0, 0, 0, 0, 0, 0, 0});
+            // reverse sweep: every block, tiled
             const int nd = (s + kDiagTile - 1) / kDiagTile;
-            for (int I = 0; I < nd; I++)
-                for (int J = 0; J <= I; J++)
-                    pieces(0, c, dsplit, [&](int kb, int ke, int) {
-                        P->t_sdiag.tasks.push_back({B, I * kDiagTile, J * kDiagTile, 0, kb, ke, dsplit > 1, 0});
-                    });
+            const int rsplit = split_for(rdwant, c);
             for (int I = 0; I < nd; I++)
                 for (int J = 0; J < nd; J++)
-                    pieces(0, c, dsplit, [&](int kb, int ke, int) {
-                        P->t_rf2.tasks.push_back({B, I * kDiagTile, J * kDiagTile, 0, kb, ke, dsplit > 1, 0});
+                    pieces(0, c, rsplit, [&](int kb, int ke, int) {
+                        P->t_rf2.tasks.push_back({B, I * kDiagTile, J * kDiagTile, 0, kb, ke, rsplit > 1, 0});
                     });
             for (int j = 0; j < s; j += bn)
                 for (int r = 0; r < c; r += kTileM) {
-                    P->t_panel.tasks.push_back({B, r, j, bn, 0, s, 0, 0});
                     P->t_rs1.tasks.push_back({B, r, j, bn, 0, s, 0, 0});
-                    pieces(0, c, split, [&](int kb, int ke, int) {
-                        P->t_gemm.tasks.push_back({B, r, j, bn, kb, ke, split > 1, 0});
-                        P->t_rs2.tasks.push_back({B, r, j, bn, kb, ke, split > 1, 0});
+                    const int rs = split_for(rwant, c);
+                    pieces(0, c, rs, [&](int kb, int ke, int) {
+                        P->t_rs2.tasks.push_back({B, r, j, bn, kb, ke, rs > 1, 0});
                     });
                     // reverse factor: Ubar is lower triangular, so row tile r
                     // contracts over [0, r+64) with Ubar and over [r, c) with Ubar^T
                     const int hi = std::min(c, r + kTileM);
-                    const int sa = split_for(want, hi);
+                    const int sa = split_for(rwant, hi);
                     pieces(0, hi, sa, [&](int kb, int ke, int) {
                         P->t_rf1a.tasks.push_back({B, r, j, bn, kb, ke, sa > 1, 0});
                     });
-                    const int sb = split_for(want, c - r);
+                    const int sb = split_for(rwant, c - r);
                     pieces(r, c, sb, [&](int kb, int ke, int q) {
                         // piece 0 also adds L_hat_bar T
                         P->t_rf1b.tasks.push_back({B, r, j, bn, kb, ke, (sb > 1) | (q == 0 ? 2 : 0), 0});
                     });
                 }
             for (int k = 0; k < c; k += kSchurTile)
-                for (int i = k; i < c; i += kSchurTile) {
-                    P->t_schur.tasks.push_back({B, i, k, kSchurTile, 0, s, 0, 0});
-                    P->t_rs3.tasks.push_back({B, i, k, kSchurTile, 0, 2 * s, 0, 0});
+                for (int i = k; i < c; i += kSchurTile) P->t_rs3.tasks.push_back({B, i, k, kSchurTile, 0, 2 * s, 0, 0});
+            if (is_small(s, c, kSbS)) continue;
+            // forward, tiled path
+            // contractions over C are split into pieces of >= kMinSplitK rows
+            // when a level has too few tiles to fill the device
+            const int split = split_for(want, c);
+            const int dsplit = split_for(dwant, c);
+            if (split > 1 || dsplit > 1) P->t_zero.push_back({B, 0, 0, 0, 0, 0, 0, 0});
+            for (int I = 0; I < nd; I++)
+                for (int J = 0; J <= I; J++)
+                    pieces(0, c, dsplit, [&](int kb, int ke, int) {
+                        P->t_sdiag.tasks.push_back({B, I * kDiagTile, J * kDiagTile, 0, kb, ke, dsplit > 1, 0});
+                    });
+            for (int j = 0; j < s; j += bn)
+                for (int r = 0; r < c; r += kTileM) {
+                    P->t_panel.tasks.push_back({B, r, j, bn, 0, s, 0, 0});
+                    pieces(0, c, split, [&](int kb, int ke, int) {
+                        P->t_gemm.tasks.push_back({B, r, j, bn, kb, ke, split > 1, 0});
+                    });
                 }
+            for (int k = 0; k < c; k += kSchurTile)
+                for (int i = k; i < c; i += kSchurTile)
+                    P->t_schur.tasks.push_back({B, i, k, kSchurTile, 0, s, 0, 0});
+        }
+        // diagonal blocks of the tiled path by width class (one launch each)
+        const int64_t cls[] = {32, 64, 1 << 30};
+        for (int k = 0; k < 3; k++) {
+            for (int B : lv[l]) {
+                const BlockDesc& d = P->blocks[B];
+                if (is_small(d.s, d.c, kSbS) || d.s > cls[k] || (k > 0 && d.s <= cls[k - 1])) continue;
+                P->t_ldlt.tasks.push_back({B, 0, 0, 0, 0, 0, 0, 0});
+            }
+            if (k < 2) P->ldlt_cut[2 * l + k] = (int64_t)P->t_ldlt.tasks.size();
         }
         for (LevelTasks* t : all) t->off[l + 1] = (int64_t)t->tasks.size();
     }
@@ -119,16 +161,27 @@ void build_schedule(selinv_plan_s* P)
     P->work_bytes.assign(kNumKinds, 0.0);
     for (const BlockDesc& d : P->blocks) {
         const double s = d.s, c = d.c;
-        P->work_flops[kLdlt] += s * s * s;              // sweep: s pivots x s^2 updates
-        P->work_bytes[kLdlt] += 8.0 * 3 * s * s;
-        P->work_flops[kPanel] += 2.0 * c * s * s;       // L_hat = F(C,B) T
-        P->work_bytes[kPanel] += 8.0 * (2 * c * s + s * s);
-        P->work_flops[kSchur] += c * c * s;             // lower half of L_hat F^T
-        P->work_bytes[kSchur] += 8.0 * (c * s + c * (c + 1) / 2);
-        P->work_flops[kGemm] += 2.0 * c * c * s;        // X = -G L_hat
-        P->work_bytes[kGemm] += 8.0 * (c * (c + 1) / 2 + 2 * c * s);
-        P->work_flops[kSdiag] += 2.0 * c * s * s;       // Y = T - L_hat^T X
-        P->work_bytes[kSdiag] += 8.0 * (2 * c * s + 2 * s * s);
+        const double fl[] = {s * s * s, 2.0 * c * s * s, c * c * s, 2.0 * c * c * s, 2.0 * c * s * s};
+        const double by[] = {8.0 * 3 * s * s, 8.0 * (2 * c * s + s * s), 8.0 * (c * s + c * (c + 1) / 2),
+                             8.0 * (c * (c + 1) / 2 + 2 * c * s), 8.0 * (2 * c * s + 2 * s * s)};
+        // sweep: s pivots x s^2 updates; L_hat = F(C,B) T; lower half of
+        // L_hat F^T; X = -G L_hat; Y = T - L_hat^T X
+        if (is_small(d.s, d.c, kSbS)) {
+            P->work_flops[kSbFactor] += fl[0] + fl[1] + fl[2];
+            P->work_bytes[kSbFactor] += by[0] + by[1] + by[2];
+            P->work_flops[kSbInvert] += fl[3] + fl[4];
+            P->work_bytes[kSbInvert] += by[3] + by[4];
+        } else {
+            const Kind k[] = {kLdlt, kPanel, kSchur, kGemm, kSdiag};
+            for (int q = 0; q < 5; q++) {
+                P->work_flops[k[q]] += fl[q];
+                P->work_bytes[k[q]] += by[q];
+            }
+        }
+        P->work_flops[kQFactor] += fl[0] + fl[1] + fl[2];
+        P->work_bytes[kQFactor] += by[0] + by[1] + by[2];
+        P->work_flops[kQInvert] += fl[3] + fl[4];
+        P->work_bytes[kQInvert] += by[3] + by[4];
         // reverse selected inversion: Xbar (2cs^2), Lhat_bar (2c^2 s + 2cs^2),
         // symmetric scatter of -(Xbar L_hat^T + L_hat Xbar^T) (2c^2 s, lower half)
         P->work_flops[kRevSel] += 4.0 * c * c * s + 4.0 * c * s * s;
@@ -142,7 +195,6 @@ void build_schedule(selinv_plan_s* P)
     P->work_bytes[kAssemble] = 8.0 * P->arena + 24.0 * nnzA;
     P->work_bytes[kExport] = 24.0 * nnzL;
 }
-
 
 // ---------------------------------------------------------------------------
 // Work queues of the persistent level kernels.  One queue per level and
@@ -186,6 +238,8 @@ static void order_blocks(const selinv_plan_s* P, int order, std::vector<int>& bl
 static double task_cost(const Task& t)
 {
     const int op = t.flags >> 8;
+    if (op == qSbFactor || op == qSbInvert) return 0.0;  // groups keep their block order
+    if (op == qMbFactor || op == qMbInvert) return 1e30;  // whole blocks: before the tiles
     if (op == qSchur) return (double)t.ke * kSchurTile * kSchurTile;
     if (op == qSdiag) return 2.0 * (t.ke - t.kb) * kDiagTile * kDiagTile;
     return (double)(t.ke - t.kb) * t.bn * kTileM;
@@ -215,23 +269,37 @@ void build_queues(const selinv_plan_s* P, const Sched& sc, std::vector<Task>& qf
     for (int l = 0; l < D; l++) {
         std::vector<int> bl = lv[l];
         order_blocks(P, sc.order, bl);
-        // factor: diagonal block, then L_hat tiles, then Schur tiles
+        std::vector<int> small, medium, big;
         for (int B : bl) {
             const BlockDesc& d = P->blocks[B];
             const int bn = bn_of(d.s);
+            const int64_t tiles = (int64_t)((d.c + kTileM - 1) / kTileM) * ((d.s + bn - 1) / bn);
+            if (is_small(d.s, d.c, sc.small_s)) small.push_back(B);
+            else if (tiles <= sc.mb_tiles) medium.push_back(B);
+            else big.push_back(B);
+        }
+        // factor: small blocks whole on a wave, medium ones whole on a
+        // work-group; big ones as diagonal block, then L_hat tiles, then
+        // Schur tiles
+        push_sb_groups(small, qSbFactor, ph[0]);
+        for (int B : medium) ph[0].push_back({B, 0, 0, bn_of(P->blocks[B].s), 0, 0, q_flags(qMbFactor, 0), 0});
+        for (int B : big) {
+            const BlockDesc& d = P->blocks[B];
+            const int bn = bn_of(d.s);
             const int npanel = ((d.c + kTileM - 1) / kTileM) * ((d.s + bn - 1) / bn);
-            ph[0].push_back({B, 0, 0, 0, 0, 0, q_flags(qLdlt, 0), 0});
+            ph[0].push_back({B, 0, 0, 0, 0, 0, q_flags(qLdlt, npanel > 0 ? 2 : 0), 0});
             for (int j = 0; j < d.s; j += bn)
-                for (int r = 0; r < d.c; r += kTileM) ph[1].push_back({B, r, j, bn, 0, d.s, q_flags(qPanel, 0), 1});
+                for (int r = 0; r < d.c; r += kTileM) ph[1].push_back({B, r, j, bn, 0, d.s, q_flags(qPanel, 2), 1});
             for (int k = 0; k < d.c; k += kSchurTile)
                 for (int i = k; i < d.c; i += kSchurTile)
                     ph[2].push_back({B, i, k, kSchurTile, 0, d.s, q_flags(qSchur, 0), 1 + npanel});
         }
         flush(qf);
         qf_off[l + 1] = (int64_t)qf.size();
-        // inversion: zero X (split blocks), then X tiles, then diagonal tiles
+        // inversion: small blocks whole; big ones as zero X (split blocks),
+        // then X tiles, then diagonal tiles
         int64_t base = 0, dbase = 0;
-        for (int B : bl) {
+        for (int B : big) {
             const BlockDesc& d = P->blocks[B];
             base += (int64_t)((d.c + kTileM - 1) / kTileM) * ((d.s + bn_of(d.s) - 1) / bn_of(d.s));
             const int nd = (d.s + kDiagTile - 1) / kDiagTile;
@@ -240,18 +308,20 @@ void build_queues(const selinv_plan_s* P, const Sched& sc, std::vector<Task>& qf
         const int64_t fill = sc.split_fill;
         const int64_t want = fill > 0 && base > 0 && base < fill ? (fill + base - 1) / base : 1;
         const int64_t dwant = fill > 0 && dbase > 0 && dbase < fill ? (fill + dbase - 1) / dbase : 1;
-        for (int B : bl) {
+        push_sb_groups(small, qSbInvert, ph[0]);
+        for (int B : medium) ph[0].push_back({B, 0, 0, bn_of(P->blocks[B].s), 0, 0, q_flags(qMbInvert, 0), 0});
+        for (int B : big) {
             const BlockDesc& d = P->blocks[B];
             const int bn = bn_of(d.s);
             const int split = split_for(want, d.c);
             const int dsplit = split_for(dwant, d.c);
             const int nz = (split > 1 || dsplit > 1) ? 1 : 0;
-            if (nz) ph[0].push_back({B, 0, 0, 0, 0, 0, q_flags(qZero, 0), 0});
+            if (nz) ph[0].push_back({B, 0, 0, 0, 0, 0, q_flags(qZero, 2), 0});
             int ng = 0;
             for (int j = 0; j < d.s; j += bn)
                 for (int r = 0; r < d.c; r += kTileM)
                     pieces(0, d.c, split, [&](int kb, int ke, int) {
-                        ph[1].push_back({B, r, j, bn, kb, ke, q_flags(qGemm, split > 1), nz});
+                        ph[1].push_back({B, r, j, bn, kb, ke, q_flags(qGemm, (split > 1) | 2), nz});
                         ng++;
                     });
             const int nd = (d.s + kDiagTile - 1) / kDiagTile;
@@ -266,50 +336,19 @@ void build_queues(const selinv_plan_s* P, const Sched& sc, std::vector<Task>& qf
     }
 }
 
-
-void queue_sizes(const selinv_plan_s* P, const Sched& sc, int64_t& nfac, int64_t& ninv)
+void queue_bound(const selinv_plan_s* P, int64_t& nfac, int64_t& ninv)
 {
-    std::vector<std::vector<int>> lv;
-    by_level(P, lv);
-    const int cap = std::max(16, std::min(128, sc.bn_cap));
-    auto bn_of = [&](int s) { return std::min(tile_bn(s), cap); };
-    auto npieces = [](int len, int split) {  // what pieces() emits for [0, len)
-        if (len <= 0) return 1;
-        const int n16 = (len + 15) / 16;
-        int k = 0;
-        for (int q = 0; q < split; q++) {
-            const int kb = (int)((int64_t)n16 * q / split) * 16;
-            const int ke = std::min(len, (int)((int64_t)n16 * (q + 1) / split) * 16);
-            if (kb < ke) k++;
-        }
-        return k;
-    };
+    // per block, whatever the schedule: one small-block, medium-block or
+    // diagonal task; output tiles at most as many as with 16-column tiles;
+    // each contraction in at most split_for's cap of pieces
     nfac = ninv = 0;
-    for (const std::vector<int>& bl : lv) {
-        int64_t base = 0, dbase = 0;
-        for (int B : bl) {
-            const BlockDesc& d = P->blocks[B];
-            const int bn = bn_of(d.s);
-            const int64_t tiles = (int64_t)((d.c + kTileM - 1) / kTileM) * ((d.s + bn - 1) / bn);
-            const int64_t nsc = (d.c + kSchurTile - 1) / kSchurTile;
-            nfac += 1 + tiles + nsc * (nsc + 1) / 2;
-            base += tiles;
-            const int nd = (d.s + kDiagTile - 1) / kDiagTile;
-            dbase += nd * (nd + 1) / 2;
-        }
-        const int64_t fill = sc.split_fill;
-        const int64_t want = fill > 0 && base > 0 && base < fill ? (fill + base - 1) / base : 1;
-        const int64_t dwant = fill > 0 && dbase > 0 && dbase < fill ? (fill + dbase - 1) / dbase : 1;
-        for (int B : bl) {
-            const BlockDesc& d = P->blocks[B];
-            const int bn = bn_of(d.s);
-            const int split = split_for(want, d.c), dsplit = split_for(dwant, d.c);
-            const int64_t tiles = (int64_t)((d.c + kTileM - 1) / kTileM) * ((d.s + bn - 1) / bn);
-            const int nd = (d.s + kDiagTile - 1) / kDiagTile;
-            ninv += (split > 1 || dsplit > 1) ? 1 : 0;
-            ninv += tiles * npieces(d.c, split);
-            ninv += (int64_t)nd * (nd + 1) / 2 * npieces(d.c, dsplit);
-        }
+    for (const BlockDesc& d : P->blocks) {
+        const int64_t rows = (d.c + kTileM - 1) / kTileM, nsc = (d.c + kSchurTile - 1) / kSchurTile;
+        const int64_t tiles = rows * ((d.s + 15) / 16);
+        const int64_t nd = (d.s + kDiagTile - 1) / kDiagTile;
+        const int64_t ms = std::max(1, ((d.c + 15) / 16) / (kMinSplitK / 16));
+        nfac += 1 + tiles + nsc * (nsc + 1) / 2;
+        ninv += 1 + tiles * ms + nd * (nd + 1) / 2 * ms;
     }
 }
 

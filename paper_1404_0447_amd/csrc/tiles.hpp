@@ -13,6 +13,12 @@ constexpr size_t kLdsDiagBytes = sizeof(double) * kLdsDiagMax * (kLdsDiagMax + 1
 constexpr bool kUseSweep = true;  // register Gauss-Jordan sweep for s <= kLdsDiagMax
 constexpr size_t kDiagShmem = kUseSweep ? sizeof(double) * 2 * kLdsDiagMax : kLdsDiagBytes;
 
+// small blocks run whole on one wave (all phases, 16 x 16 MFMA tiles)
+constexpr int kSbS = 16;          // widest small block
+constexpr int kSbC = 256;         // largest |C| of a small block
+constexpr int kSbPerTask = 4;     // small blocks per work-group task (one per wave)
+inline bool is_small(int s, int c, int smax) { return s <= smax && c <= kSbC; }
+
 constexpr int kFillTiles = 512;  // split the contraction when a level has fewer X tiles
 constexpr int kMinSplitK = 256;  // rows of C per split piece, at least
 

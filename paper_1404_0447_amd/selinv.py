@@ -29,8 +29,9 @@ EXPORTS = ["selinv_analyze", "selinv_workspace_size", "selinv_bind_workspace", "
            "selinv_get_queue", "selinv_set_spin_limit", "selinv_run", "selinv_tune",
            "selinv_last_error", "selinv_destroy"]
 ARENAS = {"L": 0, "Ainv": 1, "Lhat": 2, "W": 3, "T": 4, "Fbar": 5, "Lhat_bar": 6, "T_bar": 7}
-KINDS = ["assemble", "ldlt", "panel", "schur", "gemm", "sdiag", "export", "revsel", "revfac", "qfactor", "qinvert"]
-QOPS = ["ldlt", "panel", "schur", "zero", "gemm", "sdiag"]
+KINDS = ["assemble", "ldlt", "panel", "schur", "gemm", "sdiag", "export", "revsel", "revfac", "qfactor", "qinvert",
+         "sbfactor", "sbinvert"]
+QOPS = ["ldlt", "panel", "schur", "zero", "gemm", "sdiag", "sbfactor", "sbinvert", "mbfactor", "mbinvert"]
 ORDERS = ["plan", "lpt", "round_robin", "tile_lpt"]
 
 
@@ -51,7 +52,8 @@ class Opts(ct.Structure):
 
 
 class Sched(ct.Structure):
-    _fields_ = [("order", ct.c_int32), ("bn_cap", ct.c_int32), ("split_fill", ct.c_int32), ("grid_mult", ct.c_int32)]
+    _fields_ = [("order", ct.c_int32), ("bn_cap", ct.c_int32), ("split_fill", ct.c_int32), ("grid_mult", ct.c_int32),
+                ("small_s", ct.c_int32), ("mb_tiles", ct.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -269,9 +271,11 @@ class Plan:
         _check(lib().selinv_get_schedule(self._h, ct.byref(sc)))
         return sc.as_dict()
 
-    def set_schedule(self, order=None, bn_cap=None, split_fill=None, grid_mult=None, stream=None):
+    def set_schedule(self, order=None, bn_cap=None, split_fill=None, grid_mult=None, small_s=None, mb_tiles=None,
+                     stream=None):
         cur = self.schedule()
-        for k, v in (("order", order), ("bn_cap", bn_cap), ("split_fill", split_fill), ("grid_mult", grid_mult)):
+        for k, v in (("order", order), ("bn_cap", bn_cap), ("split_fill", split_fill), ("grid_mult", grid_mult),
+                     ("small_s", small_s), ("mb_tiles", mb_tiles)):
             if v is not None:
                 cur[k] = ORDERS.index(v) if (k == "order" and isinstance(v, str)) else int(v)
         sc = Sched(**cur)

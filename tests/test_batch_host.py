@@ -106,39 +106,72 @@ def check_queues(p, sched=None):
     lev, s, c = blk["level"], blk["s"], blk["c"]
     sched = sched or p.schedule()
     for l in range(1, int(p.info["exec_depth"]) + 1):
-        for sweep, phases in ((0, ("ldlt", "panel", "schur")), (1, ("zero", "gemm", "sdiag"))):
+        for sweep, phases, sb_op, mb_op in ((0, ("ldlt", "panel", "schur"), "sbfactor", "mbfactor"),
+                                            (1, ("zero", "gemm", "sdiag"), "sbinvert", "mbinvert")):
             q = p.queue(sweep, l)
-            b, i0, j0, bn, kb, ke, fl, need = (q[:, k] for k in range(8))
-            op = fl >> 8
-            assert set(b.tolist()) == set(np.nonzero(lev == l)[0].tolist())
-            phase = np.array([phases.index(S.QOPS[o]) for o in op], dtype=np.int64)
+            op = q[:, 6] >> 8
+            # medium blocks: one whole-block task each, tile width within the cap
+            mb = op == OP[mb_op]
+            mids = q[mb, 0]
+            assert len(set(mids.tolist())) == len(mids)
+            assert np.all(q[mb, 7] == 0) and np.all((q[mb, 6] & 3) == 0)
+            assert np.all(q[mb, 3] <= sched["bn_cap"])
+            for B, w in zip(mids, q[mb, 3]):
+                assert not (s[B] <= sched["small_s"] and c[B] <= 256)
+                assert ((c[B] + 63) // 64) * ((s[B] + w - 1) // w) <= sched["mb_tiles"]
+            q = q[~mb]
+            op = op[~mb]
+            sb = op == OP[sb_op]
+            # small blocks: whole, four to a task, each exactly once, listed first
+            ids = q[sb, :4].ravel()
+            ids = ids[ids >= 0]
+            assert len(set(ids.tolist())) == len(ids)
+            assert np.all((s[ids] <= sched["small_s"]) & (c[ids] <= 256))
+            assert np.all(q[sb, 7] == 0) and np.all((q[sb, 6] & 3) == 0)
+            if sb.any():
+                assert np.all(sb[: int(sb.sum())]), "small-block tasks come first"
+            t = q[~sb]
+            b, i0, j0, bn, kb, ke, fl, need = (t[:, k] for k in range(8))
+            top = fl >> 8
+            assert not set(b.tolist()) & set(ids.tolist())
+            assert not set(mids.tolist()) & (set(ids.tolist()) | set(b.tolist()))
+            assert set(b.tolist()) | set(ids.tolist()) | set(mids.tolist()) == set(np.nonzero(lev == l)[0].tolist())
+            for B in set(b.tolist()):
+                bnB = max(16, min(sched["bn_cap"], 16 if s[B] <= 16 else 32 if s[B] <= 32 else 64 if s[B] <= 64
+                                  else 128))
+                assert not (s[B] <= sched["small_s"] and c[B] <= 256)
+                assert ((c[B] + 63) // 64) * ((s[B] + bnB - 1) // bnB) > sched["mb_tiles"]
+            phase = np.array([phases.index(S.QOPS[o]) for o in top], dtype=np.int64)
             assert np.all(np.diff(phase) >= 0), "tasks must be listed phase by phase"
             # every task waits for exactly the earlier-phase tasks of its block,
-            # and all of them sit at smaller queue indices
+            # all of them sit at smaller queue indices and signal their block
             for B in np.unique(b):
                 idx = np.nonzero(b == B)[0]
                 for k in idx:
                     before = idx[phase[idx] < phase[k]]
                     assert need[k] == len(before)
                     assert np.all(before < k)
+                    assert np.all((fl[before] & 2) == 2)
             for B in np.unique(b):
                 sB, cB = int(s[B]), int(c[B])
                 mine = b == B
                 if sweep == 0:
-                    assert np.sum(mine & (op == OP["ldlt"])) == 1
-                    pt = mine & (op == OP["panel"])
+                    assert np.sum(mine & (top == OP["ldlt"])) == 1
+                    pt = mine & (top == OP["panel"])
                     cells = sum(min(64, cB - r) * min(w, sB - j) for r, j, w in zip(i0[pt], j0[pt], bn[pt]))
                     assert cells == cB * sB and len(set(zip(i0[pt], j0[pt]))) == pt.sum()
                     assert np.all(bn[pt] <= sched["bn_cap"])
-                    st = mine & (op == OP["schur"])
+                    st = mine & (top == OP["schur"])
                     nt = (cB + 63) // 64
                     assert sorted(zip(i0[st], j0[st])) == sorted((i * 64, k * 64) for k in range(nt)
                                                                  for i in range(k, nt))
+                    assert np.all((fl[st] & 2) == 0)
                 else:
-                    gt = mine & (op == OP["gemm"])
-                    dt = mine & (op == OP["sdiag"])
+                    gt = mine & (top == OP["gemm"])
+                    dt = mine & (top == OP["sdiag"])
                     atomic = np.any((fl[gt] & 1) == 1) or np.any((fl[dt] & 1) == 1)
-                    assert np.sum(mine & (op == OP["zero"])) == (1 if atomic else 0)
+                    assert np.sum(mine & (top == OP["zero"])) == (1 if atomic else 0)
+                    assert np.all((fl[dt] & 2) == 0)
                     for sel, keys in ((gt, list(zip(i0[gt], j0[gt]))), (dt, list(zip(i0[dt], j0[dt])))):
                         pieces = {}
                         for key, a, z, f in zip(keys, kb[sel], ke[sel], fl[sel]):
@@ -158,11 +191,13 @@ def check_queues(p, sched=None):
                     assert cells == cB * sB
 
 
-@pytest.mark.parametrize("order,bn_cap,fill", list(itertools.product(range(4), (16, 32, 64, 128), (0, 512, 4096))))
-def test_queue_invariants_every_schedule(order, bn_cap, fill):
-    p = S.Plan.batch(_small_batch(), max_super=16, exec_cap=16)
-    sc = p.set_schedule(order=order, bn_cap=bn_cap, split_fill=fill, grid_mult=1)
-    assert sc == dict(order=order, bn_cap=bn_cap, split_fill=fill, grid_mult=1)
+@pytest.mark.parametrize("order,bn_cap,fill,small,mb", [(o, b, f, sm, mbt) for o, b, f in itertools.product(
+    range(4), (16, 32, 64, 128), (0, 512, 4096)) for sm in ((0, 16) if b != 64 else (0, 1, 2, 4, 8, 16))
+    for mbt in ((0, 8) if f != 512 else (0, 1, 8, 4096))])
+def test_queue_invariants_every_schedule(order, bn_cap, fill, small, mb):
+    p = S.Plan.batch(_small_batch(), max_super=24, exec_cap=24)
+    sc = p.set_schedule(order=order, bn_cap=bn_cap, split_fill=fill, grid_mult=1, small_s=small, mb_tiles=mb)
+    assert sc == dict(order=order, bn_cap=bn_cap, split_fill=fill, grid_mult=1, small_s=small, mb_tiles=mb)
     check_queues(p)
 
 
@@ -173,7 +208,7 @@ def test_queue_orders():
     blk = p.blocks()
     cost = 2.0 * blk["c"] ** 2 * blk["s"] + 2.0 * blk["c"] * blk["s"] ** 2 + blk["s"].astype(float) ** 3
     for l in range(1, int(p.info["exec_depth"]) + 1):
-        p.set_schedule(order="plan")
+        p.set_schedule(order="plan", small_s=0, mb_tiles=0)
         q = p.queue(0, l)
         ld = q[(q[:, 6] >> 8) == OP["ldlt"], 0]
         assert np.all(np.diff(ld) > 0)
@@ -192,17 +227,18 @@ def test_queue_orders():
 def test_schedule_validation():
     p = S.Plan.batch(W.batch_2d(count=3, side_lo=8, side_hi=12, seed=2))
     for bad in (dict(order=7), dict(bn_cap=48), dict(split_fill=-1), dict(split_fill=4097), dict(grid_mult=0),
-                dict(grid_mult=17)):
+                dict(grid_mult=17), dict(small_s=3), dict(small_s=32), dict(mb_tiles=-1), dict(mb_tiles=5000)):
         with pytest.raises(S.SelinvError) as e:
             p.set_schedule(**bad)
         assert e.value.status == S.SELINV_EINVAL
-    assert p.schedule() == dict(order=1, bn_cap=128, split_fill=512, grid_mult=2)
+    assert p.schedule() == dict(order=1, bn_cap=128, split_fill=512, grid_mult=2, small_s=16, mb_tiles=8)
 
 
 def test_capacity_covers_every_valid_schedule():
-    """Queue lengths grow with split_fill: every fill up to 4096 and every
-    tile cap fits the space the workspace reserves."""
+    """The queue space the workspace reserves bounds every valid schedule."""
     p = S.Plan.from_matrix(W.laplacian((14, 14, 14), shift=0.1))
     for bn in (16, 32, 64, 128):
         for fill in (0, 1, 100, 511, 512, 2000, 4095, 4096):
-            p.set_schedule(bn_cap=bn, split_fill=fill)
+            for small in (0, 1, 2, 4, 8, 16):
+                for mb in (0, 3, 64, 4096):
+                    p.set_schedule(bn_cap=bn, split_fill=fill, small_s=small, mb_tiles=mb)

@@ -88,15 +88,16 @@ def test_persistent_single_matrix(case):
     assert H.err_c8(sel.cpu().numpy(), ref.cpu().numpy(), cp, ri) <= 1e-13
 
 
-@pytest.mark.parametrize("order,bn_cap,fill,grid", [(0, 128, 512, 2), (1, 64, 0, 1), (2, 32, 4096, 4),
-                                                    (3, 16, 512, 2), (1, 128, 4096, 1)])
-def test_batch_every_schedule_axis(order, bn_cap, fill, grid):
+@pytest.mark.parametrize("order,bn_cap,fill,grid,small,mb", [(0, 128, 512, 2, 16, 8), (1, 64, 0, 1, 0, 0),
+                                                              (2, 32, 4096, 4, 4, 64), (3, 16, 512, 2, 1, 0),
+                                                              (1, 128, 4096, 1, 16, 4096), (0, 64, 512, 2, 0, 4096)])
+def test_batch_every_schedule_axis(order, bn_cap, fill, grid, small, mb):
     _torch()
     from paper_1404_0447_amd import selinv as S
     ms = _batch()
     p = S.Plan.batch(ms).bind()
-    p.set_schedule(order=order, bn_cap=bn_cap, split_fill=fill, grid_mult=grid)
-    print(f"batch schedule {order} {bn_cap} {fill} {grid}", flush=True)
+    p.set_schedule(order=order, bn_cap=bn_cap, split_fill=fill, grid_mult=grid, small_s=small, mb_tiles=mb)
+    print(f"batch schedule {order} {bn_cap} {fill} {grid} {small} {mb}", flush=True)
     sel = p.run(_vals(ms))
     p.sync_status()
     _check_batch(p, ms, sel)
@@ -156,7 +157,7 @@ def test_tuner_and_cache(tmp_path):
     assert text.strip().startswith("{") and "selinv/" in text and '"bn_cap"' in text
     # a fresh plan of the same structure takes the cached choice
     q = S.Plan.batch(ms).bind()
-    q.set_schedule(order=0, bn_cap=16, split_fill=0, grid_mult=1)
+    q.set_schedule(order=0, bn_cap=16, split_fill=0, grid_mult=1, small_s=0, mb_tiles=0)
     sc2, ms2, sel2 = q.tune(v, cache_path=str(cache))
     assert sc2 == sc and ms2 == pytest.approx(ms_best, rel=1e-5)
     q.run(v, out=sel2)
@@ -173,6 +174,8 @@ def test_queue_wait_limit_reports_error():
     from paper_1404_0447_amd import selinv as S
     ms = _batch()[:4]
     p = S.Plan.batch(ms).bind()
+    # every block as dependent tile tasks, so that tasks do wait
+    p.set_schedule(small_s=0, mb_tiles=0)
     v = _vals(ms)
     p.set_spin_limit(0)
     p.run(v)
