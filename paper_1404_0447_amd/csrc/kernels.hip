@@ -249,33 +249,146 @@ __device__ __forceinline__ void tile_epilogue(const d4 (&acc)[2][4], F f)
 // Selected inversion, step 3: X = Ainv(C,B) = -Ainv(C,C) L_hat(C,B) for rows
 // [i0, i0+64) and columns [j0, j0+BN) of X.  Ainv(C,C) is gathered from the
 // ancestors' panels: entries with i >= k directly, the others by symmetry.
+//
+// The gather G(i,k) = Ap[cbase[p] + rel[rbase[p] + q]] (p, q = k, i when
+// i >= k, else i, k) is a chain of three dependent loads, so the main loop
+// is a software pipeline over 16-deep chunks of the contraction: while the
+// MFMAs consume chunk n from one LDS buffer, the values of chunk n+1 are
+// stored to the other, the values of chunk n+2 are loaded from the offsets
+// found one iteration earlier, the rel entries of chunk n+3 and the
+// (cbase, rbase) pairs of chunk n+4 are loaded: every load has a whole
+// iteration of MFMAs to arrive, and there is one barrier per chunk.
 // ---------------------------------------------------------------------------
+struct GemmLds {
+    double A[2][TBK][TBM + TPAD];
+    double B[2][TBK][128 + TPAD];
+};
+
 template <int BN>
-__device__ void gemm_task(TileLds& L, const Task t, const BlockDesc d, double* __restrict__ Ap,
+__device__ void gemm_task(GemmLds& L, const Task t, const BlockDesc d, double* __restrict__ Ap,
                           const double* __restrict__ Hp, const int64_t* __restrict__ cbase,
                           const int64_t* __restrict__ rbase, const int32_t* __restrict__ rel)
 {
+    using SH = TileShape<BN>;
+    constexpr int NB = BN / 16;  // B elements per thread per chunk
     const int s = d.s, c = d.c;
     const int64_t ld = (int64_t)s + c;
     const int r0 = t.i0, n0 = t.j0;
-    d4 acc[2][4] = {};
-    auto loadA = [&](int k0, int kk, int ii) -> double {
-        const int i = r0 + ii, k = k0 + kk;
-        if (i >= c || k >= c) return 0.0;
-        if (i >= k) {
-            const int64_t pk = d.coff + k;
-            return Ap[cbase[pk] + rel[rbase[pk] + i]];
-        }
-        const int64_t pi = d.coff + i;
-        return Ap[cbase[pi] + rel[rbase[pi] + k]];
-    };
-    auto loadB = [&](int k0, int kk, int j) -> double {
-        const int k = k0 + kk, jj = n0 + j;
-        return (k < c && jj < s) ? Hp[d.hoff + k + (int64_t)jj * c] : 0.0;
-    };
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm0 = (wave % SH::WM) * (TBM / SH::WM), wn0 = (wave / SH::WM) * (BN / SH::WN);
+    const int Kb = t.kb;
+    const int nch = t.ke > Kb ? (t.ke - Kb + TBK - 1) / TBK : 0;
     // chunks entirely above the diagonal band are read along k (contiguous)
-    auto alongK = [&](int k0) { return k0 >= r0 + TBM; };
-    tile_mma<BN>(L, t.kb, t.ke, acc, loadA, loadB, alongK);
+    auto along_of = [&](int ch) { return Kb + ch * TBK >= r0 + TBM; };
+    // element q of this thread in chunk ch: (kk, ii) = along ? (e & 15, e >> 4) : (e >> 6, e & 63)
+    auto elem = [&](int ch, int q, int& i, int& k) {
+        const int e = tid + q * kThreads;
+        const bool al = along_of(ch);
+        i = r0 + (al ? e >> 4 : e & 63);
+        k = Kb + ch * TBK + (al ? e & 15 : e >> 6);
+        if (ch >= nch) k = c;  // past the end: padding
+    };
+    // Loads are unconditional and every stage only issues loads into raw
+    // registers; whatever consumes a loaded value (the offset sums, the
+    // padding masks) runs in the next stage, an iteration later, so no wait
+    // falls right behind its own load.  A padding element reads an in-bounds
+    // stand-in (position 0 of the block's maps, its own L_hat) and is zeroed
+    // by its mask.
+    int64_t m_cb[4], m_rb[4];  // stage M: cbase[p], rbase[p] as loaded
+    int m_q[4];                // stage M: q (the second index), -1 for padding
+    int64_t r_cb[4];           // stage R: cbase[p]
+    int32_t r_rel[4];          // stage R: rel[rbase[p] + q] as loaded
+    bool r_ok[4];
+    double v_a[4], v_b[NB];    // stage V: values as loaded
+    bool v_ok[4], v_bok[NB];
+    bool av = false;           // stage V chunk is read along k
+    auto stage_m = [&](int ch) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int i, k;
+            elem(ch, q, i, k);
+            const bool ok = i < c && k < c;
+            const int64_t p = d.coff + (ok ? (i >= k ? k : i) : 0);
+            m_cb[q] = cbase[p];
+            m_rb[q] = rbase[p];
+            m_q[q] = ok ? (i >= k ? i : k) : -1;
+        }
+    };
+    auto stage_r = [&]() {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            r_ok[q] = m_q[q] >= 0;
+            r_rel[q] = rel[m_rb[q] + (r_ok[q] ? m_q[q] : 0)];
+            r_cb[q] = m_cb[q];
+        }
+    };
+    auto stage_v = [&](int ch) {
+        av = along_of(ch);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            v_a[q] = Ap[r_cb[q] + r_rel[q]];
+            v_ok[q] = r_ok[q];
+        }
+        const int k0 = Kb + ch * TBK;
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const int e = tid + q * kThreads;
+            const int k = k0 + (e & 15), jj = n0 + (e >> 4);
+            v_bok[q] = k < c && jj < s;
+            v_b[q] = Hp[d.hoff + (v_bok[q] ? k + (int64_t)jj * c : 0)];
+        }
+    };
+    auto stage_store = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = tid + q * kThreads;
+            const double x = v_ok[q] ? v_a[q] : 0.0;
+            const int row = av ? (e & 15) : (e >> 6), col = av ? (e >> 4) : (e & 63);
+            L.A[buf][row][col] = x;
+        }
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const int e = tid + q * kThreads;
+            L.B[buf][e & 15][e >> 4] = v_bok[q] ? v_b[q] : 0.0;
+        }
+    };
+    d4 acc[2][4] = {};
+    // prologue: chunk 0 in LDS, chunk 1 values, chunk 2 offsets, chunk 3
+    // (cbase, rbase).  Chunks past the end are all padding: the stages run
+    // for them anyway, so the loop body has no branches.
+    stage_m(0);
+    stage_r();
+    stage_v(0);
+    stage_store(0);
+    stage_m(1);
+    stage_r();
+    stage_v(1);
+    stage_m(2);
+    stage_r();
+    stage_m(3);
+    __syncthreads();
+    for (int ch = 0; ch < nch; ++ch) {
+        const int buf = ch & 1;
+#pragma unroll
+        for (int ks = 0; ks < TBK / 4; ++ks) {
+            const int kr = ks * 4 + (lane >> 4);
+            double a[SH::MT], b[SH::NT];
+#pragma unroll
+            for (int mt = 0; mt < SH::MT; ++mt) a[mt] = L.A[buf][kr][wm0 + mt * 16 + (lane & 15)];
+#pragma unroll
+            for (int nt = 0; nt < SH::NT; ++nt) b[nt] = L.B[buf][kr][wn0 + nt * 16 + (lane & 15)];
+#pragma unroll
+            for (int mt = 0; mt < SH::MT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < SH::NT; ++nt) acc[mt][nt] = mfma(a[mt], b[nt], acc[mt][nt]);
+        }
+        stage_store(buf ^ 1);
+        stage_v(ch + 2);
+        stage_r();
+        stage_m(ch + 4);
+        __syncthreads();
+    }
+    mfma_drain();
     tile_epilogue<BN>(acc, [&](int i, int j, double v) {
         const int ii = r0 + i, jj = n0 + j;
         if (ii < c && jj < s) {
@@ -291,7 +404,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm(const Task* __restrict__ task
                                                    const int64_t* __restrict__ rbase,
                                                    const int32_t* __restrict__ rel)
 {
-    __shared__ TileLds L;
+    __shared__ GemmLds L;
     const Task t = tasks[blockIdx.x];
     const BlockDesc d = blk[t.b];
 #define SELINV_CALL(BN) gemm_task<BN>(L, t, d, Ap, Hp, cbase, rbase, rel)
@@ -861,6 +974,7 @@ __global__ __launch_bounds__(kThreads) void k_sb_invert(const Task* __restrict__
 // ===========================================================================
 union PersistLds {
     TileLds tile;
+    GemmLds gemm;
     SdiagLds sd;
     double colbuf[2][kLdsDiagMax];
     SbLds sb[kThreads / 64];
@@ -964,7 +1078,7 @@ __device__ __forceinline__ void panel_bounded(TileLds& L, const Task& t, const B
 
 // gather-GEMM tile; the host keeps t.bn <= BNMAX in this variant's levels
 template <int BNMAX>
-__device__ __forceinline__ void gemm_bounded(TileLds& L, const Task& t, const BlockDesc& d, double* Ap,
+__device__ __forceinline__ void gemm_bounded(GemmLds& L, const Task& t, const BlockDesc& d, double* Ap,
                                              const double* Hp, const int64_t* cbase, const int64_t* rbase,
                                              const int32_t* rel)
 {
@@ -1098,7 +1212,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_persist_invert(const QueueArgs 
                     zero_task(d, Ap, Tp);
                     break;
                 case qGemm:
-                    gemm_bounded<BNMAX>(sm.tile, u, d, Ap, Hp, cbase, rbase, rel);
+                    gemm_bounded<BNMAX>(sm.gemm, u, d, Ap, Hp, cbase, rbase, rel);
                     break;
                 default:
                     sdiag_task(sm.sd, u, d, Ap, Hp, Tp);

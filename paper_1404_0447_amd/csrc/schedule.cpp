@@ -4,6 +4,8 @@
 // kernel kind with one work-group per task.  The reverse sweep uses the same
 // levels in the opposite orders.
 #include <algorithm>
+#include <functional>
+#include <queue>
 
 #include "kernels.hpp"
 #include "plan.hpp"
@@ -39,6 +41,73 @@ static int split_for(int64_t want, int len)
 {
     const int maxsplit = std::max(1, ((len + 15) / 16) / (kMinSplitK / 16));
     return (int)std::min<int64_t>(want, maxsplit);
+}
+
+// Tiles of one level with the same contraction length c and width weight w.
+struct TileGroup {
+    int64_t count;
+    int c;
+    int w;
+};
+
+// Split request for one level: every tile's contraction is cut into
+// split_for(want, c) pieces, one work-group each; work-groups run in rounds
+// on `slots` resident places, so a level whose count is just above a
+// multiple of slots pays a nearly empty round.  Pick the request whose
+// greedy list schedule (largest first onto the least loaded place; cost =
+// 16-row chunks times tile width) finishes first.
+static int64_t best_split(const std::vector<TileGroup>& groups, int64_t slots)
+{
+    int64_t base = 0;
+    for (const TileGroup& g : groups) base += g.count;
+    if (base == 0 || base >= 4 * slots) return 1;
+    int64_t best = 1;
+    double best_t = -1.0;
+    std::vector<double> cost;
+    for (int64_t want = 1; want <= 32; want++) {
+        cost.clear();
+        for (const TileGroup& g : groups) {
+            const int sp = split_for(want, g.c), n16 = (g.c + 15) / 16;
+            for (int q = 0; q < sp; q++) {
+                const int len = (int)((int64_t)n16 * (q + 1) / sp - (int64_t)n16 * q / sp);
+                for (int64_t k = 0; k < g.count; k++) cost.push_back((double)len * g.w);
+            }
+        }
+        std::sort(cost.begin(), cost.end(), std::greater<double>());
+        std::priority_queue<double, std::vector<double>, std::greater<double>> load;
+        for (int64_t k = 0; k < slots; k++) load.push(0.0);
+        double t = 0.0;
+        for (double x : cost) {
+            const double y = load.top() + x;
+            load.pop();
+            load.push(y);
+            t = std::max(t, y);
+        }
+        if (best_t < 0 || t < best_t * (1 - 1e-9)) {
+            best_t = t;
+            best = want;
+        }
+    }
+    return best;
+}
+
+// XCD-aware order of one level's tasks [a, end): work-group t is dispatched
+// to XCD t % kXcds, so tasks with equal key % kXcds (the same contraction
+// piece of a split level, whose L_hat slice they share) land on one XCD and
+// reuse its L2.  Keys travel in Task.pad and are cleared.
+static void xcd_order(std::vector<Task>& g, size_t a)
+{
+    std::vector<std::vector<Task>> bucket(kXcds);
+    for (size_t k = a; k < g.size(); k++) bucket[(size_t)g[k].pad % kXcds].push_back(g[k]);
+    std::vector<size_t> next(kXcds, 0);
+    size_t pos = a;
+    for (size_t t = 0; pos < g.size(); t++) {
+        size_t b = t % kXcds;
+        for (int tries = 0; tries < kXcds && next[b] >= bucket[b].size(); tries++) b = (b + 1) % kXcds;
+        Task x = bucket[b][next[b]++];
+        x.pad = 0;
+        g[pos++] = x;
+    }
 }
 
 // small blocks of a level in groups of four (one per wave of a work-group)
@@ -84,8 +153,19 @@ void build_schedule(selinv_plan_s* P)
         }
         push_sb_groups(small, qSbFactor, P->t_sb.tasks);
         auto fill_for = [](int64_t tiles) { return tiles > 0 && tiles < kFillTiles ? (kFillTiles + tiles - 1) / tiles : 1; };
-        const int64_t want = fill_for(base), dwant = fill_for(dbase);
+        // forward splits from the round model; the reverse sweep fills kFillTiles
+        std::vector<TileGroup> gg, dg;
+        for (int B : lv[l]) {
+            const BlockDesc& d = P->blocks[B];
+            if (is_small(d.s, d.c, kSbS) || d.c == 0) continue;
+            const int bn = tile_bn(d.s), nd = (d.s + kDiagTile - 1) / kDiagTile;
+            gg.push_back({(int64_t)((d.c + kTileM - 1) / kTileM) * ((d.s + bn - 1) / bn), d.c, bn});
+            dg.push_back({(int64_t)nd * (nd + 1) / 2, d.c, kDiagTile});
+        }
+        const int64_t want = best_split(gg, kGemmSlots), dwant = best_split(dg, kSdiagSlots);
         const int64_t rwant = fill_for(rbase_), rdwant = fill_for(rdbase);
+        (void)base;
+        (void)dbase;
         for (int B : lv[l]) {
             const BlockDesc& d = P->blocks[B];
             const int bn = tile_bn(d.s);
@@ -136,14 +216,16 @@ void build_schedule(selinv_plan_s* P)
             for (int j = 0; j < s; j += bn)
                 for (int r = 0; r < c; r += kTileM) {
                     P->t_panel.tasks.push_back({B, r, j, bn, 0, s, 0, 0});
-                    pieces(0, c, split, [&](int kb, int ke, int) {
-                        P->t_gemm.tasks.push_back({B, r, j, bn, kb, ke, split > 1, 0});
+                    // key for the XCD order: the piece, else the row tile
+                    pieces(0, c, split, [&](int kb, int ke, int q) {
+                        P->t_gemm.tasks.push_back({B, r, j, bn, kb, ke, split > 1, split > 1 ? q : r / kTileM});
                     });
                 }
             for (int k = 0; k < c; k += kSchurTile)
                 for (int i = k; i < c; i += kSchurTile)
                     P->t_schur.tasks.push_back({B, i, k, kSchurTile, 0, s, 0, 0});
         }
+        xcd_order(P->t_gemm.tasks, (size_t)P->t_gemm.off[l]);
         // diagonal blocks of the tiled path by width class (one launch each)
         const int64_t cls[] = {32, 64, 1 << 30};
         for (int k = 0; k < 3; k++) {

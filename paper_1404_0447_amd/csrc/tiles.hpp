@@ -20,6 +20,11 @@ constexpr int kSbPerTask = 4;     // small blocks per work-group task (one per w
 inline bool is_small(int s, int c, int smax) { return s <= smax && c <= kSbC; }
 
 constexpr int kFillTiles = 512;  // split the contraction when a level has fewer X tiles
+// resident work-groups of the gather-GEMM and diagonal-tile kernels on the
+// target (256 CUs x 2 and x 6); the per-level split is sized for them
+constexpr long kGemmSlots = 512;
+constexpr long kSdiagSlots = 1536;
+constexpr int kXcds = 8;         // work-group t runs on XCD t % 8
 constexpr int kMinSplitK = 256;  // rows of C per split piece, at least
 
 // output-column tile of a block of width s: 16, 32, 64 or 128
