@@ -47,6 +47,14 @@ __device__ __forceinline__ void mfma_drain()
     __builtin_amdgcn_sched_barrier(0);
 }
 
+// LDS written by some lanes of a wave, then read by others
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 __global__ void k_fill(double* __restrict__ p, int64_t n, double v)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -237,6 +245,111 @@ __device__ __forceinline__ void tile_epilogue(const d4 (&acc)[2][4], F f)
                 f(wm0 + mt * 16 + (lane >> 4) + 4 * v, wn0 + nt * 16 + (lane & 15), acc[mt][nt][v]);
 }
 
+// ---------------------------------------------------------------------------
+// Pipelined 64 x BN MFMA tile: acc += A(64 x K) B(K x BN) over 16-deep
+// chunks, LDS double-buffered with one barrier per chunk.  While the MFMAs
+// consume chunk n, chunk n+1's values (loaded an iteration earlier) go to
+// the other buffer, chunk n+2's values are loaded from the addresses found
+// an iteration earlier, and chunk n+3's addresses are formed.  Loads are
+// unconditional: addrA(k0, kk, ii, ok) / addrB(k0, kk, j, ok) return an
+// in-bounds stand-in when !ok, and the mask is applied at the LDS store.
+// A chunk is read along k (contiguous in k) where alongA(k0) holds, else
+// along i; B along j (kBJ: B(k, j) contiguous in j) or along k.
+// ---------------------------------------------------------------------------
+struct GemmLds {
+    double A[2][TBK][TBM + TPAD];
+    double B[2][TBK][128 + TPAD];
+};
+
+template <int BN, bool kBJ, class FA, class FB, class FAK>
+__device__ __forceinline__ void tile_mma2(GemmLds& L, int Kb, int Ke, d4 (&acc)[2][4], FA addrA, FB addrB,
+                                          FAK alongA)
+{
+    using SH = TileShape<BN>;
+    constexpr int NB = BN / 16;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm0 = (wave % SH::WM) * (TBM / SH::WM), wn0 = (wave / SH::WM) * (BN / SH::WN);
+    const int nch = Ke > Kb ? (Ke - Kb + TBK - 1) / TBK : 0;
+    const double *pa[4], *pb[NB];  // stage ADDR
+    bool oka[4], okb[NB], ala = false;
+    double va[4], vb[NB];          // stage VAL
+    bool vka[4], vkb[NB], vla = false;
+    auto stage_addr = [&](int ch) {
+        const int k0 = Kb + ch * TBK;
+        const bool past = ch >= nch;
+        ala = alongA(k0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = tid + q * kThreads;
+            const int kk = ala ? (e & 15) : (e >> 6), ii = ala ? (e >> 4) : (e & 63);
+            pa[q] = addrA(k0, kk, ii, oka[q]);
+            oka[q] = oka[q] && !past;
+        }
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const int e = tid + q * kThreads;
+            const int kk = kBJ ? e / BN : (e & 15), j = kBJ ? e % BN : (e >> 4);
+            pb[q] = addrB(k0, kk, j, okb[q]);
+            okb[q] = okb[q] && !past;
+        }
+    };
+    auto stage_val = [&]() {
+        vla = ala;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            va[q] = *pa[q];
+            vka[q] = oka[q];
+        }
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            vb[q] = *pb[q];
+            vkb[q] = okb[q];
+        }
+    };
+    auto stage_store = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = tid + q * kThreads;
+            const int kk = vla ? (e & 15) : (e >> 6), ii = vla ? (e >> 4) : (e & 63);
+            L.A[buf][kk][ii] = vka[q] ? va[q] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const int e = tid + q * kThreads;
+            const int kk = kBJ ? e / BN : (e & 15), j = kBJ ? e % BN : (e >> 4);
+            L.B[buf][kk][j] = vkb[q] ? vb[q] : 0.0;
+        }
+    };
+    stage_addr(0);
+    stage_val();
+    stage_store(0);
+    stage_addr(1);
+    stage_val();
+    stage_addr(2);
+    __syncthreads();
+    for (int ch = 0; ch < nch; ++ch) {
+        const int buf = ch & 1;
+#pragma unroll
+        for (int ks = 0; ks < TBK / 4; ++ks) {
+            const int kr = ks * 4 + (lane >> 4);
+            double a[SH::MT], b[SH::NT];
+#pragma unroll
+            for (int mt = 0; mt < SH::MT; ++mt) a[mt] = L.A[buf][kr][wm0 + mt * 16 + (lane & 15)];
+#pragma unroll
+            for (int nt = 0; nt < SH::NT; ++nt) b[nt] = L.B[buf][kr][wn0 + nt * 16 + (lane & 15)];
+#pragma unroll
+            for (int mt = 0; mt < SH::MT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < SH::NT; ++nt) acc[mt][nt] = mfma(a[mt], b[nt], acc[mt][nt]);
+        }
+        stage_store(buf ^ 1);
+        stage_val();
+        stage_addr(ch + 3);
+        __syncthreads();
+    }
+    mfma_drain();
+}
+
 #define SELINV_BN_DISPATCH(bn, CALL) \
     switch (bn) {                    \
         case 16: CALL(16); break;    \
@@ -259,11 +372,6 @@ __device__ __forceinline__ void tile_epilogue(const d4 (&acc)[2][4], F f)
 // (cbase, rbase) pairs of chunk n+4 are loaded: every load has a whole
 // iteration of MFMAs to arrive, and there is one barrier per chunk.
 // ---------------------------------------------------------------------------
-struct GemmLds {
-    double A[2][TBK][TBM + TPAD];
-    double B[2][TBK][128 + TPAD];
-};
-
 template <int BN>
 __device__ void gemm_task(GemmLds& L, const Task t, const BlockDesc d, double* __restrict__ Ap,
                           const double* __restrict__ Hp, const int64_t* __restrict__ cbase,
@@ -417,7 +525,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm(const Task* __restrict__ task
 // L_hat(C,B) = F(C,B) T for rows [i0, i0+64), columns [j0, j0+BN).
 // ---------------------------------------------------------------------------
 template <int BN>
-__device__ void panel_task(TileLds& L, const Task t, const BlockDesc d, const double* __restrict__ Lp,
+__device__ void panel_task(GemmLds& L, const Task t, const BlockDesc d, const double* __restrict__ Lp,
                            double* __restrict__ Hp, const double* __restrict__ Tp)
 {
     const int s = d.s, c = d.c;
@@ -426,15 +534,17 @@ __device__ void panel_task(TileLds& L, const Task t, const BlockDesc d, const do
     d4 acc[2][4] = {};
     const double* F = Lp + d.poff + s;
     const double* T = Tp + d.woff;
-    auto loadA = [&](int k0, int kk, int ii) -> double {
+    auto addrA = [&](int k0, int kk, int ii, bool& ok) -> const double* {
         const int i = r0 + ii, k = k0 + kk;
-        return (i < c && k < s) ? F[i + k * ld] : 0.0;
+        ok = i < c && k < s;
+        return ok ? F + i + (int64_t)k * ld : F;
     };
-    auto loadB = [&](int k0, int kk, int j) -> double {
+    auto addrB = [&](int k0, int kk, int j, bool& ok) -> const double* {
         const int k = k0 + kk, jj = n0 + j;
-        return (k < s && jj < s) ? T[k + jj * s] : 0.0;
+        ok = k < s && jj < s;
+        return ok ? T + k + (int64_t)jj * s : T;
     };
-    tile_mma<BN>(L, 0, s, acc, loadA, loadB, [](int) { return false; });
+    tile_mma2<BN, false>(L, 0, s, acc, addrA, addrB, [](int) { return false; });
     tile_epilogue<BN>(acc, [&](int i, int j, double v) {
         const int ii = r0 + i, jj = n0 + j;
         if (ii < c && jj < s) Hp[d.hoff + ii + (int64_t)jj * c] = v;
@@ -445,7 +555,7 @@ __global__ __launch_bounds__(kThreads) void k_panel(const Task* __restrict__ tas
                                                     const BlockDesc* __restrict__ blk, const double* __restrict__ Lp,
                                                     double* __restrict__ Hp, const double* __restrict__ Tp)
 {
-    __shared__ TileLds L;
+    __shared__ GemmLds L;
     const Task t = tasks[blockIdx.x];
     const BlockDesc d = blk[t.b];
 #define SELINV_CALL(BN) panel_task<BN>(L, t, d, Lp, Hp, Tp)
@@ -456,10 +566,11 @@ __global__ __launch_bounds__(kThreads) void k_panel(const Task* __restrict__ tas
 // ---------------------------------------------------------------------------
 // Factor, Schur update: F(C,C) -= L(C,B) D_B L(C,B)^T = L_hat(C,B) F(C,B)^T,
 // lower half, tile rows [i0, i0+64) x columns [k0, k0+64), added into the
-// ancestor panels through the block index maps.  FP64 atomics: sibling
-// blocks of one level may update the same ancestor entry.
+// ancestor panels through the block index maps.  FP64 atomics where sibling
+// blocks of the level may update the same ancestor entry; plain
+// read-modify-write for blocks the host found exclusive (flags bit 2).
 // ---------------------------------------------------------------------------
-__device__ void schur_task(TileLds& L, const Task t, const BlockDesc d, double* __restrict__ Lp,
+__device__ void schur_task(GemmLds& L, const Task t, const BlockDesc d, double* __restrict__ Lp,
                            const double* __restrict__ Hp, const int64_t* __restrict__ cbase,
                            const int64_t* __restrict__ rbase, const int32_t* __restrict__ rel)
 {
@@ -469,20 +580,25 @@ __device__ void schur_task(TileLds& L, const Task t, const BlockDesc d, double* 
     const double* H = Hp + d.hoff;
     const double* F = Lp + d.poff + s;
     d4 acc[2][4] = {};
-    auto loadA = [&](int t0, int tt, int ii) -> double {
+    auto addrA = [&](int t0, int tt, int ii, bool& ok) -> const double* {
         const int i = i0 + ii, k = t0 + tt;
-        return (i < c && k < s) ? H[i + (int64_t)k * c] : 0.0;
+        ok = i < c && k < s;
+        return ok ? H + i + (int64_t)k * c : H;
     };
-    auto loadB = [&](int t0, int tt, int j) -> double {
+    // B(t, j) = F(k0c + j, t): contiguous in j
+    auto addrB = [&](int t0, int tt, int j, bool& ok) -> const double* {
         const int k = k0c + j, col = t0 + tt;
-        return (k < c && col < s) ? F[k + col * ld] : 0.0;
+        ok = k < c && col < s;
+        return ok ? F + k + (int64_t)col * ld : F;
     };
-    tile_mma<64>(L, 0, s, acc, loadA, loadB, [](int) { return false; });
+    tile_mma2<64, true>(L, 0, s, acc, addrA, addrB, [](int) { return false; });
     tile_epilogue<64>(acc, [&](int i, int j, double v) {
         const int ii = i0 + i, kk = k0c + j;
         if (ii < c && kk < c && ii >= kk) {
             const int64_t pk = d.coff + kk;
-            unsafeAtomicAdd(Lp + cbase[pk] + rel[rbase[pk] + ii], -v);
+            double* x = Lp + cbase[pk] + rel[rbase[pk] + ii];
+            if (t.flags & 4) *x -= v;  // no other block of the level updates this entry
+            else unsafeAtomicAdd(x, -v);
         }
     });
 }
@@ -494,7 +610,7 @@ __global__ __launch_bounds__(kThreads) void k_schur(const Task* __restrict__ tas
                                                     const int64_t* __restrict__ rbase,
                                                     const int32_t* __restrict__ rel)
 {
-    __shared__ TileLds L;
+    __shared__ GemmLds L;
     const Task t = tasks[blockIdx.x];
     schur_task(L, t, blk[t.b], Lp, Hp, cbase, rbase, rel);
 }
@@ -776,14 +892,6 @@ struct SbLds {
     double L[16][17];
 };
 
-// LDS written by some lanes of a wave, then read by others
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
 __device__ void sb_factor(const BlockDesc d, double* __restrict__ Lp, double* __restrict__ Hp,
                           double* __restrict__ Tp, const int64_t* __restrict__ cbase,
                           const int64_t* __restrict__ rbase, const int32_t* __restrict__ rel,
@@ -1063,7 +1171,7 @@ __device__ __forceinline__ void diag_block(const BlockDesc& d, double* Lp, doubl
 
 // L_hat tile; tiles are at most as wide as the level's widest block
 template <int NB>
-__device__ __forceinline__ void panel_bounded(TileLds& L, const Task& t, const BlockDesc& d, const double* Lp,
+__device__ __forceinline__ void panel_bounded(GemmLds& L, const Task& t, const BlockDesc& d, const double* Lp,
                                               double* Hp, const double* Tp)
 {
     if (t.bn <= 16) {
@@ -1095,7 +1203,7 @@ __device__ __forceinline__ void gemm_bounded(GemmLds& L, const Task& t, const Bl
 // Levels with tiled blocks; NB bounds the diagonal sweep (s <= 16 NB, wider
 // blocks take ldlt_global) and so the kernel's registers.
 template <int NB>
-__global__ __launch_bounds__(kThreads) void k_persist_factor(const QueueArgs a, const BlockDesc* __restrict__ blk,
+__global__ __launch_bounds__(kThreads, NB < 8 ? 2 : 1) void k_persist_factor(const QueueArgs a, const BlockDesc* __restrict__ blk,
                                                              double* __restrict__ Lp, double* __restrict__ Wp,
                                                              double* __restrict__ Hp, double* __restrict__ Tp,
                                                              const int64_t* __restrict__ cbase,
@@ -1139,7 +1247,7 @@ __global__ __launch_bounds__(kThreads) void k_persist_factor(const QueueArgs a, 
                     if (++pr == nrow) pr = 0, ++pj;
                 } else {
                     o = qSchur;
-                    u = Task{t.b, si * kSchurTile, sk * kSchurTile, kSchurTile, 0, d.s, 0, 0};
+                    u = Task{t.b, si * kSchurTile, sk * kSchurTile, kSchurTile, 0, d.s, t.flags & 4, 0};
                     if (++si == nsc) si = ++sk;
                 }
             }
@@ -1148,10 +1256,10 @@ __global__ __launch_bounds__(kThreads) void k_persist_factor(const QueueArgs a, 
                     diag_block<NB>(d, Lp, Wp, Tp, a.status, a.require_spd, sm.colbuf);
                     break;
                 case qPanel:
-                    panel_bounded<NB>(sm.tile, u, d, Lp, Hp, Tp);
+                    panel_bounded<NB>(sm.gemm, u, d, Lp, Hp, Tp);
                     break;
                 default:
-                    schur_task(sm.tile, u, d, Lp, Hp, cbase, rbase, rel);
+                    schur_task(sm.gemm, u, d, Lp, Hp, cbase, rbase, rel);
                     break;
             }
             if (whole) __syncthreads();

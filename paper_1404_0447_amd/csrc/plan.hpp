@@ -42,7 +42,8 @@ struct Task {
     int32_t i0, j0;  // tile origin (rows, columns)
     int32_t bn;      // tile width (16, 32, 64, 128)
     int32_t kb, ke;  // contraction range [kb, ke)
-    int32_t flags;   // bit 0: accumulate atomically (split contraction)
+    int32_t flags;   // bit 0: accumulate atomically (split contraction); bit 2: the
+                     // block's Schur update is exclusive in its level (no atomics)
     int32_t pad;
 };
 

@@ -91,6 +91,32 @@ static int64_t best_split(const std::vector<TileGroup>& groups, int64_t slots)
     return best;
 }
 
+// Blocks of one level whose Schur updates no other block of the level
+// touches: two blocks update a common ancestor entry exactly when their row
+// structures C share a column (the diagonal entry of that column), so a
+// block is exclusive when every column of its C is in no other block's C.
+// Exclusive blocks add their updates with plain read-modify-write instead
+// of atomics.
+static void exclusive_blocks(const selinv_plan_s* P, const std::vector<int>& bl, std::vector<int32_t>& touch,
+                             std::vector<char>& excl)
+{
+    const std::vector<int32_t>& cr = P->crow;
+    for (int B : bl) {
+        const BlockDesc& d = P->blocks[B];
+        for (int r = 0; r < d.c; r++) touch[cr[d.coff + r]]++;
+    }
+    for (int B : bl) {
+        const BlockDesc& d = P->blocks[B];
+        bool ok = true;
+        for (int r = 0; r < d.c && ok; r++) ok = touch[cr[d.coff + r]] == 1;
+        excl[B] = ok;
+    }
+    for (int B : bl) {
+        const BlockDesc& d = P->blocks[B];
+        for (int r = 0; r < d.c; r++) touch[cr[d.coff + r]] = 0;
+    }
+}
+
 // XCD-aware order of one level's tasks [a, end): work-group t is dispatched
 // to XCD t % kXcds, so tasks with equal key % kXcds (the same contraction
 // piece of a split level, whose L_hat slice they share) land on one XCD and
@@ -133,7 +159,10 @@ void build_schedule(selinv_plan_s* P)
     }
     P->t_zero.clear();
     P->ldlt_cut.assign(2 * D, 0);
+    std::vector<int32_t> touch((size_t)P->n, 0);
+    std::vector<char> excl(P->blocks.size(), 0);
     for (int l = 0; l < D; l++) {
+        exclusive_blocks(P, lv[l], touch, excl);
         // tiles this level has without splitting contractions over C: of the
         // tiled forward path, and of the reverse sweep (every block)
         int64_t base = 0, dbase = 0, rbase_ = 0, rdbase = 0;
@@ -223,7 +252,7 @@ void build_schedule(selinv_plan_s* P)
                 }
             for (int k = 0; k < c; k += kSchurTile)
                 for (int i = k; i < c; i += kSchurTile)
-                    P->t_schur.tasks.push_back({B, i, k, kSchurTile, 0, s, 0, 0});
+                    P->t_schur.tasks.push_back({B, i, k, kSchurTile, 0, s, excl[B] ? 4 : 0, 0});
         }
         xcd_order(P->t_gemm.tasks, (size_t)P->t_gemm.off[l]);
         // diagonal blocks of the tiled path by width class (one launch each)
@@ -340,6 +369,8 @@ void build_queues(const selinv_plan_s* P, const Sched& sc, std::vector<Task>& qf
     const int cap = std::max(16, std::min(128, sc.bn_cap));
     auto bn_of = [&](int s) { return std::min(tile_bn(s), cap); };
     std::vector<Task> ph[3];
+    std::vector<int32_t> touch((size_t)P->n, 0);
+    std::vector<char> excl(P->blocks.size(), 0);
     auto flush = [&](std::vector<Task>& q) {
         for (auto& p : ph) {
             if (sc.order == qoTileLpt)
@@ -351,6 +382,7 @@ void build_queues(const selinv_plan_s* P, const Sched& sc, std::vector<Task>& qf
     for (int l = 0; l < D; l++) {
         std::vector<int> bl = lv[l];
         order_blocks(P, sc.order, bl);
+        exclusive_blocks(P, bl, touch, excl);
         std::vector<int> small, medium, big;
         for (int B : bl) {
             const BlockDesc& d = P->blocks[B];
@@ -364,7 +396,8 @@ void build_queues(const selinv_plan_s* P, const Sched& sc, std::vector<Task>& qf
         // work-group; big ones as diagonal block, then L_hat tiles, then
         // Schur tiles
         push_sb_groups(small, qSbFactor, ph[0]);
-        for (int B : medium) ph[0].push_back({B, 0, 0, bn_of(P->blocks[B].s), 0, 0, q_flags(qMbFactor, 0), 0});
+        for (int B : medium)
+            ph[0].push_back({B, 0, 0, bn_of(P->blocks[B].s), 0, 0, q_flags(qMbFactor, excl[B] ? 4 : 0), 0});
         for (int B : big) {
             const BlockDesc& d = P->blocks[B];
             const int bn = bn_of(d.s);
@@ -374,7 +407,7 @@ void build_queues(const selinv_plan_s* P, const Sched& sc, std::vector<Task>& qf
                 for (int r = 0; r < d.c; r += kTileM) ph[1].push_back({B, r, j, bn, 0, d.s, q_flags(qPanel, 2), 1});
             for (int k = 0; k < d.c; k += kSchurTile)
                 for (int i = k; i < d.c; i += kSchurTile)
-                    ph[2].push_back({B, i, k, kSchurTile, 0, d.s, q_flags(qSchur, 0), 1 + npanel});
+                    ph[2].push_back({B, i, k, kSchurTile, 0, d.s, q_flags(qSchur, excl[B] ? 4 : 0), 1 + npanel});
         }
         flush(qf);
         qf_off[l + 1] = (int64_t)qf.size();

@@ -101,11 +101,28 @@ def _block_matrix(p):
     return np.searchsorted(p.n_off, first, side="right") - 1
 
 
+def _exclusive(blk, level):
+    """Blocks of a level whose row structure C shares no column with another
+    block's C in that level (their Schur updates touch no common entry)."""
+    lev, c, off, rows = blk["level"], blk["c"], blk["crow_off"], blk["rows"]
+    ids = np.nonzero(lev == level)[0]
+    cnt = {}
+    for B in ids:
+        for x in rows[off[B]:off[B] + c[B]]:
+            cnt[int(x)] = cnt.get(int(x), 0) + 1
+    return {int(B) for B in ids if all(cnt[int(x)] == 1 for x in rows[off[B]:off[B] + c[B]])}
+
+
 def check_queues(p, sched=None):
     blk = p.blocks()
     lev, s, c = blk["level"], blk["s"], blk["c"]
     sched = sched or p.schedule()
     for l in range(1, int(p.info["exec_depth"]) + 1):
+        excl = _exclusive(blk, l)
+        qf = p.queue(0, l)
+        for row in qf:
+            if S.QOPS[row[6] >> 8] in ("schur", "mbfactor"):
+                assert bool(row[6] & 4) == (int(row[0]) in excl), "exclusive-update flag"
         for sweep, phases, sb_op, mb_op in ((0, ("ldlt", "panel", "schur"), "sbfactor", "mbfactor"),
                                             (1, ("zero", "gemm", "sdiag"), "sbinvert", "mbinvert")):
             q = p.queue(sweep, l)
