@@ -15,8 +15,11 @@ ARCH = os.environ.get("SELINV_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
 # packed FP32 instructions stay off in device code (hipcc -O3 would otherwise form them)
+# MFMA accumulators are kept in the architectural VGPRs: with the default
+# heuristic a loop-carried accumulator lives in VGPRs between iterations and
+# is copied to and from AGPRs around every chunk of MFMAs.
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-          "-munsafe-fp-atomics"]
+          "-munsafe-fp-atomics", "-mllvm", "-amdgpu-mfma-vgpr-form"]
 
 
 def build(verbose: bool = False) -> str:

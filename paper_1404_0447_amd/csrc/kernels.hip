@@ -88,7 +88,7 @@ __global__ void k_gather(const double* __restrict__ src, const int64_t* __restri
 // Blocks whose contractions are split over several work-groups accumulate:
 // X = Ainv(C,B) := 0 and the lower triangle of Ainv(B,B) := T.  One wave per
 // column, lanes along its rows.
-__device__ void zero_task(const BlockDesc d, double* __restrict__ Ap, const double* __restrict__ Tp)
+__device__ __forceinline__ void zero_task(const BlockDesc d, double* __restrict__ Ap, const double* __restrict__ Tp)
 {
     const int64_t ld = (int64_t)d.s + d.c;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -373,7 +373,7 @@ __device__ __forceinline__ void tile_mma2(GemmLds& L, int Kb, int Ke, d4 (&acc)[
 // iteration of MFMAs to arrive, and there is one barrier per chunk.
 // ---------------------------------------------------------------------------
 template <int BN>
-__device__ void gemm_task(GemmLds& L, const Task t, const BlockDesc d, double* __restrict__ Ap,
+__device__ __forceinline__ void gemm_task(GemmLds& L, const Task t, const BlockDesc d, double* __restrict__ Ap,
                           const double* __restrict__ Hp, const int64_t* __restrict__ cbase,
                           const int64_t* __restrict__ rbase, const int32_t* __restrict__ rel)
 {
@@ -525,7 +525,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm(const Task* __restrict__ task
 // L_hat(C,B) = F(C,B) T for rows [i0, i0+64), columns [j0, j0+BN).
 // ---------------------------------------------------------------------------
 template <int BN>
-__device__ void panel_task(GemmLds& L, const Task t, const BlockDesc d, const double* __restrict__ Lp,
+__device__ __forceinline__ void panel_task(GemmLds& L, const Task t, const BlockDesc d, const double* __restrict__ Lp,
                            double* __restrict__ Hp, const double* __restrict__ Tp)
 {
     const int s = d.s, c = d.c;
@@ -570,7 +570,7 @@ __global__ __launch_bounds__(kThreads) void k_panel(const Task* __restrict__ tas
 // blocks of the level may update the same ancestor entry; plain
 // read-modify-write for blocks the host found exclusive (flags bit 2).
 // ---------------------------------------------------------------------------
-__device__ void schur_task(GemmLds& L, const Task t, const BlockDesc d, double* __restrict__ Lp,
+__device__ __forceinline__ void schur_task(GemmLds& L, const Task t, const BlockDesc d, double* __restrict__ Lp,
                            const double* __restrict__ Hp, const int64_t* __restrict__ cbase,
                            const int64_t* __restrict__ rbase, const int32_t* __restrict__ rel)
 {
@@ -628,7 +628,7 @@ struct SdiagLds {
     double Sx[SDT][SDT + 1];
 };
 
-__device__ void sdiag_task(SdiagLds& S, const Task t, const BlockDesc d, double* __restrict__ Ap,
+__device__ __forceinline__ void sdiag_task(SdiagLds& S, const Task t, const BlockDesc d, double* __restrict__ Ap,
                            const double* __restrict__ Hp, const double* __restrict__ Tp)
 {
     auto& LI = S.LI;
@@ -768,93 +768,134 @@ __device__ void ldlt_global(const BlockDesc d, double* __restrict__ Lp, double* 
 }
 
 // Diagonal block, s <= 16 NB (NB = 2, 4, 8), by symmetric Gauss-Jordan
-// sweeps held in registers.  Thread (tx, ty) = (tid % 16, tid / 16) owns
-// M(tx + 16a, ty + 16b), a, b < NB (the kernel's registers follow NB).  Sweeping pivot j (M(j,j) = d_j, c = M(:,j)):
+// sweeps held in registers.  Sweeping pivot j (M(j,j) = d_j, c = M(:,j)):
 //   M(i,k) -= c_i c_k / d_j  (i, k != j),  M(i,j) = M(j,i) = c_i / d_j,
 //   M(j,j) = -1 / d_j.
 // After all pivots M = -F_BB^{-1} = -T.  Before its own sweep, column j
 // below the diagonal holds the Schur-complement column, so the multipliers
 // c_i / d_j (i > j) are L_BB(i,j) and d_j is D's entry: both are written
-// out as they appear.  One LDS broadcast of column j and one barrier per
-// pivot (the column buffer alternates between two slots).
+// out as they appear.
+//
+// M stays symmetric, so only its lower 16 x 16 sub-blocks are held: thread
+// (tx, ty) = (tid % 16, tid / 16) owns M(tx + 16a, ty + 16b) for a >= b
+// (a diagonal sub-block whole).  Column j is then spread over two groups of
+// threads: ty == j % 16 holds rows >= 16 (j / 16) in sub-blocks (a, j / 16),
+// tx == j % 16 holds the rows above as row j of sub-blocks (j / 16, b).
+// The sweep is latency-bound (one pivot after the other), so each pivot
+// first forms the next pivot's column and publishes it in LDS (two
+// alternating slots, one barrier per pivot), then issues the LDS reads of
+// that column, and only then updates the rest of its registers while the
+// reads are in flight.
 template <int NB>
-__device__ void ldlt_sweep(const BlockDesc d, double* __restrict__ Lp, double* __restrict__ Tp,
+__device__ __forceinline__ void ldlt_sweep(const BlockDesc d, double* __restrict__ Lp, double* __restrict__ Tp,
                            unsigned long long* __restrict__ status, int require_spd, double (*colbuf)[kLdsDiagMax])
 {
+    constexpr int NS = NB * (NB + 1) / 2;
     const int s = d.s;
     const int64_t ld = (int64_t)d.s + d.c;
     double* F = Lp + d.poff;
     double* T = Tp + d.woff;
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-    double M[NB][NB];
+    auto slot = [](int a, int b) { return a * (a + 1) / 2 + b; };
+    double M[NS];
 #pragma unroll
     for (int a = 0; a < NB; ++a)
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
+        for (int b = 0; b <= a; ++b) {
             const int i = tx + 16 * a, k = ty + 16 * b;
             double v = 0.0;
             if (i < s && k < s) v = i >= k ? F[i + k * ld] : F[k + i * ld];
-            M[a][b] = v;
+            M[slot(a, b)] = v;
         }
-    // pivots j = 16 jb + jt: jb is unrolled, so the pivot's register row
-    // (a == jb) and column (b == jb) are known at compile time
+    // column 0 to slot 0; its reads
+    if (ty == 0) {
+#pragma unroll
+        for (int a = 0; a < NB; ++a) colbuf[0][tx + 16 * a] = M[slot(a, 0)];
+    }
+    __syncthreads();
+    double ri_[NB], rk_[NB], rd;  // the pivot column as read: rows tx + 16a, ty + 16b, and d_j
+#pragma unroll
+    for (int a = 0; a < NB; ++a) ri_[a] = colbuf[0][tx + 16 * a];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) rk_[b] = colbuf[0][ty + 16 * b];
+    rd = colbuf[0][0];
 #pragma unroll
     for (int jb = 0; jb < NB; ++jb) {
         const int jt_end = min(16, s - 16 * jb);
         for (int jt = 0; jt < jt_end; ++jt) {
             const int j = 16 * jb + jt;
-            double* buf = colbuf[j & 1];
-            if (ty == jt) {
-#pragma unroll
-                for (int a = 0; a < NB; ++a) buf[tx + 16 * a] = M[a][jb];
-            }
-            __syncthreads();
-            const double dj = buf[j];
+            const double dj = rd;
             const double inv = 1.0 / dj;
+            double ci[NB], ck[NB];
+#pragma unroll
+            for (int a = 0; a < NB; ++a) ci[a] = ri_[a] * inv;  // c_i / d_j
+#pragma unroll
+            for (int b = 0; b < NB; ++b) ck[b] = rk_[b];
             if (tid == 0) {
                 const bool ok = isfinite(dj) && dj != 0.0 && (!require_spd || dj > 0.0);
                 if (!ok) atomicMin(status, (unsigned long long)(d.first + j));
             }
-            double ci[NB], ck[NB];
-#pragma unroll
-            for (int a = 0; a < NB; ++a) ci[a] = buf[tx + 16 * a] * inv;  // c_i / d_j
-#pragma unroll
-            for (int b = 0; b < NB; ++b) ck[b] = buf[ty + 16 * b];
             if (ty == jt) {  // column j of L_BB and D
 #pragma unroll
-                for (int a = 0; a < NB; ++a) {
+                for (int a = jb; a < NB; ++a) {
                     const int i = tx + 16 * a;
                     if (i > j && i < s) F[i + (int64_t)j * ld] = ci[a];
                 }
                 if (tx == 0) F[j + (int64_t)j * ld] = dj;
             }
-            const bool ri = tx == jt, rk = ty == jt;  // this lane holds row j / column j
+            // M(tx + 16a, ty + 16b) after this pivot (a, b known at compile time)
+            auto after = [&](int a, int b) {
+                const bool ri = a == jb && tx == jt, rk = b == jb && ty == jt;
+                const double upd = M[slot(a, b)] - ci[a] * ck[b];
+                return (ri && rk) ? -inv : (ri ? ck[b] * inv : (rk ? ci[a] : upd));
+            };
+            // the next pivot's column, published before the bulk update
+            const bool more = j + 1 < s;
+            double* nb = colbuf[(j + 1) & 1];
+            if (more) {
+                if (jt + 1 < 16) {
+                    if (ty == jt + 1) {
+#pragma unroll
+                        for (int a = jb; a < NB; ++a) nb[tx + 16 * a] = after(a, jb);
+                    }
+                    if (tx == jt + 1) {
+#pragma unroll
+                        for (int b = 0; b < jb; ++b) nb[ty + 16 * b] = after(jb, b);
+                    }
+                } else if (jb + 1 < NB) {
+                    if (ty == 0) {
+#pragma unroll
+                        for (int a = jb + 1; a < NB; ++a) nb[tx + 16 * a] = after(a, jb + 1);
+                    }
+                    if (tx == 0) {
+#pragma unroll
+                        for (int b = 0; b < jb + 1; ++b) nb[ty + 16 * b] = after(jb + 1, b);
+                    }
+                }
+            }
+            __syncthreads();
+            if (more) {
+#pragma unroll
+                for (int a = 0; a < NB; ++a) ri_[a] = nb[tx + 16 * a];
+#pragma unroll
+                for (int b = 0; b < NB; ++b) rk_[b] = nb[ty + 16 * b];
+                rd = nb[j + 1];
+            }
 #pragma unroll
             for (int a = 0; a < NB; ++a)
 #pragma unroll
-                for (int b = 0; b < NB; ++b) {
-                    const double upd = M[a][b] - ci[a] * ck[b];
-                    if (a == jb && b == jb) {
-                        M[a][b] = (ri && rk) ? -inv : (ri ? ck[b] * inv : (rk ? ci[a] : upd));
-                    } else if (a == jb) {
-                        M[a][b] = ri ? ck[b] * inv : upd;
-                    } else if (b == jb) {
-                        M[a][b] = rk ? ci[a] : upd;
-                    } else {
-                        M[a][b] = upd;
-                    }
-                }
+                for (int b = 0; b <= a; ++b) M[slot(a, b)] = after(a, b);
         }
     }
     // T = -M, made exactly symmetric from the lower triangle
 #pragma unroll
     for (int a = 0; a < NB; ++a)
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
+        for (int b = 0; b <= a; ++b) {
             const int i = tx + 16 * a, k = ty + 16 * b;
             if (i < s && k < s && i >= k) {
-                T[i + (int64_t)k * s] = -M[a][b];
-                T[k + (int64_t)i * s] = -M[a][b];
+                T[i + (int64_t)k * s] = -M[slot(a, b)];
+                T[k + (int64_t)i * s] = -M[slot(a, b)];
             }
         }
 }
