@@ -261,9 +261,9 @@ struct GemmLds {
     double B[2][TBK][128 + TPAD];
 };
 
-template <int BN, bool kBJ, class FA, class FB, class FAK>
+template <int BN, bool kBJ, class FA, class FB, class FAK, class FH>
 __device__ __forceinline__ void tile_mma2(GemmLds& L, int Kb, int Ke, d4 (&acc)[2][4], FA addrA, FB addrB,
-                                          FAK alongA)
+                                          FAK alongA, FH afterPrologue)
 {
     using SH = TileShape<BN>;
     constexpr int NB = BN / 16;
@@ -326,6 +326,7 @@ __device__ __forceinline__ void tile_mma2(GemmLds& L, int Kb, int Ke, d4 (&acc)[
     stage_addr(1);
     stage_val();
     stage_addr(2);
+    afterPrologue();  // loads of the caller's own that may run under the main loop
     __syncthreads();
     for (int ch = 0; ch < nch; ++ch) {
         const int buf = ch & 1;
@@ -544,7 +545,7 @@ __device__ __forceinline__ void panel_task(GemmLds& L, const Task t, const Block
         ok = k < s && jj < s;
         return ok ? T + k + (int64_t)jj * s : T;
     };
-    tile_mma2<BN, false>(L, 0, s, acc, addrA, addrB, [](int) { return false; });
+    tile_mma2<BN, false>(L, 0, s, acc, addrA, addrB, [](int) { return false; }, [] {});
     tile_epilogue<BN>(acc, [&](int i, int j, double v) {
         const int ii = r0 + i, jj = n0 + j;
         if (ii < c && jj < s) Hp[d.hoff + ii + (int64_t)jj * c] = v;
@@ -569,16 +570,46 @@ __global__ __launch_bounds__(kThreads) void k_panel(const Task* __restrict__ tas
 // ancestor panels through the block index maps.  FP64 atomics where sibling
 // blocks of the level may update the same ancestor entry; plain
 // read-modify-write for blocks the host found exclusive (flags bit 2).
+// The scatter targets do not depend on the product: their (cbase, rbase)
+// pairs are loaded before the main loop and the rel entries right after its
+// prologue, so the index chain is off the critical path and the epilogue
+// issues only the updates.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void schur_task(GemmLds& L, const Task t, const BlockDesc d, double* __restrict__ Lp,
                            const double* __restrict__ Hp, const int64_t* __restrict__ cbase,
                            const int64_t* __restrict__ rbase, const int32_t* __restrict__ rel)
 {
+    using SH = TileShape<64>;
     const int s = d.s, c = d.c;
     const int64_t ld = (int64_t)s + c;
     const int i0 = t.i0, k0c = t.j0;
     const double* H = Hp + d.hoff;
     const double* F = Lp + d.poff + s;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm0 = (wave % SH::WM) * (TBM / SH::WM), wn0 = (wave / SH::WM) * (64 / SH::WN);
+    // this thread's outputs: rows i0 + wm0 + 16 mt + lane / 16 + 4 v, columns k0 + wn0 + 16 nt + lane % 16
+    int64_t cb[SH::NT], rb[SH::NT];
+#pragma unroll
+    for (int nt = 0; nt < SH::NT; ++nt) {
+        const int kk = k0c + wn0 + nt * 16 + (lane & 15);
+        const int64_t pk = d.coff + (kk < c ? kk : 0);
+        cb[nt] = cbase[pk];
+        rb[nt] = rbase[pk];
+    }
+    int32_t ro[SH::MT][SH::NT][4];
+    auto prefetch = [&]() {
+#pragma unroll
+        for (int mt = 0; mt < SH::MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < SH::NT; ++nt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int ii = i0 + wm0 + mt * 16 + (lane >> 4) + 4 * v;
+                    const int kk = k0c + wn0 + nt * 16 + (lane & 15);
+                    const bool ok = ii < c && kk < c && ii >= kk;
+                    ro[mt][nt][v] = rel[rb[nt] + (ok ? ii : 0)];
+                }
+    };
     d4 acc[2][4] = {};
     auto addrA = [&](int t0, int tt, int ii, bool& ok) -> const double* {
         const int i = i0 + ii, k = t0 + tt;
@@ -591,16 +622,66 @@ __device__ __forceinline__ void schur_task(GemmLds& L, const Task t, const Block
         ok = k < c && col < s;
         return ok ? F + k + (int64_t)col * ld : F;
     };
-    tile_mma2<64, true>(L, 0, s, acc, addrA, addrB, [](int) { return false; });
-    tile_epilogue<64>(acc, [&](int i, int j, double v) {
-        const int ii = i0 + i, kk = k0c + j;
-        if (ii < c && kk < c && ii >= kk) {
-            const int64_t pk = d.coff + kk;
-            double* x = Lp + cbase[pk] + rel[rbase[pk] + ii];
-            if (t.flags & 4) *x -= v;  // no other block of the level updates this entry
-            else unsafeAtomicAdd(x, -v);
+    tile_mma2<64, true>(L, 0, s, acc, addrA, addrB, [](int) { return false; }, prefetch);
+    auto live = [&](int mt, int nt, int v) {
+        const int ii = i0 + wm0 + mt * 16 + (lane >> 4) + 4 * v;
+        const int kk = k0c + wn0 + nt * 16 + (lane & 15);
+        return ii < c && kk < c && ii >= kk;
+    };
+    auto target = [&](int mt, int nt, int v) { return Lp + cb[nt] + ro[mt][nt][v]; };
+    // a tile strictly below the diagonal and inside C has every entry live:
+    // its updates are issued without per-entry branches, which would put a
+    // wait on all outstanding memory operations in front of every store
+    const bool full = i0 > k0c && i0 + TBM <= c;
+    if (t.flags & 4) {
+        // no other block of the level updates these entries: plain
+        // read-modify-write, all reads issued before the first write (the
+        // targets of one thread are distinct entries)
+        double old[SH::MT][SH::NT][4];
+        if (full) {
+#pragma unroll
+            for (int mt = 0; mt < SH::MT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < SH::NT; ++nt)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) old[mt][nt][v] = *target(mt, nt, v);
+#pragma unroll
+            for (int mt = 0; mt < SH::MT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < SH::NT; ++nt)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) *target(mt, nt, v) = old[mt][nt][v] - acc[mt][nt][v];
+        } else {
+#pragma unroll
+            for (int mt = 0; mt < SH::MT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < SH::NT; ++nt)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) old[mt][nt][v] = live(mt, nt, v) ? *target(mt, nt, v) : 0.0;
+#pragma unroll
+            for (int mt = 0; mt < SH::MT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < SH::NT; ++nt)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        if (live(mt, nt, v)) *target(mt, nt, v) = old[mt][nt][v] - acc[mt][nt][v];
         }
-    });
+    } else if (full) {
+#pragma unroll
+        for (int mt = 0; mt < SH::MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < SH::NT; ++nt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) unsafeAtomicAdd(target(mt, nt, v), -acc[mt][nt][v]);
+    } else {
+#pragma unroll
+        for (int mt = 0; mt < SH::MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < SH::NT; ++nt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    if (live(mt, nt, v)) unsafeAtomicAdd(target(mt, nt, v), -acc[mt][nt][v]);
+    }
 }
 
 __global__ __launch_bounds__(kThreads) void k_schur(const Task* __restrict__ tasks,

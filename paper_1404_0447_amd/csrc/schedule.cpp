@@ -55,8 +55,12 @@ struct TileGroup {
 // on `slots` resident places, so a level whose count is just above a
 // multiple of slots pays a nearly empty round.  Pick the request whose
 // greedy list schedule (largest first onto the least loaded place; cost =
-// 16-row chunks times tile width) finishes first.
-static int64_t best_split(const std::vector<TileGroup>& groups, int64_t slots)
+// (16-row chunks + ovh) times tile width) finishes first.  ovh is the fixed
+// cost of one work-group in chunk times: the exposed latency of its first
+// loads and its epilogue (atomic for a split contraction); measured on the
+// gathered GEMM it is about seven chunks, so splitting stops paying once
+// the pieces get short.
+static int64_t best_split(const std::vector<TileGroup>& groups, int64_t slots, double ovh)
 {
     int64_t base = 0;
     for (const TileGroup& g : groups) base += g.count;
@@ -70,7 +74,7 @@ static int64_t best_split(const std::vector<TileGroup>& groups, int64_t slots)
             const int sp = split_for(want, g.c), n16 = (g.c + 15) / 16;
             for (int q = 0; q < sp; q++) {
                 const int len = (int)((int64_t)n16 * (q + 1) / sp - (int64_t)n16 * q / sp);
-                for (int64_t k = 0; k < g.count; k++) cost.push_back((double)len * g.w);
+                for (int64_t k = 0; k < g.count; k++) cost.push_back((len + ovh) * g.w);
             }
         }
         std::sort(cost.begin(), cost.end(), std::greater<double>());
@@ -191,7 +195,7 @@ void build_schedule(selinv_plan_s* P)
             gg.push_back({(int64_t)((d.c + kTileM - 1) / kTileM) * ((d.s + bn - 1) / bn), d.c, bn});
             dg.push_back({(int64_t)nd * (nd + 1) / 2, d.c, kDiagTile});
         }
-        const int64_t want = best_split(gg, kGemmSlots), dwant = best_split(dg, kSdiagSlots);
+        const int64_t want = best_split(gg, kGemmSlots, kGemmTaskOvh), dwant = best_split(dg, kSdiagSlots, kSdiagTaskOvh);
         const int64_t rwant = fill_for(rbase_), rdwant = fill_for(rdbase);
         (void)base;
         (void)dbase;
