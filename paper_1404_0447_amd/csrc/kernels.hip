@@ -570,10 +570,14 @@ __global__ __launch_bounds__(kThreads) void k_panel(const Task* __restrict__ tas
 // ancestor panels through the block index maps.  FP64 atomics where sibling
 // blocks of the level may update the same ancestor entry; plain
 // read-modify-write for blocks the host found exclusive (flags bit 2).
-// The scatter targets do not depend on the product: their (cbase, rbase)
-// pairs are loaded before the main loop and the rel entries right after its
-// prologue, so the index chain is off the critical path and the epilogue
-// issues only the updates.
+//
+// The tile is formed transposed, as F(k0.., :) L_hat(i0.., :)^T, so that the
+// sixteen lanes of an MFMA output row hold sixteen consecutive rows ii of one
+// target column kk: rows of one ancestor column are contiguous in its panel,
+// so each group of sixteen lanes updates one run of memory instead of
+// sixteen columns.  The scatter targets do not depend on the product: their
+// (cbase, rbase) pairs are loaded before the main loop and the rel entries
+// right after its prologue, so the epilogue issues only the updates.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void schur_task(GemmLds& L, const Task t, const BlockDesc d, double* __restrict__ Lp,
                            const double* __restrict__ Hp, const int64_t* __restrict__ cbase,
@@ -587,48 +591,48 @@ __device__ __forceinline__ void schur_task(GemmLds& L, const Task t, const Block
     const double* F = Lp + d.poff + s;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm0 = (wave % SH::WM) * (TBM / SH::WM), wn0 = (wave / SH::WM) * (64 / SH::WN);
-    // this thread's outputs: rows i0 + wm0 + 16 mt + lane / 16 + 4 v, columns k0 + wn0 + 16 nt + lane % 16
-    int64_t cb[SH::NT], rb[SH::NT];
+    // this thread's outputs (mt, nt, v): target column kk = k0 + wm0 + 16 mt +
+    // lane / 16 + 4 v, row ii = i0 + wn0 + 16 nt + lane % 16
+    auto col_of = [&](int mt, int v) { return k0c + wm0 + mt * 16 + (lane >> 4) + 4 * v; };
+    auto row_of = [&](int nt) { return i0 + wn0 + nt * 16 + (lane & 15); };
+    int64_t cb[SH::MT][4], rb[SH::MT][4];
 #pragma unroll
-    for (int nt = 0; nt < SH::NT; ++nt) {
-        const int kk = k0c + wn0 + nt * 16 + (lane & 15);
-        const int64_t pk = d.coff + (kk < c ? kk : 0);
-        cb[nt] = cbase[pk];
-        rb[nt] = rbase[pk];
-    }
+    for (int mt = 0; mt < SH::MT; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int kk = col_of(mt, v);
+            const int64_t pk = d.coff + (kk < c ? kk : 0);
+            cb[mt][v] = cbase[pk];
+            rb[mt][v] = rbase[pk];
+        }
     int32_t ro[SH::MT][SH::NT][4];
+    auto live = [&](int mt, int nt, int v) {
+        const int ii = row_of(nt), kk = col_of(mt, v);
+        return ii < c && kk < c && ii >= kk;
+    };
     auto prefetch = [&]() {
 #pragma unroll
         for (int mt = 0; mt < SH::MT; ++mt)
 #pragma unroll
             for (int nt = 0; nt < SH::NT; ++nt)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int ii = i0 + wm0 + mt * 16 + (lane >> 4) + 4 * v;
-                    const int kk = k0c + wn0 + nt * 16 + (lane & 15);
-                    const bool ok = ii < c && kk < c && ii >= kk;
-                    ro[mt][nt][v] = rel[rb[nt] + (ok ? ii : 0)];
-                }
+                for (int v = 0; v < 4; ++v) ro[mt][nt][v] = rel[rb[mt][v] + (live(mt, nt, v) ? row_of(nt) : 0)];
     };
     d4 acc[2][4] = {};
-    auto addrA = [&](int t0, int tt, int ii, bool& ok) -> const double* {
+    // A(kk, t) = F(k0 + kk, t): contiguous along the tile rows
+    auto addrA = [&](int t0, int tt, int kk, bool& ok) -> const double* {
+        const int k = k0c + kk, col = t0 + tt;
+        ok = k < c && col < s;
+        return ok ? F + k + (int64_t)col * ld : F;
+    };
+    // B(t, ii) = L_hat(i0 + ii, t): contiguous in ii
+    auto addrB = [&](int t0, int tt, int ii, bool& ok) -> const double* {
         const int i = i0 + ii, k = t0 + tt;
         ok = i < c && k < s;
         return ok ? H + i + (int64_t)k * c : H;
     };
-    // B(t, j) = F(k0c + j, t): contiguous in j
-    auto addrB = [&](int t0, int tt, int j, bool& ok) -> const double* {
-        const int k = k0c + j, col = t0 + tt;
-        ok = k < c && col < s;
-        return ok ? F + k + (int64_t)col * ld : F;
-    };
     tile_mma2<64, true>(L, 0, s, acc, addrA, addrB, [](int) { return false; }, prefetch);
-    auto live = [&](int mt, int nt, int v) {
-        const int ii = i0 + wm0 + mt * 16 + (lane >> 4) + 4 * v;
-        const int kk = k0c + wn0 + nt * 16 + (lane & 15);
-        return ii < c && kk < c && ii >= kk;
-    };
-    auto target = [&](int mt, int nt, int v) { return Lp + cb[nt] + ro[mt][nt][v]; };
+    auto target = [&](int mt, int nt, int v) { return Lp + cb[mt][v] + ro[mt][nt][v]; };
     // a tile strictly below the diagonal and inside C has every entry live:
     // its updates are issued without per-entry branches, which would put a
     // wait on all outstanding memory operations in front of every store

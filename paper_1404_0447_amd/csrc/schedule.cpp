@@ -57,9 +57,9 @@ struct TileGroup {
 // greedy list schedule (largest first onto the least loaded place; cost =
 // (16-row chunks + ovh) times tile width) finishes first.  ovh is the fixed
 // cost of one work-group in chunk times: the exposed latency of its first
-// loads and its epilogue (atomic for a split contraction); measured on the
-// gathered GEMM it is about seven chunks, so splitting stops paying once
-// the pieces get short.
+// loads and its epilogue (atomic for a split contraction); on the gathered
+// GEMM it measures at seven to twelve chunks, so splitting stops paying
+// once the pieces get short.
 static int64_t best_split(const std::vector<TileGroup>& groups, int64_t slots, double ovh)
 {
     int64_t base = 0;

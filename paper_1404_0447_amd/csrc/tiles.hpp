@@ -25,7 +25,7 @@ constexpr int kFillTiles = 512;  // split the contraction when a level has fewer
 constexpr long kGemmSlots = 512;
 constexpr long kSdiagSlots = 1536;
 // fixed cost of one work-group of the split contractions, in 16-deep chunks
-constexpr double kGemmTaskOvh = 7.0;
+constexpr double kGemmTaskOvh = 12.0;
 constexpr double kSdiagTaskOvh = 4.0;
 constexpr int kXcds = 8;         // work-group t runs on XCD t % 8
 constexpr int kMinSplitK = 256;  // rows of C per split piece, at least
