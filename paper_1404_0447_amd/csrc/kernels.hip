@@ -135,7 +135,8 @@ __global__ void k_export_L(const BlockDesc* __restrict__ blk, const int32_t* __r
 
 // ---------------------------------------------------------------------------
 // Generic 64 x BN MFMA tile: acc += A(64 x K) B(K x BN), K streamed in
-// chunks of 16 through LDS.  loadA(k0, kk, i) -> A(i, k0+kk) and
+// chunks of 16 through LDS, accumulated transposed (read it with
+// tile_epilogue_t).  loadA(k0, kk, i) -> A(i, k0+kk) and
 // loadB(k0, kk, j) -> B(k0+kk, j).  The A loads run with consecutive threads
 // along i, or along kk for chunks where chunkAlongK(k0) holds (contiguous
 // in k).  Four waves: BN >= 64 -> 2 x 2 waves of 32 x BN/2, else 4 x 1 waves
@@ -222,16 +223,21 @@ __device__ __forceinline__ void tile_mma(TileLds& L, int Kb, int Ke, d4 (&acc)[2
 #pragma unroll
             for (int mt = 0; mt < SH::MT; ++mt)
 #pragma unroll
-                for (int nt = 0; nt < SH::NT; ++nt) acc[mt][nt] = mfma(a[mt], b[nt], acc[mt][nt]);
+                for (int nt = 0; nt < SH::NT; ++nt) acc[mt][nt] = mfma(b[nt], a[mt], acc[mt][nt]);
         }
         __syncthreads();
     }
     mfma_drain();
 }
 
-// visit every accumulator element: f(i, j, value) with tile-local i, j
+// Visit every element f(i, j, value) (tile-local i, j) of a tile whose
+// MFMAs ran with their operands swapped: mfma(b, a) forms the transposed
+// 16 x 16 product, and register v of lane l holds row l / 16 + 4 v, column
+// l % 16 of whatever product it forms, so here lane l holds row i = l % 16.
+// Sixteen lanes then cover sixteen consecutive rows of one column, which
+// makes the stores (and atomics) into a column-major output contiguous.
 template <int BN, class F>
-__device__ __forceinline__ void tile_epilogue(const d4 (&acc)[2][4], F f)
+__device__ __forceinline__ void tile_epilogue_t(const d4 (&acc)[2][4], F f)
 {
     using SH = TileShape<BN>;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -242,7 +248,7 @@ __device__ __forceinline__ void tile_epilogue(const d4 (&acc)[2][4], F f)
         for (int nt = 0; nt < SH::NT; ++nt)
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-                f(wm0 + mt * 16 + (lane >> 4) + 4 * v, wn0 + nt * 16 + (lane & 15), acc[mt][nt][v]);
+                f(wm0 + mt * 16 + (lane & 15), wn0 + nt * 16 + (lane >> 4) + 4 * v, acc[mt][nt][v]);
 }
 
 // ---------------------------------------------------------------------------
@@ -261,7 +267,7 @@ struct GemmLds {
     double B[2][TBK][128 + TPAD];
 };
 
-template <int BN, bool kBJ, class FA, class FB, class FAK, class FH>
+template <int BN, bool kBJ, bool kT, class FA, class FB, class FAK, class FH>
 __device__ __forceinline__ void tile_mma2(GemmLds& L, int Kb, int Ke, d4 (&acc)[2][4], FA addrA, FB addrB,
                                           FAK alongA, FH afterPrologue)
 {
@@ -341,7 +347,8 @@ __device__ __forceinline__ void tile_mma2(GemmLds& L, int Kb, int Ke, d4 (&acc)[
 #pragma unroll
             for (int mt = 0; mt < SH::MT; ++mt)
 #pragma unroll
-                for (int nt = 0; nt < SH::NT; ++nt) acc[mt][nt] = mfma(a[mt], b[nt], acc[mt][nt]);
+                for (int nt = 0; nt < SH::NT; ++nt)
+                    acc[mt][nt] = kT ? mfma(b[nt], a[mt], acc[mt][nt]) : mfma(a[mt], b[nt], acc[mt][nt]);
         }
         stage_store(buf ^ 1);
         stage_val();
@@ -489,7 +496,7 @@ __device__ __forceinline__ void gemm_task(GemmLds& L, const Task t, const BlockD
 #pragma unroll
             for (int mt = 0; mt < SH::MT; ++mt)
 #pragma unroll
-                for (int nt = 0; nt < SH::NT; ++nt) acc[mt][nt] = mfma(a[mt], b[nt], acc[mt][nt]);
+                for (int nt = 0; nt < SH::NT; ++nt) acc[mt][nt] = mfma(b[nt], a[mt], acc[mt][nt]);
         }
         stage_store(buf ^ 1);
         stage_v(ch + 2);
@@ -498,7 +505,8 @@ __device__ __forceinline__ void gemm_task(GemmLds& L, const Task t, const BlockD
         __syncthreads();
     }
     mfma_drain();
-    tile_epilogue<BN>(acc, [&](int i, int j, double v) {
+    // transposed accumulation: stores and atomics run down the columns of X
+    tile_epilogue_t<BN>(acc, [&](int i, int j, double v) {
         const int ii = r0 + i, jj = n0 + j;
         if (ii < c && jj < s) {
             double* x = Ap + d.poff + s + ii + (int64_t)jj * ld;
@@ -545,8 +553,8 @@ __device__ __forceinline__ void panel_task(GemmLds& L, const Task t, const Block
         ok = k < s && jj < s;
         return ok ? T + k + (int64_t)jj * s : T;
     };
-    tile_mma2<BN, false>(L, 0, s, acc, addrA, addrB, [](int) { return false; }, [] {});
-    tile_epilogue<BN>(acc, [&](int i, int j, double v) {
+    tile_mma2<BN, false, true>(L, 0, s, acc, addrA, addrB, [](int) { return false; }, [] {});
+    tile_epilogue_t<BN>(acc, [&](int i, int j, double v) {
         const int ii = r0 + i, jj = n0 + j;
         if (ii < c && jj < s) Hp[d.hoff + ii + (int64_t)jj * c] = v;
     });
@@ -631,7 +639,7 @@ __device__ __forceinline__ void schur_task(GemmLds& L, const Task t, const Block
         ok = i < c && k < s;
         return ok ? H + i + (int64_t)k * c : H;
     };
-    tile_mma2<64, true>(L, 0, s, acc, addrA, addrB, [](int) { return false; }, prefetch);
+    tile_mma2<64, true, false>(L, 0, s, acc, addrA, addrB, [](int) { return false; }, prefetch);
     auto target = [&](int mt, int nt, int v) { return Lp + cb[mt][v] + ro[mt][nt][v]; };
     // a tile strictly below the diagonal and inside C has every entry live:
     // its updates are issued without per-entry branches, which would put a
@@ -1547,7 +1555,7 @@ __device__ void rs1_task(TileLds& L, const Task t, const BlockDesc d, double* __
         return (k < s && jj < s) ? ybar_at(Zd, ld, k, jj) : 0.0;
     };
     tile_mma<BN>(L, 0, s, acc, loadA, loadB, [](int) { return false; });
-    tile_epilogue<BN>(acc, [&](int i, int j, double v) {
+    tile_epilogue_t<BN>(acc, [&](int i, int j, double v) {
         const int ii = r0 + i, jj = n0 + j;
         if (ii < c && jj < s) Zb[d.poff + s + ii + (int64_t)jj * ld] -= v;
     });
@@ -1600,7 +1608,7 @@ __device__ void rs2_task(TileLds& L, const Task t, const BlockDesc d, const doub
         };
         tile_mma<BN>(L, 0, s, acc, loadX, loadY, [](int) { return false; });
     }
-    tile_epilogue<BN>(acc, [&](int i, int j, double v) {
+    tile_epilogue_t<BN>(acc, [&](int i, int j, double v) {
         const int ii = r0 + i, jj = n0 + j;
         if (ii < c && jj < s) {
             double* p = Hb + d.hoff + ii + (int64_t)jj * c;
@@ -1649,7 +1657,7 @@ __global__ __launch_bounds__(kThreads) void k_rs3(const Task* __restrict__ tasks
         return q < s ? H[k + (int64_t)q * c] : Xb[k + (int64_t)(q - s) * ld];
     };
     tile_mma<64>(L, 0, 2 * s, acc, loadA, loadB, [](int) { return false; });
-    tile_epilogue<64>(acc, [&](int i, int j, double v) {
+    tile_epilogue_t<64>(acc, [&](int i, int j, double v) {
         const int ii = i0 + i, kk = k0c + j;
         if (ii < c && kk < c && ii >= kk) {
             const int64_t pk = d.coff + kk;
@@ -1689,7 +1697,7 @@ __device__ void rf1a_task(TileLds& L, const Task t, const BlockDesc d, const dou
         return (k < c && jj < s) ? Lp[d.poff + s + k + (int64_t)jj * ld] : 0.0;
     };
     tile_mma<BN>(L, t.kb, t.ke, acc, loadA, loadB, [](int) { return false; });
-    tile_epilogue<BN>(acc, [&](int i, int j, double v) {
+    tile_epilogue_t<BN>(acc, [&](int i, int j, double v) {
         const int ii = r0 + i, jj = n0 + j;
         if (ii < c && jj < s) {
             double* p = Hb + d.hoff + ii + (int64_t)jj * c;
@@ -1745,7 +1753,7 @@ __device__ void rf1b_task(TileLds& L, const Task t, const BlockDesc d, double* _
         };
         tile_mma<BN>(L, 0, s, acc, loadA2, loadB2, [](int) { return false; });
     }
-    tile_epilogue<BN>(acc, [&](int i, int j, double v) {
+    tile_epilogue_t<BN>(acc, [&](int i, int j, double v) {
         const int ii = r0 + i, jj = n0 + j;
         if (ii < c && jj < s) {
             double* p = Zb + d.poff + s + ii + (int64_t)jj * ld;
