@@ -797,13 +797,86 @@ __device__ __forceinline__ void sdiag_task(SdiagLds& S, const Task t, const Bloc
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_sdiag(const Task* __restrict__ tasks, const BlockDesc* __restrict__ blk,
-                                                    double* __restrict__ Ap, const double* __restrict__ Hp,
-                                                    const double* __restrict__ Tp)
+// ---------------------------------------------------------------------------
+// Selected inversion, step 4 + symmetrisation, per-level path: one pair of
+// 64 x 64 tiles (I, J), I >= J, of the diagonal block per work-group, on the
+// pipelined MFMA tile:
+//   P1 = L_hat(:,I)^T X(:,J),  P2 = L_hat(:,J)^T X(:,I)  (P2 = P1 when I == J)
+//   Ainv(i,j) = T(i,j) - (P1(i,j) + P2(j,i)) / 2  for i >= j in the tile.
+// Both products accumulate transposed (lane l holds tile row l % 16), so the
+// stores run down the columns of the panel.  P2 reaches the thread holding
+// P1(i,j) through LDS.  A split contraction adds -(P1 + P2^T)/2 with
+// atomics to the T written beforehand (the average is linear).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void sdiag64_task(GemmLds& L, const Task t, const BlockDesc d, double* __restrict__ Ap,
+                                             const double* __restrict__ Hp, const double* __restrict__ Tp)
 {
-    __shared__ SdiagLds S;
+    using SH = TileShape<64>;
+    const int s = d.s, c = d.c;
+    const int64_t ld = (int64_t)s + c;
+    const int I0 = t.i0, J0 = t.j0;
+    const int kb = t.kb, ke = min(t.ke, c);
+    const double* H = Hp + d.hoff;       // L_hat(r, j) at H[r + j c]
+    const double* X = Ap + d.poff + s;   // X(r, j) at X[r + j ld]
+    d4 acc1[2][4] = {}, acc2[2][4] = {};
+    // A(i, r) = L_hat(r, a0 + i) and B(r, j) = X(r, b0 + j): both contiguous in r
+    auto product = [&](int a0, int b0, d4 (&acc)[2][4]) {
+        auto addrA = [&](int k0, int kk, int ii, bool& ok) -> const double* {
+            const int r = k0 + kk, col = a0 + ii;
+            ok = r < ke && col < s;
+            return ok ? H + r + (int64_t)col * c : H;
+        };
+        auto addrB = [&](int k0, int kk, int j, bool& ok) -> const double* {
+            const int r = k0 + kk, col = b0 + j;
+            ok = r < ke && col < s;
+            return ok ? X + r + (int64_t)col * ld : X;
+        };
+        tile_mma2<64, false, true>(L, kb, ke, acc, addrA, addrB, [](int) { return true; }, [] {});
+    };
+    product(I0, J0, acc1);
+    const bool diag = I0 == J0;
+    if (!diag) product(J0, I0, acc2);
+    // the loop ended on a barrier: the LDS tile is free for the exchange
+    double(*S)[TBM + 1] = reinterpret_cast<double(*)[TBM + 1]>(&L);
+    static_assert(sizeof(double) * TBM * (TBM + 1) <= sizeof(GemmLds), "exchange tile fits the LDS tile");
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm0 = (wave % SH::WM) * (TBM / SH::WM), wn0 = (wave / SH::WM) * (64 / SH::WN);
+#pragma unroll
+    for (int mt = 0; mt < SH::MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < SH::NT; ++nt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = wm0 + mt * 16 + (lane & 15), j = wn0 + nt * 16 + (lane >> 4) + 4 * v;
+                S[j][i] = diag ? acc1[mt][nt][v] : acc2[mt][nt][v];  // S[a][b] = P2(b, a)
+            }
+    __syncthreads();
+    const double* T = Tp + d.woff;
+    double* A = Ap + d.poff;
+    const bool split = t.flags & 1;
+#pragma unroll
+    for (int mt = 0; mt < SH::MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < SH::NT; ++nt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = wm0 + mt * 16 + (lane & 15), j = wn0 + nt * 16 + (lane >> 4) + 4 * v;
+                const int gi = I0 + i, gj = J0 + j;
+                if (gi < s && gj < s && gi >= gj) {
+                    const double p = 0.5 * (acc1[mt][nt][v] + S[i][j]);
+                    if (split) unsafeAtomicAdd(A + gi + (int64_t)gj * ld, -p);
+                    else A[gi + (int64_t)gj * ld] = T[gi + (int64_t)gj * s] - p;
+                }
+            }
+}
+
+__global__ __launch_bounds__(kThreads) void k_sdiag64(const Task* __restrict__ tasks,
+                                                      const BlockDesc* __restrict__ blk, double* __restrict__ Ap,
+                                                      const double* __restrict__ Hp, const double* __restrict__ Tp)
+{
+    __shared__ GemmLds L;
     const Task t = tasks[blockIdx.x];
-    sdiag_task(S, t, blk[t.b], Ap, Hp, Tp);
+    sdiag64_task(L, t, blk[t.b], Ap, Hp, Tp);
 }
 
 // ---------------------------------------------------------------------------
@@ -2062,7 +2135,7 @@ hipError_t launch_invert_level(Prof* P, const DevPtrs& D, int64_t gemm0, int64_t
         launch(P, kGemm, k_gemm, dim3((unsigned)ngemm), 0, s, D.t_gemm + gemm0, D.blocks, D.Ap,
                (const double*)D.Hp, D.cbase, D.rbase, D.rel);
     if (nsdiag > 0)
-        launch(P, kSdiag, k_sdiag, dim3((unsigned)nsdiag), 0, s, D.t_sdiag + sdiag0, D.blocks, D.Ap,
+        launch(P, kSdiag, k_sdiag64, dim3((unsigned)nsdiag), 0, s, D.t_sdiag + sdiag0, D.blocks, D.Ap,
                (const double*)D.Hp, (const double*)D.Tp);
     return hipGetLastError();
 }

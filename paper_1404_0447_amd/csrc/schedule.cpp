@@ -37,9 +37,9 @@ static void pieces(int lo, int hi, int split, F emit)
     }
 }
 
-static int split_for(int64_t want, int len)
+static int split_for(int64_t want, int len, int mink = kMinSplitK)
 {
-    const int maxsplit = std::max(1, ((len + 15) / 16) / (kMinSplitK / 16));
+    const int maxsplit = std::max(1, ((len + 15) / 16) / (mink / 16));
     return (int)std::min<int64_t>(want, maxsplit);
 }
 
@@ -60,7 +60,8 @@ struct TileGroup {
 // loads and its epilogue (atomic for a split contraction); on the gathered
 // GEMM it measures at seven to twelve chunks, so splitting stops paying
 // once the pieces get short.
-static int64_t best_split(const std::vector<TileGroup>& groups, int64_t slots, double ovh)
+static int64_t best_split(const std::vector<TileGroup>& groups, int64_t slots, double ovh, int maxwant = 32,
+                          int mink = kMinSplitK)
 {
     int64_t base = 0;
     for (const TileGroup& g : groups) base += g.count;
@@ -68,10 +69,10 @@ static int64_t best_split(const std::vector<TileGroup>& groups, int64_t slots, d
     int64_t best = 1;
     double best_t = -1.0;
     std::vector<double> cost;
-    for (int64_t want = 1; want <= 32; want++) {
+    for (int64_t want = 1; want <= maxwant; want++) {
         cost.clear();
         for (const TileGroup& g : groups) {
-            const int sp = split_for(want, g.c), n16 = (g.c + 15) / 16;
+            const int sp = split_for(want, g.c, mink), n16 = (g.c + 15) / 16;
             for (int q = 0; q < sp; q++) {
                 const int len = (int)((int64_t)n16 * (q + 1) / sp - (int64_t)n16 * q / sp);
                 for (int64_t k = 0; k < g.count; k++) cost.push_back((len + ovh) * g.w);
@@ -191,11 +192,16 @@ void build_schedule(selinv_plan_s* P)
         for (int B : lv[l]) {
             const BlockDesc& d = P->blocks[B];
             if (is_small(d.s, d.c, kSbS) || d.c == 0) continue;
-            const int bn = tile_bn(d.s), nd = (d.s + kDiagTile - 1) / kDiagTile;
+            const int bn = tile_bn(d.s), nd = (d.s + kDiagTile64 - 1) / kDiagTile64;
             gg.push_back({(int64_t)((d.c + kTileM - 1) / kTileM) * ((d.s + bn - 1) / bn), d.c, bn});
-            dg.push_back({(int64_t)nd * (nd + 1) / 2, d.c, kDiagTile});
+            // a diagonal pair runs one 64 x 64 product, an off-diagonal pair two
+            dg.push_back({(int64_t)nd, d.c, kDiagTile64});
+            if (nd > 1) dg.push_back({(int64_t)nd * (nd - 1) / 2, d.c, 2 * kDiagTile64});
         }
-        const int64_t want = best_split(gg, kGemmSlots, kGemmTaskOvh), dwant = best_split(dg, kSdiagSlots, kSdiagTaskOvh);
+        const int64_t want = best_split(gg, kGemmSlots, kGemmTaskOvh);
+        // a block has only nd (nd + 1) / 2 diagonal pairs: their contraction
+        // may be cut finer to fill the device
+        const int64_t dwant = best_split(dg, kGemmSlots, kSdiagTaskOvh, 64, kMinSplitKDiag);
         const int64_t rwant = fill_for(rbase_), rdwant = fill_for(rdbase);
         (void)base;
         (void)dbase;
@@ -239,12 +245,13 @@ void build_schedule(selinv_plan_s* P)
             // contractions over C are split into pieces of >= kMinSplitK rows
             // when a level has too few tiles to fill the device
             const int split = split_for(want, c);
-            const int dsplit = split_for(dwant, c);
+            const int dsplit = split_for(dwant, c, kMinSplitKDiag);
             if (split > 1 || dsplit > 1) P->t_zero.push_back({B, 0, 0, 0, 0, 0, 0, 0});
-            for (int I = 0; I < nd; I++)
+            const int nd64 = (s + kDiagTile64 - 1) / kDiagTile64;
+            for (int I = 0; I < nd64; I++)
                 for (int J = 0; J <= I; J++)
                     pieces(0, c, dsplit, [&](int kb, int ke, int) {
-                        P->t_sdiag.tasks.push_back({B, I * kDiagTile, J * kDiagTile, 0, kb, ke, dsplit > 1, 0});
+                        P->t_sdiag.tasks.push_back({B, I * kDiagTile64, J * kDiagTile64, 0, kb, ke, dsplit > 1, 0});
                     });
             for (int j = 0; j < s; j += bn)
                 for (int r = 0; r < c; r += kTileM) {

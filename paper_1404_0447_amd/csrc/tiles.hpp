@@ -8,6 +8,7 @@ constexpr int kMaxS = 256;       // widest supported block (cap)
 constexpr int kTileM = 64;       // rows of an MFMA output tile (gather-GEMM, panel, Schur)
 constexpr int kSchurTile = 64;   // edge of a Schur-update tile (lower c x c)
 constexpr int kDiagTile = 32;    // edge of a diagonal-block tile (pairs (I,J), I >= J)
+constexpr int kDiagTile64 = 64;  // the same on the per-level path (pipelined MFMA tile)
 constexpr int kLdsDiagMax = 128; // diagonal factorization in LDS up to this width
 constexpr size_t kLdsDiagBytes = sizeof(double) * kLdsDiagMax * (kLdsDiagMax + 1);
 constexpr bool kUseSweep = true;  // register Gauss-Jordan sweep for s <= kLdsDiagMax
@@ -21,14 +22,14 @@ inline bool is_small(int s, int c, int smax) { return s <= smax && c <= kSbC; }
 
 constexpr int kFillTiles = 512;  // split the contraction when a level has fewer X tiles
 // resident work-groups of the gather-GEMM and diagonal-tile kernels on the
-// target (256 CUs x 2 and x 6); the per-level split is sized for them
+// target (256 CUs x 2); the per-level split is sized for them
 constexpr long kGemmSlots = 512;
-constexpr long kSdiagSlots = 1536;
 // fixed cost of one work-group of the split contractions, in 16-deep chunks
 constexpr double kGemmTaskOvh = 12.0;
-constexpr double kSdiagTaskOvh = 4.0;
+constexpr double kSdiagTaskOvh = 8.0;  // smaller epilogue (half a 64 x 64 tile)
 constexpr int kXcds = 8;         // work-group t runs on XCD t % 8
 constexpr int kMinSplitK = 256;  // rows of C per split piece, at least
+constexpr int kMinSplitKDiag = 64;  // the same for the diagonal tile pairs
 
 // output-column tile of a block of width s: 16, 32, 64 or 128
 inline int tile_bn(int s) { return s <= 16 ? 16 : s <= 32 ? 32 : s <= 64 ? 64 : 128; }
