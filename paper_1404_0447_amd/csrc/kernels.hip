@@ -985,6 +985,14 @@ __device__ __forceinline__ void ldlt_sweep(const BlockDesc d, double* __restrict
 #pragma unroll
     for (int b = 0; b < NB; ++b) rk_[b] = colbuf[0][ty + 16 * b];
     rd = colbuf[0][0];
+    // A thread records the column of L_BB (and D's entry) of the one pivot
+    // per group of 16 that it owns, and stores them when the group ends:
+    // a store inside the pivot loop would make every later write of its
+    // data register wait for the store to complete, a full memory round
+    // trip per pivot.
+    double lc[NB], dd = 0.0;
+#pragma unroll
+    for (int a = 0; a < NB; ++a) lc[a] = 0.0;
 #pragma unroll
     for (int jb = 0; jb < NB; ++jb) {
         const int jt_end = min(16, s - 16 * jb);
@@ -1001,13 +1009,10 @@ __device__ __forceinline__ void ldlt_sweep(const BlockDesc d, double* __restrict
                 const bool ok = isfinite(dj) && dj != 0.0 && (!require_spd || dj > 0.0);
                 if (!ok) atomicMin(status, (unsigned long long)(d.first + j));
             }
-            if (ty == jt) {  // column j of L_BB and D
+            if (ty == jt) {  // column j of L_BB and D, stored after this group of 16 pivots
 #pragma unroll
-                for (int a = jb; a < NB; ++a) {
-                    const int i = tx + 16 * a;
-                    if (i > j && i < s) F[i + (int64_t)j * ld] = ci[a];
-                }
-                if (tx == 0) F[j + (int64_t)j * ld] = dj;
+                for (int a = jb; a < NB; ++a) lc[a] = ci[a];
+                dd = dj;
             }
             // M(tx + 16a, ty + 16b) after this pivot (a, b known at compile time)
             auto after = [&](int a, int b) {
@@ -1051,6 +1056,15 @@ __device__ __forceinline__ void ldlt_sweep(const BlockDesc d, double* __restrict
             for (int a = 0; a < NB; ++a)
 #pragma unroll
                 for (int b = 0; b <= a; ++b) M[slot(a, b)] = after(a, b);
+        }
+        const int jo = 16 * jb + ty;  // the pivot this thread recorded
+        if (jo < s) {
+#pragma unroll
+            for (int a = jb; a < NB; ++a) {
+                const int i = tx + 16 * a;
+                if (i > jo && i < s) F[i + (int64_t)jo * ld] = lc[a];
+            }
+            if (tx == 0) F[jo + (int64_t)jo * ld] = dd;
         }
     }
     // T = -M, made exactly symmetric from the lower triangle
