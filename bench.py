@@ -9,7 +9,9 @@ GEMMs, diagonal blocks) and the export of the selected values.
 Prints ONE JSON line.  `value` is algorithmic FP64 GFLOP/s of the step
 (fundamental-supernode flop counts of factor + selected inversion divided by
 the step time).  `roofline` covers the kernel kind with the largest share of
-device time, timed live with HIP events stamped in each dispatch.
+device time, timed live with HIP events stamped in each dispatch during a
+second pass over the same K steps (the stamps cost time of their own, so
+`ms_per_step` comes from the pass without them).
 `cpu_baseline` times the CPU oracle (test infrastructure, untuned) on the
 same matrix.  Two more parts of the metric ride on the same line:
 `backward` (the reverse sweep's time over the forward step's, same matrix)
@@ -96,7 +98,7 @@ def main():
     plan.sync_status()
     log(f"[bench] warmup done ({args.warmup} steps)")
 
-    plan.profile(True)
+    # timed region: K steps, nothing but the launches of the path
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -105,12 +107,26 @@ def main():
         step()
     stop.record(stream)
     torch.cuda.synchronize()
-    plan.profile(False)
     ms_total = start.elapsed_time(stop)
     ms_step = ms_total / args.steps
-    prof = plan.profile_read()
     plan.sync_status()
     log(f"[bench] timed {args.steps} steps: {ms_step:.3f} ms/step")
+    # the same K steps again with a HIP event pair stamped around every
+    # dispatch (on the stream it runs on): per-kernel durations for the
+    # roofline; the stamps cost time of their own, so the step time above
+    # comes from the run without them
+    plan.profile(True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(args.steps):
+        step()
+    stop.record(stream)
+    torch.cuda.synchronize()
+    plan.profile(False)
+    ms_step_prof = start.elapsed_time(stop) / args.steps
+    prof = plan.profile_read()
+    plan.sync_status()
+    log(f"[bench] profiled {args.steps} steps: {ms_step_prof:.3f} ms/step")
 
     work = plan.kernel_work()
     flops_step = info["flops_factor"] + info["flops_selinv"]
@@ -151,6 +167,7 @@ def main():
                    "flops_factor": info["flops_factor"], "flops_selinv": info["flops_selinv"],
                    "fuse_chains": not args.no_fuse},
         "roofline": roof,
+        "ms_per_step_profiled": round(ms_step_prof, 4),
         "phases_ms": {"factor_kernels": round(factor_ms, 4), "invert_kernels": round(invert_ms, 4),
                       **{k: round(v, 4) for k, v in kern_ms.items()}},
         "gemm_phase": {"tflops": round(gemm_phase_tf, 4), "frac_of_fp64_peak": round(gemm_phase_tf / PEAK_FP64_TFLOPS, 4),
@@ -216,8 +233,9 @@ def measure_backward(plan, vals, out, fwd_ms, args, dev):
     stream = torch.cuda.current_stream()
     for _ in range(max(1, args.warmup)):
         plan.backward(g, out=gA)
-    plan.profile(True)
     bwd_ms = _time(lambda: plan.backward(g, out=gA), args.steps, stream)
+    plan.profile(True)  # kernel split from a second, stamped run
+    _time(lambda: plan.backward(g, out=gA), args.steps, stream)
     plan.profile(False)
     prof = plan.profile_read()
     plan.sync_status()

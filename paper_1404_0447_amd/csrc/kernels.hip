@@ -963,6 +963,10 @@ __device__ __forceinline__ void ldlt_sweep(const BlockDesc d, double* __restrict
     double* T = Tp + d.woff;
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
     auto slot = [](int a, int b) { return a * (a + 1) / 2 + b; };
+    auto read_col = [&](const double* col, double (&v)[NB], int r0) {
+#pragma unroll
+        for (int a = 0; a < NB; ++a) v[a] = col[r0 + 16 * a];
+    };
     double M[NS];
 #pragma unroll
     for (int a = 0; a < NB; ++a)
@@ -980,10 +984,8 @@ __device__ __forceinline__ void ldlt_sweep(const BlockDesc d, double* __restrict
     }
     __syncthreads();
     double ri_[NB], rk_[NB], rd;  // the pivot column as read: rows tx + 16a, ty + 16b, and d_j
-#pragma unroll
-    for (int a = 0; a < NB; ++a) ri_[a] = colbuf[0][tx + 16 * a];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) rk_[b] = colbuf[0][ty + 16 * b];
+    read_col(colbuf[0], ri_, tx);
+    read_col(colbuf[0], rk_, ty);
     rd = colbuf[0][0];
     // A thread records the column of L_BB (and D's entry) of the one pivot
     // per group of 16 that it owns, and stores them when the group ends:
@@ -999,7 +1001,11 @@ __device__ __forceinline__ void ldlt_sweep(const BlockDesc d, double* __restrict
         for (int jt = 0; jt < jt_end; ++jt) {
             const int j = 16 * jb + jt;
             const double dj = rd;
-            const double inv = 1.0 / dj;
+            // 1 / d_j: hardware reciprocal and two Newton steps (each squares
+            // the relative error; the first estimate is good to about 2^-26)
+            double inv = __builtin_amdgcn_rcp(dj);
+            inv = fma(inv, fma(-dj, inv, 1.0), inv);
+            inv = fma(inv, fma(-dj, inv, 1.0), inv);
             double ci[NB], ck[NB];
 #pragma unroll
             for (int a = 0; a < NB; ++a) ci[a] = ri_[a] * inv;  // c_i / d_j
@@ -1046,10 +1052,8 @@ __device__ __forceinline__ void ldlt_sweep(const BlockDesc d, double* __restrict
             }
             __syncthreads();
             if (more) {
-#pragma unroll
-                for (int a = 0; a < NB; ++a) ri_[a] = nb[tx + 16 * a];
-#pragma unroll
-                for (int b = 0; b < NB; ++b) rk_[b] = nb[ty + 16 * b];
+                read_col(nb, ri_, tx);
+                read_col(nb, rk_, ty);
                 rd = nb[j + 1];
             }
 #pragma unroll
@@ -1088,7 +1092,7 @@ __global__ __launch_bounds__(kThreads) void k_ldlt_diag(const Task* __restrict__
                                                         double* __restrict__ Wp, double* __restrict__ Tp,
                                                         unsigned long long* __restrict__ status, int require_spd)
 {
-    __shared__ double colbuf[2][kLdsDiagMax];
+    __shared__ __align__(16) double colbuf[2][kLdsDiagMax];
     const Task t = tasks[blockIdx.x];
     const BlockDesc d = blk[t.b];
     if (d.s > 16 * NB) ldlt_global(d, Lp, Wp, Tp, status, require_spd);
@@ -1305,7 +1309,7 @@ union PersistLds {
     TileLds tile;
     GemmLds gemm;
     SdiagLds sd;
-    double colbuf[2][kLdsDiagMax];
+    alignas(16) double colbuf[2][kLdsDiagMax];
     SbLds sb[kThreads / 64];
 };
 

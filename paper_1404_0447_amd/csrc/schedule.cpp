@@ -198,7 +198,7 @@ void build_schedule(selinv_plan_s* P)
             dg.push_back({(int64_t)nd, d.c, kDiagTile64});
             if (nd > 1) dg.push_back({(int64_t)nd * (nd - 1) / 2, d.c, 2 * kDiagTile64});
         }
-        const int64_t want = best_split(gg, kGemmSlots, kGemmTaskOvh);
+        const int64_t want = best_split(gg, kGemmSlots, kGemmTaskOvh, 64);
         // a block has only nd (nd + 1) / 2 diagonal pairs: their contraction
         // may be cut finer to fill the device
         const int64_t dwant = best_split(dg, kGemmSlots, kSdiagTaskOvh, 64, kMinSplitKDiag);

@@ -28,7 +28,7 @@ constexpr long kGemmSlots = 512;
 constexpr double kGemmTaskOvh = 12.0;
 constexpr double kSdiagTaskOvh = 8.0;  // smaller epilogue (half a 64 x 64 tile)
 constexpr int kXcds = 8;         // work-group t runs on XCD t % 8
-constexpr int kMinSplitK = 256;  // rows of C per split piece, at least
+constexpr int kMinSplitK = 128;  // rows of C per split piece, at least
 constexpr int kMinSplitKDiag = 64;  // the same for the diagonal tile pairs
 
 // output-column tile of a block of width s: 16, 32, 64 or 128
