@@ -31,6 +31,8 @@
 namespace selinv {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+// two doubles read with one load from an 8-byte aligned address
+typedef double d2u __attribute__((ext_vector_type(2), aligned(8)));
 
 __device__ __forceinline__ d4 mfma(double a, double b, d4 c)
 {
@@ -380,7 +382,7 @@ __device__ __forceinline__ void tile_mma2(GemmLds& L, int Kb, int Ke, d4 (&acc)[
 // (cbase, rbase) pairs of chunk n+4 are loaded: every load has a whole
 // iteration of MFMAs to arrive, and there is one barrier per chunk.
 // ---------------------------------------------------------------------------
-template <int BN>
+template <int BN, bool kPair = false>
 __device__ __forceinline__ void gemm_task(GemmLds& L, const Task t, const BlockDesc d, double* __restrict__ Ap,
                           const double* __restrict__ Hp, const int64_t* __restrict__ cbase,
                           const int64_t* __restrict__ rbase, const int32_t* __restrict__ rel)
@@ -416,7 +418,7 @@ __device__ __forceinline__ void gemm_task(GemmLds& L, const Task t, const BlockD
     int32_t r_rel[4];          // stage R: rel[rbase[p] + q] as loaded
     bool r_ok[4];
     double v_a[4], v_b[NB];    // stage V: values as loaded
-    bool v_ok[4], v_bok[NB];
+    bool v_ok[4];
     bool av = false;           // stage V chunk is read along k
     auto stage_m = [&](int ch) {
 #pragma unroll
@@ -445,13 +447,28 @@ __device__ __forceinline__ void gemm_task(GemmLds& L, const Task t, const BlockD
             v_a[q] = Ap[r_cb[q] + r_rel[q]];
             v_ok[q] = r_ok[q];
         }
+        // L_hat needs no mask: where k >= c the gathered A is zero, and
+        // columns past s are never written; a stand-in keeps the read in bounds
         const int k0 = Kb + ch * TBK;
+        if constexpr (kPair) {
+            // rows k, k+1 of one column per load (c even: a pair never
+            // crosses the column's end)
 #pragma unroll
-        for (int q = 0; q < NB; ++q) {
-            const int e = tid + q * kThreads;
-            const int k = k0 + (e & 15), jj = n0 + (e >> 4);
-            v_bok[q] = k < c && jj < s;
-            v_b[q] = Hp[d.hoff + (v_bok[q] ? k + (int64_t)jj * c : 0)];
+            for (int q = 0; q < NB / 2; ++q) {
+                const int e = tid + q * kThreads;
+                const int k = k0 + 2 * (e & 7), jj = n0 + (e >> 3);
+                const bool ok = k < c && jj < s;
+                const d2u pr = *reinterpret_cast<const d2u*>(Hp + d.hoff + (ok ? k + (int64_t)jj * c : 0));
+                v_b[2 * q] = pr.x;
+                v_b[2 * q + 1] = pr.y;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const int e = tid + q * kThreads;
+                const int k = k0 + (e & 15), jj = n0 + (e >> 4);
+                v_b[q] = Hp[d.hoff + ((k < c && jj < s) ? k + (int64_t)jj * c : 0)];
+            }
         }
     };
     auto stage_store = [&](int buf) {
@@ -462,10 +479,19 @@ __device__ __forceinline__ void gemm_task(GemmLds& L, const Task t, const BlockD
             const int row = av ? (e & 15) : (e >> 6), col = av ? (e >> 4) : (e & 63);
             L.A[buf][row][col] = x;
         }
+        if constexpr (kPair) {
 #pragma unroll
-        for (int q = 0; q < NB; ++q) {
-            const int e = tid + q * kThreads;
-            L.B[buf][e & 15][e >> 4] = v_bok[q] ? v_b[q] : 0.0;
+            for (int q = 0; q < NB / 2; ++q) {
+                const int e = tid + q * kThreads;
+                L.B[buf][2 * (e & 7)][e >> 3] = v_b[2 * q];
+                L.B[buf][2 * (e & 7) + 1][e >> 3] = v_b[2 * q + 1];
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const int e = tid + q * kThreads;
+                L.B[buf][e & 15][e >> 4] = v_b[q];
+            }
         }
     };
     d4 acc[2][4] = {};
@@ -524,7 +550,10 @@ __global__ __launch_bounds__(kThreads) void k_gemm(const Task* __restrict__ task
     __shared__ GemmLds L;
     const Task t = tasks[blockIdx.x];
     const BlockDesc d = blk[t.b];
-#define SELINV_CALL(BN) gemm_task<BN>(L, t, d, Ap, Hp, cbase, rbase, rel)
+    // even |C|: L_hat read two rows per load
+#define SELINV_CALL(BN)                                                \
+    if (BN >= 32 && (d.c & 1) == 0) gemm_task<BN, BN >= 32>(L, t, d, Ap, Hp, cbase, rbase, rel); \
+    else gemm_task<BN, false>(L, t, d, Ap, Hp, cbase, rbase, rel)
     SELINV_BN_DISPATCH(t.bn, SELINV_CALL)
 #undef SELINV_CALL
 }
