@@ -87,10 +87,11 @@ __global__ void k_gather(const double* __restrict__ src, const int64_t* __restri
         dst[i] = src[off[i]];
 }
 
-// Blocks whose contractions are split over several work-groups accumulate:
-// X = Ainv(C,B) := 0 and the lower triangle of Ainv(B,B) := T.  One wave per
-// column, lanes along its rows.
-__device__ __forceinline__ void zero_task(const BlockDesc d, double* __restrict__ Ap, const double* __restrict__ Tp)
+// Blocks whose products accumulate over several work-groups start from
+// the lower triangle of Ainv(B,B) := T and, when the gather-GEMM is split
+// (zx), X = Ainv(C,B) := 0.  One wave per column, lanes along its rows.
+__device__ __forceinline__ void zero_task(const BlockDesc d, double* __restrict__ Ap, const double* __restrict__ Tp,
+                                          bool zx = true)
 {
     const int64_t ld = (int64_t)d.s + d.c;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -98,7 +99,8 @@ __device__ __forceinline__ void zero_task(const BlockDesc d, double* __restrict_
         double* col = Ap + d.poff + (int64_t)j * ld;
         const double* tcol = Tp + d.woff + (int64_t)j * d.s;
         for (int i = j + lane; i < d.s; i += 64) col[i] = tcol[i];
-        for (int i = lane; i < d.c; i += 64) col[d.s + i] = 0.0;
+        if (zx)
+            for (int i = lane; i < d.c; i += 64) col[d.s + i] = 0.0;
     }
 }
 
@@ -106,7 +108,8 @@ __global__ __launch_bounds__(kThreads) void k_zero_x(const Task* __restrict__ ta
                                                      const BlockDesc* __restrict__ blk, double* __restrict__ Ap,
                                                      const double* __restrict__ Tp)
 {
-    zero_task(blk[tasks[blockIdx.x].b], Ap, Tp);
+    const Task t = tasks[blockIdx.x];
+    zero_task(blk[t.b], Ap, Tp, t.flags & 1);
 }
 
 // L on the canonical pattern: diagonal-block entries are stored; an entry in
@@ -827,15 +830,20 @@ __device__ __forceinline__ void sdiag_task(SdiagLds& S, const Task t, const Bloc
 }
 
 // ---------------------------------------------------------------------------
-// Selected inversion, step 4 + symmetrisation, per-level path: one pair of
-// 64 x 64 tiles (I, J), I >= J, of the diagonal block per work-group, on the
-// pipelined MFMA tile:
-//   P1 = L_hat(:,I)^T X(:,J),  P2 = L_hat(:,J)^T X(:,I)  (P2 = P1 when I == J)
-//   Ainv(i,j) = T(i,j) - (P1(i,j) + P2(j,i)) / 2  for i >= j in the tile.
-// Both products accumulate transposed (lane l holds tile row l % 16), so the
-// stores run down the columns of the panel.  P2 reaches the thread holding
-// P1(i,j) through LDS.  A split contraction adds -(P1 + P2^T)/2 with
-// atomics to the T written beforehand (the average is linear).
+// Selected inversion, step 4 + symmetrisation, per-level path, on 64 x 64
+// tiles of the diagonal block, with P = L_hat^T X (so Y = T - P) and
+// Ainv(i,j) = T(i,j) - (P(i,j) + P(j,i)) / 2 for i >= j:
+//  * diagonal tile I: P(I,I) on the pipelined MFMA tile; the transpose
+//    reaches the thread holding P(i,j) through LDS; stored as T - (P + P^T)/2,
+//    or with a split contraction added as -(P + P^T)/2 (atomics) to the T
+//    written beforehand;
+//  * tile (I,J), I > J: two tasks, one per half, each adding -1/2 of its
+//    product to Ainv(I,J) with atomics (T written beforehand):
+//    L_hat(:,I)^T X(:,J) (flags bit 3 clear) and X(:,I)^T L_hat(:,J) =
+//    P(J,I)^T (bit 3 set).  One product per task keeps the longest task of a
+//    level short.
+// Products accumulate transposed (lane l holds tile row l % 16), so stores
+// and atomics run down the columns of the panel.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void sdiag64_task(GemmLds& L, const Task t, const BlockDesc d, double* __restrict__ Ap,
                                              const double* __restrict__ Hp, const double* __restrict__ Tp)
@@ -847,29 +855,42 @@ __device__ __forceinline__ void sdiag64_task(GemmLds& L, const Task t, const Blo
     const int kb = t.kb, ke = min(t.ke, c);
     const double* H = Hp + d.hoff;       // L_hat(r, j) at H[r + j c]
     const double* X = Ap + d.poff + s;   // X(r, j) at X[r + j ld]
-    d4 acc1[2][4] = {}, acc2[2][4] = {};
-    // A(i, r) = L_hat(r, a0 + i) and B(r, j) = X(r, b0 + j): both contiguous in r
-    auto product = [&](int a0, int b0, d4 (&acc)[2][4]) {
-        auto addrA = [&](int k0, int kk, int ii, bool& ok) -> const double* {
-            const int r = k0 + kk, col = a0 + ii;
-            ok = r < ke && col < s;
-            return ok ? H + r + (int64_t)col * c : H;
-        };
-        auto addrB = [&](int k0, int kk, int j, bool& ok) -> const double* {
-            const int r = k0 + kk, col = b0 + j;
-            ok = r < ke && col < s;
-            return ok ? X + r + (int64_t)col * ld : X;
-        };
-        tile_mma2<64, false, true>(L, kb, ke, acc, addrA, addrB, [](int) { return true; }, [] {});
+    const bool diag = I0 == J0, second = t.flags & 8;
+    // A(i, r) = U(r, I0 + i), B(r, j) = V(r, J0 + j): both contiguous in r
+    const double* U = second ? X : H;
+    const double* V = second ? H : X;
+    const int64_t ldu = second ? ld : c, ldv = second ? c : ld;
+    d4 acc[2][4] = {};
+    auto addrA = [&](int k0, int kk, int ii, bool& ok) -> const double* {
+        const int r = k0 + kk, col = I0 + ii;
+        ok = r < ke && col < s;
+        return ok ? U + r + (int64_t)col * ldu : U;
     };
-    product(I0, J0, acc1);
-    const bool diag = I0 == J0;
-    if (!diag) product(J0, I0, acc2);
-    // the loop ended on a barrier: the LDS tile is free for the exchange
-    double(*S)[TBM + 1] = reinterpret_cast<double(*)[TBM + 1]>(&L);
-    static_assert(sizeof(double) * TBM * (TBM + 1) <= sizeof(GemmLds), "exchange tile fits the LDS tile");
+    auto addrB = [&](int k0, int kk, int j, bool& ok) -> const double* {
+        const int r = k0 + kk, col = J0 + j;
+        ok = r < ke && col < s;
+        return ok ? V + r + (int64_t)col * ldv : V;
+    };
+    tile_mma2<64, false, true>(L, kb, ke, acc, addrA, addrB, [](int) { return true; }, [] {});
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm0 = (wave % SH::WM) * (TBM / SH::WM), wn0 = (wave / SH::WM) * (64 / SH::WN);
+    const double* T = Tp + d.woff;
+    double* A = Ap + d.poff;
+    if (!diag) {
+#pragma unroll
+        for (int mt = 0; mt < SH::MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < SH::NT; ++nt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int gi = I0 + wm0 + mt * 16 + (lane & 15), gj = J0 + wn0 + nt * 16 + (lane >> 4) + 4 * v;
+                    if (gi < s && gj < s) unsafeAtomicAdd(A + gi + (int64_t)gj * ld, -0.5 * acc[mt][nt][v]);
+                }
+        return;
+    }
+    // diagonal tile: the loop ended on a barrier, the LDS tile is free
+    double(*S)[TBM + 1] = reinterpret_cast<double(*)[TBM + 1]>(&L);
+    static_assert(sizeof(double) * TBM * (TBM + 1) <= sizeof(GemmLds), "exchange tile fits the LDS tile");
 #pragma unroll
     for (int mt = 0; mt < SH::MT; ++mt)
 #pragma unroll
@@ -877,11 +898,9 @@ __device__ __forceinline__ void sdiag64_task(GemmLds& L, const Task t, const Blo
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int i = wm0 + mt * 16 + (lane & 15), j = wn0 + nt * 16 + (lane >> 4) + 4 * v;
-                S[j][i] = diag ? acc1[mt][nt][v] : acc2[mt][nt][v];  // S[a][b] = P2(b, a)
+                S[j][i] = acc[mt][nt][v];  // S[a][b] = P(b, a)
             }
     __syncthreads();
-    const double* T = Tp + d.woff;
-    double* A = Ap + d.poff;
     const bool split = t.flags & 1;
 #pragma unroll
     for (int mt = 0; mt < SH::MT; ++mt)
@@ -892,7 +911,7 @@ __device__ __forceinline__ void sdiag64_task(GemmLds& L, const Task t, const Blo
                 const int i = wm0 + mt * 16 + (lane & 15), j = wn0 + nt * 16 + (lane >> 4) + 4 * v;
                 const int gi = I0 + i, gj = J0 + j;
                 if (gi < s && gj < s && gi >= gj) {
-                    const double p = 0.5 * (acc1[mt][nt][v] + S[i][j]);
+                    const double p = 0.5 * (acc[mt][nt][v] + S[i][j]);
                     if (split) unsafeAtomicAdd(A + gi + (int64_t)gj * ld, -p);
                     else A[gi + (int64_t)gj * ld] = T[gi + (int64_t)gj * s] - p;
                 }

@@ -194,9 +194,9 @@ void build_schedule(selinv_plan_s* P)
             if (is_small(d.s, d.c, kSbS) || d.c == 0) continue;
             const int bn = tile_bn(d.s), nd = (d.s + kDiagTile64 - 1) / kDiagTile64;
             gg.push_back({(int64_t)((d.c + kTileM - 1) / kTileM) * ((d.s + bn - 1) / bn), d.c, bn});
-            // a diagonal pair runs one 64 x 64 product, an off-diagonal pair two
-            dg.push_back({(int64_t)nd, d.c, kDiagTile64});
-            if (nd > 1) dg.push_back({(int64_t)nd * (nd - 1) / 2, d.c, 2 * kDiagTile64});
+            // one 64 x 64 product per task: nd diagonal tiles, two halves per
+            // off-diagonal tile
+            dg.push_back({(int64_t)nd * nd, d.c, kDiagTile64});
         }
         const int64_t want = best_split(gg, kGemmSlots, kGemmTaskOvh, 64);
         // a block has only nd (nd + 1) / 2 diagonal pairs: their contraction
@@ -246,13 +246,18 @@ void build_schedule(selinv_plan_s* P)
             // when a level has too few tiles to fill the device
             const int split = split_for(want, c);
             const int dsplit = split_for(dwant, c, kMinSplitKDiag);
-            if (split > 1 || dsplit > 1) P->t_zero.push_back({B, 0, 0, 0, 0, 0, 0, 0});
             const int nd64 = (s + kDiagTile64 - 1) / kDiagTile64;
+            // Ainv(B,B) accumulates (from T) when a contraction is split or
+            // the block has off-diagonal tiles; X only when the GEMM is split
+            const bool acc = dsplit > 1 || nd64 > 1;
+            if (split > 1 || acc) P->t_zero.push_back({B, 0, 0, 0, 0, 0, split > 1, 0});
             for (int I = 0; I < nd64; I++)
                 for (int J = 0; J <= I; J++)
-                    pieces(0, c, dsplit, [&](int kb, int ke, int) {
-                        P->t_sdiag.tasks.push_back({B, I * kDiagTile64, J * kDiagTile64, 0, kb, ke, dsplit > 1, 0});
-                    });
+                    for (int half = 0; half < (I == J ? 1 : 2); half++)
+                        pieces(0, c, dsplit, [&](int kb, int ke, int) {
+                            P->t_sdiag.tasks.push_back(
+                                {B, I * kDiagTile64, J * kDiagTile64, 0, kb, ke, (int)acc | (half << 3), 0});
+                        });
             for (int j = 0; j < s; j += bn)
                 for (int r = 0; r < c; r += kTileM) {
                     P->t_panel.tasks.push_back({B, r, j, bn, 0, s, 0, 0});
