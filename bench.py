@@ -49,6 +49,29 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(workload, kind):
+    """HBM bytes per dispatch of a kernel kind (FETCH_SIZE + WRITE_SIZE, each
+    scaled by the same counter's reading for a plain 1 GiB copy), from the
+    rocprofv3 summary under profiles/; None when there is none for this
+    workload or the kernel source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
+    src = os.path.join(ROOT, "paper_1404_0447_amd", "csrc", "kernels.hip")
+    if not os.path.exists(path):
+        return None
+    rec, sha = {}, None
+    for line in open(path):
+        f = line.split()
+        if len(f) == 5 and f[0] == "traffic":
+            rec[f[1]] = float(f[3]) + float(f[4])
+        elif len(f) == 2 and f[0] == "kernels_sha256_16":
+            sha = f[1]
+    now = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if sha != now or kind not in rec:
+        return None
+    return round(rec[kind], 1)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -60,6 +83,9 @@ def main():
     ap.add_argument("--no-bwd", action="store_true", help="skip the backward (adjoint) timing")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-speedup measurement")
     ap.add_argument("--batch-reps", type=int, default=10, help="timed replays of the batched graph")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="only run a plain device copy of 1 GiB (read 1 GiB, write 1 GiB) three times: the "
+                         "reference dispatch for scaling FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the multi-GPU "
@@ -74,6 +100,15 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.copy_calib:
+        n = 1 << 27  # doubles: 1 GiB
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.add(src, 0.0, out=dst)  # one elementwise kernel: reads src, writes dst
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calib_bytes_read": n * 8, "copy_calib_bytes_written": n * 8, "dispatches": 3}))
+        return
     t0 = time.time()
     m = W.make(args.workload)
     cap = W.CONFIGS[args.workload]["cap"]
@@ -149,6 +184,8 @@ def main():
         achieved = work[dom][0] / (kern_ms[dom] * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None}
+    roof["traffic"] = measured_traffic(args.workload, dom)  # HBM bytes per launch
+    roof["traffic_unit"] = "bytes per launch"
     roof.update({"kernel": dom, "avg_launch_ms": round(per_launch[dom], 5),
                  "launches_per_step": launches_per_step[dom],
                  "algorithmic_per_step": work[dom][0] if roof["unit"] == "TFLOP/s" else work[dom][1]})
