@@ -428,11 +428,11 @@ selinv_status selinv_factor(selinv_plan P, const double* d_valsA, hipStream_t s)
         const auto& q = P->t_sb.off;
         const auto& a = P->t_ldlt.off;
         const auto& b = P->t_panel.off;
-        const auto& c = P->t_schur.off;
         const int64_t diag[4] = {a[l], P->ldlt_cut[2 * l], P->ldlt_cut[2 * l + 1], a[l + 1]};
         e = launch_sb_factor(&P->prof, D, q[l], q[l + 1] - q[l], P->opts.require_spd, s);
+        const auto& cut = P->schur_cuts[l];
         if (!e)
-            e = launch_factor_level(&P->prof, D, diag, b[l], b[l + 1] - b[l], c[l], c[l + 1] - c[l],
+            e = launch_factor_level(&P->prof, D, diag, b[l], b[l + 1] - b[l], cut.data(), (int)cut.size(),
                                     P->opts.require_spd, s);
         if (e) return hip_fail(e, "factor level launch");
     }

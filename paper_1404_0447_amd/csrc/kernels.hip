@@ -2172,7 +2172,7 @@ hipError_t launch_sb_invert(Prof* P, const DevPtrs& D, int64_t sb0, int64_t nsb,
 }
 
 hipError_t launch_factor_level(Prof* P, const DevPtrs& D, const int64_t diag[4], int64_t panel0, int64_t npanel,
-                               int64_t schur0, int64_t nschur, int require_spd, hipStream_t s)
+                               const int64_t* schur_cuts, int ncuts, int require_spd, hipStream_t s)
 {
     // diagonal blocks by width class: [diag[0], diag[1]) s <= 32, then <= 64,
     // then wider
@@ -2188,9 +2188,11 @@ hipError_t launch_factor_level(Prof* P, const DevPtrs& D, const int64_t diag[4],
     if (npanel > 0)
         launch(P, kPanel, k_panel, dim3((unsigned)npanel), 0, s, D.t_panel + panel0, D.blocks,
                (const double*)D.Lp, D.Hp, (const double*)D.Tp);
-    if (nschur > 0)
-        launch(P, kSchur, k_schur, dim3((unsigned)nschur), 0, s, D.t_schur + schur0, D.blocks, D.Lp,
-               (const double*)D.Hp, D.cbase, D.rbase, D.rel);
+    // one launch per colour group (groups update disjoint entries)
+    for (int g = 0; g + 1 < ncuts; g++)
+        if (schur_cuts[g + 1] > schur_cuts[g])
+            launch(P, kSchur, k_schur, dim3((unsigned)(schur_cuts[g + 1] - schur_cuts[g])), 0, s,
+                   D.t_schur + schur_cuts[g], D.blocks, D.Lp, (const double*)D.Hp, D.cbase, D.rbase, D.rel);
     return hipGetLastError();
 }
 

@@ -137,6 +137,8 @@ struct selinv_plan_s {
     // t_diag lists every block (used by the reverse sweep)
     selinv::LevelTasks t_diag, t_ldlt, t_panel, t_schur, t_gemm, t_sdiag, t_sb;
     std::vector<int64_t> ldlt_cut;     // per level: t_ldlt splits into s <= 32 | <= 64 | wider at 2l, 2l+1
+    // per level: t_schur in colour groups [cut[g], cut[g+1]) whose blocks share no column of C
+    std::vector<std::vector<int64_t>> schur_cuts;
     // reverse sweep: selected inversion (leaves first) and factorization (root first)
     selinv::LevelTasks t_rs1, t_rs2, t_rs3, t_rf1a, t_rf1b, t_rf2;
     std::vector<selinv::Task> t_zero;  // blocks whose X accumulates over split contractions

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <functional>
 #include <queue>
+#include <unordered_map>
 
 #include "kernels.hpp"
 #include "plan.hpp"
@@ -96,6 +97,50 @@ static int64_t best_split(const std::vector<TileGroup>& groups, int64_t slots, d
     return best;
 }
 
+// Schur tiles of one level, [t0, end) of `tasks`, appended block by block.
+// Two blocks update a common ancestor entry exactly when their C share a
+// column, so a greedy colouring of the level's blocks (largest update
+// first; colour = lowest one no block sharing a column has taken) gives
+// groups whose updates are disjoint: each group runs as one launch with
+// plain read-modify-write (flags bit 2).  Past 63 colours the rest keep
+// FP64 atomics in a last group.  cuts receives the group boundaries.
+static void schur_colours(const selinv_plan_s* P, std::vector<Task>& tasks, int64_t t0, std::vector<uint64_t>& mask,
+                          std::vector<int64_t>& cuts)
+{
+    const std::vector<int32_t>& cr = P->crow;
+    std::vector<int> bl;
+    for (int64_t t = t0; t < (int64_t)tasks.size(); t++)
+        if (bl.empty() || bl.back() != tasks[t].b) bl.push_back(tasks[t].b);
+    std::vector<int> order = bl;
+    auto work = [&](int B) {
+        const BlockDesc& d = P->blocks[B];
+        return (double)d.c * d.c * d.s;
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
+    std::unordered_map<int, int> col;
+    for (int B : order) {
+        const BlockDesc& d = P->blocks[B];
+        uint64_t used = 0;
+        for (int r = 0; r < d.c; r++) used |= mask[cr[d.coff + r]];
+        int k = 0;
+        while (k < 63 && ((used >> k) & 1)) k++;
+        col[B] = k;
+        for (int r = 0; r < d.c; r++) mask[cr[d.coff + r]] |= uint64_t(1) << k;
+    }
+    for (int B : bl) {
+        const BlockDesc& d = P->blocks[B];
+        for (int r = 0; r < d.c; r++) mask[cr[d.coff + r]] = 0;
+    }
+    std::stable_sort(tasks.begin() + t0, tasks.end(), [&](const Task& a, const Task& b) { return col[a.b] < col[b.b]; });
+    cuts.assign(1, t0);
+    for (int64_t t = t0; t < (int64_t)tasks.size(); t++) {
+        const int k = col[tasks[t].b];
+        tasks[t].flags = k < 63 ? (tasks[t].flags | 4) : (tasks[t].flags & ~4);
+        if (t > t0 && k != col[tasks[t - 1].b]) cuts.push_back(t);
+    }
+    cuts.push_back((int64_t)tasks.size());
+}
+
 // Blocks of one level whose Schur updates no other block of the level
 // touches: two blocks update a common ancestor entry exactly when their row
 // structures C share a column (the diagonal entry of that column), so a
@@ -164,6 +209,8 @@ void build_schedule(selinv_plan_s* P)
     }
     P->t_zero.clear();
     P->ldlt_cut.assign(2 * D, 0);
+    P->schur_cuts.assign(D, {});
+    std::vector<uint64_t> colour_mask((size_t)P->n, 0);
     std::vector<int32_t> touch((size_t)P->n, 0);
     std::vector<char> excl(P->blocks.size(), 0);
     for (int l = 0; l < D; l++) {
@@ -270,6 +317,7 @@ void build_schedule(selinv_plan_s* P)
                 for (int i = k; i < c; i += kSchurTile)
                     P->t_schur.tasks.push_back({B, i, k, kSchurTile, 0, s, excl[B] ? 4 : 0, 0});
         }
+        schur_colours(P, P->t_schur.tasks, P->t_schur.off[l], colour_mask, P->schur_cuts[l]);
         xcd_order(P->t_gemm.tasks, (size_t)P->t_gemm.off[l]);
         // diagonal blocks of the tiled path by width class (one launch each)
         const int64_t cls[] = {32, 64, 1 << 30};
