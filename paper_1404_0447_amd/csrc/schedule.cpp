@@ -167,25 +167,6 @@ static void exclusive_blocks(const selinv_plan_s* P, const std::vector<int>& bl,
     }
 }
 
-// XCD-aware order of one level's tasks [a, end): work-group t is dispatched
-// to XCD t % kXcds, so tasks with equal key % kXcds (the same contraction
-// piece of a split level, whose L_hat slice they share) land on one XCD and
-// reuse its L2.  Keys travel in Task.pad and are cleared.
-static void xcd_order(std::vector<Task>& g, size_t a)
-{
-    std::vector<std::vector<Task>> bucket(kXcds);
-    for (size_t k = a; k < g.size(); k++) bucket[(size_t)g[k].pad % kXcds].push_back(g[k]);
-    std::vector<size_t> next(kXcds, 0);
-    size_t pos = a;
-    for (size_t t = 0; pos < g.size(); t++) {
-        size_t b = t % kXcds;
-        for (int tries = 0; tries < kXcds && next[b] >= bucket[b].size(); tries++) b = (b + 1) % kXcds;
-        Task x = bucket[b][next[b]++];
-        x.pad = 0;
-        g[pos++] = x;
-    }
-}
-
 // small blocks of a level in groups of four (one per wave of a work-group)
 static void push_sb_groups(const std::vector<int>& small, int op, std::vector<Task>& out)
 {
@@ -308,9 +289,8 @@ void build_schedule(selinv_plan_s* P)
             for (int j = 0; j < s; j += bn)
                 for (int r = 0; r < c; r += kTileM) {
                     P->t_panel.tasks.push_back({B, r, j, bn, 0, s, 0, 0});
-                    // key for the XCD order: the piece, else the row tile
-                    pieces(0, c, split, [&](int kb, int ke, int q) {
-                        P->t_gemm.tasks.push_back({B, r, j, bn, kb, ke, split > 1, split > 1 ? q : r / kTileM});
+                    pieces(0, c, split, [&](int kb, int ke, int) {
+                        P->t_gemm.tasks.push_back({B, r, j, bn, kb, ke, split > 1, 0});
                     });
                 }
             for (int k = 0; k < c; k += kSchurTile)
@@ -318,7 +298,6 @@ void build_schedule(selinv_plan_s* P)
                     P->t_schur.tasks.push_back({B, i, k, kSchurTile, 0, s, excl[B] ? 4 : 0, 0});
         }
         schur_colours(P, P->t_schur.tasks, P->t_schur.off[l], colour_mask, P->schur_cuts[l]);
-        xcd_order(P->t_gemm.tasks, (size_t)P->t_gemm.off[l]);
         // diagonal blocks of the tiled path by width class (one launch each)
         const int64_t cls[] = {32, 64, 1 << 30};
         for (int k = 0; k < 3; k++) {

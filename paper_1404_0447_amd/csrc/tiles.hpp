@@ -27,7 +27,6 @@ constexpr long kGemmSlots = 512;
 // fixed cost of one work-group of the split contractions, in 16-deep chunks
 constexpr double kGemmTaskOvh = 12.0;
 constexpr double kSdiagTaskOvh = 8.0;  // smaller epilogue (half a 64 x 64 tile)
-constexpr int kXcds = 8;         // work-group t runs on XCD t % 8
 constexpr int kMinSplitK = 128;  // rows of C per split piece, at least
 constexpr int kMinSplitKDiag = 64;  // the same for the diagonal tile pairs
 
