@@ -385,20 +385,25 @@ __device__ __forceinline__ void tile_mma2(GemmLds& L, int Kb, int Ke, d4 (&acc)[
 // (cbase, rbase) pairs of chunk n+4 are loaded: every load has a whole
 // iteration of MFMAs to arrive, and there is one barrier per chunk.
 // ---------------------------------------------------------------------------
-template <int BN, bool kPair = false>
-__device__ __forceinline__ void gemm_task(GemmLds& L, const Task t, const BlockDesc d, double* __restrict__ Ap,
-                          const double* __restrict__ Hp, const int64_t* __restrict__ cbase,
-                          const int64_t* __restrict__ rbase, const int32_t* __restrict__ rel)
+// The pipelined gather-GEMM loop, shared by the forward gather-GEMM and the
+// reverse sweep: acc += A B over the contraction [Kb, Ke) for tile rows
+// [r0, r0+64) and columns [n0, n0+BN), accumulated transposed, with
+//   A(i, k) = S[cbase[p] + rel[rbase[p] + q]],  p = min(i, k), q = max(i, k)
+// (an arena gathered through the block index maps; kTri = 1 keeps k <= i
+// only, 2 keeps k >= i only, 0 all) and B(k, j) = Bm[k + (n0 + j) ldb].
+template <int BN, bool kPair, int kTri>
+__device__ __forceinline__ void gather_mma(GemmLds& L, const BlockDesc d, const int r0, const int n0, const int Kb,
+                                           const int Ke, const double* __restrict__ S, const double* __restrict__ Bm,
+                                           const int64_t ldb, const int64_t* __restrict__ cbase,
+                                           const int64_t* __restrict__ rbase, const int32_t* __restrict__ rel,
+                                           d4 (&acc)[2][4])
 {
     using SH = TileShape<BN>;
     constexpr int NB = BN / 16;  // B elements per thread per chunk
     const int s = d.s, c = d.c;
-    const int64_t ld = (int64_t)s + c;
-    const int r0 = t.i0, n0 = t.j0;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm0 = (wave % SH::WM) * (TBM / SH::WM), wn0 = (wave / SH::WM) * (BN / SH::WN);
-    const int Kb = t.kb;
-    const int nch = t.ke > Kb ? (t.ke - Kb + TBK - 1) / TBK : 0;
+    const int nch = Ke > Kb ? (Ke - Kb + TBK - 1) / TBK : 0;
     // chunks entirely above the diagonal band are read along k (contiguous)
     auto along_of = [&](int ch) { return Kb + ch * TBK >= r0 + TBM; };
     // element q of this thread in chunk ch: (kk, ii) = along ? (e & 15, e >> 4) : (e >> 6, e & 63)
@@ -428,7 +433,7 @@ __device__ __forceinline__ void gemm_task(GemmLds& L, const Task t, const BlockD
         for (int q = 0; q < 4; ++q) {
             int i, k;
             elem(ch, q, i, k);
-            const bool ok = i < c && k < c;
+            const bool ok = i < c && k < c && (kTri == 0 || (kTri == 1 ? k <= i : k >= i));
             const int64_t p = d.coff + (ok ? (i >= k ? k : i) : 0);
             m_cb[q] = cbase[p];
             m_rb[q] = rbase[p];
@@ -447,7 +452,7 @@ __device__ __forceinline__ void gemm_task(GemmLds& L, const Task t, const BlockD
         av = along_of(ch);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            v_a[q] = Ap[r_cb[q] + r_rel[q]];
+            v_a[q] = S[r_cb[q] + r_rel[q]];
             v_ok[q] = r_ok[q];
         }
         // L_hat needs no mask: where k >= c the gathered A is zero, and
@@ -461,7 +466,7 @@ __device__ __forceinline__ void gemm_task(GemmLds& L, const Task t, const BlockD
                 const int e = tid + q * kThreads;
                 const int k = k0 + 2 * (e & 7), jj = n0 + (e >> 3);
                 const bool ok = k < c && jj < s;
-                const d2u pr = *reinterpret_cast<const d2u*>(Hp + d.hoff + (ok ? k + (int64_t)jj * c : 0));
+                const d2u pr = *reinterpret_cast<const d2u*>(Bm + (ok ? k + (int64_t)jj * ldb : 0));
                 v_b[2 * q] = pr.x;
                 v_b[2 * q + 1] = pr.y;
             }
@@ -470,7 +475,7 @@ __device__ __forceinline__ void gemm_task(GemmLds& L, const Task t, const BlockD
             for (int q = 0; q < NB; ++q) {
                 const int e = tid + q * kThreads;
                 const int k = k0 + (e & 15), jj = n0 + (e >> 4);
-                v_b[q] = Hp[d.hoff + ((k < c && jj < s) ? k + (int64_t)jj * c : 0)];
+                v_b[q] = Bm[(k < c && jj < s) ? k + (int64_t)jj * ldb : 0];
             }
         }
     };
@@ -497,7 +502,6 @@ __device__ __forceinline__ void gemm_task(GemmLds& L, const Task t, const BlockD
             }
         }
     };
-    d4 acc[2][4] = {};
     // prologue: chunk 0 in LDS, chunk 1 values, chunk 2 offsets, chunk 3
     // (cbase, rbase).  Chunks past the end are all padding: the stages run
     // for them anyway, so the loop body has no branches.
@@ -534,6 +538,18 @@ __device__ __forceinline__ void gemm_task(GemmLds& L, const Task t, const BlockD
         __syncthreads();
     }
     mfma_drain();
+}
+
+template <int BN, bool kPair = false>
+__device__ __forceinline__ void gemm_task(GemmLds& L, const Task t, const BlockDesc d, double* __restrict__ Ap,
+                          const double* __restrict__ Hp, const int64_t* __restrict__ cbase,
+                          const int64_t* __restrict__ rbase, const int32_t* __restrict__ rel)
+{
+    const int s = d.s, c = d.c;
+    const int64_t ld = (int64_t)s + c;
+    const int r0 = t.i0, n0 = t.j0;
+    d4 acc[2][4] = {};
+    gather_mma<BN, kPair, 0>(L, d, r0, n0, t.kb, t.ke, Ap, Hp + d.hoff, c, cbase, rbase, rel, acc);
     // transposed accumulation: stores and atomics run down the columns of X
     tile_epilogue_t<BN>(acc, [&](int i, int j, double v) {
         const int ii = r0 + i, jj = n0 + j;
@@ -891,6 +907,7 @@ __device__ __forceinline__ void sdiag64_task(GemmLds& L, const Task t, const Blo
     // diagonal tile: the loop ended on a barrier, the LDS tile is free
     double(*S)[TBM + 1] = reinterpret_cast<double(*)[TBM + 1]>(&L);
     static_assert(sizeof(double) * TBM * (TBM + 1) <= sizeof(GemmLds), "exchange tile fits the LDS tile");
+    static_assert(sizeof(TileLds) <= sizeof(GemmLds), "the one-stage tile fits the LDS tile");
 #pragma unroll
     for (int mt = 0; mt < SH::MT; ++mt)
 #pragma unroll
@@ -1711,8 +1728,8 @@ __global__ __launch_bounds__(kThreads) void k_rs1(const Task* __restrict__ tasks
 #undef SELINV_CALL
 }
 
-template <int BN>
-__device__ void rs2_task(TileLds& L, const Task t, const BlockDesc d, const double* __restrict__ Ap,
+template <int BN, bool kPair>
+__device__ void rs2_task(GemmLds& L, const Task t, const BlockDesc d, const double* __restrict__ Ap,
                          const double* __restrict__ Zb, double* __restrict__ Hb, const int64_t* __restrict__ cbase,
                          const int64_t* __restrict__ rbase, const int32_t* __restrict__ rel)
 {
@@ -1721,21 +1738,8 @@ __device__ void rs2_task(TileLds& L, const Task t, const BlockDesc d, const doub
     const int r0 = t.i0, n0 = t.j0;
     const double* Zd = Zb + d.poff;
     d4 acc[2][4] = {};
-    auto loadG = [&](int k0, int kk, int ii) -> double {
-        const int i = r0 + ii, k = k0 + kk;
-        if (i >= c || k >= c) return 0.0;
-        if (i >= k) {
-            const int64_t pk = d.coff + k;
-            return Ap[cbase[pk] + rel[rbase[pk] + i]];
-        }
-        const int64_t pi = d.coff + i;
-        return Ap[cbase[pi] + rel[rbase[pi] + k]];
-    };
-    auto loadXb = [&](int k0, int kk, int j) -> double {
-        const int k = k0 + kk, jj = n0 + j;
-        return (k < c && jj < s) ? Zb[d.poff + s + k + (int64_t)jj * ld] : 0.0;
-    };
-    tile_mma<BN>(L, t.kb, t.ke, acc, loadG, loadXb, [&](int k0) { return k0 >= r0 + TBM; });
+    // G Xbar: G gathered from the inverse panels, Xbar = Zbar(C,B)
+    gather_mma<BN, kPair, 0>(L, d, r0, n0, t.kb, t.ke, Ap, Zb + d.poff + s, ld, cbase, rbase, rel, acc);
     if (t.kb == 0) {  // -X Ybar, once per tile
         auto loadX = [&](int k0, int kk, int ii) -> double {
             const int i = r0 + ii, k = k0 + kk;
@@ -1745,7 +1749,7 @@ __device__ void rs2_task(TileLds& L, const Task t, const BlockDesc d, const doub
             const int k = k0 + kk, jj = n0 + j;
             return (k < s && jj < s) ? ybar_at(Zd, ld, k, jj) : 0.0;
         };
-        tile_mma<BN>(L, 0, s, acc, loadX, loadY, [](int) { return false; });
+        tile_mma<BN>(reinterpret_cast<TileLds&>(L), 0, s, acc, loadX, loadY, [](int) { return false; });
     }
     tile_epilogue_t<BN>(acc, [&](int i, int j, double v) {
         const int ii = r0 + i, jj = n0 + j;
@@ -1761,10 +1765,12 @@ __global__ __launch_bounds__(kThreads) void k_rs2(const Task* __restrict__ tasks
                                                   double* __restrict__ Hb, const int64_t* __restrict__ cbase,
                                                   const int64_t* __restrict__ rbase, const int32_t* __restrict__ rel)
 {
-    __shared__ TileLds L;
+    __shared__ GemmLds L;
     const Task t = tasks[blockIdx.x];
     const BlockDesc d = blk[t.b];
-#define SELINV_CALL(BN) rs2_task<BN>(L, t, d, Ap, Zb, Hb, cbase, rbase, rel)
+#define SELINV_CALL(BN)                                                                        \
+    if (BN >= 32 && (d.c & 1) == 0) rs2_task<BN, BN >= 32>(L, t, d, Ap, Zb, Hb, cbase, rbase, rel); \
+    else rs2_task<BN, false>(L, t, d, Ap, Zb, Hb, cbase, rbase, rel)
     SELINV_BN_DISPATCH(t.bn, SELINV_CALL)
 #undef SELINV_CALL
 }
@@ -1816,8 +1822,8 @@ __global__ void k_tbar_init(const Task* __restrict__ tasks, const BlockDesc* __r
 }
 
 // Lhat_bar += Ubar F(C,B), Ubar(i,k) = -Fbar(C[i],C[k]) for i >= k
-template <int BN>
-__device__ void rf1a_task(TileLds& L, const Task t, const BlockDesc d, const double* __restrict__ Zb,
+template <int BN, bool kPair>
+__device__ void rf1a_task(GemmLds& L, const Task t, const BlockDesc d, const double* __restrict__ Zb,
                           const double* __restrict__ Lp, double* __restrict__ Hb, const int64_t* __restrict__ cbase,
                           const int64_t* __restrict__ rbase, const int32_t* __restrict__ rel)
 {
@@ -1825,22 +1831,13 @@ __device__ void rf1a_task(TileLds& L, const Task t, const BlockDesc d, const dou
     const int64_t ld = (int64_t)s + c;
     const int r0 = t.i0, n0 = t.j0;
     d4 acc[2][4] = {};
-    auto loadA = [&](int k0, int kk, int ii) -> double {
-        const int i = r0 + ii, k = k0 + kk;
-        if (i >= c || k > i) return 0.0;
-        const int64_t pk = d.coff + k;
-        return -Zb[cbase[pk] + rel[rbase[pk] + i]];
-    };
-    auto loadB = [&](int k0, int kk, int j) -> double {
-        const int k = k0 + kk, jj = n0 + j;
-        return (k < c && jj < s) ? Lp[d.poff + s + k + (int64_t)jj * ld] : 0.0;
-    };
-    tile_mma<BN>(L, t.kb, t.ke, acc, loadA, loadB, [](int) { return false; });
+    // Ubar(i,k) = -Fbar(C[i],C[k]) for k <= i, gathered from the adjoint panels; B = F(C,B)
+    gather_mma<BN, kPair, 1>(L, d, r0, n0, t.kb, t.ke, Zb, Lp + d.poff + s, ld, cbase, rbase, rel, acc);
     tile_epilogue_t<BN>(acc, [&](int i, int j, double v) {
         const int ii = r0 + i, jj = n0 + j;
         if (ii < c && jj < s) {
             double* p = Hb + d.hoff + ii + (int64_t)jj * c;
-            if (t.flags & 1) unsafeAtomicAdd(p, v); else *p += v;
+            if (t.flags & 1) unsafeAtomicAdd(p, -v); else *p -= v;
         }
     });
 }
@@ -1851,17 +1848,19 @@ __global__ __launch_bounds__(kThreads) void k_rf1a(const Task* __restrict__ task
                                                    const int64_t* __restrict__ rbase,
                                                    const int32_t* __restrict__ rel)
 {
-    __shared__ TileLds L;
+    __shared__ GemmLds L;
     const Task t = tasks[blockIdx.x];
     const BlockDesc d = blk[t.b];
-#define SELINV_CALL(BN) rf1a_task<BN>(L, t, d, Zb, Lp, Hb, cbase, rbase, rel)
+#define SELINV_CALL(BN)                                                                         \
+    if (BN >= 32 && (d.c & 1) == 0) rf1a_task<BN, BN >= 32>(L, t, d, Zb, Lp, Hb, cbase, rbase, rel); \
+    else rf1a_task<BN, false>(L, t, d, Zb, Lp, Hb, cbase, rbase, rel)
     SELINV_BN_DISPATCH(t.bn, SELINV_CALL)
 #undef SELINV_CALL
 }
 
 // Fbar(C,B) = Ubar^T L_hat (+ Lhat_bar T on piece 0), Ubar^T(i,k) = -Fbar(C[k],C[i]) for k >= i
-template <int BN>
-__device__ void rf1b_task(TileLds& L, const Task t, const BlockDesc d, double* __restrict__ Zb,
+template <int BN, bool kPair>
+__device__ void rf1b_task(GemmLds& L, const Task t, const BlockDesc d, double* __restrict__ Zb,
                           const double* __restrict__ Hp, const double* __restrict__ Hb, const double* __restrict__ Tp,
                           const int64_t* __restrict__ cbase, const int64_t* __restrict__ rbase,
                           const int32_t* __restrict__ rel)
@@ -1870,17 +1869,12 @@ __device__ void rf1b_task(TileLds& L, const Task t, const BlockDesc d, double* _
     const int64_t ld = (int64_t)s + c;
     const int r0 = t.i0, n0 = t.j0;
     d4 acc[2][4] = {};
-    auto loadA = [&](int k0, int kk, int ii) -> double {
-        const int i = r0 + ii, k = k0 + kk;
-        if (i >= c || k >= c || k < i) return 0.0;
-        const int64_t pi = d.coff + i;
-        return -Zb[cbase[pi] + rel[rbase[pi] + k]];
-    };
-    auto loadB = [&](int k0, int kk, int j) -> double {
-        const int k = k0 + kk, jj = n0 + j;
-        return (k < c && jj < s) ? Hp[d.hoff + k + (int64_t)jj * c] : 0.0;
-    };
-    tile_mma<BN>(L, t.kb, t.ke, acc, loadA, loadB, [&](int k0) { return k0 >= r0 + TBM; });
+    // -Ubar^T L_hat: Fbar(C[k],C[i]) for k >= i, gathered from the adjoint panels
+    gather_mma<BN, kPair, 2>(L, d, r0, n0, t.kb, t.ke, Zb, Hp + d.hoff, c, cbase, rbase, rel, acc);
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = -acc[mt][nt];
     if (t.flags & 2) {
         auto loadA2 = [&](int k0, int kk, int ii) -> double {
             const int i = r0 + ii, k = k0 + kk;
@@ -1890,7 +1884,7 @@ __device__ void rf1b_task(TileLds& L, const Task t, const BlockDesc d, double* _
             const int k = k0 + kk, jj = n0 + j;
             return (k < s && jj < s) ? Tp[d.woff + k + (int64_t)jj * s] : 0.0;
         };
-        tile_mma<BN>(L, 0, s, acc, loadA2, loadB2, [](int) { return false; });
+        tile_mma<BN>(reinterpret_cast<TileLds&>(L), 0, s, acc, loadA2, loadB2, [](int) { return false; });
     }
     tile_epilogue_t<BN>(acc, [&](int i, int j, double v) {
         const int ii = r0 + i, jj = n0 + j;
@@ -1908,10 +1902,12 @@ __global__ __launch_bounds__(kThreads) void k_rf1b(const Task* __restrict__ task
                                                    const int64_t* __restrict__ rbase,
                                                    const int32_t* __restrict__ rel)
 {
-    __shared__ TileLds L;
+    __shared__ GemmLds L;
     const Task t = tasks[blockIdx.x];
     const BlockDesc d = blk[t.b];
-#define SELINV_CALL(BN) rf1b_task<BN>(L, t, d, Zb, Hp, Hb, Tp, cbase, rbase, rel)
+#define SELINV_CALL(BN)                                                                             \
+    if (BN >= 32 && (d.c & 1) == 0) rf1b_task<BN, BN >= 32>(L, t, d, Zb, Hp, Hb, Tp, cbase, rbase, rel); \
+    else rf1b_task<BN, false>(L, t, d, Zb, Hp, Hb, Tp, cbase, rbase, rel)
     SELINV_BN_DISPATCH(t.bn, SELINV_CALL)
 #undef SELINV_CALL
 }
