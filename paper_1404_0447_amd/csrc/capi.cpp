@@ -51,6 +51,7 @@ void compute_layout(selinv_plan_s* P)
     L.blocks = take(sizeof(BlockDesc) * P->blocks.size());
     L.crow = take(sizeof(int32_t) * P->crow.size());
     L.cbase = take(sizeof(int64_t) * P->cbase.size());
+    L.cr2 = take(2 * sizeof(int64_t) * P->cbase.size());
     L.rbase = take(sizeof(int64_t) * P->rbase.size());
     L.rel = take(sizeof(int32_t) * P->rel.size());
     L.asm_off = take(sizeof(int64_t) * P->asm_off.size());
@@ -99,6 +100,7 @@ DevPtrs dev_ptrs(const selinv_plan_s* P)
     D.blocks = (const BlockDesc*)(w + L.blocks);
     D.crow = (const int32_t*)(w + L.crow);
     D.cbase = (const int64_t*)(w + L.cbase);
+    D.cr2 = (const int64_t*)(w + L.cr2);
     D.rbase = (const int64_t*)(w + L.rbase);
     D.rel = (const int32_t*)(w + L.rel);
     D.asm_off = (const int64_t*)(w + L.asm_off);
@@ -381,6 +383,14 @@ selinv_status selinv_bind_workspace(selinv_plan P, void* d_ws, size_t bytes, hip
     if (!e) e = upload(P->ws, L.blocks, P->blocks, s);
     if (!e) e = upload(P->ws, L.crow, P->crow, s);
     if (!e) e = upload(P->ws, L.cbase, P->cbase, s);
+    if (!e) {
+        P->cr2.resize(2 * P->cbase.size());
+        for (size_t p = 0; p < P->cbase.size(); p++) {
+            P->cr2[2 * p] = P->cbase[p];
+            P->cr2[2 * p + 1] = P->rbase[p];
+        }
+        e = upload(P->ws, L.cr2, P->cr2, s);
+    }
     if (!e) e = upload(P->ws, L.rbase, P->rbase, s);
     if (!e) e = upload(P->ws, L.rel, P->rel, s);
     if (!e) e = upload(P->ws, L.asm_off, P->asm_off, s);

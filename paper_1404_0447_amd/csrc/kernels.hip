@@ -33,6 +33,8 @@ namespace selinv {
 typedef double d4 __attribute__((ext_vector_type(4)));
 // two doubles read with one load from an 8-byte aligned address
 typedef double d2u __attribute__((ext_vector_type(2), aligned(8)));
+// (cbase, rbase) of one position, one 16-byte load
+typedef int64_t i64x2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ d4 mfma(double a, double b, d4 c)
 {
@@ -272,7 +274,7 @@ struct GemmLds {
     double B[2][TBK][128 + TPAD];
 };
 
-template <int BN, bool kBJ, bool kT, class FA, class FB, class FAK, class FH>
+template <int BN, bool kBJ, bool kT, bool kPairK = false, class FA, class FB, class FAK, class FH>
 __device__ __forceinline__ void tile_mma2(GemmLds& L, int Kb, int Ke, d4 (&acc)[2][4], FA addrA, FB addrB,
                                           FAK alongA, FH afterPrologue)
 {
@@ -285,10 +287,28 @@ __device__ __forceinline__ void tile_mma2(GemmLds& L, int Kb, int Ke, d4 (&acc)[
     bool oka[4], okb[NB], ala = false;
     double va[4], vb[NB];          // stage VAL
     bool vka[4], vkb[NB], vla = false;
+    // kPairK (both operands read along k, kBJ false, every chunk along k):
+    // rows k, k+1 of one column per load, the caller guaranteeing that a
+    // pair never straddles the end of the contraction
     auto stage_addr = [&](int ch) {
         const int k0 = Kb + ch * TBK;
         const bool past = ch >= nch;
         ala = alongA(k0);
+        if constexpr (kPairK) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int e = tid + q * kThreads;
+                pa[q] = addrA(k0, 2 * (e & 7), e >> 3, oka[q]);
+                oka[q] = oka[q] && !past;
+            }
+#pragma unroll
+            for (int q = 0; q < NB / 2; ++q) {
+                const int e = tid + q * kThreads;
+                pb[q] = addrB(k0, 2 * (e & 7), e >> 3, okb[q]);
+                okb[q] = okb[q] && !past;
+            }
+            return;
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int e = tid + q * kThreads;
@@ -306,6 +326,23 @@ __device__ __forceinline__ void tile_mma2(GemmLds& L, int Kb, int Ke, d4 (&acc)[
     };
     auto stage_val = [&]() {
         vla = ala;
+        if constexpr (kPairK) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const d2u x = *reinterpret_cast<const d2u*>(pa[q]);
+                va[2 * q] = x.x;
+                va[2 * q + 1] = x.y;
+                vka[q] = oka[q];
+            }
+#pragma unroll
+            for (int q = 0; q < NB / 2; ++q) {
+                const d2u x = *reinterpret_cast<const d2u*>(pb[q]);
+                vb[2 * q] = x.x;
+                vb[2 * q + 1] = x.y;
+                vkb[q] = okb[q];
+            }
+            return;
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             va[q] = *pa[q];
@@ -318,6 +355,21 @@ __device__ __forceinline__ void tile_mma2(GemmLds& L, int Kb, int Ke, d4 (&acc)[
         }
     };
     auto stage_store = [&](int buf) {
+        if constexpr (kPairK) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int e = tid + q * kThreads;
+                L.A[buf][2 * (e & 7)][e >> 3] = vka[q] ? va[2 * q] : 0.0;
+                L.A[buf][2 * (e & 7) + 1][e >> 3] = vka[q] ? va[2 * q + 1] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < NB / 2; ++q) {
+                const int e = tid + q * kThreads;
+                L.B[buf][2 * (e & 7)][e >> 3] = vkb[q] ? vb[2 * q] : 0.0;
+                L.B[buf][2 * (e & 7) + 1][e >> 3] = vkb[q] ? vb[2 * q + 1] : 0.0;
+            }
+            return;
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int e = tid + q * kThreads;
@@ -394,9 +446,8 @@ __device__ __forceinline__ void tile_mma2(GemmLds& L, int Kb, int Ke, d4 (&acc)[
 template <int BN, bool kPair, int kTri>
 __device__ __forceinline__ void gather_mma(GemmLds& L, const BlockDesc d, const int r0, const int n0, const int Kb,
                                            const int Ke, const double* __restrict__ S, const double* __restrict__ Bm,
-                                           const int64_t ldb, const int64_t* __restrict__ cbase,
-                                           const int64_t* __restrict__ rbase, const int32_t* __restrict__ rel,
-                                           d4 (&acc)[2][4])
+                                           const int64_t ldb, const int64_t* __restrict__ cr2,
+                                           const int32_t* __restrict__ rel, d4 (&acc)[2][4])
 {
     using SH = TileShape<BN>;
     constexpr int NB = BN / 16;  // B elements per thread per chunk
@@ -435,8 +486,9 @@ __device__ __forceinline__ void gather_mma(GemmLds& L, const BlockDesc d, const 
             elem(ch, q, i, k);
             const bool ok = i < c && k < c && (kTri == 0 || (kTri == 1 ? k <= i : k >= i));
             const int64_t p = d.coff + (ok ? (i >= k ? k : i) : 0);
-            m_cb[q] = cbase[p];
-            m_rb[q] = rbase[p];
+            const i64x2 cr = *reinterpret_cast<const i64x2*>(cr2 + 2 * p);  // (cbase[p], rbase[p])
+            m_cb[q] = cr.x;
+            m_rb[q] = cr.y;
             m_q[q] = ok ? (i >= k ? i : k) : -1;
         }
     };
@@ -542,14 +594,13 @@ __device__ __forceinline__ void gather_mma(GemmLds& L, const BlockDesc d, const 
 
 template <int BN, bool kPair = false>
 __device__ __forceinline__ void gemm_task(GemmLds& L, const Task t, const BlockDesc d, double* __restrict__ Ap,
-                          const double* __restrict__ Hp, const int64_t* __restrict__ cbase,
-                          const int64_t* __restrict__ rbase, const int32_t* __restrict__ rel)
+                          const double* __restrict__ Hp, const int64_t* __restrict__ cr2, const int32_t* __restrict__ rel)
 {
     const int s = d.s, c = d.c;
     const int64_t ld = (int64_t)s + c;
     const int r0 = t.i0, n0 = t.j0;
     d4 acc[2][4] = {};
-    gather_mma<BN, kPair, 0>(L, d, r0, n0, t.kb, t.ke, Ap, Hp + d.hoff, c, cbase, rbase, rel, acc);
+    gather_mma<BN, kPair, 0>(L, d, r0, n0, t.kb, t.ke, Ap, Hp + d.hoff, c, cr2, rel, acc);
     // transposed accumulation: stores and atomics run down the columns of X
     tile_epilogue_t<BN>(acc, [&](int i, int j, double v) {
         const int ii = r0 + i, jj = n0 + j;
@@ -562,8 +613,7 @@ __device__ __forceinline__ void gemm_task(GemmLds& L, const Task t, const BlockD
 
 __global__ __launch_bounds__(kThreads) void k_gemm(const Task* __restrict__ tasks, const BlockDesc* __restrict__ blk,
                                                    double* __restrict__ Ap, const double* __restrict__ Hp,
-                                                   const int64_t* __restrict__ cbase,
-                                                   const int64_t* __restrict__ rbase,
+                                                   const int64_t* __restrict__ cr2,
                                                    const int32_t* __restrict__ rel)
 {
     __shared__ GemmLds L;
@@ -571,8 +621,8 @@ __global__ __launch_bounds__(kThreads) void k_gemm(const Task* __restrict__ task
     const BlockDesc d = blk[t.b];
     // even |C|: L_hat read two rows per load
 #define SELINV_CALL(BN)                                                \
-    if (BN >= 32 && (d.c & 1) == 0) gemm_task<BN, BN >= 32>(L, t, d, Ap, Hp, cbase, rbase, rel); \
-    else gemm_task<BN, false>(L, t, d, Ap, Hp, cbase, rbase, rel)
+    if (BN >= 32 && (d.c & 1) == 0) gemm_task<BN, BN >= 32>(L, t, d, Ap, Hp, cr2, rel); \
+    else gemm_task<BN, false>(L, t, d, Ap, Hp, cr2, rel)
     SELINV_BN_DISPATCH(t.bn, SELINV_CALL)
 #undef SELINV_CALL
 }
@@ -887,7 +937,11 @@ __device__ __forceinline__ void sdiag64_task(GemmLds& L, const Task t, const Blo
         ok = r < ke && col < s;
         return ok ? V + r + (int64_t)col * ldv : V;
     };
-    tile_mma2<64, false, true>(L, kb, ke, acc, addrA, addrB, [](int) { return true; }, [] {});
+    // pairs of rows never straddle the end of the contraction when c and kb are even
+    if ((c & 1) == 0 && (kb & 1) == 0)
+        tile_mma2<64, false, true, true>(L, kb, ke, acc, addrA, addrB, [](int) { return true; }, [] {});
+    else
+        tile_mma2<64, false, true>(L, kb, ke, acc, addrA, addrB, [](int) { return true; }, [] {});
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm0 = (wave % SH::WM) * (TBM / SH::WM), wn0 = (wave / SH::WM) * (64 / SH::WN);
     const double* T = Tp + d.woff;
@@ -1477,16 +1531,16 @@ __device__ __forceinline__ void panel_bounded(GemmLds& L, const Task& t, const B
 // gather-GEMM tile; the host keeps t.bn <= BNMAX in this variant's levels
 template <int BNMAX>
 __device__ __forceinline__ void gemm_bounded(GemmLds& L, const Task& t, const BlockDesc& d, double* Ap,
-                                             const double* Hp, const int64_t* cbase, const int64_t* rbase,
+                                             const double* Hp, const int64_t* cr2,
                                              const int32_t* rel)
 {
     if (t.bn <= 16) {
-        gemm_task<16>(L, t, d, Ap, Hp, cbase, rbase, rel);
+        gemm_task<16>(L, t, d, Ap, Hp, cr2, rel);
     } else if (t.bn <= 32) {
-        gemm_task<32>(L, t, d, Ap, Hp, cbase, rbase, rel);
+        gemm_task<32>(L, t, d, Ap, Hp, cr2, rel);
     } else if constexpr (BNMAX >= 64) {
-        if (t.bn <= 64) gemm_task<64>(L, t, d, Ap, Hp, cbase, rbase, rel);
-        else if constexpr (BNMAX >= 128) gemm_task<128>(L, t, d, Ap, Hp, cbase, rbase, rel);
+        if (t.bn <= 64) gemm_task<64>(L, t, d, Ap, Hp, cr2, rel);
+        else if constexpr (BNMAX >= 128) gemm_task<128>(L, t, d, Ap, Hp, cr2, rel);
     }
 }
 
@@ -1567,7 +1621,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_persist_invert(const QueueArgs 
                                                                 const double* __restrict__ Tp,
                                                                 const int64_t* __restrict__ cbase,
                                                                 const int64_t* __restrict__ rbase,
-                                                                const int32_t* __restrict__ rel)
+                                                                const int32_t* __restrict__ rel,
+                                                                const int64_t* __restrict__ cr2)
 {
     __shared__ PersistLds sm;
     __shared__ int s_idx;
@@ -1610,7 +1665,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_persist_invert(const QueueArgs 
                     zero_task(d, Ap, Tp);
                     break;
                 case qGemm:
-                    gemm_bounded<BNMAX>(sm.gemm, u, d, Ap, Hp, cbase, rbase, rel);
+                    gemm_bounded<BNMAX>(sm.gemm, u, d, Ap, Hp, cr2, rel);
                     break;
                 default:
                     sdiag_task(sm.sd, u, d, Ap, Hp, Tp);
@@ -1653,7 +1708,8 @@ __global__ __launch_bounds__(kThreads) void k_light_invert(const QueueArgs a, co
                                                            const double* __restrict__ Tp,
                                                            const int64_t* __restrict__ cbase,
                                                            const int64_t* __restrict__ rbase,
-                                                           const int32_t* __restrict__ rel)
+                                                           const int32_t* __restrict__ rel,
+                                                                const int64_t* __restrict__ cr2)
 {
     __shared__ SbLds S[kThreads / 64];
     const int64_t nslots = a.ntasks * kSbPerTask;
@@ -1730,8 +1786,7 @@ __global__ __launch_bounds__(kThreads) void k_rs1(const Task* __restrict__ tasks
 
 template <int BN, bool kPair>
 __device__ void rs2_task(GemmLds& L, const Task t, const BlockDesc d, const double* __restrict__ Ap,
-                         const double* __restrict__ Zb, double* __restrict__ Hb, const int64_t* __restrict__ cbase,
-                         const int64_t* __restrict__ rbase, const int32_t* __restrict__ rel)
+                         const double* __restrict__ Zb, double* __restrict__ Hb, const int64_t* __restrict__ cr2, const int32_t* __restrict__ rel)
 {
     const int s = d.s, c = d.c;
     const int64_t ld = (int64_t)s + c;
@@ -1739,7 +1794,7 @@ __device__ void rs2_task(GemmLds& L, const Task t, const BlockDesc d, const doub
     const double* Zd = Zb + d.poff;
     d4 acc[2][4] = {};
     // G Xbar: G gathered from the inverse panels, Xbar = Zbar(C,B)
-    gather_mma<BN, kPair, 0>(L, d, r0, n0, t.kb, t.ke, Ap, Zb + d.poff + s, ld, cbase, rbase, rel, acc);
+    gather_mma<BN, kPair, 0>(L, d, r0, n0, t.kb, t.ke, Ap, Zb + d.poff + s, ld, cr2, rel, acc);
     if (t.kb == 0) {  // -X Ybar, once per tile
         auto loadX = [&](int k0, int kk, int ii) -> double {
             const int i = r0 + ii, k = k0 + kk;
@@ -1762,15 +1817,14 @@ __device__ void rs2_task(GemmLds& L, const Task t, const BlockDesc d, const doub
 
 __global__ __launch_bounds__(kThreads) void k_rs2(const Task* __restrict__ tasks, const BlockDesc* __restrict__ blk,
                                                   const double* __restrict__ Ap, const double* __restrict__ Zb,
-                                                  double* __restrict__ Hb, const int64_t* __restrict__ cbase,
-                                                  const int64_t* __restrict__ rbase, const int32_t* __restrict__ rel)
+                                                  double* __restrict__ Hb, const int64_t* __restrict__ cr2, const int32_t* __restrict__ rel)
 {
     __shared__ GemmLds L;
     const Task t = tasks[blockIdx.x];
     const BlockDesc d = blk[t.b];
 #define SELINV_CALL(BN)                                                                        \
-    if (BN >= 32 && (d.c & 1) == 0) rs2_task<BN, BN >= 32>(L, t, d, Ap, Zb, Hb, cbase, rbase, rel); \
-    else rs2_task<BN, false>(L, t, d, Ap, Zb, Hb, cbase, rbase, rel)
+    if (BN >= 32 && (d.c & 1) == 0) rs2_task<BN, BN >= 32>(L, t, d, Ap, Zb, Hb, cr2, rel); \
+    else rs2_task<BN, false>(L, t, d, Ap, Zb, Hb, cr2, rel)
     SELINV_BN_DISPATCH(t.bn, SELINV_CALL)
 #undef SELINV_CALL
 }
@@ -1824,15 +1878,14 @@ __global__ void k_tbar_init(const Task* __restrict__ tasks, const BlockDesc* __r
 // Lhat_bar += Ubar F(C,B), Ubar(i,k) = -Fbar(C[i],C[k]) for i >= k
 template <int BN, bool kPair>
 __device__ void rf1a_task(GemmLds& L, const Task t, const BlockDesc d, const double* __restrict__ Zb,
-                          const double* __restrict__ Lp, double* __restrict__ Hb, const int64_t* __restrict__ cbase,
-                          const int64_t* __restrict__ rbase, const int32_t* __restrict__ rel)
+                          const double* __restrict__ Lp, double* __restrict__ Hb, const int64_t* __restrict__ cr2, const int32_t* __restrict__ rel)
 {
     const int s = d.s, c = d.c;
     const int64_t ld = (int64_t)s + c;
     const int r0 = t.i0, n0 = t.j0;
     d4 acc[2][4] = {};
     // Ubar(i,k) = -Fbar(C[i],C[k]) for k <= i, gathered from the adjoint panels; B = F(C,B)
-    gather_mma<BN, kPair, 1>(L, d, r0, n0, t.kb, t.ke, Zb, Lp + d.poff + s, ld, cbase, rbase, rel, acc);
+    gather_mma<BN, kPair, 1>(L, d, r0, n0, t.kb, t.ke, Zb, Lp + d.poff + s, ld, cr2, rel, acc);
     tile_epilogue_t<BN>(acc, [&](int i, int j, double v) {
         const int ii = r0 + i, jj = n0 + j;
         if (ii < c && jj < s) {
@@ -1844,16 +1897,15 @@ __device__ void rf1a_task(GemmLds& L, const Task t, const BlockDesc d, const dou
 
 __global__ __launch_bounds__(kThreads) void k_rf1a(const Task* __restrict__ tasks, const BlockDesc* __restrict__ blk,
                                                    const double* __restrict__ Zb, const double* __restrict__ Lp,
-                                                   double* __restrict__ Hb, const int64_t* __restrict__ cbase,
-                                                   const int64_t* __restrict__ rbase,
+                                                   double* __restrict__ Hb, const int64_t* __restrict__ cr2,
                                                    const int32_t* __restrict__ rel)
 {
     __shared__ GemmLds L;
     const Task t = tasks[blockIdx.x];
     const BlockDesc d = blk[t.b];
 #define SELINV_CALL(BN)                                                                         \
-    if (BN >= 32 && (d.c & 1) == 0) rf1a_task<BN, BN >= 32>(L, t, d, Zb, Lp, Hb, cbase, rbase, rel); \
-    else rf1a_task<BN, false>(L, t, d, Zb, Lp, Hb, cbase, rbase, rel)
+    if (BN >= 32 && (d.c & 1) == 0) rf1a_task<BN, BN >= 32>(L, t, d, Zb, Lp, Hb, cr2, rel); \
+    else rf1a_task<BN, false>(L, t, d, Zb, Lp, Hb, cr2, rel)
     SELINV_BN_DISPATCH(t.bn, SELINV_CALL)
 #undef SELINV_CALL
 }
@@ -1862,7 +1914,7 @@ __global__ __launch_bounds__(kThreads) void k_rf1a(const Task* __restrict__ task
 template <int BN, bool kPair>
 __device__ void rf1b_task(GemmLds& L, const Task t, const BlockDesc d, double* __restrict__ Zb,
                           const double* __restrict__ Hp, const double* __restrict__ Hb, const double* __restrict__ Tp,
-                          const int64_t* __restrict__ cbase, const int64_t* __restrict__ rbase,
+                          const int64_t* __restrict__ cr2,
                           const int32_t* __restrict__ rel)
 {
     const int s = d.s, c = d.c;
@@ -1870,7 +1922,7 @@ __device__ void rf1b_task(GemmLds& L, const Task t, const BlockDesc d, double* _
     const int r0 = t.i0, n0 = t.j0;
     d4 acc[2][4] = {};
     // -Ubar^T L_hat: Fbar(C[k],C[i]) for k >= i, gathered from the adjoint panels
-    gather_mma<BN, kPair, 2>(L, d, r0, n0, t.kb, t.ke, Zb, Hp + d.hoff, c, cbase, rbase, rel, acc);
+    gather_mma<BN, kPair, 2>(L, d, r0, n0, t.kb, t.ke, Zb, Hp + d.hoff, c, cr2, rel, acc);
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
@@ -1898,16 +1950,15 @@ __device__ void rf1b_task(GemmLds& L, const Task t, const BlockDesc d, double* _
 __global__ __launch_bounds__(kThreads) void k_rf1b(const Task* __restrict__ tasks, const BlockDesc* __restrict__ blk,
                                                    double* __restrict__ Zb, const double* __restrict__ Hp,
                                                    const double* __restrict__ Hb, const double* __restrict__ Tp,
-                                                   const int64_t* __restrict__ cbase,
-                                                   const int64_t* __restrict__ rbase,
+                                                   const int64_t* __restrict__ cr2,
                                                    const int32_t* __restrict__ rel)
 {
     __shared__ GemmLds L;
     const Task t = tasks[blockIdx.x];
     const BlockDesc d = blk[t.b];
 #define SELINV_CALL(BN)                                                                             \
-    if (BN >= 32 && (d.c & 1) == 0) rf1b_task<BN, BN >= 32>(L, t, d, Zb, Hp, Hb, Tp, cbase, rbase, rel); \
-    else rf1b_task<BN, false>(L, t, d, Zb, Hp, Hb, Tp, cbase, rbase, rel)
+    if (BN >= 32 && (d.c & 1) == 0) rf1b_task<BN, BN >= 32>(L, t, d, Zb, Hp, Hb, Tp, cr2, rel); \
+    else rf1b_task<BN, false>(L, t, d, Zb, Hp, Hb, Tp, cr2, rel)
     SELINV_BN_DISPATCH(t.bn, SELINV_CALL)
 #undef SELINV_CALL
 }
@@ -2075,7 +2126,7 @@ hipError_t launch_revsel_level(Prof* P, const DevPtrs& D, int64_t a0, int64_t na
     if (na > 0) launch(P, kRevSel, k_rs1, dim3((unsigned)na), 0, s, D.t_rs1 + a0, D.blocks, D.Zb, (const double*)D.Hp);
     if (nb > 0)
         launch(P, kRevSel, k_rs2, dim3((unsigned)nb), 0, s, D.t_rs2 + b0, D.blocks, (const double*)D.Ap,
-               (const double*)D.Zb, D.Hb, D.cbase, D.rbase, D.rel);
+               (const double*)D.Zb, D.Hb, D.cr2, D.rel);
     if (nc > 0)
         launch(P, kRevSel, k_rs3, dim3((unsigned)nc), 0, s, D.t_rs3 + c0, D.blocks, D.Zb, (const double*)D.Hp,
                D.cbase, D.rbase, D.rel);
@@ -2094,10 +2145,10 @@ hipError_t launch_revfac_level(Prof* P, const DevPtrs& D, int64_t a0, int64_t na
 {
     if (na > 0)
         launch(P, kRevFac, k_rf1a, dim3((unsigned)na), 0, s, D.t_rf1a + a0, D.blocks, (const double*)D.Zb,
-               (const double*)D.Lp, D.Hb, D.cbase, D.rbase, D.rel);
+               (const double*)D.Lp, D.Hb, D.cr2, D.rel);
     if (nb > 0)
         launch(P, kRevFac, k_rf1b, dim3((unsigned)nb), 0, s, D.t_rf1b + b0, D.blocks, D.Zb, (const double*)D.Hp,
-               (const double*)D.Hb, (const double*)D.Tp, D.cbase, D.rbase, D.rel);
+               (const double*)D.Hb, (const double*)D.Tp, D.cr2, D.rel);
     if (nc > 0)
         launch(P, kRevFac, k_rf2, dim3((unsigned)nc), 0, s, D.t_rf2 + c0, D.blocks, (const double*)D.Lp,
                (const double*)D.Hb, D.Tb);
@@ -2197,7 +2248,7 @@ hipError_t launch_invert_level(Prof* P, const DevPtrs& D, int64_t gemm0, int64_t
 {
     if (ngemm > 0)
         launch(P, kGemm, k_gemm, dim3((unsigned)ngemm), 0, s, D.t_gemm + gemm0, D.blocks, D.Ap,
-               (const double*)D.Hp, D.cbase, D.rbase, D.rel);
+               (const double*)D.Hp, D.cr2, D.rel);
     if (nsdiag > 0)
         launch(P, kSdiag, k_sdiag64, dim3((unsigned)nsdiag), 0, s, D.t_sdiag + sdiag0, D.blocks, D.Ap,
                (const double*)D.Hp, (const double*)D.Tp);
@@ -2253,7 +2304,7 @@ hipError_t launch_persist_invert(Prof* P, const DevPtrs& D, const Task* q, int64
     const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(grid, ntasks));
 #define SELINV_PI(K)                                                                                              \
     launch(P, kQInvert, K, dim3(g), 0, s, a, D.blocks, D.Ap, (const double*)D.Hp, (const double*)D.Tp, D.cbase, \
-           D.rbase, D.rel)
+           D.rbase, D.rel, D.cr2)
     switch (variant) {
         case kLightInvert: SELINV_PI(k_light_invert); break;
         case kInvert32: SELINV_PI(k_persist_invert<32>); break;

@@ -17,6 +17,7 @@ struct DevPtrs {
     const BlockDesc* blocks;
     const int32_t* crow;
     const int64_t *cbase, *rbase;
+    const int64_t* cr2;  // (cbase, rbase) interleaved, for the gather loops
     const int32_t* rel;
     const int64_t *asm_off, *exp_off;
     const int32_t* colblk;     // column -> execution block

@@ -102,7 +102,7 @@ struct Prof {
 
 struct DeviceLayout {
     // byte offsets into the workspace
-    size_t lp, ap, hp, wp, tp, status, blocks, crow, cbase, rbase, rel, asm_off, exp_off, colblk, colptrL;
+    size_t lp, ap, hp, wp, tp, status, blocks, crow, cbase, rbase, cr2, rel, asm_off, exp_off, colblk, colptrL;
     size_t t_diag, t_ldlt, t_panel, t_schur, t_gemm, t_sdiag, t_zero, t_sb;
     size_t zb, hb, tb;  // adjoint arenas (backward)
     size_t t_rs1, t_rs2, t_rs3, t_rf1a, t_rf1b, t_rf2;
@@ -128,6 +128,7 @@ struct selinv_plan_s {
     std::vector<selinv::BlockDesc> blocks;
     std::vector<int32_t> crow;         // = exec.crows
     std::vector<int64_t> cbase, rbase;
+    std::vector<int64_t> cr2;  // (cbase, rbase) interleaved; kept while an upload may read it
     std::vector<int32_t> rel;
     std::vector<int64_t> asm_off, exp_off;
     std::vector<int32_t> colblk;       // column -> execution block
