@@ -110,8 +110,10 @@ def row_identity(sel, m, colptrL, rowindL, perm):
     return acc - 1.0
 
 
-def row_identity_fast(sel, m, colptrL, rowindL, perm):
-    """Vectorised row identity (large cases)."""
+def row_identity_fast(sel, m, colptrL, rowindL, perm, with_scale=False):
+    """Vectorised row identity (large cases): sum_j A_ij Ainv_ji - 1 per row,
+    and with with_scale also sum_j |A_ij Ainv_ji| (the size of the terms
+    that cancel)."""
     n = m.n
     cols = np.repeat(np.arange(n), np.diff(colptrL)).astype(np.int64)
     rows = np.asarray(rowindL, dtype=np.int64)
@@ -128,4 +130,8 @@ def row_identity_fast(sel, m, colptrL, rowindL, perm):
     vals = np.asarray(sel)[order[pos]]
     acc = np.zeros(n)
     np.add.at(acc, r, v * vals)
+    if with_scale:
+        mag = np.zeros(n)
+        np.add.at(mag, r, np.abs(v * vals))
+        return acc - 1.0, mag
     return acc - 1.0

@@ -163,3 +163,47 @@ def test_lap3d_40_full():
     p, sel, s = _check(m, 128, True)
     r = H.row_identity_fast(sel, m, s.colptrL, s.rowindL, s.perm)
     assert np.max(np.abs(r)) <= 1e-10
+
+
+@pytest.mark.slow
+def test_molecular_full():
+    """Localized-basis matrix, 16^3 jittered atoms x 8 unknowns (n = 32768),
+    full size, in the benchmark's launch configuration: every selected entry
+    and the factor against the oracle."""
+    from paper_1404_0447_amd import workloads as W
+    m = W.make("molecular_16")
+    print(f"molecular full n={m.n}", flush=True)
+    p, sel, s = _check(m, W.CONFIGS["molecular_16"]["cap"], True)
+    r = H.row_identity_fast(sel, m, s.colptrL, s.rowindL, s.perm)
+    assert np.max(np.abs(r)) <= 1e-10
+
+
+@pytest.mark.slow
+def test_lap3d_64_full_properties():
+    """64^3 grid, log-uniform conductivities in [0.1, 10], shift 1e-3, cap 256
+    (n = 262144, 1.6e8 selected entries), in the benchmark's launch
+    configuration.  The oracle would take minutes at this size, so the check
+    uses identities that hold at any size: sum_j A_ij Ainv_ji = 1 on every
+    row (A's pattern lies inside L's), |Ainv_ij| <= sqrt(Ainv_ii Ainv_jj) and
+    Ainv_ii > 0 on every selected entry; and two calls agree to rounding."""
+    torch = _torch()
+    from paper_1404_0447_amd import workloads as W
+    m = W.make("lap3d_64")
+    print(f"lap3d_64 full n={m.n}", flush=True)
+    p, sel, _ = _run(m, W.CONFIGS["lap3d_64"]["cap"], True)
+    cp, ri, pm = p.pattern()
+    d = sel[cp[:-1]]
+    assert np.all(d > 0)
+    cols = np.repeat(np.arange(m.n), np.diff(cp))
+    ratio = np.abs(sel) / np.sqrt(d[ri] * d[cols])
+    assert np.max(ratio) <= 1.0 + 1e-12
+    del ratio, cols
+    # relative to the size of the terms that cancel in each row
+    r, mag = H.row_identity_fast(sel, m, cp, ri, pm, with_scale=True)
+    rel = np.abs(r) / np.maximum(mag, 1.0)
+    assert np.max(rel) <= 1e-12, f"row identity {np.max(rel):.3e}"
+    v = torch.as_tensor(m.vals, dtype=torch.float64, device="cuda")
+    p.factor(v)
+    again = p.invert().cpu().numpy()
+    p.sync_status()
+    assert H.err_c8(again, sel, cp, ri) <= 1e-13
