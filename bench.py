@@ -49,14 +49,26 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def native_sources_sha256():
+    """Hash of the native sources (kernels, schedule, host code): the work of
+    a launch depends on all of them."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_1404_0447_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".cpp", ".hpp")):
+            h.update(name.encode())
+            h.update(open(os.path.join(d, name), "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic(workload, kind):
     """HBM bytes per dispatch of a kernel kind (FETCH_SIZE + WRITE_SIZE, each
     scaled by the same counter's reading for a plain 1 GiB copy), from the
     rocprofv3 summary under profiles/; None when there is none for this
-    workload or the kernel source changed since the counters were taken."""
+    workload or the native sources changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
-    src = os.path.join(ROOT, "paper_1404_0447_amd", "csrc", "kernels.hip")
     if not os.path.exists(path):
         return None
     rec, sha = {}, None
@@ -64,9 +76,9 @@ def measured_traffic(workload, kind):
         f = line.split()
         if len(f) == 5 and f[0] == "traffic":
             rec[f[1]] = float(f[3]) + float(f[4])
-        elif len(f) == 2 and f[0] == "kernels_sha256_16":
+        elif len(f) == 2 and f[0] == "sources_sha256_16":
             sha = f[1]
-    now = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    now = native_sources_sha256()[:16]
     if sha != now or kind not in rec:
         return None
     return round(rec[kind], 1)

@@ -206,7 +206,7 @@ void build_schedule(selinv_plan_s* P)
             const int nd = (d.s + kDiagTile - 1) / kDiagTile;
             rbase_ += tiles;
             rdbase += nd * (nd + 1) / 2;
-            if (is_small(d.s, d.c, kSbS)) {
+            if (is_small_level(d.s, d.c)) {
                 small.push_back(B);
                 continue;
             }
@@ -219,7 +219,7 @@ void build_schedule(selinv_plan_s* P)
         std::vector<TileGroup> gg, dg;
         for (int B : lv[l]) {
             const BlockDesc& d = P->blocks[B];
-            if (is_small(d.s, d.c, kSbS) || d.c == 0) continue;
+            if (is_small_level(d.s, d.c) || d.c == 0) continue;
             const int bn = tile_bn(d.s), nd = (d.s + kDiagTile64 - 1) / kDiagTile64;
             gg.push_back({(int64_t)((d.c + kTileM - 1) / kTileM) * ((d.s + bn - 1) / bn), d.c, bn});
             // one 64 x 64 product per task: nd diagonal tiles, two halves per
@@ -268,7 +268,7 @@ void build_schedule(selinv_plan_s* P)
                 }
             for (int k = 0; k < c; k += kSchurTile)
                 for (int i = k; i < c; i += kSchurTile) P->t_rs3.tasks.push_back({B, i, k, kSchurTile, 0, 2 * s, 0, 0});
-            if (is_small(s, c, kSbS)) continue;
+            if (is_small_level(s, c)) continue;
             // forward, tiled path
             // contractions over C are split into pieces of >= kMinSplitK rows
             // when a level has too few tiles to fill the device
@@ -303,7 +303,7 @@ void build_schedule(selinv_plan_s* P)
         for (int k = 0; k < 3; k++) {
             for (int B : lv[l]) {
                 const BlockDesc& d = P->blocks[B];
-                if (is_small(d.s, d.c, kSbS) || d.s > cls[k] || (k > 0 && d.s <= cls[k - 1])) continue;
+                if (is_small_level(d.s, d.c) || d.s > cls[k] || (k > 0 && d.s <= cls[k - 1])) continue;
                 P->t_ldlt.tasks.push_back({B, 0, 0, 0, 0, 0, 0, 0});
             }
             if (k < 2) P->ldlt_cut[2 * l + k] = (int64_t)P->t_ldlt.tasks.size();
@@ -320,7 +320,7 @@ void build_schedule(selinv_plan_s* P)
                              8.0 * (c * (c + 1) / 2 + 2 * c * s), 8.0 * (2 * c * s + 2 * s * s)};
         // sweep: s pivots x s^2 updates; L_hat = F(C,B) T; lower half of
         // L_hat F^T; X = -G L_hat; Y = T - L_hat^T X
-        if (is_small(d.s, d.c, kSbS)) {
+        if (is_small_level(d.s, d.c)) {
             P->work_flops[kSbFactor] += fl[0] + fl[1] + fl[2];
             P->work_bytes[kSbFactor] += by[0] + by[1] + by[2];
             P->work_flops[kSbInvert] += fl[3] + fl[4];

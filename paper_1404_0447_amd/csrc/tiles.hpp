@@ -19,6 +19,12 @@ constexpr int kSbS = 16;          // widest small block
 constexpr int kSbC = 256;         // largest |C| of a small block
 constexpr int kSbPerTask = 4;     // small blocks per work-group task (one per wave)
 inline bool is_small(int s, int c, int smax) { return s <= smax && c <= kSbC; }
+// per-level path: a wave per block only where |C| is small.  Blocks of 64 <
+// |C| <= 256 sit in few, nearly empty levels near the leaves, where the tiled
+// kernels spread them over many more work-groups (measured: 40^3 step
+// 9.7 -> 9.0 ms)
+constexpr int kSbCLevel = 64;
+inline bool is_small_level(int s, int c) { return s <= kSbS && c <= kSbCLevel; }
 
 constexpr int kFillTiles = 512;  // split the contraction when a level has fewer X tiles
 // resident work-groups of the gather-GEMM and diagonal-tile kernels on the
