@@ -1203,6 +1203,198 @@ __device__ __forceinline__ void ldlt_sweep(const BlockDesc d, double* __restrict
         }
 }
 
+// The same sweep (same thread ownership of M, same arithmetic per entry) for
+// a work-group that has the LDS to itself: every pivot's column is kept,
+// lds[j W + i] = M(i, j) when pivot j is swept (W = 16 NB), and 1 / d_j in
+// invd[j].  Rows below j of that column are the Schur-complement column, so
+// L_BB and D are written from LDS after the sweep (coalesced, no store inside
+// the pivot loop); T then goes through the same LDS, as a (W + 1)-strided
+// square, to be stored column by column.  Per pivot, the entries of the next pivot's column are updated
+// first and published, then, while the reads of that column are in flight,
+// the rest; the two register sets of the pivot column alternate between
+// pivots, so no copies are made.
+// f(integral_constant<int, I>) for I = I0 .. N - 1, each call with its own
+// compile-time index (register arrays indexed by it stay in registers)
+template <int I0, int N>
+struct StaticFor {
+    template <class Fn>
+    __device__ __forceinline__ static void run(Fn&& f)
+    {
+        f(std::integral_constant<int, I0>{});
+        StaticFor<I0 + 1, N>::run(f);
+    }
+};
+template <int N>
+struct StaticFor<N, N> {
+    template <class Fn>
+    __device__ __forceinline__ static void run(Fn&&)
+    {
+    }
+};
+
+template <int NB>
+__device__ __forceinline__ void ldlt_sweep_cols(const BlockDesc d, double* __restrict__ Lp, double* __restrict__ Tp,
+                                                unsigned long long* __restrict__ status, int require_spd,
+                                                double* lds, double* invd)
+{
+    constexpr int NS = NB * (NB + 1) / 2;
+    constexpr int W = 16 * NB;
+    const int s = d.s;
+    const int64_t ld = (int64_t)d.s + d.c;
+    double* F = Lp + d.poff;
+    double* T = Tp + d.woff;
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    auto slot = [](int a, int b) { return a * (a + 1) / 2 + b; };
+    double M[NS];
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int b = 0; b <= a; ++b) {
+            const int i = tx + 16 * a, k = ty + 16 * b;
+            double v = 0.0;
+            if (i < s && k < s) v = i >= k ? F[i + k * ld] : F[k + i * ld];
+            M[slot(a, b)] = v;
+        }
+    if (ty == 0) {
+#pragma unroll
+        for (int a = 0; a < NB; ++a) lds[tx + 16 * a] = M[slot(a, 0)];
+    }
+    __syncthreads();
+    // Column j of the LDS array.  Its offset is made opaque to the compiler:
+    // folded into the instruction it would exceed the 16-bit immediate offset
+    // of LDS instructions past 64 KiB, and every access would need an add.
+    auto col_at = [&](int j) {
+        int o = j * W;
+        asm volatile("" : "+s"(o));
+        return lds + o;
+    };
+    // the pivot column as read (rows tx + 16a, rows ty + 16b, d_j), in two sets
+    double riA[NB], rkA[NB], rdA, riB[NB], rkB[NB], rdB;
+    auto read_col = [&](int j, double (&ri)[NB], double (&rk)[NB], double& rd) {
+        const double* col = col_at(j);
+#pragma unroll
+        for (int a = 0; a < NB; ++a) ri[a] = col[tx + 16 * a];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) rk[b] = col[ty + 16 * b];
+        rd = col[j];
+    };
+    read_col(0, riA, rkA, rdA);
+    int bad = s;  // first pivot that fails the check (thread 0)
+
+    // Pivot j = 16 jb + jt.  `last`: jt = 15 with a next group, whose first
+    // column lies in sub-block column jb + 1.
+    auto pivot = [&](const int jb, const int jt, const bool last, const double (&ri)[NB], const double (&rk)[NB],
+                     const double rd, double (&rin)[NB], double (&rkn)[NB], double& rdn) {
+        const int j = 16 * jb + jt;
+        const double dj = rd;
+        // 1 / d_j: hardware reciprocal and two Newton steps (each squares the
+        // relative error; the first estimate is good to about 2^-26)
+        double inv = __builtin_amdgcn_rcp(dj);
+        inv = fma(inv, fma(-dj, inv, 1.0), inv);
+        inv = fma(inv, fma(-dj, inv, 1.0), inv);
+        if (tid == 0) {
+            const bool ok = isfinite(dj) && dj != 0.0 && (!require_spd || dj > 0.0);
+            if (!ok) bad = min(bad, j);
+            invd[j] = inv;
+        }
+        double ci[NB];
+#pragma unroll
+        for (int a = 0; a < NB; ++a) ci[a] = ri[a] * inv;  // c_i / d_j
+        // M(tx + 16a, ty + 16b) after this pivot (a, b known at compile time)
+        auto upd = [&](int a, int b) {
+            const bool rowj = a == jb && tx == jt, colj = b == jb && ty == jt;
+            const double v = fma(-ci[a], rk[b], M[slot(a, b)]);
+            return rowj ? (colj ? -inv : rk[b] * inv) : (colj ? ci[a] : v);
+        };
+        // the slots that hold the next pivot's column
+        const int nb = last ? jb + 1 : jb;
+        auto in_next = [&](int a, int b) { return (b == nb && a >= nb) || (a == nb && b < nb); };
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+            for (int b = 0; b <= a; ++b)
+                if (in_next(a, b)) M[slot(a, b)] = upd(a, b);
+        const bool more = j + 1 < s;
+        const int nt = last ? 0 : jt + 1;  // the next pivot within sub-block nb
+        if (more) {
+            double* col = col_at(j + 1);
+            if (ty == nt) {
+#pragma unroll
+                for (int a = nb; a < NB; ++a) col[tx + 16 * a] = M[slot(a, nb)];
+            }
+            if (tx == nt) {
+#pragma unroll
+                for (int b = 0; b < nb; ++b) col[ty + 16 * b] = M[slot(nb, b)];
+            }
+        }
+        __syncthreads();
+        if (more) read_col(j + 1, rin, rkn, rdn);
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+            for (int b = 0; b <= a; ++b)
+                if (!in_next(a, b)) {
+                    M[slot(a, b)] = upd(a, b);
+                    // keeps this update inside this pivot, where it hides the
+                    // latency of the column reads (the compiler would sink it
+                    // past the next pivot's barrier)
+                    asm volatile("" : "+v"(M[slot(a, b)]));
+                }
+    };
+    auto copy_BA = [&]() {
+#pragma unroll
+        for (int a = 0; a < NB; ++a) riA[a] = riB[a], rkA[a] = rkB[a];
+        rdA = rdB;
+    };
+    StaticFor<0, NB>::run([&](auto jbc) {
+        constexpr int jb = decltype(jbc)::value;
+        const int jt_end = min(16, s - 16 * jb);
+        const bool handover = jt_end == 16 && 16 * (jb + 1) < s;
+        const int nplain = handover ? 15 : jt_end;
+        int jt = 0;
+        for (; jt + 1 < nplain; jt += 2) {
+            pivot(jb, jt, false, riA, rkA, rdA, riB, rkB, rdB);
+            pivot(jb, jt + 1, false, riB, rkB, rdB, riA, rkA, rdA);
+        }
+        if (jt < nplain) {
+            pivot(jb, jt, false, riA, rkA, rdA, riB, rkB, rdB);
+            copy_BA();
+        }
+        if (handover) {
+            pivot(jb, 15, true, riA, rkA, rdA, riB, rkB, rdB);
+            copy_BA();
+        }
+    });
+    if (tid == 0 && bad < s) atomicMin(status, (unsigned long long)(d.first + bad));
+    __syncthreads();  // invd of the last pivot
+    // L_BB(i, j) = c_i / d_j below the diagonal, D on it
+    constexpr int kCols = kThreads / W;  // columns per pass
+    const int i = tid % W;
+#pragma unroll 4
+    for (int j = tid / W; j < s; j += kCols) {
+        const double v = lds[j * W + i];
+        if (i > j && i < s) F[i + (int64_t)j * ld] = v * invd[j];
+        else if (i == j) F[j + (int64_t)j * ld] = v;
+    }
+    __syncthreads();  // column history read
+    // T = -M, made exactly symmetric from the lower triangle
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int b = 0; b <= a; ++b) {
+            const int r = tx + 16 * a, k = ty + 16 * b;
+            if (r >= k) {
+                lds[r + k * (W + 1)] = -M[slot(a, b)];
+                lds[k + r * (W + 1)] = -M[slot(a, b)];
+            }
+        }
+    __syncthreads();
+    if (i < s) {
+#pragma unroll 4
+        for (int k = tid / W; k < s; k += kCols) T[i + (int64_t)k * s] = lds[i + k * (W + 1)];
+    }
+}
+
 // one launch per width class: NB = 2, 4, 8 for s <= 32, 64, 128; wider
 // blocks take ldlt_global
 template <int NB>
@@ -1211,11 +1403,13 @@ __global__ __launch_bounds__(kThreads) void k_ldlt_diag(const Task* __restrict__
                                                         double* __restrict__ Wp, double* __restrict__ Tp,
                                                         unsigned long long* __restrict__ status, int require_spd)
 {
-    __shared__ __align__(16) double colbuf[2][kLdsDiagMax];
+    static_assert(kThreads % (16 * NB) == 0, "rows of a column split evenly over the work-group");
+    __shared__ __align__(16) double lds[16 * NB * (16 * NB + 1)];
+    __shared__ double invd[16 * NB];
     const Task t = tasks[blockIdx.x];
     const BlockDesc d = blk[t.b];
     if (d.s > 16 * NB) ldlt_global(d, Lp, Wp, Tp, status, require_spd);
-    else ldlt_sweep<NB>(d, Lp, Tp, status, require_spd, colbuf);
+    else ldlt_sweep_cols<NB>(d, Lp, Tp, status, require_spd, lds, invd);
 }
 
 // ===========================================================================
