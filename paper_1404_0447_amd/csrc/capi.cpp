@@ -443,7 +443,7 @@ selinv_status selinv_factor(selinv_plan P, const double* d_valsA, hipStream_t s)
         const auto& cut = P->schur_cuts[l];
         if (!e)
             e = launch_factor_level(&P->prof, D, diag, b[l], b[l + 1] - b[l], cut.data(), (int)cut.size(),
-                                    P->opts.require_spd, s);
+                                    P->panel_deep[l], P->opts.require_spd, s);
         if (e) return hip_fail(e, "factor level launch");
     }
     P->factored = true;

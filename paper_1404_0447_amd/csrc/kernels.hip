@@ -93,11 +93,12 @@ __global__ void k_gather(const double* __restrict__ src, const int64_t* __restri
 // the lower triangle of Ainv(B,B) := T and, when the gather-GEMM is split
 // (zx), X = Ainv(C,B) := 0.  One wave per column, lanes along its rows.
 __device__ __forceinline__ void zero_task(const BlockDesc d, double* __restrict__ Ap, const double* __restrict__ Tp,
-                                          bool zx = true)
+                                          bool zx = true, int j0 = 0, int j1 = 1 << 30)
 {
     const int64_t ld = (int64_t)d.s + d.c;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int j = wave; j < d.s; j += kThreads / 64) {
+    j1 = min(j1, d.s);
+    for (int j = j0 + wave; j < j1; j += kThreads / 64) {
         double* col = Ap + d.poff + (int64_t)j * ld;
         const double* tcol = Tp + d.woff + (int64_t)j * d.s;
         for (int i = j + lane; i < d.s; i += 64) col[i] = tcol[i];
@@ -111,7 +112,7 @@ __global__ __launch_bounds__(kThreads) void k_zero_x(const Task* __restrict__ ta
                                                      const double* __restrict__ Tp)
 {
     const Task t = tasks[blockIdx.x];
-    zero_task(blk[t.b], Ap, Tp, t.flags & 1);
+    zero_task(blk[t.b], Ap, Tp, t.flags & 1, t.kb, t.ke);  // columns [kb, ke)
 }
 
 // L on the canonical pattern: diagonal-block entries are stored; an entry in
@@ -415,6 +416,86 @@ __device__ __forceinline__ void tile_mma2(GemmLds& L, int Kb, int Ke, d4 (&acc)[
     mfma_drain();
 }
 
+// ---------------------------------------------------------------------------
+// The same 64 x BN product for a contraction of at most NCH chunks of 16
+// (NCH <= 8: at most 128), for levels with few tiles, where a tile's time is
+// its latency: every chunk's loads are issued before the first product, so
+// the global-memory latency is paid once instead of once per chunk.  The
+// loads of all NCH chunks are unconditional (past the contraction the
+// address callbacks return an in-bounds stand-in and a false mask), which
+// keeps them in one straight run: with a branch per chunk the wait before
+// the first product would have to cover every path, i.e. all loads.  A read
+// along i, B as in tile_mma2 (kBJ), operands swapped when kT; masks kept as
+// bits.  BN <= 64 (at most 8 values per thread a chunk).
+// ---------------------------------------------------------------------------
+template <int BN, int NCH, bool kBJ, bool kT, class FA, class FB, class FH>
+__device__ __forceinline__ void tile_mma_deep(GemmLds& L, int Kb, int Ke, d4 (&acc)[2][4], FA addrA, FB addrB,
+                                              FH afterPrologue)
+{
+    static_assert(BN <= 64 && NCH <= 8, "at most 8 chunks of 8 values in registers");
+    using SH = TileShape<BN>;
+    constexpr int NB = BN / 16;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm0 = (wave % SH::WM) * (TBM / SH::WM), wn0 = (wave / SH::WM) * (BN / SH::WN);
+    const int nch = Ke > Kb ? (Ke - Kb + TBK - 1) / TBK : 0;
+    double va[NCH][4], vb[NCH][NB];
+    uint32_t oka = 0, okb = 0;  // bit 4 ch + q (A), NB ch + q (B)
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+        const int k0 = Kb + ch * TBK;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = tid + q * kThreads;
+            bool ok;
+            va[ch][q] = *addrA(k0, e >> 6, e & 63, ok);
+            oka |= (uint32_t)ok << (4 * ch + q);
+        }
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const int e = tid + q * kThreads;
+            const int kk = kBJ ? e / BN : (e & 15), j = kBJ ? e % BN : (e >> 4);
+            bool ok;
+            vb[ch][q] = *addrB(k0, kk, j, ok);
+            okb |= (uint32_t)ok << (NB * ch + q);
+        }
+    }
+    afterPrologue();
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+        if (ch >= nch) break;
+        const int buf = ch & 1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = tid + q * kThreads;
+            L.A[buf][e >> 6][e & 63] = (oka >> (4 * ch + q)) & 1 ? va[ch][q] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const int e = tid + q * kThreads;
+            const int kk = kBJ ? e / BN : (e & 15), j = kBJ ? e % BN : (e >> 4);
+            L.B[buf][kk][j] = (okb >> (NB * ch + q)) & 1 ? vb[ch][q] : 0.0;
+        }
+        // chunk ch - 1 was read from the other buffer before every wave
+        // passed the previous barrier; this buffer was last read two chunks ago
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < TBK / 4; ++ks) {
+            const int kr = ks * 4 + (lane >> 4);
+            double a[SH::MT], b[SH::NT];
+#pragma unroll
+            for (int mt = 0; mt < SH::MT; ++mt) a[mt] = L.A[buf][kr][wm0 + mt * 16 + (lane & 15)];
+#pragma unroll
+            for (int nt = 0; nt < SH::NT; ++nt) b[nt] = L.B[buf][kr][wn0 + nt * 16 + (lane & 15)];
+#pragma unroll
+            for (int mt = 0; mt < SH::MT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < SH::NT; ++nt)
+                    acc[mt][nt] = kT ? mfma(b[nt], a[mt], acc[mt][nt]) : mfma(a[mt], b[nt], acc[mt][nt]);
+        }
+    }
+    mfma_drain();
+}
+
 #define SELINV_BN_DISPATCH(bn, CALL) \
     switch (bn) {                    \
         case 16: CALL(16); break;    \
@@ -631,7 +712,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm(const Task* __restrict__ task
 // Factor panel (Algorithm 1 step 2, fused into the factorization):
 // L_hat(C,B) = F(C,B) T for rows [i0, i0+64), columns [j0, j0+BN).
 // ---------------------------------------------------------------------------
-template <int BN>
+template <int BN, bool kDeep = false>
 __device__ __forceinline__ void panel_task(GemmLds& L, const Task t, const BlockDesc d, const double* __restrict__ Lp,
                            double* __restrict__ Hp, const double* __restrict__ Tp)
 {
@@ -651,7 +732,15 @@ __device__ __forceinline__ void panel_task(GemmLds& L, const Task t, const Block
         ok = k < s && jj < s;
         return ok ? T + k + (int64_t)jj * s : T;
     };
-    tile_mma2<BN, false, true>(L, 0, s, acc, addrA, addrB, [](int) { return false; }, [] {});
+    if constexpr (kDeep) {
+        // chunks of 16 the contraction s needs: 1, 2, 4 or 8 (s <= 128)
+        if (s <= 16) tile_mma_deep<BN, 1, false, true>(L, 0, s, acc, addrA, addrB, [] {});
+        else if (s <= 32) tile_mma_deep<BN, 2, false, true>(L, 0, s, acc, addrA, addrB, [] {});
+        else if (s <= 64) tile_mma_deep<BN, 4, false, true>(L, 0, s, acc, addrA, addrB, [] {});
+        else tile_mma_deep<BN, 8, false, true>(L, 0, s, acc, addrA, addrB, [] {});
+    } else {
+        tile_mma2<BN, false, true>(L, 0, s, acc, addrA, addrB, [](int) { return false; }, [] {});
+    }
     tile_epilogue_t<BN>(acc, [&](int i, int j, double v) {
         const int ii = r0 + i, jj = n0 + j;
         if (ii < c && jj < s) Hp[d.hoff + ii + (int64_t)jj * c] = v;
@@ -670,6 +759,23 @@ __global__ __launch_bounds__(kThreads) void k_panel(const Task* __restrict__ tas
 #undef SELINV_CALL
 }
 
+// levels with few panel tiles (width <= 64 each): the contraction (s <= 128)
+// loaded up front
+__global__ __launch_bounds__(kThreads) void k_panel_deep(const Task* __restrict__ tasks,
+                                                         const BlockDesc* __restrict__ blk,
+                                                         const double* __restrict__ Lp, double* __restrict__ Hp,
+                                                         const double* __restrict__ Tp)
+{
+    __shared__ GemmLds L;
+    const Task t = tasks[blockIdx.x];
+    const BlockDesc d = blk[t.b];
+    switch (t.bn) {
+        case 16: panel_task<16, true>(L, t, d, Lp, Hp, Tp); break;
+        case 32: panel_task<32, true>(L, t, d, Lp, Hp, Tp); break;
+        default: panel_task<64, true>(L, t, d, Lp, Hp, Tp); break;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Factor, Schur update: F(C,C) -= L(C,B) D_B L(C,B)^T = L_hat(C,B) F(C,B)^T,
 // lower half, tile rows [i0, i0+64) x columns [k0, k0+64), added into the
@@ -685,6 +791,7 @@ __global__ __launch_bounds__(kThreads) void k_panel(const Task* __restrict__ tas
 // (cbase, rbase) pairs are loaded before the main loop and the rel entries
 // right after its prologue, so the epilogue issues only the updates.
 // ---------------------------------------------------------------------------
+template <bool kDeep = false>
 __device__ __forceinline__ void schur_task(GemmLds& L, const Task t, const BlockDesc d, double* __restrict__ Lp,
                            const double* __restrict__ Hp, const int64_t* __restrict__ cbase,
                            const int64_t* __restrict__ rbase, const int32_t* __restrict__ rel)
@@ -737,7 +844,14 @@ __device__ __forceinline__ void schur_task(GemmLds& L, const Task t, const Block
         ok = i < c && k < s;
         return ok ? H + i + (int64_t)k * c : H;
     };
-    tile_mma2<64, true, false>(L, 0, s, acc, addrA, addrB, [](int) { return false; }, prefetch);
+    if constexpr (kDeep) {
+        if (s <= 16) tile_mma_deep<64, 1, true, false>(L, 0, s, acc, addrA, addrB, prefetch);
+        else if (s <= 32) tile_mma_deep<64, 2, true, false>(L, 0, s, acc, addrA, addrB, prefetch);
+        else if (s <= 64) tile_mma_deep<64, 4, true, false>(L, 0, s, acc, addrA, addrB, prefetch);
+        else tile_mma_deep<64, 8, true, false>(L, 0, s, acc, addrA, addrB, prefetch);
+    } else {
+        tile_mma2<64, true, false>(L, 0, s, acc, addrA, addrB, [](int) { return false; }, prefetch);
+    }
     auto target = [&](int mt, int nt, int v) { return Lp + cb[mt][v] + ro[mt][nt][v]; };
     // a tile strictly below the diagonal and inside C has every entry live:
     // its updates are issued without per-entry branches, which would put a
@@ -804,6 +918,19 @@ __global__ __launch_bounds__(kThreads) void k_schur(const Task* __restrict__ tas
     __shared__ GemmLds L;
     const Task t = tasks[blockIdx.x];
     schur_task(L, t, blk[t.b], Lp, Hp, cbase, rbase, rel);
+}
+
+// colour groups with few tiles: the contraction (s <= 128) loaded up front
+__global__ __launch_bounds__(kThreads) void k_schur_deep(const Task* __restrict__ tasks,
+                                                         const BlockDesc* __restrict__ blk, double* __restrict__ Lp,
+                                                         const double* __restrict__ Hp,
+                                                         const int64_t* __restrict__ cbase,
+                                                         const int64_t* __restrict__ rbase,
+                                                         const int32_t* __restrict__ rel)
+{
+    __shared__ GemmLds L;
+    const Task t = tasks[blockIdx.x];
+    schur_task<true>(L, t, blk[t.b], Lp, Hp, cbase, rbase, rel);
 }
 
 // ---------------------------------------------------------------------------
@@ -1232,6 +1359,16 @@ struct StaticFor<N, N> {
     }
 };
 
+// 1 / d: hardware reciprocal and two Newton steps (each squares the relative
+// error; the first estimate is good to about 2^-26)
+__device__ __forceinline__ double recip(double d)
+{
+    double inv = __builtin_amdgcn_rcp(d);
+    inv = fma(inv, fma(-d, inv, 1.0), inv);
+    inv = fma(inv, fma(-d, inv, 1.0), inv);
+    return inv;
+}
+
 template <int NB>
 __device__ __forceinline__ void ldlt_sweep_cols(const BlockDesc d, double* __restrict__ Lp, double* __restrict__ Tp,
                                                 unsigned long long* __restrict__ status, int require_spd,
@@ -1279,7 +1416,6 @@ __device__ __forceinline__ void ldlt_sweep_cols(const BlockDesc d, double* __res
         rd = col[j];
     };
     read_col(0, riA, rkA, rdA);
-    int bad = s;  // first pivot that fails the check (thread 0)
 
     // Pivot j = 16 jb + jt.  `last`: jt = 15 with a next group, whose first
     // column lies in sub-block column jb + 1.
@@ -1287,33 +1423,35 @@ __device__ __forceinline__ void ldlt_sweep_cols(const BlockDesc d, double* __res
                      const double rd, double (&rin)[NB], double (&rkn)[NB], double& rdn) {
         const int j = 16 * jb + jt;
         const double dj = rd;
-        // 1 / d_j: hardware reciprocal and two Newton steps (each squares the
-        // relative error; the first estimate is good to about 2^-26)
-        double inv = __builtin_amdgcn_rcp(dj);
-        inv = fma(inv, fma(-dj, inv, 1.0), inv);
-        inv = fma(inv, fma(-dj, inv, 1.0), inv);
-        if (tid == 0) {
-            const bool ok = isfinite(dj) && dj != 0.0 && (!require_spd || dj > 0.0);
-            if (!ok) bad = min(bad, j);
-            invd[j] = inv;
-        }
+        const double inv = recip(dj);
         double ci[NB];
 #pragma unroll
         for (int a = 0; a < NB; ++a) ci[a] = ri[a] * inv;  // c_i / d_j
-        // M(tx + 16a, ty + 16b) after this pivot (a, b known at compile time)
-        auto upd = [&](int a, int b) {
-            const bool rowj = a == jb && tx == jt, colj = b == jb && ty == jt;
-            const double v = fma(-ci[a], rk[b], M[slot(a, b)]);
-            return rowj ? (colj ? -inv : rk[b] * inv) : (colj ? ci[a] : v);
-        };
         // the slots that hold the next pivot's column
         const int nb = last ? jb + 1 : jb;
         auto in_next = [&](int a, int b) { return (b == nb && a >= nb) || (a == nb && b < nb); };
+        // M(i, k) -= c_i c_k / d_j for every slot of one phase, then row and
+        // column j overwritten by the lanes that hold them (a, b known at
+        // compile time; jb too, so only the slots of sub-block row / column
+        // jb take part)
+        auto update = [&](bool first) {
 #pragma unroll
-        for (int a = 0; a < NB; ++a)
+            for (int a = 0; a < NB; ++a)
 #pragma unroll
-            for (int b = 0; b <= a; ++b)
-                if (in_next(a, b)) M[slot(a, b)] = upd(a, b);
+                for (int b = 0; b <= a; ++b)
+                    if (in_next(a, b) == first) M[slot(a, b)] = fma(-ci[a], rk[b], M[slot(a, b)]);
+            if (ty == jt) {  // column j: c_i / d_j, and -1 / d_j on the diagonal
+#pragma unroll
+                for (int a = jb; a < NB; ++a)
+                    if (in_next(a, jb) == first) M[slot(a, jb)] = (a == jb && tx == jt) ? -inv : ci[a];
+            }
+            if (tx == jt) {  // row j
+#pragma unroll
+                for (int b = 0; b <= jb; ++b)
+                    if (in_next(jb, b) == first) M[slot(jb, b)] = (b == jb && ty == jt) ? -inv : rk[b] * inv;
+            }
+        };
+        update(true);
         const bool more = j + 1 < s;
         const int nt = last ? 0 : jt + 1;  // the next pivot within sub-block nb
         if (more) {
@@ -1329,17 +1467,15 @@ __device__ __forceinline__ void ldlt_sweep_cols(const BlockDesc d, double* __res
         }
         __syncthreads();
         if (more) read_col(j + 1, rin, rkn, rdn);
+        update(false);
+        // keeps this pivot's updates inside it, where they hide the latency
+        // of the column reads (the compiler would sink them past the next
+        // pivot's barrier)
 #pragma unroll
         for (int a = 0; a < NB; ++a)
 #pragma unroll
             for (int b = 0; b <= a; ++b)
-                if (!in_next(a, b)) {
-                    M[slot(a, b)] = upd(a, b);
-                    // keeps this update inside this pivot, where it hides the
-                    // latency of the column reads (the compiler would sink it
-                    // past the next pivot's barrier)
-                    asm volatile("" : "+v"(M[slot(a, b)]));
-                }
+                if (!in_next(a, b)) asm volatile("" : "+v"(M[slot(a, b)]));
     };
     auto copy_BA = [&]() {
 #pragma unroll
@@ -1365,16 +1501,33 @@ __device__ __forceinline__ void ldlt_sweep_cols(const BlockDesc d, double* __res
             copy_BA();
         }
     });
-    if (tid == 0 && bad < s) atomicMin(status, (unsigned long long)(d.first + bad));
-    __syncthreads();  // invd of the last pivot
-    // L_BB(i, j) = c_i / d_j below the diagonal, D on it
+    // d_j is column j's diagonal entry: the pivot check (the first failing
+    // pivot wins the atomic minimum) and 1 / d_j as the sweep formed it
+    if (tid < s) {
+        const double dj = lds[tid * W + tid];
+        const bool ok = isfinite(dj) && dj != 0.0 && (!require_spd || dj > 0.0);
+        if (!ok) atomicMin(status, (unsigned long long)(d.first + tid));
+        invd[tid] = recip(dj);
+    }
+    __syncthreads();
+    // L_BB(i, j) = c_i / d_j below the diagonal, D on it; eight columns per
+    // thread at a time, their LDS reads issued together
     constexpr int kCols = kThreads / W;  // columns per pass
+    constexpr int kU = 8;
     const int i = tid % W;
-#pragma unroll 4
-    for (int j = tid / W; j < s; j += kCols) {
-        const double v = lds[j * W + i];
-        if (i > j && i < s) F[i + (int64_t)j * ld] = v * invd[j];
-        else if (i == j) F[j + (int64_t)j * ld] = v;
+    for (int j0 = tid / W; j0 < s; j0 += kCols * kU) {
+        double v[kU], r[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int j = min(j0 + u * kCols, W - 1);
+            v[u] = lds[j * W + i];
+            r[u] = invd[j];
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int j = j0 + u * kCols;
+            if (j < s && i >= j && i < s) F[i + (int64_t)j * ld] = i == j ? v[u] : v[u] * r[u];
+        }
     }
     __syncthreads();  // column history read
     // T = -M, made exactly symmetric from the lower triangle
@@ -1389,9 +1542,15 @@ __device__ __forceinline__ void ldlt_sweep_cols(const BlockDesc d, double* __res
             }
         }
     __syncthreads();
-    if (i < s) {
-#pragma unroll 4
-        for (int k = tid / W; k < s; k += kCols) T[i + (int64_t)k * s] = lds[i + k * (W + 1)];
+    for (int k0 = tid / W; k0 < s; k0 += kCols * kU) {
+        double v[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) v[u] = lds[i + min(k0 + u * kCols, W - 1) * (W + 1)];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int k = k0 + u * kCols;
+            if (k < s && i < s) T[i + (int64_t)k * s] = v[u];
+        }
     }
 }
 
@@ -2413,7 +2572,7 @@ hipError_t launch_sb_invert(Prof* P, const DevPtrs& D, int64_t sb0, int64_t nsb,
 }
 
 hipError_t launch_factor_level(Prof* P, const DevPtrs& D, const int64_t diag[4], int64_t panel0, int64_t npanel,
-                               const int64_t* schur_cuts, int ncuts, int require_spd, hipStream_t s)
+                               const int64_t* schur_cuts, int ncuts, int panel_deep, int require_spd, hipStream_t s)
 {
     // diagonal blocks by width class: [diag[0], diag[1]) s <= 32, then <= 64,
     // then wider
@@ -2427,13 +2586,15 @@ hipError_t launch_factor_level(Prof* P, const DevPtrs& D, const int64_t diag[4],
         launch(P, kLdlt, k_ldlt_diag<8>, dim3((unsigned)(diag[3] - diag[2])), 0, s, D.t_ldlt + diag[2], D.blocks,
                D.Lp, D.Wp, D.Tp, D.status, require_spd);
     if (npanel > 0)
-        launch(P, kPanel, k_panel, dim3((unsigned)npanel), 0, s, D.t_panel + panel0, D.blocks,
-               (const double*)D.Lp, D.Hp, (const double*)D.Tp);
+        launch(P, kPanel, panel_deep ? k_panel_deep : k_panel, dim3((unsigned)npanel), 0, s, D.t_panel + panel0,
+               D.blocks, (const double*)D.Lp, D.Hp, (const double*)D.Tp);
     // one launch per colour group (groups update disjoint entries)
-    for (int g = 0; g + 1 < ncuts; g++)
-        if (schur_cuts[g + 1] > schur_cuts[g])
-            launch(P, kSchur, k_schur, dim3((unsigned)(schur_cuts[g + 1] - schur_cuts[g])), 0, s,
+    for (int g = 0; g + 1 < ncuts; g++) {
+        const int64_t n = schur_cuts[g + 1] - schur_cuts[g];
+        if (n > 0)
+            launch(P, kSchur, n <= kDeepMaxTiles ? k_schur_deep : k_schur, dim3((unsigned)n), 0, s,
                    D.t_schur + schur_cuts[g], D.blocks, D.Lp, (const double*)D.Hp, D.cbase, D.rbase, D.rel);
+    }
     return hipGetLastError();
 }
 

@@ -44,7 +44,7 @@ hipError_t launch_gather(Prof* P, int kind, const double* src, const int64_t* of
                          hipStream_t s);
 // diag[0..3]: the level's diagonal-block tasks for s <= 32, <= 64 and wider
 hipError_t launch_factor_level(Prof* P, const DevPtrs& D, const int64_t diag[4], int64_t panel0, int64_t npanel,
-                               const int64_t* schur_cuts, int ncuts, int require_spd, hipStream_t s);
+                               const int64_t* schur_cuts, int ncuts, int panel_deep, int require_spd, hipStream_t s);
 hipError_t launch_invert_level(Prof* P, const DevPtrs& D, int64_t gemm0, int64_t ngemm, int64_t sdiag0,
                                int64_t nsdiag, hipStream_t s);
 // persistent work-queue kernels: resident work-groups per CU, and one

@@ -191,6 +191,7 @@ void build_schedule(selinv_plan_s* P)
     P->t_zero.clear();
     P->ldlt_cut.assign(2 * D, 0);
     P->schur_cuts.assign(D, {});
+    P->panel_deep.assign(D, 0);
     std::vector<uint64_t> colour_mask((size_t)P->n, 0);
     std::vector<int32_t> touch((size_t)P->n, 0);
     std::vector<char> excl(P->blocks.size(), 0);
@@ -233,9 +234,20 @@ void build_schedule(selinv_plan_s* P)
         const int64_t rwant = fill_for(rbase_), rdwant = fill_for(rdbase);
         (void)base;
         (void)dbase;
+        // few panel tiles: at most 64 wide each, for the whole-contraction kernel
+        int64_t npanel64 = 0;
+        for (int B : lv[l]) {
+            const BlockDesc& d = P->blocks[B];
+            if (is_small_level(d.s, d.c)) continue;
+            const int pbn = std::min(tile_bn(d.s), 64);
+            npanel64 += (int64_t)((d.c + kTileM - 1) / kTileM) * ((d.s + pbn - 1) / pbn);
+        }
+        const bool deep = npanel64 <= kDeepMaxTiles;
+        P->panel_deep[l] = deep;
         for (int B : lv[l]) {
             const BlockDesc& d = P->blocks[B];
             const int bn = tile_bn(d.s);
+            const int pbn = deep ? std::min(bn, 64) : bn;
             const int s = d.s, c = d.c;
             P->t_diag.tasks.push_back({B, 0, 0, 0, 0, 0, 0, 0});
             // reverse sweep: every block, tiled
@@ -278,7 +290,11 @@ void build_schedule(selinv_plan_s* P)
             // Ainv(B,B) accumulates (from T) when a contraction is split or
             // the block has off-diagonal tiles; X only when the GEMM is split
             const bool acc = dsplit > 1 || nd64 > 1;
-            if (split > 1 || acc) P->t_zero.push_back({B, 0, 0, 0, 0, 0, split > 1, 0});
+            // a task per kZeroCols columns: one work-group per block would
+            // serialise the largest blocks' (s + c) x s columns
+            if (split > 1 || acc)
+                for (int j = 0; j < s; j += kZeroCols)
+                    P->t_zero.push_back({B, 0, 0, 0, j, std::min(s, j + kZeroCols), split > 1, 0});
             for (int I = 0; I < nd64; I++)
                 for (int J = 0; J <= I; J++)
                     for (int half = 0; half < (I == J ? 1 : 2); half++)
@@ -286,9 +302,10 @@ void build_schedule(selinv_plan_s* P)
                             P->t_sdiag.tasks.push_back(
                                 {B, I * kDiagTile64, J * kDiagTile64, 0, kb, ke, (int)acc | (half << 3), 0});
                         });
+            for (int j = 0; j < s; j += pbn)
+                for (int r = 0; r < c; r += kTileM) P->t_panel.tasks.push_back({B, r, j, pbn, 0, s, 0, 0});
             for (int j = 0; j < s; j += bn)
                 for (int r = 0; r < c; r += kTileM) {
-                    P->t_panel.tasks.push_back({B, r, j, bn, 0, s, 0, 0});
                     pieces(0, c, split, [&](int kb, int ke, int) {
                         P->t_gemm.tasks.push_back({B, r, j, bn, kb, ke, split > 1, 0});
                     });

@@ -24,6 +24,12 @@ inline bool is_small(int s, int c, int smax) { return s <= smax && c <= kSbC; }
 // kernels spread them over many more work-groups (measured: 40^3 step
 // 9.7 -> 9.0 ms)
 constexpr int kSbCLevel = 64;
+// A level with at most this many panel tiles (a Schur colour group with at
+// most this many tiles) loads each tile's whole contraction (s <= 128) before
+// its first product: there the tiles' latency, not the device's throughput,
+// sets the level time.
+constexpr int kDeepMaxTiles = 256;
+constexpr int kZeroCols = 8;  // columns of Ainv(:, B) a task of the set-up kernel clears
 inline bool is_small_level(int s, int c) { return s <= kSbS && c <= kSbCLevel; }
 
 constexpr int kFillTiles = 512;  // split the contraction when a level has fewer X tiles
