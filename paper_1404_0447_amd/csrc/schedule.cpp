@@ -131,6 +131,14 @@ static void schur_colours(const selinv_plan_s* P, std::vector<Task>& tasks, int6
         const BlockDesc& d = P->blocks[B];
         for (int r = 0; r < d.c; r++) mask[cr[d.coff + r]] = 0;
     }
+    // more colours than kMaxSchurColours: one launch, FP64 atomics (blocks
+    // found exclusive keep read-modify-write)
+    int ncol = 0;
+    for (const auto& kv : col) ncol = std::max(ncol, kv.second + 1);
+    if (ncol > kMaxSchurColours) {
+        cuts.assign({t0, (int64_t)tasks.size()});
+        return;
+    }
     std::stable_sort(tasks.begin() + t0, tasks.end(), [&](const Task& a, const Task& b) { return col[a.b] < col[b.b]; });
     cuts.assign(1, t0);
     for (int64_t t = t0; t < (int64_t)tasks.size(); t++) {
