@@ -432,7 +432,7 @@ template <int BN, int NCH, bool kBJ, bool kT, class FA, class FB, class FH>
 __device__ __forceinline__ void tile_mma_deep(GemmLds& L, int Kb, int Ke, d4 (&acc)[2][4], FA addrA, FB addrB,
                                               FH afterPrologue)
 {
-    static_assert(BN <= 64 && NCH <= 8, "at most 8 chunks of 8 values in registers");
+    static_assert(BN <= 64 && NCH * TBK <= kDeepK, "at most 8 chunks of 8 values in registers");
     using SH = TileShape<BN>;
     constexpr int NB = BN / 16;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -737,7 +737,8 @@ __device__ __forceinline__ void panel_task(GemmLds& L, const Task t, const Block
         if (s <= 16) tile_mma_deep<BN, 1, false, true>(L, 0, s, acc, addrA, addrB, [] {});
         else if (s <= 32) tile_mma_deep<BN, 2, false, true>(L, 0, s, acc, addrA, addrB, [] {});
         else if (s <= 64) tile_mma_deep<BN, 4, false, true>(L, 0, s, acc, addrA, addrB, [] {});
-        else tile_mma_deep<BN, 8, false, true>(L, 0, s, acc, addrA, addrB, [] {});
+        else if (s <= kDeepK) tile_mma_deep<BN, 8, false, true>(L, 0, s, acc, addrA, addrB, [] {});
+        else tile_mma2<BN, false, true>(L, 0, s, acc, addrA, addrB, [](int) { return false; }, [] {});
     } else {
         tile_mma2<BN, false, true>(L, 0, s, acc, addrA, addrB, [](int) { return false; }, [] {});
     }
@@ -848,7 +849,8 @@ __device__ __forceinline__ void schur_task(GemmLds& L, const Task t, const Block
         if (s <= 16) tile_mma_deep<64, 1, true, false>(L, 0, s, acc, addrA, addrB, prefetch);
         else if (s <= 32) tile_mma_deep<64, 2, true, false>(L, 0, s, acc, addrA, addrB, prefetch);
         else if (s <= 64) tile_mma_deep<64, 4, true, false>(L, 0, s, acc, addrA, addrB, prefetch);
-        else tile_mma_deep<64, 8, true, false>(L, 0, s, acc, addrA, addrB, prefetch);
+        else if (s <= kDeepK) tile_mma_deep<64, 8, true, false>(L, 0, s, acc, addrA, addrB, prefetch);
+        else tile_mma2<64, true, false>(L, 0, s, acc, addrA, addrB, [](int) { return false; }, prefetch);
     } else {
         tile_mma2<64, true, false>(L, 0, s, acc, addrA, addrB, [](int) { return false; }, prefetch);
     }
@@ -2585,14 +2587,16 @@ hipError_t launch_factor_level(Prof* P, const DevPtrs& D, const int64_t diag[4],
     if (diag[3] > diag[2])
         launch(P, kLdlt, k_ldlt_diag<8>, dim3((unsigned)(diag[3] - diag[2])), 0, s, D.t_ldlt + diag[2], D.blocks,
                D.Lp, D.Wp, D.Tp, D.status, require_spd);
+    // panel_deep: bit 0 the level's panel tiles take the whole-contraction
+    // kernel; bit 1 its blocks are narrow enough for it (s <= kDeepK)
     if (npanel > 0)
-        launch(P, kPanel, panel_deep ? k_panel_deep : k_panel, dim3((unsigned)npanel), 0, s, D.t_panel + panel0,
-               D.blocks, (const double*)D.Lp, D.Hp, (const double*)D.Tp);
+        launch(P, kPanel, (panel_deep & 1) ? k_panel_deep : k_panel, dim3((unsigned)npanel), 0, s,
+               D.t_panel + panel0, D.blocks, (const double*)D.Lp, D.Hp, (const double*)D.Tp);
     // one launch per colour group (groups update disjoint entries)
     for (int g = 0; g + 1 < ncuts; g++) {
         const int64_t n = schur_cuts[g + 1] - schur_cuts[g];
         if (n > 0)
-            launch(P, kSchur, n <= kDeepMaxTiles ? k_schur_deep : k_schur, dim3((unsigned)n), 0, s,
+            launch(P, kSchur, (panel_deep & 2) && n <= kDeepMaxTiles ? k_schur_deep : k_schur, dim3((unsigned)n), 0, s,
                    D.t_schur + schur_cuts[g], D.blocks, D.Lp, (const double*)D.Hp, D.cbase, D.rbase, D.rel);
     }
     return hipGetLastError();

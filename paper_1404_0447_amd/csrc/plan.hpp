@@ -140,7 +140,10 @@ struct selinv_plan_s {
     std::vector<int64_t> ldlt_cut;     // per level: t_ldlt splits into s <= 32 | <= 64 | wider at 2l, 2l+1
     // per level: t_schur in colour groups [cut[g], cut[g+1]) whose blocks share no column of C
     std::vector<std::vector<int64_t>> schur_cuts;
-    std::vector<char> panel_deep;  // per level: panel tiles <= 64 wide and at most kDeepMaxTiles of them
+    // per level: bit 0, panel tiles <= 64 wide and at most kDeepMaxTiles of
+    // them (whole-contraction panel kernel); bit 1, every block of the level
+    // at most kDeepK wide (whole-contraction kernels allowed at all)
+    std::vector<char> panel_deep;
     // reverse sweep: selected inversion (leaves first) and factorization (root first)
     selinv::LevelTasks t_rs1, t_rs2, t_rs3, t_rf1a, t_rf1b, t_rf2;
     std::vector<selinv::Task> t_zero;  // column ranges [kb, ke) of blocks whose X or Ainv(B,B) accumulates

@@ -244,14 +244,19 @@ void build_schedule(selinv_plan_s* P)
         (void)dbase;
         // few panel tiles: at most 64 wide each, for the whole-contraction kernel
         int64_t npanel64 = 0;
+        int smax = 0;
         for (int B : lv[l]) {
             const BlockDesc& d = P->blocks[B];
             if (is_small_level(d.s, d.c)) continue;
             const int pbn = std::min(tile_bn(d.s), 64);
             npanel64 += (int64_t)((d.c + kTileM - 1) / kTileM) * ((d.s + pbn - 1) / pbn);
+            smax = std::max(smax, d.s);
         }
-        const bool deep = npanel64 <= kDeepMaxTiles;
-        P->panel_deep[l] = deep;
+        // the whole-contraction kernels hold a contraction of at most kDeepK
+        // (blocks wider than 128 columns exist only with exec_cap > 128)
+        const bool deep_ok = smax <= kDeepK;
+        const bool deep = deep_ok && npanel64 <= kDeepMaxTiles;
+        P->panel_deep[l] = (char)((deep ? 1 : 0) | (deep_ok ? 2 : 0));
         for (int B : lv[l]) {
             const BlockDesc& d = P->blocks[B];
             const int bn = tile_bn(d.s);

@@ -29,6 +29,7 @@ constexpr int kSbCLevel = 64;
 // its first product: there the tiles' latency, not the device's throughput,
 // sets the level time.
 constexpr int kDeepMaxTiles = 256;
+constexpr int kDeepK = 128;  // longest contraction of the whole-contraction kernels
 constexpr int kZeroCols = 8;  // columns of Ainv(:, B) a task of the set-up kernel clears
 // A level's Schur update runs in colour groups (read-modify-write, one launch
 // each) only when its blocks need at most this many colours; more launches

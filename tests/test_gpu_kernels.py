@@ -89,3 +89,13 @@ def test_block_kernels_random_pattern():
     from paper_1404_0447_amd import workloads as W
     m = W.random_spd_pattern(160, 0.06, 9)
     _check_blocks(m, 40, True)
+
+
+def test_block_kernels_wide_blocks():
+    """Execution blocks up to 256 columns (exec_cap 256): blocks wider than
+    128 with a nonempty C sit on levels with few tiles, where the panel and
+    Schur kernels that load the whole contraction up front must not take
+    them (their contraction holds at most 128)."""
+    from paper_1404_0447_amd import workloads as W
+    m = W.laplacian((20, 20, 20), coeff="loguniform", lo=0.1, hi=10.0, shift=1e-3, seed=5)
+    _check_blocks(m, 256, True, exec_cap=256)

@@ -90,7 +90,8 @@ def test_random_patterns(seed, cap):
 
 @pytest.mark.parametrize("dims,cap,exec_cap", [((12, 11, 10), 16, 0), ((16, 16, 16), 128, 0),
                                                ((16, 16, 16), 64, 256), ((48, 40), 32, 0),
-                                               ((16, 16, 16), 256, 32), ((20, 20, 20), 256, 0)])
+                                               ((16, 16, 16), 256, 32), ((20, 20, 20), 256, 0),
+                                               ((20, 20, 20), 256, 256)])
 def test_grids_variable_coefficients(dims, cap, exec_cap):
     from paper_1404_0447_amd import workloads as W
     m = W.laplacian(dims, coeff="loguniform", lo=0.1, hi=10.0, shift=1e-3, seed=5)
