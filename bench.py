@@ -174,6 +174,17 @@ def main():
     prof = plan.profile_read()
     plan.sync_status()
     log(f"[bench] profiled {args.steps} steps: {ms_step_prof:.3f} ms/step")
+    # the same K steps once more, an event pair around each: the spread
+    # of single steps (mean, std, median)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    for a, b in evs:
+        a.record(stream)
+        step()
+        b.record(stream)
+    torch.cuda.synchronize()
+    plan.sync_status()
+    per_step = np.array([a.elapsed_time(b) for a, b in evs])
 
     work = plan.kernel_work()
     flops_step = info["flops_factor"] + info["flops_selinv"]
@@ -201,10 +212,12 @@ def main():
     roof.update({"kernel": dom, "avg_launch_ms": round(per_launch[dom], 5),
                  "launches_per_step": launches_per_step[dom],
                  "algorithmic_per_step": work[dom][0] if roof["unit"] == "TFLOP/s" else work[dom][1]})
-    gemm_phase_ms = kern_ms["gemm"] + kern_ms["sdiag"]
+    # GEMM phase (steps 3-4 of the selected inversion): the tiled kernels and
+    # the small-block kernel that runs both steps for blocks with s <= 16
+    gemm_phase_ms = kern_ms["gemm"] + kern_ms["sdiag"] + kern_ms["sbinvert"]
     gemm_phase_tf = info["flops_gemm"] / (gemm_phase_ms * 1e-3) / 1e12 if gemm_phase_ms > 0 else 0.0
     invert_ms = gemm_phase_ms + kern_ms["export"]
-    factor_ms = sum(kern_ms[k] for k in ("assemble", "ldlt", "panel", "schur"))
+    factor_ms = sum(kern_ms[k] for k in ("assemble", "ldlt", "panel", "schur", "sbfactor"))
 
     result = {
         "metric": METRIC, "value": round(value, 3), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
@@ -221,6 +234,10 @@ def main():
                       **{k: round(v, 4) for k, v in kern_ms.items()}},
         "gemm_phase": {"tflops": round(gemm_phase_tf, 4), "frac_of_fp64_peak": round(gemm_phase_tf / PEAK_FP64_TFLOPS, 4),
                        "flops": info["flops_gemm"], "ms": round(gemm_phase_ms, 4)},
+        "factor_gflops": round(info["flops_factor"] / (factor_ms * 1e-3) / 1e9, 2) if factor_ms > 0 else None,
+        "invert_gflops": round(info["flops_selinv"] / (invert_ms * 1e-3) / 1e9, 2) if invert_ms > 0 else None,
+        "step_ms": {"mean": round(float(per_step.mean()), 4), "std": round(float(per_step.std()), 4),
+                    "median": round(float(np.median(per_step)), 4), "runs": int(per_step.size)},
         "cpu_baseline": None,
     }
 
@@ -243,8 +260,10 @@ def main():
         d = ref[cp[:-1]]
         cols = np.repeat(np.arange(m.n), np.diff(cp))
         err = float(np.max(np.abs(got - ref) / np.sqrt(np.abs(d[ri] * d[cols]))))
+        cpu_model = next((ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo")
+                          if ln.startswith("model name")), "unknown")
         result["cpu_baseline"] = {"value": round(cpu_gflops, 3), "unit": "GFLOP/s", "cores": O.threads(),
-                                  "kind": "oracle",
+                                  "kind": "oracle", "cpu_model": cpu_model, "nproc": os.cpu_count(),
                                   "sample": f"full {args.workload} matrix, factor + selected inversion "
                                             f"(excl. symbolic), {tf + ts:.2f}s",
                                   "speedup_gpu_over_cpu": round(value / cpu_gflops, 2)}
