@@ -42,7 +42,8 @@ constexpr int kFillTiles = 512;  // split the contraction when a level has fewer
 // target (256 CUs x 2); the per-level split is sized for them
 constexpr long kGemmSlots = 512;
 // fixed cost of one work-group of the split contractions, in 16-deep chunks
-constexpr double kGemmTaskOvh = 12.0;
+// (swept over 3..12 at 64^3: 6 fastest)
+constexpr double kGemmTaskOvh = 6.0;
 constexpr double kSdiagTaskOvh = 8.0;  // smaller epilogue (half a 64 x 64 tile)
 constexpr int kMinSplitK = 128;  // rows of C per split piece, at least
 constexpr int kMinSplitKDiag = 64;  // the same for the diagonal tile pairs
