@@ -19,11 +19,11 @@ constexpr int kSbS = 16;          // widest small block
 constexpr int kSbC = 256;         // largest |C| of a small block
 constexpr int kSbPerTask = 4;     // small blocks per work-group task (one per wave)
 inline bool is_small(int s, int c, int smax) { return s <= smax && c <= kSbC; }
-// per-level path: a wave per block only where |C| is small.  Blocks of 64 <
-// |C| <= 256 sit in few, nearly empty levels near the leaves, where the tiled
-// kernels spread them over many more work-groups (measured: 40^3 step
-// 9.7 -> 9.0 ms)
-constexpr int kSbCLevel = 64;
+// per-level path: a wave per block only where |C| is small.  Blocks with a
+// larger |C| sit in few, nearly empty levels near the leaves, where the tiled
+// kernels spread them over many more work-groups (swept over 0..256: 32
+// fastest at 40^3, 64^3 and molecular 16^3)
+constexpr int kSbCLevel = 32;
 // A level with at most this many panel tiles (a Schur colour group with at
 // most this many tiles) loads each tile's whole contraction (s <= 128) before
 // its first product: there the tiles' latency, not the device's throughput,
