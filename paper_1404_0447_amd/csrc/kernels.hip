@@ -1332,16 +1332,6 @@ __device__ __forceinline__ void ldlt_sweep(const BlockDesc d, double* __restrict
         }
 }
 
-// The same sweep (same thread ownership of M, same arithmetic per entry) for
-// a work-group that has the LDS to itself: every pivot's column is kept,
-// lds[j W + i] = M(i, j) when pivot j is swept (W = 16 NB), and 1 / d_j in
-// invd[j].  Rows below j of that column are the Schur-complement column, so
-// L_BB and D are written from LDS after the sweep (coalesced, no store inside
-// the pivot loop); T then goes through the same LDS, as a (W + 1)-strided
-// square, to be stored column by column.  Per pivot, the entries of the next pivot's column are updated
-// first and published, then, while the reads of that column are in flight,
-// the rest; the two register sets of the pivot column alternate between
-// pivots, so no copies are made.
 // f(integral_constant<int, I>) for I = I0 .. N - 1, each call with its own
 // compile-time index (register arrays indexed by it stay in registers)
 template <int I0, int N>
@@ -1371,6 +1361,16 @@ __device__ __forceinline__ double recip(double d)
     return inv;
 }
 
+// The same sweep (same thread ownership of M, same arithmetic per entry) for
+// a work-group that has the LDS to itself: every pivot's column is kept,
+// lds[j W + i] = M(i, j) when pivot j is swept (W = 16 NB), and 1 / d_j in
+// invd[j].  Rows below j of that column are the Schur-complement column, so
+// L_BB and D are written from LDS after the sweep (coalesced, no store inside
+// the pivot loop); T then goes through the same LDS, as a (W + 1)-strided
+// square, to be stored column by column.  Per pivot, the entries of the next
+// pivot's column are updated first and published, then, while the reads of
+// that column are in flight, the rest; the two register sets of the pivot
+// column alternate between pivots, so no copies are made.
 template <int NB>
 __device__ __forceinline__ void ldlt_sweep_cols(const BlockDesc d, double* __restrict__ Lp, double* __restrict__ Tp,
                                                 unsigned long long* __restrict__ status, int require_spd,
