@@ -37,7 +37,9 @@ constexpr int kZeroCols = 8;  // columns of Ainv(:, B) a task of the set-up kern
 constexpr int kMaxSchurColours = 3;
 inline bool is_small_level(int s, int c) { return s <= kSbS && c <= kSbCLevel; }
 
-constexpr int kFillTiles = 512;  // split the contraction when a level has fewer X tiles
+// reverse sweep: split the contraction when a level has fewer tiles than this
+// (swept over 256..2048: 1024 fastest at 64^3 and molecular 16^3)
+constexpr int kFillTiles = 1024;
 // resident work-groups of the gather-GEMM and diagonal-tile kernels on the
 // target (256 CUs x 2); the per-level split is sized for them
 constexpr long kGemmSlots = 512;
