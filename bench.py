@@ -234,6 +234,12 @@ def main():
                       **{k: round(v, 4) for k, v in kern_ms.items()}},
         "gemm_phase": {"tflops": round(gemm_phase_tf, 4), "frac_of_fp64_peak": round(gemm_phase_tf / PEAK_FP64_TFLOPS, 4),
                        "flops": info["flops_gemm"], "ms": round(gemm_phase_ms, 4)},
+        # measured HBM bytes per launch (rocprof counters, when they match
+        # the sources) over the average launch time: the gather-GEMM's
+        # gather and the export's copy, against 8 TB/s
+        "hbm_gbs": {k: (round(measured_traffic(args.workload, k) / (per_launch[k] * 1e-3) / 1e9, 1)
+                        if measured_traffic(args.workload, k) and per_launch.get(k) else None)
+                    for k in ("gemm", "export")},
         "factor_gflops": round(info["flops_factor"] / (factor_ms * 1e-3) / 1e9, 2) if factor_ms > 0 else None,
         "invert_gflops": round(info["flops_selinv"] / (invert_ms * 1e-3) / 1e9, 2) if invert_ms > 0 else None,
         "step_ms": {"mean": round(float(per_step.mean()), 4), "std": round(float(per_step.std()), 4),
