@@ -52,7 +52,9 @@
 typedef int64_t i64;
 
 /* Planted-mistake switch used only by the tests that show the pins catch
- * errors.  0 = correct code. */
+ * errors.  0 = correct code; the mistakes are listed where the tests plant
+ * them (1-7 in the arithmetic and the symbolic phase, 8-9 in the export of
+ * the factor). */
 static int g_mut = 0;
 void orc_set_mutation(int m) { g_mut = m; }
 int orc_get_threads(void)
@@ -67,7 +69,10 @@ int orc_get_threads(void)
 /* ------------------------------------------------------------------ */
 /* Nested dissection over a box of grid points                         */
 /* ------------------------------------------------------------------ */
-static void nd_box(const int lo[3], const int hi[3], const int full[3], int dofs,
+/* rim_last = 1 orders a separator plane's interior points before its rim
+ * (the points with a coordinate along another grid axis of more than one
+ * point at the box's first or last value), each part in lexicographic order */
+static void nd_box(const int lo[3], const int hi[3], const int full[3], int dofs, int rim_last,
                    int* perm, i64* pos)
 {
     int ext[3];
@@ -81,30 +86,44 @@ static void nd_box(const int lo[3], const int hi[3], const int full[3], int dofs
     memcpy(l2, lo, sizeof l2);
     memcpy(h2, hi, sizeof h2);
     h2[d] = mid;
-    nd_box(l2, h2, full, dofs, perm, pos);
+    nd_box(l2, h2, full, dofs, rim_last, perm, pos);
     memcpy(h2, hi, sizeof h2);
     l2[d] = mid + 1;
-    nd_box(l2, h2, full, dofs, perm, pos);
+    nd_box(l2, h2, full, dofs, rim_last, perm, pos);
     memcpy(l2, lo, sizeof l2);
     l2[d] = mid;
     h2[d] = mid + 1;
-    for (int z = l2[2]; z < h2[2]; z++)
-        for (int y = l2[1]; y < h2[1]; y++)
-            for (int x = l2[0]; x < h2[0]; x++) {
-                i64 pt = (i64)x + (i64)full[0] * ((i64)y + (i64)full[1] * z);
-                for (int b = 0; b < dofs; b++) perm[(*pos)++] = (int)(pt * dofs + b);
-            }
+    for (int want_rim = 0; want_rim < 2; want_rim++) {
+        if (!rim_last && want_rim == 0) continue;  /* one lexicographic pass */
+        for (int z = l2[2]; z < h2[2]; z++)
+            for (int y = l2[1]; y < h2[1]; y++)
+                for (int x = l2[0]; x < h2[0]; x++) {
+                    if (rim_last) {
+                        int c3[3] = {x, y, z}, on_rim = 0;
+                        for (int k = 0; k < 3; k++)
+                            if (k != d && full[k] > 1 && (c3[k] == lo[k] || c3[k] == hi[k] - 1)) on_rim = 1;
+                        if (on_rim != want_rim) continue;
+                    }
+                    i64 pt = (i64)x + (i64)full[0] * ((i64)y + (i64)full[1] * z);
+                    for (int b = 0; b < dofs; b++) perm[(*pos)++] = (int)(pt * dofs + b);
+                }
+    }
 }
 
 /* perm[new] = old.  Returns the number of unknowns. */
-i64 orc_nd_order(int ndim, const int* dims, int dofs, int* perm)
+i64 orc_nd_order_sep(int ndim, const int* dims, int dofs, int rim_last, int* perm)
 {
     int full[3] = {1, 1, 1};
     for (int k = 0; k < ndim && k < 3; k++) full[k] = dims[k];
     int lo[3] = {0, 0, 0};
     i64 pos = 0;
-    nd_box(lo, full, full, dofs, perm, &pos);
+    nd_box(lo, full, full, dofs, rim_last, perm, &pos);
     return pos;
+}
+
+i64 orc_nd_order(int ndim, const int* dims, int dofs, int* perm)
+{
+    return orc_nd_order_sep(ndim, dims, dofs, 0, perm);
 }
 
 /* ------------------------------------------------------------------ */
@@ -124,9 +143,10 @@ typedef struct {
     i64* poff;    /* panel offsets, panel K is (s+c) x s column-major */
     i64 arena;
     /* block index maps: per supernode a flat list of segments
-     * [J, a, pos(C[a]), pos(C[a+1]), ..., pos(C[c-1])] */
+     * [J, a, pos(C[a]), pos(C[a+1]), ..., pos(C[c-1])]; rptr[K] is where
+     * K's list starts in the concatenation (the lists are built on demand,
+     * map_build) */
     i64* rptr;
-    int* rel;
     int err;
 } orc_sym;
 
@@ -160,12 +180,57 @@ static int row_pos(const orc_sym* S, int J, int r)
     return -1;
 }
 
+/* first index q >= lo of the sorted array v[0..len) with v[q] >= r
+ * (galloping from lo, then bisection) */
+static int lower_from(const int* v, int len, int lo, int r)
+{
+    int step = 1, hi = lo;
+    while (hi < len && v[hi] < r) { lo = hi + 1; hi += step; step *= 2; }
+    if (hi > len) hi = len;
+    while (lo < hi) {
+        int m = (lo + hi) / 2;
+        if (v[m] < r) lo = m + 1; else hi = m;
+    }
+    return lo;
+}
+
+/* Block index map of supernode K (Section 3.2, the relative indices of
+ * C(K) inside each ancestor): for each ancestor J met in C(K), in ascending
+ * order, the record [J, a, pos(C[a]), ..., pos(C[c-1])] with a the first
+ * position of C(K) inside J's columns and pos(x) the row of x within
+ * rows(J) = cols(J) U C(J).  Writes rptr[K+1] - rptr[K] ints to out. */
+static void map_build(const orc_sym* S, int K, int* out)
+{
+    const int* C = sn_C(S, K);
+    int c = sn_c(S, K);
+    i64 q = 0;
+    for (int r = 0; r < c;) {
+        int J = S->sn[C[r]];
+        int f = S->xsuper[J], l = S->xsuper[J + 1];
+        const int* CJ = sn_C(S, J);
+        int cJ = sn_c(S, J), lo = 0;
+        out[q++] = J;
+        out[q++] = r;
+        for (int t = r; t < c; t++) {
+            int x = C[t], p = -1;
+            if (x >= f && x < l) {
+                p = x - f;
+            } else {
+                lo = lower_from(CJ, cJ, lo, x);
+                if (lo < cJ && CJ[lo] == x) p = (l - f) + lo;
+            }
+            out[q++] = p;
+        }
+        while (r < c && S->sn[C[r]] == J) r++;
+    }
+}
+
 void orc_sym_free(orc_sym* S)
 {
     if (!S) return;
     free(S->perm); free(S->iperm); free(S->parent); free(S->sptr); free(S->srow);
     free(S->xsuper); free(S->sn); free(S->sparent); free(S->level); free(S->poff);
-    free(S->rptr); free(S->rel);
+    free(S->rptr);
     free(S);
 }
 
@@ -290,7 +355,8 @@ orc_sym* orc_symbolic(int n, const i64* colptr, const int* rowind, const int* pe
         S->poff[K + 1] = S->poff[K] + (s + c) * s;
     }
     S->arena = S->poff[N];
-    /* block index maps */
+    /* sizes of the block index maps (the records are built per supernode,
+     * on demand, by map_build) */
     S->rptr = (i64*)malloc(sizeof(i64) * ((size_t)N + 1));
     S->rptr[0] = 0;
     for (int K = 0; K < N; K++) {
@@ -303,23 +369,6 @@ orc_sym* orc_symbolic(int n, const i64* colptr, const int* rowind, const int* pe
             while (r < c && S->sn[C[r]] == J) r++;
         }
         S->rptr[K + 1] = S->rptr[K] + tot;
-    }
-    S->rel = (int*)malloc(sizeof(int) * (size_t)(S->rptr[N] + 1));
-    for (int K = 0; K < N; K++) {
-        const int* C = sn_C(S, K);
-        int c = sn_c(S, K);
-        i64 q = S->rptr[K];
-        for (int r = 0; r < c;) {
-            int J = S->sn[C[r]];
-            S->rel[q++] = J;
-            S->rel[q++] = r;
-            for (int t = r; t < c; t++) {
-                int p = row_pos(S, J, C[t]);
-                if (p < 0) S->err = 3;
-                S->rel[q++] = p;
-            }
-            while (r < c && S->sn[C[r]] == J) r++;
-        }
     }
     return S;
 }
@@ -350,7 +399,32 @@ void orc_sym_get(const orc_sym* S, int* perm, int* parent, int* xsuper, int* spa
 void orc_sym_rel(const orc_sym* S, i64* rptr, int* rel)
 {
     memcpy(rptr, S->rptr, sizeof(i64) * ((size_t)S->N + 1));
-    memcpy(rel, S->rel, sizeof(int) * (size_t)S->rptr[S->N]);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int K = 0; K < S->N; K++) map_build(S, K, rel + S->rptr[K]);
+}
+
+/* -1 entries in a map are rows missing from their ancestor (an error) */
+int orc_sym_check_maps(const orc_sym* S)
+{
+    int bad = 0;
+#pragma omp parallel
+    {
+        i64 cap = 0;
+        int* buf = NULL;
+#pragma omp for schedule(dynamic, 16) reduction(| : bad)
+        for (int K = 0; K < S->N; K++) {
+            i64 len = S->rptr[K + 1] - S->rptr[K];
+            if (len > cap) { free(buf); cap = len; buf = (int*)malloc(sizeof(int) * (size_t)cap); }
+            map_build(S, K, buf);
+            for (i64 q = 0; q < len;) {
+                int a = buf[q + 1], c = sn_c(S, K);
+                for (int t = a; t < c; t++) bad |= buf[q + 2 + t - a] < 0;
+                q += 2 + (c - a);
+            }
+        }
+        free(buf);
+    }
+    return bad;
 }
 
 /* canonical lower pattern of L in permuted numbering: column j holds j then
@@ -383,19 +457,17 @@ void orc_sym_flops(const orc_sym* S, double* gemm, double* factor)
 /* O3: supernodal LDL^T and selected inversion                         */
 /* ------------------------------------------------------------------ */
 
-/* segment lookup: for supernode K, pointer to the block index map of the
- * segment containing position r of C(K), and that segment's start a */
-static const int* seg_of(const orc_sym* S, int K, int r, int* J, int* a)
+/* segment lookup in the block index map of supernode K (map, as written by
+ * map_build): pointer to the positions of the segment containing position r
+ * of C(K), that segment's ancestor J and start a */
+static const int* seg_of(const int* map, i64 len, int c, int r, int* J, int* a)
 {
-    int c = sn_c(S, K);
-    i64 q = S->rptr[K];
+    i64 q = 0;
     for (;;) {
-        int JJ = S->rel[q], aa = S->rel[q + 1];
-        int len = c - aa;
-        /* the segment covers positions aa .. (next segment start - 1) */
-        i64 nq = q + 2 + len;
-        int nexta = nq < S->rptr[K + 1] ? S->rel[nq + 1] : c;
-        if (r >= aa && r < nexta) { *J = JJ; *a = aa; return S->rel + q + 2; }
+        int JJ = map[q], aa = map[q + 1];
+        i64 nq = q + 2 + (c - aa);
+        int nexta = nq < len ? map[nq + 1] : c;
+        if (r >= aa && r < nexta) { *J = JJ; *a = aa; return map + q + 2; }
         q = nq;
     }
 }
@@ -405,7 +477,12 @@ static const int* seg_of(const orc_sym* S, int K, int r, int* J, int* a)
  * sel:   nnz(L) values of A^{-1} on the canonical pattern (may be NULL).
  * Lout:  nnz(L) values of L on the canonical pattern, D on the diagonal
  *        (may be NULL).
- * Returns 0, or -3 on a bad pivot with *bad_col = original column index. */
+ * Returns 0, -3 on a bad pivot with *bad_col = original column index, -4 when
+ * out of memory, -5 when a block index map is inconsistent.
+ *
+ * Loop nests run along columns (contiguous in memory); every sum still runs
+ * over its own index in ascending order, as the formulas are written, so the
+ * order of the loops does not change a single rounding. */
 int orc_factor_selinv(const orc_sym* S, const i64* colptr, const int* rowind, const double* valsA,
                       int require_spd, double* sel, double* Lout, i64* bad_col, double* t_factor,
                       double* t_selinv)
@@ -414,7 +491,17 @@ int orc_factor_selinv(const orc_sym* S, const i64* colptr, const int* rowind, co
     double* Lp = (double*)calloc((size_t)S->arena + 1, sizeof(double));
     double* Ai = (double*)calloc((size_t)S->arena + 1, sizeof(double));
     if (!Lp || !Ai) { free(Lp); free(Ai); return -4; }
-    int bad = -1;
+    int bad = -1, maperr = 0;
+    /* block index maps of every supernode (symbolic data: built before the
+     * timed region); a -1 entry is a row missing from its ancestor's rows */
+    int* maps = (int*)malloc(sizeof(int) * (size_t)(S->rptr[N] + 1));
+    if (!maps) { free(Lp); free(Ai); return -4; }
+#pragma omp parallel for schedule(dynamic, 16) reduction(| : maperr)
+    for (int K = 0; K < N; K++) {
+        map_build(S, K, maps + S->rptr[K]);
+        for (i64 q = S->rptr[K]; q < S->rptr[K + 1]; q++) maperr |= maps[q] < 0;
+    }
+    if (maperr) { free(Lp); free(Ai); free(maps); return -5; }
     double t0 = 0;
 #ifdef _OPENMP
     t0 = omp_get_wtime();
@@ -444,31 +531,54 @@ int orc_factor_selinv(const orc_sym* S, const i64* colptr, const int* rowind, co
             int ok = isfinite(dj) && dj != 0.0 && (!require_spd || dj > 0.0);
             if (!ok) { bad = S->xsuper[K] + j; break; }
             F[j + j * ld] = dj;
-#pragma omp parallel for schedule(static) if (ld > 512)
-            for (i64 i = j + 1; i < ld; i++) {
-                double v = F[i + j * ld];
-                for (int k = 0; k < j; k++) v -= F[i + k * ld] * F[k + k * ld] * F[j + k * ld];
-                F[i + j * ld] = v / dj;
+            double* Fj = F + (i64)j * ld;
+            /* rows are independent: threads take runs of 256 rows */
+#pragma omp parallel for schedule(static) if (ld > 2048)
+            for (i64 i0 = j + 1; i0 < ld; i0 += 256) {
+                i64 i1 = i0 + 256 < ld ? i0 + 256 : ld;
+                for (int k = 0; k < j; k++) {
+                    const double* Fk = F + (i64)k * ld;
+                    double dk = Fk[k], ljk = Fk[j];
+                    for (i64 i = i0; i < i1; i++) Fj[i] -= Fk[i] * dk * ljk;
+                }
+                for (i64 i = i0; i < i1; i++) Fj[i] = Fj[i] / dj;
             }
         }
         if (bad >= 0) break;
         if (c == 0) continue;
+        const int* map = maps + S->rptr[K];
+        i64 mlen = S->rptr[K + 1] - S->rptr[K];
         /* Schur complement update of the ancestors:
-         * F(C,C) -= L(C,K) D_K L(C,K)^T, added into the owning panels. */
+         * F(C,C) -= L(C,K) D_K L(C,K)^T, added into the owning panels.
+         * Row r of L(C,K) is copied to LT(:,r), and row r of L(C,K) D_K
+         * (the products L(r,t) d_t) to DT(:,r), so that each entry's sum over
+         * t reads two contiguous vectors. */
         const int* C = sn_C(S, K);
+        double* LT = (double*)malloc(sizeof(double) * (size_t)c * s);
+        double* DT = (double*)malloc(sizeof(double) * (size_t)c * s);
+#pragma omp parallel for schedule(static) if ((i64)c * s > 65536)
+        for (int r = 0; r < c; r++)
+            for (int t = 0; t < s; t++) {
+                LT[t + (i64)r * s] = F[s + r + t * ld];
+                DT[t + (i64)r * s] = F[s + r + t * ld] * F[t + t * ld];
+            }
 #pragma omp parallel for schedule(dynamic, 4) if (c > 64)
         for (int kk = 0; kk < c; kk++) {
             int J, a;
-            const int* pos = seg_of(S, K, kk, &J, &a);
+            const int* pos = seg_of(map, mlen, c, kk, &J, &a);
             i64 ldJ = sn_s(S, J) + sn_c(S, J);
             double* FJ = Lp + S->poff[J] + (i64)(C[kk] - S->xsuper[J]) * ldJ;
+            const double* lk = LT + (i64)kk * s;
             int i0 = (g_mut == 5) ? kk + 1 : kk;
             for (int ii = i0; ii < c; ii++) {
+                const double* di = DT + (i64)ii * s;
                 double u = 0;
-                for (int t = 0; t < s; t++) u += F[s + ii + t * ld] * F[t + t * ld] * F[s + kk + t * ld];
+                for (int t = 0; t < s; t++) u += di[t] * lk[t];
                 FJ[pos[ii - a]] -= u;
             }
         }
+        free(LT);
+        free(DT);
     }
     double t1 = 0;
 #ifdef _OPENMP
@@ -476,7 +586,7 @@ int orc_factor_selinv(const orc_sym* S, const i64* colptr, const int* rowind, co
 #endif
     if (bad >= 0) {
         if (bad_col) *bad_col = S->perm[bad];
-        free(Lp); free(Ai);
+        free(Lp); free(Ai); free(maps);
         return -3;
     }
     /* Algorithm 1, K = N .. 1 (root first; parents have larger indices) */
@@ -487,64 +597,102 @@ int orc_factor_selinv(const orc_sym* S, const i64* colptr, const int* rowind, co
         double* X = Ai + S->poff[K];
         const int* C = sn_C(S, K);
         double* Lh = (double*)malloc(sizeof(double) * ((size_t)c * s + 1));
-        /* step 2: L_hat(C,K) = L(C,K) L_KK^{-1}  (row-wise x L_KK = L(r,:)) */
-        for (int r = 0; r < c; r++)
+        /* step 2: L_hat(C,K) = L(C,K) L_KK^{-1}, i.e. L_hat L_KK = L(C,K),
+         * solved for the columns of L_hat from the last one back */
+        /* rows are independent: threads take runs of 256 rows */
+#pragma omp parallel for schedule(static) if ((i64)c * s > 65536)
+        for (int r0 = 0; r0 < c; r0 += 256) {
+            int r1 = r0 + 256 < c ? r0 + 256 : c;
             for (int j = s - 1; j >= 0; j--) {
-                double v = F[s + r + (i64)j * ld];
+                double* Hj = Lh + (i64)j * c;
+                for (int r = r0; r < r1; r++) Hj[r] = F[s + r + (i64)j * ld];
                 if (g_mut != 3)
-                    for (int k = j + 1; k < s; k++) v -= Lh[r + (i64)k * c] * F[k + (i64)j * ld];
-                Lh[r + (i64)j * c] = v;
+                    for (int k = j + 1; k < s; k++) {
+                        const double* Hk = Lh + (i64)k * c;
+                        double lkj = F[k + (i64)j * ld];
+                        for (int r = r0; r < r1; r++) Hj[r] -= Hk[r] * lkj;
+                    }
             }
+        }
         if (c > 0) {
+            const int* map = maps + S->rptr[K];
+            i64 mlen = S->rptr[K + 1] - S->rptr[K];
             /* step 1 + gather: G = Ainv(C,C) from the stored lower entries */
             double* G = (double*)malloc(sizeof(double) * (size_t)c * c);
 #pragma omp parallel for schedule(dynamic, 4) if (c > 64)
             for (int kk = 0; kk < c; kk++) {
                 int J, a;
-                const int* pos = seg_of(S, K, kk, &J, &a);
+                const int* pos = seg_of(map, mlen, c, kk, &J, &a);
                 i64 ldJ = sn_s(S, J) + sn_c(S, J);
                 const double* AJ = Ai + S->poff[J] + (i64)(C[kk] - S->xsuper[J]) * ldJ;
-                for (int ii = kk; ii < c; ii++) {
-                    double g = AJ[pos[ii - a]];
-                    G[ii + (i64)kk * c] = g;
-                    G[kk + (i64)ii * c] = (g_mut == 4 && ii != kk) ? 0.0 : g;
-                }
+                for (int ii = kk; ii < c; ii++) G[ii + (i64)kk * c] = AJ[pos[ii - a]];
             }
-            /* step 3: Ainv(C,K) = -Ainv(C,C) L_hat(C,K) */
-#pragma omp parallel for schedule(static) if (c > 64)
-            for (int r = 0; r < c; r++)
-                for (int j = 0; j < s; j++) {
-                    double v = 0;
-                    for (int k = 0; k < c; k++) v += G[r + (i64)k * c] * Lh[k + (i64)j * c];
-                    X[s + r + (i64)j * ld] = (g_mut == 1) ? v : -v;
+            /* the entries above the diagonal by symmetry, G(k,i) = G(i,k),
+             * copied in 64 x 64 tiles so that both sides stay in cache */
+#pragma omp parallel for schedule(dynamic, 1) if (c > 64)
+            for (int kb = 0; kb < c; kb += 64)
+                for (int ib = kb; ib < c; ib += 64)
+                    for (int kk = kb; kk < kb + 64 && kk < c; kk++)
+                        for (int ii = (ib > kk + 1 ? ib : kk + 1); ii < ib + 64 && ii < c; ii++)
+                            G[kk + (i64)ii * c] = (g_mut == 4) ? 0.0 : G[ii + (i64)kk * c];
+            /* step 3: Ainv(C,K) = -Ainv(C,C) L_hat(C,K).  G is symmetric, so
+             * row r of G is read as its column r (G(r,k) = G(k,r)); with L_hat
+             * transposed, the s sums of row r advance together over k. */
+            double* HT = (double*)malloc(sizeof(double) * (size_t)c * s);
+            for (int j = 0; j < s; j++)
+                for (int k = 0; k < c; k++) HT[j + (i64)k * s] = Lh[k + (i64)j * c];
+#pragma omp parallel if (c > 64)
+            {
+                double* v = (double*)malloc(sizeof(double) * (size_t)s);
+#pragma omp for schedule(static)
+                for (int r = 0; r < c; r++) {
+                    const double* Gr = G + (i64)r * c;
+                    for (int j = 0; j < s; j++) v[j] = 0;
+                    for (int k = 0; k < c; k++) {
+                        const double g = Gr[k];
+                        const double* h = HT + (i64)k * s;
+                        for (int j = 0; j < s; j++) v[j] += g * h[j];
+                    }
+                    for (int j = 0; j < s; j++) X[s + r + (i64)j * ld] = (g_mut == 1) ? v[j] : -v[j];
                 }
+                free(v);
+            }
+            free(HT);
             free(G);
         }
         /* step 4: Ainv(K,K) = U_KK^{-1} L_KK^{-1} - U_hat(K,C) Ainv(C,K),
          * with U = D L^T and U_hat = L_hat^T.  T(:,j) solves L D L^T x = e_j. */
         double* Y = (double*)malloc(sizeof(double) * (size_t)s * s);
-        double* y = (double*)malloc(sizeof(double) * (size_t)s);
-        for (int j = 0; j < s; j++) {
-            for (int i = 0; i < s; i++) y[i] = (i == j) ? 1.0 : 0.0;
-            for (int i = 0; i < s; i++)
-                for (int k = 0; k < i; k++) y[i] -= F[i + (i64)k * ld] * y[k];
-            for (int i = 0; i < s; i++) y[i] = (g_mut == 6) ? y[i] * F[i + (i64)i * ld] : y[i] / F[i + (i64)i * ld];
-            for (int i = s - 1; i >= 0; i--)
-                for (int k = i + 1; k < s; k++) y[i] -= F[k + (i64)i * ld] * y[k];
-            for (int i = 0; i < s; i++) Y[i + (i64)j * s] = (g_mut == 2) ? 0.0 : y[i];
-        }
-        for (int j = 0; j < s; j++)
-            for (int i = 0; i < s; i++) {
-                double v = 0;
-                for (int r = 0; r < c; r++) v += Lh[r + (i64)i * c] * X[s + r + (i64)j * ld];
-                Y[i + (i64)j * s] -= v;
+#pragma omp parallel if (s > 16)
+        {
+            double* y = (double*)malloc(sizeof(double) * (size_t)s);
+#pragma omp for schedule(static)
+            for (int j = 0; j < s; j++) {
+                for (int i = 0; i < s; i++) y[i] = (i == j) ? 1.0 : 0.0;
+                for (int i = 0; i < s; i++)
+                    for (int k = 0; k < i; k++) y[i] -= F[i + (i64)k * ld] * y[k];
+                for (int i = 0; i < s; i++)
+                    y[i] = (g_mut == 6) ? y[i] * F[i + (i64)i * ld] : y[i] / F[i + (i64)i * ld];
+                for (int i = s - 1; i >= 0; i--)
+                    for (int k = i + 1; k < s; k++) y[i] -= F[k + (i64)i * ld] * y[k];
+                for (int i = 0; i < s; i++) Y[i + (i64)j * s] = (g_mut == 2) ? 0.0 : y[i];
             }
+            free(y);
+#pragma omp for schedule(static)
+            for (int j = 0; j < s; j++)
+                for (int i = 0; i < s; i++) {
+                    double v = 0;
+                    for (int r = 0; r < c; r++) v += Lh[r + (i64)i * c] * X[s + r + (i64)j * ld];
+                    Y[i + (i64)j * s] -= v;
+                }
+        }
         /* symmetrise the diagonal block */
         for (int j = 0; j < s; j++)
             for (int i = 0; i < s; i++)
                 X[i + (i64)j * ld] = 0.5 * (Y[i + (i64)j * s] + Y[j + (i64)i * s]);
-        free(Y); free(y); free(Lh);
+        free(Y); free(Lh);
     }
+    free(maps);
     double t2 = 0;
 #ifdef _OPENMP
     t2 = omp_get_wtime();
@@ -560,7 +708,12 @@ int orc_factor_selinv(const orc_sym* S, const i64* colptr, const int* rowind, co
             for (i64 i = j; i < ld; i++) {
                 i64 o = S->poff[K] + i + (i64)j * ld;
                 if (sel) sel[q] = Ai[o];
-                if (Lout) Lout[q] = Lp[o];
+                if (Lout) {
+                    double v = Lp[o];
+                    if (g_mut == 8 && i > j) v *= Lp[S->poff[K] + j + (i64)j * ld]; /* L D, not L */
+                    if (g_mut == 9 && i == j) v = 1.0 / v;                         /* D^{-1}, not D */
+                    Lout[q] = v;
+                }
                 q++;
             }
     }
@@ -590,6 +743,15 @@ static int dense_ldlt(int n, double* A)
         }
     }
     return -1;
+}
+
+/* O1's factor alone: the dense LDL^T of a symmetric n x n column-major A
+ * (strict lower triangle L, diagonal D, upper triangle left as given).
+ * Returns 0 or -3 on a zero pivot. */
+int orc_dense_ldlt(int n, const double* A, double* F)
+{
+    memcpy(F, A, sizeof(double) * (size_t)n * n);
+    return dense_ldlt(n, F) >= 0 ? -3 : 0;
 }
 
 /* O1: A^{-1} by LDL^T and n triangular solves L y = e_j, D z = y, L^T x = z. */

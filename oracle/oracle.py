@@ -41,6 +41,8 @@ def lib():
         vp = ct.c_void_p
         L.orc_nd_order.argtypes = [ct.c_int, _i32p, ct.c_int, _i32p]
         L.orc_nd_order.restype = ct.c_int64
+        L.orc_nd_order_sep.argtypes = [ct.c_int, _i32p, ct.c_int, ct.c_int, _i32p]
+        L.orc_nd_order_sep.restype = ct.c_int64
         L.orc_symbolic.argtypes = [ct.c_int, _i64p, _i32p, vp, ct.c_int]
         L.orc_symbolic.restype = vp
         for f in ("orc_sym_error", "orc_sym_nsuper"):
@@ -60,6 +62,8 @@ def lib():
         L.orc_factor_selinv.restype = ct.c_int
         L.orc_dense_inverse.argtypes = [ct.c_int, _f64p, _f64p]
         L.orc_dense_inverse.restype = ct.c_int
+        L.orc_dense_ldlt.argtypes = [ct.c_int, _f64p, _f64p]
+        L.orc_dense_ldlt.restype = ct.c_int
         L.orc_selinv_columns.argtypes = [ct.c_int, _f64p, _i64p, _i32p, _f64p]
         L.orc_selinv_columns.restype = ct.c_int
         L.orc_dense_grad.argtypes = [ct.c_int, _f64p, _i64p, _i32p, _f64p, _i64p, _i32p, _f64p]
@@ -81,11 +85,11 @@ def threads() -> int:
     return int(lib().orc_get_threads())
 
 
-def nd_order(ndim, dims, dofs=1):
+def nd_order(ndim, dims, dofs=1, rim_last=False):
     dims = np.asarray(list(dims) + [1] * (3 - len(dims)), dtype=np.int32)[:3]
     n = int(np.prod(dims[:max(ndim, 1)])) * dofs
     perm = np.empty(n, dtype=np.int32)
-    got = lib().orc_nd_order(int(ndim), dims, int(dofs), perm)
+    got = lib().orc_nd_order_sep(int(ndim), dims, int(dofs), int(bool(rim_last)), perm)
     assert got == n
     return perm
 
@@ -101,17 +105,36 @@ class Symbolic:
     level: np.ndarray
     cptr: np.ndarray
     crows: np.ndarray
-    rptr: np.ndarray
-    rel: np.ndarray
     colptrL: np.ndarray
     rowindL: np.ndarray
     gemm_flops: float
     factor_flops: float
     handle: int = 0
+    _maps: tuple = None
+    _owner: object = None  # the OracleSym that owns handle (keeps it alive)
 
     @property
     def nnzL(self):
         return int(self.colptrL[-1])
+
+    def _index_maps(self):
+        """Block index maps (built on first use; quadratic in |C|)."""
+        if self._maps is None:
+            L = lib()
+            rs = L.orc_sym_relsize(self.handle)
+            rptr = np.empty(self.N + 1, np.int64)
+            rel = np.empty(max(rs, 1), np.int32)
+            L.orc_sym_rel(self.handle, rptr, rel)
+            self._maps = (rptr, rel[:rs])
+        return self._maps
+
+    @property
+    def rptr(self):
+        return self._index_maps()[0]
+
+    @property
+    def rel(self):
+        return self._index_maps()[1]
 
 
 class OracleSym:
@@ -140,18 +163,14 @@ class OracleSym:
                       _ptr(cptr), None)
         crows = np.empty(max(int(cptr[-1]), 1), np.int32)
         L.orc_sym_get(self.h, None, None, None, None, None, _ptr(cptr), _ptr(crows))
-        rs = L.orc_sym_relsize(self.h)
-        rptr = np.empty(N + 1, np.int64)
-        rel = np.empty(max(rs, 1), np.int32)
-        L.orc_sym_rel(self.h, rptr, rel)
         colptrL = np.empty(n + 1, np.int64)
         rowindL = np.empty(max(nnzL, 1), np.int32)
         L.orc_sym_pattern(self.h, colptrL, rowindL)
         g, f = ct.c_double(), ct.c_double()
         L.orc_sym_flops(self.h, ct.byref(g), ct.byref(f))
         self.sym = Symbolic(n, N, perm_o, parent, xsuper, sparent[:N], level[:N], cptr,
-                            crows[: int(cptr[-1])], rptr, rel[:rs], colptrL, rowindL[:nnzL],
-                            g.value, f.value, self.h)
+                            crows[: int(cptr[-1])], colptrL, rowindL[:nnzL], g.value, f.value, self.h,
+                            _owner=self)
 
     def factor_selinv(self, vals, require_spd=True, want_L=False):
         """O3: returns (sel, L_or_None, status, bad_col, t_factor, t_selinv)."""
@@ -177,10 +196,10 @@ class OracleSym:
 
 def symbolic(m, cap=128, perm="nd"):
     """Oracle symbolic for a workloads.Matrix. perm: "nd" (from geometry),
-    "natural", or an explicit new->old array."""
+    "nd_rim" (separator rims last), "natural", or an explicit new->old array."""
     if isinstance(perm, str):
-        if perm == "nd" and m.ndim > 0:
-            p = nd_order(m.ndim, m.dims, m.dofs)
+        if perm in ("nd", "nd_rim") and m.ndim > 0:
+            p = nd_order(m.ndim, m.dims, m.dofs, rim_last=perm == "nd_rim")
         else:
             p = None
     else:
@@ -197,6 +216,17 @@ def dense_inverse(a):
     if st != 0:
         raise ValueError("dense LDL^T hit a zero pivot")
     return dst.reshape(n, n).T.copy()
+
+
+def dense_ldlt(a):
+    """O1's dense factor: (L unit lower, d) with A = L diag(d) L^T."""
+    n = a.shape[0]
+    src = np.ascontiguousarray(np.asarray(a, dtype=np.float64).T).ravel()
+    dst = np.empty(n * n)
+    if lib().orc_dense_ldlt(n, src, dst) != 0:
+        raise ValueError("dense LDL^T hit a zero pivot")
+    f = dst.reshape(n, n).T
+    return np.tril(f, -1) + np.eye(n), np.diag(f).copy()
 
 
 def selinv_columns(a_perm, colptrL, rowindL):

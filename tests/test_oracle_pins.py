@@ -302,3 +302,170 @@ def test_planted_mistakes_are_caught(mutation):
     finally:
         O.set_mutation(0)
     assert not _pin_suite_fails()
+
+
+# ---------------------------------------------------------------- the exported factor (O3's L and D)
+def _factor_cases():
+    return [
+        ("random", W.random_spd_pattern(120, 0.04, 21), 7, "random"),
+        ("grid2d", W.laplacian((9, 8), coeff="uniform", lo=0.5, hi=2.0, shift=0.05, seed=3), 16, "nd"),
+        ("grid3d", W.laplacian((5, 4, 3), coeff="loguniform", lo=0.1, hi=10.0, shift=1e-3, seed=5), 4, "nd"),
+        ("molecular", W.molecular(side=3, dofs=8, seed=2), 32, "nd"),
+        ("fig1", W.fig1_pattern(), 6, "natural"),
+    ]
+
+
+def _unpack_factor(Lv, s):
+    """Dense unit-lower L and diagonal D from values on the canonical pattern
+    (D stored on the diagonal positions)."""
+    n = s.n
+    cols = np.repeat(np.arange(n), np.diff(s.colptrL))
+    Ld = np.zeros((n, n))
+    Ld[s.rowindL, cols] = Lv
+    d = np.diag(Ld).copy()
+    np.fill_diagonal(Ld, 1.0)
+    return Ld, d
+
+
+@pytest.mark.parametrize("name", [c[0] for c in _factor_cases()])
+def test_o3_factor_export_reconstructs_A(name):
+    """The L and D that O3 exports satisfy P A P^T = L D L^T (the LDL^T form
+    of Section 2.1), equal the unique LDL^T of the dense permuted matrix given
+    by a library Cholesky (L = C diag(C)^{-1}, D = diag(C)^2), and equal O1's
+    dense factor on the pattern of L."""
+    _, m, cap, how = next(c for c in _factor_cases() if c[0] == name)
+    perm = np.random.default_rng(5).permutation(m.n).astype(np.int32) if how == "random" else how
+    osym = O.symbolic(m, cap=cap, perm=perm)
+    s = osym.sym
+    _, Lv, st, _, _, _ = osym.factor_selinv(m.vals, want_L=True)
+    assert st == 0
+    Ld, d = _unpack_factor(Lv, s)
+    ap = m.dense()[np.ix_(s.perm, s.perm)]
+    scale = np.max(np.abs(ap))
+    assert np.max(np.abs(Ld @ np.diag(d) @ Ld.T - ap)) <= 1e-13 * scale
+    C = np.linalg.cholesky(ap)
+    cd = np.diag(C)
+    assert np.max(np.abs(Ld - C / cd[None, :])) <= 1e-12
+    assert np.max(np.abs(d - cd ** 2) / (cd ** 2)) <= 1e-12
+    L1, d1 = O.dense_ldlt(ap)
+    assert np.max(np.abs(Ld - L1)) <= 1e-13 and np.max(np.abs(d - d1) / np.abs(d1)) <= 1e-13
+    # entries of the dense factor outside the pattern of L are zero (no fill missed)
+    outside = np.ones_like(L1, dtype=bool)
+    cols = np.repeat(np.arange(m.n), np.diff(s.colptrL))
+    outside[s.rowindL, cols] = False
+    outside[np.triu_indices(m.n)] = False
+    assert np.all(L1[outside] == 0.0)
+
+
+# ---------------------------------------------------------------- flop and byte counts
+# Work per supernode (s columns, c rows below): GEMM phase 2c^2 s + 2cs^2,
+# factor c^2 s + cs^2 + s^3/3, whole selected inversion 2c^2 s + 3cs^2 + 2s^3/3,
+# gathered bytes 8 c(c+1)/2.  The (s, c) lists below are read off by hand.
+#
+# Fig. 1 (Section 2.1) under the fundamental partition with a cap of 6: the
+# paper's supernodes 9 and 10 merge; C of each supernode is the union of the
+# row sets of the off-diagonal blocks in its block column, plus the fill block
+# {25, 26, 28} below supernode 8.
+FIG1_SC = [(2, 2),   # cols 0-1,   block (2,1): rows 2-3
+           (2, 4),   # cols 2-3,   block (5,2): rows 10, 12, 13, 14
+           (4, 2),   # cols 4-7,   block (4,3): rows 8-9
+           (2, 6),   # cols 8-9,   block (5,4): rows 10-15
+           (6, 2),   # cols 10-15, block (9,5): rows 23-24
+           (2, 6),   # cols 16-17, blocks (8,6) rows 20-22 and (10,6) rows 25, 26, 28
+           (2, 3),   # cols 18-19, block (8,7): rows 20-22
+           (3, 5),   # cols 20-22, block (9,8) rows 23-24 and the fill rows 25, 26, 28
+           (6, 0)]   # cols 23-28, the root
+# totals of the formulas over that list, added up by hand
+FIG1_GEMM, FIG1_FACTOR, FIG1_SELINV, FIG1_GATHER = 1100.0, 2213.0 / 3.0, 5125.0 / 3.0, 656.0
+
+
+def _tridiag_natural_counts(n):
+    """Natural order: columns 0..n-3 are single-column supernodes with C = {j+1};
+    the last two columns form one supernode with C empty."""
+    k = n - 2
+    return 4.0 * k, k * 7.0 / 3.0 + 8.0 / 3.0, k * 17.0 / 3.0 + 16.0 / 3.0, 8.0 * k
+
+
+def test_fig1_partition_matches_hand_list():
+    m = W.fig1_pattern()
+    s = O.symbolic(m, cap=6, perm="natural").sym
+    got = [(int(s.xsuper[k + 1] - s.xsuper[k]), int(s.cptr[k + 1] - s.cptr[k])) for k in range(s.N)]
+    assert got == FIG1_SC
+
+
+def test_flop_counts_fig1_oracle_and_library():
+    from paper_1404_0447_amd import selinv as S
+    m = W.fig1_pattern()
+    s = O.symbolic(m, cap=6, perm="natural").sym
+    assert s.gemm_flops == pytest.approx(FIG1_GEMM, rel=1e-14)
+    assert s.factor_flops == pytest.approx(FIG1_FACTOR, rel=1e-14)
+    inf = S.Plan(m.n, m.colptr, m.rowind, max_super=6).info
+    assert inf["flops_gemm"] == pytest.approx(FIG1_GEMM, rel=1e-14)
+    assert inf["flops_factor"] == pytest.approx(FIG1_FACTOR, rel=1e-14)
+    assert inf["flops_selinv"] == pytest.approx(FIG1_SELINV, rel=1e-14)
+    assert inf["gather_bytes"] == pytest.approx(FIG1_GATHER, rel=1e-14)
+
+
+@pytest.mark.parametrize("n", [3, 50, 257])
+def test_flop_counts_tridiagonal_natural(n):
+    from paper_1404_0447_amd import selinv as S
+    m = W.tridiag_1d(n, 0.1)
+    gemm, factor, selinv, gather = _tridiag_natural_counts(n)
+    s = O.symbolic(m, cap=8, perm="natural").sym
+    assert s.N == n - 1
+    assert s.gemm_flops == pytest.approx(gemm, rel=1e-14)
+    assert s.factor_flops == pytest.approx(factor, rel=1e-14)
+    inf = S.Plan(m.n, m.colptr, m.rowind, max_super=8).info
+    assert inf["nsuper"] == n - 1
+    assert inf["flops_gemm"] == pytest.approx(gemm, rel=1e-14)
+    assert inf["flops_factor"] == pytest.approx(factor, rel=1e-14)
+    assert inf["flops_selinv"] == pytest.approx(selinv, rel=1e-14)
+    assert inf["gather_bytes"] == pytest.approx(gather, rel=1e-14)
+
+
+@pytest.mark.parametrize("mutation", [8, 9])
+def test_planted_export_mistakes_are_caught(mutation):
+    """8 exports L D instead of L below the diagonal, 9 exports D^{-1} instead
+    of D; the reconstruction pins above catch both."""
+    O.set_mutation(mutation)
+    try:
+        caught = 0
+        for name in [c[0] for c in _factor_cases()]:
+            try:
+                test_o3_factor_export_reconstructs_A(name)
+            except AssertionError:
+                caught += 1
+        assert caught == len(_factor_cases())
+    finally:
+        O.set_mutation(0)
+    for name in [c[0] for c in _factor_cases()]:
+        test_o3_factor_export_reconstructs_A(name)
+
+
+# ---------------------------------------------------------------- rim-last separators
+def test_nd_rim_last_hand_examples():
+    # 5 x 5: the top separator is the column x = 2; its interior (y = 1..3)
+    # comes before its rim (y = 0 and y = 4)
+    assert list(O.nd_order(2, (5, 5), rim_last=True)[-5:]) == [7, 12, 17, 2, 22]
+    assert list(O.nd_order(2, (5, 5))[-5:]) == [2, 7, 12, 17, 22]
+    # 3 x 3 x 3: the top separator is the plane x = 1; only (y, z) = (1, 1) is interior
+    assert list(O.nd_order(3, (3, 3, 3), rim_last=True)[-9:]) == [13, 1, 4, 7, 10, 16, 19, 22, 25]
+    # 1D: a separator is one point, nothing to reorder
+    assert list(O.nd_order(1, (7,), rim_last=True)) == list(O.nd_order(1, (7,)))
+
+
+@pytest.mark.parametrize("dims", [(16, 16), (7, 9, 6)])
+def test_rim_last_changes_pattern_not_values(dims):
+    m = W.laplacian(dims, coeff="uniform", lo=0.5, hi=2.0, shift=0.05, seed=11)
+    a = O.symbolic(m, cap=16, perm="nd")
+    b = O.symbolic(m, cap=16, perm="nd_rim")
+    assert sorted(b.sym.perm) == list(range(m.n)) and not np.array_equal(a.sym.perm, b.sym.perm)
+    sa, sb = a.factor_selinv(m.vals)[0], b.factor_selinv(m.vals)[0]
+    da = H.sel_to_dict(sa, a.sym.colptrL, a.sym.rowindL, a.sym.perm)
+    db = H.sel_to_dict(sb, b.sym.colptrL, b.sym.rowindL, b.sym.perm)
+    common = set(da) & set(db)
+    assert len(common) > m.nnz
+    assert max(abs(da[k] - db[k]) for k in common) < 1e-12
+    exact = np.linalg.inv(m.dense())
+    assert H.err_c8(sb, H.sel_from_dense(exact, b.sym.colptrL, b.sym.rowindL, b.sym.perm), b.sym.colptrL,
+                    b.sym.rowindL) < 1e-11
