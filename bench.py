@@ -4,20 +4,25 @@
 A step is one pass of the whole hot path on device-resident input: numeric
 factorization (assemble, diagonal LDL^T, panels with the normalised L_hat,
 Schur updates) followed by the root-to-leaf selected inversion (gathered
-GEMMs, diagonal blocks) and the export of the selected values.
+GEMMs, diagonal blocks) and the export of the selected values.  The default
+workload is the 64^3 variable-coefficient Laplacian with supernodes capped
+at 256 columns.
 
 Prints ONE JSON line.  `value` is algorithmic FP64 GFLOP/s of the step
 (fundamental-supernode flop counts of factor + selected inversion divided by
 the step time).  `roofline` covers the kernel kind with the largest share of
 device time, timed live with HIP events stamped in each dispatch during a
 second pass over the same K steps (the stamps cost time of their own, so
-`ms_per_step` comes from the pass without them).
-`cpu_baseline` times the CPU oracle (test infrastructure, untuned) on the
-same matrix.  Two more parts of the metric ride on the same line:
-`backward` (the reverse sweep's time over the forward step's, same matrix)
-and `batched` (256 independent 2D grids: the batch on the persistent
-per-level kernels replayed from a HIP graph, against a loop of per-matrix
-runs with per-level launches, same kernels, same GPU).
+`ms_per_step` comes from the pass without them); `peaks` holds the device's
+measured FP64 MFMA and copy ceilings beside the published ones.
+`cpu_baseline` times the CPU oracle (test infrastructure, untuned) on a
+bounded sample of the same workload.  More parts of the metric ride on the
+same line: `backward` (the reverse sweep's time over the forward step's,
+same matrix, without and with checkpointing of the inverse panels),
+`deterministic` (the atomic-free mode's step), `extra_workloads` (the 40^3
+grid and the molecular matrix) and `batched` (256 independent 2D grids: the
+batch on the persistent per-level kernels replayed from a HIP graph, against
+a loop of per-matrix runs with per-level launches, same kernels, same GPU).
 """
 from __future__ import annotations
 
@@ -89,11 +94,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="lap3d_40", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="lap3d_64", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fuse", action="store_true", help="run fundamental supernodes unamalgamated")
     ap.add_argument("--no-bwd", action="store_true", help="skip the backward (adjoint) timing")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-speedup measurement")
+    ap.add_argument("--no-extra", action="store_true", help="skip the 40^3 and molecular side measurements")
+    ap.add_argument("--no-det", action="store_true", help="skip the deterministic-mode step")
+    ap.add_argument("--checkpoint-every", type=int, default=4,
+                    help="checkpoint interval of the second backward measurement (0: skip it)")
     ap.add_argument("--batch-reps", type=int, default=10, help="timed replays of the batched graph")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain device copy of 1 GiB (read 1 GiB, write 1 GiB) three times: the "
@@ -219,6 +228,12 @@ def main():
     invert_ms = gemm_phase_ms + kern_ms["export"]
     factor_ms = sum(kern_ms[k] for k in ("assemble", "ldlt", "panel", "schur", "sbfactor"))
 
+    log("[bench] device ceilings: FP64 MFMA loop and copy ...")
+    mf_tf, copy_gbs = S.measure_peaks(device=dev)
+    roof["measured_peak"] = round(mf_tf if roof["unit"] == "TFLOP/s" else copy_gbs, 2)
+    roof["frac_of_measured_peak"] = round(roof["achieved"] / roof["measured_peak"], 4) if roof["measured_peak"] else None
+    log(f"[bench] measured FP64 MFMA {mf_tf:.1f} TFLOP/s, copy {copy_gbs:.0f} GB/s")
+
     result = {
         "metric": METRIC, "value": round(value, 3), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
@@ -244,37 +259,33 @@ def main():
         "invert_gflops": round(info["flops_selinv"] / (invert_ms * 1e-3) / 1e9, 2) if invert_ms > 0 else None,
         "step_ms": {"mean": round(float(per_step.mean()), 4), "std": round(float(per_step.std()), 4),
                     "median": round(float(np.median(per_step)), 4), "runs": int(per_step.size)},
+        "peaks": {"fp64_mfma_tflops_measured": round(mf_tf, 2), "fp64_mfma_tflops_published": PEAK_FP64_TFLOPS,
+                  "copy_gbs_measured": round(copy_gbs, 1), "hbm_gbs_published": PEAK_HBM_GBS,
+                  "gemm_phase_frac_of_measured": round(gemm_phase_tf / mf_tf, 4) if mf_tf > 0 else None},
         "cpu_baseline": None,
     }
 
     if not args.no_bwd:
         result["backward"] = measure_backward(plan, vals, out, ms_step, args, dev)
+        if args.checkpoint_every > 1:
+            del plan  # its workspace is not needed any more
+            torch.cuda.empty_cache()
+            result["backward"]["checkpointed"] = measure_checkpointed(m, cap, args, dev, ms_step,
+                                                                      result["backward"].get("grad_probe"))
+    if not args.no_det:
+        result["deterministic"] = measure_deterministic(m, cap, args, dev, ms_step, out)
+    if not args.no_extra:
+        result["extra_workloads"] = {w: measure_extra(w, args, dev) for w in ("lap3d_40", "molecular_16")
+                                     if w != args.workload}
     if not args.no_batch:
         result["batched"] = measure_batched(args, dev)
 
     if not args.no_cpu:
-        from oracle import oracle as O
-        log("[bench] cpu baseline: oracle symbolic ...")
-        osym = O.symbolic(m, cap=cap)
-        log("[bench] cpu baseline: oracle factor + selected inversion ...")
-        t0 = time.time()
-        ref, _, st, _, tf, ts = osym.factor_selinv(m.vals)
-        wall = time.time() - t0
-        cpu_gflops = flops_step / (tf + ts) / 1e9
-        got = out.cpu().numpy()
-        cp, ri, _ = plan.pattern()
-        d = ref[cp[:-1]]
-        cols = np.repeat(np.arange(m.n), np.diff(cp))
-        err = float(np.max(np.abs(got - ref) / np.sqrt(np.abs(d[ri] * d[cols]))))
-        cpu_model = next((ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo")
-                          if ln.startswith("model name")), "unknown")
-        result["cpu_baseline"] = {"value": round(cpu_gflops, 3), "unit": "GFLOP/s", "cores": O.threads(),
-                                  "kind": "oracle", "cpu_model": cpu_model, "nproc": os.cpu_count(),
-                                  "sample": f"full {args.workload} matrix, factor + selected inversion "
-                                            f"(excl. symbolic), {tf + ts:.2f}s",
-                                  "speedup_gpu_over_cpu": round(value / cpu_gflops, 2)}
-        result["max_err_vs_oracle"] = err
-        log(f"[bench] oracle {tf + ts:.2f}s ({wall:.1f}s wall), max err vs oracle {err:.2e}")
+        result["cpu_baseline"], err = cpu_baseline(m, args.workload, cap, flops_step, value, out)
+        if err is not None:
+            result["max_err_vs_oracle"] = err
+    if "backward" in result:
+        result["backward"].pop("grad_probe", None)
     print(json.dumps(result), flush=True)
 
 
@@ -289,6 +300,223 @@ def _time(fn, reps, stream):
     stop.record(stream)
     torch.cuda.synchronize()
     return start.elapsed_time(stop) / reps
+
+
+def sub_box(m, dims, box_hi):
+    """Principal submatrix of a grid matrix on the points [0, box_hi) (x, y,
+    z), as a grid matrix of its own.  When the box is a subtree of the
+    nested dissection of the full grid, its factorization is that subtree's
+    part of the full factorization."""
+    import numpy as np
+    from paper_1404_0447_amd import workloads as W
+    nx, ny, nz = dims
+    idx = np.arange(m.n)
+    x, y, z = idx % nx, (idx // nx) % ny, idx // (nx * ny)
+    keep = (x < box_hi[0]) & (y < box_hi[1]) & (z < box_hi[2])
+    new = np.full(m.n, -1, np.int64)
+    new[keep] = x[keep] + box_hi[0] * (y[keep] + box_hi[1] * z[keep])
+    cols = np.repeat(np.arange(m.n), np.diff(m.colptr))
+    r, c = m.rowind.astype(np.int64), cols
+    sel = keep[r] & keep[c]
+    rr, cc, vv = new[r[sel]], new[c[sel]], m.vals[sel]
+    n = int(keep.sum())
+    colptr = np.zeros(n + 1, np.int64)
+    np.add.at(colptr, cc + 1, 1)
+    colptr = np.cumsum(colptr)
+    order = np.lexsort((rr, cc))
+    return W.Matrix(n, colptr, rr[order].astype(np.int32), vv[order], ndim=3, dims=tuple(box_hi), dofs=1)
+
+
+def cpu_baseline(m, workload, cap, flops_step, gpu_gflops, out):
+    """The oracle (its factor + selected inversion, symbolic phase excluded)
+    on the host cores: the whole matrix when it is small, else the half box
+    [0,32) x [0,64) x [0,64) of the 64^3 grid, which is the subtree its nested
+    dissection orders first (n = 131,072, about 10-30 s of CPU work)."""
+    import numpy as np
+    from oracle import oracle as O
+    if workload == "lap3d_64":
+        sample_m = sub_box(m, m.dims, (32, 64, 64))
+        # the sub-box, in its own nested-dissection order, is exactly the
+        # first subtree of the full grid's order
+        i = np.arange(sample_m.n)
+        to_full = (i % 32) + 64 * ((i // 32) % 64) + 4096 * (i // 2048)
+        full = O.nd_order(3, m.dims)
+        assert np.array_equal(full[:sample_m.n], to_full[O.nd_order(3, (32, 64, 64))])
+        sample = ("principal submatrix of the 64^3 matrix on the half box [0,32)x[0,64)x[0,64), the first "
+                  "subtree of its nested dissection (n=131072), cap 256")
+    else:
+        sample_m, sample = m, f"the whole {workload} matrix"
+    log(f"[bench] cpu baseline: oracle symbolic on {sample_m.n} unknowns ...")
+    osym = O.symbolic(sample_m, cap=cap)
+    fl = osym.sym.factor_flops + selinv_flops(osym.sym)
+    log("[bench] cpu baseline: oracle factor + selected inversion ...")
+    t0 = time.time()
+    ref, _, st, _, tf, ts = osym.factor_selinv(sample_m.vals)
+    wall = time.time() - t0
+    assert st == 0
+    cpu_gflops = fl / (tf + ts) / 1e9
+    err = None
+    if sample_m is m:
+        got = out.cpu().numpy()
+        cp, ri = osym.sym.colptrL, osym.sym.rowindL
+        d = ref[cp[:-1]]
+        cols = np.repeat(np.arange(m.n), np.diff(cp))
+        err = float(np.max(np.abs(got - ref) / np.sqrt(np.abs(d[ri] * d[cols]))))
+    cpu_model = next((ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo")
+                      if ln.startswith("model name")), "unknown")
+    res = {"value": round(cpu_gflops, 3), "unit": "GFLOP/s", "cores": O.threads(), "kind": "oracle",
+           "cpu_model": cpu_model, "nproc": os.cpu_count(),
+           "sample": f"{sample}: factor + selected inversion (symbolic excluded), {fl:.3e} flops in "
+                     f"{tf + ts:.2f}s, one run",
+           "speedup_gpu_over_cpu": round(gpu_gflops / cpu_gflops, 2)}
+    log(f"[bench] oracle {tf + ts:.2f}s ({wall:.1f}s wall) = {cpu_gflops:.2f} GFLOP/s on {O.threads()} threads")
+    return res, err
+
+
+def selinv_flops(sym):
+    """Sum of 2c^2 s + 3cs^2 + 2s^3/3 over the oracle's supernodes."""
+    import numpy as np
+    s = np.diff(sym.xsuper).astype(np.float64)
+    c = np.diff(sym.cptr).astype(np.float64)
+    return float(np.sum(2 * c * c * s + 3 * c * s * s + 2.0 / 3.0 * s ** 3))
+
+
+def time_forward(plan, vals, out, steps, warmup, stream, profile=False):
+    """(ms per factor + invert step, per-kind profile or None)."""
+    import torch
+
+    def step():
+        plan.factor(vals)
+        plan.invert(out)
+    for _ in range(warmup):
+        step()
+    plan.sync_status()
+    ms = _time(step, steps, stream)
+    prof = None
+    if profile:
+        plan.profile(True)
+        _time(step, steps, stream)
+        plan.profile(False)
+        prof = plan.profile_read()
+    plan.sync_status()
+    return ms, prof
+
+
+def measure_checkpointed(m, cap, args, dev, fwd_ms, grad_probe):
+    """Backward with checkpointing: the inverse panels of every k-th level
+    are copied to the persistent store by the forward, the transient memory
+    (inverse panels and adjoint arenas) is released between forward and
+    backward, and the backward restores the checkpoints and recomputes the
+    other levels before the reverse sweep."""
+    import numpy as np
+    import torch
+    from paper_1404_0447_amd import selinv as S
+    k = args.checkpoint_every
+    stream = torch.cuda.current_stream()
+    p = S.Plan.from_matrix(m, max_super=cap, checkpoint_every=k).bind(device=dev)
+    vals = torch.as_tensor(m.vals, dtype=torch.float64, device=dev)
+    out = torch.empty(int(p.info["nnzL"]), dtype=torch.float64, device=dev)
+    fwd_k, _ = time_forward(p, vals, out, args.steps, args.warmup, stream)
+    g = torch.as_tensor(np.random.default_rng(0).standard_normal(int(p.info["nnzL"])), device=dev)
+    gA = torch.empty(int(p.info["nnzA"]), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    p.factor(vals)
+    p.invert(out)
+    p.release_transient()
+    torch.cuda.synchronize()
+    held = torch.cuda.memory_allocated(dev)
+    torch.cuda.reset_peak_memory_stats(dev)
+    p.backward(g, out=gA)
+    torch.cuda.synchronize()
+    peak = torch.cuda.max_memory_allocated(dev)
+    for _ in range(max(1, args.warmup) - 1):
+        p.backward(g, out=gA)
+    bwd = _time(lambda: p.backward(g, out=gA), args.steps, stream)
+    p.profile(True)
+    _time(lambda: p.backward(g, out=gA), args.steps, stream)
+    p.profile(False)
+    prof = p.profile_read()
+    p.sync_status()
+    res = {"checkpoint_every": k, "fwd_ms": round(fwd_k, 4), "bwd_ms": round(bwd, 4),
+           "bwd_over_fwd": round(bwd / fwd_ms, 3), "bwd_over_own_fwd": round(bwd / fwd_k, 3),
+           "recompute_ms": round((prof["gemm"][0] + prof["sdiag"][0] + prof["sbinvert"][0]) / args.steps, 4),
+           "checkpoint_copy_ms": round(prof["checkpoint"][0] / args.steps, 4),
+           "persistent_bytes": p.persistent_bytes, "transient_bytes": p.transient_bytes,
+           "checkpoint_store_bytes": int(p.kernel_work()["checkpoint"][1] / 2),
+           "device_bytes_held_between_fwd_and_bwd": int(held),
+           "device_bytes_held_without_checkpointing": int(held + p.transient_bytes),
+           "device_peak_bytes_in_backward": int(peak)}
+    if grad_probe is not None:
+        gk = gA[: len(grad_probe)].cpu().numpy()
+        res["grad_max_rel_diff_vs_full"] = float(np.abs(gk - grad_probe).max() / max(np.abs(grad_probe).max(), 1e-300))
+    log(f"[bench] backward with checkpoint_every={k}: {bwd:.3f} ms ({bwd / fwd_ms:.2f}x forward), "
+        f"held {held / 1e9:.2f} GB between forward and backward (vs {(held + p.transient_bytes) / 1e9:.2f} GB)")
+    del p
+    torch.cuda.empty_cache()
+    return res
+
+
+def measure_deterministic(m, cap, args, dev, fwd_ms, out_ref):
+    """The atomic-free mode on the same matrix: step time, and two runs
+    compared bit for bit."""
+    import numpy as np
+    import torch
+    from paper_1404_0447_amd import selinv as S
+    stream = torch.cuda.current_stream()
+    p = S.Plan.from_matrix(m, max_super=cap, deterministic=True).bind(device=dev)
+    vals = torch.as_tensor(m.vals, dtype=torch.float64, device=dev)
+    out = torch.empty(int(p.info["nnzL"]), dtype=torch.float64, device=dev)
+    ms, prof = time_forward(p, vals, out, args.steps, args.warmup, stream)
+    a = out.clone()
+    p.factor(vals)
+    p.invert(out)
+    p.sync_status()
+    same = bool(torch.equal(a, out))
+    diff = float((out - out_ref).abs().max().item())
+    log(f"[bench] deterministic step {ms:.3f} ms ({ms / fwd_ms:.2f}x), bitwise repeatable: {same}")
+    del p
+    torch.cuda.empty_cache()
+    return {"ms_per_step": round(ms, 4), "over_default": round(ms / fwd_ms, 3), "bitwise_repeatable": same,
+            "max_abs_diff_vs_default": diff}
+
+
+def measure_extra(workload, args, dev):
+    """Forward step (and for the molecular matrix the backward) of another
+    configuration, with the GEMM phase from stamped kernel times."""
+    import numpy as np
+    import torch
+    from paper_1404_0447_amd import selinv as S
+    from paper_1404_0447_amd import workloads as W
+    stream = torch.cuda.current_stream()
+    t0 = time.time()
+    m = W.make(workload)
+    cap = W.CONFIGS[workload]["cap"]
+    p = S.Plan.from_matrix(m, max_super=cap).bind(device=dev)
+    info = p.info
+    vals = torch.as_tensor(m.vals, dtype=torch.float64, device=dev)
+    out = torch.empty(int(info["nnzL"]), dtype=torch.float64, device=dev)
+    ms, prof = time_forward(p, vals, out, args.steps, args.warmup, stream, profile=True)
+    kern = {k: prof[k][0] / args.steps for k in prof}
+    gp = kern["gemm"] + kern["sdiag"] + kern["sbinvert"]
+    gtf = info["flops_gemm"] / (gp * 1e-3) / 1e12 if gp > 0 else 0.0
+    res = {"workload": WORKLOADS[workload], "ms_per_step": round(ms, 4),
+           "gflops": round((info["flops_factor"] + info["flops_selinv"]) / (ms * 1e-3) / 1e9, 2),
+           "gemm_phase_tflops": round(gtf, 3), "gemm_phase_frac_of_fp64_peak": round(gtf / PEAK_FP64_TFLOPS, 4),
+           "ldlt_ms": round(kern["ldlt"], 4), "dominant_kernel": max(kern, key=lambda k: kern[k])}
+    if workload == "molecular_16":
+        g = torch.as_tensor(np.random.default_rng(0).standard_normal(int(info["nnzL"])), device=dev)
+        gA = torch.empty(int(info["nnzA"]), dtype=torch.float64, device=dev)
+        p.factor(vals)
+        p.invert(out)
+        p.backward(g, out=gA)
+        bwd = _time(lambda: p.backward(g, out=gA), args.steps, stream)
+        res["bwd_ms"] = round(bwd, 4)
+        res["bwd_over_fwd"] = round(bwd / ms, 3)
+    p.sync_status()
+    log(f"[bench] {workload}: {ms:.3f} ms/step, GEMM phase {gtf:.1f} TFLOP/s ({time.time() - t0:.1f}s)")
+    del p
+    torch.cuda.empty_cache()
+    return res
 
 
 def measure_backward(plan, vals, out, fwd_ms, args, dev):
@@ -316,7 +544,7 @@ def measure_backward(plan, vals, out, fwd_ms, args, dev):
     log(f"[bench] backward {bwd_ms:.3f} ms/step ({bwd_ms / fwd_ms:.2f}x forward)")
     return {"fwd_ms": round(fwd_ms, 4), "bwd_ms": round(bwd_ms, 4), "bwd_over_fwd": round(bwd_ms / fwd_ms, 3),
             "kernels_ms": {k: round(prof[k][0] / args.steps, 4) for k in ("revsel", "revfac")},
-            "target": "<= 3"}
+            "target": "<= 3", "grad_probe": gA[:100000].cpu().numpy()}
 
 
 def measure_batched(args, dev):

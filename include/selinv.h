@@ -73,6 +73,29 @@ typedef struct {
     int32_t exec_cap;     /* cap on an execution block's width (<= 256); 0 =
                              min(max_super, 128).  Blocks wider than 128 take
                              a slow diagonal-factorization path.           */
+    int32_t sep_order;    /* order of the points of a nested-dissection
+                             separator plane: 0 lexicographic (x fastest);
+                             1 rim last: the points on the plane's boundary
+                             (a coordinate along another grid axis of more
+                             than one point at the box's first or last
+                             value) after the interior ones, each group
+                             lexicographic.  Changes the pattern of L, never
+                             the values of A^{-1}.                          */
+    int32_t deterministic; /* 1: no floating-point atomics anywhere (no split
+                             contractions, every Schur and adjoint scatter in
+                             colour groups of disjoint updates, no small-block
+                             kernels): results are bitwise reproducible from
+                             run to run, through selinv_run and its graph, and
+                             between a batch and its matrices run alone.
+                             Slower.                                        */
+    int32_t checkpoint_every; /* adjoint: the inverse panels of every k-th
+                             level (levels 1, 1+k, 1+2k, ...; root = 1) are
+                             copied to the persistent checkpoint store by
+                             selinv_invert; selinv_backward restores them and
+                             recomputes the other levels root first before
+                             the reverse sweep, so the transient memory may be
+                             released between the two.  <= 1: every level is
+                             kept in place and nothing is recomputed.       */
 } selinv_opts;
 
 typedef struct {
@@ -98,13 +121,33 @@ selinv_status selinv_analyze(int64_t n, const int64_t* colptr, const int32_t* ro
                              const selinv_geom* geom, const int32_t* perm_or_null,
                              const selinv_opts* opts, selinv_plan* out);
 
-/* Bytes of device workspace the plan needs (factor, inverse, index maps). */
+/* Bytes of device workspace the plan needs (factor, inverse, index maps):
+ * persistent + transient, for one buffer holding both. */
 selinv_status selinv_workspace_size(selinv_plan p, size_t* bytes);
 
-/* Bind caller-owned device memory (>= selinv_workspace_size bytes, 256-byte
- * aligned) and upload the index maps on stream s.  The plan never allocates
+/* The two parts of the workspace.  Persistent: the factor, L_hat, T_K, the
+ * index maps and task lists, and the checkpoint store; it must stay bound
+ * from selinv_factor to selinv_backward.  Transient: the inverse panels and
+ * the adjoint arenas, needed only inside selinv_invert, selinv_backward and
+ * selinv_run.  Either pointer may be NULL. */
+selinv_status selinv_workspace_sizes(selinv_plan p, size_t* persistent, size_t* transient);
+
+/* Bind caller-owned device memory (256-byte aligned) and upload the index
+ * maps on stream s.  bytes >= selinv_workspace_size: the transient part
+ * lives after the persistent part; persistent <= bytes < that: only the
+ * persistent part, and a transient buffer must be bound with
+ * selinv_bind_transient before an inversion.  The plan never allocates
  * device memory itself. */
 selinv_status selinv_bind_workspace(selinv_plan p, void* d_ws, size_t bytes, hipStream_t s);
+
+/* Bind a separate transient buffer (>= the transient size, 256-byte
+ * aligned; the caller keeps ownership), or with d_tr = NULL release the one
+ * bound (falling back to the workspace's own transient part if it has one).
+ * The inverse panels it held are gone: after a release or a rebind,
+ * selinv_backward needs checkpoint_every > 1 (it rebuilds them from the
+ * checkpoints) or a new selinv_invert.  No device work; drops a captured
+ * graph. */
+selinv_status selinv_bind_transient(selinv_plan p, void* d_tr, size_t bytes);
 
 /* Supernodal LDL^T of A (Section 2.1, LDL^T form; no pivoting, Section 4).
  * d_valsA: nnzA doubles in the CSC order given to selinv_analyze. */
@@ -115,6 +158,12 @@ selinv_status selinv_factor(selinv_plan p, const double* d_valsA, hipStream_t s)
  * order of selinv_get_pattern. */
 selinv_status selinv_invert(selinv_plan p, double* d_sel, hipStream_t s);
 
+/* Number of factorizations (selinv_factor, selinv_run) this plan has run.
+ * A caller that keeps a plan across calls (an autograd node) records it
+ * after the forward and checks it before selinv_backward: a different value
+ * means the plan's factor and inverse now belong to other values. */
+selinv_status selinv_generation(selinv_plan p, uint64_t* gen);
+
 /* Reverse sweep (adjoint).  For f = sum over the pattern of L of
  * gsel_q * Ainv_q (d_gsel: nnzL doubles, canonical order), writes
  * d_gA[p] = df/da_p for every stored entry p of A (nnzA doubles, the CSC
@@ -123,8 +172,11 @@ selinv_status selinv_invert(selinv_plan p, double* d_sel, hipStream_t s);
  * diagonal, S = G + G^T.  Runs the selected inversion in reverse (leaves
  * first, Algorithm 1 backwards) and then the factorization in reverse (root
  * first).  Needs selinv_factor and selinv_invert of the same values first;
- * uses only the workspace (no allocation).  SELINV_EUNSUPPORTED if an
- * execution block is wider than 128 columns. */
+ * uses only the workspace (no allocation).  With checkpoint_every > 1 it
+ * first restores the checkpointed levels' inverse panels and recomputes the
+ * others (root first); otherwise the inverse panels must still hold the
+ * inversion (SELINV_ESTATE after the transient memory was released).
+ * SELINV_EUNSUPPORTED if an execution block is wider than 128 columns. */
 selinv_status selinv_backward(selinv_plan p, const double* d_gsel, double* d_gA, hipStream_t s);
 
 /* Copy L (unit lower, D on the diagonal) on the canonical pattern to d_L. */
@@ -171,7 +223,8 @@ enum {
     SELINV_K_QINVERT = 10, /* persistent inversion level (GEMM, SDIAG tasks)      */
     SELINV_K_SBFACTOR = 11, /* small blocks, whole factor step, one wave each      */
     SELINV_K_SBINVERT = 12, /* small blocks, whole inversion step, one wave each   */
-    SELINV_NKINDS = 13
+    SELINV_K_CHECKPOINT = 13, /* inverse panels to / from the checkpoint store      */
+    SELINV_NKINDS = 14
 };
 
 /* Enable (1) or disable (0) per-launch timing: every later kernel launch of
@@ -310,6 +363,18 @@ selinv_status selinv_run(selinv_plan p, const double* d_valsA, double* d_sel, in
  * schedule and its time in ms.  Synchronises s. */
 selinv_status selinv_tune(selinv_plan p, const double* d_valsA, double* d_sel, const char* cache_path,
                           selinv_sched* chosen, double* best_ms, hipStream_t s);
+
+/* Device ceilings for the roofline, measured on the current device (not
+ * part of the method): a sustained FP64 MFMA rate (every wave issuing
+ * independent v_mfma_f64_16x16x4f64 back to back, best of four launches)
+ * and a copy bandwidth (the first half of d_buf copied into the second,
+ * bytes read + written over the kernel time, best of four after one
+ * warm-up).  d_buf: caller-owned device scratch of `bytes` >= 64 MiB,
+ * 256-byte aligned (its contents are overwritten; 2 GiB or more measures
+ * HBM rather than cache).  Synchronises s.  SELINV_EINVAL for a bad
+ * buffer. */
+selinv_status selinv_measure_peaks(void* d_buf, size_t bytes, double* fp64_mfma_tflops, double* copy_gbs,
+                                   hipStream_t s);
 
 /* Message for the last failing call on this thread. */
 const char* selinv_last_error(void);

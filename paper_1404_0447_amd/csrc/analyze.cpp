@@ -14,8 +14,12 @@ namespace selinv {
 // Nested dissection of a grid box.  Boxes are split across their longest
 // axis (ties to the lowest axis) at lo + floor(extent/2); the order is the
 // left box, the right box, then the separator plane with points in
-// lexicographic order (x fastest).  dofs unknowns per point stay together.
-// Implemented as an explicit post-order walk of the bisection tree.
+// lexicographic order (x fastest) or, with rim_last, its interior points
+// first and then its rim (points with a coordinate along another axis of
+// the grid, one of more than one point, at the box's first or last value),
+// each lexicographic.  dofs unknowns per point stay
+// together.  Implemented as an explicit post-order walk of the bisection
+// tree.
 // ---------------------------------------------------------------------------
 namespace {
 struct Box {
@@ -24,7 +28,7 @@ struct Box {
 };
 }  // namespace
 
-void nd_order_box(int ndim, const int32_t dims[3], int dofs, std::vector<int32_t>& perm)
+void nd_order_box(int ndim, const int32_t dims[3], int dofs, int rim_last, std::vector<int32_t>& perm)
 {
     int32_t full[3] = {1, 1, 1};
     for (int d = 0; d < ndim && d < 3; d++) full[d] = dims[d];
@@ -58,16 +62,26 @@ void nd_order_box(int ndim, const int32_t dims[3], int dofs, std::vector<int32_t
             r.lo[f.axis] = f.mid + 1;
             if (!r.empty()) { st.push_back({r, 0, 0, 0}); continue; }
         }
-        // stage 2: separator plane
+        // stage 2: separator plane (pass 0 interior, pass 1 rim when rim_last)
         Box s = f.b;
         s.lo[f.axis] = f.mid;
         s.hi[f.axis] = f.mid + 1;
-        for (int32_t z = s.lo[2]; z < s.hi[2]; z++)
-            for (int32_t y = s.lo[1]; y < s.hi[1]; y++)
-                for (int32_t x = s.lo[0]; x < s.hi[0]; x++) {
-                    int64_t pt = x + (int64_t)full[0] * (y + (int64_t)full[1] * z);
-                    for (int k = 0; k < dofs; k++) perm.push_back((int32_t)(pt * dofs + k));
-                }
+        const int ax = f.axis;
+        for (int pass = rim_last ? 0 : 1; pass < 2; pass++)
+            for (int32_t z = s.lo[2]; z < s.hi[2]; z++)
+                for (int32_t y = s.lo[1]; y < s.hi[1]; y++)
+                    for (int32_t x = s.lo[0]; x < s.hi[0]; x++) {
+                        if (rim_last) {
+                            const int32_t p3[3] = {x, y, z};
+                            bool rim = false;
+                            for (int d = 0; d < 3; d++)
+                                if (d != ax && full[d] > 1 && (p3[d] == f.b.lo[d] || p3[d] == f.b.hi[d] - 1))
+                                    rim = true;
+                            if (rim != (pass == 1)) continue;
+                        }
+                        int64_t pt = x + (int64_t)full[0] * (y + (int64_t)full[1] * z);
+                        for (int k = 0; k < dofs; k++) perm.push_back((int32_t)(pt * dofs + k));
+                    }
         st.pop_back();
     }
 }
@@ -161,7 +175,7 @@ selinv_status analyze(selinv_plan_s* P, const selinv_geom* geom, const int32_t* 
     } else if (geom && geom->ndim > 0) {
         int32_t d3[3] = {geom->dims[0], geom->ndim > 1 ? geom->dims[1] : 1, geom->ndim > 2 ? geom->dims[2] : 1};
         int dofs = geom->dofs_per_point > 0 ? geom->dofs_per_point : 1;
-        nd_order_box(geom->ndim, d3, dofs, P->perm);
+        nd_order_box(geom->ndim, d3, dofs, P->opts.sep_order, P->perm);
         if ((int64_t)P->perm.size() != n) {
             err = "geometry does not match n";
             return SELINV_EINVAL;

@@ -42,8 +42,8 @@ void compute_layout(selinv_plan_s* P)
         o = align_up(o + std::max<size_t>(bytes, 1));
         return at;
     };
+    // persistent part
     L.lp = take(sizeof(double) * P->arena);
-    L.ap = take(sizeof(double) * P->arena);
     L.hp = take(sizeof(double) * P->harena);
     L.wp = take(sizeof(double) * P->warena);
     L.tp = take(sizeof(double) * P->warena);
@@ -66,9 +66,6 @@ void compute_layout(selinv_plan_s* P)
     L.t_gemm = take(sizeof(Task) * P->t_gemm.tasks.size());
     L.t_sdiag = take(sizeof(Task) * P->t_sdiag.tasks.size());
     L.t_zero = take(sizeof(Task) * P->t_zero.size());
-    L.zb = take(sizeof(double) * P->arena);
-    L.hb = take(sizeof(double) * P->harena);
-    L.tb = take(sizeof(double) * P->warena);
     L.t_rs1 = take(sizeof(Task) * P->t_rs1.tasks.size());
     L.t_rs2 = take(sizeof(Task) * P->t_rs2.tasks.size());
     L.t_rs3 = take(sizeof(Task) * P->t_rs3.tasks.size());
@@ -82,17 +79,28 @@ void compute_layout(selinv_plan_s* P)
     const size_t nb = P->blocks.size(), nl = (size_t)std::max(P->exec.depth, 0);
     L.q_done = take(sizeof(unsigned) * 2 * (nb + nl));
     L.q_head = L.q_done + sizeof(unsigned) * 2 * nb;
-    L.total = o;
-    P->info.workspace_bytes = (int64_t)o;
+    L.ck = take(sizeof(double) * (size_t)P->ck_size);
+    L.ck_off = take(sizeof(int64_t) * P->ck_off.size());
+    L.persist = o;
+    // transient part
+    o = 0;
+    L.ap = take(sizeof(double) * P->arena);
+    L.zb = take(sizeof(double) * P->arena);
+    L.hb = take(sizeof(double) * P->harena);
+    L.tb = take(sizeof(double) * P->warena);
+    L.transient = o;
+    L.total = L.persist + L.transient;
+    P->info.workspace_bytes = (int64_t)L.total;
 }
 
 DevPtrs dev_ptrs(const selinv_plan_s* P)
 {
     const DeviceLayout& L = P->lay;
     char* w = P->ws;
+    char* t = P->tr;  // may be null: then the transient arenas are unusable
     DevPtrs D;
     D.Lp = (double*)(w + L.lp);
-    D.Ap = (double*)(w + L.ap);
+    D.Ap = t ? (double*)(t + L.ap) : nullptr;
     D.Hp = (double*)(w + L.hp);
     D.Wp = (double*)(w + L.wp);
     D.Tp = (double*)(w + L.tp);
@@ -115,9 +123,11 @@ DevPtrs dev_ptrs(const selinv_plan_s* P)
     D.t_gemm = (const Task*)(w + L.t_gemm);
     D.t_sdiag = (const Task*)(w + L.t_sdiag);
     D.t_zero = (const Task*)(w + L.t_zero);
-    D.Zb = (double*)(w + L.zb);
-    D.Hb = (double*)(w + L.hb);
-    D.Tb = (double*)(w + L.tb);
+    D.Zb = t ? (double*)(t + L.zb) : nullptr;
+    D.Hb = t ? (double*)(t + L.hb) : nullptr;
+    D.Tb = t ? (double*)(t + L.tb) : nullptr;
+    D.ck = (double*)(w + L.ck);
+    D.ck_off = (const int64_t*)(w + L.ck_off);
     D.t_rs1 = (const Task*)(w + L.t_rs1);
     D.t_rs2 = (const Task*)(w + L.t_rs2);
     D.t_rs3 = (const Task*)(w + L.t_rs3);
@@ -181,8 +191,11 @@ selinv_status analyze_one(int64_t n, const int64_t* colptr, const int32_t* rowin
 
 selinv_status resolve_opts(const selinv_opts* opts, selinv_opts& o)
 {
-    o = selinv_opts{128, 1, 1, 0};
+    o = selinv_opts{128, 1, 1, 0, 0, 0, 1};
     if (opts) o = *opts;
+    if (o.sep_order != 0 && o.sep_order != 1) return fail(SELINV_EINVAL, "sep_order must be 0 or 1");
+    if (o.deterministic != 0 && o.deterministic != 1) return fail(SELINV_EINVAL, "deterministic must be 0 or 1");
+    if (o.checkpoint_every < 1) o.checkpoint_every = 1;
     if (o.max_super <= 0) o.max_super = 128;
     // execution blocks default to <= 128 columns (the width the register
     // sweep of the diagonal block holds); the L pattern does not depend on
@@ -252,6 +265,67 @@ void drop_graph(selinv_plan_s* P)
     P->graph = nullptr;
     P->graph_in = nullptr;
     P->graph_out = nullptr;
+}
+}  // namespace
+
+namespace {
+// Factor, leaves first: assemble, then per level the small blocks and the
+// tiled path (diagonal blocks, panels, Schur colour groups).
+hipError_t factor_levels(selinv_plan_s* P, const DevPtrs& D, const double* d_valsA, hipStream_t s, Prof* prof)
+{
+    hipError_t e = launch_status_reset(D.status, s);
+    if (!e) e = launch_fill(prof, kAssemble, D.Lp, P->arena, 0.0, s);
+    if (!e) e = launch_scatter_set(prof, kAssemble, d_valsA, D.asm_off, P->nnzA, D.Lp, s);
+    const int depth = P->exec.depth;
+    const int flags = (P->opts.require_spd ? 1 : 0) | (P->opts.deterministic ? 2 : 0);
+    for (int l = depth - 1; l >= 0 && !e; l--) {
+        const auto& q = P->t_sb.off;
+        const auto& a = P->t_ldlt.off;
+        const auto& b = P->t_panel.off;
+        const int64_t diag[4] = {a[l], P->ldlt_cut[2 * l], P->ldlt_cut[2 * l + 1], a[l + 1]};
+        e = launch_sb_factor(prof, D, q[l], q[l + 1] - q[l], P->opts.require_spd, s);
+        const auto& cut = P->schur_cuts[l];
+        if (!e)
+            e = launch_factor_level(prof, D, diag, b[l], b[l + 1] - b[l], cut.data(), (int)cut.size(),
+                                    P->panel_deep[l], flags, s);
+    }
+    return e;
+}
+
+// One level of the inversion: small blocks, gather-GEMM, diagonal step (in
+// two launches where the deterministic mode orders the half-products).
+hipError_t invert_level(selinv_plan_s* P, const DevPtrs& D, int l, hipStream_t s, Prof* prof)
+{
+    const auto& q = P->t_sb.off;
+    const auto& g = P->t_gemm.off;
+    const auto& d = P->t_sdiag.off;
+    hipError_t e = launch_sb_invert(prof, D, q[l], q[l + 1] - q[l], s);
+    if (!e) e = launch_invert_level(prof, D, g[l], g[l + 1] - g[l], d[l], P->sdiag_cut[l], d[l + 1], s);
+    return e;
+}
+
+// Inversion, root first, then the export to the canonical order.
+hipError_t invert_levels(selinv_plan_s* P, const DevPtrs& D, double* d_sel, hipStream_t s, Prof* prof)
+{
+    hipError_t e = launch_zero_x(prof, D, 0, (int64_t)P->t_zero.size(), s);
+    for (int l = 0; l < P->exec.depth && !e; l++) e = invert_level(P, D, l, s, prof);
+    if (!e) e = launch_gather(prof, kExport, D.Ap, D.exp_off, P->colptrL.back(), d_sel, s);
+    return e;
+}
+
+// The inverse panels from the checkpoint store (checkpointed levels) and by
+// recomputation (the other levels, root first, each from its ancestors).
+hipError_t rebuild_inverse(selinv_plan_s* P, const DevPtrs& D, hipStream_t s, Prof* prof)
+{
+    hipError_t e = launch_checkpoint(prof, D, (int64_t)P->t_diag.tasks.size(), 1, s);
+    const int k = P->opts.checkpoint_every;
+    for (int l = 0; l < P->exec.depth && !e; l++) {
+        if (l % k == 0) continue;
+        const int64_t z0 = P->t_zero_off[l], z1 = P->t_zero_off[l + 1];
+        e = launch_zero_x(prof, D, z0, z1 - z0, s);
+        if (!e) e = invert_level(P, D, l, s, prof);
+    }
+    return e;
 }
 }  // namespace
 
@@ -354,16 +428,53 @@ selinv_status selinv_workspace_size(selinv_plan P, size_t* bytes)
     return SELINV_OK;
 }
 
+selinv_status selinv_workspace_sizes(selinv_plan P, size_t* persistent, size_t* transient)
+{
+    if (!P) return fail(SELINV_EINVAL, "NULL plan");
+    if (persistent) *persistent = P->lay.persist;
+    if (transient) *transient = P->lay.transient;
+    return SELINV_OK;
+}
+
+selinv_status selinv_bind_transient(selinv_plan P, void* d_tr, size_t bytes)
+{
+    if (!P) return fail(SELINV_EINVAL, "NULL plan");
+    if (d_tr) {
+        if (bytes < P->lay.transient) return fail(SELINV_ENOMEM, "transient buffer too small");
+        if (((uintptr_t)d_tr & 255) != 0) return fail(SELINV_EINVAL, "transient buffer must be 256-byte aligned");
+    }
+    drop_graph(P);
+    if (d_tr) {
+        P->tr = (char*)d_tr;
+        P->tr_separate = true;
+    } else {
+        P->tr = (P->ws && P->ws_bytes >= P->lay.total) ? P->ws + P->lay.persist : nullptr;
+        P->tr_separate = false;
+    }
+    P->ap_valid = false;
+    return SELINV_OK;
+}
+
+selinv_status selinv_generation(selinv_plan P, uint64_t* gen)
+{
+    if (!P || !gen) return fail(SELINV_EINVAL, "NULL argument");
+    *gen = P->generation;
+    return SELINV_OK;
+}
+
 selinv_status selinv_bind_workspace(selinv_plan P, void* d_ws, size_t bytes, hipStream_t s)
 {
     if (!P || !d_ws) return fail(SELINV_EINVAL, "NULL argument");
-    if (bytes < P->lay.total) return fail(SELINV_ENOMEM, "workspace too small");
+    if (bytes < P->lay.persist) return fail(SELINV_ENOMEM, "workspace too small");
     if (((uintptr_t)d_ws & 255) != 0) return fail(SELINV_EINVAL, "workspace must be 256-byte aligned");
     drop_graph(P);
     P->ws = (char*)d_ws;
     P->ws_bytes = bytes;
+    P->tr = bytes >= P->lay.total ? P->ws + P->lay.persist : nullptr;
+    P->tr_separate = false;
     P->factored = false;
     P->inverted = false;
+    P->ap_valid = false;
     P->queues_on_device = false;
     const DeviceLayout& L = P->lay;
     static hipError_t init = kernels_init();
@@ -413,6 +524,7 @@ selinv_status selinv_bind_workspace(selinv_plan P, void* d_ws, size_t bytes, hip
     if (!e) e = upload(P->ws, L.t_rf2, P->t_rf2.tasks, s);
     if (!e) e = upload(P->ws, L.q_fac, P->q_fac, s);
     if (!e) e = upload(P->ws, L.q_inv, P->q_inv, s);
+    if (!e) e = upload(P->ws, L.ck_off, P->ck_off, s);
     if (!e) e = hipStreamSynchronize(s);
     if (e) {
         P->ws = nullptr;
@@ -427,27 +539,13 @@ selinv_status selinv_factor(selinv_plan P, const double* d_valsA, hipStream_t s)
     if (!P) return fail(SELINV_EINVAL, "NULL plan");
     if (!P->ws) return fail(SELINV_ESTATE, "no workspace bound");
     if (P->nnzA > 0 && !d_valsA) return fail(SELINV_EINVAL, "d_valsA is NULL");
-    DevPtrs D = dev_ptrs(P);
-    // status word := "no failure"; zero the factor arena; assemble A
-    hipError_t e = launch_status_reset(D.status, s);
-    if (!e) e = launch_fill(&P->prof, kAssemble, D.Lp, P->arena, 0.0, s);
-    if (!e) e = launch_scatter_set(&P->prof, kAssemble, d_valsA, D.asm_off, P->nnzA, D.Lp, s);
-    if (e) return hip_fail(e, "factor setup");
-    const int depth = P->exec.depth;
-    for (int l = depth - 1; l >= 0; l--) {
-        const auto& q = P->t_sb.off;
-        const auto& a = P->t_ldlt.off;
-        const auto& b = P->t_panel.off;
-        const int64_t diag[4] = {a[l], P->ldlt_cut[2 * l], P->ldlt_cut[2 * l + 1], a[l + 1]};
-        e = launch_sb_factor(&P->prof, D, q[l], q[l + 1] - q[l], P->opts.require_spd, s);
-        const auto& cut = P->schur_cuts[l];
-        if (!e)
-            e = launch_factor_level(&P->prof, D, diag, b[l], b[l + 1] - b[l], cut.data(), (int)cut.size(),
-                                    P->panel_deep[l], P->opts.require_spd, s);
-        if (e) return hip_fail(e, "factor level launch");
-    }
-    P->factored = true;
+    P->generation++;
+    P->factored = false;
     P->inverted = false;
+    P->ap_valid = false;
+    hipError_t e = factor_levels(P, dev_ptrs(P), d_valsA, s, &P->prof);
+    if (e) return hip_fail(e, "factor launch");
+    P->factored = true;
     return SELINV_OK;
 }
 
@@ -456,20 +554,31 @@ selinv_status selinv_backward(selinv_plan P, const double* d_gsel, double* d_gA,
     if (!P) return fail(SELINV_EINVAL, "NULL plan");
     if (!P->ws) return fail(SELINV_ESTATE, "no workspace bound");
     if (!P->inverted) return fail(SELINV_ESTATE, "backward needs factor and invert of the same values first");
+    if (!P->tr) return fail(SELINV_ESTATE, "no transient memory bound (selinv_bind_transient)");
+    const bool rebuild = P->opts.checkpoint_every > 1;
+    if (!rebuild && !P->ap_valid)
+        return fail(SELINV_ESTATE, "the inverse panels were released and checkpoint_every is 1: invert again");
     if ((P->colptrL.back() > 0 && !d_gsel) || (P->nnzA > 0 && !d_gA)) return fail(SELINV_EINVAL, "NULL buffer");
     for (const BlockDesc& d : P->blocks)
         if (d.s > kLdsDiagMax)
             return fail(SELINV_EUNSUPPORTED, "backward supports execution blocks of at most 128 columns");
     DevPtrs D = dev_ptrs(P);
-    hipError_t e = launch_backward_init(&P->prof, D, P->arena, P->harena, d_gsel, P->colptrL.back(), s);
+    hipError_t e = hipSuccess;
+    // checkpointed levels restored, the others recomputed root first: every
+    // level's gathers read all of its ancestors' panels
+    if (rebuild) e = rebuild_inverse(P, D, s, &P->prof);
+    if (e) return hip_fail(e, "inverse rebuild");
+    P->ap_valid = true;
+    e = launch_backward_init(&P->prof, D, P->arena, P->harena, d_gsel, P->colptrL.back(), s);
     if (e) return hip_fail(e, "backward setup");
     const int depth = P->exec.depth;
     // reverse selected inversion: leaves first
     for (int l = depth - 1; l >= 0; l--) {
         const auto& a = P->t_rs1.off;
         const auto& b = P->t_rs2.off;
-        const auto& c = P->t_rs3.off;
-        e = launch_revsel_level(&P->prof, D, a[l], a[l + 1] - a[l], b[l], b[l + 1] - b[l], c[l], c[l + 1] - c[l], s);
+        const auto& cut = P->rs3_cuts[l];
+        e = launch_revsel_level(&P->prof, D, a[l], a[l + 1] - a[l], b[l], b[l + 1] - b[l], cut.data(), (int)cut.size(),
+                                s);
         if (e) return hip_fail(e, "reverse inversion launch");
     }
     e = launch_revfac_init(&P->prof, D, (int64_t)P->t_diag.tasks.size(), P->arena, s);
@@ -494,22 +603,14 @@ selinv_status selinv_invert(selinv_plan P, double* d_sel, hipStream_t s)
     if (!P) return fail(SELINV_EINVAL, "NULL plan");
     if (!P->ws) return fail(SELINV_ESTATE, "no workspace bound");
     if (!P->factored) return fail(SELINV_ESTATE, "invert called before factor");
+    if (!P->tr) return fail(SELINV_ESTATE, "no transient memory bound (selinv_bind_transient)");
     if (P->colptrL.back() > 0 && !d_sel) return fail(SELINV_EINVAL, "d_sel is NULL");
     DevPtrs D = dev_ptrs(P);
-    hipError_t e = launch_zero_x(&P->prof, D, (int64_t)P->t_zero.size(), s);
-    if (e) return hip_fail(e, "invert setup");
-    const int depth = P->exec.depth;
-    for (int l = 0; l < depth; l++) {
-        const auto& q = P->t_sb.off;
-        const auto& g = P->t_gemm.off;
-        const auto& d = P->t_sdiag.off;
-        e = launch_sb_invert(&P->prof, D, q[l], q[l + 1] - q[l], s);
-        if (!e) e = launch_invert_level(&P->prof, D, g[l], g[l + 1] - g[l], d[l], d[l + 1] - d[l], s);
-        if (e) return hip_fail(e, "invert level launch");
-    }
-    e = launch_gather(&P->prof, kExport, D.Ap, D.exp_off, P->colptrL.back(), d_sel, s);
-    if (e) return hip_fail(e, "export launch");
+    hipError_t e = invert_levels(P, D, d_sel, s, &P->prof);
+    if (!e && P->opts.checkpoint_every > 1) e = launch_checkpoint(&P->prof, D, (int64_t)P->t_diag.tasks.size(), 0, s);
+    if (e) return hip_fail(e, "invert launch");
     P->inverted = true;
+    P->ap_valid = true;
     return SELINV_OK;
 }
 
@@ -643,21 +744,24 @@ selinv_status selinv_get_arena(selinv_plan P, int32_t which, double* d_out, int6
     if (!P) return fail(SELINV_EINVAL, "NULL plan");
     size_t off;
     int64_t n;
+    bool transient = false;
     switch (which) {
         case 0: off = P->lay.lp; n = P->arena; break;
-        case 1: off = P->lay.ap; n = P->arena; break;
+        case 1: off = P->lay.ap; n = P->arena; transient = true; break;
         case 2: off = P->lay.hp; n = P->harena; break;
         case 3: off = P->lay.wp; n = P->warena; break;
         case 4: off = P->lay.tp; n = P->warena; break;
-        case 5: off = P->lay.zb; n = P->arena; break;
-        case 6: off = P->lay.hb; n = P->harena; break;
-        case 7: off = P->lay.tb; n = P->warena; break;
+        case 5: off = P->lay.zb; n = P->arena; transient = true; break;
+        case 6: off = P->lay.hb; n = P->harena; transient = true; break;
+        case 7: off = P->lay.tb; n = P->warena; transient = true; break;
         default: return fail(SELINV_EINVAL, "unknown arena");
     }
     if (count) *count = n;
     if (!d_out || n == 0) return SELINV_OK;
     if (!P->ws) return fail(SELINV_ESTATE, "no workspace bound");
-    hipError_t e = hipMemcpyAsync(d_out, P->ws + off, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
+    char* base = transient ? P->tr : P->ws;
+    if (!base) return fail(SELINV_ESTATE, "no transient memory bound");
+    hipError_t e = hipMemcpyAsync(d_out, base + off, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
     if (e) return hip_fail(e, "get_arena");
     return SELINV_OK;
 }
@@ -729,6 +833,26 @@ selinv_status run_persistent(selinv_plan_s* P, const double* d_valsA, double* d_
     }
     if (!e) e = launch_gather(prof, kExport, D.Ap, D.exp_off, P->colptrL.back(), d_sel, s);
     if (e) return hip_fail(e, "persistent launch");
+    return SELINV_OK;
+}
+
+// What selinv_run launches: the persistent kernels, or in deterministic
+// mode the per-level sequence (no atomics), followed by the checkpoint copy
+// when checkpointing is on.  Kernels only, so it can be captured.
+selinv_status run_sequence(selinv_plan_s* P, const double* d_valsA, double* d_sel, hipStream_t s, Prof* prof)
+{
+    if (!P->opts.deterministic) {
+        if (selinv_status st = run_persistent(P, d_valsA, d_sel, s, prof)) return st;
+    } else {
+        const DevPtrs D = dev_ptrs(P);
+        hipError_t e = factor_levels(P, D, d_valsA, s, prof);
+        if (!e) e = invert_levels(P, D, d_sel, s, prof);
+        if (e) return hip_fail(e, "deterministic run launch");
+    }
+    if (P->opts.checkpoint_every > 1) {
+        hipError_t e = launch_checkpoint(prof, dev_ptrs(P), (int64_t)P->t_diag.tasks.size(), 0, s);
+        if (e) return hip_fail(e, "checkpoint launch");
+    }
     return SELINV_OK;
 }
 
@@ -903,9 +1027,12 @@ selinv_status selinv_run(selinv_plan P, const double* d_valsA, double* d_sel, in
 {
     if (!P) return fail(SELINV_EINVAL, "NULL plan");
     if (!P->ws || !P->queues_on_device) return fail(SELINV_ESTATE, "no workspace bound");
+    if (!P->tr) return fail(SELINV_ESTATE, "no transient memory bound (selinv_bind_transient)");
     if ((P->nnzA > 0 && !d_valsA) || (P->colptrL.back() > 0 && !d_sel)) return fail(SELINV_EINVAL, "NULL buffer");
+    P->generation++;
+    P->factored = P->inverted = P->ap_valid = false;
     if (!use_graph) {
-        if (selinv_status st = run_persistent(P, d_valsA, d_sel, s, &P->prof)) return st;
+        if (selinv_status st = run_sequence(P, d_valsA, d_sel, s, &P->prof)) return st;
     } else {
         if (!P->graph_exec || P->graph_in != (const void*)d_valsA || P->graph_out != (void*)d_sel) {
             drop_graph(P);
@@ -914,7 +1041,7 @@ selinv_status selinv_run(selinv_plan P, const double* d_valsA, double* d_sel, in
             if (e) return hip_fail(e, "capture stream");
             e = hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal);
             if (e) return hip_fail(e, "begin capture");
-            selinv_status st = run_persistent(P, d_valsA, d_sel, P->cap_stream, nullptr);
+            selinv_status st = run_sequence(P, d_valsA, d_sel, P->cap_stream, nullptr);
             hipGraph_t g = nullptr;
             e = hipStreamEndCapture(P->cap_stream, &g);
             if (st != SELINV_OK) {
@@ -936,6 +1063,7 @@ selinv_status selinv_run(selinv_plan P, const double* d_valsA, double* d_sel, in
     }
     P->factored = true;
     P->inverted = true;
+    P->ap_valid = true;
     return SELINV_OK;
 }
 
@@ -944,6 +1072,9 @@ selinv_status selinv_tune(selinv_plan P, const double* d_valsA, double* d_sel, c
 {
     if (!P) return fail(SELINV_EINVAL, "NULL plan");
     if (!P->ws) return fail(SELINV_ESTATE, "no workspace bound");
+    if (!P->tr) return fail(SELINV_ESTATE, "no transient memory bound (selinv_bind_transient)");
+    if (P->opts.deterministic)
+        return fail(SELINV_EUNSUPPORTED, "the deterministic mode runs per-level launches: no schedule to tune");
     const std::string key = tune_key(P);
     selinv_sched best{};
     double ms = 0.0;
@@ -956,11 +1087,10 @@ selinv_status selinv_tune(selinv_plan P, const double* d_valsA, double* d_sel, c
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t he = hipEventCreate(&e0);
     if (!he) he = hipEventCreate(&e1);
-    if (he) return hip_fail(he, "tune events");
-    auto destroy = [&]() {
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-    };
+    if (he) {
+        if (e0) (void)hipEventDestroy(e0);
+        return hip_fail(he, "tune events");
+    }
     const bool prof_was = P->prof.on;
     P->prof.on = false;
     // time one schedule: a warm-up run, then the best of three
@@ -970,8 +1100,9 @@ selinv_status selinv_tune(selinv_plan P, const double* d_valsA, double* d_sel, c
         t = 1e30;
         for (int r = 0; r < 3; r++) {
             hipError_t e = hipEventRecord(e0, s);
-            if (!e && run_persistent(P, d_valsA, d_sel, s, nullptr) != SELINV_OK) return SELINV_EHIP;
-            if (!e) e = hipEventRecord(e1, s);
+            if (e) return hip_fail(e, "tune timing");
+            if (selinv_status st = run_persistent(P, d_valsA, d_sel, s, nullptr)) return st;
+            e = hipEventRecord(e1, s);
             if (!e) e = hipEventSynchronize(e1);
             float dt = 0.f;
             if (!e) e = hipEventElapsedTime(&dt, e0, e1);
@@ -985,6 +1116,7 @@ selinv_status selinv_tune(selinv_plan P, const double* d_valsA, double* d_sel, c
     // order, tile cap, split fill, grid size
     best = selinv_sched{P->sched.order,     P->sched.bn_cap,  P->sched.split_fill,
                         P->sched.grid_mult, P->sched.small_s, P->sched.mb_tiles};
+    const selinv_sched start = best;
     double tbest = 0.0;
     selinv_status st = evaluate(best, tbest);
     for (int dim = 0; dim < 6 && st == SELINV_OK; dim++) {
@@ -1005,9 +1137,18 @@ selinv_status selinv_tune(selinv_plan P, const double* d_valsA, double* d_sel, c
             }
         }
     }
-    destroy();
+    // every exit: events freed, timing flag restored, and the plan left on
+    // the best schedule found (the starting one if none was timed)
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     P->prof.on = prof_was;
-    if (st != SELINV_OK) return st;
+    if (st != SELINV_OK) {
+        const std::string msg = g_err;
+        const selinv_sched keep = tbest > 0.0 ? best : start;
+        (void)selinv_set_schedule(P, &keep, s);
+        g_err = msg;
+        return st;
+    }
     if ((st = selinv_set_schedule(P, &best, s))) return st;
     if (cache_path && !cache_store(cache_path, key, best, tbest))
         return fail(SELINV_EINVAL, std::string("cannot write the tuning cache ") + cache_path);

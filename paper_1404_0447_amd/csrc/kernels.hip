@@ -115,6 +115,26 @@ __global__ __launch_bounds__(kThreads) void k_zero_x(const Task* __restrict__ ta
     zero_task(blk[t.b], Ap, Tp, t.flags & 1, t.kb, t.ke);  // columns [kb, ke)
 }
 
+// Checkpoint copy of whole inverse panels ((s + c) x s, contiguous): dir 0
+// panel -> store, dir 1 store -> panel; blocks without a slot are skipped.
+__global__ __launch_bounds__(kThreads) void k_ck_copy(const Task* __restrict__ tasks,
+                                                      const BlockDesc* __restrict__ blk,
+                                                      const int64_t* __restrict__ ck_off, double* __restrict__ Ap,
+                                                      double* __restrict__ ck, int dir)
+{
+    const int b = tasks[blockIdx.x].b;
+    const int64_t o = ck_off[b];
+    if (o < 0) return;
+    const BlockDesc d = blk[b];
+    const int64_t n = ((int64_t)d.s + d.c) * d.s;
+    double* panel = Ap + d.poff;
+    double* slot = ck + o;
+    for (int64_t i = threadIdx.x; i < n; i += kThreads) {
+        if (dir == 0) slot[i] = panel[i];
+        else panel[i] = slot[i];
+    }
+}
+
 // L on the canonical pattern: diagonal-block entries are stored; an entry in
 // C(B) rows is L(r,j) = sum_{k>=j} L_hat(r,k) L_BB(k,j).  One thread per column.
 __global__ void k_export_L(const BlockDesc* __restrict__ blk, const int32_t* __restrict__ colblk,
@@ -1083,7 +1103,11 @@ __device__ __forceinline__ void sdiag64_task(GemmLds& L, const Task t, const Blo
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int gi = I0 + wm0 + mt * 16 + (lane & 15), gj = J0 + wn0 + nt * 16 + (lane >> 4) + 4 * v;
-                    if (gi < s && gj < s) unsafeAtomicAdd(A + gi + (int64_t)gj * ld, -0.5 * acc[mt][nt][v]);
+                    if (gi < s && gj < s) {
+                        double* a = A + gi + (int64_t)gj * ld;
+                        if (t.flags & 16) *a -= 0.5 * acc[mt][nt][v];  // the only writer of its launch
+                        else unsafeAtomicAdd(a, -0.5 * acc[mt][nt][v]);
+                    }
                 }
         return;
     }
@@ -2215,7 +2239,10 @@ __global__ __launch_bounds__(kThreads) void k_rs3(const Task* __restrict__ tasks
         const int ii = i0 + i, kk = k0c + j;
         if (ii < c && kk < c && ii >= kk) {
             const int64_t pk = d.coff + kk;
-            unsafeAtomicAdd(Zb + cbase[pk] + rel[rbase[pk] + ii], ii == kk ? -0.5 * v : -v);
+            double* z = Zb + cbase[pk] + rel[rbase[pk] + ii];
+            const double u = ii == kk ? -0.5 * v : -v;
+            if (t.flags & 4) *z += u;  // colour group: no other writer in this launch
+            else unsafeAtomicAdd(z, u);
         }
     });
 }
@@ -2475,16 +2502,19 @@ hipError_t launch_backward_init(Prof* P, const DevPtrs& D, int64_t arena, int64_
     return e;
 }
 
-hipError_t launch_revsel_level(Prof* P, const DevPtrs& D, int64_t a0, int64_t na, int64_t b0, int64_t nb, int64_t c0,
-                               int64_t nc, hipStream_t s)
+hipError_t launch_revsel_level(Prof* P, const DevPtrs& D, int64_t a0, int64_t na, int64_t b0, int64_t nb,
+                               const int64_t* rs3_cuts, int ncuts, hipStream_t s)
 {
     if (na > 0) launch(P, kRevSel, k_rs1, dim3((unsigned)na), 0, s, D.t_rs1 + a0, D.blocks, D.Zb, (const double*)D.Hp);
     if (nb > 0)
         launch(P, kRevSel, k_rs2, dim3((unsigned)nb), 0, s, D.t_rs2 + b0, D.blocks, (const double*)D.Ap,
                (const double*)D.Zb, D.Hb, D.cr2, D.rel);
-    if (nc > 0)
-        launch(P, kRevSel, k_rs3, dim3((unsigned)nc), 0, s, D.t_rs3 + c0, D.blocks, D.Zb, (const double*)D.Hp,
-               D.cbase, D.rbase, D.rel);
+    for (int g = 0; g + 1 < ncuts; g++) {
+        const int64_t n = rs3_cuts[g + 1] - rs3_cuts[g];
+        if (n > 0)
+            launch(P, kRevSel, k_rs3, dim3((unsigned)n), 0, s, D.t_rs3 + rs3_cuts[g], D.blocks, D.Zb,
+                   (const double*)D.Hp, D.cbase, D.rbase, D.rel);
+    }
     return hipGetLastError();
 }
 
@@ -2542,10 +2572,17 @@ hipError_t launch_gather(Prof* P, int kind, const double* src, const int64_t* of
     return hipGetLastError();
 }
 
-hipError_t launch_zero_x(Prof* P, const DevPtrs& D, int64_t nblocks, hipStream_t s)
+hipError_t launch_zero_x(Prof* P, const DevPtrs& D, int64_t t0, int64_t n, hipStream_t s)
 {
-    if (nblocks <= 0) return hipSuccess;
-    launch(P, kGemm, k_zero_x, dim3((unsigned)nblocks), 0, s, D.t_zero, D.blocks, D.Ap, (const double*)D.Tp);
+    if (n <= 0) return hipSuccess;
+    launch(P, kGemm, k_zero_x, dim3((unsigned)n), 0, s, D.t_zero + t0, D.blocks, D.Ap, (const double*)D.Tp);
+    return hipGetLastError();
+}
+
+hipError_t launch_checkpoint(Prof* P, const DevPtrs& D, int64_t ntasks, int dir, hipStream_t s)
+{
+    if (ntasks <= 0) return hipSuccess;
+    launch(P, kCheckpoint, k_ck_copy, dim3((unsigned)ntasks), 0, s, D.t_diag, D.blocks, D.ck_off, D.Ap, D.ck, dir);
     return hipGetLastError();
 }
 
@@ -2574,8 +2611,10 @@ hipError_t launch_sb_invert(Prof* P, const DevPtrs& D, int64_t sb0, int64_t nsb,
 }
 
 hipError_t launch_factor_level(Prof* P, const DevPtrs& D, const int64_t diag[4], int64_t panel0, int64_t npanel,
-                               const int64_t* schur_cuts, int ncuts, int panel_deep, int require_spd, hipStream_t s)
+                               const int64_t* schur_cuts, int ncuts, int panel_deep, int flags, hipStream_t s)
 {
+    const int require_spd = flags & 1;
+    if (flags & 2) panel_deep = 0;  // deterministic: one kernel per kind, whatever the level's size
     // diagonal blocks by width class: [diag[0], diag[1]) s <= 32, then <= 64,
     // then wider
     if (diag[1] > diag[0])
@@ -2603,14 +2642,17 @@ hipError_t launch_factor_level(Prof* P, const DevPtrs& D, const int64_t diag[4],
 }
 
 hipError_t launch_invert_level(Prof* P, const DevPtrs& D, int64_t gemm0, int64_t ngemm, int64_t sdiag0,
-                               int64_t nsdiag, hipStream_t s)
+                               int64_t sdiag_cut, int64_t sdiag1, hipStream_t s)
 {
     if (ngemm > 0)
         launch(P, kGemm, k_gemm, dim3((unsigned)ngemm), 0, s, D.t_gemm + gemm0, D.blocks, D.Ap,
                (const double*)D.Hp, D.cr2, D.rel);
-    if (nsdiag > 0)
-        launch(P, kSdiag, k_sdiag64, dim3((unsigned)nsdiag), 0, s, D.t_sdiag + sdiag0, D.blocks, D.Ap,
+    if (sdiag_cut > sdiag0)
+        launch(P, kSdiag, k_sdiag64, dim3((unsigned)(sdiag_cut - sdiag0)), 0, s, D.t_sdiag + sdiag0, D.blocks, D.Ap,
                (const double*)D.Hp, (const double*)D.Tp);
+    if (sdiag1 > sdiag_cut)
+        launch(P, kSdiag, k_sdiag64, dim3((unsigned)(sdiag1 - sdiag_cut)), 0, s, D.t_sdiag + sdiag_cut, D.blocks,
+               D.Ap, (const double*)D.Hp, (const double*)D.Tp);
     return hipGetLastError();
 }
 

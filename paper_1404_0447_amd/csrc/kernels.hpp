@@ -24,17 +24,25 @@ struct DevPtrs {
     const int64_t* colptrL;    // canonical column pointers of L
     const Task *t_diag, *t_ldlt, *t_panel, *t_schur, *t_gemm, *t_sdiag, *t_zero, *t_sb;
     const Task *t_rs1, *t_rs2, *t_rs3, *t_rf1a, *t_rf1b, *t_rf2;
+    double* ck;             // checkpoint store of inverse panels
+    const int64_t* ck_off;  // per block: its offset in the store (-1: not stored)
 };
 
 hipError_t kernels_init();
 hipError_t launch_backward_init(Prof* P, const DevPtrs& D, int64_t arena, int64_t harena, const double* gsel,
                                 int64_t nnzL, hipStream_t s);
-hipError_t launch_revsel_level(Prof* P, const DevPtrs& D, int64_t a0, int64_t na, int64_t b0, int64_t nb, int64_t c0,
-                               int64_t nc, hipStream_t s);
+// rs3_cuts[0..ncuts): the level's t_rs3 tasks in groups launched one after
+// the other (colour groups of disjoint scatters in the deterministic mode)
+hipError_t launch_revsel_level(Prof* P, const DevPtrs& D, int64_t a0, int64_t na, int64_t b0, int64_t nb,
+                               const int64_t* rs3_cuts, int ncuts, hipStream_t s);
 hipError_t launch_revfac_init(Prof* P, const DevPtrs& D, int64_t nblocks, int64_t arena, hipStream_t s);
 hipError_t launch_revfac_level(Prof* P, const DevPtrs& D, int64_t a0, int64_t na, int64_t b0, int64_t nb, int64_t c0,
                                int64_t nc, int64_t d0, int64_t nd, hipStream_t s);
-hipError_t launch_zero_x(Prof* P, const DevPtrs& D, int64_t nblocks, hipStream_t s);
+// set-up of the inversion: tasks t_zero[t0 .. t0+n)
+hipError_t launch_zero_x(Prof* P, const DevPtrs& D, int64_t t0, int64_t n, hipStream_t s);
+// inverse panels of the blocks listed by t_diag[0 .. ntasks) that have a
+// checkpoint slot: dir 0 copies them to the store, dir 1 back
+hipError_t launch_checkpoint(Prof* P, const DevPtrs& D, int64_t ntasks, int dir, hipStream_t s);
 hipError_t launch_export_L(Prof* P, const DevPtrs& D, int64_t n, double* out, hipStream_t s);
 hipError_t launch_status_reset(unsigned long long* status, hipStream_t s);
 hipError_t launch_fill(Prof* P, int kind, double* p, int64_t n, double v, hipStream_t s);
@@ -42,11 +50,15 @@ hipError_t launch_scatter_set(Prof* P, int kind, const double* src, const int64_
                               hipStream_t s);
 hipError_t launch_gather(Prof* P, int kind, const double* src, const int64_t* off, int64_t n, double* dst,
                          hipStream_t s);
-// diag[0..3]: the level's diagonal-block tasks for s <= 32, <= 64 and wider
+// diag[0..3]: the level's diagonal-block tasks for s <= 32, <= 64 and wider;
+// flags bit 0 require_spd, bit 1 deterministic (the tiled kernels only, no
+// whole-contraction variants)
 hipError_t launch_factor_level(Prof* P, const DevPtrs& D, const int64_t diag[4], int64_t panel0, int64_t npanel,
-                               const int64_t* schur_cuts, int ncuts, int panel_deep, int require_spd, hipStream_t s);
+                               const int64_t* schur_cuts, int ncuts, int panel_deep, int flags, hipStream_t s);
+// diagonal-step tasks t_sdiag[sdiag0 .. sdiag_cut) then [sdiag_cut .. sdiag1),
+// as two launches
 hipError_t launch_invert_level(Prof* P, const DevPtrs& D, int64_t gemm0, int64_t ngemm, int64_t sdiag0,
-                               int64_t nsdiag, hipStream_t s);
+                               int64_t sdiag_cut, int64_t sdiag1, hipStream_t s);
 // persistent work-queue kernels: resident work-groups per CU, and one
 // level's launch over ntasks queue entries at q
 hipError_t persist_occupancy(int occ[kNumVariants]);

@@ -86,7 +86,7 @@ enum PersistVariant {
 // Kernel kinds (same numbering as SELINV_K_* in selinv.h).
 enum Kind {
     kAssemble = 0, kLdlt, kPanel, kSchur, kGemm, kSdiag, kExport, kRevSel, kRevFac, kQFactor, kQInvert, kSbFactor,
-    kSbInvert, kNumKinds
+    kSbInvert, kCheckpoint, kNumKinds
 };
 
 // Optional per-launch timing: start/stop events are stamped by the dispatch
@@ -100,14 +100,23 @@ struct Prof {
     ~Prof();
 };
 
+// The workspace has a persistent part (the factor, the index maps, the task
+// lists and the checkpoint store: what must survive from the forward calls
+// to selinv_backward) and a transient part (the inverse panels and the
+// adjoint arenas), which may live in a separate buffer that the caller binds
+// and releases (selinv_bind_transient).
 struct DeviceLayout {
-    // byte offsets into the workspace
-    size_t lp, ap, hp, wp, tp, status, blocks, crow, cbase, rbase, cr2, rel, asm_off, exp_off, colblk, colptrL;
+    // byte offsets into the persistent part
+    size_t lp, hp, wp, tp, status, blocks, crow, cbase, rbase, cr2, rel, asm_off, exp_off, colblk, colptrL;
     size_t t_diag, t_ldlt, t_panel, t_schur, t_gemm, t_sdiag, t_zero, t_sb;
-    size_t zb, hb, tb;  // adjoint arenas (backward)
     size_t t_rs1, t_rs2, t_rs3, t_rf1a, t_rf1b, t_rf2;
     size_t q_fac, q_inv, q_done, q_head;  // persistent path: queues, counters
-    size_t total;
+    size_t ck, ck_off;                    // checkpoint store (Ainv panels of checkpointed levels), its offsets
+    size_t persist;                       // bytes of the persistent part
+    // byte offsets into the transient part
+    size_t ap, zb, hb, tb;  // inverse panels; adjoint arenas (backward)
+    size_t transient;       // bytes of the transient part
+    size_t total;           // persistent + transient (one buffer holding both)
 };
 
 }  // namespace selinv
@@ -146,7 +155,20 @@ struct selinv_plan_s {
     std::vector<char> panel_deep;
     // reverse sweep: selected inversion (leaves first) and factorization (root first)
     selinv::LevelTasks t_rs1, t_rs2, t_rs3, t_rf1a, t_rf1b, t_rf2;
-    std::vector<selinv::Task> t_zero;  // column ranges [kb, ke) of blocks whose X or Ainv(B,B) accumulates
+    // per level: t_rs3 in colour groups (deterministic mode; otherwise one group)
+    std::vector<std::vector<int64_t>> rs3_cuts;
+    // per level: t_sdiag splits into [start, cut) and [cut, end) launches
+    // (deterministic mode: the second half-products of off-diagonal tiles
+    // run after the first; otherwise cut = end)
+    std::vector<int64_t> sdiag_cut;
+    // column ranges [kb, ke) of blocks whose X or Ainv(B,B) accumulates, in
+    // level order; level l owns t_zero[t_zero_off[l] .. t_zero_off[l+1])
+    std::vector<selinv::Task> t_zero;
+    std::vector<int64_t> t_zero_off;
+    // checkpointing of the inverse panels for the adjoint: per block the
+    // offset (doubles) of its copy in the store, -1 if its level is dropped
+    std::vector<int64_t> ck_off;
+    int64_t ck_size = 0;
     selinv::DeviceLayout lay{};
     selinv_info info{};
     // batch (block-diagonal union of independent matrices): per-matrix
@@ -172,10 +194,14 @@ struct selinv_plan_s {
     std::string dev_arch;
     unsigned spin_limit = 1u << 22;         // polls of a dependency wait before it is abandoned
     // binding state
-    char* ws = nullptr;
+    char* ws = nullptr;        // persistent part (and, when large enough, the transient part after it)
     size_t ws_bytes = 0;
+    char* tr = nullptr;        // transient part in use (nullptr: none bound)
+    bool tr_separate = false;  // bound with selinv_bind_transient
     bool factored = false;
     bool inverted = false;
+    bool ap_valid = false;     // the inverse panels hold the last inversion's values
+    uint64_t generation = 0;   // factorizations so far (selinv_factor, selinv_run)
     selinv::Prof prof;
     std::vector<double> work_flops, work_bytes;  // per kernel kind, per call
     ~selinv_plan_s();
@@ -185,7 +211,7 @@ namespace selinv {
 // analyze.cpp
 selinv_status analyze(selinv_plan_s* P, const selinv_geom* geom, const int32_t* perm_or_null,
                       std::string& err);
-void nd_order_box(int ndim, const int32_t dims[3], int dofs, std::vector<int32_t>& perm);
+void nd_order_box(int ndim, const int32_t dims[3], int dofs, int rim_last, std::vector<int32_t>& perm);
 void block_index_maps(const Partition& part, std::vector<int64_t>& rptr, std::vector<int32_t>& rel);
 // schedule.cpp
 void build_schedule(selinv_plan_s* P);

@@ -149,6 +149,55 @@ static void schur_colours(const selinv_plan_s* P, std::vector<Task>& tasks, int6
     cuts.push_back((int64_t)tasks.size());
 }
 
+// Colours for the blocks `bl` of one level with no limit on their number
+// (deterministic mode): blocks sharing a column of C get different colours;
+// greedy passes, colour k taking every still uncoloured block (largest
+// update first) whose columns no block of colour k has claimed.
+static std::unordered_map<int, int> colour_unbounded(const selinv_plan_s* P, const std::vector<int>& bl,
+                                                     std::vector<int32_t>& stamp)
+{
+    const std::vector<int32_t>& cr = P->crow;
+    std::vector<int> order = bl;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const BlockDesc &x = P->blocks[a], &y = P->blocks[b];
+        return (double)x.c * x.c * x.s > (double)y.c * y.c * y.s;
+    });
+    std::unordered_map<int, int> col;
+    size_t left = order.size();
+    for (int k = 0; left > 0; k++) {
+        for (int B : order) {
+            if (col.count(B)) continue;
+            const BlockDesc& d = P->blocks[B];
+            bool ok = true;
+            for (int r = 0; r < d.c && ok; r++) ok = stamp[cr[d.coff + r]] != k;
+            if (!ok) continue;
+            col[B] = k;
+            for (int r = 0; r < d.c; r++) stamp[cr[d.coff + r]] = k;
+            left--;
+        }
+    }
+    for (int B : bl) {
+        const BlockDesc& d = P->blocks[B];
+        for (int r = 0; r < d.c; r++) stamp[cr[d.coff + r]] = -1;
+    }
+    return col;
+}
+
+// Tasks [t0, end) of one level grouped by the colour of their block (stable
+// within a colour), flags |= `bit` on every task, cuts = group boundaries.
+static void group_by_colour(std::vector<Task>& tasks, int64_t t0, const std::unordered_map<int, int>& col, int bit,
+                            std::vector<int64_t>& cuts)
+{
+    std::stable_sort(tasks.begin() + t0, tasks.end(),
+                     [&](const Task& a, const Task& b) { return col.at(a.b) < col.at(b.b); });
+    cuts.assign(1, t0);
+    for (int64_t t = t0; t < (int64_t)tasks.size(); t++) {
+        tasks[t].flags |= bit;
+        if (t > t0 && col.at(tasks[t].b) != col.at(tasks[t - 1].b)) cuts.push_back(t);
+    }
+    cuts.push_back((int64_t)tasks.size());
+}
+
 // Blocks of one level whose Schur updates no other block of the level
 // touches: two blocks update a common ancestor entry exactly when their row
 // structures C share a column (the diagonal entry of that column), so a
@@ -197,11 +246,18 @@ void build_schedule(selinv_plan_s* P)
         t->off.assign(D + 1, 0);
     }
     P->t_zero.clear();
+    P->t_zero_off.assign(D + 1, 0);
     P->ldlt_cut.assign(2 * D, 0);
     P->schur_cuts.assign(D, {});
+    P->rs3_cuts.assign(D, {});
+    P->sdiag_cut.assign(D, 0);
     P->panel_deep.assign(D, 0);
+    // deterministic mode: no small-block kernels (their Schur updates use
+    // atomics), no split contractions, no whole-contraction kernel variants
+    const bool det = P->opts.deterministic != 0;
+    auto small_block = [&](int s, int c) { return !det && is_small_level(s, c); };
     std::vector<uint64_t> colour_mask((size_t)P->n, 0);
-    std::vector<int32_t> touch((size_t)P->n, 0);
+    std::vector<int32_t> touch((size_t)P->n, 0), stamp((size_t)P->n, -1);
     std::vector<char> excl(P->blocks.size(), 0);
     for (int l = 0; l < D; l++) {
         exclusive_blocks(P, lv[l], touch, excl);
@@ -215,7 +271,7 @@ void build_schedule(selinv_plan_s* P)
             const int nd = (d.s + kDiagTile - 1) / kDiagTile;
             rbase_ += tiles;
             rdbase += nd * (nd + 1) / 2;
-            if (is_small_level(d.s, d.c)) {
+            if (small_block(d.s, d.c)) {
                 small.push_back(B);
                 continue;
             }
@@ -228,18 +284,18 @@ void build_schedule(selinv_plan_s* P)
         std::vector<TileGroup> gg, dg;
         for (int B : lv[l]) {
             const BlockDesc& d = P->blocks[B];
-            if (is_small_level(d.s, d.c) || d.c == 0) continue;
+            if (small_block(d.s, d.c) || d.c == 0) continue;
             const int bn = tile_bn(d.s), nd = (d.s + kDiagTile64 - 1) / kDiagTile64;
             gg.push_back({(int64_t)((d.c + kTileM - 1) / kTileM) * ((d.s + bn - 1) / bn), d.c, bn});
             // one 64 x 64 product per task: nd diagonal tiles, two halves per
             // off-diagonal tile
             dg.push_back({(int64_t)nd * nd, d.c, kDiagTile64});
         }
-        const int64_t want = best_split(gg, kGemmSlots, kGemmTaskOvh, 64);
+        const int64_t want = det ? 1 : best_split(gg, kGemmSlots, kGemmTaskOvh, 64);
         // a block has only nd (nd + 1) / 2 diagonal pairs: their contraction
         // may be cut finer to fill the device
-        const int64_t dwant = best_split(dg, kGemmSlots, kSdiagTaskOvh, 64, kMinSplitKDiag);
-        const int64_t rwant = fill_for(rbase_), rdwant = fill_for(rdbase);
+        const int64_t dwant = det ? 1 : best_split(dg, kGemmSlots, kSdiagTaskOvh, 64, kMinSplitKDiag);
+        const int64_t rwant = det ? 1 : fill_for(rbase_), rdwant = det ? 1 : fill_for(rdbase);
         (void)base;
         (void)dbase;
         // few panel tiles: at most 64 wide each, for the whole-contraction kernel
@@ -247,14 +303,14 @@ void build_schedule(selinv_plan_s* P)
         int smax = 0;
         for (int B : lv[l]) {
             const BlockDesc& d = P->blocks[B];
-            if (is_small_level(d.s, d.c)) continue;
+            if (small_block(d.s, d.c)) continue;
             const int pbn = std::min(tile_bn(d.s), 64);
             npanel64 += (int64_t)((d.c + kTileM - 1) / kTileM) * ((d.s + pbn - 1) / pbn);
             smax = std::max(smax, d.s);
         }
         // the whole-contraction kernels hold a contraction of at most kDeepK
         // (blocks wider than 128 columns exist only with exec_cap > 128)
-        const bool deep_ok = smax <= kDeepK;
+        const bool deep_ok = !det && smax <= kDeepK;
         const bool deep = deep_ok && npanel64 <= kDeepMaxTiles;
         P->panel_deep[l] = (char)((deep ? 1 : 0) | (deep_ok ? 2 : 0));
         for (int B : lv[l]) {
@@ -293,7 +349,7 @@ void build_schedule(selinv_plan_s* P)
                 }
             for (int k = 0; k < c; k += kSchurTile)
                 for (int i = k; i < c; i += kSchurTile) P->t_rs3.tasks.push_back({B, i, k, kSchurTile, 0, 2 * s, 0, 0});
-            if (is_small_level(s, c)) continue;
+            if (small_block(s, c)) continue;
             // forward, tiled path
             // contractions over C are split into pieces of >= kMinSplitK rows
             // when a level has too few tiles to fill the device
@@ -308,12 +364,14 @@ void build_schedule(selinv_plan_s* P)
             if (split > 1 || acc)
                 for (int j = 0; j < s; j += kZeroCols)
                     P->t_zero.push_back({B, 0, 0, 0, j, std::min(s, j + kZeroCols), split > 1, 0});
+            // deterministic: the half-products add with plain read-modify-write
+            // (flags bit 4), the second halves in a launch of their own
             for (int I = 0; I < nd64; I++)
                 for (int J = 0; J <= I; J++)
                     for (int half = 0; half < (I == J ? 1 : 2); half++)
                         pieces(0, c, dsplit, [&](int kb, int ke, int) {
-                            P->t_sdiag.tasks.push_back(
-                                {B, I * kDiagTile64, J * kDiagTile64, 0, kb, ke, (int)acc | (half << 3), 0});
+                            P->t_sdiag.tasks.push_back({B, I * kDiagTile64, J * kDiagTile64, 0, kb, ke,
+                                                        (int)acc | (half << 3) | (det && I != J ? 16 : 0), 0});
                         });
             for (int j = 0; j < s; j += pbn)
                 for (int r = 0; r < c; r += kTileM) P->t_panel.tasks.push_back({B, r, j, pbn, 0, s, 0, 0});
@@ -327,13 +385,28 @@ void build_schedule(selinv_plan_s* P)
                 for (int i = k; i < c; i += kSchurTile)
                     P->t_schur.tasks.push_back({B, i, k, kSchurTile, 0, s, excl[B] ? 4 : 0, 0});
         }
-        schur_colours(P, P->t_schur.tasks, P->t_schur.off[l], colour_mask, P->schur_cuts[l]);
+        if (det) {
+            // every Schur update and adjoint scatter in colour groups, however many
+            const auto col = colour_unbounded(P, lv[l], stamp);
+            group_by_colour(P->t_schur.tasks, P->t_schur.off[l], col, 4, P->schur_cuts[l]);
+            group_by_colour(P->t_rs3.tasks, P->t_rs3.off[l], col, 4, P->rs3_cuts[l]);
+            std::stable_partition(P->t_sdiag.tasks.begin() + P->t_sdiag.off[l], P->t_sdiag.tasks.end(),
+                                  [](const Task& t) { return (t.flags & 8) == 0; });
+            P->sdiag_cut[l] = P->t_sdiag.off[l] +
+                              std::count_if(P->t_sdiag.tasks.begin() + P->t_sdiag.off[l], P->t_sdiag.tasks.end(),
+                                            [](const Task& t) { return (t.flags & 8) == 0; });
+        } else {
+            schur_colours(P, P->t_schur.tasks, P->t_schur.off[l], colour_mask, P->schur_cuts[l]);
+            P->rs3_cuts[l] = {P->t_rs3.off[l], (int64_t)P->t_rs3.tasks.size()};
+            P->sdiag_cut[l] = (int64_t)P->t_sdiag.tasks.size();
+        }
+        P->t_zero_off[l + 1] = (int64_t)P->t_zero.size();
         // diagonal blocks of the tiled path by width class (one launch each)
         const int64_t cls[] = {32, 64, 1 << 30};
         for (int k = 0; k < 3; k++) {
             for (int B : lv[l]) {
                 const BlockDesc& d = P->blocks[B];
-                if (is_small_level(d.s, d.c) || d.s > cls[k] || (k > 0 && d.s <= cls[k - 1])) continue;
+                if (small_block(d.s, d.c) || d.s > cls[k] || (k > 0 && d.s <= cls[k - 1])) continue;
                 P->t_ldlt.tasks.push_back({B, 0, 0, 0, 0, 0, 0, 0});
             }
             if (k < 2) P->ldlt_cut[2 * l + k] = (int64_t)P->t_ldlt.tasks.size();
@@ -350,7 +423,7 @@ void build_schedule(selinv_plan_s* P)
                              8.0 * (c * (c + 1) / 2 + 2 * c * s), 8.0 * (2 * c * s + 2 * s * s)};
         // sweep: s pivots x s^2 updates; L_hat = F(C,B) T; lower half of
         // L_hat F^T; X = -G L_hat; Y = T - L_hat^T X
-        if (is_small_level(d.s, d.c)) {
+        if (small_block(d.s, d.c)) {
             P->work_flops[kSbFactor] += fl[0] + fl[1] + fl[2];
             P->work_bytes[kSbFactor] += by[0] + by[1] + by[2];
             P->work_flops[kSbInvert] += fl[3] + fl[4];
@@ -378,6 +451,18 @@ void build_schedule(selinv_plan_s* P)
     const double nnzL = (double)P->colptrL.back(), nnzA = (double)P->nnzA;
     P->work_bytes[kAssemble] = 8.0 * P->arena + 24.0 * nnzA;
     P->work_bytes[kExport] = 24.0 * nnzL;
+    // checkpoint slots: whole inverse panels of levels 1, 1 + k, 1 + 2k, ...
+    const int k = std::max(1, (int)P->opts.checkpoint_every);
+    P->ck_off.assign(P->blocks.size(), -1);
+    P->ck_size = 0;
+    if (k > 1)
+        for (size_t B = 0; B < P->blocks.size(); B++) {
+            const BlockDesc& d = P->blocks[B];
+            if ((d.level - 1) % k != 0) continue;
+            P->ck_off[B] = P->ck_size;
+            P->ck_size += ((int64_t)d.s + d.c) * d.s;
+        }
+    P->work_bytes[kCheckpoint] = 16.0 * (double)P->ck_size;
 }
 
 // ---------------------------------------------------------------------------

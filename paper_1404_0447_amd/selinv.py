@@ -20,17 +20,17 @@ _NAMES = {0: "OK", -1: "EINVAL", -2: "ESTATE", -3: "EPIVOT", -4: "ENOMEM", -5: "
           -7: "EQUEUE"}
 
 # every symbol include/selinv.h declares
-EXPORTS = ["selinv_analyze", "selinv_workspace_size", "selinv_bind_workspace", "selinv_factor", "selinv_invert",
-           "selinv_backward",
+EXPORTS = ["selinv_analyze", "selinv_workspace_size", "selinv_workspace_sizes", "selinv_bind_workspace",
+           "selinv_bind_transient", "selinv_generation", "selinv_factor", "selinv_invert", "selinv_backward",
            "selinv_get_factor", "selinv_sync_status", "selinv_get_info", "selinv_get_pattern",
            "selinv_symbolic_sizes", "selinv_get_symbolic", "selinv_profile", "selinv_profile_read",
            "selinv_kernel_work", "selinv_get_arena", "selinv_get_blocks", "selinv_get_exec_rows",
            "selinv_analyze_batch", "selinv_batch_offsets", "selinv_set_schedule", "selinv_get_schedule",
-           "selinv_get_queue", "selinv_set_spin_limit", "selinv_run", "selinv_tune",
+           "selinv_get_queue", "selinv_set_spin_limit", "selinv_run", "selinv_tune", "selinv_measure_peaks",
            "selinv_last_error", "selinv_destroy"]
 ARENAS = {"L": 0, "Ainv": 1, "Lhat": 2, "W": 3, "T": 4, "Fbar": 5, "Lhat_bar": 6, "T_bar": 7}
 KINDS = ["assemble", "ldlt", "panel", "schur", "gemm", "sdiag", "export", "revsel", "revfac", "qfactor", "qinvert",
-         "sbfactor", "sbinvert"]
+         "sbfactor", "sbinvert", "checkpoint"]
 QOPS = ["ldlt", "panel", "schur", "zero", "gemm", "sdiag", "sbfactor", "sbinvert", "mbfactor", "mbinvert"]
 ORDERS = ["plan", "lpt", "round_robin", "tile_lpt"]
 
@@ -48,7 +48,14 @@ class Geom(ct.Structure):
 
 class Opts(ct.Structure):
     _fields_ = [("max_super", ct.c_int32), ("fuse_chains", ct.c_int32), ("require_spd", ct.c_int32),
-                ("exec_cap", ct.c_int32)]
+                ("exec_cap", ct.c_int32), ("sep_order", ct.c_int32), ("deterministic", ct.c_int32),
+                ("checkpoint_every", ct.c_int32)]
+
+
+def _opts(max_super, fuse_chains, require_spd, exec_cap, sep_order, deterministic, checkpoint_every):
+    so = {"lex": 0, "rim_last": 1}.get(sep_order, sep_order)
+    return Opts(int(max_super), int(bool(fuse_chains)), int(bool(require_spd)), int(exec_cap), int(so),
+                int(bool(deterministic)), int(checkpoint_every))
 
 
 class Sched(ct.Structure):
@@ -78,7 +85,10 @@ def lib():
         vp, i64, i32 = ct.c_void_p, ct.c_int64, ct.c_int32
         L.selinv_analyze.argtypes = [i64, vp, vp, vp, vp, vp, ct.POINTER(vp)]
         L.selinv_workspace_size.argtypes = [vp, ct.POINTER(ct.c_size_t)]
+        L.selinv_workspace_sizes.argtypes = [vp, ct.POINTER(ct.c_size_t), ct.POINTER(ct.c_size_t)]
         L.selinv_bind_workspace.argtypes = [vp, vp, ct.c_size_t, vp]
+        L.selinv_bind_transient.argtypes = [vp, vp, ct.c_size_t]
+        L.selinv_generation.argtypes = [vp, ct.POINTER(ct.c_uint64)]
         L.selinv_factor.argtypes = [vp, vp, vp]
         L.selinv_invert.argtypes = [vp, vp, vp]
         L.selinv_get_factor.argtypes = [vp, vp, vp]
@@ -102,6 +112,7 @@ def lib():
         L.selinv_set_spin_limit.argtypes = [vp, ct.c_uint32]
         L.selinv_run.argtypes = [vp, vp, vp, i32, vp]
         L.selinv_tune.argtypes = [vp, vp, vp, ct.c_char_p, ct.POINTER(Sched), ct.POINTER(ct.c_double), vp]
+        L.selinv_measure_peaks.argtypes = [vp, ct.c_size_t, ct.POINTER(ct.c_double), ct.POINTER(ct.c_double), vp]
         L.selinv_last_error.restype = ct.c_char_p
         L.selinv_destroy.argtypes = [vp]
         for f in EXPORTS:
@@ -132,10 +143,12 @@ class Plan:
     """Symbolic analysis + bound device workspace for one sparsity pattern."""
 
     def __init__(self, n, colptr, rowind, geom=None, perm=None, max_super=128, fuse_chains=True,
-                 require_spd=True, exec_cap=0, _handle=None):
+                 require_spd=True, exec_cap=0, sep_order=0, deterministic=False, checkpoint_every=1,
+                 _handle=None):
         L = lib()
         self.n = int(n)
         if _handle is not None:
+            self.checkpoint_every, self.deterministic = 1, False  # set by the caller (batch)
             self._adopt(_handle)
             return
         self._colptr = np.ascontiguousarray(colptr, dtype=np.int64)
@@ -146,7 +159,9 @@ class Plan:
             d3 = list(dims) + [1] * (3 - len(dims))
             g = Geom(int(ndim), (ct.c_int32 * 3)(*[int(x) for x in d3[:3]]), int(dofs))
         pm = None if perm is None else np.ascontiguousarray(perm, dtype=np.int32)
-        o = Opts(int(max_super), int(bool(fuse_chains)), int(bool(require_spd)), int(exec_cap))
+        o = _opts(max_super, fuse_chains, require_spd, exec_cap, sep_order, deterministic, checkpoint_every)
+        self.checkpoint_every = max(1, int(checkpoint_every))
+        self.deterministic = bool(deterministic)
         h = ct.c_void_p()
         st = L.selinv_analyze(self.n, _p(self._colptr), _p(self._rowind), ct.byref(g) if g is not None else None,
                               _p(pm), ct.byref(o), ct.byref(h))
@@ -157,7 +172,11 @@ class Plan:
         L = lib()
         self._h = h
         self._ws = None
+        self._tr = None
         self._bound = False
+        pb, tb = ct.c_size_t(), ct.c_size_t()
+        _check(L.selinv_workspace_sizes(self._h, ct.byref(pb), ct.byref(tb)))
+        self.persistent_bytes, self.transient_bytes = int(pb.value), int(tb.value)
         inf = Info()
         _check(L.selinv_get_info(self._h, ct.byref(inf)))
         self.info = {k: getattr(inf, k) for k, _ in Info._fields_}
@@ -169,7 +188,8 @@ class Plan:
         self.n_off, self.nnzA_off, self.nnzL_off = offs
 
     @classmethod
-    def batch(cls, matrices, max_super=128, fuse_chains=True, require_spd=True, exec_cap=0):
+    def batch(cls, matrices, max_super=128, fuse_chains=True, require_spd=True, exec_cap=0, sep_order=0,
+              deterministic=False, checkpoint_every=1):
         """One plan for a list of independent workloads.Matrix (their
         block-diagonal union); values and results concatenate in list order."""
         L = lib()
@@ -183,11 +203,13 @@ class Plan:
         for i, m in enumerate(matrices):
             d3 = list(m.dims) + [1] * (3 - len(m.dims))
             geoms[i] = Geom(int(m.ndim), (ct.c_int32 * 3)(*[int(x) for x in d3[:3]]), int(m.dofs))
-        o = Opts(int(max_super), int(bool(fuse_chains)), int(bool(require_spd)), int(exec_cap))
+        o = _opts(max_super, fuse_chains, require_spd, exec_cap, sep_order, deterministic, checkpoint_every)
         h = ct.c_void_p()
         st = L.selinv_analyze_batch(cnt, _p(ns), cp_arr, ri_arr, geoms, ct.byref(o), ct.byref(h))
         _check(st)
-        return cls(int(ns.sum()), None, None, _handle=h)
+        p = cls(int(ns.sum()), None, None, _handle=h)
+        p.checkpoint_every, p.deterministic = max(1, int(checkpoint_every)), bool(deterministic)
+        return p
 
     @classmethod
     def from_matrix(cls, m, **kw):
@@ -224,14 +246,38 @@ class Plan:
 
     # ------------------------------------------------------------ device calls
     def bind(self, device="cuda", stream=None):
+        """Allocate and bind the persistent workspace and a separate transient
+        buffer (released with release_transient, re-allocated on demand)."""
         import torch
-        nb = ct.c_size_t()
-        _check(lib().selinv_workspace_size(self._h, ct.byref(nb)))
-        self._ws = torch.empty(int(nb.value), dtype=torch.uint8, device=device)
-        _check(lib().selinv_bind_workspace(self._h, ct.c_void_p(self._ws.data_ptr()), int(nb.value),
+        self._ws = torch.empty(max(self.persistent_bytes, 1), dtype=torch.uint8, device=device)
+        _check(lib().selinv_bind_workspace(self._h, ct.c_void_p(self._ws.data_ptr()), self.persistent_bytes,
                                            _stream(stream)))
         self._bound = True
+        self._tr = None
+        self._ensure_transient()
         return self
+
+    def _ensure_transient(self):
+        import torch
+        if self._tr is None:
+            self._tr = torch.empty(max(self.transient_bytes, 1), dtype=torch.uint8, device=self._ws.device)
+            _check(lib().selinv_bind_transient(self._h, ct.c_void_p(self._tr.data_ptr()), self.transient_bytes))
+
+    def release_transient(self, stream=None):
+        """Give the transient buffer back to torch's caching allocator (in
+        stream order: work already queued on `stream` still reads it).  The
+        inverse panels are lost; selinv_backward then needs
+        checkpoint_every > 1."""
+        if self._tr is not None:
+            if stream is not None:
+                self._tr.record_stream(stream)
+            _check(lib().selinv_bind_transient(self._h, None, 0))
+            self._tr = None
+
+    def generation(self):
+        g = ct.c_uint64()
+        _check(lib().selinv_generation(self._h, ct.byref(g)))
+        return int(g.value)
 
     def _need(self, t, n, name):
         import torch
@@ -251,6 +297,7 @@ class Plan:
         if out is None:
             out = torch.empty(nnzL, dtype=torch.float64, device=self._ws.device)
         self._need(out, nnzL, "out")
+        self._ensure_transient()
         _check(lib().selinv_invert(self._h, ct.c_void_p(out.data_ptr()), _stream(stream)))
         return out
 
@@ -261,6 +308,7 @@ class Plan:
         if out is None:
             out = torch.empty(int(self.info["nnzA"]), dtype=torch.float64, device=self._ws.device)
         self._need(out, int(self.info["nnzA"]), "out")
+        self._ensure_transient()
         _check(lib().selinv_backward(self._h, ct.c_void_p(gsel.data_ptr()), ct.c_void_p(out.data_ptr()),
                                      _stream(stream)))
         return out
@@ -304,6 +352,7 @@ class Plan:
         if out is None:
             out = torch.empty(nnzL, dtype=torch.float64, device=self._ws.device)
         self._need(out, nnzL, "out")
+        self._ensure_transient()
         _check(lib().selinv_run(self._h, ct.c_void_p(vals.data_ptr()), ct.c_void_p(out.data_ptr()),
                                 int(bool(graph)), _stream(stream)))
         return out
@@ -322,6 +371,7 @@ class Plan:
         sc = Sched()
         ms = ct.c_double()
         path = None if cache_path is None else os.fsencode(cache_path)
+        self._ensure_transient()
         _check(lib().selinv_tune(self._h, ct.c_void_p(vals.data_ptr()), ct.c_void_p(out.data_ptr()), path,
                                  ct.byref(sc), ct.byref(ms), _stream(stream)))
         return sc.as_dict(), float(ms.value), out
@@ -393,24 +443,52 @@ class Plan:
             pass
 
 
+def measure_peaks(device="cuda", nbytes=2 << 30, stream=None):
+    """Measured FP64 MFMA TFLOP/s and copy GB/s of the device (roofline
+    ceilings beside the published ones)."""
+    import torch
+    buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    tf, gb = ct.c_double(), ct.c_double()
+    st = lib().selinv_measure_peaks(ct.c_void_p(buf.data_ptr()), nbytes, ct.byref(tf), ct.byref(gb),
+                                    _stream(stream))
+    if st != SELINV_OK:
+        raise SelinvError(st, "measure_peaks failed")
+    return float(tf.value), float(gb.value)
+
+
 def _autograd_function():
     import torch
 
     class SelInv(torch.autograd.Function):
         """vals (A's stored lower entries, nnzA) -> selected entries of A^{-1}
         on the pattern of L (nnzL).  The backward is the library's reverse
-        sweep; an off-diagonal entry of A stands for A_ij and A_ji."""
+        sweep; an off-diagonal entry of A stands for A_ij and A_ji.
+
+        The forward synchronises once to report a pivot failure.  The plan
+        holds the factor and the inverse the backward differentiates: a later
+        forward on the same plan replaces them, and the backward of the
+        earlier one then raises.  With checkpoint_every > 1 the transient
+        memory is released between forward and backward (the backward
+        rebuilds the inverse panels from the checkpoints)."""
 
         @staticmethod
         def forward(ctx, vals, plan):
             plan.factor(vals.contiguous())
             sel = plan.invert()
+            plan.sync_status()
             ctx.plan = plan
+            ctx.generation = plan.generation()
+            if plan.checkpoint_every > 1:
+                plan.release_transient()
             return sel
 
         @staticmethod
         def backward(ctx, gsel):
-            g = ctx.plan.backward(gsel.contiguous().to(torch.float64))
+            plan = ctx.plan
+            if plan.generation() != ctx.generation:
+                raise RuntimeError("selinv backward: the plan ran another factorization after this forward; "
+                                   "its factor and inverse belong to other values (use one plan per forward)")
+            g = plan.backward(gsel.contiguous().to(torch.float64))
             return g, None
 
     return SelInv

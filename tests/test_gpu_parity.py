@@ -164,6 +164,8 @@ def test_lap3d_40_full():
     p, sel, s = _check(m, 128, True)
     r = H.row_identity_fast(sel, m, s.colptrL, s.rowindL, s.perm)
     assert np.max(np.abs(r)) <= 1e-10
+    # an irreducible Stieltjes matrix has an entrywise positive inverse
+    assert np.all(sel > 0)
 
 
 @pytest.mark.slow
@@ -203,8 +205,36 @@ def test_lap3d_64_full_properties():
     r, mag = H.row_identity_fast(sel, m, cp, ri, pm, with_scale=True)
     rel = np.abs(r) / np.maximum(mag, 1.0)
     assert np.max(rel) <= 1e-12, f"row identity {np.max(rel):.3e}"
+    assert np.all(sel > 0)  # entrywise positive inverse (irreducible Stieltjes matrix)
     v = torch.as_tensor(m.vals, dtype=torch.float64, device="cuda")
     p.factor(v)
     again = p.invert().cpu().numpy()
     p.sync_status()
     assert H.err_c8(again, sel, cp, ri) <= 1e-13
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(1200)
+def test_lap3d_64_full_oracle():
+    """64^3 grid, cap 256, in the benchmark's launch configuration: every one
+    of the 1.6e8 selected entries and every factor entry against the
+    oracle's supernodal factorization and selected inversion of the whole
+    matrix (about a minute of host time)."""
+    import time
+    from paper_1404_0447_amd import workloads as W
+    m = W.make("lap3d_64")
+    cap = W.CONFIGS["lap3d_64"]["cap"]
+    print(f"lap3d_64 oracle parity n={m.n}: GPU", flush=True)
+    p, sel, Lv = _run(m, cap, True)
+    cp, ri, pm = p.pattern()
+    del p
+    t0 = time.time()
+    print("lap3d_64 oracle parity: oracle", flush=True)
+    s, osel, oL = _oracle(m, cap)
+    print(f"lap3d_64 oracle parity: oracle done in {time.time() - t0:.0f}s", flush=True)
+    assert np.array_equal(cp, s.colptrL) and np.array_equal(ri, s.rowindL) and np.array_equal(pm, s.perm)
+    e = H.err_c8(sel, osel, cp, ri)
+    print(f"lap3d_64 selected inverse error {e:.3e}", flush=True)
+    assert e <= TOL, f"selected inverse error {e:.3e}"
+    eL = H.err_c8(Lv, oL, cp, ri)
+    assert eL <= 1e-12, f"factor error {eL:.3e}"

@@ -121,3 +121,43 @@ def test_device_calls_need_a_workspace():
     L = S.lib()
     st = L.selinv_invert(p._h, None, None)
     assert st == S.SELINV_ESTATE
+
+
+@pytest.mark.parametrize("dims,cap", [((16, 16), 128), ((9, 8, 7), 16), ((12, 12, 12), 128)])
+def test_rim_last_parity(dims, cap):
+    m = W.laplacian(dims, shift=0.1)
+    o = O.symbolic(m, cap=cap, perm="nd_rim").sym
+    p = S.Plan.from_matrix(m, max_super=cap, sep_order="rim_last")
+    cp, ri, pm = p.pattern()
+    sy = p.symbolic()
+    assert np.array_equal(pm, o.perm)
+    assert np.array_equal(cp, o.colptrL) and np.array_equal(ri, o.rowindL)
+    for k in ("parent", "xsuper", "sparent", "level", "cptr", "crows", "rptr", "rel"):
+        assert np.array_equal(sy[k], getattr(o, k)), k
+
+
+def test_options_are_validated():
+    m = W.laplacian((6, 6), shift=0.1)
+    for kw in (dict(sep_order=2), dict(deterministic=2)):
+        o = S.Opts(128, 1, 1, 0, kw.get("sep_order", 0), kw.get("deterministic", 0), 1)
+        h = ct.c_void_p()
+        st = S.lib().selinv_analyze(m.n, m.colptr.ctypes.data_as(ct.c_void_p),
+                                    m.rowind.ctypes.data_as(ct.c_void_p), None, None, ct.byref(o), ct.byref(h))
+        assert st == S.SELINV_EINVAL
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_workspace_parts_and_checkpoint_store(k):
+    m = W.laplacian((9, 8, 7), shift=0.1)
+    p = S.Plan.from_matrix(m, max_super=16, checkpoint_every=k)
+    nb = ct.c_size_t()
+    assert S.lib().selinv_workspace_size(p._h, ct.byref(nb)) == 0
+    assert nb.value == p.persistent_bytes + p.transient_bytes == p.info["workspace_bytes"]
+    b = p.blocks()
+    slot = ((b["level"] - 1) % k == 0) if k > 1 else np.zeros(len(b["level"]), bool)
+    store = int(((b["s"].astype(np.int64) + b["c"]) * b["s"])[slot].sum())
+    assert p.kernel_work()["checkpoint"][1] == 16.0 * store
+    if k > 1:
+        q = S.Plan.from_matrix(m, max_super=16)
+        assert p.persistent_bytes >= q.persistent_bytes + 8 * store - 256  # an empty store still takes 256 B
+        assert p.transient_bytes == q.transient_bytes
