@@ -96,6 +96,15 @@ typedef struct {
                              the reverse sweep, so the transient memory may be
                              released between the two.  <= 1: every level is
                              kept in place and nothing is recomputed.       */
+    int32_t relaxed;      /* 1: report relaxed supernodes (Section 2.1): the
+                             execution blocks, i.e. fundamental supernodes
+                             cut into pieces of at most exec_cap columns and
+                             chains of single-child pieces merged up to
+                             exec_cap columns; the pattern (and the selected
+                             values, the factor and the gradient input) then
+                             includes the explicit zeros of L inside those
+                             blocks, whose A^{-1} entries are computed too.
+                             Needs fuse_chains = 1.                         */
 } selinv_opts;
 
 typedef struct {

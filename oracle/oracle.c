@@ -237,7 +237,19 @@ void orc_sym_free(orc_sym* S)
 /* Build the symbolic structure of L for the lower CSC pattern (colptr,
  * rowind) of A in original numbering, under perm (new -> old; NULL =
  * identity). */
+static void relax_partition(orc_sym* S, int rcap);
+
+/* As orc_symbolic; with rcap > 0 the supernodes are then relaxed (see
+ * relax_partition) and every result (pattern, levels, maps, arena) refers to
+ * the relaxed partition. */
+orc_sym* orc_symbolic_relaxed(int n, const i64* colptr, const int* rowind, const int* perm, int cap, int rcap);
+
 orc_sym* orc_symbolic(int n, const i64* colptr, const int* rowind, const int* perm, int cap)
+{
+    return orc_symbolic_relaxed(n, colptr, rowind, perm, cap, 0);
+}
+
+orc_sym* orc_symbolic_relaxed(int n, const i64* colptr, const int* rowind, const int* perm, int cap, int rcap)
 {
     orc_sym* S = (orc_sym*)calloc(1, sizeof(orc_sym));
     S->n = n;
@@ -344,6 +356,10 @@ orc_sym* orc_symbolic(int n, const i64* colptr, const int* rowind, const int* pe
         int p = S->parent[S->xsuper[K + 1] - 1];
         S->sparent[K] = p >= 0 ? S->sn[p] : -1;
     }
+    if (rcap > 0) {
+        relax_partition(S, rcap);
+        N = S->N;
+    }
     /* Algorithm 2: sigma(root) = 1, sigma(I) = sigma(parent(I)) + 1 */
     for (int K = N - 1; K >= 0; K--)
         S->level[K] = S->sparent[K] < 0 ? 1 : S->level[S->sparent[K]] + 1;
@@ -373,9 +389,61 @@ orc_sym* orc_symbolic(int n, const i64* colptr, const int* rowind, const int* pe
     return S;
 }
 
+/* Relaxed supernodes (Section 2.1 relaxes supernodes within a column limit
+ * and stores the explicit zeros this creates).  Reading used here: each
+ * fundamental supernode is cut into pieces of at most rcap columns from its
+ * first column; going through the pieces in column order, a piece joins the
+ * block before it when it continues a chain -- it is not the first piece of
+ * its supernode, or its supernode has exactly one child and that child is
+ * the supernode just before it -- and the block then has at most rcap
+ * columns.  The rows below a block are the structure of its last column,
+ * which contains the structures of the columns below it (they form a
+ * chain), so the block's other columns get explicit zeros there.  Replaces
+ * xsuper, sn and sparent; levels and maps follow from them. */
+static void relax_partition(orc_sym* S, int rcap)
+{
+    int n = S->n, N = S->N;
+    int* nch = (int*)calloc((size_t)N + 1, sizeof(int));
+    for (int K = 0; K < N; K++)
+        if (S->sparent[K] >= 0) nch[S->sparent[K]]++;
+    int* xs = (int*)malloc(sizeof(int) * ((size_t)n + 1));
+    int M = 0;
+    for (int K = 0; K < N; K++) {
+        int f = S->xsuper[K], l = S->xsuper[K + 1];
+        for (int a = f; a < l; a += rcap) {
+            int b = a + rcap < l ? a + rcap : l;
+            int chain = a > f || (K > 0 && S->sparent[K - 1] == K && nch[K] == 1);
+            int fits = M > 0 && b - xs[M - 1] <= rcap;
+            if (!(chain && fits)) xs[M++] = a;
+        }
+    }
+    xs[M] = n;
+    free(nch);
+    free(S->xsuper);
+    S->xsuper = xs;
+    S->N = M;
+    for (int K = 0; K < M; K++)
+        for (int j = xs[K]; j < xs[K + 1]; j++) S->sn[j] = K;
+    for (int K = 0; K < M; K++) {
+        int p = S->parent[xs[K + 1] - 1];
+        S->sparent[K] = p >= 0 ? S->sn[p] : -1;
+    }
+}
+
 int orc_sym_error(const orc_sym* S) { return S->err; }
 int orc_sym_nsuper(const orc_sym* S) { return S->N; }
-i64 orc_sym_nnzL(const orc_sym* S) { return S->sptr[S->n] + S->n; }
+/* entries of the pattern: per supernode, its dense lower diagonal block and
+ * the rows below it in every column (for fundamental supernodes this is
+ * n + sum |struct(j)|) */
+i64 orc_sym_nnzL(const orc_sym* S)
+{
+    i64 q = 0;
+    for (int K = 0; K < S->N; K++) {
+        i64 s = sn_s(S, K), c = sn_c(S, K);
+        q += s * (s + 1) / 2 + s * c;
+    }
+    return q;
+}
 i64 orc_sym_relsize(const orc_sym* S) { return S->rptr[S->N]; }
 i64 orc_sym_arena(const orc_sym* S) { return S->arena; }
 
@@ -427,15 +495,20 @@ int orc_sym_check_maps(const orc_sym* S)
     return bad;
 }
 
-/* canonical lower pattern of L in permuted numbering: column j holds j then
- * struct(j), ascending */
+/* canonical lower pattern in permuted numbering: column j of supernode K
+ * holds j, the later columns of K, then C(K), ascending (for fundamental
+ * supernodes: j then struct(j)) */
 void orc_sym_pattern(const orc_sym* S, i64* colptrL, int* rowindL)
 {
     i64 q = 0;
-    for (int j = 0; j < S->n; j++) {
-        colptrL[j] = q;
-        rowindL[q++] = j;
-        for (i64 p = S->sptr[j]; p < S->sptr[j + 1]; p++) rowindL[q++] = S->srow[p];
+    for (int K = 0; K < S->N; K++) {
+        const int* C = sn_C(S, K);
+        int c = sn_c(S, K), l = S->xsuper[K + 1];
+        for (int j = S->xsuper[K]; j < l; j++) {
+            colptrL[j] = q;
+            for (int i = j; i < l; i++) rowindL[q++] = i;
+            for (int t = 0; t < c; t++) rowindL[q++] = C[t];
+        }
     }
     colptrL[S->n] = q;
 }
@@ -846,4 +919,200 @@ void orc_dense_grad(int n, const double* Ainv, const i64* colptrL, const int* ro
             g[p] = (i == j) ? -0.5 * m : -m;
         }
     free(Sm); free(T);
+}
+
+/* ------------------------------------------------------------------ */
+/* Complex symmetric matrices A(z) = H - z S (Section 4.3: the pole     */
+/* expansion inverts such matrices, symmetric but not Hermitian).       */
+/* The same LDL^T and Algorithm 1 with complex numbers: transposes are  */
+/* plain transposes, never conjugates.  Values are interleaved (re, im).*/
+/* ------------------------------------------------------------------ */
+#include <complex.h>
+
+typedef double complex zc;
+
+/* O3 for complex values: valsA and sel hold 2 doubles per entry.  A pivot
+ * that is zero or not finite is reported (there is no sign condition).
+ * Returns 0, -3 (bad pivot, *bad_col = original column), -4 (memory) or -5
+ * (inconsistent index map). */
+int orc_factor_selinv_z(const orc_sym* S, const i64* colptr, const int* rowind, const double* valsA, double* sel,
+                        i64* bad_col)
+{
+    int n = S->n, N = S->N;
+    zc* Lp = (zc*)calloc((size_t)S->arena + 1, sizeof(zc));
+    zc* Ai = (zc*)calloc((size_t)S->arena + 1, sizeof(zc));
+    int* maps = (int*)malloc(sizeof(int) * (size_t)(S->rptr[N] + 1));
+    if (!Lp || !Ai || !maps) { free(Lp); free(Ai); free(maps); return -4; }
+    int bad = -1, maperr = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(| : maperr)
+    for (int K = 0; K < N; K++) {
+        map_build(S, K, maps + S->rptr[K]);
+        for (i64 q = S->rptr[K]; q < S->rptr[K + 1]; q++) maperr |= maps[q] < 0;
+    }
+    if (maperr) { free(Lp); free(Ai); free(maps); return -5; }
+    for (int j = 0; j < n; j++)
+        for (i64 p = colptr[j]; p < colptr[j + 1]; p++) {
+            int a = S->iperm[rowind[p]], b = S->iperm[j];
+            int lo = a > b ? a : b, hi = a > b ? b : a;
+            int K = S->sn[hi];
+            i64 ld = sn_s(S, K) + sn_c(S, K);
+            int r = row_pos(S, K, lo);
+            Lp[S->poff[K] + r + (i64)(hi - S->xsuper[K]) * ld] += valsA[2 * p] + I * valsA[2 * p + 1];
+        }
+    /* factor: column LDL^T of each panel, then the Schur update of the ancestors */
+    for (int K = 0; K < N && bad < 0; K++) {
+        int s = sn_s(S, K), c = sn_c(S, K);
+        i64 ld = s + c;
+        zc* F = Lp + S->poff[K];
+        for (int j = 0; j < s; j++) {
+            zc dj = F[j + j * ld];
+            for (int k = 0; k < j; k++) dj -= F[j + k * ld] * F[j + k * ld] * F[k + k * ld];
+            if (dj == 0 || !isfinite(creal(dj)) || !isfinite(cimag(dj))) { bad = S->xsuper[K] + j; break; }
+            F[j + j * ld] = dj;
+            zc* Fj = F + (i64)j * ld;
+            for (int k = 0; k < j; k++) {
+                const zc* Fk = F + (i64)k * ld;
+                zc dk = Fk[k], ljk = Fk[j];
+                for (i64 i = j + 1; i < ld; i++) Fj[i] -= Fk[i] * dk * ljk;
+            }
+            for (i64 i = j + 1; i < ld; i++) Fj[i] = Fj[i] / dj;
+        }
+        if (bad >= 0 || c == 0) continue;
+        const int* map = maps + S->rptr[K];
+        i64 mlen = S->rptr[K + 1] - S->rptr[K];
+        const int* C = sn_C(S, K);
+#pragma omp parallel for schedule(dynamic, 4) if (c > 64)
+        for (int kk = 0; kk < c; kk++) {
+            int J, a;
+            const int* pos = seg_of(map, mlen, c, kk, &J, &a);
+            i64 ldJ = sn_s(S, J) + sn_c(S, J);
+            zc* FJ = Lp + S->poff[J] + (i64)(C[kk] - S->xsuper[J]) * ldJ;
+            for (int ii = kk; ii < c; ii++) {
+                zc u = 0;
+                for (int t = 0; t < s; t++) u += F[s + ii + t * ld] * F[t + t * ld] * F[s + kk + t * ld];
+                FJ[pos[ii - a]] -= u;
+            }
+        }
+    }
+    if (bad >= 0) {
+        if (bad_col) *bad_col = S->perm[bad];
+        free(Lp); free(Ai); free(maps);
+        return -3;
+    }
+    /* Algorithm 1, root first */
+    for (int K = N - 1; K >= 0; K--) {
+        int s = sn_s(S, K), c = sn_c(S, K);
+        i64 ld = s + c;
+        const zc* F = Lp + S->poff[K];
+        zc* X = Ai + S->poff[K];
+        const int* C = sn_C(S, K);
+        zc* Lh = (zc*)malloc(sizeof(zc) * ((size_t)c * s + 1));
+        /* step 2: L_hat L_KK = L(C,K), columns from the last one back */
+        for (int j = s - 1; j >= 0; j--) {
+            zc* Hj = Lh + (i64)j * c;
+            for (int r = 0; r < c; r++) Hj[r] = F[s + r + (i64)j * ld];
+            for (int k = j + 1; k < s; k++) {
+                const zc* Hk = Lh + (i64)k * c;
+                zc lkj = F[k + (i64)j * ld];
+                for (int r = 0; r < c; r++) Hj[r] -= Hk[r] * lkj;
+            }
+        }
+        if (c > 0) {
+            const int* map = maps + S->rptr[K];
+            i64 mlen = S->rptr[K + 1] - S->rptr[K];
+            /* gather G = Ainv(C,C) (symmetric: the upper entries mirror the lower) */
+            zc* G = (zc*)malloc(sizeof(zc) * (size_t)c * c);
+#pragma omp parallel for schedule(dynamic, 4) if (c > 64)
+            for (int kk = 0; kk < c; kk++) {
+                int J, a;
+                const int* pos = seg_of(map, mlen, c, kk, &J, &a);
+                i64 ldJ = sn_s(S, J) + sn_c(S, J);
+                const zc* AJ = Ai + S->poff[J] + (i64)(C[kk] - S->xsuper[J]) * ldJ;
+                for (int ii = kk; ii < c; ii++) {
+                    G[ii + (i64)kk * c] = AJ[pos[ii - a]];
+                    G[kk + (i64)ii * c] = AJ[pos[ii - a]];
+                }
+            }
+            /* step 3: Ainv(C,K) = -G L_hat */
+#pragma omp parallel for schedule(static) if (c > 64)
+            for (int r = 0; r < c; r++)
+                for (int j = 0; j < s; j++) {
+                    zc v = 0;
+                    for (int k = 0; k < c; k++) v += G[k + (i64)r * c] * Lh[k + (i64)j * c];
+                    X[s + r + (i64)j * ld] = -v;
+                }
+            free(G);
+        }
+        /* step 4: Ainv(K,K) = L_KK^{-T} D^{-1} L_KK^{-1} - L_hat^T Ainv(C,K), symmetrised */
+        zc* Y = (zc*)malloc(sizeof(zc) * (size_t)s * s);
+        zc* y = (zc*)malloc(sizeof(zc) * (size_t)s);
+        for (int j = 0; j < s; j++) {
+            for (int i = 0; i < s; i++) y[i] = (i == j) ? 1.0 : 0.0;
+            for (int i = 0; i < s; i++)
+                for (int k = 0; k < i; k++) y[i] -= F[i + (i64)k * ld] * y[k];
+            for (int i = 0; i < s; i++) y[i] = y[i] / F[i + (i64)i * ld];
+            for (int i = s - 1; i >= 0; i--)
+                for (int k = i + 1; k < s; k++) y[i] -= F[k + (i64)i * ld] * y[k];
+            for (int i = 0; i < s; i++) Y[i + (i64)j * s] = y[i];
+        }
+        for (int j = 0; j < s; j++)
+            for (int i = 0; i < s; i++) {
+                zc v = 0;
+                for (int r = 0; r < c; r++) v += Lh[r + (i64)i * c] * X[s + r + (i64)j * ld];
+                Y[i + (i64)j * s] -= v;
+            }
+        for (int j = 0; j < s; j++)
+            for (int i = 0; i < s; i++) X[i + (i64)j * ld] = 0.5 * (Y[i + (i64)j * s] + Y[j + (i64)i * s]);
+        free(Y); free(y); free(Lh);
+    }
+    i64 q = 0;
+    for (int K = 0; K < N; K++) {
+        int s = sn_s(S, K), c = sn_c(S, K);
+        i64 ld = s + c;
+        for (int j = 0; j < s; j++)
+            for (i64 i = j; i < ld; i++) {
+                zc v = Ai[S->poff[K] + i + (i64)j * ld];
+                sel[2 * q] = creal(v);
+                sel[2 * q + 1] = cimag(v);
+                q++;
+            }
+    }
+    free(Lp); free(Ai); free(maps);
+    return 0;
+}
+
+/* O1 for complex symmetric A (column-major, interleaved re/im): dense LDL^T
+ * without conjugation, then n triangular solves.  Returns 0 or -3. */
+int orc_dense_inverse_z(int n, const double* A, double* Ainv)
+{
+    zc* F = (zc*)malloc(sizeof(zc) * (size_t)n * n);
+    for (i64 e = 0; e < (i64)n * n; e++) F[e] = A[2 * e] + I * A[2 * e + 1];
+    for (int j = 0; j < n; j++) {
+        zc dj = F[j + (i64)j * n];
+        for (int k = 0; k < j; k++) dj -= F[j + (i64)k * n] * F[j + (i64)k * n] * F[k + (i64)k * n];
+        if (dj == 0 || !isfinite(creal(dj)) || !isfinite(cimag(dj))) { free(F); return -3; }
+        F[j + (i64)j * n] = dj;
+        for (int i = j + 1; i < n; i++) {
+            zc v = F[i + (i64)j * n];
+            for (int k = 0; k < j; k++) v -= F[i + (i64)k * n] * F[k + (i64)k * n] * F[j + (i64)k * n];
+            F[i + (i64)j * n] = v / dj;
+        }
+    }
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int j = 0; j < n; j++) {
+        zc* x = (zc*)malloc(sizeof(zc) * (size_t)n);
+        for (int i = 0; i < n; i++) x[i] = (i == j) ? 1.0 : 0.0;
+        for (int i = 0; i < n; i++)
+            for (int k = 0; k < i; k++) x[i] -= F[i + (i64)k * n] * x[k];
+        for (int i = 0; i < n; i++) x[i] /= F[i + (i64)i * n];
+        for (int i = n - 1; i >= 0; i--)
+            for (int k = i + 1; k < n; k++) x[i] -= F[k + (i64)i * n] * x[k];
+        for (int i = 0; i < n; i++) {
+            Ainv[2 * (i + (i64)j * n)] = creal(x[i]);
+            Ainv[2 * (i + (i64)j * n) + 1] = cimag(x[i]);
+        }
+        free(x);
+    }
+    free(F);
+    return 0;
 }

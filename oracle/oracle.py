@@ -45,6 +45,8 @@ def lib():
         L.orc_nd_order_sep.restype = ct.c_int64
         L.orc_symbolic.argtypes = [ct.c_int, _i64p, _i32p, vp, ct.c_int]
         L.orc_symbolic.restype = vp
+        L.orc_symbolic_relaxed.argtypes = [ct.c_int, _i64p, _i32p, vp, ct.c_int, ct.c_int]
+        L.orc_symbolic_relaxed.restype = vp
         for f in ("orc_sym_error", "orc_sym_nsuper"):
             getattr(L, f).argtypes = [vp]
             getattr(L, f).restype = ct.c_int
@@ -64,6 +66,10 @@ def lib():
         L.orc_dense_inverse.restype = ct.c_int
         L.orc_dense_ldlt.argtypes = [ct.c_int, _f64p, _f64p]
         L.orc_dense_ldlt.restype = ct.c_int
+        L.orc_factor_selinv_z.argtypes = [vp, _i64p, _i32p, _f64p, _f64p, ct.POINTER(ct.c_int64)]
+        L.orc_factor_selinv_z.restype = ct.c_int
+        L.orc_dense_inverse_z.argtypes = [ct.c_int, _f64p, _f64p]
+        L.orc_dense_inverse_z.restype = ct.c_int
         L.orc_selinv_columns.argtypes = [ct.c_int, _f64p, _i64p, _i32p, _f64p]
         L.orc_selinv_columns.restype = ct.c_int
         L.orc_dense_grad.argtypes = [ct.c_int, _f64p, _i64p, _i32p, _f64p, _i64p, _i32p, _f64p]
@@ -140,14 +146,14 @@ class Symbolic:
 class OracleSym:
     """Owns an orc_sym handle."""
 
-    def __init__(self, colptr, rowind, perm, cap):
+    def __init__(self, colptr, rowind, perm, cap, relax=0):
         L = lib()
         n = len(colptr) - 1
         self._colptr = np.ascontiguousarray(colptr, dtype=np.int64)
         self._rowind = np.ascontiguousarray(rowind, dtype=np.int32)
         p = None if perm is None else np.ascontiguousarray(perm, dtype=np.int32)
         self._perm = p
-        self.h = L.orc_symbolic(n, self._colptr, self._rowind, _ptr(p), int(cap))
+        self.h = L.orc_symbolic_relaxed(n, self._colptr, self._rowind, _ptr(p), int(cap), int(relax))
         err = L.orc_sym_error(self.h)
         if err:
             raise ValueError(f"oracle symbolic error {err}")
@@ -185,6 +191,16 @@ class OracleSym:
                                  _ptr(sel), _ptr(Lv), ct.byref(bad), ct.byref(tf), ct.byref(ts))
         return (sel[:nnzL], None if Lv is None else Lv[:nnzL], st, bad.value, tf.value, ts.value)
 
+    def factor_selinv_complex(self, vals):
+        """O3 on complex values (a complex array, nnzA): returns
+        (complex sel on the pattern, status, bad_col)."""
+        v = np.ascontiguousarray(np.asarray(vals, dtype=np.complex128)).view(np.float64)
+        nnzL = self.sym.nnzL
+        out = np.empty(2 * max(nnzL, 1))
+        bad = ct.c_int64(-1)
+        st = lib().orc_factor_selinv_z(self.h, self._colptr, self._rowind, v, out, ct.byref(bad))
+        return out[: 2 * nnzL].view(np.complex128).copy(), st, bad.value
+
     def __del__(self):
         try:
             if getattr(self, "h", None):
@@ -194,9 +210,10 @@ class OracleSym:
             pass
 
 
-def symbolic(m, cap=128, perm="nd"):
+def symbolic(m, cap=128, perm="nd", relax=0):
     """Oracle symbolic for a workloads.Matrix. perm: "nd" (from geometry),
-    "nd_rim" (separator rims last), "natural", or an explicit new->old array."""
+    "nd_rim" (separator rims last), "natural", or an explicit new->old array.
+    relax > 0: relaxed supernodes of at most `relax` columns."""
     if isinstance(perm, str):
         if perm in ("nd", "nd_rim") and m.ndim > 0:
             p = nd_order(m.ndim, m.dims, m.dofs, rim_last=perm == "nd_rim")
@@ -204,7 +221,7 @@ def symbolic(m, cap=128, perm="nd"):
             p = None
     else:
         p = perm
-    return OracleSym(m.colptr, m.rowind, p, cap)
+    return OracleSym(m.colptr, m.rowind, p, cap, relax)
 
 
 def dense_inverse(a):
@@ -216,6 +233,16 @@ def dense_inverse(a):
     if st != 0:
         raise ValueError("dense LDL^T hit a zero pivot")
     return dst.reshape(n, n).T.copy()
+
+
+def dense_inverse_complex(a):
+    """O1 for a complex symmetric matrix (no conjugation anywhere)."""
+    n = a.shape[0]
+    src = np.ascontiguousarray(np.asarray(a, dtype=np.complex128).T).view(np.float64).ravel()
+    dst = np.empty(2 * n * n)
+    if lib().orc_dense_inverse_z(n, src, dst) != 0:
+        raise ValueError("dense LDL^T hit a zero pivot")
+    return dst.view(np.complex128).reshape(n, n).T.copy()
 
 
 def dense_ldlt(a):

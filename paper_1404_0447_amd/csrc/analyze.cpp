@@ -362,9 +362,20 @@ selinv_status analyze(selinv_plan_s* P, const selinv_geom* geom, const int32_t* 
         std::copy(F.C(K), F.C(K) + F.clen(K), E.crows.begin() + q);
     }
     priority_levels(E);
-    // ---- canonical pattern of L (fundamental)
+    // ---- the reported partition: the fundamental supernodes, or with
+    //      `relaxed` the execution blocks themselves (their explicit zeros
+    //      become part of the reported pattern)
+    if (P->opts.relaxed) {
+        F = E;
+        N = F.nblocks();
+    }
+    // ---- canonical pattern: per column j of block K, j, the later columns
+    //      of K, then C(K) (for fundamental supernodes: j and struct(j))
     P->colptrL.assign(n + 1, 0);
-    for (int64_t j = 0; j < n; j++) P->colptrL[j + 1] = P->colptrL[j] + 1 + P->cnt[j];
+    for (int K = 0; K < N; K++)
+        for (int32_t j = F.xs[K]; j < F.xs[K + 1]; j++)
+            P->colptrL[j + 1] = (F.xs[K + 1] - j) + F.clen(K);
+    for (int64_t j = 0; j < n; j++) P->colptrL[j + 1] += P->colptrL[j];
     P->rowindL.resize((size_t)P->colptrL[n]);
     for (int K = 0; K < N; K++) {
         int32_t f = F.xs[K], l = F.xs[K + 1];

@@ -93,11 +93,13 @@ void compute_layout(selinv_plan_s* P)
     P->info.workspace_bytes = (int64_t)L.total;
 }
 
-DevPtrs dev_ptrs(const selinv_plan_s* P)
+}  // namespace
+
+namespace selinv {
+DevPtrs dev_ptrs_at(const selinv_plan_s* P, char* w, char* t)
 {
     const DeviceLayout& L = P->lay;
-    char* w = P->ws;
-    char* t = P->tr;  // may be null: then the transient arenas are unusable
+    // t may be null: then the transient arenas are unusable
     DevPtrs D;
     D.Lp = (double*)(w + L.lp);
     D.Ap = t ? (double*)(t + L.ap) : nullptr;
@@ -138,11 +140,61 @@ DevPtrs dev_ptrs(const selinv_plan_s* P)
 }
 
 template <class T>
-hipError_t upload(char* ws, size_t off, const std::vector<T>& v, hipStream_t s)
+static hipError_t upload(char* ws, size_t off, const std::vector<T>& v, hipStream_t s)
 {
     if (v.empty()) return hipSuccess;
     return hipMemcpyAsync(ws + off, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s);
 }
+
+// the plan's tables (block descriptors, index maps, task lists, queues,
+// checkpoint offsets) into the persistent part at ws, on stream s
+hipError_t upload_tables(selinv_plan_s* P, char* ws, hipStream_t s)
+{
+    const DeviceLayout& L = P->lay;
+    P->cr2.resize(2 * P->cbase.size());
+    for (size_t p = 0; p < P->cbase.size(); p++) {
+        P->cr2[2 * p] = P->cbase[p];
+        P->cr2[2 * p + 1] = P->rbase[p];
+    }
+    hipError_t e = upload(ws, L.blocks, P->blocks, s);
+    if (!e) e = upload(ws, L.crow, P->crow, s);
+    if (!e) e = upload(ws, L.cbase, P->cbase, s);
+    if (!e) e = upload(ws, L.cr2, P->cr2, s);
+    if (!e) e = upload(ws, L.rbase, P->rbase, s);
+    if (!e) e = upload(ws, L.rel, P->rel, s);
+    if (!e) e = upload(ws, L.asm_off, P->asm_off, s);
+    if (!e) e = upload(ws, L.exp_off, P->exp_off, s);
+    if (!e) e = upload(ws, L.colblk, P->colblk, s);
+    if (!e) e = upload(ws, L.colptrL, P->colptrL, s);
+    if (!e) e = upload(ws, L.t_diag, P->t_diag.tasks, s);
+    if (!e) e = upload(ws, L.t_ldlt, P->t_ldlt.tasks, s);
+    if (!e) e = upload(ws, L.t_sb, P->t_sb.tasks, s);
+    if (!e) e = upload(ws, L.t_panel, P->t_panel.tasks, s);
+    if (!e) e = upload(ws, L.t_schur, P->t_schur.tasks, s);
+    if (!e) e = upload(ws, L.t_gemm, P->t_gemm.tasks, s);
+    if (!e) e = upload(ws, L.t_sdiag, P->t_sdiag.tasks, s);
+    if (!e) e = upload(ws, L.t_zero, P->t_zero, s);
+    if (!e) e = upload(ws, L.t_rs1, P->t_rs1.tasks, s);
+    if (!e) e = upload(ws, L.t_rs2, P->t_rs2.tasks, s);
+    if (!e) e = upload(ws, L.t_rs3, P->t_rs3.tasks, s);
+    if (!e) e = upload(ws, L.t_rf1a, P->t_rf1a.tasks, s);
+    if (!e) e = upload(ws, L.t_rf1b, P->t_rf1b.tasks, s);
+    if (!e) e = upload(ws, L.t_rf2, P->t_rf2.tasks, s);
+    if (!e) e = upload(ws, L.q_fac, P->q_fac, s);
+    if (!e) e = upload(ws, L.q_inv, P->q_inv, s);
+    if (!e) e = upload(ws, L.ck_off, P->ck_off, s);
+    return e;
+}
+
+selinv_status set_error(selinv_status st, const std::string& msg)
+{
+    g_err = msg;
+    return st;
+}
+}  // namespace selinv
+
+namespace {
+DevPtrs dev_ptrs(const selinv_plan_s* P) { return dev_ptrs_at(P, P->ws, P->tr); }
 }  // namespace
 
 extern "C" {
@@ -191,8 +243,10 @@ selinv_status analyze_one(int64_t n, const int64_t* colptr, const int32_t* rowin
 
 selinv_status resolve_opts(const selinv_opts* opts, selinv_opts& o)
 {
-    o = selinv_opts{128, 1, 1, 0, 0, 0, 1};
+    o = selinv_opts{128, 1, 1, 0, 0, 0, 1, 0};
     if (opts) o = *opts;
+    if (o.relaxed != 0 && o.relaxed != 1) return fail(SELINV_EINVAL, "relaxed must be 0 or 1");
+    if (o.relaxed && !o.fuse_chains) return fail(SELINV_EINVAL, "relaxed supernodes need fuse_chains = 1");
     if (o.sep_order != 0 && o.sep_order != 1) return fail(SELINV_EINVAL, "sep_order must be 0 or 1");
     if (o.deterministic != 0 && o.deterministic != 1) return fail(SELINV_EINVAL, "deterministic must be 0 or 1");
     if (o.checkpoint_every < 1) o.checkpoint_every = 1;
@@ -268,7 +322,7 @@ void drop_graph(selinv_plan_s* P)
 }
 }  // namespace
 
-namespace {
+namespace selinv {
 // Factor, leaves first: assemble, then per level the small blocks and the
 // tiled path (diagonal blocks, panels, Schur colour groups).
 hipError_t factor_levels(selinv_plan_s* P, const DevPtrs& D, const double* d_valsA, hipStream_t s, Prof* prof)
@@ -327,7 +381,7 @@ hipError_t rebuild_inverse(selinv_plan_s* P, const DevPtrs& D, hipStream_t s, Pr
     }
     return e;
 }
-}  // namespace
+}  // namespace selinv
 
 selinv_plan_s::~selinv_plan_s()
 {
@@ -476,7 +530,6 @@ selinv_status selinv_bind_workspace(selinv_plan P, void* d_ws, size_t bytes, hip
     P->inverted = false;
     P->ap_valid = false;
     P->queues_on_device = false;
-    const DeviceLayout& L = P->lay;
     static hipError_t init = kernels_init();
     if (init != hipSuccess) return hip_fail(init, "kernel attributes");
     hipError_t e = hipSuccess;
@@ -491,40 +544,7 @@ selinv_status selinv_bind_workspace(selinv_plan P, void* d_ws, size_t bytes, hip
     }
     P->n_cu = prop.multiProcessorCount;
     P->dev_arch = prop.gcnArchName;
-    if (!e) e = upload(P->ws, L.blocks, P->blocks, s);
-    if (!e) e = upload(P->ws, L.crow, P->crow, s);
-    if (!e) e = upload(P->ws, L.cbase, P->cbase, s);
-    if (!e) {
-        P->cr2.resize(2 * P->cbase.size());
-        for (size_t p = 0; p < P->cbase.size(); p++) {
-            P->cr2[2 * p] = P->cbase[p];
-            P->cr2[2 * p + 1] = P->rbase[p];
-        }
-        e = upload(P->ws, L.cr2, P->cr2, s);
-    }
-    if (!e) e = upload(P->ws, L.rbase, P->rbase, s);
-    if (!e) e = upload(P->ws, L.rel, P->rel, s);
-    if (!e) e = upload(P->ws, L.asm_off, P->asm_off, s);
-    if (!e) e = upload(P->ws, L.exp_off, P->exp_off, s);
-    if (!e) e = upload(P->ws, L.colblk, P->colblk, s);
-    if (!e) e = upload(P->ws, L.colptrL, P->colptrL, s);
-    if (!e) e = upload(P->ws, L.t_diag, P->t_diag.tasks, s);
-    if (!e) e = upload(P->ws, L.t_ldlt, P->t_ldlt.tasks, s);
-    if (!e) e = upload(P->ws, L.t_sb, P->t_sb.tasks, s);
-    if (!e) e = upload(P->ws, L.t_panel, P->t_panel.tasks, s);
-    if (!e) e = upload(P->ws, L.t_schur, P->t_schur.tasks, s);
-    if (!e) e = upload(P->ws, L.t_gemm, P->t_gemm.tasks, s);
-    if (!e) e = upload(P->ws, L.t_sdiag, P->t_sdiag.tasks, s);
-    if (!e) e = upload(P->ws, L.t_zero, P->t_zero, s);
-    if (!e) e = upload(P->ws, L.t_rs1, P->t_rs1.tasks, s);
-    if (!e) e = upload(P->ws, L.t_rs2, P->t_rs2.tasks, s);
-    if (!e) e = upload(P->ws, L.t_rs3, P->t_rs3.tasks, s);
-    if (!e) e = upload(P->ws, L.t_rf1a, P->t_rf1a.tasks, s);
-    if (!e) e = upload(P->ws, L.t_rf1b, P->t_rf1b.tasks, s);
-    if (!e) e = upload(P->ws, L.t_rf2, P->t_rf2.tasks, s);
-    if (!e) e = upload(P->ws, L.q_fac, P->q_fac, s);
-    if (!e) e = upload(P->ws, L.q_inv, P->q_inv, s);
-    if (!e) e = upload(P->ws, L.ck_off, P->ck_off, s);
+    if (!e) e = upload_tables(P, P->ws, s);
     if (!e) e = hipStreamSynchronize(s);
     if (e) {
         P->ws = nullptr;

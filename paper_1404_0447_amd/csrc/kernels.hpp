@@ -3,6 +3,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <cstdint>
+#include <string>
 #include <vector>
 
 #include "plan.hpp"
@@ -71,5 +72,15 @@ hipError_t launch_persist_invert(Prof* P, const DevPtrs& D, const Task* q, int64
 // small-block path of one level (per-level launches)
 hipError_t launch_sb_factor(Prof* P, const DevPtrs& D, int64_t sb0, int64_t nsb, int require_spd, hipStream_t s);
 hipError_t launch_sb_invert(Prof* P, const DevPtrs& D, int64_t sb0, int64_t nsb, hipStream_t s);
+
+// Launch sequences and helpers of the C ABI (capi.cpp), shared with the
+// static-scratch entry point.
+DevPtrs dev_ptrs_at(const selinv_plan_s* P, char* ws, char* tr);
+hipError_t upload_tables(selinv_plan_s* P, char* ws, hipStream_t s);
+hipError_t factor_levels(selinv_plan_s* P, const DevPtrs& D, const double* d_valsA, hipStream_t s, Prof* prof);
+hipError_t invert_level(selinv_plan_s* P, const DevPtrs& D, int l, hipStream_t s, Prof* prof);
+hipError_t invert_levels(selinv_plan_s* P, const DevPtrs& D, double* d_sel, hipStream_t s, Prof* prof);
+hipError_t rebuild_inverse(selinv_plan_s* P, const DevPtrs& D, hipStream_t s, Prof* prof);
+selinv_status set_error(selinv_status st, const std::string& msg);
 
 }  // namespace selinv

@@ -49,13 +49,13 @@ class Geom(ct.Structure):
 class Opts(ct.Structure):
     _fields_ = [("max_super", ct.c_int32), ("fuse_chains", ct.c_int32), ("require_spd", ct.c_int32),
                 ("exec_cap", ct.c_int32), ("sep_order", ct.c_int32), ("deterministic", ct.c_int32),
-                ("checkpoint_every", ct.c_int32)]
+                ("checkpoint_every", ct.c_int32), ("relaxed", ct.c_int32)]
 
 
-def _opts(max_super, fuse_chains, require_spd, exec_cap, sep_order, deterministic, checkpoint_every):
+def _opts(max_super, fuse_chains, require_spd, exec_cap, sep_order, deterministic, checkpoint_every, relaxed):
     so = {"lex": 0, "rim_last": 1}.get(sep_order, sep_order)
     return Opts(int(max_super), int(bool(fuse_chains)), int(bool(require_spd)), int(exec_cap), int(so),
-                int(bool(deterministic)), int(checkpoint_every))
+                int(bool(deterministic)), int(checkpoint_every), int(bool(relaxed)))
 
 
 class Sched(ct.Structure):
@@ -144,7 +144,7 @@ class Plan:
 
     def __init__(self, n, colptr, rowind, geom=None, perm=None, max_super=128, fuse_chains=True,
                  require_spd=True, exec_cap=0, sep_order=0, deterministic=False, checkpoint_every=1,
-                 _handle=None):
+                 relaxed=False, _handle=None):
         L = lib()
         self.n = int(n)
         if _handle is not None:
@@ -159,7 +159,8 @@ class Plan:
             d3 = list(dims) + [1] * (3 - len(dims))
             g = Geom(int(ndim), (ct.c_int32 * 3)(*[int(x) for x in d3[:3]]), int(dofs))
         pm = None if perm is None else np.ascontiguousarray(perm, dtype=np.int32)
-        o = _opts(max_super, fuse_chains, require_spd, exec_cap, sep_order, deterministic, checkpoint_every)
+        o = _opts(max_super, fuse_chains, require_spd, exec_cap, sep_order, deterministic, checkpoint_every,
+                  relaxed)
         self.checkpoint_every = max(1, int(checkpoint_every))
         self.deterministic = bool(deterministic)
         h = ct.c_void_p()
@@ -189,7 +190,7 @@ class Plan:
 
     @classmethod
     def batch(cls, matrices, max_super=128, fuse_chains=True, require_spd=True, exec_cap=0, sep_order=0,
-              deterministic=False, checkpoint_every=1):
+              deterministic=False, checkpoint_every=1, relaxed=False):
         """One plan for a list of independent workloads.Matrix (their
         block-diagonal union); values and results concatenate in list order."""
         L = lib()
@@ -203,7 +204,8 @@ class Plan:
         for i, m in enumerate(matrices):
             d3 = list(m.dims) + [1] * (3 - len(m.dims))
             geoms[i] = Geom(int(m.ndim), (ct.c_int32 * 3)(*[int(x) for x in d3[:3]]), int(m.dofs))
-        o = _opts(max_super, fuse_chains, require_spd, exec_cap, sep_order, deterministic, checkpoint_every)
+        o = _opts(max_super, fuse_chains, require_spd, exec_cap, sep_order, deterministic, checkpoint_every,
+                  relaxed)
         h = ct.c_void_p()
         st = L.selinv_analyze_batch(cnt, _p(ns), cp_arr, ri_arr, geoms, ct.byref(o), ct.byref(h))
         _check(st)

@@ -221,3 +221,35 @@ def test_rim_last_matches_oracle(dims):
     cp, ri, pm = p.pattern()
     assert np.array_equal(pm, s.perm) and np.array_equal(cp, s.colptrL) and np.array_equal(ri, s.rowindL)
     assert H.err_c8(sel, osel, cp, ri) <= TOL
+
+
+# ------------------------------------------------------------------ relaxed supernodes
+@pytest.mark.parametrize("name", ["lap2d_24", "lap3d_12", "molecular_4", "lap3d_14_wide"])
+def test_relaxed_matches_oracle(name):
+    from paper_1404_0447_amd import selinv as S
+    m, cap = _cases()[name]
+    ecap = min(cap, 128)
+    p = S.Plan.from_matrix(m, max_super=cap, relaxed=True).bind()
+    sel = _fwd(p, m.vals).cpu().numpy()
+    Lv = p.factor_values().cpu().numpy()
+    from oracle import oracle as O
+    o = O.symbolic(m, cap=cap, relax=ecap)
+    osel, oL, st, _, _, _ = o.factor_selinv(m.vals, want_L=True)
+    assert st == 0
+    cp, ri, pm = p.pattern()
+    assert np.array_equal(cp, o.sym.colptrL) and np.array_equal(ri, o.sym.rowindL) and np.array_equal(pm, o.sym.perm)
+    assert H.err_c8(sel, osel, cp, ri) <= TOL
+    assert H.err_c8(Lv, oL, cp, ri) <= 1e-12
+
+
+def test_relaxed_gradient_matches_dense_reference():
+    torch = _torch()
+    from paper_1404_0447_amd import selinv as S
+    from tests.test_gpu_backward import _dense_reference
+    m, cap = _cases()["lap3d_12"]
+    p = S.Plan.from_matrix(m, max_super=cap, relaxed=True).bind()
+    _fwd(p, m.vals)
+    w = np.random.default_rng(5).standard_normal(int(p.info["nnzL"]))
+    g = p.backward(torch.as_tensor(w, device="cuda")).cpu().numpy()
+    ref = _dense_reference(m, p, w)
+    assert np.abs(g - ref).max() <= 1e-10 * np.abs(ref).max()

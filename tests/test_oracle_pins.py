@@ -469,3 +469,51 @@ def test_rim_last_changes_pattern_not_values(dims):
     exact = np.linalg.inv(m.dense())
     assert H.err_c8(sb, H.sel_from_dense(exact, b.sym.colptrL, b.sym.rowindL, b.sym.perm), b.sym.colptrL,
                     b.sym.rowindL) < 1e-11
+
+
+# ---------------------------------------------------------------- relaxed supernodes
+@pytest.mark.parametrize("case", ["grid2d", "grid3d", "molecular", "random"])
+def test_relaxed_values_are_the_inverse_on_the_superset_pattern(case):
+    """With relaxed supernodes the pattern grows by explicit zeros of L; the
+    selected values there are still entries of A^{-1} (checked against the
+    dense inverse by a library routine), the exported L is exactly zero
+    there, and on the fundamental pattern the values agree with the
+    unrelaxed run."""
+    if case == "grid2d":
+        m, cap, rc, perm = W.laplacian((14, 12), coeff="uniform", lo=0.5, hi=2.0, shift=0.05, seed=3), 128, 128, "nd"
+    elif case == "grid3d":
+        m, cap, rc, perm = W.laplacian((7, 6, 5), coeff="loguniform", lo=0.1, hi=10.0, shift=1e-3, seed=5), 16, 8, "nd"
+    elif case == "molecular":
+        m, cap, rc, perm = W.molecular(side=4, dofs=8, seed=2), 64, 64, "nd"
+    else:
+        m, cap, rc, perm = W.random_spd_pattern(120, 0.04, 4), 8, 8, "natural"
+    r = O.symbolic(m, cap=cap, perm=perm, relax=rc)
+    f = O.symbolic(m, cap=cap, perm=perm)
+    assert r.sym.nnzL > f.sym.nnzL  # there are explicit zeros
+    sel, Lv, st, _, _, _ = r.factor_selinv(m.vals, want_L=True)
+    assert st == 0
+    s = r.sym
+    exact = np.linalg.inv(m.dense())
+    assert H.err_c8(sel, H.sel_from_dense(exact, s.colptrL, s.rowindL, s.perm), s.colptrL, s.rowindL) < 1e-11
+    # L: zero wherever the fundamental pattern has no entry
+    n = m.n
+    fkeys = set(zip(np.repeat(np.arange(n), np.diff(f.sym.colptrL)).tolist(), f.sym.rowindL.tolist()))
+    cols = np.repeat(np.arange(n), np.diff(s.colptrL))
+    extra = np.array([(int(c), int(i)) not in fkeys for c, i in zip(cols, s.rowindL)])
+    assert extra.any() and np.all(Lv[extra] == 0.0)
+    fsel = f.factor_selinv(m.vals)[0]
+    dr = H.sel_to_dict(sel, s.colptrL, s.rowindL, s.perm)
+    df = H.sel_to_dict(fsel, f.sym.colptrL, f.sym.rowindL, f.sym.perm)
+    assert max(abs(dr[k] - df[k]) for k in df) < 1e-12
+
+
+def test_relaxed_partition_hand_example():
+    """Natural-order tridiagonal of 10 columns: fundamental supernodes are the
+    single columns 0..7 and {8, 9}; each column's only child is the one
+    before it, so relaxing with at most 4 columns gives [0,4), [4,8), [8,10),
+    and the blocks' rows below them are {4}, {8} and none."""
+    m = W.tridiag_1d(10, 0.1)
+    s = O.symbolic(m, cap=8, perm="natural", relax=4).sym
+    assert list(s.xsuper) == [0, 4, 8, 10]
+    assert [list(s.crows[s.cptr[k]:s.cptr[k + 1]]) for k in range(s.N)] == [[4], [8], []]
+    assert s.nnzL == (10 + 4) + (10 + 4) + 3

@@ -138,8 +138,9 @@ def test_rim_last_parity(dims, cap):
 
 def test_options_are_validated():
     m = W.laplacian((6, 6), shift=0.1)
-    for kw in (dict(sep_order=2), dict(deterministic=2)):
-        o = S.Opts(128, 1, 1, 0, kw.get("sep_order", 0), kw.get("deterministic", 0), 1)
+    for kw in (dict(sep_order=2), dict(deterministic=2), dict(relaxed=2), dict(relaxed=1, fuse=0)):
+        o = S.Opts(128, kw.get("fuse", 1), 1, 0, kw.get("sep_order", 0), kw.get("deterministic", 0), 1,
+                   kw.get("relaxed", 0))
         h = ct.c_void_p()
         st = S.lib().selinv_analyze(m.n, m.colptr.ctypes.data_as(ct.c_void_p),
                                     m.rowind.ctypes.data_as(ct.c_void_p), None, None, ct.byref(o), ct.byref(h))
@@ -161,3 +162,37 @@ def test_workspace_parts_and_checkpoint_store(k):
         q = S.Plan.from_matrix(m, max_super=16)
         assert p.persistent_bytes >= q.persistent_bytes + 8 * store - 256  # an empty store still takes 256 B
         assert p.transient_bytes == q.transient_bytes
+
+
+def _compare_relaxed(m, cap, exec_cap=0, perm="nd"):
+    ecap = exec_cap if exec_cap > 0 else min(cap, 128)
+    o = O.symbolic(m, cap=cap, perm=perm, relax=ecap).sym
+    p = S.Plan.from_matrix(m, max_super=cap, exec_cap=exec_cap, relaxed=True) if perm == "nd" else \
+        S.Plan(m.n, m.colptr, m.rowind, max_super=cap, exec_cap=exec_cap, relaxed=True)
+    cp, ri, pm = p.pattern()
+    sy = p.symbolic()
+    assert np.array_equal(pm, o.perm)
+    assert np.array_equal(cp, o.colptrL) and np.array_equal(ri, o.rowindL)
+    for k in ("parent", "xsuper", "sparent", "level", "cptr", "crows", "rptr", "rel"):
+        assert np.array_equal(sy[k], getattr(o, k)), k
+    inf = p.info
+    assert inf["nnzL"] == o.nnzL and inf["nsuper"] == o.N == inf["nblocks"]
+    assert inf["flops_gemm"] == pytest.approx(o.gemm_flops, rel=1e-12)
+    # the relaxed pattern contains the fundamental one
+    f = O.symbolic(m, cap=cap, perm=perm).sym
+    n = m.n
+    fset = set(zip(np.repeat(np.arange(n), np.diff(f.colptrL)).tolist(), f.rowindL.tolist()))
+    rset = set(zip(np.repeat(np.arange(n), np.diff(cp)).tolist(), ri.tolist()))
+    assert fset <= rset and o.nnzL >= f.nnzL and o.N <= f.N
+    return p, o
+
+
+@pytest.mark.parametrize("dims,cap,exec_cap", [((16, 16), 128, 0), ((9, 8, 7), 16, 0), ((12, 12, 12), 128, 32),
+                                               ((10, 10, 10), 256, 0), ((30,), 8, 0)])
+def test_relaxed_parity(dims, cap, exec_cap):
+    _compare_relaxed(W.laplacian(dims, shift=0.1), cap, exec_cap)
+
+
+def test_relaxed_parity_molecular_and_random():
+    _compare_relaxed(W.molecular(side=4, dofs=8, seed=4), 128)
+    _compare_relaxed(W.random_spd_pattern(150, 0.03, 9), 8, perm="natural")
