@@ -385,6 +385,34 @@ selinv_status selinv_tune(selinv_plan p, const double* d_valsA, double* d_sel, c
 selinv_status selinv_measure_peaks(void* d_buf, size_t bytes, double* fp64_mfma_tflops, double* copy_gbs,
                                    hipStream_t s);
 
+/* ------------------------------------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * ------------------------------------------------------------------------ */
+
+/* Size of the library's static per-device scratch array (64 MiB): each GPU
+ * the library runs on holds one copy until the process ends. */
+#define SELINV_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* selinv_factor + selinv_invert (same results up to the order of
+ * floating-point atomic additions) with the plan's whole workspace (tables,
+ * factor, inverse panels) in the static scratch array instead of a bound
+ * workspace: the call allocates nothing (no hipMalloc, no allocating
+ * library routine).  The plan needs no selinv_bind_workspace and its bound
+ * workspace, if any, is left untouched.  d_valsA: nnzA doubles as in
+ * selinv_factor; d_sel: nnzL doubles as in selinv_invert (caller-owned).
+ * The first call on a device looks up the array's device address; the
+ * plan's tables are copied in (host to device, stream-ordered) whenever
+ * the array last served another plan, so repeated calls with one plan
+ * launch kernels only.  Every call on a GPU shares that GPU's array, which
+ * keeps the last call's contents: calls that overlap on one GPU (other
+ * streams, other threads) race.  bad_col: NULL, or the call synchronises s
+ * and reports a pivot failure as SELINV_EPIVOT with *bad_col = original
+ * column (else -1).  SELINV_ENOMEM when selinv_workspace_size exceeds
+ * SELINV_STATIC_SCRATCH_BYTES. */
+selinv_status selinv_factor_invert_static(selinv_plan p, const double* d_valsA, double* d_sel, int64_t* bad_col,
+                                          hipStream_t s);
+
 /* Message for the last failing call on this thread. */
 const char* selinv_last_error(void);
 

@@ -202,6 +202,7 @@ struct selinv_plan_s {
     bool inverted = false;
     bool ap_valid = false;     // the inverse panels hold the last inversion's values
     uint64_t generation = 0;   // factorizations so far (selinv_factor, selinv_run)
+    uint64_t static_uid = 0;   // identity in the static scratch (0: never used there)
     selinv::Prof prof;
     std::vector<double> work_flops, work_bytes;  // per kernel kind, per call
     ~selinv_plan_s();

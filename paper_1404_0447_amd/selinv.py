@@ -27,7 +27,8 @@ EXPORTS = ["selinv_analyze", "selinv_workspace_size", "selinv_workspace_sizes", 
            "selinv_kernel_work", "selinv_get_arena", "selinv_get_blocks", "selinv_get_exec_rows",
            "selinv_analyze_batch", "selinv_batch_offsets", "selinv_set_schedule", "selinv_get_schedule",
            "selinv_get_queue", "selinv_set_spin_limit", "selinv_run", "selinv_tune", "selinv_measure_peaks",
-           "selinv_last_error", "selinv_destroy"]
+           "selinv_factor_invert_static", "selinv_last_error", "selinv_destroy"]
+STATIC_SCRATCH_BYTES = 64 << 20
 ARENAS = {"L": 0, "Ainv": 1, "Lhat": 2, "W": 3, "T": 4, "Fbar": 5, "Lhat_bar": 6, "T_bar": 7}
 KINDS = ["assemble", "ldlt", "panel", "schur", "gemm", "sdiag", "export", "revsel", "revfac", "qfactor", "qinvert",
          "sbfactor", "sbinvert", "checkpoint"]
@@ -113,6 +114,7 @@ def lib():
         L.selinv_run.argtypes = [vp, vp, vp, i32, vp]
         L.selinv_tune.argtypes = [vp, vp, vp, ct.c_char_p, ct.POINTER(Sched), ct.POINTER(ct.c_double), vp]
         L.selinv_measure_peaks.argtypes = [vp, ct.c_size_t, ct.POINTER(ct.c_double), ct.POINTER(ct.c_double), vp]
+        L.selinv_factor_invert_static.argtypes = [vp, vp, vp, ct.POINTER(i64), vp]
         L.selinv_last_error.restype = ct.c_char_p
         L.selinv_destroy.argtypes = [vp]
         for f in EXPORTS:
@@ -377,6 +379,22 @@ class Plan:
         _check(lib().selinv_tune(self._h, ct.c_void_p(vals.data_ptr()), ct.c_void_p(out.data_ptr()), path,
                                  ct.byref(sc), ct.byref(ms), _stream(stream)))
         return sc.as_dict(), float(ms.value), out
+
+    def factor_invert_static(self, vals, out=None, check=True, stream=None):
+        """Factor + invert in the library's static device scratch (no device
+        allocation inside the call; out must be given to allocate nothing
+        here either).  check=True synchronises and reports a pivot failure."""
+        import torch
+        nnzL = int(self.info["nnzL"])
+        self._need(vals, int(self.info["nnzA"]), "vals")
+        if out is None:
+            out = torch.empty(nnzL, dtype=torch.float64, device=vals.device)
+        self._need(out, nnzL, "out")
+        bad = ct.c_int64(-1)
+        st = lib().selinv_factor_invert_static(self._h, ct.c_void_p(vals.data_ptr()), ct.c_void_p(out.data_ptr()),
+                                               ct.byref(bad) if check else None, _stream(stream))
+        _check(st, bad.value)
+        return out
 
     def split(self, sel):
         """Per-matrix views of a batch's concatenated selected values."""
