@@ -101,6 +101,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-speedup measurement")
     ap.add_argument("--no-extra", action="store_true", help="skip the 40^3 and molecular side measurements")
     ap.add_argument("--no-det", action="store_true", help="skip the deterministic-mode step")
+    ap.add_argument("--no-poles", action="store_true", help="skip the complex pole-batch measurement")
     ap.add_argument("--checkpoint-every", type=int, default=4,
                     help="checkpoint interval of the second backward measurement (0: skip it)")
     ap.add_argument("--batch-reps", type=int, default=10, help="timed replays of the batched graph")
@@ -279,6 +280,8 @@ def main():
                                      if w != args.workload}
     if not args.no_batch:
         result["batched"] = measure_batched(args, dev)
+    if not args.no_poles:
+        result["poles"] = measure_poles(args, dev)
 
     if not args.no_cpu:
         result["cpu_baseline"], err = cpu_baseline(m, args.workload, cap, flops_step, value, out)
@@ -515,6 +518,57 @@ def measure_extra(workload, args, dev):
     p.sync_status()
     log(f"[bench] {workload}: {ms:.3f} ms/step, GEMM phase {gtf:.1f} TFLOP/s ({time.time() - t0:.1f}s)")
     del p
+    torch.cuda.empty_cache()
+    return res
+
+
+def measure_poles(args, dev):
+    """Complex symmetric A(z_k) = H - z_k S on a jittered 10^3-atom lattice
+    (8 unknowns per atom, n = 8000) for 32 poles on a half circle: one
+    analysis for all poles, factor + selected inversion of the whole batch
+    (one launch per level and kernel), against the same poles one after the
+    other on a single-matrix plan.  Flops are counted as real flops (a
+    complex multiply-add is 8 of them: 4x the real formulas)."""
+    import numpy as np
+    import torch
+    from paper_1404_0447_amd import selinv as S
+    from paper_1404_0447_amd import workloads as W
+    stream = torch.cuda.current_stream()
+    t0 = time.time()
+    H, Sm = W.hamiltonian_overlap(side=10, dofs=8, seed=6)
+    z = W.poles(32, 0.0, 40.0)
+    batch = S.Plan.poles(H, len(z)).bind(device=dev)
+    vals = torch.as_tensor(np.concatenate([W.pencil_values(H, Sm, zk) for zk in z]), device=dev)
+    out = torch.empty(int(batch.info["nnzL"]), dtype=torch.complex128, device=dev)
+    log(f"[bench] poles: {len(z)} x n={H.n}, nnzL={batch.info['nnzL']} ({time.time() - t0:.1f}s)")
+
+    def run_batch():
+        batch.factor_complex(vals)
+        batch.invert_complex(out)
+    run_batch()
+    batch.sync_status()
+    ms_batch = _time(run_batch, max(1, args.steps // 2), stream)
+    one = S.Plan.poles(H, 1).bind(device=dev)
+    pv = [vals[int(batch.nnzA_off[k]):int(batch.nnzA_off[k + 1])] for k in range(len(z))]
+    po = torch.empty(int(one.info["nnzL"]), dtype=torch.complex128, device=dev)
+
+    def run_loop():
+        for v in pv:
+            one.factor_complex(v)
+            one.invert_complex(po)
+    run_loop()
+    one.sync_status()
+    ms_loop = _time(run_loop, max(1, args.steps // 5), stream)
+    flops = 4.0 * (batch.info["flops_factor"] + batch.info["flops_selinv"])
+    res = {"workload": "A(z) = H - z S, jittered 10^3-atom lattice x 8 (n=8000), 32 poles on a half circle "
+                       "(center 0, radius 40), complex FP64",
+           "poles": len(z), "n_per_pole": H.n, "nnzL_total": batch.info["nnzL"],
+           "ms_batch": round(ms_batch, 4), "ms_per_pole_batched": round(ms_batch / len(z), 4),
+           "ms_loop_one_pole_at_a_time": round(ms_loop, 4), "batch_speedup": round(ms_loop / ms_batch, 2),
+           "gflops_real_equivalent": round(flops / (ms_batch * 1e-3) / 1e9, 2),
+           "frac_of_fp64_peak": round(flops / (ms_batch * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4)}
+    log(f"[bench] poles: batch {ms_batch:.3f} ms ({ms_batch / len(z):.3f} ms/pole), one at a time {ms_loop:.3f} ms")
+    del batch, one
     torch.cuda.empty_cache()
     return res
 

@@ -105,6 +105,12 @@ typedef struct {
                              includes the explicit zeros of L inside those
                              blocks, whose A^{-1} entries are computed too.
                              Needs fuse_chains = 1.                         */
+    int32_t complex_values; /* 1: the values are complex (A(z) = H - z S of the
+                             pole expansion, Section 4.3: symmetric, not
+                             Hermitian); use selinv_factor_complex and
+                             selinv_invert_complex.  Execution blocks are
+                             then at most 64 columns wide and the schedule is
+                             the deterministic one.                         */
 } selinv_opts;
 
 typedef struct {
@@ -129,6 +135,16 @@ typedef struct {
 selinv_status selinv_analyze(int64_t n, const int64_t* colptr, const int32_t* rowind,
                              const selinv_geom* geom, const int32_t* perm_or_null,
                              const selinv_opts* opts, selinv_plan* out);
+
+/* One symbolic analysis for `count` matrices of the same pattern (the poles
+ * z_1 .. z_count of a pole expansion, Section 4.3: A(z_k) = H - z_k S all
+ * share H's pattern): the plan is the block-diagonal union of count copies
+ * of the analysed matrix, run with one launch per level for all of them.
+ * Arguments as in selinv_analyze; values and results concatenate pole by
+ * pole (selinv_batch_offsets). */
+selinv_status selinv_analyze_poles(int64_t n, const int64_t* colptr, const int32_t* rowind,
+                                   const selinv_geom* geom, const int32_t* perm_or_null,
+                                   const selinv_opts* opts, int32_t count, selinv_plan* out);
 
 /* Bytes of device workspace the plan needs (factor, inverse, index maps):
  * persistent + transient, for one buffer holding both. */
@@ -166,6 +182,18 @@ selinv_status selinv_factor(selinv_plan p, const double* d_valsA, hipStream_t s)
  * Algorithm 2): writes nnzL doubles of A^{-1} to d_sel in the canonical
  * order of selinv_get_pattern. */
 selinv_status selinv_invert(selinv_plan p, double* d_sel, hipStream_t s);
+
+/* Complex values (plans analysed with complex_values = 1).  d_valsA: nnzA
+ * complex entries as (re, im) pairs of doubles in the CSC order of
+ * selinv_analyze; d_sel: nnzL complex entries of A^{-1} on the canonical
+ * pattern.  The LDL^T has complex pivots (no sign condition; a zero or
+ * non-finite pivot is SELINV_EPIVOT through selinv_sync_status) and every
+ * transpose in Algorithm 1 is a plain transpose.  The real-valued calls
+ * (selinv_factor, selinv_invert, selinv_backward, selinv_run, selinv_tune,
+ * selinv_get_factor) refuse such a plan with SELINV_EINVAL, and these two
+ * refuse a real plan. */
+selinv_status selinv_factor_complex(selinv_plan p, const double* d_valsA, hipStream_t s);
+selinv_status selinv_invert_complex(selinv_plan p, double* d_sel, hipStream_t s);
 
 /* Number of factorizations (selinv_factor, selinv_run) this plan has run.
  * A caller that keeps a plan across calls (an autograd node) records it

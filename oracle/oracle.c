@@ -54,7 +54,7 @@ typedef int64_t i64;
 /* Planted-mistake switch used only by the tests that show the pins catch
  * errors.  0 = correct code; the mistakes are listed where the tests plant
  * them (1-7 in the arithmetic and the symbolic phase, 8-9 in the export of
- * the factor). */
+ * the factor, 10 in the complex tier, 11 in the pivoted tier). */
 static int g_mut = 0;
 void orc_set_mutation(int m) { g_mut = m; }
 int orc_get_threads(void)
@@ -1030,7 +1030,8 @@ int orc_factor_selinv_z(const orc_sym* S, const i64* colptr, const int* rowind, 
                 const zc* AJ = Ai + S->poff[J] + (i64)(C[kk] - S->xsuper[J]) * ldJ;
                 for (int ii = kk; ii < c; ii++) {
                     G[ii + (i64)kk * c] = AJ[pos[ii - a]];
-                    G[kk + (i64)ii * c] = AJ[pos[ii - a]];
+                    /* planted mistake 10: a Hermitian mirror (conjugate) */
+                    G[kk + (i64)ii * c] = (g_mut == 10 && ii != kk) ? conj(AJ[pos[ii - a]]) : AJ[pos[ii - a]];
                 }
             }
             /* step 3: Ainv(C,K) = -G L_hat */
@@ -1115,4 +1116,260 @@ int orc_dense_inverse_z(int n, const double* A, double* Ainv)
     }
     free(F);
     return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Symmetric indefinite matrices: LDL^T with 1x1 and 2x2 pivots         */
+/* (Section 2.1: D may have 2x2 blocks), chosen by the Bunch-Kaufman    */
+/* rule inside each supernode's diagonal block.  The rest of the method */
+/* needs the diagonal block only through its inverse T = F_KK^{-1}      */
+/* (L_hat = F(C,K) T, the Schur update L_hat F(C,K)^T and Algorithm 1). */
+/* ------------------------------------------------------------------ */
+
+/* Bunch-Kaufman factorization of the symmetric s x s matrix M (column
+ * major, both triangles): P M P^T = L D L^T with L unit lower and D of 1x1
+ * and 2x2 blocks.  On return M's strict lower part holds L, piv[k] the row
+ * swapped with k at step k, bs[k] = 1 or 2 the size of the pivot starting at
+ * k (0 for the second column of a 2x2 pivot), and the D blocks stay on M's
+ * diagonal / first subdiagonal.  Returns 0, or -1 for a singular block. */
+static int bk_factor(int s, double* M, int* piv, int* bs)
+{
+    const double alpha = (1.0 + sqrt(17.0)) / 8.0;
+#define AT(i, j) M[(i) + (i64)(j) * s]
+    int k = 0;
+    while (k < s) {
+        double lambda = 0.0;
+        int r = k;
+        for (int i = k + 1; i < s; i++)
+            if (fabs(AT(i, k)) > lambda) { lambda = fabs(AT(i, k)); r = i; }
+        int size = 1, swap = k;
+        if (lambda == 0.0) {
+            if (AT(k, k) == 0.0) return -1;
+        } else if (fabs(AT(k, k)) < alpha * lambda) {
+            double sigma = 0.0;
+            for (int j = k; j < s; j++)
+                if (j != r && fabs(AT(r, j)) > sigma) sigma = fabs(AT(r, j));
+            if (fabs(AT(k, k)) * sigma >= alpha * lambda * lambda) {
+                size = 1;
+            } else if (fabs(AT(r, r)) >= alpha * sigma) {
+                size = 1;
+                swap = r;
+            } else {
+                size = 2;
+                swap = r;
+            }
+        }
+        if (g_mut == 11 && size == 2) { size = 1; swap = k; } /* planted mistake: no 2x2 pivots */
+        /* symmetric interchange of row/column kp with `swap` (both triangles) */
+        int kp = (size == 2) ? k + 1 : k;
+        if (swap != kp) {
+            for (int j = 0; j < s; j++) { double t = AT(kp, j); AT(kp, j) = AT(swap, j); AT(swap, j) = t; }
+            for (int i = 0; i < s; i++) { double t = AT(i, kp); AT(i, kp) = AT(i, swap); AT(i, swap) = t; }
+        }
+        piv[kp] = swap;
+        if (size == 2) piv[k] = k;
+        if (size == 1) {
+            double d = AT(k, k);
+            if (d == 0.0 || !isfinite(d)) return -1;
+            for (int i = k + 1; i < s; i++) AT(i, k) /= d;           /* L(:,k) */
+            for (int j = k + 1; j < s; j++)                          /* trailing update, both triangles */
+                for (int i = k + 1; i < s; i++) AT(i, j) -= AT(i, k) * d * AT(j, k);
+            for (int j = k + 1; j < s; j++) AT(k, j) = AT(j, k);     /* keep the row consistent (unused) */
+            bs[k] = 1;
+            k += 1;
+        } else {
+            double a = AT(k, k), b = AT(k + 1, k), c = AT(k + 1, k + 1);
+            double det = a * c - b * b;
+            if (det == 0.0 || !isfinite(det)) return -1;
+            /* rows i > k+1: [L(i,k) L(i,k+1)] = [M(i,k) M(i,k+1)] D^{-1} */
+            for (int i = k + 2; i < s; i++) {
+                double u = AT(i, k), v = AT(i, k + 1);
+                AT(i, k) = (u * c - v * b) / det;
+                AT(i, k + 1) = (v * a - u * b) / det;
+            }
+            for (int j = k + 2; j < s; j++)
+                for (int i = k + 2; i < s; i++)
+                    AT(i, j) -= AT(i, k) * (a * AT(j, k) + b * AT(j, k + 1)) + AT(i, k + 1) * (b * AT(j, k) + c * AT(j, k + 1));
+            bs[k] = 2;
+            bs[k + 1] = 0;
+            k += 2;
+        }
+    }
+    return 0;
+#undef AT
+}
+
+/* T = M^{-1} from the factorization: T(:,j) = P^T L^{-T} D^{-1} L^{-1} P e_j,
+ * the interchanges applied in order and undone in reverse order */
+static void bk_inverse(int s, const double* F, const int* piv, const int* bs, double* T)
+{
+#define AT(i, j) F[(i) + (i64)(j) * s]
+    double* x = (double*)malloc(sizeof(double) * (size_t)s);
+    for (int j = 0; j < s; j++) {
+        for (int i = 0; i < s; i++) x[i] = (i == j) ? 1.0 : 0.0;
+        for (int k = 0; k < s; k++) { double t = x[k]; x[k] = x[piv[k]]; x[piv[k]] = t; }
+        for (int k = 0; k < s; k++) {                          /* L y = P e_j */
+            if (bs[k] == 0) continue;
+            int w = bs[k];
+            for (int i = k + w; i < s; i++) {
+                x[i] -= AT(i, k) * x[k];
+                if (w == 2) x[i] -= AT(i, k + 1) * x[k + 1];
+            }
+        }
+        for (int k = 0; k < s; k++) {                          /* D z = y */
+            if (bs[k] == 1) x[k] /= AT(k, k);
+            else if (bs[k] == 2) {
+                double a = AT(k, k), b = AT(k + 1, k), c = AT(k + 1, k + 1), det = a * c - b * b;
+                double u = x[k], v = x[k + 1];
+                x[k] = (c * u - b * v) / det;
+                x[k + 1] = (a * v - b * u) / det;
+            }
+        }
+        for (int k = s - 1; k >= 0; k--) {                     /* L^T w = z */
+            if (bs[k] == 0) continue;
+            int w = bs[k];
+            for (int i = k + w; i < s; i++) {
+                x[k] -= AT(i, k) * x[i];
+                if (w == 2) x[k + 1] -= AT(i, k + 1) * x[i];
+            }
+        }
+        for (int k = s - 1; k >= 0; k--) { double t = x[k]; x[k] = x[piv[k]]; x[piv[k]] = t; }
+        for (int i = 0; i < s; i++) T[i + (i64)j * s] = x[i];
+    }
+    free(x);
+#undef AT
+}
+
+/* O3 with 1x1/2x2 pivots inside the diagonal blocks.  Per supernode K, leaves
+ * first: T = F_KK^{-1} (Bunch-Kaufman), L_hat(C,K) = F(C,K) T, and the Schur
+ * update F(C,C) -= L_hat F(C,K)^T into the ancestors; then Algorithm 1 root
+ * first with that L_hat and T.  Returns 0, -3 (singular diagonal block,
+ * *bad_col = original index of its first column), -4 or -5 as
+ * orc_factor_selinv. */
+int orc_factor_selinv_bk(const orc_sym* S, const i64* colptr, const int* rowind, const double* valsA, double* sel,
+                         i64* bad_col)
+{
+    int n = S->n, N = S->N;
+    double* Lp = (double*)calloc((size_t)S->arena + 1, sizeof(double));
+    double* Ai = (double*)calloc((size_t)S->arena + 1, sizeof(double));
+    i64* hoff = (i64*)malloc(sizeof(i64) * ((size_t)N + 1));
+    i64* toff = (i64*)malloc(sizeof(i64) * ((size_t)N + 1));
+    hoff[0] = toff[0] = 0;
+    for (int K = 0; K < N; K++) {
+        hoff[K + 1] = hoff[K] + (i64)sn_c(S, K) * sn_s(S, K);
+        toff[K + 1] = toff[K] + (i64)sn_s(S, K) * sn_s(S, K);
+    }
+    double* Lh = (double*)malloc(sizeof(double) * (size_t)(hoff[N] + 1));
+    double* Tt = (double*)malloc(sizeof(double) * (size_t)(toff[N] + 1));
+    int* maps = (int*)malloc(sizeof(int) * (size_t)(S->rptr[N] + 1));
+    if (!Lp || !Ai || !Lh || !Tt || !maps) { free(Lp); free(Ai); free(Lh); free(Tt); free(maps); free(hoff); free(toff); return -4; }
+    int maperr = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(| : maperr)
+    for (int K = 0; K < N; K++) {
+        map_build(S, K, maps + S->rptr[K]);
+        for (i64 q = S->rptr[K]; q < S->rptr[K + 1]; q++) maperr |= maps[q] < 0;
+    }
+    int status = maperr ? -5 : 0;
+    for (int j = 0; j < n && !status; j++)
+        for (i64 p = colptr[j]; p < colptr[j + 1]; p++) {
+            int a = S->iperm[rowind[p]], b = S->iperm[j];
+            int lo = a > b ? a : b, hi = a > b ? b : a;
+            int K = S->sn[hi];
+            i64 ld = sn_s(S, K) + sn_c(S, K);
+            Lp[S->poff[K] + row_pos(S, K, lo) + (i64)(hi - S->xsuper[K]) * ld] += valsA[p];
+        }
+    for (int K = 0; K < N && !status; K++) {
+        int s = sn_s(S, K), c = sn_c(S, K);
+        i64 ld = s + c;
+        double* F = Lp + S->poff[K];
+        /* the diagonal block, both triangles */
+        double* M = (double*)malloc(sizeof(double) * (size_t)s * s);
+        int* piv = (int*)malloc(sizeof(int) * (size_t)s);
+        int* bs = (int*)malloc(sizeof(int) * (size_t)s);
+        for (int j = 0; j < s; j++)
+            for (int i = j; i < s; i++) M[i + (i64)j * s] = M[j + (i64)i * s] = F[i + (i64)j * ld];
+        if (bk_factor(s, M, piv, bs)) {
+            if (bad_col) *bad_col = S->perm[S->xsuper[K]];
+            status = -3;
+        } else {
+            double* T = Tt + toff[K];
+            bk_inverse(s, M, piv, bs, T);
+            double* H = Lh + hoff[K];
+            /* L_hat(C,K) = F(C,K) T */
+            for (int r = 0; r < c; r++)
+                for (int j = 0; j < s; j++) {
+                    double v = 0;
+                    for (int k = 0; k < s; k++) v += F[s + r + (i64)k * ld] * T[k + (i64)j * s];
+                    H[r + (i64)j * c] = v;
+                }
+            if (c > 0) {
+                const int* map = maps + S->rptr[K];
+                i64 mlen = S->rptr[K + 1] - S->rptr[K];
+                const int* C = sn_C(S, K);
+#pragma omp parallel for schedule(dynamic, 4) if (c > 64)
+                for (int kk = 0; kk < c; kk++) {
+                    int J, a;
+                    const int* pos = seg_of(map, mlen, c, kk, &J, &a);
+                    i64 ldJ = sn_s(S, J) + sn_c(S, J);
+                    double* FJ = Lp + S->poff[J] + (i64)(C[kk] - S->xsuper[J]) * ldJ;
+                    for (int ii = kk; ii < c; ii++) {
+                        double u = 0;
+                        for (int t = 0; t < s; t++) u += H[ii + (i64)t * c] * F[s + kk + (i64)t * ld];
+                        FJ[pos[ii - a]] -= u;
+                    }
+                }
+            }
+        }
+        free(M); free(piv); free(bs);
+    }
+    /* Algorithm 1, root first, with the stored L_hat and T */
+    for (int K = N - 1; K >= 0 && !status; K--) {
+        int s = sn_s(S, K), c = sn_c(S, K);
+        i64 ld = s + c;
+        double* X = Ai + S->poff[K];
+        const double* H = Lh + hoff[K];
+        const double* T = Tt + toff[K];
+        const int* C = sn_C(S, K);
+        if (c > 0) {
+            const int* map = maps + S->rptr[K];
+            i64 mlen = S->rptr[K + 1] - S->rptr[K];
+            double* G = (double*)malloc(sizeof(double) * (size_t)c * c);
+#pragma omp parallel for schedule(dynamic, 4) if (c > 64)
+            for (int kk = 0; kk < c; kk++) {
+                int J, a;
+                const int* pos = seg_of(map, mlen, c, kk, &J, &a);
+                i64 ldJ = sn_s(S, J) + sn_c(S, J);
+                const double* AJ = Ai + S->poff[J] + (i64)(C[kk] - S->xsuper[J]) * ldJ;
+                for (int ii = kk; ii < c; ii++) G[ii + (i64)kk * c] = G[kk + (i64)ii * c] = AJ[pos[ii - a]];
+            }
+#pragma omp parallel for schedule(static) if (c > 64)
+            for (int r = 0; r < c; r++)
+                for (int j = 0; j < s; j++) {
+                    double v = 0;
+                    for (int k = 0; k < c; k++) v += G[k + (i64)r * c] * H[k + (i64)j * c];
+                    X[s + r + (i64)j * ld] = -v;
+                }
+            free(G);
+        }
+        for (int j = 0; j < s; j++)
+            for (int i = 0; i < s; i++) {
+                double v = T[i + (i64)j * s], w = T[j + (i64)i * s];
+                for (int r = 0; r < c; r++) {
+                    v -= H[r + (i64)i * c] * X[s + r + (i64)j * ld];
+                    w -= H[r + (i64)j * c] * X[s + r + (i64)i * ld];
+                }
+                X[i + (i64)j * ld] = 0.5 * (v + w);
+            }
+    }
+    if (!status) {
+        i64 q = 0;
+        for (int K = 0; K < N; K++) {
+            int s = sn_s(S, K), c = sn_c(S, K);
+            i64 ld = s + c;
+            for (int j = 0; j < s; j++)
+                for (i64 i = j; i < ld; i++) sel[q++] = Ai[S->poff[K] + i + (i64)j * ld];
+        }
+    }
+    free(Lp); free(Ai); free(Lh); free(Tt); free(maps); free(hoff); free(toff);
+    return status;
 }

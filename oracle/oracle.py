@@ -66,6 +66,8 @@ def lib():
         L.orc_dense_inverse.restype = ct.c_int
         L.orc_dense_ldlt.argtypes = [ct.c_int, _f64p, _f64p]
         L.orc_dense_ldlt.restype = ct.c_int
+        L.orc_factor_selinv_bk.argtypes = [vp, _i64p, _i32p, _f64p, _f64p, ct.POINTER(ct.c_int64)]
+        L.orc_factor_selinv_bk.restype = ct.c_int
         L.orc_factor_selinv_z.argtypes = [vp, _i64p, _i32p, _f64p, _f64p, ct.POINTER(ct.c_int64)]
         L.orc_factor_selinv_z.restype = ct.c_int
         L.orc_dense_inverse_z.argtypes = [ct.c_int, _f64p, _f64p]
@@ -190,6 +192,16 @@ class OracleSym:
                                  np.ascontiguousarray(vals, dtype=np.float64), int(require_spd),
                                  _ptr(sel), _ptr(Lv), ct.byref(bad), ct.byref(tf), ct.byref(ts))
         return (sel[:nnzL], None if Lv is None else Lv[:nnzL], st, bad.value, tf.value, ts.value)
+
+    def factor_selinv_pivoted(self, vals):
+        """O3 with 1x1/2x2 (Bunch-Kaufman) pivots inside each diagonal block,
+        for symmetric indefinite matrices: returns (sel, status, bad_col)."""
+        nnzL = self.sym.nnzL
+        out = np.empty(max(nnzL, 1))
+        bad = ct.c_int64(-1)
+        st = lib().orc_factor_selinv_bk(self.h, self._colptr, self._rowind,
+                                        np.ascontiguousarray(vals, dtype=np.float64), out, ct.byref(bad))
+        return out[:nnzL], st, bad.value
 
     def factor_selinv_complex(self, vals):
         """O3 on complex values (a complex array, nnzA): returns

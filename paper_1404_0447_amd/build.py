@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libselinv.so")
-SOURCES = ["analyze.cpp", "schedule.cpp", "batch.cpp", "capi.cpp", "kernels.hip", "probe.hip", "static_scratch.hip"]
+SOURCES = ["analyze.cpp", "schedule.cpp", "batch.cpp", "capi.cpp", "kernels.hip", "zkernels.hip", "probe.hip", "static_scratch.hip"]
 ARCH = os.environ.get("SELINV_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

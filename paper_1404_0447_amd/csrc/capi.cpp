@@ -42,11 +42,12 @@ void compute_layout(selinv_plan_s* P)
         o = align_up(o + std::max<size_t>(bytes, 1));
         return at;
     };
-    // persistent part
-    L.lp = take(sizeof(double) * P->arena);
-    L.hp = take(sizeof(double) * P->harena);
-    L.wp = take(sizeof(double) * P->warena);
-    L.tp = take(sizeof(double) * P->warena);
+    // persistent part (complex values: two doubles per entry, no adjoint)
+    const size_t w = P->opts.complex_values ? 2 : 1;
+    L.lp = take(w * sizeof(double) * P->arena);
+    L.hp = take(w * sizeof(double) * P->harena);
+    L.wp = take(w * sizeof(double) * P->warena);
+    L.tp = take(w * sizeof(double) * P->warena);
     L.status = take(2 * sizeof(unsigned long long));
     L.blocks = take(sizeof(BlockDesc) * P->blocks.size());
     L.crow = take(sizeof(int32_t) * P->crow.size());
@@ -84,10 +85,11 @@ void compute_layout(selinv_plan_s* P)
     L.persist = o;
     // transient part
     o = 0;
-    L.ap = take(sizeof(double) * P->arena);
-    L.zb = take(sizeof(double) * P->arena);
-    L.hb = take(sizeof(double) * P->harena);
-    L.tb = take(sizeof(double) * P->warena);
+    const size_t adj = P->opts.complex_values ? 0 : 1;
+    L.ap = take(w * sizeof(double) * P->arena);
+    L.zb = take(adj * sizeof(double) * P->arena);
+    L.hb = take(adj * sizeof(double) * P->harena);
+    L.tb = take(adj * sizeof(double) * P->warena);
     L.transient = o;
     L.total = L.persist + L.transient;
     P->info.workspace_bytes = (int64_t)L.total;
@@ -243,8 +245,9 @@ selinv_status analyze_one(int64_t n, const int64_t* colptr, const int32_t* rowin
 
 selinv_status resolve_opts(const selinv_opts* opts, selinv_opts& o)
 {
-    o = selinv_opts{128, 1, 1, 0, 0, 0, 1, 0};
+    o = selinv_opts{128, 1, 1, 0, 0, 0, 1, 0, 0};
     if (opts) o = *opts;
+    if (o.complex_values != 0 && o.complex_values != 1) return fail(SELINV_EINVAL, "complex_values must be 0 or 1");
     if (o.relaxed != 0 && o.relaxed != 1) return fail(SELINV_EINVAL, "relaxed must be 0 or 1");
     if (o.relaxed && !o.fuse_chains) return fail(SELINV_EINVAL, "relaxed supernodes need fuse_chains = 1");
     if (o.sep_order != 0 && o.sep_order != 1) return fail(SELINV_EINVAL, "sep_order must be 0 or 1");
@@ -257,6 +260,12 @@ selinv_status resolve_opts(const selinv_opts* opts, selinv_opts& o)
     if (o.exec_cap <= 0) o.exec_cap = std::min(o.max_super, (int32_t)kLdsDiagMax);
     if (o.max_super > 256 || o.exec_cap > 256)
         return fail(SELINV_EUNSUPPORTED, "supernode width cap above 256 is not supported");
+    if (o.complex_values) {
+        // the complex kernels hold a whole diagonal block in LDS and add
+        // without atomics: blocks of at most 64 columns, deterministic schedule
+        o.exec_cap = std::min(o.exec_cap, (int32_t)kZMaxS);
+        o.deterministic = 1;
+    }
     return SELINV_OK;
 }
 
@@ -330,18 +339,19 @@ hipError_t factor_levels(selinv_plan_s* P, const DevPtrs& D, const double* d_val
     hipError_t e = launch_status_reset(D.status, s);
     if (!e) e = launch_fill(prof, kAssemble, D.Lp, P->arena, 0.0, s);
     if (!e) e = launch_scatter_set(prof, kAssemble, d_valsA, D.asm_off, P->nnzA, D.Lp, s);
-    const int depth = P->exec.depth;
-    const int flags = (P->opts.require_spd ? 1 : 0) | (P->opts.deterministic ? 2 : 0);
-    for (int l = depth - 1; l >= 0 && !e; l--) {
+    const int spd = P->opts.require_spd ? 1 : 0;
+    const int deep_ok = P->opts.deterministic ? 0 : 3;
+    for (int l = P->exec.depth - 1; l >= 0 && !e; l--) {
         const auto& q = P->t_sb.off;
-        const auto& a = P->t_ldlt.off;
         const auto& b = P->t_panel.off;
-        const int64_t diag[4] = {a[l], P->ldlt_cut[2 * l], P->ldlt_cut[2 * l + 1], a[l + 1]};
-        e = launch_sb_factor(prof, D, q[l], q[l + 1] - q[l], P->opts.require_spd, s);
+        const auto& a = P->t_ldlt.off;
         const auto& cut = P->schur_cuts[l];
-        if (!e)
-            e = launch_factor_level(prof, D, diag, b[l], b[l + 1] - b[l], cut.data(), (int)cut.size(),
-                                    P->panel_deep[l], flags, s);
+        const int deep = P->panel_deep[l] & deep_ok;
+        const int64_t dg[4] = {a[l], P->ldlt_cut[2 * l], P->ldlt_cut[2 * l + 1], a[l + 1]};
+        e = launch_sb_factor(prof, D, q[l], q[l + 1] - q[l], spd, s);
+        if (!e) e = launch_ldlt_level(prof, D, dg, spd, s);
+        if (!e) e = launch_panel_level(prof, D, b[l], b[l + 1] - b[l], deep, s);
+        if (!e) e = launch_schur_groups(prof, D, cut.data(), 0, (int)cut.size() - 1, deep, s);
     }
     return e;
 }
@@ -464,6 +474,43 @@ selinv_status selinv_analyze_batch(int32_t count, const int64_t* ns, const int64
     return SELINV_OK;
 }
 
+selinv_status selinv_analyze_poles(int64_t n, const int64_t* colptr, const int32_t* rowind, const selinv_geom* geom,
+                                   const int32_t* perm_or_null, const selinv_opts* opts, int32_t count,
+                                   selinv_plan* out)
+{
+    if (!out) return fail(SELINV_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (count < 1) return fail(SELINV_EINVAL, "count must be >= 1");
+    if ((int64_t)count * n > INT32_MAX - 1) return fail(SELINV_EINVAL, "batch too large: total order exceeds 2^31 - 2");
+    selinv_opts o;
+    if (selinv_status st = resolve_opts(opts, o)) return st;
+    selinv_plan_s* one = new (std::nothrow) selinv_plan_s();
+    if (!one) return fail(SELINV_ENOMEM, "out of host memory");
+    selinv_plan_s* U = nullptr;
+    try {
+        std::string err;
+        selinv_status st = analyze_one(n, colptr, rowind, geom, perm_or_null, o, one, err);
+        if (st != SELINV_OK) {
+            delete one;
+            return fail(st, err);
+        }
+        // the one analysis, repeated: the union reads its parts only
+        std::vector<selinv_plan_s*> parts((size_t)count, one);
+        U = new selinv_plan_s();
+        U->opts = o;
+        merge_plans(parts, U);
+        delete one;
+        one = nullptr;
+        finish_plan(U);
+    } catch (const std::bad_alloc&) {
+        delete one;
+        delete U;
+        return fail(SELINV_ENOMEM, "out of host memory during analysis");
+    }
+    *out = U;
+    return SELINV_OK;
+}
+
 selinv_status selinv_batch_offsets(selinv_plan P, int32_t* count, int64_t* n_off, int64_t* nnzA_off,
                                    int64_t* nnzL_off)
 {
@@ -530,7 +577,7 @@ selinv_status selinv_bind_workspace(selinv_plan P, void* d_ws, size_t bytes, hip
     P->inverted = false;
     P->ap_valid = false;
     P->queues_on_device = false;
-    static hipError_t init = kernels_init();
+    const hipError_t init = kernels_init();
     if (init != hipSuccess) return hip_fail(init, "kernel attributes");
     hipError_t e = hipSuccess;
     int dev = 0;
@@ -557,6 +604,7 @@ selinv_status selinv_bind_workspace(selinv_plan P, void* d_ws, size_t bytes, hip
 selinv_status selinv_factor(selinv_plan P, const double* d_valsA, hipStream_t s)
 {
     if (!P) return fail(SELINV_EINVAL, "NULL plan");
+    if (P->opts.complex_values) return fail(SELINV_EINVAL, "the plan holds complex values (selinv_*_complex)");
     if (!P->ws) return fail(SELINV_ESTATE, "no workspace bound");
     if (P->nnzA > 0 && !d_valsA) return fail(SELINV_EINVAL, "d_valsA is NULL");
     P->generation++;
@@ -572,6 +620,7 @@ selinv_status selinv_factor(selinv_plan P, const double* d_valsA, hipStream_t s)
 selinv_status selinv_backward(selinv_plan P, const double* d_gsel, double* d_gA, hipStream_t s)
 {
     if (!P) return fail(SELINV_EINVAL, "NULL plan");
+    if (P->opts.complex_values) return fail(SELINV_EINVAL, "the plan holds complex values (selinv_*_complex)");
     if (!P->ws) return fail(SELINV_ESTATE, "no workspace bound");
     if (!P->inverted) return fail(SELINV_ESTATE, "backward needs factor and invert of the same values first");
     if (!P->tr) return fail(SELINV_ESTATE, "no transient memory bound (selinv_bind_transient)");
@@ -621,6 +670,7 @@ selinv_status selinv_backward(selinv_plan P, const double* d_gsel, double* d_gA,
 selinv_status selinv_invert(selinv_plan P, double* d_sel, hipStream_t s)
 {
     if (!P) return fail(SELINV_EINVAL, "NULL plan");
+    if (P->opts.complex_values) return fail(SELINV_EINVAL, "the plan holds complex values (selinv_*_complex)");
     if (!P->ws) return fail(SELINV_ESTATE, "no workspace bound");
     if (!P->factored) return fail(SELINV_ESTATE, "invert called before factor");
     if (!P->tr) return fail(SELINV_ESTATE, "no transient memory bound (selinv_bind_transient)");
@@ -634,9 +684,55 @@ selinv_status selinv_invert(selinv_plan P, double* d_sel, hipStream_t s)
     return SELINV_OK;
 }
 
+selinv_status selinv_factor_complex(selinv_plan P, const double* d_valsA, hipStream_t s)
+{
+    if (!P) return fail(SELINV_EINVAL, "NULL plan");
+    if (!P->opts.complex_values) return fail(SELINV_EINVAL, "the plan holds real values (analyse with complex_values)");
+    if (!P->ws) return fail(SELINV_ESTATE, "no workspace bound");
+    if (P->nnzA > 0 && !d_valsA) return fail(SELINV_EINVAL, "d_valsA is NULL");
+    P->generation++;
+    P->factored = P->inverted = P->ap_valid = false;
+    const DevPtrs D = dev_ptrs(P);
+    hipError_t e = launch_status_reset(D.status, s);
+    if (!e) e = launch_fill(nullptr, kAssemble, D.Lp, 2 * P->arena, 0.0, s);
+    if (!e) e = launch_zassemble(d_valsA, D.asm_off, P->nnzA, D.Lp, s);
+    for (int l = P->exec.depth - 1; l >= 0 && !e; l--) {
+        const auto& a = P->t_ldlt.off;
+        const auto& b = P->t_panel.off;
+        const auto& cut = P->schur_cuts[l];
+        e = launch_zfactor_level(D, a[l], a[l + 1] - a[l], b[l], b[l + 1] - b[l], cut.data(), (int)cut.size(), s);
+    }
+    if (e) return hip_fail(e, "complex factor launch");
+    P->factored = true;
+    return SELINV_OK;
+}
+
+selinv_status selinv_invert_complex(selinv_plan P, double* d_sel, hipStream_t s)
+{
+    if (!P) return fail(SELINV_EINVAL, "NULL plan");
+    if (!P->opts.complex_values) return fail(SELINV_EINVAL, "the plan holds real values (analyse with complex_values)");
+    if (!P->ws) return fail(SELINV_ESTATE, "no workspace bound");
+    if (!P->factored) return fail(SELINV_ESTATE, "invert called before factor");
+    if (!P->tr) return fail(SELINV_ESTATE, "no transient memory bound (selinv_bind_transient)");
+    if (P->colptrL.back() > 0 && !d_sel) return fail(SELINV_EINVAL, "d_sel is NULL");
+    const DevPtrs D = dev_ptrs(P);
+    hipError_t e = hipSuccess;
+    for (int l = 0; l < P->exec.depth && !e; l++) {
+        const auto& g = P->t_gemm.off;
+        const auto& d = P->t_sdiag.off;
+        e = launch_zinvert_level(D, g[l], g[l + 1] - g[l], d[l], d[l + 1] - d[l], s);
+    }
+    if (!e) e = launch_zexport(D.Ap, D.exp_off, P->colptrL.back(), d_sel, s);
+    if (e) return hip_fail(e, "complex invert launch");
+    P->inverted = true;
+    P->ap_valid = true;
+    return SELINV_OK;
+}
+
 selinv_status selinv_get_factor(selinv_plan P, double* d_L, hipStream_t s)
 {
     if (!P) return fail(SELINV_EINVAL, "NULL plan");
+    if (P->opts.complex_values) return fail(SELINV_EINVAL, "the plan holds complex values (selinv_*_complex)");
     if (!P->ws) return fail(SELINV_ESTATE, "no workspace bound");
     if (!P->factored) return fail(SELINV_ESTATE, "no factor computed");
     DevPtrs D = dev_ptrs(P);
@@ -1046,6 +1142,7 @@ selinv_status selinv_set_spin_limit(selinv_plan P, uint32_t polls)
 selinv_status selinv_run(selinv_plan P, const double* d_valsA, double* d_sel, int32_t use_graph, hipStream_t s)
 {
     if (!P) return fail(SELINV_EINVAL, "NULL plan");
+    if (P->opts.complex_values) return fail(SELINV_EINVAL, "the plan holds complex values (selinv_*_complex)");
     if (!P->ws || !P->queues_on_device) return fail(SELINV_ESTATE, "no workspace bound");
     if (!P->tr) return fail(SELINV_ESTATE, "no transient memory bound (selinv_bind_transient)");
     if ((P->nnzA > 0 && !d_valsA) || (P->colptrL.back() > 0 && !d_sel)) return fail(SELINV_EINVAL, "NULL buffer");
@@ -1091,6 +1188,7 @@ selinv_status selinv_tune(selinv_plan P, const double* d_valsA, double* d_sel, c
                           selinv_sched* chosen, double* best_ms, hipStream_t s)
 {
     if (!P) return fail(SELINV_EINVAL, "NULL plan");
+    if (P->opts.complex_values) return fail(SELINV_EINVAL, "the plan holds complex values (selinv_*_complex)");
     if (!P->ws) return fail(SELINV_ESTATE, "no workspace bound");
     if (!P->tr) return fail(SELINV_ESTATE, "no transient memory bound (selinv_bind_transient)");
     if (P->opts.deterministic)

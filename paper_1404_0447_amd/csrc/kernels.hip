@@ -22,6 +22,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <atomic>
 #include <type_traits>
 
 #include "kernels.hpp"
@@ -1597,6 +1598,219 @@ __global__ __launch_bounds__(kThreads) void k_ldlt_diag(const Task* __restrict__
     else ldlt_sweep_cols<NB>(d, Lp, Tp, status, require_spd, lds, invd);
 }
 
+// ---------------------------------------------------------------------------
+// Diagonal block of a symmetric indefinite matrix: T_K = F_KK^{-1} from an
+// LDL^T with 1x1 and 2x2 pivots chosen by the Bunch-Kaufman rule, with
+// symmetric interchanges inside the block (Section 2.1: D may have 2x2
+// blocks).  The rest of the method needs the diagonal block only through T
+// (L_hat = F(C,K) T, the Schur update L_hat F(C,K)^T, Algorithm 1 and the
+// adjoint), so L_KK and D stay in LDS.  One work-group per block (s <= 128),
+// the block in dynamic LDS with both triangles; T's columns are then solved
+// one per thread in global memory (Tp) and symmetrised.  A singular 1x1 or
+// 2x2 pivot latches the block's first column in the status word.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_ldlt_bk(const Task* __restrict__ tasks, const BlockDesc* __restrict__ blk,
+                                                      const double* __restrict__ Lp, double* __restrict__ Tp,
+                                                      unsigned long long* __restrict__ status)
+{
+    extern __shared__ double M[];  // M[i + j * ls], ls = s + 1
+    __shared__ int piv[kLdsDiagMax], bsz[kLdsDiagMax];
+    __shared__ int s_size, s_swap, s_bad;
+    __shared__ double red_v[64];
+    __shared__ int red_i[64];
+    const BlockDesc d = blk[tasks[blockIdx.x].b];
+    const int s = d.s, ls = s + 1, t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int64_t ld = (int64_t)s + d.c;
+    const double alpha = (1.0 + sqrt(17.0)) / 8.0;
+    for (int e = t; e < s * s; e += kThreads) {
+        const int i = e % s, j = e / s;
+        if (i >= j) {
+            const double v = Lp[d.poff + i + (int64_t)j * ld];
+            M[i + j * ls] = v;
+            M[j + i * ls] = v;
+        }
+    }
+    if (t == 0) s_bad = 0;
+    __syncthreads();
+    // wave 0: largest |x_q| over q in [q0, q1) (q != skip), value and index
+    auto wave_max = [&](auto val, int q0, int q1, int skip, double& best, int& arg) {
+        double b = -1.0;
+        int a = -1;
+        for (int q = q0 + lane; q < q1; q += 64)
+            if (q != skip) {
+                const double v = fabs(val(q));
+                if (v > b) { b = v; a = q; }
+            }
+        red_v[lane] = b;
+        red_i[lane] = a;
+        wave_sync();
+        for (int w = 32; w > 0; w >>= 1) {
+            if (lane < w && (red_v[lane + w] > red_v[lane] ||
+                             (red_v[lane + w] == red_v[lane] && red_i[lane + w] >= 0 &&
+                              (red_i[lane] < 0 || red_i[lane + w] < red_i[lane])))) {
+                red_v[lane] = red_v[lane + w];
+                red_i[lane] = red_i[lane + w];
+            }
+            wave_sync();
+        }
+        best = red_v[0];
+        arg = red_i[0];
+    };
+    int k = 0;
+    while (k < s) {
+        if (wave == 0) {
+            double lambda;
+            int r;
+            wave_max([&](int q) { return M[q + k * ls]; }, k + 1, s, -1, lambda, r);
+            int size = 1, swap = k;
+            const double akk = fabs(M[k + k * ls]);
+            bool bad = false;
+            if (r < 0 || lambda <= 0.0) {
+                bad = akk == 0.0;
+            } else if (akk < alpha * lambda) {
+                double sigma;
+                int dummy;
+                wave_max([&](int q) { return M[r + q * ls]; }, k, s, r, sigma, dummy);
+                if (akk * sigma >= alpha * lambda * lambda) {
+                    size = 1;
+                } else if (fabs(M[r + r * ls]) >= alpha * sigma) {
+                    size = 1;
+                    swap = r;
+                } else {
+                    size = 2;
+                    swap = r;
+                }
+            }
+            if (lane == 0) {
+                s_size = size;
+                s_swap = swap;
+                if (bad) s_bad = 1;
+            }
+        }
+        __syncthreads();
+        const int size = s_size, swap = s_swap, kp = size == 2 ? k + 1 : k;
+        if (s_bad) break;
+        // symmetric interchange of kp and swap: rows, then columns
+        if (swap != kp) {
+            for (int j = t; j < s; j += kThreads) {
+                const double a = M[kp + j * ls];
+                M[kp + j * ls] = M[swap + j * ls];
+                M[swap + j * ls] = a;
+            }
+            __syncthreads();
+            for (int i = t; i < s; i += kThreads) {
+                const double a = M[i + kp * ls];
+                M[i + kp * ls] = M[i + swap * ls];
+                M[i + swap * ls] = a;
+            }
+        }
+        if (t == 0) {
+            piv[kp] = swap;
+            if (size == 2) piv[k] = k;
+            bsz[k] = size;
+            if (size == 2) bsz[k + 1] = 0;
+        }
+        __syncthreads();
+        const int m = s - k - size;
+        if (size == 1) {
+            const double dk = M[k + k * ls];
+            if (dk == 0.0 || !isfinite(dk)) {
+                if (t == 0) s_bad = 1;
+                __syncthreads();
+                break;
+            }
+            // trailing update with the unscaled column, then the column of L
+            for (int e = t; e < m * m; e += kThreads) {
+                const int i = k + 1 + e % m, j = k + 1 + e / m;
+                M[i + j * ls] -= M[i + k * ls] * M[j + k * ls] / dk;
+            }
+            __syncthreads();
+            for (int i = k + 1 + t; i < s; i += kThreads) M[i + k * ls] /= dk;
+        } else {
+            const double a = M[k + k * ls], b = M[k + 1 + k * ls], c = M[k + 1 + (k + 1) * ls];
+            const double det = a * c - b * b;
+            if (det == 0.0 || !isfinite(det)) {
+                if (t == 0) s_bad = 1;
+                __syncthreads();
+                break;
+            }
+            // M(i,j) -= [M(i,k) M(i,k+1)] D^{-1} [M(j,k); M(j,k+1)]
+            for (int e = t; e < m * m; e += kThreads) {
+                const int i = k + 2 + e % m, j = k + 2 + e / m;
+                const double u = M[i + k * ls], v = M[i + (k + 1) * ls];
+                const double x = M[j + k * ls], y = M[j + (k + 1) * ls];
+                M[i + j * ls] -= (u * (c * x - b * y) + v * (a * y - b * x)) / det;
+            }
+            __syncthreads();
+            for (int i = k + 2 + t; i < s; i += kThreads) {
+                const double u = M[i + k * ls], v = M[i + (k + 1) * ls];
+                M[i + k * ls] = (u * c - v * b) / det;
+                M[i + (k + 1) * ls] = (v * a - u * b) / det;
+            }
+        }
+        __syncthreads();
+        k += size;
+    }
+    if (s_bad) {
+        if (t == 0) atomicMin(status, (unsigned long long)d.first);
+        return;
+    }
+    // T(:, j) = P^T L^{-T} D^{-1} L^{-1} P e_j, one thread per column
+    double* T = Tp + d.woff;
+    if (t < s) {
+        double* x = T + (int64_t)t * s;
+        for (int i = 0; i < s; ++i) x[i] = i == t ? 1.0 : 0.0;
+        for (int q = 0; q < s; ++q) {
+            const double a = x[q];
+            x[q] = x[piv[q]];
+            x[piv[q]] = a;
+        }
+        for (int q = 0; q < s; ++q) {
+            const int w = bsz[q];
+            if (w == 0) continue;
+            for (int i = q + w; i < s; ++i) {
+                double v = x[i] - M[i + q * ls] * x[q];
+                if (w == 2) v -= M[i + (q + 1) * ls] * x[q + 1];
+                x[i] = v;
+            }
+        }
+        for (int q = 0; q < s; ++q) {
+            if (bsz[q] == 1) {
+                x[q] /= M[q + q * ls];
+            } else if (bsz[q] == 2) {
+                const double a = M[q + q * ls], b = M[q + 1 + q * ls], c = M[q + 1 + (q + 1) * ls];
+                const double det = a * c - b * b, u = x[q], v = x[q + 1];
+                x[q] = (c * u - b * v) / det;
+                x[q + 1] = (a * v - b * u) / det;
+            }
+        }
+        for (int q = s - 1; q >= 0; --q) {
+            const int w = bsz[q];
+            if (w == 0) continue;
+            double u = x[q], v = w == 2 ? x[q + 1] : 0.0;
+            for (int i = q + w; i < s; ++i) {
+                u -= M[i + q * ls] * x[i];
+                if (w == 2) v -= M[i + (q + 1) * ls] * x[i];
+            }
+            x[q] = u;
+            if (w == 2) x[q + 1] = v;
+        }
+        for (int q = s - 1; q >= 0; --q) {
+            const double a = x[q];
+            x[q] = x[piv[q]];
+            x[piv[q]] = a;
+        }
+    }
+    __syncthreads();
+    // symmetrise: T := (T + T^T) / 2, through LDS (M is no longer needed)
+    for (int e = t; e < s * s; e += kThreads) M[e] = T[e];
+    __syncthreads();
+    for (int e = t; e < s * s; e += kThreads) {
+        const int i = e % s, j = e / s;
+        T[e] = 0.5 * (M[i + j * s] + M[j + i * s]);
+    }
+}
+
 // ===========================================================================
 // Small blocks (s <= 16, c <= 256): one wave runs a whole block, every phase
 // in turn, on 16 x 16 FP64 MFMA tiles (output rows in groups of 16, the
@@ -2489,8 +2703,17 @@ static inline unsigned grid_for(int64_t n)
 
 hipError_t kernels_init()
 {
-    // the reverse diagonal step needs more than the default 64 KB of LDS
-    return hipFuncSetAttribute((const void*)k_rf3, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsDiagBytes);
+    // the reverse diagonal step needs more than the default 64 KB of LDS;
+    // set once per process (a failure is not remembered: the next call tries again)
+    static std::atomic<bool> done{false};
+    if (done.load()) return hipSuccess;
+    hipError_t e =
+        hipFuncSetAttribute((const void*)k_rf3, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsDiagBytes);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)k_ldlt_bk, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)kLdsDiagBytes);
+    if (e == hipSuccess) done.store(true);
+    return e;
 }
 
 hipError_t launch_backward_init(Prof* P, const DevPtrs& D, int64_t arena, int64_t harena, const double* gsel,
@@ -2610,11 +2833,16 @@ hipError_t launch_sb_invert(Prof* P, const DevPtrs& D, int64_t sb0, int64_t nsb,
     return hipGetLastError();
 }
 
-hipError_t launch_factor_level(Prof* P, const DevPtrs& D, const int64_t diag[4], int64_t panel0, int64_t npanel,
-                               const int64_t* schur_cuts, int ncuts, int panel_deep, int flags, hipStream_t s)
+hipError_t launch_ldlt_bk(Prof* P, const DevPtrs& D, int64_t t0, int64_t n, hipStream_t s)
 {
-    const int require_spd = flags & 1;
-    if (flags & 2) panel_deep = 0;  // deterministic: one kernel per kind, whatever the level's size
+    if (n > 0)
+        launch(P, kLdlt, k_ldlt_bk, dim3((unsigned)n), kLdsDiagBytes, s, D.t_ldlt + t0, D.blocks, (const double*)D.Lp,
+               D.Tp, D.status);
+    return hipGetLastError();
+}
+
+hipError_t launch_ldlt_level(Prof* P, const DevPtrs& D, const int64_t diag[4], int require_spd, hipStream_t s)
+{
     // diagonal blocks by width class: [diag[0], diag[1]) s <= 32, then <= 64,
     // then wider
     if (diag[1] > diag[0])
@@ -2626,17 +2854,28 @@ hipError_t launch_factor_level(Prof* P, const DevPtrs& D, const int64_t diag[4],
     if (diag[3] > diag[2])
         launch(P, kLdlt, k_ldlt_diag<8>, dim3((unsigned)(diag[3] - diag[2])), 0, s, D.t_ldlt + diag[2], D.blocks,
                D.Lp, D.Wp, D.Tp, D.status, require_spd);
+    return hipGetLastError();
+}
+
+hipError_t launch_panel_level(Prof* P, const DevPtrs& D, int64_t panel0, int64_t npanel, int panel_deep, hipStream_t s)
+{
     // panel_deep: bit 0 the level's panel tiles take the whole-contraction
     // kernel; bit 1 its blocks are narrow enough for it (s <= kDeepK)
     if (npanel > 0)
         launch(P, kPanel, (panel_deep & 1) ? k_panel_deep : k_panel, dim3((unsigned)npanel), 0, s,
                D.t_panel + panel0, D.blocks, (const double*)D.Lp, D.Hp, (const double*)D.Tp);
+    return hipGetLastError();
+}
+
+hipError_t launch_schur_groups(Prof* P, const DevPtrs& D, const int64_t* cuts, int g0, int g1, int panel_deep,
+                               hipStream_t s)
+{
     // one launch per colour group (groups update disjoint entries)
-    for (int g = 0; g + 1 < ncuts; g++) {
-        const int64_t n = schur_cuts[g + 1] - schur_cuts[g];
+    for (int g = g0; g < g1; g++) {
+        const int64_t n = cuts[g + 1] - cuts[g];
         if (n > 0)
             launch(P, kSchur, (panel_deep & 2) && n <= kDeepMaxTiles ? k_schur_deep : k_schur, dim3((unsigned)n), 0, s,
-                   D.t_schur + schur_cuts[g], D.blocks, D.Lp, (const double*)D.Hp, D.cbase, D.rbase, D.rel);
+                   D.t_schur + cuts[g], D.blocks, D.Lp, (const double*)D.Hp, D.cbase, D.rbase, D.rel);
     }
     return hipGetLastError();
 }

@@ -51,11 +51,16 @@ hipError_t launch_scatter_set(Prof* P, int kind, const double* src, const int64_
                               hipStream_t s);
 hipError_t launch_gather(Prof* P, int kind, const double* src, const int64_t* off, int64_t n, double* dst,
                          hipStream_t s);
-// diag[0..3]: the level's diagonal-block tasks for s <= 32, <= 64 and wider;
-// flags bit 0 require_spd, bit 1 deterministic (the tiled kernels only, no
-// whole-contraction variants)
-hipError_t launch_factor_level(Prof* P, const DevPtrs& D, const int64_t diag[4], int64_t panel0, int64_t npanel,
-                               const int64_t* schur_cuts, int ncuts, int panel_deep, int flags, hipStream_t s);
+// diagonal blocks t_ldlt[t0 .. t0+n) with 1x1/2x2 (Bunch-Kaufman) pivots: T only
+hipError_t launch_ldlt_bk(Prof* P, const DevPtrs& D, int64_t t0, int64_t n, hipStream_t s);
+// diag[0..3]: the level's diagonal-block tasks for s <= 32, <= 64 and wider
+hipError_t launch_ldlt_level(Prof* P, const DevPtrs& D, const int64_t diag[4], int require_spd, hipStream_t s);
+// panel_deep bit 0: whole-contraction panel kernel; bit 1: whole-contraction
+// Schur kernel allowed for small groups (0 in the deterministic mode)
+hipError_t launch_panel_level(Prof* P, const DevPtrs& D, int64_t panel0, int64_t npanel, int panel_deep, hipStream_t s);
+// Schur colour groups [g0, g1) of a level, cuts as in schur_cuts
+hipError_t launch_schur_groups(Prof* P, const DevPtrs& D, const int64_t* cuts, int g0, int g1, int panel_deep,
+                               hipStream_t s);
 // diagonal-step tasks t_sdiag[sdiag0 .. sdiag_cut) then [sdiag_cut .. sdiag1),
 // as two launches
 hipError_t launch_invert_level(Prof* P, const DevPtrs& D, int64_t gemm0, int64_t ngemm, int64_t sdiag0,
@@ -72,6 +77,15 @@ hipError_t launch_persist_invert(Prof* P, const DevPtrs& D, const Task* q, int64
 // small-block path of one level (per-level launches)
 hipError_t launch_sb_factor(Prof* P, const DevPtrs& D, int64_t sb0, int64_t nsb, int require_spd, hipStream_t s);
 hipError_t launch_sb_invert(Prof* P, const DevPtrs& D, int64_t sb0, int64_t nsb, hipStream_t s);
+
+// complex-symmetric path (zkernels.hip): values are (re, im) pairs; the level
+// lists are those of the deterministic schedule (blocks of at most 64 columns)
+hipError_t launch_zassemble(const double* vals, const int64_t* off, int64_t n, double* Lp, hipStream_t s);
+hipError_t launch_zexport(const double* Ap, const int64_t* off, int64_t n, double* out, hipStream_t s);
+hipError_t launch_zfactor_level(const DevPtrs& D, int64_t diag0, int64_t ndiag, int64_t panel0, int64_t npanel,
+                                const int64_t* schur_cuts, int ncuts, hipStream_t s);
+hipError_t launch_zinvert_level(const DevPtrs& D, int64_t gemm0, int64_t ngemm, int64_t sdiag0, int64_t nsdiag,
+                                hipStream_t s);
 
 // Launch sequences and helpers of the C ABI (capi.cpp), shared with the
 // static-scratch entry point.

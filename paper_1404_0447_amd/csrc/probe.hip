@@ -39,11 +39,20 @@ __global__ __launch_bounds__(kProbeThreads) void k_mfma_peak(double* __restrict_
     out[blockIdx.x * (int64_t)kProbeThreads + threadIdx.x] = s;
 }
 
-// dst = src, 16 bytes per thread and iteration, grid-stride
+// dst = src: each thread moves four 16-byte elements per iteration (all four
+// loads issued before the stores), grid-stride; the tail element by element
 __global__ __launch_bounds__(kProbeThreads) void k_copy(const pd2* __restrict__ src, pd2* __restrict__ dst, int64_t n)
 {
     const int64_t stride = (int64_t)gridDim.x * kProbeThreads;
-    for (int64_t i = blockIdx.x * (int64_t)kProbeThreads + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+    const int64_t n4 = n / (4 * stride) * (4 * stride);
+    for (int64_t i = blockIdx.x * (int64_t)kProbeThreads + threadIdx.x; i < n4; i += 4 * stride) {
+        const pd2 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+        dst[i] = a;
+        dst[i + stride] = b;
+        dst[i + 2 * stride] = c;
+        dst[i + 3 * stride] = d;
+    }
+    for (int64_t i = n4 + blockIdx.x * (int64_t)kProbeThreads + threadIdx.x; i < n; i += stride) dst[i] = src[i];
 }
 
 thread_local std::string g_probe_err;
@@ -85,7 +94,7 @@ extern "C" selinv_status selinv_measure_peaks(void* d_buf, size_t bytes, double*
     const int64_t n = (int64_t)(bytes / 2 / sizeof(pd2));
     const pd2* src = (const pd2*)d_buf;
     pd2* dst = (pd2*)d_buf + n;
-    const int cgroups = prop.multiProcessorCount * 16;
+    const int cgroups = prop.multiProcessorCount * 8;
     for (int r = 0; r < 5 && !e; r++) {
         e = hipEventRecord(e0, s);
         hipLaunchKernelGGL(k_copy, dim3(cgroups), dim3(kProbeThreads), 0, s, src, dst, n);

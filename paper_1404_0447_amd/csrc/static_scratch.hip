@@ -65,7 +65,7 @@ extern "C" selinv_status selinv_factor_invert_static(selinv_plan P, const double
         if (P->static_uid == 0) P->static_uid = g_next_uid++;
         // the tables only when the array holds another plan's
         if (g_owner[dev] != P->static_uid) {
-            static hipError_t init = kernels_init();
+            const hipError_t init = kernels_init();
             if (init) return set_error(SELINV_EHIP, std::string("kernel attributes: ") + hipGetErrorString(init));
             e = upload_tables(P, base, s);
             if (e) {

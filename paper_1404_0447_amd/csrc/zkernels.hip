@@ -1,0 +1,329 @@
+// Complex-symmetric path: the same supernodal LDL^T and selected inversion
+// (Algorithm 1) for A(z) = H - z S, the matrices of the pole expansion
+// (Section 4.3).  Values are complex (re, im interleaved, 16 bytes each);
+// every transpose is a plain transpose, never a conjugate.  Blocks are at
+// most 64 columns wide; the plan's level schedule is the deterministic one
+// (no split contractions, Schur updates in colour groups), so no kernel
+// here needs atomics.  Products run on the FP64 vector units: a 64 x 64
+// complex output tile per work-group, each thread a 4 x 4 patch, operands
+// staged through LDS in 16-deep chunks.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+#include "plan.hpp"
+#include "tiles.hpp"
+
+namespace selinv {
+namespace {
+
+typedef double z2 __attribute__((ext_vector_type(2)));  // (re, im)
+
+__device__ __forceinline__ z2 zmul(z2 a, z2 b) { return z2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+__device__ __forceinline__ void zfma(z2& acc, z2 a, z2 b)
+{
+    acc.x = fma(a.x, b.x, fma(-a.y, b.y, acc.x));
+    acc.y = fma(a.x, b.y, fma(a.y, b.x, acc.y));
+}
+__device__ __forceinline__ z2 zdiv(z2 a, z2 b)
+{
+    const double den = b.x * b.x + b.y * b.y;
+    return z2{(a.x * b.x + a.y * b.y) / den, (a.y * b.x - a.x * b.y) / den};
+}
+
+constexpr int kZT = 64;  // output tile edge
+constexpr int kZK = 16;  // contraction chunk
+
+struct ZLds {
+    z2 a[kZK][kZT + 1];
+    z2 b[kZK][kZT + 1];
+};
+
+// acc[u][v] += sum over k < K of A(i, k) B(k, j), i = 4 tx + u, j = 4 ty + v;
+// loadA(k, i), loadB(k, j) return 0 outside the operands.
+template <class LA, class LB>
+__device__ __forceinline__ void ztile(ZLds& L, int K, z2 (&acc)[4][4], LA loadA, LB loadB)
+{
+    const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+    for (int k0 = 0; k0 < K; k0 += kZK) {
+#pragma unroll
+        for (int q = 0; q < (kZK * kZT) / kThreads; ++q) {
+            const int e = t + q * kThreads, kk = e / kZT, i = e % kZT;
+            L.a[kk][i] = loadA(k0 + kk, i);
+            L.b[kk][i] = loadB(k0 + kk, i);
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < kZK; ++kk) {
+            z2 a[4], b[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                a[u] = L.a[kk][4 * tx + u];
+                b[u] = L.b[kk][4 * ty + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) zfma(acc[u][v], a[u], b[v]);
+        }
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ z2 zload(const double* p, int64_t e) { return *reinterpret_cast<const z2*>(p + 2 * e); }
+__device__ __forceinline__ void zstore(double* p, int64_t e, z2 v) { *reinterpret_cast<z2*>(p + 2 * e) = v; }
+
+// ---------------------------------------------------------------------------
+// diagonal block: F_KK = L_KK D_K L_KK^T (unit lower L, complex pivots), then
+// T_K = F_KK^{-1} = L^{-T} D^{-1} L^{-1}.  One work-group per block, s <= 64,
+// the block in LDS.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_zdiag(const Task* __restrict__ tasks, const BlockDesc* __restrict__ blk,
+                                                    double* __restrict__ Lp, double* __restrict__ Tp,
+                                                    unsigned long long* __restrict__ status)
+{
+    __shared__ z2 F[kZT][kZT + 1];  // F[i][j]: row i, column j (lower part used)
+    __shared__ z2 T[kZT][kZT + 1];
+    const BlockDesc d = blk[tasks[blockIdx.x].b];
+    const int s = d.s, t = threadIdx.x;
+    const int64_t ld = (int64_t)d.s + d.c;
+    for (int e = t; e < s * s; e += kThreads) {
+        const int i = e % s, j = e / s;
+        if (i >= j) F[i][j] = zload(Lp, d.poff + i + (int64_t)j * ld);
+    }
+    __syncthreads();
+    bool ok = true;
+    for (int j = 0; j < s; ++j) {
+        const z2 dj = F[j][j];
+        ok = ok && (dj.x != 0.0 || dj.y != 0.0) && isfinite(dj.x) && isfinite(dj.y);
+        // trailing update: F(i,k) -= F(i,j) F(k,j) / d_j for j < k <= i
+        const int m = s - j - 1, pairs = m * (m + 1) / 2;
+        for (int e = t; e < pairs; e += kThreads) {
+            // e -> (i, k), k <= i, both in (j, s)
+            int kk = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+            while ((kk + 1) * (kk + 2) / 2 <= e) ++kk;
+            while (kk * (kk + 1) / 2 > e) --kk;
+            const int ii = e - kk * (kk + 1) / 2;  // ii <= kk
+            const int i = j + 1 + kk, k = j + 1 + ii;
+            F[i][k] -= zdiv(zmul(F[i][j], F[k][j]), dj);
+        }
+        __syncthreads();
+        // column j of L
+        for (int i = j + 1 + t; i < s; i += kThreads) F[i][j] = zdiv(F[i][j], dj);
+        __syncthreads();
+    }
+    if (!ok) {
+        if (t == 0) {
+            int bad = s;
+            for (int j = 0; j < s; ++j)
+                if (!((F[j][j].x != 0.0 || F[j][j].y != 0.0) && isfinite(F[j][j].x) && isfinite(F[j][j].y))) {
+                    bad = j;
+                    break;
+                }
+            atomicMin(status, (unsigned long long)(d.first + (bad < s ? bad : 0)));
+        }
+        return;
+    }
+    // T(:, j) solves L D L^T x = e_j: one thread per column
+    if (t < s) {
+        const int j = t;
+        for (int i = 0; i < s; ++i) T[i][j] = z2{i == j ? 1.0 : 0.0, 0.0};
+        for (int i = 0; i < s; ++i)
+            for (int k = 0; k < i; ++k) T[i][j] -= zmul(F[i][k], T[k][j]);
+        for (int i = 0; i < s; ++i) T[i][j] = zdiv(T[i][j], F[i][i]);
+        for (int i = s - 1; i >= 0; --i)
+            for (int k = i + 1; k < s; ++k) T[i][j] -= zmul(F[k][i], T[k][j]);
+    }
+    __syncthreads();
+    for (int e = t; e < s * s; e += kThreads) {
+        const int i = e % s, j = e / s;
+        if (i >= j) zstore(Lp, d.poff + i + (int64_t)j * ld, F[i][j]);
+        zstore(Tp, d.woff + i + (int64_t)j * s, T[i][j]);
+    }
+}
+
+// L_hat(C,K) rows [r0, r0+64) = F(C,K) T_K
+__global__ __launch_bounds__(kThreads) void k_zpanel(const Task* __restrict__ tasks, const BlockDesc* __restrict__ blk,
+                                                     const double* __restrict__ Lp, double* __restrict__ Hp,
+                                                     const double* __restrict__ Tp)
+{
+    __shared__ ZLds L;
+    const Task tk = tasks[blockIdx.x];
+    const BlockDesc d = blk[tk.b];
+    const int s = d.s, c = d.c, r0 = tk.i0;
+    const int64_t ld = (int64_t)s + c;
+    z2 acc[4][4] = {};
+    ztile(L, s, acc,
+          [&](int k, int i) { return (k < s && r0 + i < c) ? zload(Lp, d.poff + s + r0 + i + (int64_t)k * ld) : z2{0, 0}; },
+          [&](int k, int j) { return (k < s && j < s) ? zload(Tp, d.woff + k + (int64_t)j * s) : z2{0, 0}; });
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = r0 + 4 * tx + u, j = 4 * ty + v;
+            if (i < c && j < s) zstore(Hp, d.hoff + i + (int64_t)j * c, acc[u][v]);
+        }
+}
+
+// Schur update of one 64 x 64 lower tile (rows i0.., columns k0.. of C):
+// F(C[i], C[k]) -= sum_t L_hat(i, t) F(C[k], t), scattered into the owning
+// ancestor panels; the tasks of one launch touch disjoint entries.
+__global__ __launch_bounds__(kThreads) void k_zschur(const Task* __restrict__ tasks, const BlockDesc* __restrict__ blk,
+                                                     double* __restrict__ Lp, const double* __restrict__ Hp,
+                                                     const int64_t* __restrict__ cbase,
+                                                     const int64_t* __restrict__ rbase, const int32_t* __restrict__ rel)
+{
+    __shared__ ZLds L;
+    const Task tk = tasks[blockIdx.x];
+    const BlockDesc d = blk[tk.b];
+    const int s = d.s, c = d.c, i0 = tk.i0, k0 = tk.j0;
+    const int64_t ld = (int64_t)s + c;
+    z2 acc[4][4] = {};
+    ztile(L, s, acc,
+          [&](int t, int i) { return (t < s && i0 + i < c) ? zload(Hp, d.hoff + i0 + i + (int64_t)t * c) : z2{0, 0}; },
+          [&](int t, int k) { return (t < s && k0 + k < c) ? zload(Lp, d.poff + s + k0 + k + (int64_t)t * ld) : z2{0, 0}; });
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int ii = i0 + 4 * tx + u, kk = k0 + 4 * ty + v;
+            if (ii < c && kk < c && ii >= kk) {
+                const int64_t pk = d.coff + kk;
+                const int64_t e = cbase[pk] + rel[rbase[pk] + ii];
+                zstore(Lp, e, zload(Lp, e) - acc[u][v]);
+            }
+        }
+}
+
+// Ainv(C,K) rows [r0, r0+64) = -G L_hat with G = Ainv(C,C) gathered from the
+// ancestors' inverse panels (lower entries; the upper ones by symmetry)
+__global__ __launch_bounds__(kThreads) void k_zgemm(const Task* __restrict__ tasks, const BlockDesc* __restrict__ blk,
+                                                    double* __restrict__ Ap, const double* __restrict__ Hp,
+                                                    const int64_t* __restrict__ cbase,
+                                                    const int64_t* __restrict__ rbase, const int32_t* __restrict__ rel)
+{
+    __shared__ ZLds L;
+    const Task tk = tasks[blockIdx.x];
+    const BlockDesc d = blk[tk.b];
+    const int s = d.s, c = d.c, r0 = tk.i0;
+    const int64_t ld = (int64_t)s + c;
+    z2 acc[4][4] = {};
+    ztile(L, c, acc,
+          [&](int k, int i) {
+              const int ii = r0 + i;
+              if (k >= c || ii >= c) return z2{0, 0};
+              const int lo = ii >= k ? ii : k, hi = ii >= k ? k : ii;  // G(lo, hi), lo >= hi
+              const int64_t ph = d.coff + hi;
+              return zload(Ap, cbase[ph] + rel[rbase[ph] + lo]);
+          },
+          [&](int k, int j) { return (k < c && j < s) ? zload(Hp, d.hoff + k + (int64_t)j * c) : z2{0, 0}; });
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = r0 + 4 * tx + u, j = 4 * ty + v;
+            if (i < c && j < s) zstore(Ap, d.poff + s + i + (int64_t)j * ld, -acc[u][v]);
+        }
+}
+
+// Ainv(K,K) = T - (P + P^T) / 2 with P = L_hat^T Ainv(C,K) (lower triangle)
+__global__ __launch_bounds__(kThreads) void k_zsdiag(const Task* __restrict__ tasks, const BlockDesc* __restrict__ blk,
+                                                     double* __restrict__ Ap, const double* __restrict__ Hp,
+                                                     const double* __restrict__ Tp)
+{
+    __shared__ ZLds L;
+    __shared__ z2 P[kZT][kZT + 1];  // P, for the transpose
+    const Task tk = tasks[blockIdx.x];
+    const BlockDesc d = blk[tk.b];
+    const int s = d.s, c = d.c;
+    const int64_t ld = (int64_t)s + c;
+    z2 acc[4][4] = {};
+    ztile(L, c, acc,
+          [&](int r, int i) { return (r < c && i < s) ? zload(Hp, d.hoff + r + (int64_t)i * c) : z2{0, 0}; },
+          [&](int r, int j) { return (r < c && j < s) ? zload(Ap, d.poff + s + r + (int64_t)j * ld) : z2{0, 0}; });
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) P[4 * tx + u][4 * ty + v] = acc[u][v];
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = 4 * tx + u, j = 4 * ty + v;
+            if (i < s && j < s && i >= j) {
+                const z2 p = 0.5 * (P[i][j] + P[j][i]);
+                zstore(Ap, d.poff + i + (int64_t)j * ld, zload(Tp, d.woff + i + (int64_t)j * s) - p);
+            }
+        }
+}
+
+// assemble: panel entry off[q] (a complex element) := value q; export: out
+// entry q := panel entry off[q]
+__global__ void k_zscatter(const double* __restrict__ src, const int64_t* __restrict__ off, int64_t n,
+                           double* __restrict__ dst)
+{
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+        zstore(dst, off[q], zload(src, q));
+}
+
+__global__ void k_zgather(const double* __restrict__ src, const int64_t* __restrict__ off, int64_t n,
+                          double* __restrict__ dst)
+{
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+        zstore(dst, q, zload(src, off[q]));
+}
+
+unsigned zgrid(int64_t n)
+{
+    int64_t g = (n + kThreads - 1) / kThreads;
+    return (unsigned)(g < 1 ? 1 : g > 65536 ? 65536 : g);
+}
+}  // namespace
+
+hipError_t launch_zassemble(const double* vals, const int64_t* off, int64_t n, double* Lp, hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(k_zscatter, dim3(zgrid(n)), dim3(kThreads), 0, s, vals, off, n, Lp);
+    return hipGetLastError();
+}
+
+hipError_t launch_zexport(const double* Ap, const int64_t* off, int64_t n, double* out, hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(k_zgather, dim3(zgrid(n)), dim3(kThreads), 0, s, Ap, off, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_zfactor_level(const DevPtrs& D, int64_t diag0, int64_t ndiag, int64_t panel0, int64_t npanel,
+                                const int64_t* schur_cuts, int ncuts, hipStream_t s)
+{
+    if (ndiag > 0)
+        hipLaunchKernelGGL(k_zdiag, dim3((unsigned)ndiag), dim3(kThreads), 0, s, D.t_ldlt + diag0, D.blocks, D.Lp,
+                           D.Tp, D.status);
+    if (npanel > 0)
+        hipLaunchKernelGGL(k_zpanel, dim3((unsigned)npanel), dim3(kThreads), 0, s, D.t_panel + panel0, D.blocks,
+                           (const double*)D.Lp, D.Hp, (const double*)D.Tp);
+    for (int g = 0; g + 1 < ncuts; g++) {
+        const int64_t n = schur_cuts[g + 1] - schur_cuts[g];
+        if (n > 0)
+            hipLaunchKernelGGL(k_zschur, dim3((unsigned)n), dim3(kThreads), 0, s, D.t_schur + schur_cuts[g], D.blocks,
+                               D.Lp, (const double*)D.Hp, D.cbase, D.rbase, D.rel);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_zinvert_level(const DevPtrs& D, int64_t gemm0, int64_t ngemm, int64_t sdiag0, int64_t nsdiag,
+                                hipStream_t s)
+{
+    if (ngemm > 0)
+        hipLaunchKernelGGL(k_zgemm, dim3((unsigned)ngemm), dim3(kThreads), 0, s, D.t_gemm + gemm0, D.blocks, D.Ap,
+                           (const double*)D.Hp, D.cbase, D.rbase, D.rel);
+    if (nsdiag > 0)
+        hipLaunchKernelGGL(k_zsdiag, dim3((unsigned)nsdiag), dim3(kThreads), 0, s, D.t_sdiag + sdiag0, D.blocks,
+                           D.Ap, (const double*)D.Hp, (const double*)D.Tp);
+    return hipGetLastError();
+}
+
+}  // namespace selinv

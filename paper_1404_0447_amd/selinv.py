@@ -25,7 +25,8 @@ EXPORTS = ["selinv_analyze", "selinv_workspace_size", "selinv_workspace_sizes", 
            "selinv_get_factor", "selinv_sync_status", "selinv_get_info", "selinv_get_pattern",
            "selinv_symbolic_sizes", "selinv_get_symbolic", "selinv_profile", "selinv_profile_read",
            "selinv_kernel_work", "selinv_get_arena", "selinv_get_blocks", "selinv_get_exec_rows",
-           "selinv_analyze_batch", "selinv_batch_offsets", "selinv_set_schedule", "selinv_get_schedule",
+           "selinv_analyze_batch", "selinv_analyze_poles", "selinv_factor_complex", "selinv_invert_complex",
+           "selinv_batch_offsets", "selinv_set_schedule", "selinv_get_schedule",
            "selinv_get_queue", "selinv_set_spin_limit", "selinv_run", "selinv_tune", "selinv_measure_peaks",
            "selinv_factor_invert_static", "selinv_last_error", "selinv_destroy"]
 STATIC_SCRATCH_BYTES = 64 << 20
@@ -50,13 +51,14 @@ class Geom(ct.Structure):
 class Opts(ct.Structure):
     _fields_ = [("max_super", ct.c_int32), ("fuse_chains", ct.c_int32), ("require_spd", ct.c_int32),
                 ("exec_cap", ct.c_int32), ("sep_order", ct.c_int32), ("deterministic", ct.c_int32),
-                ("checkpoint_every", ct.c_int32), ("relaxed", ct.c_int32)]
+                ("checkpoint_every", ct.c_int32), ("relaxed", ct.c_int32), ("complex_values", ct.c_int32)]
 
 
-def _opts(max_super, fuse_chains, require_spd, exec_cap, sep_order, deterministic, checkpoint_every, relaxed):
+def _opts(max_super, fuse_chains, require_spd, exec_cap, sep_order, deterministic, checkpoint_every, relaxed,
+          complex_values=False):
     so = {"lex": 0, "rim_last": 1}.get(sep_order, sep_order)
     return Opts(int(max_super), int(bool(fuse_chains)), int(bool(require_spd)), int(exec_cap), int(so),
-                int(bool(deterministic)), int(checkpoint_every), int(bool(relaxed)))
+                int(bool(deterministic)), int(checkpoint_every), int(bool(relaxed)), int(bool(complex_values)))
 
 
 class Sched(ct.Structure):
@@ -106,6 +108,9 @@ def lib():
         L.selinv_get_blocks.argtypes = [vp] + [vp] * 8
         L.selinv_get_exec_rows.argtypes = [vp, vp]
         L.selinv_analyze_batch.argtypes = [i32, vp, vp, vp, vp, vp, ct.POINTER(vp)]
+        L.selinv_analyze_poles.argtypes = [i64, vp, vp, vp, vp, vp, i32, ct.POINTER(vp)]
+        L.selinv_factor_complex.argtypes = [vp, vp, vp]
+        L.selinv_invert_complex.argtypes = [vp, vp, vp]
         L.selinv_batch_offsets.argtypes = [vp, ct.POINTER(i32), vp, vp, vp]
         L.selinv_set_schedule.argtypes = [vp, ct.POINTER(Sched), vp]
         L.selinv_get_schedule.argtypes = [vp, ct.POINTER(Sched)]
@@ -146,7 +151,7 @@ class Plan:
 
     def __init__(self, n, colptr, rowind, geom=None, perm=None, max_super=128, fuse_chains=True,
                  require_spd=True, exec_cap=0, sep_order=0, deterministic=False, checkpoint_every=1,
-                 relaxed=False, _handle=None):
+                 relaxed=False, complex_values=False, _handle=None):
         L = lib()
         self.n = int(n)
         if _handle is not None:
@@ -162,7 +167,7 @@ class Plan:
             g = Geom(int(ndim), (ct.c_int32 * 3)(*[int(x) for x in d3[:3]]), int(dofs))
         pm = None if perm is None else np.ascontiguousarray(perm, dtype=np.int32)
         o = _opts(max_super, fuse_chains, require_spd, exec_cap, sep_order, deterministic, checkpoint_every,
-                  relaxed)
+                  relaxed, complex_values)
         self.checkpoint_every = max(1, int(checkpoint_every))
         self.deterministic = bool(deterministic)
         h = ct.c_void_p()
@@ -213,6 +218,26 @@ class Plan:
         _check(st)
         p = cls(int(ns.sum()), None, None, _handle=h)
         p.checkpoint_every, p.deterministic = max(1, int(checkpoint_every)), bool(deterministic)
+        return p
+
+    @classmethod
+    def poles(cls, m, count, max_super=128, fuse_chains=True, exec_cap=0, sep_order=0, relaxed=False):
+        """One analysis of the pattern of workloads.Matrix m for `count` complex
+        matrices A(z_k) = H - z_k S on that pattern (block-diagonal union, one
+        launch per level for all poles)."""
+        L = lib()
+        cp = np.ascontiguousarray(m.colptr, dtype=np.int64)
+        ri = np.ascontiguousarray(m.rowind, dtype=np.int32)
+        g = None
+        if m.ndim > 0:
+            d3 = list(m.dims) + [1] * (3 - len(m.dims))
+            g = Geom(int(m.ndim), (ct.c_int32 * 3)(*[int(x) for x in d3[:3]]), int(m.dofs))
+        o = _opts(max_super, fuse_chains, False, exec_cap, sep_order, False, 1, relaxed, True)
+        h = ct.c_void_p()
+        _check(L.selinv_analyze_poles(m.n, _p(cp), _p(ri), ct.byref(g) if g is not None else None, None, ct.byref(o),
+                                      int(count), ct.byref(h)))
+        p = cls(m.n * int(count), None, None, _handle=h)
+        p.deterministic = True
         return p
 
     @classmethod
@@ -303,6 +328,29 @@ class Plan:
         self._need(out, nnzL, "out")
         self._ensure_transient()
         _check(lib().selinv_invert(self._h, ct.c_void_p(out.data_ptr()), _stream(stream)))
+        return out
+
+    def _need_z(self, t, n, name):
+        import torch
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()
+                and t.numel() == n):
+            raise ValueError(f"{name}: expected a contiguous complex128 CUDA tensor with {n} entries")
+
+    def factor_complex(self, vals, stream=None):
+        """LDL^T of a complex symmetric matrix (complex128 values on A's pattern)."""
+        if not self._bound:
+            self.bind(device=vals.device)
+        self._need_z(vals, int(self.info["nnzA"]), "vals")
+        _check(lib().selinv_factor_complex(self._h, ct.c_void_p(vals.data_ptr()), _stream(stream)))
+
+    def invert_complex(self, out=None, stream=None):
+        import torch
+        nnzL = int(self.info["nnzL"])
+        if out is None:
+            out = torch.empty(nnzL, dtype=torch.complex128, device=self._ws.device)
+        self._need_z(out, nnzL, "out")
+        self._ensure_transient()
+        _check(lib().selinv_invert_complex(self._h, ct.c_void_p(out.data_ptr()), _stream(stream)))
         return out
 
     def backward(self, gsel, out=None, stream=None):

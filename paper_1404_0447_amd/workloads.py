@@ -270,6 +270,69 @@ def molecular(side=16, dofs=8, cutoff=1.8, jitter=0.1, seed=4, shift=None):
                             jitter=jitter, seed=seed, shift=shift))
 
 
+def hamiltonian_overlap(side=8, dofs=8, cutoff=1.8, jitter=0.1, seed=6):
+    """A pair (H, S) on one pattern, for the pole expansion A(z) = H - z S.
+
+    H is the block matrix of ``molecular`` with no diagonal shift (real
+    symmetric, indefinite).  S has the same lower pattern: identity plus
+    0.1 x N(0,1) entries (stream 2 of the same seed; self blocks symmetrised
+    through the lower-triangle storage), then shifted on the diagonal so that
+    its smallest eigenvalue (Lanczos) is at least 0.5 (positive definite, like
+    an overlap matrix of a localized basis).  Returns (H, S) as Matrix
+    objects with identical colptr/rowind."""
+    H = molecular(side=side, dofs=dofs, cutoff=cutoff, jitter=jitter, seed=seed, shift=0.0)
+    g = SplitMix64(seed, 2)
+    v = 0.1 * g.normal(H.nnz)
+    v[H.colptr[:-1]] += 1.0
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    low = sp.csc_matrix((v, H.rowind, H.colptr), shape=(H.n, H.n))
+    full = low + sp.tril(low, -1).T
+    lam = spla.eigsh(full, k=1, which="SA", tol=1e-8, return_eigenvectors=False, v0=np.ones(H.n))[0]
+    shift = max(0.0, math.ceil((0.5 - lam) * 1000.0) / 1000.0)
+    v[H.colptr[:-1]] += shift
+    S = Matrix(H.n, H.colptr, H.rowind, v, ndim=H.ndim, dims=H.dims, dofs=H.dofs,
+               meta=dict(kind="overlap", seed=seed, shift=shift))
+    H.meta["kind"] = "hamiltonian"
+    return H, S
+
+
+def indefinite_molecular(side=4, dofs=8, cutoff=1.8, jitter=0.1, seed=8, coupling=0.08):
+    """Symmetric indefinite block matrix whose diagonal blocks need 2x2
+    pivots.  On the ``molecular`` pattern, every atom's self block is the
+    saddle-point block [[0, I], [I, 0]] (basis functions 0..dofs/2-1 paired
+    with dofs/2..dofs-1, eigenvalues +1 and -1, zero diagonal), and every
+    other entry is ``coupling`` times the ``molecular`` value (N(0,1)
+    entries, no shift); the diagonal stays exactly 0.  An LDL^T with 1x1
+    pivots and no interchanges stops at the first column; 2x2 pivots inside
+    the diagonal blocks do not."""
+    m = molecular(side=side, dofs=dofs, cutoff=cutoff, jitter=jitter, seed=seed, shift=0.0)
+    v = coupling * m.vals
+    cols = np.repeat(np.arange(m.n), np.diff(m.colptr))
+    rows = m.rowind.astype(np.int64)
+    same_atom = rows // dofs == cols // dofs
+    v[same_atom] = 0.0
+    h = dofs // 2
+    pair = same_atom & (rows % dofs == cols % dofs + h) & (cols % dofs < h)
+    v[pair] = 1.0
+    return Matrix(m.n, m.colptr, m.rowind, v, ndim=m.ndim, dims=m.dims, dofs=m.dofs,
+                  meta=dict(kind="indefinite", side=side, dofs=dofs, seed=seed, coupling=coupling))
+
+
+def poles(count, center, radius):
+    """Poles z_k = center + radius * exp(i pi (k + 1/2) / count), k < count:
+    points on the upper half of a circle around the spectrum, never real
+    (Im z > 0 keeps A(z) = H - z S nonsingular for SPD S)."""
+    k = np.arange(count)
+    return center + radius * np.exp(1j * np.pi * (k + 0.5) / count)
+
+
+def pencil_values(H, S, z):
+    """Values of A(z) = H - z S on the common lower pattern (complex)."""
+    assert np.array_equal(H.colptr, S.colptr) and np.array_equal(H.rowind, S.rowind)
+    return H.vals - z * S.vals
+
+
 def fig1_pattern():
     """The 29x29 example of Fig. 1 (Section 2.1): lower pattern, 0-based.
 

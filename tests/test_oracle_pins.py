@@ -517,3 +517,163 @@ def test_relaxed_partition_hand_example():
     assert list(s.xsuper) == [0, 4, 8, 10]
     assert [list(s.crows[s.cptr[k]:s.cptr[k + 1]]) for k in range(s.N)] == [[4], [8], []]
     assert s.nnzL == (10 + 4) + (10 + 4) + 3
+
+
+# ---------------------------------------------------------------- complex symmetric A(z) = H - z S
+def _complex_cases():
+    H, S = W.hamiltonian_overlap(side=3, dofs=8, seed=6)
+    z = W.poles(4, 0.0, 30.0)
+    m = W.random_spd_pattern(90, 0.05, 13)
+    on_diag = m.rowind == np.repeat(np.arange(m.n), np.diff(m.colptr))
+    return {
+        "pencil_pole0": (H, W.pencil_values(H, S, z[0]), 32),
+        "pencil_pole3": (H, W.pencil_values(H, S, z[3]), 16),
+        "random_shifted": (m, m.vals - (1.5 + 0.7j) * on_diag, 8),
+    }
+
+
+def _dense_complex(m, vals):
+    a = np.zeros((m.n, m.n), dtype=np.complex128)
+    cols = np.repeat(np.arange(m.n), np.diff(m.colptr))
+    a[m.rowind, cols] = vals
+    a[cols, m.rowind] = vals
+    return a
+
+
+@pytest.mark.parametrize("name", ["pencil_pole0", "pencil_pole3", "random_shifted"])
+def test_complex_tiers_against_library_inverse(name):
+    """O1 and O3 for a complex symmetric matrix against a library inverse
+    (numpy's LU, no symmetry used), restricted to the pattern; symmetric, not
+    Hermitian, so a conjugate anywhere would fail; row identity."""
+    m, vals, cap = _complex_cases()[name]
+    a = _dense_complex(m, vals)
+    exact = np.linalg.inv(a)
+    assert np.max(np.abs(O.dense_inverse_complex(a) - exact)) <= 1e-12 * np.max(np.abs(exact))
+    osym = O.symbolic(m, cap=cap, perm="nd" if m.ndim > 0 else "natural")
+    s = osym.sym
+    sel, st, _ = osym.factor_selinv_complex(vals)
+    assert st == 0
+    cols = np.repeat(np.arange(m.n), np.diff(s.colptrL))
+    ref = exact[s.perm[s.rowindL], s.perm[cols]]
+    d = np.abs(ref[s.colptrL[:-1]])
+    scale = np.sqrt(d[s.rowindL] * d[cols])
+    assert np.max(np.abs(sel - ref) / scale) <= 1e-11
+    # sum_j A_ij Ainv_ji = 1 using selected entries only
+    full = {}
+    for q, (i, j) in enumerate(zip(s.perm[s.rowindL], s.perm[cols])):
+        full[(i, j)] = full[(j, i)] = sel[q]
+    r = np.zeros(m.n, dtype=np.complex128)
+    acols = np.repeat(np.arange(m.n), np.diff(m.colptr))
+    for i, j, v in zip(m.rowind, acols, vals):
+        r[i] += v * full[(j, i)]
+        if i != j:
+            r[j] += v * full[(i, j)]
+    assert np.max(np.abs(r - 1.0)) <= 1e-10
+
+
+@pytest.mark.parametrize("n,z", [(40, 0.3 + 0.5j), (61, -1.0 + 0.2j), (25, 3.0 - 2.0j)])
+def test_complex_tridiagonal_closed_form(n, z):
+    """tridiag(-1, 2 - z, -1): (A^{-1})_ij = sinh(i t) sinh((n+1-j) t) / (sinh t sinh((n+1) t))
+    for i <= j (1-based), cosh t = 1 - z/2, with complex t."""
+    import cmath
+    m = W.tridiag_1d(n, 0.0)
+    vals = m.vals - z * (np.repeat(np.arange(n), np.diff(m.colptr)) == m.rowind)
+    osym = O.symbolic(m, cap=4, perm="nd")
+    s = osym.sym
+    sel, st, _ = osym.factor_selinv_complex(vals)
+    assert st == 0
+    t = cmath.acosh(1.0 - z / 2.0)
+
+    def exact(i, j):
+        i, j = min(i, j), max(i, j)
+        return cmath.sinh(i * t) * cmath.sinh((n + 1 - j) * t) / (cmath.sinh(t) * cmath.sinh((n + 1) * t))
+    cols = np.repeat(np.arange(n), np.diff(s.colptrL))
+    ref = np.array([exact(int(s.perm[i]) + 1, int(s.perm[j]) + 1) for i, j in zip(s.rowindL, cols)])
+    assert np.max(np.abs(sel - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_planted_conjugation_is_caught():
+    O.set_mutation(10)
+    try:
+        with pytest.raises(AssertionError):
+            test_complex_tiers_against_library_inverse("pencil_pole0")
+    finally:
+        O.set_mutation(0)
+    test_complex_tiers_against_library_inverse("pencil_pole0")
+
+
+# ---------------------------------------------------------------- 1x1 / 2x2 pivots (symmetric indefinite)
+@pytest.mark.parametrize("side,cap", [(3, 32), (4, 64), (4, 16), (5, 128)])
+def test_pivoted_tier_on_indefinite_matrices(side, cap):
+    """Zero diagonal entries: the unpivoted LDL^T reports a bad pivot; the
+    LDL^T with Bunch-Kaufman 1x1/2x2 pivots inside the diagonal blocks gives
+    the selected entries of the inverse (against a library LU inverse), the
+    row identity holds, and on an SPD matrix it agrees with the unpivoted
+    tier."""
+    m = W.indefinite_molecular(side=side, seed=8)
+    osym = O.symbolic(m, cap=cap)
+    s = osym.sym
+    _, _, st, _, _, _ = osym.factor_selinv(m.vals, require_spd=False)
+    assert st == -3
+    sel, st, _ = osym.factor_selinv_pivoted(m.vals)
+    assert st == 0
+    exact = np.linalg.inv(m.dense())
+    ref = H.sel_from_dense(exact, s.colptrL, s.rowindL, s.perm)
+    # indefinite: |Ainv_ij| <= sqrt(Ainv_ii Ainv_jj) does not hold, so the
+    # error is taken relative to the largest entry (kappa is 10..1e3 here)
+    assert np.max(np.abs(sel - ref)) <= 1e-12 * np.max(np.abs(ref))
+    r = H.row_identity_fast(sel, m, s.colptrL, s.rowindL, s.perm)
+    assert np.max(np.abs(r)) <= 1e-10
+
+
+def test_pivoted_tier_equals_unpivoted_on_spd():
+    m = W.laplacian((7, 6, 5), coeff="loguniform", lo=0.1, hi=10.0, shift=1e-3, seed=5)
+    osym = O.symbolic(m, cap=16)
+    a = osym.factor_selinv(m.vals)[0]
+    b, st, _ = osym.factor_selinv_pivoted(m.vals)
+    assert st == 0
+    s = osym.sym
+    assert H.err_c8(b, a, s.colptrL, s.rowindL) <= 1e-12
+
+
+def test_pivoted_tier_needs_2x2_pivots():
+    """[[0, 1], [1, 0]] blocks on the diagonal, coupled: no 1x1 pivot exists
+    in the first column, a 2x2 pivot does."""
+    n = 6
+    a = np.zeros((n, n))
+    for k in range(0, n, 2):
+        a[k, k + 1] = a[k + 1, k] = 1.0
+    a[2:4, 0:2] = a[0:2, 2:4] = 0.25  # couple the blocks
+    colptr, rowind, vals = _with_diagonal(a)
+    m = W.Matrix(n, colptr, rowind, vals)
+    osym = O.symbolic(m, cap=8, perm="natural")
+    s = osym.sym
+    assert osym.factor_selinv(vals, require_spd=False)[2] == -3
+    sel, st, _ = osym.factor_selinv_pivoted(vals)
+    assert st == 0
+    ref = H.sel_from_dense(np.linalg.inv(a), s.colptrL, s.rowindL, s.perm)
+    assert np.max(np.abs(sel - ref)) <= 1e-14
+
+
+def _with_diagonal(a):
+    """Lower CSC of a dense symmetric matrix with every diagonal entry stored."""
+    n = a.shape[0]
+    mask = np.tril(a != 0) | np.eye(n, dtype=bool)
+    rows, cols = np.nonzero(mask)
+    order = np.lexsort((rows, cols))
+    rows, cols = rows[order], cols[order]
+    colptr = np.zeros(n + 1, np.int64)
+    np.add.at(colptr, cols + 1, 1)
+    return np.cumsum(colptr), rows.astype(np.int32), a[rows, cols]
+
+
+def test_planted_missing_2x2_pivots_are_caught():
+    O.set_mutation(11)
+    try:
+        with pytest.raises(AssertionError):
+            test_pivoted_tier_needs_2x2_pivots()
+        with pytest.raises(AssertionError):
+            test_pivoted_tier_on_indefinite_matrices(4, 64)
+    finally:
+        O.set_mutation(0)
+    test_pivoted_tier_needs_2x2_pivots()

@@ -196,3 +196,19 @@ def test_relaxed_parity(dims, cap, exec_cap):
 def test_relaxed_parity_molecular_and_random():
     _compare_relaxed(W.molecular(side=4, dofs=8, seed=4), 128)
     _compare_relaxed(W.random_spd_pattern(150, 0.03, 9), 8, perm="natural")
+
+
+def test_complex_plans_on_the_host():
+    """Complex plans: blocks of at most 64 columns, the pattern of the real
+    plan, complex-sized arenas; a pole plan is count copies of one analysis."""
+    m = W.laplacian((12, 12, 12), shift=0.1)
+    r = S.Plan.from_matrix(m)
+    z = S.Plan.from_matrix(m, complex_values=True)
+    assert z.blocks()["s"].max() <= 64
+    assert np.array_equal(r.pattern()[0], z.pattern()[0]) and np.array_equal(r.pattern()[1], z.pattern()[1])
+    zo = O.symbolic(m, cap=128, relax=64).sym
+    zb = z.blocks()
+    assert np.array_equal(np.concatenate([zb["first"], [m.n]]), zo.xsuper)
+    p = S.Plan.poles(m, 5)
+    assert p.count == 5 and p.info["n"] == 5 * m.n and p.info["nnzL"] == 5 * z.info["nnzL"]
+    assert np.array_equal(np.diff(p.nnzA_off), np.full(5, m.nnz))
