@@ -111,6 +111,20 @@ typedef struct {
                              selinv_invert_complex.  Execution blocks are
                              then at most 64 columns wide and the schedule is
                              the deterministic one.                         */
+    int32_t pivoting;     /* 1: symmetric indefinite A: each diagonal block
+                             F_KK is factored with symmetric interchanges
+                             inside the block and 1x1 or 2x2 pivots
+                             (Bunch-Kaufman rule), D block diagonal (Section
+                             2.1).  Only T_K = F_KK^{-1} enters the rest of
+                             the method, so Algorithm 1, the Schur updates
+                             and the adjoint are unchanged.  No interchange
+                             crosses a block: a singular F_KK is reported as
+                             SELINV_EPIVOT with the block's first column.
+                             Needs require_spd = 0 and real values;
+                             execution blocks are then at most 128 columns,
+                             every level runs as per-level launches (no
+                             persistent queues, no small-block kernels), and
+                             selinv_get_factor and selinv_tune refuse.     */
 } selinv_opts;
 
 typedef struct {

@@ -245,8 +245,12 @@ selinv_status analyze_one(int64_t n, const int64_t* colptr, const int32_t* rowin
 
 selinv_status resolve_opts(const selinv_opts* opts, selinv_opts& o)
 {
-    o = selinv_opts{128, 1, 1, 0, 0, 0, 1, 0, 0};
+    o = selinv_opts{128, 1, 1, 0, 0, 0, 1, 0, 0, 0};
     if (opts) o = *opts;
+    if (o.pivoting != 0 && o.pivoting != 1) return fail(SELINV_EINVAL, "pivoting must be 0 or 1");
+    if (o.pivoting && o.require_spd) return fail(SELINV_EINVAL, "pivoting needs require_spd = 0");
+    if (o.pivoting && o.complex_values)
+        return fail(SELINV_EUNSUPPORTED, "pivoting is not supported for complex values");
     if (o.complex_values != 0 && o.complex_values != 1) return fail(SELINV_EINVAL, "complex_values must be 0 or 1");
     if (o.relaxed != 0 && o.relaxed != 1) return fail(SELINV_EINVAL, "relaxed must be 0 or 1");
     if (o.relaxed && !o.fuse_chains) return fail(SELINV_EINVAL, "relaxed supernodes need fuse_chains = 1");
@@ -266,6 +270,8 @@ selinv_status resolve_opts(const selinv_opts* opts, selinv_opts& o)
         o.exec_cap = std::min(o.exec_cap, (int32_t)kZMaxS);
         o.deterministic = 1;
     }
+    // the pivoted diagonal kernel holds a whole block in LDS
+    if (o.pivoting) o.exec_cap = std::min(o.exec_cap, (int32_t)kLdsDiagMax);
     return SELINV_OK;
 }
 
@@ -349,7 +355,8 @@ hipError_t factor_levels(selinv_plan_s* P, const DevPtrs& D, const double* d_val
         const int deep = P->panel_deep[l] & deep_ok;
         const int64_t dg[4] = {a[l], P->ldlt_cut[2 * l], P->ldlt_cut[2 * l + 1], a[l + 1]};
         e = launch_sb_factor(prof, D, q[l], q[l + 1] - q[l], spd, s);
-        if (!e) e = launch_ldlt_level(prof, D, dg, spd, s);
+        if (!e) e = P->opts.pivoting ? launch_ldlt_bk(prof, D, a[l], a[l + 1] - a[l], s)
+                                     : launch_ldlt_level(prof, D, dg, spd, s);
         if (!e) e = launch_panel_level(prof, D, b[l], b[l + 1] - b[l], deep, s);
         if (!e) e = launch_schur_groups(prof, D, cut.data(), 0, (int)cut.size() - 1, deep, s);
     }
@@ -733,6 +740,7 @@ selinv_status selinv_get_factor(selinv_plan P, double* d_L, hipStream_t s)
 {
     if (!P) return fail(SELINV_EINVAL, "NULL plan");
     if (P->opts.complex_values) return fail(SELINV_EINVAL, "the plan holds complex values (selinv_*_complex)");
+    if (P->opts.pivoting) return fail(SELINV_EUNSUPPORTED, "with pivoting the diagonal blocks keep T only: no factor");
     if (!P->ws) return fail(SELINV_ESTATE, "no workspace bound");
     if (!P->factored) return fail(SELINV_ESTATE, "no factor computed");
     DevPtrs D = dev_ptrs(P);
@@ -953,17 +961,18 @@ selinv_status run_persistent(selinv_plan_s* P, const double* d_valsA, double* d_
 }
 
 // What selinv_run launches: the persistent kernels, or in deterministic
-// mode the per-level sequence (no atomics), followed by the checkpoint copy
-// when checkpointing is on.  Kernels only, so it can be captured.
+// mode (no atomics) and with pivoting (the pivoted diagonal kernel) the
+// per-level sequence, followed by the checkpoint copy when checkpointing is
+// on.  Kernels only, so it can be captured.
 selinv_status run_sequence(selinv_plan_s* P, const double* d_valsA, double* d_sel, hipStream_t s, Prof* prof)
 {
-    if (!P->opts.deterministic) {
+    if (!P->opts.deterministic && !P->opts.pivoting) {
         if (selinv_status st = run_persistent(P, d_valsA, d_sel, s, prof)) return st;
     } else {
         const DevPtrs D = dev_ptrs(P);
         hipError_t e = factor_levels(P, D, d_valsA, s, prof);
         if (!e) e = invert_levels(P, D, d_sel, s, prof);
-        if (e) return hip_fail(e, "deterministic run launch");
+        if (e) return hip_fail(e, "per-level run launch");
     }
     if (P->opts.checkpoint_every > 1) {
         hipError_t e = launch_checkpoint(prof, dev_ptrs(P), (int64_t)P->t_diag.tasks.size(), 0, s);
@@ -1191,8 +1200,8 @@ selinv_status selinv_tune(selinv_plan P, const double* d_valsA, double* d_sel, c
     if (P->opts.complex_values) return fail(SELINV_EINVAL, "the plan holds complex values (selinv_*_complex)");
     if (!P->ws) return fail(SELINV_ESTATE, "no workspace bound");
     if (!P->tr) return fail(SELINV_ESTATE, "no transient memory bound (selinv_bind_transient)");
-    if (P->opts.deterministic)
-        return fail(SELINV_EUNSUPPORTED, "the deterministic mode runs per-level launches: no schedule to tune");
+    if (P->opts.deterministic || P->opts.pivoting)
+        return fail(SELINV_EUNSUPPORTED, "deterministic and pivoting plans run per-level launches: no schedule to tune");
     const std::string key = tune_key(P);
     selinv_sched best{};
     double ms = 0.0;

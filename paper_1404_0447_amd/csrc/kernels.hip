@@ -1622,6 +1622,10 @@ __global__ __launch_bounds__(kThreads) void k_ldlt_bk(const Task* __restrict__ t
     const int s = d.s, ls = s + 1, t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int64_t ld = (int64_t)s + d.c;
     const double alpha = (1.0 + sqrt(17.0)) / 8.0;
+    if (s > kLdsDiagMax) {  // the analysis caps pivoted blocks at this width
+        if (t == 0) atomicMin(status, (unsigned long long)d.first);
+        return;
+    }
     for (int e = t; e < s * s; e += kThreads) {
         const int i = e % s, j = e / s;
         if (i >= j) {
@@ -1634,6 +1638,7 @@ __global__ __launch_bounds__(kThreads) void k_ldlt_bk(const Task* __restrict__ t
     __syncthreads();
     // wave 0: largest |x_q| over q in [q0, q1) (q != skip), value and index
     auto wave_max = [&](auto val, int q0, int q1, int skip, double& best, int& arg) {
+        wave_sync();  // the previous reduction's result has been read
         double b = -1.0;
         int a = -1;
         for (int q = q0 + lane; q < q1; q += 64)

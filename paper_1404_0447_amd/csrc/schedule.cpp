@@ -255,7 +255,9 @@ void build_schedule(selinv_plan_s* P)
     // deterministic mode: no small-block kernels (their Schur updates use
     // atomics), no split contractions, no whole-contraction kernel variants
     const bool det = P->opts.deterministic != 0;
-    auto small_block = [&](int s, int c) { return !det && is_small_level(s, c); };
+    // the small-block kernels factor without pivots: none with pivoting
+    const bool piv = P->opts.pivoting != 0;
+    auto small_block = [&](int s, int c) { return !det && !piv && is_small_level(s, c); };
     std::vector<uint64_t> colour_mask((size_t)P->n, 0);
     std::vector<int32_t> touch((size_t)P->n, 0), stamp((size_t)P->n, -1);
     std::vector<char> excl(P->blocks.size(), 0);

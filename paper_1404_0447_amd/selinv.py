@@ -51,14 +51,16 @@ class Geom(ct.Structure):
 class Opts(ct.Structure):
     _fields_ = [("max_super", ct.c_int32), ("fuse_chains", ct.c_int32), ("require_spd", ct.c_int32),
                 ("exec_cap", ct.c_int32), ("sep_order", ct.c_int32), ("deterministic", ct.c_int32),
-                ("checkpoint_every", ct.c_int32), ("relaxed", ct.c_int32), ("complex_values", ct.c_int32)]
+                ("checkpoint_every", ct.c_int32), ("relaxed", ct.c_int32), ("complex_values", ct.c_int32),
+                ("pivoting", ct.c_int32)]
 
 
 def _opts(max_super, fuse_chains, require_spd, exec_cap, sep_order, deterministic, checkpoint_every, relaxed,
-          complex_values=False):
+          complex_values=False, pivoting=False):
     so = {"lex": 0, "rim_last": 1}.get(sep_order, sep_order)
     return Opts(int(max_super), int(bool(fuse_chains)), int(bool(require_spd)), int(exec_cap), int(so),
-                int(bool(deterministic)), int(checkpoint_every), int(bool(relaxed)), int(bool(complex_values)))
+                int(bool(deterministic)), int(checkpoint_every), int(bool(relaxed)), int(bool(complex_values)),
+                int(bool(pivoting)))
 
 
 class Sched(ct.Structure):
@@ -151,7 +153,7 @@ class Plan:
 
     def __init__(self, n, colptr, rowind, geom=None, perm=None, max_super=128, fuse_chains=True,
                  require_spd=True, exec_cap=0, sep_order=0, deterministic=False, checkpoint_every=1,
-                 relaxed=False, complex_values=False, _handle=None):
+                 relaxed=False, complex_values=False, pivoting=False, _handle=None):
         L = lib()
         self.n = int(n)
         if _handle is not None:
@@ -166,8 +168,10 @@ class Plan:
             d3 = list(dims) + [1] * (3 - len(dims))
             g = Geom(int(ndim), (ct.c_int32 * 3)(*[int(x) for x in d3[:3]]), int(dofs))
         pm = None if perm is None else np.ascontiguousarray(perm, dtype=np.int32)
+        if pivoting:
+            require_spd = False  # a pivoted factorization takes indefinite blocks
         o = _opts(max_super, fuse_chains, require_spd, exec_cap, sep_order, deterministic, checkpoint_every,
-                  relaxed, complex_values)
+                  relaxed, complex_values, pivoting)
         self.checkpoint_every = max(1, int(checkpoint_every))
         self.deterministic = bool(deterministic)
         h = ct.c_void_p()

@@ -147,6 +147,32 @@ def test_options_are_validated():
         assert st == S.SELINV_EINVAL
 
 
+@pytest.mark.parametrize("kw,want", [(dict(pivoting=2, spd=0), "EINVAL"), (dict(pivoting=1, spd=1), "EINVAL"),
+                                     (dict(pivoting=1, spd=0, cplx=1), "EUNSUPPORTED")])
+def test_pivoting_options_are_validated(kw, want):
+    m = W.laplacian((6, 6), shift=0.1)
+    o = S._opts(128, 1, kw["spd"], 0, 0, 0, 1, 0, kw.get("cplx", 0), kw["pivoting"])
+    o.pivoting = kw["pivoting"]
+    h = ct.c_void_p()
+    st = S.lib().selinv_analyze(m.n, m.colptr.ctypes.data_as(ct.c_void_p), m.rowind.ctypes.data_as(ct.c_void_p),
+                                None, None, ct.byref(o), ct.byref(h))
+    assert st == getattr(S, "SELINV_" + want)
+
+
+def test_pivoting_caps_blocks_and_drops_small_block_kernels():
+    """Pivoted diagonal blocks sit whole in LDS (at most 128 columns), and
+    the small-block kernels, which factor without pivots, take no block; the
+    pattern of L is that of the default plan."""
+    m = W.laplacian((9, 8, 7), shift=0.1)
+    p = S.Plan.from_matrix(m, max_super=256, pivoting=True)
+    q = S.Plan.from_matrix(m, max_super=256)
+    assert p.blocks()["s"].max() <= 128
+    kw = p.kernel_work()
+    assert kw["sbfactor"][0] == 0.0 and kw["sbinvert"][0] == 0.0
+    for a, b in zip(p.pattern(), q.pattern()):
+        assert np.array_equal(a, b)
+
+
 @pytest.mark.parametrize("k", [1, 2, 3])
 def test_workspace_parts_and_checkpoint_store(k):
     m = W.laplacian((9, 8, 7), shift=0.1)
