@@ -105,6 +105,8 @@ def main():
     ap.add_argument("--checkpoint-every", type=int, default=4,
                     help="checkpoint interval of the second backward measurement (0: skip it)")
     ap.add_argument("--batch-reps", type=int, default=10, help="timed replays of the batched graph")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only the batched measurement, printed as its own JSON line (for profiling it)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain device copy of 1 GiB (read 1 GiB, write 1 GiB) three times: the "
                          "reference dispatch for scaling FETCH_SIZE / WRITE_SIZE counters")
@@ -130,6 +132,9 @@ def main():
             torch.add(src, 0.0, out=dst)  # one elementwise kernel: reads src, writes dst
         torch.cuda.synchronize()
         print(json.dumps({"copy_calib_bytes_read": n * 8, "copy_calib_bytes_written": n * 8, "dispatches": 3}))
+        return
+    if args.batch_only:
+        print(json.dumps({"batched": measure_batched(args, dev)}))
         return
     t0 = time.time()
     m = W.make(args.workload)
@@ -648,6 +653,20 @@ def measure_batched(args, dev):
     for p in plans:
         p.sync_status()
     ms_loop = _time(loop, max(1, reps // 5), stream)
+    # the largest member alone: a lower bound for any schedule of the batch
+    # is the time of its longest dependency chain, which lies in the largest
+    # grids (their top separators are the deepest chains of blocks)
+    big = int(np.argmax([p.info["flops_factor"] + p.info["flops_selinv"] for p in plans]))
+    pb, vb, ob = plans[big], pv[big], po[big]
+
+    def one_member():
+        pb.factor(vb)
+        pb.invert(ob)
+    one_member()
+    ms_big = _time(one_member, reps, stream)
+    pb.run(vb, out=ob, graph=True)
+    ms_big_graph = _time(lambda: pb.run(vb, out=ob, graph=True), reps, stream)
+    pb.sync_status()
     flops = batch.info["flops_factor"] + batch.info["flops_selinv"]
     res = {"workload": "256 2D 5-point grids, side U{32..96}, shift U[0.01,1], seed 3",
            "count": len(ms), "n": batch.info["n"], "nnzL": batch.info["nnzL"], "blocks": batch.info["nblocks"],
@@ -655,9 +674,14 @@ def measure_batched(args, dev):
            "ms_graph": round(ms_graph, 4), "ms_persistent_direct": round(ms_direct, 4),
            "ms_union_per_level_launches": round(ms_union, 4), "ms_loop_per_matrix": round(ms_loop, 4),
            "speedup_vs_loop": round(ms_loop / ms_graph, 2),
+           "speedup_graph_vs_union_per_level": round(ms_union / ms_graph, 3),
+           "largest_member": {"n": int(pb.n), "ms_per_level": round(ms_big, 4),
+                              "ms_persistent_graph": round(ms_big_graph, 4),
+                              "batch_graph_over_largest": round(ms_graph / min(ms_big, ms_big_graph), 3)},
            "gflops_graph": round(flops / (ms_graph * 1e-3) / 1e9, 3)}
     log(f"[bench] batched graph {ms_graph:.3f} ms, direct {ms_direct:.3f} ms, union per-level {ms_union:.3f} ms, "
         f"loop {ms_loop:.3f} ms: speedup {ms_loop / ms_graph:.1f}x")
+    log(f"[bench] largest member alone (n={pb.n}): per-level {ms_big:.3f} ms, persistent graph {ms_big_graph:.3f} ms")
     if not args.no_cpu:
         from oracle import oracle as O
         worst, cpu_s = 0.0, 0.0
