@@ -135,3 +135,39 @@ def row_identity_fast(sel, m, colptrL, rowindL, perm, with_scale=False):
         np.add.at(mag, r, np.abs(v * vals))
         return acc - 1.0, mag
     return acc - 1.0
+
+
+def product_identity(sel, m, colptrL, rowindL, perm, rows=None):
+    """(A Ainv)_ik - delta_ik over every pair (i, k) at which the product can
+    be formed from selected entries alone: all j with A_ij != 0 have (j, k)
+    in the symmetric pattern of L (rows: only these i, original numbering).
+    Returns (max |residual| / sum_j |A_ij Ainv_jk|, number of pairs checked,
+    number of them with i != k)."""
+    import scipy.sparse as sp
+    n = m.n
+    cols = np.repeat(np.arange(n), np.diff(colptrL)).astype(np.int64)
+    perm = np.asarray(perm, dtype=np.int64)
+    r0, c0 = perm[np.asarray(rowindL, dtype=np.int64)], perm[cols]
+    off = r0 != c0
+    rr = np.concatenate([r0, c0[off]])
+    cc = np.concatenate([c0, r0[off]])
+    vv = np.concatenate([np.asarray(sel), np.asarray(sel)[off]])
+    S = sp.csr_matrix((vv, (rr, cc)), shape=(n, n))
+    Sp = sp.csr_matrix((np.ones_like(vv), (rr, cc)), shape=(n, n))
+    ar, ac, av = m.coo_full()
+    A = sp.csr_matrix((av, (ar, ac)), shape=(n, n))
+    if rows is not None:
+        A = A[np.asarray(rows)]
+    Ap = A.copy()
+    Ap.data[:] = 1.0
+    Aabs = abs(A)
+    deg = np.diff(Ap.indptr)
+    C = (Ap @ Sp).tocoo()  # C_ik = #{j : A_ij != 0 and (j, k) selected}
+    full = C.data == deg[C.row]
+    i, k = C.row[full], C.col[full]
+    gi = np.asarray(rows)[i] if rows is not None else i  # i in the original numbering
+    R = (A @ S).tocsr()
+    M = (Aabs @ abs(S)).tocsr()
+    res = np.asarray(R[i, k]).ravel() - (gi == k)
+    mag = np.asarray(M[i, k]).ravel()
+    return float(np.max(np.abs(res) / np.maximum(mag, 1e-300))), int(len(i)), int(np.sum(gi != k))

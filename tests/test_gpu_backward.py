@@ -146,7 +146,11 @@ def test_finite_differences_molecular():
         sel = _forward(p, v)
         return float(torch.dot(sel, wt).item())
 
-    worst = 0.0
+    # the noise of f itself: repeated evaluations differ by the order of the
+    # split contractions' atomic additions; never below a few ulps of f
+    f0 = [f(m.vals) for _ in range(4)]
+    delta = max(max(f0) - min(f0), 4e-16 * abs(f0[0]))
+    worst, resolved, unresolved = 0.0, 0, []
     for q in idx:
         # Richardson over (h, h/2) removes the h^2 truncation term, so h can be
         # large enough that the rounding noise of f (30M terms) / h stays small
@@ -159,6 +163,18 @@ def test_finite_differences_molecular():
             return (f(vp) - f(vm)) / (2 * step)
         d1, d2 = fd(h), fd(h / 2)
         rich = (4 * d2 - d1) / 3  # Richardson: removes the h^2 term
-        rel = abs(rich - g[q]) / max(abs(g[q]), 1e-3 * gmax)
-        worst = max(worst, rel)
-    assert worst <= 1e-6, f"worst relative FD error {worst:.3e}"
+        # each difference quotient carries at most delta / step of f's noise,
+        # so the Richardson value at most (4 (2 delta / h) + delta / h) / 3 = 3 delta / h
+        noise = 3 * delta / h
+        err = abs(rich - g[q])
+        if abs(g[q]) >= 1e4 * noise:
+            resolved += 1
+            worst = max(worst, err / abs(g[q]))
+        else:
+            unresolved.append((int(q), float(g[q]), float(err), float(noise)))
+            assert err <= 1e-6 * abs(g[q]) + 2 * noise, f"entry {q}: error {err:.3e} above its noise bound {noise:.3e}"
+    msg = (f"relative FD error {worst:.3e} on {resolved} entries resolved above the noise of f (delta {delta:.2e}); "
+           f"{len(unresolved)} entries within their noise bound")
+    print(msg, flush=True)
+    assert resolved >= 16, msg
+    assert worst <= 1e-6, msg

@@ -164,6 +164,11 @@ def test_lap3d_40_full():
     p, sel, s = _check(m, 128, True)
     r = H.row_identity_fast(sel, m, s.colptrL, s.rowindL, s.perm)
     assert np.max(np.abs(r)) <= 1e-10
+    # (A Ainv)_ik = delta_ik wherever the selected entries suffice to form it
+    # (rows sampled: the full product is a 3e8-entry sparse product)
+    rows = np.random.default_rng(40).choice(m.n, 4000, replace=False)
+    rel, npairs, noff = H.product_identity(sel, m, s.colptrL, s.rowindL, s.perm, rows=rows)
+    assert noff > 10 ** 4 and rel <= 1e-10, (rel, npairs, noff)
     # an irreducible Stieltjes matrix has an entrywise positive inverse
     assert np.all(sel > 0)
 
@@ -179,6 +184,9 @@ def test_molecular_full():
     p, sel, s = _check(m, W.CONFIGS["molecular_16"]["cap"], True)
     r = H.row_identity_fast(sel, m, s.colptrL, s.rowindL, s.perm)
     assert np.max(np.abs(r)) <= 1e-10
+    rows = np.random.default_rng(16).choice(m.n, 4000, replace=False)
+    rel, npairs, noff = H.product_identity(sel, m, s.colptrL, s.rowindL, s.perm, rows=rows)
+    assert noff > 10 ** 4 and rel <= 1e-10, (rel, npairs, noff)
 
 
 @pytest.mark.slow

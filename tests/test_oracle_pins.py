@@ -234,6 +234,34 @@ def test_invariants_cfg1():
     assert np.all(sel > 0)
 
 
+@pytest.mark.parametrize("case", ["lap2d_32", "molecular_3", "lap3d_9x8x7", "random"])
+def test_product_identity(case):
+    """(A Ainv)_ik = delta_ik at every pair (i, k), i != k included, whose
+    terms are all selected entries (A_ij != 0 implies (j, k) in the pattern):
+    beyond the row identity, this pins entries of the pattern that are not
+    entries of A."""
+    m = {"lap2d_32": lambda: W.make("lap2d_32"), "molecular_3": lambda: W.molecular(side=3, dofs=8, seed=4),
+         "lap3d_9x8x7": lambda: W.laplacian((9, 8, 7), coeff="uniform", lo=0.5, hi=2.0, shift=0.05, seed=2),
+         "random": lambda: W.random_spd_pattern(300, 0.03, 11)}[case]()
+    o = O.symbolic(m, cap=16)
+    sel = o.factor_selinv(m.vals)[0]
+    rel, npairs, noff = H.product_identity(sel, m, o.sym.colptrL, o.sym.rowindL, o.sym.perm)
+    assert noff >= 500 and rel <= 1e-12, (rel, npairs, noff)
+
+
+@pytest.mark.parametrize("mutation", [1, 2, 4])
+def test_product_identity_catches_planted_mistakes(mutation):
+    m = W.laplacian((9, 8, 7), coeff="uniform", lo=0.5, hi=2.0, shift=0.05, seed=2)
+    o = O.symbolic(m, cap=16)
+    O.set_mutation(mutation)
+    try:
+        sel = o.factor_selinv(m.vals)[0]
+    finally:
+        O.set_mutation(0)
+    rel = H.product_identity(sel, m, o.sym.colptrL, o.sym.rowindL, o.sym.perm)[0]
+    assert rel > 1e-6
+
+
 def test_ordering_invariance():
     m = W.laplacian((12, 10), coeff="uniform", lo=0.5, hi=2.0, shift=0.05, seed=7)
     a = O.symbolic(m, cap=8, perm="nd")
