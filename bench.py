@@ -102,6 +102,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the 40^3 and molecular side measurements")
     ap.add_argument("--no-det", action="store_true", help="skip the deterministic-mode step")
     ap.add_argument("--no-poles", action="store_true", help="skip the complex pole-batch measurement")
+    ap.add_argument("--no-pivot", action="store_true", help="skip the symmetric indefinite (2x2 pivots) measurement")
     ap.add_argument("--checkpoint-every", type=int, default=4,
                     help="checkpoint interval of the second backward measurement (0: skip it)")
     ap.add_argument("--batch-reps", type=int, default=10, help="timed replays of the batched graph")
@@ -287,6 +288,8 @@ def main():
         result["batched"] = measure_batched(args, dev)
     if not args.no_poles:
         result["poles"] = measure_poles(args, dev)
+    if not args.no_pivot:
+        result["pivoting"] = measure_pivoting(args, dev)
 
     if not args.no_cpu:
         result["cpu_baseline"], err = cpu_baseline(m, args.workload, cap, flops_step, value, out)
@@ -524,6 +527,37 @@ def measure_extra(workload, args, dev):
     log(f"[bench] {workload}: {ms:.3f} ms/step, GEMM phase {gtf:.1f} TFLOP/s ({time.time() - t0:.1f}s)")
     del p
     torch.cuda.empty_cache()
+    return res
+
+
+def measure_pivoting(args, dev):
+    """Symmetric indefinite saddle-point matrix on the 16^3-atom molecular
+    pattern (seed 8, 8 unknowns per atom, n = 32768), factored with 1x1/2x2
+    Bunch-Kaufman pivots inside the diagonal blocks, against the SPD
+    molecular matrix of the same pattern (same seed, shifted) on the default
+    path: the cost of pivoting."""
+    import torch
+    from paper_1404_0447_amd import selinv as S
+    from paper_1404_0447_amd import workloads as W
+    stream = torch.cuda.current_stream()
+    t0 = time.time()
+    mi = W.indefinite_molecular(side=16, dofs=8, seed=8)
+    ms_spd = W.molecular(side=16, dofs=8, seed=8)
+    res = {"workload": "saddle-point blocks [[0, I], [I, 0]] per atom on a jittered 16^3-atom lattice x 8 (n=32768), "
+                       "other entries 0.08 x N(0,1) blocks, seed 8, supernodes capped at 128"}
+    for key, m, kw in (("pivoted", mi, {"pivoting": True}), ("spd_same_pattern", ms_spd, {})):
+        p = S.Plan.from_matrix(m, max_super=128, **kw).bind(device=dev)
+        vals = torch.as_tensor(m.vals, dtype=torch.float64, device=dev)
+        out = torch.empty(int(p.info["nnzL"]), dtype=torch.float64, device=dev)
+        ms, prof = time_forward(p, vals, out, args.steps, args.warmup, stream, profile=True)
+        res[key] = {"ms_per_step": round(ms, 4), "ldlt_ms": round(prof["ldlt"][0] / args.steps, 4),
+                    "gflops": round((p.info["flops_factor"] + p.info["flops_selinv"]) / (ms * 1e-3) / 1e9, 2)}
+        del p
+        torch.cuda.empty_cache()
+    res["pivoted_over_spd"] = round(res["pivoted"]["ms_per_step"] / res["spd_same_pattern"]["ms_per_step"], 3)
+    log(f"[bench] pivoting: indefinite {res['pivoted']['ms_per_step']:.3f} ms/step (diagonal blocks "
+        f"{res['pivoted']['ldlt_ms']:.3f} ms), SPD on the same pattern {res['spd_same_pattern']['ms_per_step']:.3f} ms "
+        f"({time.time() - t0:.1f}s)")
     return res
 
 

@@ -355,7 +355,7 @@ hipError_t factor_levels(selinv_plan_s* P, const DevPtrs& D, const double* d_val
         const int deep = P->panel_deep[l] & deep_ok;
         const int64_t dg[4] = {a[l], P->ldlt_cut[2 * l], P->ldlt_cut[2 * l + 1], a[l + 1]};
         e = launch_sb_factor(prof, D, q[l], q[l + 1] - q[l], spd, s);
-        if (!e) e = P->opts.pivoting ? launch_ldlt_bk(prof, D, a[l], a[l + 1] - a[l], s)
+        if (!e) e = P->opts.pivoting ? launch_ldlt_bk(prof, D, dg, s)
                                      : launch_ldlt_level(prof, D, dg, spd, s);
         if (!e) e = launch_panel_level(prof, D, b[l], b[l + 1] - b[l], deep, s);
         if (!e) e = launch_schur_groups(prof, D, cut.data(), 0, (int)cut.size() - 1, deep, s);

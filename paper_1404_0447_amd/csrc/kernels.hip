@@ -1654,29 +1654,28 @@ __global__ __launch_bounds__(kThreads) void k_ldlt_bk(const Task* __restrict__ t
     extern __shared__ double M[];  // M[i + j * ls], ls = s + 1
     __shared__ int piv[kLdsDiagMax], bsz[kLdsDiagMax];
     __shared__ int s_size, s_swap, s_bad;
-    __shared__ double red_v[64];
-    __shared__ int red_i[64];
     const BlockDesc d = blk[tasks[blockIdx.x].b];
     const int s = d.s, ls = s + 1, t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int64_t ld = (int64_t)s + d.c;
     const double alpha = (1.0 + sqrt(17.0)) / 8.0;
-    if (s > kLdsDiagMax) {  // the analysis caps pivoted blocks at this width
+    if (s > kLdsDiagMax) {  // the analysis caps pivoted blocks at this width (and the launch sizes LDS for its class)
         if (t == 0) atomicMin(status, (unsigned long long)d.first);
         return;
     }
-    for (int e = t; e < s * s; e += kThreads) {
-        const int i = e % s, j = e / s;
-        if (i >= j) {
+    // the thread grid (ti, tj) = (t % 16, t / 16) strides over rows and
+    // columns (no division per entry)
+    const int ti = t & 15, tj = t >> 4;
+    for (int j = tj; j < s; j += 16)
+        for (int i = j + ti; i < s; i += 16) {
             const double v = Lp[d.poff + i + (int64_t)j * ld];
             M[i + j * ls] = v;
             M[j + i * ls] = v;
         }
-    }
     if (t == 0) s_bad = 0;
     __syncthreads();
     // wave 0: largest |x_q| over q in [q0, q1) (q != skip), value and index
+    // (ties to the smaller index), reduced by lane exchanges
     auto wave_max = [&](auto val, int q0, int q1, int skip, double& best, int& arg) {
-        wave_sync();  // the previous reduction's result has been read
         double b = -1.0;
         int a = -1;
         for (int q = q0 + lane; q < q1; q += 64)
@@ -1684,20 +1683,16 @@ __global__ __launch_bounds__(kThreads) void k_ldlt_bk(const Task* __restrict__ t
                 const double v = fabs(val(q));
                 if (v > b) { b = v; a = q; }
             }
-        red_v[lane] = b;
-        red_i[lane] = a;
-        wave_sync();
-        for (int w = 32; w > 0; w >>= 1) {
-            if (lane < w && (red_v[lane + w] > red_v[lane] ||
-                             (red_v[lane + w] == red_v[lane] && red_i[lane + w] >= 0 &&
-                              (red_i[lane] < 0 || red_i[lane + w] < red_i[lane])))) {
-                red_v[lane] = red_v[lane + w];
-                red_i[lane] = red_i[lane + w];
+        for (int h = 32; h > 0; h >>= 1) {
+            const double ob = __shfl_xor(b, h);
+            const int oa = __shfl_xor(a, h);
+            if (ob > b || (ob == b && oa >= 0 && (a < 0 || oa < a))) {
+                b = ob;
+                a = oa;
             }
-            wave_sync();
         }
-        best = red_v[0];
-        arg = red_i[0];
+        best = b;
+        arg = a;
     };
     int k = 0;
     while (k < s) {
@@ -1754,7 +1749,6 @@ __global__ __launch_bounds__(kThreads) void k_ldlt_bk(const Task* __restrict__ t
             if (size == 2) bsz[k + 1] = 0;
         }
         __syncthreads();
-        const int m = s - k - size;
         if (size == 1) {
             const double dk = M[k + k * ls];
             if (dk == 0.0 || !isfinite(dk)) {
@@ -1763,9 +1757,10 @@ __global__ __launch_bounds__(kThreads) void k_ldlt_bk(const Task* __restrict__ t
                 break;
             }
             // trailing update with the unscaled column, then the column of L
-            for (int e = t; e < m * m; e += kThreads) {
-                const int i = k + 1 + e % m, j = k + 1 + e / m;
-                M[i + j * ls] -= M[i + k * ls] * M[j + k * ls] / dk;
+            const double rdk = 1.0 / dk;
+            for (int j = k + 1 + tj; j < s; j += 16) {
+                const double xj = M[j + k * ls] * rdk;
+                for (int i = k + 1 + ti; i < s; i += 16) M[i + j * ls] -= M[i + k * ls] * xj;
             }
             __syncthreads();
             for (int i = k + 1 + t; i < s; i += kThreads) M[i + k * ls] /= dk;
@@ -1778,11 +1773,14 @@ __global__ __launch_bounds__(kThreads) void k_ldlt_bk(const Task* __restrict__ t
                 break;
             }
             // M(i,j) -= [M(i,k) M(i,k+1)] D^{-1} [M(j,k); M(j,k+1)]
-            for (int e = t; e < m * m; e += kThreads) {
-                const int i = k + 2 + e % m, j = k + 2 + e / m;
-                const double u = M[i + k * ls], v = M[i + (k + 1) * ls];
+            const double rdet = 1.0 / det;
+            for (int j = k + 2 + tj; j < s; j += 16) {
                 const double x = M[j + k * ls], y = M[j + (k + 1) * ls];
-                M[i + j * ls] -= (u * (c * x - b * y) + v * (a * y - b * x)) / det;
+                const double gx = (c * x - b * y) * rdet, gy = (a * y - b * x) * rdet;
+                for (int i = k + 2 + ti; i < s; i += 16) {
+                    const double u = M[i + k * ls], v = M[i + (k + 1) * ls];
+                    M[i + j * ls] -= u * gx + v * gy;
+                }
             }
             __syncthreads();
             for (int i = k + 2 + t; i < s; i += kThreads) {
@@ -1798,60 +1796,103 @@ __global__ __launch_bounds__(kThreads) void k_ldlt_bk(const Task* __restrict__ t
         if (t == 0) atomicMin(status, (unsigned long long)d.first);
         return;
     }
-    // T(:, j) = P^T L^{-T} D^{-1} L^{-1} P e_j, one thread per column
+    // Z = (L D L^T)^{-1} of the interchanged block, in place of L and D,
+    // pivot block by pivot block from the last (the dense form of the
+    // selected-inversion recurrence): for the block b at q of width w and
+    // the rows r below it, Y = -Z(r,r) L(r,b), Z(b,b) = D_b^{-1} - L(r,b)^T Y,
+    // Z(r,b) = Y.  Z(r,r) is read from the lower triangle; L(r,b) stays in
+    // place until Y is complete.  Then T(i,j) = Z(pos(i), pos(j)), pos the
+    // position of original index i after the interchanges.
+    __shared__ double Yv[2][kLdsDiagMax], part[2][2][kLdsDiagMax], red[3][kThreads / 64];
+    __shared__ int pos_of[kLdsDiagMax], at[kLdsDiagMax];
+    auto z = [&](int a, int b) { return a >= b ? M[a + b * ls] : M[b + a * ls]; };
+    for (int q = s - 1; q >= 0;) {
+        const int w = (q > 0 && bsz[q - 1] == 2) ? 2 : 1;  // the block ending at q
+        const int b0 = q - w + 1, r0 = q + 1, nr = s - r0;
+        // Y(i, c) = -sum_k Z(i, k) L(k, b0 + c), rows i in [r0, s): two threads per row, halves of k
+        {
+            const int row = t % kLdsDiagMax, half = t / kLdsDiagMax;
+            const int i = r0 + row;
+            if (row < nr) {
+                const int k0 = r0 + half * ((nr + 1) / 2), k1 = half ? s : r0 + (nr + 1) / 2;
+                double y0 = 0.0, y1 = 0.0;
+                for (int k = k0; k < k1; ++k) {
+                    const double zk = z(i, k);
+                    y0 = fma(-zk, M[k + b0 * ls], y0);
+                    if (w == 2) y1 = fma(-zk, M[k + (b0 + 1) * ls], y1);
+                }
+                part[half][0][row] = y0;
+                part[half][1][row] = y1;
+            }
+        }
+        __syncthreads();
+        for (int row = t; row < nr; row += kThreads) {
+            Yv[0][row] = part[0][0][row] + part[1][0][row];
+            Yv[1][row] = part[0][1][row] + part[1][1][row];
+        }
+        __syncthreads();
+        // L(r,b)^T Y: three sums over the rows (w = 1: one)
+        double p00 = 0.0, p10 = 0.0, p11 = 0.0;
+        for (int row = t; row < nr; row += kThreads) {
+            const double l0 = M[r0 + row + b0 * ls], y0 = Yv[0][row];
+            p00 = fma(l0, y0, p00);
+            if (w == 2) {
+                const double l1 = M[r0 + row + (b0 + 1) * ls], y1 = Yv[1][row];
+                p10 = fma(l1, y0, p10);
+                p11 = fma(l1, y1, p11);
+            }
+        }
+        for (int h = 32; h > 0; h >>= 1) {
+            p00 += __shfl_xor(p00, h);
+            p10 += __shfl_xor(p10, h);
+            p11 += __shfl_xor(p11, h);
+        }
+        if (lane == 0) {
+            red[0][wave] = p00;
+            red[1][wave] = p10;
+            red[2][wave] = p11;
+        }
+        // Z(r, b) = Y, then Z(b, b) = D_b^{-1} - L^T Y
+        for (int row = t; row < nr; row += kThreads) {
+            M[r0 + row + b0 * ls] = Yv[0][row];
+            if (w == 2) M[r0 + row + (b0 + 1) * ls] = Yv[1][row];
+        }
+        __syncthreads();  // the wave sums are in red
+        if (t == 0) {
+            double r00 = 0.0, r10 = 0.0, r11 = 0.0;
+            for (int v = 0; v < kThreads / 64; ++v) {
+                r00 += red[0][v];
+                r10 += red[1][v];
+                r11 += red[2][v];
+            }
+            if (w == 1) {
+                M[b0 + b0 * ls] = 1.0 / M[b0 + b0 * ls] - r00;
+            } else {
+                const double a = M[b0 + b0 * ls], b = M[b0 + 1 + b0 * ls], c = M[b0 + 1 + (b0 + 1) * ls];
+                const double det = a * c - b * b;
+                // L^T Y is symmetric in exact arithmetic: its off-diagonal entry from the lower product
+                M[b0 + b0 * ls] = c / det - r00;
+                M[b0 + 1 + b0 * ls] = -b / det - r10;
+                M[b0 + 1 + (b0 + 1) * ls] = a / det - r11;
+            }
+        }
+        __syncthreads();
+        q = b0 - 1;
+    }
+    // pos_of[original index] = its position after the interchanges
+    if (t == 0) {
+        for (int k = 0; k < s; ++k) at[k] = k;  // at[position] = original index
+        for (int k = 0; k < s; ++k) {
+            const int a = at[k];
+            at[k] = at[piv[k]];
+            at[piv[k]] = a;
+        }
+        for (int k = 0; k < s; ++k) pos_of[at[k]] = k;
+    }
+    __syncthreads();
     double* T = Tp + d.woff;
-    if (t < s) {
-        double* x = T + (int64_t)t * s;
-        for (int i = 0; i < s; ++i) x[i] = i == t ? 1.0 : 0.0;
-        for (int q = 0; q < s; ++q) {
-            const double a = x[q];
-            x[q] = x[piv[q]];
-            x[piv[q]] = a;
-        }
-        for (int q = 0; q < s; ++q) {
-            const int w = bsz[q];
-            if (w == 0) continue;
-            for (int i = q + w; i < s; ++i) {
-                double v = x[i] - M[i + q * ls] * x[q];
-                if (w == 2) v -= M[i + (q + 1) * ls] * x[q + 1];
-                x[i] = v;
-            }
-        }
-        for (int q = 0; q < s; ++q) {
-            if (bsz[q] == 1) {
-                x[q] /= M[q + q * ls];
-            } else if (bsz[q] == 2) {
-                const double a = M[q + q * ls], b = M[q + 1 + q * ls], c = M[q + 1 + (q + 1) * ls];
-                const double det = a * c - b * b, u = x[q], v = x[q + 1];
-                x[q] = (c * u - b * v) / det;
-                x[q + 1] = (a * v - b * u) / det;
-            }
-        }
-        for (int q = s - 1; q >= 0; --q) {
-            const int w = bsz[q];
-            if (w == 0) continue;
-            double u = x[q], v = w == 2 ? x[q + 1] : 0.0;
-            for (int i = q + w; i < s; ++i) {
-                u -= M[i + q * ls] * x[i];
-                if (w == 2) v -= M[i + (q + 1) * ls] * x[i];
-            }
-            x[q] = u;
-            if (w == 2) x[q + 1] = v;
-        }
-        for (int q = s - 1; q >= 0; --q) {
-            const double a = x[q];
-            x[q] = x[piv[q]];
-            x[piv[q]] = a;
-        }
-    }
-    __syncthreads();
-    // symmetrise: T := (T + T^T) / 2, through LDS (M is no longer needed)
-    for (int e = t; e < s * s; e += kThreads) M[e] = T[e];
-    __syncthreads();
-    for (int e = t; e < s * s; e += kThreads) {
-        const int i = e % s, j = e / s;
-        T[e] = 0.5 * (M[i + j * s] + M[j + i * s]);
-    }
+    for (int j = tj; j < s; j += 16)
+        for (int i = ti; i < s; i += 16) T[i + j * s] = z(pos_of[i], pos_of[j]);
 }
 
 // ===========================================================================
@@ -2876,11 +2917,17 @@ hipError_t launch_sb_invert(Prof* P, const DevPtrs& D, int64_t sb0, int64_t nsb,
     return hipGetLastError();
 }
 
-hipError_t launch_ldlt_bk(Prof* P, const DevPtrs& D, int64_t t0, int64_t n, hipStream_t s)
+hipError_t launch_ldlt_bk(Prof* P, const DevPtrs& D, const int64_t diag[4], hipStream_t s)
 {
-    if (n > 0)
-        launch(P, kLdlt, k_ldlt_bk, dim3((unsigned)n), kLdsDiagBytes, s, D.t_ldlt + t0, D.blocks, (const double*)D.Lp,
-               D.Tp, D.status);
+    // by width class, each with the LDS its widest block needs (so that the
+    // many narrow blocks near the leaves share a CU)
+    const int wmax[3] = {32, 64, kLdsDiagMax};
+    for (int k = 0; k < 3; k++) {
+        const int64_t n = diag[k + 1] - diag[k];
+        if (n > 0)
+            launch(P, kLdlt, k_ldlt_bk, dim3((unsigned)n), sizeof(double) * wmax[k] * (wmax[k] + 1), s,
+                   D.t_ldlt + diag[k], D.blocks, (const double*)D.Lp, D.Tp, D.status);
+    }
     return hipGetLastError();
 }
 

@@ -51,8 +51,9 @@ hipError_t launch_scatter_set(Prof* P, int kind, const double* src, const int64_
                               hipStream_t s);
 hipError_t launch_gather(Prof* P, int kind, const double* src, const int64_t* off, int64_t n, double* dst,
                          hipStream_t s);
-// diagonal blocks t_ldlt[t0 .. t0+n) with 1x1/2x2 (Bunch-Kaufman) pivots: T only
-hipError_t launch_ldlt_bk(Prof* P, const DevPtrs& D, int64_t t0, int64_t n, hipStream_t s);
+// diagonal blocks with 1x1/2x2 (Bunch-Kaufman) pivots, T only; diag as for
+// launch_ldlt_level (s <= 32, <= 64 and wider)
+hipError_t launch_ldlt_bk(Prof* P, const DevPtrs& D, const int64_t diag[4], hipStream_t s);
 // diag[0..3]: the level's diagonal-block tasks for s <= 32, <= 64 and wider
 hipError_t launch_ldlt_level(Prof* P, const DevPtrs& D, const int64_t diag[4], int require_spd, hipStream_t s);
 // panel_deep bit 0: whole-contraction panel kernel; bit 1: whole-contraction

@@ -40,18 +40,33 @@ struct ZLds {
 
 // acc[u][v] += sum over k < K of A(i, k) B(k, j), i = 4 tx + u, j = 4 ty + v;
 // loadA(k, i), loadB(k, j) return 0 outside the operands.
+// The next chunk's operands are loaded into registers while the current
+// chunk's products run, so their latency (for the gathered operand a chain
+// of index loads) overlaps the arithmetic.
 template <class LA, class LB>
 __device__ __forceinline__ void ztile(ZLds& L, int K, z2 (&acc)[4][4], LA loadA, LB loadB)
 {
     const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+    constexpr int NQ = (kZK * kZT) / kThreads;
+    z2 ra[NQ], rb[NQ];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int e = t + q * kThreads, kk = e / kZT, i = e % kZT;
+            ra[q] = loadA(k0 + kk, i);
+            rb[q] = loadB(k0 + kk, i);
+        }
+    };
+    if (K > 0) fetch(0);
     for (int k0 = 0; k0 < K; k0 += kZK) {
 #pragma unroll
-        for (int q = 0; q < (kZK * kZT) / kThreads; ++q) {
+        for (int q = 0; q < NQ; ++q) {
             const int e = t + q * kThreads, kk = e / kZT, i = e % kZT;
-            L.a[kk][i] = loadA(k0 + kk, i);
-            L.b[kk][i] = loadB(k0 + kk, i);
+            L.a[kk][i] = ra[q];
+            L.b[kk][i] = rb[q];
         }
         __syncthreads();
+        if (k0 + kZK < K) fetch(k0 + kZK);
 #pragma unroll 4
         for (int kk = 0; kk < kZK; ++kk) {
             z2 a[4], b[4];
