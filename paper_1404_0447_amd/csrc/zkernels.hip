@@ -4,9 +4,9 @@
 // every transpose is a plain transpose, never a conjugate.  Blocks are at
 // most 64 columns wide; the plan's level schedule is the deterministic one
 // (no split contractions, Schur updates in colour groups), so no kernel
-// here needs atomics.  Products run on the FP64 vector units: a 64 x 64
-// complex output tile per work-group, each thread a 4 x 4 patch, operands
-// staged through LDS in 16-deep chunks.
+// here needs atomics.  Products run on FP64 MFMA: a 64 x 64 complex output
+// tile per work-group, real and imaginary parts as separate accumulators,
+// operands staged through LDS in 16-deep chunks.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -19,11 +19,6 @@ namespace {
 typedef double z2 __attribute__((ext_vector_type(2)));  // (re, im)
 
 __device__ __forceinline__ z2 zmul(z2 a, z2 b) { return z2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
-__device__ __forceinline__ void zfma(z2& acc, z2 a, z2 b)
-{
-    acc.x = fma(a.x, b.x, fma(-a.y, b.y, acc.x));
-    acc.y = fma(a.x, b.y, fma(a.y, b.x, acc.y));
-}
 __device__ __forceinline__ z2 zdiv(z2 a, z2 b)
 {
     const double den = b.x * b.x + b.y * b.y;
@@ -33,20 +28,37 @@ __device__ __forceinline__ z2 zdiv(z2 a, z2 b)
 constexpr int kZT = 64;  // output tile edge
 constexpr int kZK = 16;  // contraction chunk
 
-struct ZLds {
-    z2 a[kZK][kZT + 1];
-    z2 b[kZK][kZT + 1];
+// ---------------------------------------------------------------------------
+// A 64 x 64 complex product tile on FP64 MFMA: real and imaginary parts in
+// separate LDS planes, four waves of 32 x 32 (2 x 2 MFMA tiles each), and
+// per 4-deep step four real products per output tile:
+//   C_re += A_re B_re - A_im B_im,  C_im += A_re B_im + A_im B_re.
+// v_mfma_f64_16x16x4f64: lane l holds A[l%16][l/16], B[l/16][l%16]; result
+// element (l/16 + 4 v, l%16) in register v.  Operands of the next chunk are
+// loaded into registers while the current one's products run.
+// ---------------------------------------------------------------------------
+typedef double zd4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ zd4 zmfma(double a, double b, zd4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+constexpr int kZP = kZT + 4;  // padded LDS row
+
+struct ZLdsM {
+    double ar[kZK][kZP], ai[kZK][kZP], br[kZK][kZP], bi[kZK][kZP];
 };
 
-// acc[u][v] += sum over k < K of A(i, k) B(k, j), i = 4 tx + u, j = 4 ty + v;
-// loadA(k, i), loadB(k, j) return 0 outside the operands.
-// The next chunk's operands are loaded into registers while the current
-// chunk's products run, so their latency (for the gathered operand a chain
-// of index loads) overlaps the arithmetic.
+struct ZAcc {
+    zd4 re[2][2], im[2][2];
+};
+
 template <class LA, class LB>
-__device__ __forceinline__ void ztile(ZLds& L, int K, z2 (&acc)[4][4], LA loadA, LB loadB)
+__device__ __forceinline__ void ztile_mfma(ZLdsM& L, int K, ZAcc& acc, LA loadA, LB loadB)
 {
-    const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wm0 = (wave & 1) * 32, wn0 = (wave >> 1) * 32;
     constexpr int NQ = (kZK * kZT) / kThreads;
     z2 ra[NQ], rb[NQ];
     auto fetch = [&](int k0) {
@@ -62,26 +74,54 @@ __device__ __forceinline__ void ztile(ZLds& L, int K, z2 (&acc)[4][4], LA loadA,
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             const int e = t + q * kThreads, kk = e / kZT, i = e % kZT;
-            L.a[kk][i] = ra[q];
-            L.b[kk][i] = rb[q];
+            L.ar[kk][i] = ra[q].x;
+            L.ai[kk][i] = ra[q].y;
+            L.br[kk][i] = rb[q].x;
+            L.bi[kk][i] = rb[q].y;
         }
         __syncthreads();
         if (k0 + kZK < K) fetch(k0 + kZK);
-#pragma unroll 4
-        for (int kk = 0; kk < kZK; ++kk) {
-            z2 a[4], b[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                a[u] = L.a[kk][4 * tx + u];
-                b[u] = L.b[kk][4 * ty + u];
+        for (int ks = 0; ks < kZK / 4; ++ks) {
+            const int kr = 4 * ks + (lane >> 4);
+            double xr[2], xi[2], yr[2], yi[2];
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                xr[m] = L.ar[kr][wm0 + 16 * m + (lane & 15)];
+                xi[m] = L.ai[kr][wm0 + 16 * m + (lane & 15)];
+                yr[m] = L.br[kr][wn0 + 16 * m + (lane & 15)];
+                yi[m] = L.bi[kr][wn0 + 16 * m + (lane & 15)];
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int m = 0; m < 2; ++m)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) zfma(acc[u][v], a[u], b[v]);
+                for (int n = 0; n < 2; ++n) {
+                    acc.re[m][n] = zmfma(xr[m], yr[n], acc.re[m][n]);
+                    acc.re[m][n] = zmfma(-xi[m], yi[n], acc.re[m][n]);
+                    acc.im[m][n] = zmfma(xr[m], yi[n], acc.im[m][n]);
+                    acc.im[m][n] = zmfma(xi[m], yr[n], acc.im[m][n]);
+                }
         }
         __syncthreads();
     }
+    __builtin_amdgcn_sched_barrier(0);
+    asm volatile("s_nop 15\n\ts_nop 15\n\ts_nop 15\n\ts_nop 15" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// f(i, j, value) for every element of the tile (tile-local i, j)
+template <class F>
+__device__ __forceinline__ void zvisit(const ZAcc& acc, F f)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm0 = (wave & 1) * 32, wn0 = (wave >> 1) * 32;
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int n = 0; n < 2; ++n)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                f(wm0 + 16 * m + (lane >> 4) + 4 * v, wn0 + 16 * n + (lane & 15), z2{acc.re[m][n][v], acc.im[m][n][v]});
 }
 
 __device__ __forceinline__ z2 zload(const double* p, int64_t e) { return *reinterpret_cast<const z2*>(p + 2 * e); }
@@ -161,23 +201,20 @@ __global__ __launch_bounds__(kThreads) void k_zpanel(const Task* __restrict__ ta
                                                      const double* __restrict__ Lp, double* __restrict__ Hp,
                                                      const double* __restrict__ Tp)
 {
-    __shared__ ZLds L;
     const Task tk = tasks[blockIdx.x];
     const BlockDesc d = blk[tk.b];
     const int s = d.s, c = d.c, r0 = tk.i0;
     const int64_t ld = (int64_t)s + c;
-    z2 acc[4][4] = {};
-    ztile(L, s, acc,
-          [&](int k, int i) { return (k < s && r0 + i < c) ? zload(Lp, d.poff + s + r0 + i + (int64_t)k * ld) : z2{0, 0}; },
-          [&](int k, int j) { return (k < s && j < s) ? zload(Tp, d.woff + k + (int64_t)j * s) : z2{0, 0}; });
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int i = r0 + 4 * tx + u, j = 4 * ty + v;
-            if (i < c && j < s) zstore(Hp, d.hoff + i + (int64_t)j * c, acc[u][v]);
-        }
+    auto la = [&](int k, int i) { return (k < s && r0 + i < c) ? zload(Lp, d.poff + s + r0 + i + (int64_t)k * ld) : z2{0, 0}; };
+    auto lb = [&](int k, int j) { return (k < s && j < s) ? zload(Tp, d.woff + k + (int64_t)j * s) : z2{0, 0}; };
+    auto out = [&](int ti, int j, z2 v) {
+        const int i = r0 + ti;
+        if (i < c && j < s) zstore(Hp, d.hoff + i + (int64_t)j * c, v);
+    };
+    __shared__ ZLdsM L;
+    ZAcc acc = {};
+    ztile_mfma(L, s, acc, la, lb);
+    zvisit(acc, out);
 }
 
 // Schur update of one 64 x 64 lower tile (rows i0.., columns k0.. of C):
@@ -188,27 +225,24 @@ __global__ __launch_bounds__(kThreads) void k_zschur(const Task* __restrict__ ta
                                                      const int64_t* __restrict__ cbase,
                                                      const int64_t* __restrict__ rbase, const int32_t* __restrict__ rel)
 {
-    __shared__ ZLds L;
     const Task tk = tasks[blockIdx.x];
     const BlockDesc d = blk[tk.b];
     const int s = d.s, c = d.c, i0 = tk.i0, k0 = tk.j0;
     const int64_t ld = (int64_t)s + c;
-    z2 acc[4][4] = {};
-    ztile(L, s, acc,
-          [&](int t, int i) { return (t < s && i0 + i < c) ? zload(Hp, d.hoff + i0 + i + (int64_t)t * c) : z2{0, 0}; },
-          [&](int t, int k) { return (t < s && k0 + k < c) ? zload(Lp, d.poff + s + k0 + k + (int64_t)t * ld) : z2{0, 0}; });
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int ii = i0 + 4 * tx + u, kk = k0 + 4 * ty + v;
-            if (ii < c && kk < c && ii >= kk) {
-                const int64_t pk = d.coff + kk;
-                const int64_t e = cbase[pk] + rel[rbase[pk] + ii];
-                zstore(Lp, e, zload(Lp, e) - acc[u][v]);
-            }
+    auto la = [&](int t, int i) { return (t < s && i0 + i < c) ? zload(Hp, d.hoff + i0 + i + (int64_t)t * c) : z2{0, 0}; };
+    auto lb = [&](int t, int k) { return (t < s && k0 + k < c) ? zload(Lp, d.poff + s + k0 + k + (int64_t)t * ld) : z2{0, 0}; };
+    auto out = [&](int ti, int tk2, z2 v) {
+        const int ii = i0 + ti, kk = k0 + tk2;
+        if (ii < c && kk < c && ii >= kk) {
+            const int64_t pk = d.coff + kk;
+            const int64_t e = cbase[pk] + rel[rbase[pk] + ii];
+            zstore(Lp, e, zload(Lp, e) - v);
         }
+    };
+    __shared__ ZLdsM L;
+    ZAcc acc = {};
+    ztile_mfma(L, s, acc, la, lb);
+    zvisit(acc, out);
 }
 
 // Ainv(C,K) rows [r0, r0+64) = -G L_hat with G = Ainv(C,C) gathered from the
@@ -218,29 +252,26 @@ __global__ __launch_bounds__(kThreads) void k_zgemm(const Task* __restrict__ tas
                                                     const int64_t* __restrict__ cbase,
                                                     const int64_t* __restrict__ rbase, const int32_t* __restrict__ rel)
 {
-    __shared__ ZLds L;
     const Task tk = tasks[blockIdx.x];
     const BlockDesc d = blk[tk.b];
     const int s = d.s, c = d.c, r0 = tk.i0;
     const int64_t ld = (int64_t)s + c;
-    z2 acc[4][4] = {};
-    ztile(L, c, acc,
-          [&](int k, int i) {
-              const int ii = r0 + i;
-              if (k >= c || ii >= c) return z2{0, 0};
-              const int lo = ii >= k ? ii : k, hi = ii >= k ? k : ii;  // G(lo, hi), lo >= hi
-              const int64_t ph = d.coff + hi;
-              return zload(Ap, cbase[ph] + rel[rbase[ph] + lo]);
-          },
-          [&](int k, int j) { return (k < c && j < s) ? zload(Hp, d.hoff + k + (int64_t)j * c) : z2{0, 0}; });
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int i = r0 + 4 * tx + u, j = 4 * ty + v;
-            if (i < c && j < s) zstore(Ap, d.poff + s + i + (int64_t)j * ld, -acc[u][v]);
-        }
+    auto la = [&](int k, int i) {
+        const int ii = r0 + i;
+        if (k >= c || ii >= c) return z2{0, 0};
+        const int lo = ii >= k ? ii : k, hi = ii >= k ? k : ii;  // G(lo, hi), lo >= hi
+        const int64_t ph = d.coff + hi;
+        return zload(Ap, cbase[ph] + rel[rbase[ph] + lo]);
+    };
+    auto lb = [&](int k, int j) { return (k < c && j < s) ? zload(Hp, d.hoff + k + (int64_t)j * c) : z2{0, 0}; };
+    auto out = [&](int ti, int j, z2 v) {
+        const int i = r0 + ti;
+        if (i < c && j < s) zstore(Ap, d.poff + s + i + (int64_t)j * ld, -v);
+    };
+    __shared__ ZLdsM L;
+    ZAcc acc = {};
+    ztile_mfma(L, c, acc, la, lb);
+    zvisit(acc, out);
 }
 
 // Ainv(K,K) = T - (P + P^T) / 2 with P = L_hat^T Ainv(C,K) (lower triangle)
@@ -248,22 +279,19 @@ __global__ __launch_bounds__(kThreads) void k_zsdiag(const Task* __restrict__ ta
                                                      double* __restrict__ Ap, const double* __restrict__ Hp,
                                                      const double* __restrict__ Tp)
 {
-    __shared__ ZLds L;
     __shared__ z2 P[kZT][kZT + 1];  // P, for the transpose
     const Task tk = tasks[blockIdx.x];
     const BlockDesc d = blk[tk.b];
     const int s = d.s, c = d.c;
     const int64_t ld = (int64_t)s + c;
-    z2 acc[4][4] = {};
-    ztile(L, c, acc,
-          [&](int r, int i) { return (r < c && i < s) ? zload(Hp, d.hoff + r + (int64_t)i * c) : z2{0, 0}; },
-          [&](int r, int j) { return (r < c && j < s) ? zload(Ap, d.poff + s + r + (int64_t)j * ld) : z2{0, 0}; });
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) P[4 * tx + u][4 * ty + v] = acc[u][v];
+    auto la = [&](int r, int i) { return (r < c && i < s) ? zload(Hp, d.hoff + r + (int64_t)i * c) : z2{0, 0}; };
+    auto lb = [&](int r, int j) { return (r < c && j < s) ? zload(Ap, d.poff + s + r + (int64_t)j * ld) : z2{0, 0}; };
+    __shared__ ZLdsM L;
+    ZAcc acc = {};
+    ztile_mfma(L, c, acc, la, lb);
+    zvisit(acc, [&](int i, int j, z2 v) { P[i][j] = v; });
     __syncthreads();
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
