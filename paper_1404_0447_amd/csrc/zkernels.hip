@@ -19,11 +19,6 @@ namespace {
 typedef double z2 __attribute__((ext_vector_type(2)));  // (re, im)
 
 __device__ __forceinline__ z2 zmul(z2 a, z2 b) { return z2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
-__device__ __forceinline__ z2 zdiv(z2 a, z2 b)
-{
-    const double den = b.x * b.x + b.y * b.y;
-    return z2{(a.x * b.x + a.y * b.y) / den, (a.y * b.x - a.x * b.y) / den};
-}
 
 constexpr int kZT = 64;  // output tile edge
 constexpr int kZK = 16;  // contraction chunk
@@ -128,72 +123,87 @@ __device__ __forceinline__ z2 zload(const double* p, int64_t e) { return *reinte
 __device__ __forceinline__ void zstore(double* p, int64_t e, z2 v) { *reinterpret_cast<z2*>(p + 2 * e) = v; }
 
 // ---------------------------------------------------------------------------
-// diagonal block: F_KK = L_KK D_K L_KK^T (unit lower L, complex pivots), then
-// T_K = F_KK^{-1} = L^{-T} D^{-1} L^{-1}.  One work-group per block, s <= 64,
-// the block in LDS.
+// diagonal block: F_KK = L_KK D_K L_KK^T (unit lower L, complex pivots, no
+// interchanges), then T_K = F_KK^{-1} in place of L and D by the dense
+// selected-inversion recurrence, pivot by pivot from the last: with r the
+// rows below pivot j, Y = -Z(r,r) L(r,j), Z(j,j) = 1/d_j - L(r,j)^T Y,
+// Z(r,j) = Y (plain transposes).  One work-group per block, s <= 64, the
+// lower triangle in LDS; only T leaves the kernel (the rest of the method
+// reads the diagonal block through T alone).
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ z2 zrecip(z2 b)
+{
+    const double den = b.x * b.x + b.y * b.y;
+    return z2{b.x / den, -b.y / den};
+}
+
 __global__ __launch_bounds__(kThreads) void k_zdiag(const Task* __restrict__ tasks, const BlockDesc* __restrict__ blk,
                                                     double* __restrict__ Lp, double* __restrict__ Tp,
                                                     unsigned long long* __restrict__ status)
 {
-    __shared__ z2 F[kZT][kZT + 1];  // F[i][j]: row i, column j (lower part used)
-    __shared__ z2 T[kZT][kZT + 1];
+    __shared__ z2 F[kZT][kZT + 1];  // F[i][k], i >= k: the lower triangle, then Z
+    __shared__ z2 Yp[4][kZT];       // partial sums of Y, four threads per row
+    __shared__ z2 Yv[kZT];
+    __shared__ z2 red[kThreads / 64];
     const BlockDesc d = blk[tasks[blockIdx.x].b];
-    const int s = d.s, t = threadIdx.x;
+    const int s = d.s, t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int ti = t & 15, tj = t >> 4;  // 16 x 16 thread grid over rows and columns
     const int64_t ld = (int64_t)d.s + d.c;
-    for (int e = t; e < s * s; e += kThreads) {
-        const int i = e % s, j = e / s;
-        if (i >= j) F[i][j] = zload(Lp, d.poff + i + (int64_t)j * ld);
-    }
+    for (int k = tj; k < s; k += 16)
+        for (int i = k + ti; i < s; i += 16) F[i][k] = zload(Lp, d.poff + i + (int64_t)k * ld);
     __syncthreads();
-    bool ok = true;
+    int bad = -1;
     for (int j = 0; j < s; ++j) {
         const z2 dj = F[j][j];
-        ok = ok && (dj.x != 0.0 || dj.y != 0.0) && isfinite(dj.x) && isfinite(dj.y);
-        // trailing update: F(i,k) -= F(i,j) F(k,j) / d_j for j < k <= i
-        const int m = s - j - 1, pairs = m * (m + 1) / 2;
-        for (int e = t; e < pairs; e += kThreads) {
-            // e -> (i, k), k <= i, both in (j, s)
-            int kk = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-            while ((kk + 1) * (kk + 2) / 2 <= e) ++kk;
-            while (kk * (kk + 1) / 2 > e) --kk;
-            const int ii = e - kk * (kk + 1) / 2;  // ii <= kk
-            const int i = j + 1 + kk, k = j + 1 + ii;
-            F[i][k] -= zdiv(zmul(F[i][j], F[k][j]), dj);
+        if (bad < 0 && !((dj.x != 0.0 || dj.y != 0.0) && isfinite(dj.x) && isfinite(dj.y))) bad = j;
+        const z2 rdj = zrecip(dj);
+        // trailing update F(i,k) -= F(i,j) F(k,j) / d_j, j < k <= i
+        for (int k = j + 1 + tj; k < s; k += 16) {
+            const z2 fk = zmul(F[k][j], rdj);
+            for (int i = k + ti; i < s; i += 16) F[i][k] -= zmul(F[i][j], fk);
         }
         __syncthreads();
-        // column j of L
-        for (int i = j + 1 + t; i < s; i += kThreads) F[i][j] = zdiv(F[i][j], dj);
+        for (int i = j + 1 + t; i < s; i += kThreads) F[i][j] = zmul(F[i][j], rdj);  // column j of L
         __syncthreads();
     }
-    if (!ok) {
-        if (t == 0) {
-            int bad = s;
-            for (int j = 0; j < s; ++j)
-                if (!((F[j][j].x != 0.0 || F[j][j].y != 0.0) && isfinite(F[j][j].x) && isfinite(F[j][j].y))) {
-                    bad = j;
-                    break;
-                }
-            atomicMin(status, (unsigned long long)(d.first + (bad < s ? bad : 0)));
-        }
+    if (bad >= 0) {
+        if (t == 0) atomicMin(status, (unsigned long long)(d.first + bad));
         return;
     }
-    // T(:, j) solves L D L^T x = e_j: one thread per column
-    if (t < s) {
-        const int j = t;
-        for (int i = 0; i < s; ++i) T[i][j] = z2{i == j ? 1.0 : 0.0, 0.0};
-        for (int i = 0; i < s; ++i)
-            for (int k = 0; k < i; ++k) T[i][j] -= zmul(F[i][k], T[k][j]);
-        for (int i = 0; i < s; ++i) T[i][j] = zdiv(T[i][j], F[i][i]);
-        for (int i = s - 1; i >= 0; --i)
-            for (int k = i + 1; k < s; ++k) T[i][j] -= zmul(F[k][i], T[k][j]);
+    auto z = [&](int a, int b) { return a >= b ? F[a][b] : F[b][a]; };
+    for (int j = s - 1; j >= 0; --j) {
+        const int r0 = j + 1, nr = s - r0;
+        // Y(i) = -sum_k Z(i,k) L(k,j), rows i in (j, s), four threads per row
+        {
+            const int row = t & 63, part = t >> 6;
+            if (row < nr) {
+                const int i = r0 + row, q = (nr + 3) / 4;
+                const int k0 = r0 + part * q, k1 = min(s, k0 + q);
+                z2 y = {0.0, 0.0};
+                for (int k = k0; k < k1; ++k) y -= zmul(z(i, k), F[k][j]);
+                Yp[part][row] = y;
+            }
+        }
+        __syncthreads();
+        z2 p = {0.0, 0.0};
+        if (t < nr) {
+            const z2 y = Yp[0][t] + Yp[1][t] + Yp[2][t] + Yp[3][t];
+            Yv[t] = y;
+            p = zmul(F[r0 + t][j], y);
+        }
+        // L(r,j)^T Y by lane exchanges within each wave, then across the four
+        for (int h = 32; h > 0; h >>= 1) {
+            p.x += __shfl_xor(p.x, h);
+            p.y += __shfl_xor(p.y, h);
+        }
+        if (lane == 0) red[wave] = p;
+        __syncthreads();
+        if (t < nr) F[r0 + t][j] = Yv[t];
+        if (t == 0) F[j][j] = zrecip(F[j][j]) - (red[0] + red[1] + red[2] + red[3]);
+        __syncthreads();
     }
-    __syncthreads();
-    for (int e = t; e < s * s; e += kThreads) {
-        const int i = e % s, j = e / s;
-        if (i >= j) zstore(Lp, d.poff + i + (int64_t)j * ld, F[i][j]);
-        zstore(Tp, d.woff + i + (int64_t)j * s, T[i][j]);
-    }
+    for (int k = tj; k < s; k += 16)
+        for (int i = ti; i < s; i += 16) zstore(Tp, d.woff + i + (int64_t)k * s, z(i, k));
 }
 
 // L_hat(C,K) rows [r0, r0+64) = F(C,K) T_K
@@ -279,16 +289,21 @@ __global__ __launch_bounds__(kThreads) void k_zsdiag(const Task* __restrict__ ta
                                                      double* __restrict__ Ap, const double* __restrict__ Hp,
                                                      const double* __restrict__ Tp)
 {
-    __shared__ z2 P[kZT][kZT + 1];  // P, for the transpose
+    // the product's operand planes, then P for the transpose (the tile loop
+    // ends with a barrier, so P may reuse the space)
+    __shared__ union {
+        ZLdsM L;
+        z2 P[kZT][kZT + 1];
+    } U;
+    auto& P = U.P;
     const Task tk = tasks[blockIdx.x];
     const BlockDesc d = blk[tk.b];
     const int s = d.s, c = d.c;
     const int64_t ld = (int64_t)s + c;
     auto la = [&](int r, int i) { return (r < c && i < s) ? zload(Hp, d.hoff + r + (int64_t)i * c) : z2{0, 0}; };
     auto lb = [&](int r, int j) { return (r < c && j < s) ? zload(Ap, d.poff + s + r + (int64_t)j * ld) : z2{0, 0}; };
-    __shared__ ZLdsM L;
     ZAcc acc = {};
-    ztile_mfma(L, c, acc, la, lb);
+    ztile_mfma(U.L, c, acc, la, lb);
     zvisit(acc, [&](int i, int j, z2 v) { P[i][j] = v; });
     __syncthreads();
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
