@@ -246,3 +246,26 @@ def test_lap3d_64_full_oracle():
     assert e <= TOL, f"selected inverse error {e:.3e}"
     eL = H.err_c8(Lv, oL, cp, ri)
     assert eL <= 1e-12, f"factor error {eL:.3e}"
+
+
+def test_empty_and_one_by_one_matrices():
+    """n = 0: every call is a no-op with empty outputs; n = 1: Ainv = 1/a on
+    the default, pivoted (a < 0) and complex paths."""
+    torch = _torch()
+    from paper_1404_0447_amd import selinv as S
+    p = S.Plan(0, np.zeros(1, np.int64), np.zeros(0, np.int32)).bind()
+    p.factor(torch.zeros(0, dtype=torch.float64, device="cuda"))
+    assert p.invert().numel() == 0
+    p.sync_status()
+    one = (np.array([0, 1], np.int64), np.array([0], np.int32))
+    p = S.Plan(1, *one).bind()
+    p.factor(torch.tensor([4.0], dtype=torch.float64, device="cuda"))
+    assert p.invert().cpu().numpy()[0] == 0.25
+    p = S.Plan(1, *one, pivoting=True).bind()
+    p.factor(torch.tensor([-2.0], dtype=torch.float64, device="cuda"))
+    assert p.invert().cpu().numpy()[0] == -0.5
+    p = S.Plan(1, *one, complex_values=True).bind()
+    p.factor_complex(torch.tensor([1.0 + 1.0j], dtype=torch.complex128, device="cuda"))
+    z = p.invert_complex().cpu().numpy()[0]
+    assert abs(z - 1.0 / (1.0 + 1.0j)) <= 1e-16
+    p.sync_status()
