@@ -112,9 +112,9 @@ typedef struct {
                              then at most 64 columns wide and the schedule is
                              the deterministic one.                         */
     int32_t pivoting;     /* 1: symmetric indefinite A: each diagonal block
-                             F_KK is factored with symmetric interchanges
-                             inside the block and 1x1 or 2x2 pivots
-                             (Bunch-Kaufman rule), D block diagonal (Section
+                             F_KK is inverted with 1x1 or 2x2 pivots chosen
+                             inside the block by the Bunch-Kaufman rule
+                             (symmetric pivoting, D block diagonal, Section
                              2.1).  Only T_K = F_KK^{-1} enters the rest of
                              the method, so Algorithm 1, the Schur updates
                              and the adjoint are unchanged.  No interchange

@@ -1637,262 +1637,297 @@ __global__ __launch_bounds__(kThreads) void k_ldlt_diag(const Task* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// Diagonal block of a symmetric indefinite matrix: T_K = F_KK^{-1} from an
-// LDL^T with 1x1 and 2x2 pivots chosen by the Bunch-Kaufman rule, with
-// symmetric interchanges inside the block (Section 2.1: D may have 2x2
-// blocks).  The rest of the method needs the diagonal block only through T
-// (L_hat = F(C,K) T, the Schur update L_hat F(C,K)^T, Algorithm 1 and the
-// adjoint), so L_KK and D stay in LDS.  One work-group per block (s <= 128),
-// the block in dynamic LDS with both triangles; T's columns are then solved
-// one per thread in global memory (Tp) and symmetrised.  A singular 1x1 or
+// Diagonal block of a symmetric indefinite matrix: T_K = F_KK^{-1} with 1x1
+// and 2x2 pivots chosen by the Bunch-Kaufman rule (Section 2.1: D may have
+// 2x2 blocks; Bunch and Kaufman 1977 for the rule).  The rest of the method
+// needs the diagonal block only through T (L_hat = F(C,K) T, the Schur update
+// L_hat F(C,K)^T, Algorithm 1 and the adjoint), so the block is inverted
+// directly by the symmetric sweep (Gauss-Jordan with diagonal pivots), which
+// accepts the pivots in any order: a pivot on index p (d = M(p,p), c = column
+// p) sets M(i,j) -= c_i c_j / d, M(i,p) = c_i / d, M(p,p) = -1/d; a 2x2 pivot
+// on b = {p, r} does the same with E = M(b,b): M -= M(:,b) E^{-1} M(b,:),
+// M(:,b) = M(:,b) E^{-1}, M(b,b) = -E^{-1}.  After every index is swept, M =
+// -F_KK^{-1}.  The unswept part of M is the Schur complement the pivoted
+// LDL^T would hold, so the rule is applied to it unchanged; an interchange
+// only reorders the list of unswept indices (ord[position] = index), and no
+// data moves.  The block lives in registers with the ownership of the
+// positive definite sweep (lower 16 x 16 sub-blocks, thread (tx, ty) holds
+// rows tx + 16a, columns ty + 16b); a pivot's column goes through LDS, where
+// every wave reads it and takes the rule's decisions itself (the same values
+// give every wave the same decision, so no decision is broadcast).  One
+// work-group per block, NB = 2, 4, 8 for s <= 32, 64, 128.  A singular 1x1 or
 // 2x2 pivot latches the block's first column in the status word.
 // ---------------------------------------------------------------------------
+
+// a value every lane holds alike, made known to the compiler as uniform
+__device__ __forceinline__ double uniform_f64(double x)
+{
+    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(x));
+    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(x));
+    return __hiloint2double(hi, lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x)
+{
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(x), __double2loint(x), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(x), __double2hiint(x), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double readlane_f64(double x, int l)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+    return __hiloint2double(hi, lo);
+}
+
+// largest x over the wave (NaN lanes ignored): within each row of 16 lanes
+// by DPP (exchange within quads, then rotations by 4 and 8), then across
+// the four rows
+__device__ __forceinline__ double wave_max_f64(double x)
+{
+    x = fmax(x, dpp_f64<0xB1>(x));   // quad_perm [1,0,3,2]
+    x = fmax(x, dpp_f64<0x4E>(x));   // quad_perm [2,3,0,1]
+    x = fmax(x, dpp_f64<0x124>(x));  // row_ror:4
+    x = fmax(x, dpp_f64<0x128>(x));  // row_ror:8
+    return fmax(fmax(readlane_f64(x, 0), readlane_f64(x, 16)), fmax(readlane_f64(x, 32), readlane_f64(x, 48)));
+}
+
+// f(integral_constant<int, pb>) for the one pb in [0, NB) equal to the
+// uniform value v
+template <int NB, class Fn>
+__device__ __forceinline__ void with_subblock(int v, Fn&& f)
+{
+    StaticFor<0, NB>::run([&](auto c) {
+        if (v == decltype(c)::value) f(c);
+    });
+}
+
+template <int NB>
 __global__ __launch_bounds__(kThreads) void k_ldlt_bk(const Task* __restrict__ tasks, const BlockDesc* __restrict__ blk,
                                                       const double* __restrict__ Lp, double* __restrict__ Tp,
                                                       unsigned long long* __restrict__ status)
 {
-    extern __shared__ double M[];  // M[i + j * ls], ls = s + 1
-    __shared__ int piv[kLdsDiagMax], bsz[kLdsDiagMax];
-    __shared__ int s_size, s_swap, s_bad;
+    constexpr int NS = NB * (NB + 1) / 2;
+    constexpr int W = 16 * NB;
+    constexpr int NH = (W + 63) / 64;  // positions per lane in a search
+    // columns of the pivots: [0], [1] alternate as the next candidate's
+    // column, [2] holds the second candidate's (the row searched for sigma)
+    __shared__ double cb[3][W];
     const BlockDesc d = blk[tasks[blockIdx.x].b];
-    const int s = d.s, ls = s + 1, t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int64_t ld = (int64_t)s + d.c;
-    const double alpha = (1.0 + sqrt(17.0)) / 8.0;
-    if (s > kLdsDiagMax) {  // the analysis caps pivoted blocks at this width (and the launch sizes LDS for its class)
-        if (t == 0) atomicMin(status, (unsigned long long)d.first);
+    const int s = d.s;
+    if (s > W) {  // the launch groups blocks by width, so this does not happen
+        if (threadIdx.x == 0) atomicMin(status, (unsigned long long)d.first);
         return;
     }
-    // the thread grid (ti, tj) = (t % 16, t / 16) strides over rows and
-    // columns (no division per entry)
-    const int ti = t & 15, tj = t >> 4;
-    for (int j = tj; j < s; j += 16)
-        for (int i = j + ti; i < s; i += 16) {
-            const double v = Lp[d.poff + i + (int64_t)j * ld];
-            M[i + j * ls] = v;
-            M[j + i * ls] = v;
+    const int64_t ld = (int64_t)s + d.c;
+    const double* F = Lp + d.poff;
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4, lane = tid & 63;
+    const double alpha = (1.0 + sqrt(17.0)) / 8.0;
+    auto slot = [](int a, int b) { return a * (a + 1) / 2 + b; };
+    double M[NS];
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int b = 0; b <= a; ++b) {
+            const int i = tx + 16 * a, k = ty + 16 * b;
+            double v = 0.0;
+            if (i < s && k < s) v = i >= k ? F[i + k * ld] : F[k + i * ld];
+            M[slot(a, b)] = v;
         }
-    if (t == 0) s_bad = 0;
-    __syncthreads();
-    // wave 0: largest |x_q| over q in [q0, q1) (q != skip), value and index
-    // (ties to the smaller index), reduced by lane exchanges
-    auto wave_max = [&](auto val, int q0, int q1, int skip, double& best, int& arg) {
-        double b = -1.0;
+    // ord[q] for the positions q = lane + 64h this lane stands for in searches
+    int ordq[NH];
+#pragma unroll
+    for (int h = 0; h < NH; ++h) ordq[h] = lane + 64 * h;
+    auto ord_at = [&](int q) {
+        int v = ordq[0];
+        if (NH > 1 && q >= 64) v = ordq[NH - 1];
+        return __builtin_amdgcn_readlane(v, q & 63);
+    };
+    auto swap_positions = [&](int q0, int q1) {
+        const int v0 = ord_at(q0), v1 = ord_at(q1);
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+            const int q = lane + 64 * h;
+            ordq[h] = q == q0 ? v1 : (q == q1 ? v0 : ordq[h]);
+        }
+    };
+    // column p of M into col: rows at and below p's sub-block row from the
+    // column's owners, rows above it from the owners of row p
+    auto publish = [&](int p, double* col) {
+        const int pt = p & 15;
+        with_subblock<NB>(p >> 4, [&](auto pbc) {
+            constexpr int pb = decltype(pbc)::value;
+            if (ty == pt) {
+#pragma unroll
+                for (int a = pb; a < NB; ++a) col[tx + 16 * a] = M[slot(a, pb)];
+            }
+            if (tx == pt) {
+#pragma unroll
+                for (int b = 0; b < pb; ++b) col[ty + 16 * b] = M[slot(pb, b)];
+            }
+        });
+    };
+    // largest |col[ord[q]]| over positions q in [q0, s), q != skip, and the
+    // smallest position holding it (-1 if none)
+    auto search = [&](const double* col, int q0, int skip, double& best, int& arg) {
+        double v[NH];
+        double m = -1.0;
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+            const int q = lane + 64 * h;
+            const bool in = q >= q0 && q < s && q != skip;
+            const double x = col[in ? ordq[h] : 0];
+            v[h] = in ? fabs(x) : -1.0;
+            m = fmax(m, v[h]);
+        }
+        m = wave_max_f64(m);
         int a = -1;
-        for (int q = q0 + lane; q < q1; q += 64)
-            if (q != skip) {
-                const double v = fabs(val(q));
-                if (v > b) { b = v; a = q; }
-            }
-        for (int h = 32; h > 0; h >>= 1) {
-            const double ob = __shfl_xor(b, h);
-            const int oa = __shfl_xor(a, h);
-            if (ob > b || (ob == b && oa >= 0 && (a < 0 || oa < a))) {
-                b = ob;
-                a = oa;
-            }
+        if (m >= 0.0) {
+            const unsigned long long b0 = __ballot(v[0] == m);
+            if (b0) a = __builtin_ctzll(b0);
+            else if (NH > 1) a = 64 + __builtin_ctzll(__ballot(v[NH - 1] == m));
         }
-        best = b;
+        best = m;
         arg = a;
     };
-    int k = 0;
-    while (k < s) {
-        if (wave == 0) {
-            double lambda;
-            int r;
-            wave_max([&](int q) { return M[q + k * ls]; }, k + 1, s, -1, lambda, r);
-            int size = 1, swap = k;
-            const double akk = fabs(M[k + k * ls]);
-            bool bad = false;
-            if (r < 0 || lambda <= 0.0) {
-                bad = akk == 0.0;
-            } else if (akk < alpha * lambda) {
-                double sigma;
-                int dummy;
-                wave_max([&](int q) { return M[r + q * ls]; }, k, s, r, sigma, dummy);
-                if (akk * sigma >= alpha * lambda * lambda) {
-                    size = 1;
-                } else if (fabs(M[r + r * ls]) >= alpha * sigma) {
-                    size = 1;
-                    swap = r;
-                } else {
-                    size = 2;
-                    swap = r;
-                }
-            }
-            if (lane == 0) {
-                s_size = size;
-                s_swap = swap;
-                if (bad) s_bad = 1;
-            }
-        }
-        __syncthreads();
-        const int size = s_size, swap = s_swap, kp = size == 2 ? k + 1 : k;
-        if (s_bad) break;
-        // symmetric interchange of kp and swap: rows, then columns
-        if (swap != kp) {
-            for (int j = t; j < s; j += kThreads) {
-                const double a = M[kp + j * ls];
-                M[kp + j * ls] = M[swap + j * ls];
-                M[swap + j * ls] = a;
-            }
+    // pivot column values at this thread's rows (ri) and columns (rk)
+    auto read_col = [&](const double* col, double (&ri)[NB], double (&rk)[NB]) {
+#pragma unroll
+        for (int a = 0; a < NB; ++a) ri[a] = col[tx + 16 * a];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) rk[b] = col[ty + 16 * b];
+    };
+    // Lanes holding row p (rows tx + 16a) and column p (columns ty + 16b).
+    // Row and column p are cleared and the pivot's own entries of the update
+    // vectors set (row side at p to -1/d, column side at p to -1); the
+    // update M(i,j) -= g_i x_j then writes the new row and column p too:
+    // g_i where M(i,p) = 0, x_p = -1; x_j / d where M(p,j) = 0; -1/d at (p,p).
+    auto hits = [&](int p, bool (&rz)[NB], bool (&cz)[NB]) {
+#pragma unroll
+        for (int a = 0; a < NB; ++a) rz[a] = tx + 16 * a == p;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) cz[b] = ty + 16 * b == p;
+    };
+
+    publish(0, cb[0]);
+    __syncthreads();
+    int cur = 0;
+    bool bad = false;
+    double ri0[NB], rk0[NB], ri1[NB], rk1[NB];
+    for (int k = 0; k < s;) {
+        const int pk = ord_at(k);
+        read_col(cb[cur], ri0, rk0);
+        double lam;
+        int rq;
+        search(cb[cur], k + 1, -1, lam, rq);
+        const double akk = fabs(uniform_f64(cb[cur][pk]));
+        int size = 1, sq = k;
+        bool on_r = false;  // 1x1 pivot on the second candidate
+        if (rq < 0 || !(lam > 0.0)) {
+            bad = akk == 0.0;
+        } else if (akk < alpha * lam) {
+            const int pr = ord_at(rq);
+            publish(pr, cb[2]);
             __syncthreads();
-            for (int i = t; i < s; i += kThreads) {
-                const double a = M[i + kp * ls];
-                M[i + kp * ls] = M[i + swap * ls];
-                M[i + swap * ls] = a;
+            double sig;
+            int unused;
+            search(cb[2], k, rq, sig, unused);
+            if (akk * sig >= alpha * lam * lam) {
+                // 1x1 pivot on the first candidate
+            } else if (fabs(uniform_f64(cb[2][pr])) >= alpha * sig) {
+                on_r = true;
+                sq = rq;
+            } else {
+                size = 2;
+                sq = rq;
             }
         }
-        if (t == 0) {
-            piv[kp] = swap;
-            if (size == 2) piv[k] = k;
-            bsz[k] = size;
-            if (size == 2) bsz[k + 1] = 0;
-        }
-        __syncthreads();
+        if (bad) break;
+        const int kp = size == 2 ? k + 1 : k;
+        if (sq != kp) swap_positions(kp, sq);
+        const int p0 = ord_at(k);
+        bool rz[NB], cz[NB];
+        hits(p0, rz, cz);
         if (size == 1) {
-            const double dk = M[k + k * ls];
-            if (dk == 0.0 || !isfinite(dk)) {
-                if (t == 0) s_bad = 1;
-                __syncthreads();
+            if (on_r) read_col(cb[2], ri0, rk0);
+            const double dd = uniform_f64((on_r ? cb[2] : cb[cur])[p0]);
+            if (dd == 0.0 || !isfinite(dd)) {
+                bad = true;
                 break;
             }
-            // trailing update with the unscaled column, then the column of L
-            const double rdk = 1.0 / dk;
-            for (int j = k + 1 + tj; j < s; j += 16) {
-                const double xj = M[j + k * ls] * rdk;
-                for (int i = k + 1 + ti; i < s; i += 16) M[i + j * ls] -= M[i + k * ls] * xj;
-            }
-            __syncthreads();
-            for (int i = k + 1 + t; i < s; i += kThreads) M[i + k * ls] /= dk;
+            const double inv = recip(dd);
+            // g = c / d (rows), x = c (columns), the pivot's entries as above
+#pragma unroll
+            for (int a = 0; a < NB; ++a) ri0[a] = rz[a] ? -inv : ri0[a] * inv;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) rk0[b] = cz[b] ? -1.0 : rk0[b];
+#pragma unroll
+            for (int a = 0; a < NB; ++a)
+#pragma unroll
+                for (int b = 0; b <= a; ++b)
+                    M[slot(a, b)] = fma(-ri0[a], rk0[b], (rz[a] || cz[b]) ? 0.0 : M[slot(a, b)]);
         } else {
-            const double a = M[k + k * ls], b = M[k + 1 + k * ls], c = M[k + 1 + (k + 1) * ls];
-            const double det = a * c - b * b;
+            const int p1 = ord_at(k + 1);
+            bool rz1[NB], cz1[NB];
+            hits(p1, rz1, cz1);
+            read_col(cb[2], ri1, rk1);
+            const double e00 = uniform_f64(cb[cur][p0]), e01 = uniform_f64(cb[cur][p1]),
+                         e11 = uniform_f64(cb[2][p1]);
+            const double det = e00 * e11 - e01 * e01;
             if (det == 0.0 || !isfinite(det)) {
-                if (t == 0) s_bad = 1;
-                __syncthreads();
+                bad = true;
                 break;
             }
-            // M(i,j) -= [M(i,k) M(i,k+1)] D^{-1} [M(j,k); M(j,k+1)]
-            const double rdet = 1.0 / det;
-            for (int j = k + 2 + tj; j < s; j += 16) {
-                const double x = M[j + k * ls], y = M[j + (k + 1) * ls];
-                const double gx = (c * x - b * y) * rdet, gy = (a * y - b * x) * rdet;
-                for (int i = k + 2 + ti; i < s; i += 16) {
-                    const double u = M[i + k * ls], v = M[i + (k + 1) * ls];
-                    M[i + j * ls] -= u * gx + v * gy;
-                }
+            const double rdet = recip(det);
+            const double i00 = e11 * rdet, i01 = -e01 * rdet, i11 = e00 * rdet;
+            // rows: (g0, g1) = M(i, b) E^{-1}, and -E^{-1}'s rows at p0, p1;
+            // columns: (x0, x1) = M(b, j), and -(1, 0), -(0, 1) at p0, p1.
+            // With rows and columns p0, p1 cleared, M(i,j) -= g0_i x0_j +
+            // g1_i x1_j gives M(:,b) E^{-1} in those columns, E^{-1} M(b,:)
+            // in those rows and -E^{-1} on the block.
+#pragma unroll
+            for (int a = 0; a < NB; ++a) {
+                const double x = ri0[a], y = ri1[a];
+                ri0[a] = rz[a] ? -i00 : (rz1[a] ? -i01 : x * i00 + y * i01);
+                ri1[a] = rz[a] ? -i01 : (rz1[a] ? -i11 : x * i01 + y * i11);
+                rz[a] = rz[a] || rz1[a];
             }
-            __syncthreads();
-            for (int i = k + 2 + t; i < s; i += kThreads) {
-                const double u = M[i + k * ls], v = M[i + (k + 1) * ls];
-                M[i + k * ls] = (u * c - v * b) / det;
-                M[i + (k + 1) * ls] = (v * a - u * b) / det;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                rk0[b] = cz[b] ? -1.0 : (cz1[b] ? 0.0 : rk0[b]);
+                rk1[b] = cz[b] ? 0.0 : (cz1[b] ? -1.0 : rk1[b]);
+                cz[b] = cz[b] || cz1[b];
             }
+#pragma unroll
+            for (int a = 0; a < NB; ++a)
+#pragma unroll
+                for (int b = 0; b <= a; ++b)
+                    M[slot(a, b)] = fma(-ri0[a], rk0[b],
+                                        fma(-ri1[a], rk1[b], (rz[a] || cz[b]) ? 0.0 : M[slot(a, b)]));
         }
-        __syncthreads();
         k += size;
+        if (k < s) publish(ord_at(k), cb[cur ^ 1]);
+        __syncthreads();
+        cur ^= 1;
     }
-    if (s_bad) {
-        if (t == 0) atomicMin(status, (unsigned long long)d.first);
+    if (bad) {  // every thread took the same decisions
+        if (tid == 0) atomicMin(status, (unsigned long long)d.first);
         return;
     }
-    // Z = (L D L^T)^{-1} of the interchanged block, in place of L and D,
-    // pivot block by pivot block from the last (the dense form of the
-    // selected-inversion recurrence): for the block b at q of width w and
-    // the rows r below it, Y = -Z(r,r) L(r,b), Z(b,b) = D_b^{-1} - L(r,b)^T Y,
-    // Z(r,b) = Y.  Z(r,r) is read from the lower triangle; L(r,b) stays in
-    // place until Y is complete.  Then T(i,j) = Z(pos(i), pos(j)), pos the
-    // position of original index i after the interchanges.
-    __shared__ double Yv[2][kLdsDiagMax], part[2][2][kLdsDiagMax], red[3][kThreads / 64];
-    __shared__ int pos_of[kLdsDiagMax], at[kLdsDiagMax];
-    auto z = [&](int a, int b) { return a >= b ? M[a + b * ls] : M[b + a * ls]; };
-    for (int q = s - 1; q >= 0;) {
-        const int w = (q > 0 && bsz[q - 1] == 2) ? 2 : 1;  // the block ending at q
-        const int b0 = q - w + 1, r0 = q + 1, nr = s - r0;
-        // Y(i, c) = -sum_k Z(i, k) L(k, b0 + c), rows i in [r0, s): two threads per row, halves of k
-        {
-            const int row = t % kLdsDiagMax, half = t / kLdsDiagMax;
-            const int i = r0 + row;
-            if (row < nr) {
-                const int k0 = r0 + half * ((nr + 1) / 2), k1 = half ? s : r0 + (nr + 1) / 2;
-                double y0 = 0.0, y1 = 0.0;
-                for (int k = k0; k < k1; ++k) {
-                    const double zk = z(i, k);
-                    y0 = fma(-zk, M[k + b0 * ls], y0);
-                    if (w == 2) y1 = fma(-zk, M[k + (b0 + 1) * ls], y1);
-                }
-                part[half][0][row] = y0;
-                part[half][1][row] = y1;
-            }
-        }
-        __syncthreads();
-        for (int row = t; row < nr; row += kThreads) {
-            Yv[0][row] = part[0][0][row] + part[1][0][row];
-            Yv[1][row] = part[0][1][row] + part[1][1][row];
-        }
-        __syncthreads();
-        // L(r,b)^T Y: three sums over the rows (w = 1: one)
-        double p00 = 0.0, p10 = 0.0, p11 = 0.0;
-        for (int row = t; row < nr; row += kThreads) {
-            const double l0 = M[r0 + row + b0 * ls], y0 = Yv[0][row];
-            p00 = fma(l0, y0, p00);
-            if (w == 2) {
-                const double l1 = M[r0 + row + (b0 + 1) * ls], y1 = Yv[1][row];
-                p10 = fma(l1, y0, p10);
-                p11 = fma(l1, y1, p11);
-            }
-        }
-        for (int h = 32; h > 0; h >>= 1) {
-            p00 += __shfl_xor(p00, h);
-            p10 += __shfl_xor(p10, h);
-            p11 += __shfl_xor(p11, h);
-        }
-        if (lane == 0) {
-            red[0][wave] = p00;
-            red[1][wave] = p10;
-            red[2][wave] = p11;
-        }
-        // Z(r, b) = Y, then Z(b, b) = D_b^{-1} - L^T Y
-        for (int row = t; row < nr; row += kThreads) {
-            M[r0 + row + b0 * ls] = Yv[0][row];
-            if (w == 2) M[r0 + row + (b0 + 1) * ls] = Yv[1][row];
-        }
-        __syncthreads();  // the wave sums are in red
-        if (t == 0) {
-            double r00 = 0.0, r10 = 0.0, r11 = 0.0;
-            for (int v = 0; v < kThreads / 64; ++v) {
-                r00 += red[0][v];
-                r10 += red[1][v];
-                r11 += red[2][v];
-            }
-            if (w == 1) {
-                M[b0 + b0 * ls] = 1.0 / M[b0 + b0 * ls] - r00;
-            } else {
-                const double a = M[b0 + b0 * ls], b = M[b0 + 1 + b0 * ls], c = M[b0 + 1 + (b0 + 1) * ls];
-                const double det = a * c - b * b;
-                // L^T Y is symmetric in exact arithmetic: its off-diagonal entry from the lower product
-                M[b0 + b0 * ls] = c / det - r00;
-                M[b0 + 1 + b0 * ls] = -b / det - r10;
-                M[b0 + 1 + (b0 + 1) * ls] = a / det - r11;
-            }
-        }
-        __syncthreads();
-        q = b0 - 1;
-    }
-    // pos_of[original index] = its position after the interchanges
-    if (t == 0) {
-        for (int k = 0; k < s; ++k) at[k] = k;  // at[position] = original index
-        for (int k = 0; k < s; ++k) {
-            const int a = at[k];
-            at[k] = at[piv[k]];
-            at[piv[k]] = a;
-        }
-        for (int k = 0; k < s; ++k) pos_of[at[k]] = k;
-    }
-    __syncthreads();
+    // T = -M from the lower triangle (exactly symmetric)
     double* T = Tp + d.woff;
-    for (int j = tj; j < s; j += 16)
-        for (int i = ti; i < s; i += 16) T[i + j * s] = z(pos_of[i], pos_of[j]);
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int b = 0; b <= a; ++b) {
+            const int i = tx + 16 * a, j = ty + 16 * b;
+            if (i < s && j < s && i >= j) {
+                T[i + (int64_t)j * s] = -M[slot(a, b)];
+                T[j + (int64_t)i * s] = -M[slot(a, b)];
+            }
+        }
 }
 
 // ===========================================================================
@@ -2791,11 +2826,8 @@ hipError_t kernels_init()
     // set once per process (a failure is not remembered: the next call tries again)
     static std::atomic<bool> done{false};
     if (done.load()) return hipSuccess;
-    hipError_t e =
+    const hipError_t e =
         hipFuncSetAttribute((const void*)k_rf3, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsDiagBytes);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void*)k_ldlt_bk, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)kLdsDiagBytes);
     if (e == hipSuccess) done.store(true);
     return e;
 }
@@ -2919,15 +2951,16 @@ hipError_t launch_sb_invert(Prof* P, const DevPtrs& D, int64_t sb0, int64_t nsb,
 
 hipError_t launch_ldlt_bk(Prof* P, const DevPtrs& D, const int64_t diag[4], hipStream_t s)
 {
-    // by width class, each with the LDS its widest block needs (so that the
-    // many narrow blocks near the leaves share a CU)
-    const int wmax[3] = {32, 64, kLdsDiagMax};
-    for (int k = 0; k < 3; k++) {
-        const int64_t n = diag[k + 1] - diag[k];
-        if (n > 0)
-            launch(P, kLdlt, k_ldlt_bk, dim3((unsigned)n), sizeof(double) * wmax[k] * (wmax[k] + 1), s,
-                   D.t_ldlt + diag[k], D.blocks, (const double*)D.Lp, D.Tp, D.status);
-    }
+    // by width class: [diag[0], diag[1]) s <= 32, then <= 64, then <= 128
+    if (diag[1] > diag[0])
+        launch(P, kLdlt, k_ldlt_bk<2>, dim3((unsigned)(diag[1] - diag[0])), 0, s, D.t_ldlt + diag[0], D.blocks,
+               (const double*)D.Lp, D.Tp, D.status);
+    if (diag[2] > diag[1])
+        launch(P, kLdlt, k_ldlt_bk<4>, dim3((unsigned)(diag[2] - diag[1])), 0, s, D.t_ldlt + diag[1], D.blocks,
+               (const double*)D.Lp, D.Tp, D.status);
+    if (diag[3] > diag[2])
+        launch(P, kLdlt, k_ldlt_bk<8>, dim3((unsigned)(diag[3] - diag[2])), 0, s, D.t_ldlt + diag[2], D.blocks,
+               (const double*)D.Lp, D.Tp, D.status);
     return hipGetLastError();
 }
 
