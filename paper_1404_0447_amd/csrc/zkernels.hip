@@ -256,32 +256,133 @@ __global__ __launch_bounds__(kThreads) void k_zschur(const Task* __restrict__ ta
 }
 
 // Ainv(C,K) rows [r0, r0+64) = -G L_hat with G = Ainv(C,C) gathered from the
-// ancestors' inverse panels (lower entries; the upper ones by symmetry)
+// ancestors' inverse panels: G(i,k) = Ainv[cbase[p] + rel[rbase[p] + q]] with
+// p = min(i,k), q = max(i,k) (lower entries; the upper ones by symmetry).
+// Each element's address is a chain of three dependent loads, so the loop is
+// pipelined over four chunks, one stage a chunk apart: (cbase, rbase) pairs
+// of chunk n+3, rel entries of chunk n+2, values of chunk n+1 (G and L_hat),
+// the LDS planes of chunk n feeding the MFMAs.  Chunks entirely above the
+// diagonal band (every k past the tile's rows, p = i) are read along k, so
+// sixteen lanes walk one row of an ancestor panel; the others along i.
+// Loads are unconditional (a padding element reads an in-bounds stand-in and
+// is zeroed by its mask at the LDS store), so no wait sits behind a branch.
 __global__ __launch_bounds__(kThreads) void k_zgemm(const Task* __restrict__ tasks, const BlockDesc* __restrict__ blk,
                                                     double* __restrict__ Ap, const double* __restrict__ Hp,
-                                                    const int64_t* __restrict__ cbase,
-                                                    const int64_t* __restrict__ rbase, const int32_t* __restrict__ rel)
+                                                    const int64_t* __restrict__ cr2, const int32_t* __restrict__ rel)
 {
+    typedef int64_t i64v2 __attribute__((ext_vector_type(2)));
     const Task tk = tasks[blockIdx.x];
     const BlockDesc d = blk[tk.b];
     const int s = d.s, c = d.c, r0 = tk.i0;
     const int64_t ld = (int64_t)s + c;
-    auto la = [&](int k, int i) {
-        const int ii = r0 + i;
-        if (k >= c || ii >= c) return z2{0, 0};
-        const int lo = ii >= k ? ii : k, hi = ii >= k ? k : ii;  // G(lo, hi), lo >= hi
-        const int64_t ph = d.coff + hi;
-        return zload(Ap, cbase[ph] + rel[rbase[ph] + lo]);
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wm0 = (wave & 1) * 32, wn0 = (wave >> 1) * 32;
+    constexpr int NQ = (kZK * kZT) / kThreads;  // elements of each operand per thread and chunk
+    const int nch = (c + kZK - 1) / kZK;
+    const double* Lh = Hp + 2 * d.hoff;
+    auto along_of = [&](int ch) { return ch * kZK >= r0 + kZT; };
+    // stage M: (cbase, rbase) of p and q (-1: padding); stage R: cbase and
+    // the rel entry; stage V: the values
+    int64_t m_cb[NQ], m_rb[NQ];
+    int m_q[NQ];
+    int64_t r_cb[NQ];
+    int32_t r_rel[NQ];
+    bool r_ok[NQ];
+    z2 v_a[NQ], v_b[NQ];
+    bool v_ok[NQ], v_bok[NQ], v_al = false;
+    auto stage_m = [&](int ch) {
+        const bool al = along_of(ch);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int e = t + q * kThreads;
+            const int k = ch * kZK + (al ? (e & 15) : (e >> 6)), i = r0 + (al ? (e >> 4) : (e & 63));
+            const bool ok = ch < nch && k < c && i < c;
+            const int64_t p = d.coff + (ok ? (i >= k ? k : i) : 0);
+            const i64v2 cr = *reinterpret_cast<const i64v2*>(cr2 + 2 * p);
+            m_cb[q] = cr.x;
+            m_rb[q] = cr.y;
+            m_q[q] = ok ? (i >= k ? i : k) : -1;
+        }
     };
-    auto lb = [&](int k, int j) { return (k < c && j < s) ? zload(Hp, d.hoff + k + (int64_t)j * c) : z2{0, 0}; };
-    auto out = [&](int ti, int j, z2 v) {
-        const int i = r0 + ti;
-        if (i < c && j < s) zstore(Ap, d.poff + s + i + (int64_t)j * ld, -v);
+    auto stage_r = [&]() {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            r_ok[q] = m_q[q] >= 0;
+            r_rel[q] = rel[m_rb[q] + (r_ok[q] ? m_q[q] : 0)];
+            r_cb[q] = m_cb[q];
+        }
+    };
+    auto stage_v = [&](int ch) {
+        v_al = along_of(ch);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            v_a[q] = zload(Ap, r_cb[q] + r_rel[q]);
+            v_ok[q] = r_ok[q];
+            // L_hat(k, j) along k (contiguous), a stand-in past the ends
+            const int e = t + q * kThreads;
+            const int k = ch * kZK + (e & 15), j = e >> 4;
+            v_bok[q] = k < c && j < s;
+            v_b[q] = zload(Lh, v_bok[q] ? k + (int64_t)j * c : 0);
+        }
     };
     __shared__ ZLdsM L;
+    auto stage_store = [&]() {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int e = t + q * kThreads;
+            const int kk = v_al ? (e & 15) : (e >> 6), i = v_al ? (e >> 4) : (e & 63);
+            const z2 x = v_ok[q] ? v_a[q] : z2{0.0, 0.0};
+            L.ar[kk][i] = x.x;
+            L.ai[kk][i] = x.y;
+            const z2 y = v_bok[q] ? v_b[q] : z2{0.0, 0.0};
+            L.br[e & 15][e >> 4] = y.x;
+            L.bi[e & 15][e >> 4] = y.y;
+        }
+    };
     ZAcc acc = {};
-    ztile_mfma(L, c, acc, la, lb);
-    zvisit(acc, out);
+    stage_m(0);
+    stage_r();
+    stage_v(0);
+    stage_m(1);
+    stage_r();
+    stage_m(2);
+    // registers now: values of chunk 0, rel entries of chunk 1, pairs of chunk 2
+    for (int ch = 0; ch < nch; ++ch) {
+        stage_store();
+        __syncthreads();
+        stage_v(ch + 1);
+        stage_r();
+        stage_m(ch + 3);
+#pragma unroll
+        for (int ks = 0; ks < kZK / 4; ++ks) {
+            const int kr = 4 * ks + (lane >> 4);
+            double xr[2], xi[2], yr[2], yi[2];
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                xr[m] = L.ar[kr][wm0 + 16 * m + (lane & 15)];
+                xi[m] = L.ai[kr][wm0 + 16 * m + (lane & 15)];
+                yr[m] = L.br[kr][wn0 + 16 * m + (lane & 15)];
+                yi[m] = L.bi[kr][wn0 + 16 * m + (lane & 15)];
+            }
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int n = 0; n < 2; ++n) {
+                    acc.re[m][n] = zmfma(xr[m], yr[n], acc.re[m][n]);
+                    acc.re[m][n] = zmfma(-xi[m], yi[n], acc.re[m][n]);
+                    acc.im[m][n] = zmfma(xr[m], yi[n], acc.im[m][n]);
+                    acc.im[m][n] = zmfma(xi[m], yr[n], acc.im[m][n]);
+                }
+        }
+        __syncthreads();
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    asm volatile("s_nop 15\n\ts_nop 15\n\ts_nop 15\n\ts_nop 15" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+    zvisit(acc, [&](int ti, int j, z2 v) {
+        const int i = r0 + ti;
+        if (i < c && j < s) zstore(Ap, d.poff + s + i + (int64_t)j * ld, -v);
+    });
 }
 
 // Ainv(K,K) = T - (P + P^T) / 2 with P = L_hat^T Ainv(C,K) (lower triangle)
@@ -377,7 +478,7 @@ hipError_t launch_zinvert_level(const DevPtrs& D, int64_t gemm0, int64_t ngemm, 
 {
     if (ngemm > 0)
         hipLaunchKernelGGL(k_zgemm, dim3((unsigned)ngemm), dim3(kThreads), 0, s, D.t_gemm + gemm0, D.blocks, D.Ap,
-                           (const double*)D.Hp, D.cbase, D.rbase, D.rel);
+                           (const double*)D.Hp, D.cr2, D.rel);
     if (nsdiag > 0)
         hipLaunchKernelGGL(k_zsdiag, dim3((unsigned)nsdiag), dim3(kThreads), 0, s, D.t_sdiag + sdiag0, D.blocks,
                            D.Ap, (const double*)D.Hp, (const double*)D.Tp);
