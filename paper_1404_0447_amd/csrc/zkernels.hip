@@ -49,8 +49,14 @@ struct ZAcc {
     zd4 re[2][2], im[2][2];
 };
 
-template <class LA, class LB>
-__device__ __forceinline__ void ztile_mfma(ZLdsM& L, int K, ZAcc& acc, LA loadA, LB loadB)
+struct ZNoHook {
+    __device__ void operator()() const {}
+};
+
+// after_first: loads of the caller's own, issued once the first chunk's
+// operand loads are in flight (they may then wait under the products)
+template <class LA, class LB, class AF = ZNoHook>
+__device__ __forceinline__ void ztile_mfma(ZLdsM& L, int K, ZAcc& acc, LA loadA, LB loadB, AF after_first = AF())
 {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int wm0 = (wave & 1) * 32, wn0 = (wave >> 1) * 32;
@@ -65,6 +71,7 @@ __device__ __forceinline__ void ztile_mfma(ZLdsM& L, int K, ZAcc& acc, LA loadA,
         }
     };
     if (K > 0) fetch(0);
+    after_first();
     for (int k0 = 0; k0 < K; k0 += kZK) {
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
@@ -229,30 +236,67 @@ __global__ __launch_bounds__(kThreads) void k_zpanel(const Task* __restrict__ ta
 
 // Schur update of one 64 x 64 lower tile (rows i0.., columns k0.. of C):
 // F(C[i], C[k]) -= sum_t L_hat(i, t) F(C[k], t), scattered into the owning
-// ancestor panels; the tasks of one launch touch disjoint entries.
+// ancestor panels; the tasks of one launch touch disjoint entries.  The
+// scatter targets do not depend on the product: their (cbase, rbase) pairs
+// are loaded before the products and the rel entries under them, and the
+// epilogue reads every target before it writes the first.
 __global__ __launch_bounds__(kThreads) void k_zschur(const Task* __restrict__ tasks, const BlockDesc* __restrict__ blk,
                                                      double* __restrict__ Lp, const double* __restrict__ Hp,
-                                                     const int64_t* __restrict__ cbase,
-                                                     const int64_t* __restrict__ rbase, const int32_t* __restrict__ rel)
+                                                     const int64_t* __restrict__ cr2, const int32_t* __restrict__ rel)
 {
+    typedef int64_t i64v2 __attribute__((ext_vector_type(2)));
     const Task tk = tasks[blockIdx.x];
     const BlockDesc d = blk[tk.b];
     const int s = d.s, c = d.c, i0 = tk.i0, k0 = tk.j0;
     const int64_t ld = (int64_t)s + c;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm0 = (wave & 1) * 32, wn0 = (wave >> 1) * 32;
+    // this thread's outputs (as zvisit visits them): rows i0 + wm0 + 16m +
+    // lane / 16 + 4v, columns k0 + wn0 + 16n + lane % 16
+    auto row_of = [&](int m, int v) { return i0 + wm0 + 16 * m + (lane >> 4) + 4 * v; };
+    auto col_of = [&](int n) { return k0 + wn0 + 16 * n + (lane & 15); };
+    auto live = [&](int m, int n, int v) {
+        const int ii = row_of(m, v), kk = col_of(n);
+        return ii < c && kk < c && ii >= kk;
+    };
+    int64_t cb[2], rb[2];
+#pragma unroll
+    for (int n = 0; n < 2; ++n) {
+        const int kk = col_of(n);
+        const i64v2 cr = *reinterpret_cast<const i64v2*>(cr2 + 2 * (d.coff + (kk < c ? kk : 0)));
+        cb[n] = cr.x;
+        rb[n] = cr.y;
+    }
+    int32_t ro[2][2][4];
+    auto prefetch = [&]() {
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int n = 0; n < 2; ++n)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) ro[m][n][v] = rel[rb[n] + (live(m, n, v) ? row_of(m, v) : 0)];
+    };
     auto la = [&](int t, int i) { return (t < s && i0 + i < c) ? zload(Hp, d.hoff + i0 + i + (int64_t)t * c) : z2{0, 0}; };
     auto lb = [&](int t, int k) { return (t < s && k0 + k < c) ? zload(Lp, d.poff + s + k0 + k + (int64_t)t * ld) : z2{0, 0}; };
-    auto out = [&](int ti, int tk2, z2 v) {
-        const int ii = i0 + ti, kk = k0 + tk2;
-        if (ii < c && kk < c && ii >= kk) {
-            const int64_t pk = d.coff + kk;
-            const int64_t e = cbase[pk] + rel[rbase[pk] + ii];
-            zstore(Lp, e, zload(Lp, e) - v);
-        }
-    };
     __shared__ ZLdsM L;
     ZAcc acc = {};
-    ztile_mfma(L, s, acc, la, lb);
-    zvisit(acc, out);
+    ztile_mfma(L, s, acc, la, lb, prefetch);
+    z2 old[2][2][4];
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int n = 0; n < 2; ++n)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                old[m][n][v] = live(m, n, v) ? zload(Lp, cb[n] + ro[m][n][v]) : z2{0.0, 0.0};
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int n = 0; n < 2; ++n)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                if (live(m, n, v))
+                    zstore(Lp, cb[n] + ro[m][n][v], old[m][n][v] - z2{acc.re[m][n][v], acc.im[m][n][v]});
 }
 
 // Ainv(C,K) rows [r0, r0+64) = -G L_hat with G = Ainv(C,C) gathered from the
@@ -468,7 +512,7 @@ hipError_t launch_zfactor_level(const DevPtrs& D, int64_t diag0, int64_t ndiag, 
         const int64_t n = schur_cuts[g + 1] - schur_cuts[g];
         if (n > 0)
             hipLaunchKernelGGL(k_zschur, dim3((unsigned)n), dim3(kThreads), 0, s, D.t_schur + schur_cuts[g], D.blocks,
-                               D.Lp, (const double*)D.Hp, D.cbase, D.rbase, D.rel);
+                               D.Lp, (const double*)D.Hp, D.cr2, D.rel);
     }
     return hipGetLastError();
 }
