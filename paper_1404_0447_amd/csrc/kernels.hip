@@ -1770,18 +1770,21 @@ __global__ __launch_bounds__(kThreads) void k_ldlt_bk(const Task* __restrict__ t
         });
     };
     // largest |col[ord[q]]| over positions q in [q0, s), q != skip, and the
-    // smallest position holding it (-1 if none)
-    auto search = [&](const double* col, int q0, int skip, double& best, int& arg) {
-        double v[NH];
-        double m = -1.0;
+    // smallest position holding it (-1 if none): the LDS reads, then the
+    // reduction (split so that other reads can be issued in between)
+    auto search_load = [&](const double* col, int q0, int skip, double (&v)[NH]) {
 #pragma unroll
         for (int h = 0; h < NH; ++h) {
             const int q = lane + 64 * h;
             const bool in = q >= q0 && q < s && q != skip;
             const double x = col[in ? ordq[h] : 0];
             v[h] = in ? fabs(x) : -1.0;
-            m = fmax(m, v[h]);
         }
+    };
+    auto search_reduce = [&](const double (&v)[NH], double& best, int& arg) {
+        double m = -1.0;
+#pragma unroll
+        for (int h = 0; h < NH; ++h) m = fmax(m, v[h]);
         m = wave_max_f64(m);
         int a = -1;
         if (m >= 0.0) {
@@ -1818,25 +1821,37 @@ __global__ __launch_bounds__(kThreads) void k_ldlt_bk(const Task* __restrict__ t
     double ri0[NB], rk0[NB], ri1[NB], rk1[NB];
     for (int k = 0; k < s;) {
         const int pk = ord_at(k);
+        // the candidate's diagonal and the search first (they decide the
+        // step), then its column for the update
+        const double akk_raw = cb[cur][pk];
+        double v[NH];
+        search_load(cb[cur], k + 1, -1, v);
         read_col(cb[cur], ri0, rk0);
         double lam;
         int rq;
-        search(cb[cur], k + 1, -1, lam, rq);
-        const double akk = fabs(uniform_f64(cb[cur][pk]));
+        search_reduce(v, lam, rq);
+        const double akk_s = uniform_f64(akk_raw), akk = fabs(akk_s);
         int size = 1, sq = k;
-        bool on_r = false;  // 1x1 pivot on the second candidate
+        bool on_r = false;   // 1x1 pivot on the second candidate
+        double rr_s = 0.0;   // M(r, r), signed
+        double e01 = 0.0;    // M(r, k), signed
         if (rq < 0 || !(lam > 0.0)) {
             bad = akk == 0.0;
         } else if (akk < alpha * lam) {
             const int pr = ord_at(rq);
+            const double e01_raw = cb[cur][pr];
             publish(pr, cb[2]);
             __syncthreads();
+            const double rr_raw = cb[2][pr];
+            search_load(cb[2], k, rq, v);
             double sig;
             int unused;
-            search(cb[2], k, rq, sig, unused);
+            search_reduce(v, sig, unused);
+            rr_s = uniform_f64(rr_raw);
+            e01 = uniform_f64(e01_raw);
             if (akk * sig >= alpha * lam * lam) {
                 // 1x1 pivot on the first candidate
-            } else if (fabs(uniform_f64(cb[2][pr])) >= alpha * sig) {
+            } else if (fabs(rr_s) >= alpha * sig) {
                 on_r = true;
                 sq = rq;
             } else {
@@ -1852,7 +1867,7 @@ __global__ __launch_bounds__(kThreads) void k_ldlt_bk(const Task* __restrict__ t
         hits(p0, rz, cz);
         if (size == 1) {
             if (on_r) read_col(cb[2], ri0, rk0);
-            const double dd = uniform_f64((on_r ? cb[2] : cb[cur])[p0]);
+            const double dd = on_r ? rr_s : akk_s;
             if (dd == 0.0 || !isfinite(dd)) {
                 bad = true;
                 break;
@@ -1873,8 +1888,7 @@ __global__ __launch_bounds__(kThreads) void k_ldlt_bk(const Task* __restrict__ t
             bool rz1[NB], cz1[NB];
             hits(p1, rz1, cz1);
             read_col(cb[2], ri1, rk1);
-            const double e00 = uniform_f64(cb[cur][p0]), e01 = uniform_f64(cb[cur][p1]),
-                         e11 = uniform_f64(cb[2][p1]);
+            const double e00 = akk_s, e11 = rr_s;
             const double det = e00 * e11 - e01 * e01;
             if (det == 0.0 || !isfinite(det)) {
                 bad = true;
