@@ -342,7 +342,9 @@ def cpu_baseline(m, workload, cap, flops_step, gpu_gflops, out):
     """The oracle (its factor + selected inversion, symbolic phase excluded)
     on the host cores: the whole matrix when it is small, else the half box
     [0,32) x [0,64) x [0,64) of the 64^3 grid, which is the subtree its nested
-    dissection orders first (n = 131,072, about 10-30 s of CPU work)."""
+    dissection orders first (n = 131,072, about 7 s of CPU work a run on 16
+    threads).  The figure is the median of three runs; one single-thread run
+    on the 32^3 corner box (the whole matrix when it is small) sits beside it."""
     import numpy as np
     from oracle import oracle as O
     if workload == "lap3d_64":
@@ -355,17 +357,24 @@ def cpu_baseline(m, workload, cap, flops_step, gpu_gflops, out):
         assert np.array_equal(full[:sample_m.n], to_full[O.nd_order(3, (32, 64, 64))])
         sample = ("principal submatrix of the 64^3 matrix on the half box [0,32)x[0,64)x[0,64), the first "
                   "subtree of its nested dissection (n=131072), cap 256")
+        single_m = sub_box(m, m.dims, (32, 32, 32))
+        single = "principal submatrix of the 64^3 matrix on the corner box [0,32)^3 (n=32768), cap 256"
     else:
         sample_m, sample = m, f"the whole {workload} matrix"
+        single_m, single = m, sample
     log(f"[bench] cpu baseline: oracle symbolic on {sample_m.n} unknowns ...")
     osym = O.symbolic(sample_m, cap=cap)
     fl = osym.sym.factor_flops + selinv_flops(osym.sym)
-    log("[bench] cpu baseline: oracle factor + selected inversion ...")
+    log("[bench] cpu baseline: oracle factor + selected inversion, three runs ...")
+    runs, ref = [], None
     t0 = time.time()
-    ref, _, st, _, tf, ts = osym.factor_selinv(sample_m.vals)
+    for _ in range(3):
+        ref, _, st, _, tf, ts = osym.factor_selinv(sample_m.vals)
+        assert st == 0
+        runs.append(tf + ts)
     wall = time.time() - t0
-    assert st == 0
-    cpu_gflops = fl / (tf + ts) / 1e9
+    t_med = float(np.median(runs))
+    cpu_gflops = fl / t_med / 1e9
     err = None
     if sample_m is m:
         got = out.cpu().numpy()
@@ -373,14 +382,28 @@ def cpu_baseline(m, workload, cap, flops_step, gpu_gflops, out):
         d = ref[cp[:-1]]
         cols = np.repeat(np.arange(m.n), np.diff(cp))
         err = float(np.max(np.abs(got - ref) / np.sqrt(np.abs(d[ri] * d[cols]))))
+    cores = O.threads()
+    # one thread, smaller sample
+    osym1 = O.symbolic(single_m, cap=cap)
+    fl1 = osym1.sym.factor_flops + selinv_flops(osym1.sym)
+    O.set_threads(1)
+    try:
+        _, _, st, _, tf1, ts1 = osym1.factor_selinv(single_m.vals)
+    finally:
+        O.set_threads(cores)
+    assert st == 0
     cpu_model = next((ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo")
                       if ln.startswith("model name")), "unknown")
-    res = {"value": round(cpu_gflops, 3), "unit": "GFLOP/s", "cores": O.threads(), "kind": "oracle",
+    res = {"value": round(cpu_gflops, 3), "unit": "GFLOP/s", "cores": cores, "kind": "oracle",
            "cpu_model": cpu_model, "nproc": os.cpu_count(),
-           "sample": f"{sample}: factor + selected inversion (symbolic excluded), {fl:.3e} flops in "
-                     f"{tf + ts:.2f}s, one run",
+           "sample": f"{sample}: factor + selected inversion (symbolic excluded), {fl:.3e} flops, median of "
+                     f"3 runs ({', '.join(f'{r:.2f}' for r in runs)} s)",
+           "runs_s": [round(r, 3) for r in runs],
+           "single_thread": {"value": round(fl1 / (tf1 + ts1) / 1e9, 3), "unit": "GFLOP/s", "cores": 1,
+                             "sample": f"{single}: {fl1:.3e} flops in {tf1 + ts1:.2f}s, one run"},
            "speedup_gpu_over_cpu": round(gpu_gflops / cpu_gflops, 2)}
-    log(f"[bench] oracle {tf + ts:.2f}s ({wall:.1f}s wall) = {cpu_gflops:.2f} GFLOP/s on {O.threads()} threads")
+    log(f"[bench] oracle median {t_med:.2f}s of 3 ({wall:.1f}s wall) = {cpu_gflops:.2f} GFLOP/s on {cores} threads; "
+        f"1 thread {res['single_thread']['value']:.2f} GFLOP/s on n={single_m.n}")
     return res, err
 
 

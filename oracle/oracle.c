@@ -65,6 +65,14 @@ int orc_get_threads(void)
     return 1;
 #endif
 }
+/* threads of the following parallel regions (n > 0); returns the setting */
+int orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#endif
+    return orc_get_threads();
+}
 
 /* ------------------------------------------------------------------ */
 /* Nested dissection over a box of grid points                         */

@@ -77,6 +77,8 @@ def lib():
         L.orc_dense_grad.argtypes = [ct.c_int, _f64p, _i64p, _i32p, _f64p, _i64p, _i32p, _f64p]
         L.orc_set_mutation.argtypes = [ct.c_int]
         L.orc_get_threads.restype = ct.c_int
+        L.orc_set_threads.argtypes = [ct.c_int]
+        L.orc_set_threads.restype = ct.c_int
         _lib = L
     return _lib
 
@@ -91,6 +93,11 @@ def set_mutation(m: int) -> None:
 
 def threads() -> int:
     return int(lib().orc_get_threads())
+
+
+def set_threads(n: int) -> int:
+    """OpenMP threads of the oracle's later calls; returns the setting."""
+    return int(lib().orc_set_threads(int(n)))
 
 
 def nd_order(ndim, dims, dofs=1, rim_last=False):
