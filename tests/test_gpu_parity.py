@@ -193,8 +193,8 @@ def test_molecular_full():
 def test_lap3d_64_full_properties():
     """64^3 grid, log-uniform conductivities in [0.1, 10], shift 1e-3, cap 256
     (n = 262144, 1.6e8 selected entries), in the benchmark's launch
-    configuration.  The oracle would take minutes at this size, so the check
-    uses identities that hold at any size: sum_j A_ij Ainv_ji = 1 on every
+    configuration: identities that hold at any size (the element-wise oracle
+    comparison is the next test): sum_j A_ij Ainv_ji = 1 on every
     row (A's pattern lies inside L's), |Ainv_ij| <= sqrt(Ainv_ii Ainv_jj) and
     Ainv_ii > 0 on every selected entry; and two calls agree to rounding."""
     torch = _torch()
