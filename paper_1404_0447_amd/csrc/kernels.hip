@@ -3,7 +3,8 @@
 // Data layout (all FP64, in one caller-bound workspace):
 //   Lp  panels of the factor: block B is an (s+c) x s column-major panel,
 //       ld = s+c; rows = cols(B) then C(B).  The s x s block holds L_BB
-//       (unit diagonal implied, D on the diagonal); the C rows hold
+//       (unit diagonal implied, D on the diagonal; with 2x2 pivots it keeps
+//       the assembled F_BB, whose inverse goes to Tp alone); the C rows hold
 //       F(C,B), the assembled and updated entries of A (L(C,B) is
 //       F(C,B) L_BB^{-T} D^{-1} and is formed only on export).
 //   Ap  same layout, holds the selected entries of A^{-1}.

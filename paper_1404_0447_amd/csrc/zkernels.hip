@@ -9,6 +9,8 @@
 // operands staged through LDS in 16-deep chunks.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "kernels.hpp"
 #include "plan.hpp"
 #include "tiles.hpp"
@@ -129,88 +131,132 @@ __device__ __forceinline__ void zvisit(const ZAcc& acc, F f)
 __device__ __forceinline__ z2 zload(const double* p, int64_t e) { return *reinterpret_cast<const z2*>(p + 2 * e); }
 __device__ __forceinline__ void zstore(double* p, int64_t e, z2 v) { *reinterpret_cast<z2*>(p + 2 * e) = v; }
 
-// ---------------------------------------------------------------------------
-// diagonal block: F_KK = L_KK D_K L_KK^T (unit lower L, complex pivots, no
-// interchanges), then T_K = F_KK^{-1} in place of L and D by the dense
-// selected-inversion recurrence, pivot by pivot from the last: with r the
-// rows below pivot j, Y = -Z(r,r) L(r,j), Z(j,j) = 1/d_j - L(r,j)^T Y,
-// Z(r,j) = Y (plain transposes).  One work-group per block, s <= 64, the
-// lower triangle in LDS; only T leaves the kernel (the rest of the method
-// reads the diagonal block through T alone).
-// ---------------------------------------------------------------------------
 __device__ __forceinline__ z2 zrecip(z2 b)
 {
     const double den = b.x * b.x + b.y * b.y;
     return z2{b.x / den, -b.y / den};
 }
 
+// ---------------------------------------------------------------------------
+// Diagonal block by the symmetric sweep (Gauss-Jordan) in registers: pivot p
+// in natural order (d = M(p,p), c = column p) sets M(i,j) -= c_i c_j / d,
+// M(i,p) = c_i / d, M(p,p) = -1/d, plain (not conjugate) products, so after
+// all s pivots M = -F_KK^{-1} = -T_K; only T leaves the kernel.  Thread
+// (tx, ty) holds the lower 16 x 16 sub-blocks' entries (tx + 16a, ty + 16b),
+// a >= b; a pivot's column goes through LDS (two alternating slots, one
+// barrier per pivot).  Row and column p are cleared by lane masks and the
+// pivot's own entries of the update vectors set to -1/d (rows) and -1
+// (columns), so one rank-1 pass also writes the new row and column p.  s <=
+// 64, one work-group per block; a zero or non-finite pivot latches its column.
+// ---------------------------------------------------------------------------
+template <int N, class Fn>
+__device__ __forceinline__ void zfor(Fn&& f)
+{
+    if constexpr (N > 0) {
+        zfor<N - 1>(f);
+        f(std::integral_constant<int, N - 1>{});
+    }
+}
+
+__device__ __forceinline__ z2 zuniform(z2 v)
+{
+    const double x = v.x, y = v.y;
+    const int a = __builtin_amdgcn_readfirstlane(__double2loint(x)), b = __builtin_amdgcn_readfirstlane(__double2hiint(x));
+    const int c = __builtin_amdgcn_readfirstlane(__double2loint(y)), e = __builtin_amdgcn_readfirstlane(__double2hiint(y));
+    return z2{__hiloint2double(b, a), __hiloint2double(e, c)};
+}
+
 __global__ __launch_bounds__(kThreads) void k_zdiag(const Task* __restrict__ tasks, const BlockDesc* __restrict__ blk,
                                                     double* __restrict__ Lp, double* __restrict__ Tp,
                                                     unsigned long long* __restrict__ status)
 {
-    __shared__ z2 F[kZT][kZT + 1];  // F[i][k], i >= k: the lower triangle, then Z
-    __shared__ z2 Yp[4][kZT];       // partial sums of Y, four threads per row
-    __shared__ z2 Yv[kZT];
-    __shared__ z2 red[kThreads / 64];
+    constexpr int NB = kZT / 16;
+    constexpr int NS = NB * (NB + 1) / 2;
+    __shared__ z2 cb[2][kZT];
     const BlockDesc d = blk[tasks[blockIdx.x].b];
-    const int s = d.s, t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int ti = t & 15, tj = t >> 4;  // 16 x 16 thread grid over rows and columns
+    const int s = d.s, tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
     const int64_t ld = (int64_t)d.s + d.c;
-    for (int k = tj; k < s; k += 16)
-        for (int i = k + ti; i < s; i += 16) F[i][k] = zload(Lp, d.poff + i + (int64_t)k * ld);
+    auto slot = [](int a, int b) { return a * (a + 1) / 2 + b; };
+    z2 M[NS];
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int b = 0; b <= a; ++b) {
+            const int i = tx + 16 * a, k = ty + 16 * b;
+            z2 v = {0.0, 0.0};
+            if (i < s && k < s) v = i >= k ? zload(Lp, d.poff + i + (int64_t)k * ld) : zload(Lp, d.poff + k + (int64_t)i * ld);
+            M[slot(a, b)] = v;
+        }
+    // column p into col: rows at and below p's sub-block row from the
+    // column's owners, the rows above from the owners of row p
+    auto publish = [&](int p, z2* col) {
+        const int pt = p & 15, pb = p >> 4;
+        zfor<NB>([&](auto c) {
+            constexpr int b0 = decltype(c)::value;
+            if (pb == b0) {
+                if (ty == pt) {
+#pragma unroll
+                    for (int a = b0; a < NB; ++a) col[tx + 16 * a] = M[slot(a, b0)];
+                }
+                if (tx == pt) {
+#pragma unroll
+                    for (int b = 0; b < b0; ++b) col[ty + 16 * b] = M[slot(b0, b)];
+                }
+            }
+        });
+    };
+    if (s > 0) publish(0, cb[0]);
     __syncthreads();
     int bad = -1;
-    for (int j = 0; j < s; ++j) {
-        const z2 dj = F[j][j];
-        if (bad < 0 && !((dj.x != 0.0 || dj.y != 0.0) && isfinite(dj.x) && isfinite(dj.y))) bad = j;
-        const z2 rdj = zrecip(dj);
-        // trailing update F(i,k) -= F(i,j) F(k,j) / d_j, j < k <= i
-        for (int k = j + 1 + tj; k < s; k += 16) {
-            const z2 fk = zmul(F[k][j], rdj);
-            for (int i = k + ti; i < s; i += 16) F[i][k] -= zmul(F[i][j], fk);
+    for (int p = 0; p < s; ++p) {
+        const z2* col = cb[p & 1];
+        z2 ri[NB], rk[NB];
+#pragma unroll
+        for (int a = 0; a < NB; ++a) ri[a] = col[tx + 16 * a];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) rk[b] = col[ty + 16 * b];
+        const z2 dp = zuniform(col[p]);
+        if (!((dp.x != 0.0 || dp.y != 0.0) && isfinite(dp.x) && isfinite(dp.y))) {
+            bad = p;
+            break;
         }
-        __syncthreads();
-        for (int i = j + 1 + t; i < s; i += kThreads) F[i][j] = zmul(F[i][j], rdj);  // column j of L
+        const z2 inv = zrecip(dp);
+        bool rz[NB], cz[NB];
+#pragma unroll
+        for (int a = 0; a < NB; ++a) {
+            rz[a] = tx + 16 * a == p;
+            ri[a] = rz[a] ? -inv : zmul(ri[a], inv);
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            cz[b] = ty + 16 * b == p;
+            rk[b] = cz[b] ? z2{-1.0, 0.0} : rk[b];
+        }
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+            for (int b = 0; b <= a; ++b) {
+                const z2 m = (rz[a] || cz[b]) ? z2{0.0, 0.0} : M[slot(a, b)];
+                M[slot(a, b)] = m - zmul(ri[a], rk[b]);
+            }
+        if (p + 1 < s) publish(p + 1, cb[(p + 1) & 1]);
         __syncthreads();
     }
-    if (bad >= 0) {
-        if (t == 0) atomicMin(status, (unsigned long long)(d.first + bad));
+    if (bad >= 0) {  // every thread took the same branch
+        if (tid == 0) atomicMin(status, (unsigned long long)(d.first + bad));
         return;
     }
-    auto z = [&](int a, int b) { return a >= b ? F[a][b] : F[b][a]; };
-    for (int j = s - 1; j >= 0; --j) {
-        const int r0 = j + 1, nr = s - r0;
-        // Y(i) = -sum_k Z(i,k) L(k,j), rows i in (j, s), four threads per row
-        {
-            const int row = t & 63, part = t >> 6;
-            if (row < nr) {
-                const int i = r0 + row, q = (nr + 3) / 4;
-                const int k0 = r0 + part * q, k1 = min(s, k0 + q);
-                z2 y = {0.0, 0.0};
-                for (int k = k0; k < k1; ++k) y -= zmul(z(i, k), F[k][j]);
-                Yp[part][row] = y;
+    // T = -M from the lower triangle (exactly symmetric)
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int b = 0; b <= a; ++b) {
+            const int i = tx + 16 * a, j = ty + 16 * b;
+            if (i < s && j < s && i >= j) {
+                zstore(Tp, d.woff + i + (int64_t)j * s, -M[slot(a, b)]);
+                zstore(Tp, d.woff + j + (int64_t)i * s, -M[slot(a, b)]);
             }
         }
-        __syncthreads();
-        z2 p = {0.0, 0.0};
-        if (t < nr) {
-            const z2 y = Yp[0][t] + Yp[1][t] + Yp[2][t] + Yp[3][t];
-            Yv[t] = y;
-            p = zmul(F[r0 + t][j], y);
-        }
-        // L(r,j)^T Y by lane exchanges within each wave, then across the four
-        for (int h = 32; h > 0; h >>= 1) {
-            p.x += __shfl_xor(p.x, h);
-            p.y += __shfl_xor(p.y, h);
-        }
-        if (lane == 0) red[wave] = p;
-        __syncthreads();
-        if (t < nr) F[r0 + t][j] = Yv[t];
-        if (t == 0) F[j][j] = zrecip(F[j][j]) - (red[0] + red[1] + red[2] + red[3]);
-        __syncthreads();
-    }
-    for (int k = tj; k < s; k += 16)
-        for (int i = ti; i < s; i += 16) zstore(Tp, d.woff + i + (int64_t)k * s, z(i, k));
 }
 
 // L_hat(C,K) rows [r0, r0+64) = F(C,K) T_K
