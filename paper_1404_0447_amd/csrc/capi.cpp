@@ -265,12 +265,13 @@ selinv_status resolve_opts(const selinv_opts* opts, selinv_opts& o)
     if (o.max_super > 256 || o.exec_cap > 256)
         return fail(SELINV_EUNSUPPORTED, "supernode width cap above 256 is not supported");
     if (o.complex_values) {
-        // the complex kernels hold a whole diagonal block in LDS and add
-        // without atomics: blocks of at most 64 columns, deterministic schedule
+        // the complex kernels hold a whole diagonal block in registers (four
+        // 16-row sub-blocks) and one 64 x 64 output tile per diagonal step, and
+        // add without atomics: blocks of at most 64 columns, deterministic schedule
         o.exec_cap = std::min(o.exec_cap, (int32_t)kZMaxS);
         o.deterministic = 1;
     }
-    // the pivoted diagonal kernel holds a whole block in LDS
+    // the pivoted diagonal kernel holds a whole block in registers
     if (o.pivoting) o.exec_cap = std::min(o.exec_cap, (int32_t)kLdsDiagMax);
     return SELINV_OK;
 }

@@ -1192,13 +1192,12 @@ __global__ __launch_bounds__(kThreads) void k_sdiag64(const Task* __restrict__ t
 }
 
 // ---------------------------------------------------------------------------
-// Factor, diagonal block, s <= kLdsDiagMax: the s x s block lives in LDS.
-// Right-looking LDL^T without pivoting; the same row operations applied to
-// the identity build W = L_BB^{-1}, kept in the (otherwise unused) upper
-// triangle: W(i,k), i > k, at S[k][i].  Then T = W^T D^{-1} W on MFMA (lower
-// 16 x 16 tiles, mirrored).  A pivot that is zero, not finite, or
-// (require_spd) not positive is latched as the smallest failing column.
-// Larger blocks take the same steps on global memory.
+// Factor, diagonal block wider than the register sweeps hold (s > 128, only
+// with exec_cap above 128), on global memory: right-looking LDL^T without
+// pivoting in place of F_BB, then W = L_BB^{-1} column by column (forward
+// substitution, one thread a column) and T = W^T D^{-1} W.  A pivot that is
+// zero, not finite, or (require_spd) not positive is latched as the smallest
+// failing column.
 // ---------------------------------------------------------------------------
 __device__ void ldlt_global(const BlockDesc d, double* __restrict__ Lp, double* __restrict__ Wp,
                             double* __restrict__ Tp, unsigned long long* __restrict__ status, int require_spd)

@@ -9,8 +9,8 @@ constexpr int kTileM = 64;       // rows of an MFMA output tile (gather-GEMM, pa
 constexpr int kSchurTile = 64;   // edge of a Schur-update tile (lower c x c)
 constexpr int kDiagTile = 32;    // edge of a diagonal-block tile (pairs (I,J), I >= J)
 constexpr int kDiagTile64 = 64;  // the same on the per-level path (pipelined MFMA tile)
-constexpr int kLdsDiagMax = 128; // diagonal factorization in LDS up to this width
-constexpr int kZMaxS = 64;       // widest block of the complex path (its diagonal block lives in LDS)
+constexpr int kLdsDiagMax = 128; // diagonal blocks swept in registers up to this width
+constexpr int kZMaxS = 64;       // widest block of the complex path (one 64-wide tile per diagonal step)
 constexpr size_t kLdsDiagBytes = sizeof(double) * kLdsDiagMax * (kLdsDiagMax + 1);
 constexpr bool kUseSweep = true;  // register Gauss-Jordan sweep for s <= kLdsDiagMax
 constexpr size_t kDiagShmem = kUseSweep ? sizeof(double) * 2 * kLdsDiagMax : kLdsDiagBytes;
