@@ -124,3 +124,31 @@ def test_complex_plan_refuses_real_calls():
     with pytest.raises(S.SelinvError) as e:
         q.factor_complex(torch.as_tensor(m.vals.astype(np.complex128), device="cuda"))
     assert e.value.status == S.SELINV_EINVAL
+
+
+def test_complex_zero_pivot_reported_and_plan_recovers():
+    """The first pivot of the elimination order set to exactly 0 + 0i: the
+    complex factorization reports SELINV_EPIVOT with that original column;
+    the same plan then factors a good matrix."""
+    torch = _torch()
+    from paper_1404_0447_amd import selinv as S
+    from paper_1404_0447_amd import workloads as W
+    m = W.laplacian((6, 6), coeff="uniform", lo=0.5, hi=2.0, shift=0.1, seed=3)
+    print("[complex] zero pivot n=36", flush=True)
+    p = S.Plan.from_matrix(m, complex_values=True).bind()
+    cp, ri, pm = p.pattern()
+    vals = m.vals.astype(np.complex128) * (1.0 + 0.5j)
+    first = int(pm[0])
+    diag = np.flatnonzero((m.rowind == first) & (np.repeat(np.arange(m.n), np.diff(m.colptr)) == first))
+    assert len(diag) == 1
+    vals[diag[0]] = 0.0
+    p.factor_complex(torch.as_tensor(vals, device="cuda"))
+    with pytest.raises(S.SelinvError) as e:
+        p.sync_status()
+    assert e.value.status == S.SELINV_EPIVOT
+    assert e.value.bad_col == first
+    good = m.vals.astype(np.complex128) * (1.0 + 0.5j)
+    got = _gpu(p, good)
+    s, o = _oracle(m, good, 128)
+    assert np.array_equal(cp, s.colptrL) and np.array_equal(ri, s.rowindL)
+    assert _err(got, o, s.colptrL, s.rowindL) <= TOL
