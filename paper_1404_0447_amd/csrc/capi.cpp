@@ -90,6 +90,7 @@ void compute_layout(selinv_plan_s* P)
     L.zb = take(adj * sizeof(double) * P->arena);
     L.hb = take(adj * sizeof(double) * P->harena);
     L.tb = take(adj * sizeof(double) * P->warena);
+    L.zsp = take(P->opts.complex_values ? sizeof(double) * kZSlotDoubles * (size_t)P->zsd_slots : 0);
     L.transient = o;
     L.total = L.persist + L.transient;
     P->info.workspace_bytes = (int64_t)L.total;
@@ -130,6 +131,7 @@ DevPtrs dev_ptrs_at(const selinv_plan_s* P, char* w, char* t)
     D.Zb = t ? (double*)(t + L.zb) : nullptr;
     D.Hb = t ? (double*)(t + L.hb) : nullptr;
     D.Tb = t ? (double*)(t + L.tb) : nullptr;
+    D.Zs = t ? (double*)(t + L.zsp) : nullptr;
     D.ck = (double*)(w + L.ck);
     D.ck_off = (const int64_t*)(w + L.ck_off);
     D.t_rs1 = (const Task*)(w + L.t_rs1);
@@ -728,7 +730,7 @@ selinv_status selinv_invert_complex(selinv_plan P, double* d_sel, hipStream_t s)
     for (int l = 0; l < P->exec.depth && !e; l++) {
         const auto& g = P->t_gemm.off;
         const auto& d = P->t_sdiag.off;
-        e = launch_zinvert_level(D, g[l], g[l + 1] - g[l], d[l], d[l + 1] - d[l], s);
+        e = launch_zinvert_level(D, g[l], g[l + 1] - g[l], d[l], P->sdiag_cut[l], d[l + 1], s);
     }
     if (!e) e = launch_zexport(D.Ap, D.exp_off, P->colptrL.back(), d_sel, s);
     if (e) return hip_fail(e, "complex invert launch");

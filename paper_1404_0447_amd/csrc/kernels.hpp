@@ -14,6 +14,7 @@ namespace selinv {
 struct DevPtrs {
     double *Lp, *Ap, *Hp, *Wp, *Tp;
     double *Zb, *Hb, *Tb;  // adjoint arenas
+    double* Zs;            // complex plans: partial products of the split diagonal step
     unsigned long long* status;
     const BlockDesc* blocks;
     const int32_t* crow;
@@ -85,8 +86,11 @@ hipError_t launch_zassemble(const double* vals, const int64_t* off, int64_t n, d
 hipError_t launch_zexport(const double* Ap, const int64_t* off, int64_t n, double* out, hipStream_t s);
 hipError_t launch_zfactor_level(const DevPtrs& D, int64_t diag0, int64_t ndiag, int64_t panel0, int64_t npanel,
                                 const int64_t* schur_cuts, int ncuts, hipStream_t s);
-hipError_t launch_zinvert_level(const DevPtrs& D, int64_t gemm0, int64_t ngemm, int64_t sdiag0, int64_t nsdiag,
-                                hipStream_t s);
+// inversion of one level: gather-GEMM tasks, then the diagonal step's tasks
+// [sdiag0, sdiag_cut) (whole blocks, or pieces of split ones) and the split
+// blocks' summing tasks [sdiag_cut, sdiag1)
+hipError_t launch_zinvert_level(const DevPtrs& D, int64_t gemm0, int64_t ngemm, int64_t sdiag0, int64_t sdiag_cut,
+                                int64_t sdiag1, hipStream_t s);
 
 // Launch sequences and helpers of the C ABI (capi.cpp), shared with the
 // static-scratch entry point.

@@ -115,6 +115,7 @@ struct DeviceLayout {
     size_t persist;                       // bytes of the persistent part
     // byte offsets into the transient part
     size_t ap, zb, hb, tb;  // inverse panels; adjoint arenas (backward)
+    size_t zsp;             // complex plans: partial products of the split diagonal step
     size_t transient;       // bytes of the transient part
     size_t total;           // persistent + transient (one buffer holding both)
 };
@@ -161,6 +162,10 @@ struct selinv_plan_s {
     // (deterministic mode: the second half-products of off-diagonal tiles
     // run after the first; otherwise cut = end)
     std::vector<int64_t> sdiag_cut;
+    // complex plans: scratch slots of the split diagonal step (the most any
+    // level uses; t_sdiag then holds the pieces before sdiag_cut and one
+    // summing task per split block after it)
+    int64_t zsd_slots = 0;
     // column ranges [kb, ke) of blocks whose X or Ainv(B,B) accumulates, in
     // level order; level l owns t_zero[t_zero_off[l] .. t_zero_off[l+1])
     std::vector<selinv::Task> t_zero;

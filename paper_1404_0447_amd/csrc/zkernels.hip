@@ -3,8 +3,9 @@
 // (Section 4.3).  Values are complex (re, im interleaved, 16 bytes each);
 // every transpose is a plain transpose, never a conjugate.  Blocks are at
 // most 64 columns wide; the plan's level schedule is the deterministic one
-// (no split contractions, Schur updates in colour groups), so no kernel
-// here needs atomics.  Products run on FP64 MFMA: a 64 x 64 complex output
+// (Schur updates in colour groups; a diagonal step's long contraction may be
+// cut into pieces, summed afterwards in a fixed order), so no kernel here
+// needs atomics.  Products run on FP64 MFMA: a 64 x 64 complex output
 // tile per work-group, real and imaginary parts as separate accumulators,
 // operands staged through LDS in 16-deep chunks.
 #include <hip/hip_runtime.h>
@@ -477,10 +478,14 @@ __global__ __launch_bounds__(kThreads, 3) void k_zgemm(const Task* __restrict__ 
     });
 }
 
-// Ainv(K,K) = T - (P + P^T) / 2 with P = L_hat^T Ainv(C,K) (lower triangle)
+// Ainv(K,K) = T - (P + P^T) / 2 with P = L_hat^T Ainv(C,K) (lower triangle),
+// the contraction over rows [kb, ke) of C.  A piece of a split block (flags
+// bit 5) stores its P to scratch slot `pad` (row-major, kZMaxS x kZMaxS
+// complex) instead; k_zsdiag_sum completes the block.
+static_assert(kZT == kZMaxS, "one output tile holds a whole diagonal block");
 __global__ __launch_bounds__(kThreads) void k_zsdiag(const Task* __restrict__ tasks, const BlockDesc* __restrict__ blk,
                                                      double* __restrict__ Ap, const double* __restrict__ Hp,
-                                                     const double* __restrict__ Tp)
+                                                     const double* __restrict__ Tp, double* __restrict__ Zs)
 {
     // the product's operand planes, then P for the transpose (the tile loop
     // ends with a barrier, so P may reuse the space)
@@ -493,10 +498,22 @@ __global__ __launch_bounds__(kThreads) void k_zsdiag(const Task* __restrict__ ta
     const BlockDesc d = blk[tk.b];
     const int s = d.s, c = d.c;
     const int64_t ld = (int64_t)s + c;
-    auto la = [&](int r, int i) { return (r < c && i < s) ? zload(Hp, d.hoff + r + (int64_t)i * c) : z2{0, 0}; };
-    auto lb = [&](int r, int j) { return (r < c && j < s) ? zload(Ap, d.poff + s + r + (int64_t)j * ld) : z2{0, 0}; };
+    const int kb = tk.kb, ke = tk.ke;
+    auto la = [&](int r, int i) {
+        r += kb;
+        return (r < ke && i < s) ? zload(Hp, d.hoff + r + (int64_t)i * c) : z2{0, 0};
+    };
+    auto lb = [&](int r, int j) {
+        r += kb;
+        return (r < ke && j < s) ? zload(Ap, d.poff + s + r + (int64_t)j * ld) : z2{0, 0};
+    };
     ZAcc acc = {};
-    ztile_mfma(U.L, c, acc, la, lb);
+    ztile_mfma(U.L, ke - kb, acc, la, lb);
+    if (tk.flags & 32) {
+        double* z = Zs + (int64_t)tk.pad * kZSlotDoubles;
+        zvisit(acc, [&](int i, int j, z2 v) { zstore(z, (int64_t)i * kZT + j, v); });
+        return;
+    }
     zvisit(acc, [&](int i, int j, z2 v) { P[i][j] = v; });
     __syncthreads();
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
@@ -510,6 +527,32 @@ __global__ __launch_bounds__(kThreads) void k_zsdiag(const Task* __restrict__ ta
                 zstore(Ap, d.poff + i + (int64_t)j * ld, zload(Tp, d.woff + i + (int64_t)j * s) - p);
             }
         }
+}
+
+// A split block's diagonal step: P = the sum of its pieces' partial
+// products (slots kb .. kb + bn - 1, in that order), then Ainv(K,K) = T -
+// (P + P^T) / 2 on the lower triangle.
+__global__ __launch_bounds__(kThreads) void k_zsdiag_sum(const Task* __restrict__ tasks,
+                                                         const BlockDesc* __restrict__ blk, double* __restrict__ Ap,
+                                                         const double* __restrict__ Tp, const double* __restrict__ Zs)
+{
+    __shared__ z2 P[kZT][kZT + 1];
+    const Task tk = tasks[blockIdx.x];
+    const BlockDesc d = blk[tk.b];
+    const int s = d.s;
+    const int64_t ld = (int64_t)s + d.c;
+    const double* z0 = Zs + (int64_t)tk.kb * kZSlotDoubles;
+    for (int e = threadIdx.x; e < kZT * kZT; e += kThreads) {
+        z2 a = {0, 0};
+        for (int q = 0; q < tk.bn; q++) a += zload(z0 + (int64_t)q * kZSlotDoubles, e);
+        P[e / kZT][e % kZT] = a;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < s * s; e += kThreads) {
+        const int i = e % s, j = e / s;
+        if (i >= j)
+            zstore(Ap, d.poff + i + (int64_t)j * ld, zload(Tp, d.woff + i + (int64_t)j * s) - 0.5 * (P[i][j] + P[j][i]));
+    }
 }
 
 // assemble: panel entry off[q] (a complex element) := value q; export: out
@@ -565,15 +608,18 @@ hipError_t launch_zfactor_level(const DevPtrs& D, int64_t diag0, int64_t ndiag, 
     return hipGetLastError();
 }
 
-hipError_t launch_zinvert_level(const DevPtrs& D, int64_t gemm0, int64_t ngemm, int64_t sdiag0, int64_t nsdiag,
-                                hipStream_t s)
+hipError_t launch_zinvert_level(const DevPtrs& D, int64_t gemm0, int64_t ngemm, int64_t sdiag0, int64_t sdiag_cut,
+                                int64_t sdiag1, hipStream_t s)
 {
     if (ngemm > 0)
         hipLaunchKernelGGL(k_zgemm, dim3((unsigned)ngemm), dim3(kThreads), 0, s, D.t_gemm + gemm0, D.blocks, D.Ap,
                            (const double*)D.Hp, D.cr2, D.rel);
-    if (nsdiag > 0)
-        hipLaunchKernelGGL(k_zsdiag, dim3((unsigned)nsdiag), dim3(kThreads), 0, s, D.t_sdiag + sdiag0, D.blocks,
-                           D.Ap, (const double*)D.Hp, (const double*)D.Tp);
+    if (sdiag_cut > sdiag0)
+        hipLaunchKernelGGL(k_zsdiag, dim3((unsigned)(sdiag_cut - sdiag0)), dim3(kThreads), 0, s, D.t_sdiag + sdiag0,
+                           D.blocks, D.Ap, (const double*)D.Hp, (const double*)D.Tp, D.Zs);
+    if (sdiag1 > sdiag_cut)
+        hipLaunchKernelGGL(k_zsdiag_sum, dim3((unsigned)(sdiag1 - sdiag_cut)), dim3(kThreads), 0, s,
+                           D.t_sdiag + sdiag_cut, D.blocks, D.Ap, (const double*)D.Tp, (const double*)D.Zs);
     return hipGetLastError();
 }
 

@@ -152,3 +152,17 @@ def test_complex_zero_pivot_reported_and_plan_recovers():
     s, o = _oracle(m, good, 128)
     assert np.array_equal(cp, s.colptrL) and np.array_equal(ri, s.rowindL)
     assert _err(got, o, s.colptrL, s.rowindL) <= TOL
+
+
+def test_complex_path_is_bitwise_repeatable():
+    """The complex schedule adds in a fixed order everywhere (Schur colour
+    groups, split diagonal steps summed piece by piece): two runs on the same
+    values agree bit for bit."""
+    from paper_1404_0447_amd import selinv as S
+    from paper_1404_0447_amd import workloads as W
+    H, Sm = W.hamiltonian_overlap(side=5, dofs=8, seed=6)
+    vals = W.pencil_values(H, Sm, W.poles(8, 0.0, 30.0)[3])
+    p = S.Plan.from_matrix(H, max_super=128, complex_values=True).bind()
+    a = _gpu(p, vals)
+    b = _gpu(p, vals)
+    assert np.array_equal(a, b)
