@@ -167,8 +167,10 @@ selinv_status selinv_workspace_size(selinv_plan p, size_t* bytes);
 /* The two parts of the workspace.  Persistent: the factor, L_hat, T_K, the
  * index maps and task lists, and the checkpoint store; it must stay bound
  * from selinv_factor to selinv_backward.  Transient: the inverse panels and
- * the adjoint arenas, needed only inside selinv_invert, selinv_backward and
- * selinv_run.  Either pointer may be NULL. */
+ * the adjoint arenas (complex plans: the inverse panels and the partial
+ * products of split diagonal steps), needed only inside selinv_invert,
+ * selinv_invert_complex, selinv_backward and selinv_run.  Either pointer
+ * may be NULL. */
 selinv_status selinv_workspace_sizes(selinv_plan p, size_t* persistent, size_t* transient);
 
 /* Bind caller-owned device memory (256-byte aligned) and upload the index
