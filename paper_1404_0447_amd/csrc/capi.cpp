@@ -730,7 +730,8 @@ selinv_status selinv_invert_complex(selinv_plan P, double* d_sel, hipStream_t s)
     for (int l = 0; l < P->exec.depth && !e; l++) {
         const auto& g = P->t_gemm.off;
         const auto& d = P->t_sdiag.off;
-        e = launch_zinvert_level(D, g[l], g[l + 1] - g[l], d[l], P->sdiag_cut[l], d[l + 1], s);
+        const int64_t gc[4] = {g[l], P->zgemm_mid[l], P->zgemm_cut[l], g[l + 1]};
+        e = launch_zinvert_level(D, gc, d[l], P->sdiag_cut[l], d[l + 1], s);
     }
     if (!e) e = launch_zexport(D.Ap, D.exp_off, P->colptrL.back(), d_sel, s);
     if (e) return hip_fail(e, "complex invert launch");

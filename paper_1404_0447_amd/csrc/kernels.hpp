@@ -86,10 +86,11 @@ hipError_t launch_zassemble(const double* vals, const int64_t* off, int64_t n, d
 hipError_t launch_zexport(const double* Ap, const int64_t* off, int64_t n, double* out, hipStream_t s);
 hipError_t launch_zfactor_level(const DevPtrs& D, int64_t diag0, int64_t ndiag, int64_t panel0, int64_t npanel,
                                 const int64_t* schur_cuts, int ncuts, hipStream_t s);
-// inversion of one level: gather-GEMM tasks, then the diagonal step's tasks
-// [sdiag0, sdiag_cut) (whole blocks, or pieces of split ones) and the split
-// blocks' summing tasks [sdiag_cut, sdiag1)
-hipError_t launch_zinvert_level(const DevPtrs& D, int64_t gemm0, int64_t ngemm, int64_t sdiag0, int64_t sdiag_cut,
+// inversion of one level: the gather-GEMM's whole tiles [gemm[0], gemm[1]),
+// pieces of split tiles [gemm[1], gemm[2]) and their summing tasks
+// [gemm[2], gemm[3]); then the diagonal step's tasks [sdiag0, sdiag_cut)
+// (whole blocks and pieces) and summing tasks [sdiag_cut, sdiag1)
+hipError_t launch_zinvert_level(const DevPtrs& D, const int64_t gemm[4], int64_t sdiag0, int64_t sdiag_cut,
                                 int64_t sdiag1, hipStream_t s);
 
 // Launch sequences and helpers of the C ABI (capi.cpp), shared with the

@@ -162,10 +162,12 @@ struct selinv_plan_s {
     // (deterministic mode: the second half-products of off-diagonal tiles
     // run after the first; otherwise cut = end)
     std::vector<int64_t> sdiag_cut;
-    // complex plans: scratch slots of the split diagonal step (the most any
-    // level uses; t_sdiag then holds the pieces before sdiag_cut and one
-    // summing task per split block after it)
+    // complex plans: scratch slots of the split gather-GEMM and diagonal
+    // step (the most any level's launch uses; per level, t_gemm holds whole
+    // tiles, pieces from zgemm_mid and one summing task per split tile from
+    // zgemm_cut; t_sdiag likewise, its summing tasks from sdiag_cut)
     int64_t zsd_slots = 0;
+    std::vector<int64_t> zgemm_mid, zgemm_cut;
     // column ranges [kb, ke) of blocks whose X or Ainv(B,B) accumulates, in
     // level order; level l owns t_zero[t_zero_off[l] .. t_zero_off[l+1])
     std::vector<selinv::Task> t_zero;

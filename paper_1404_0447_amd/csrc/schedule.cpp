@@ -234,43 +234,48 @@ static void push_sb_groups(const std::vector<int>& small, int op, std::vector<Ta
     }
 }
 
-// Complex plans (deterministic schedule, one diagonal-step task per block):
-// a level with fewer than kZSplitFill / 2 blocks cuts each block's
-// contraction over C into pieces of at least kZSplitRows rows (boundaries
-// on 16-row chunks), about kZSplitFill pieces in all.  A piece (flags bit
-// 5) writes its partial product L_hat(C_piece, K)^T Ainv(C_piece, K) to
-// scratch slot `pad`; after the pieces, one task per split block (bn =
-// pieces, kb = first slot) sums them in piece order and forms Ainv(K,K).
-// Unsplit blocks keep their task, which does both.  Every sum has a fixed
-// order, so the results stay bitwise repeatable.  Returns the slots used.
-static int64_t zsdiag_split(selinv_plan_s* P, int l)
+// Complex plans (deterministic schedule: every gather-GEMM tile and
+// diagonal-step task contracts over all of C): a level with fewer than
+// kZSplitFill / 2 tasks of one kind cuts each task's contraction into
+// pieces of at least kZSplitRows rows (boundaries on 16-row chunks), about
+// kZSplitFill pieces in all.  A piece (flags bit 5) writes its partial
+// product over its rows of C to scratch slot `pad`; after the pieces, one
+// task per split task (same block and tile origin, bn = pieces, kb = first
+// slot, flags bit 6) sums them in piece order and writes the result.
+// Unsplit tasks keep their form and do both.  Every sum has a fixed order,
+// so the results stay bitwise repeatable.  The level's list becomes whole
+// tasks, then pieces (from `mid`), then summing tasks (from `cut`); returns
+// the slots used.
+static int64_t zsplit_level(const selinv_plan_s* P, LevelTasks& lt, int l, int64_t& mid, int64_t& cut)
 {
-    std::vector<Task>& t = P->t_sdiag.tasks;
-    const int64_t t0 = P->t_sdiag.off[l], n = (int64_t)t.size() - t0;
-    P->sdiag_cut[l] = (int64_t)t.size();
+    std::vector<Task>& t = lt.tasks;
+    const int64_t t0 = lt.off[l], n = (int64_t)t.size() - t0;
+    mid = cut = (int64_t)t.size();
     if (n <= 0 || n >= kZSplitFill / 2) return 0;
     const int want = (int)((kZSplitFill + n - 1) / n);
-    std::vector<Task> pieces, sums;
+    std::vector<Task> whole, pieces, sums;
     int64_t slot = 0;
     for (int64_t q = t0; q < (int64_t)t.size(); q++) {
         const Task k = t[q];
         const int c = P->blocks[k.b].c;
         const int np = std::max(1, std::min(want, c / kZSplitRows));
         if (np == 1) {
-            pieces.push_back(k);
+            whole.push_back(k);
             continue;
         }
         for (int i = 0; i < np; i++) {
             const int kb = (int)((int64_t)c * i / np) & ~15;
             const int ke = i + 1 == np ? c : (int)((int64_t)c * (i + 1) / np) & ~15;
-            pieces.push_back({k.b, 0, 0, 0, kb, ke, 32, (int32_t)(slot + i)});
+            pieces.push_back({k.b, k.i0, k.j0, k.bn, kb, ke, 32, (int32_t)(slot + i)});
         }
-        sums.push_back({k.b, 0, 0, np, (int32_t)slot, 0, 64, 0});
+        sums.push_back({k.b, k.i0, k.j0, np, (int32_t)slot, 0, 64, 0});
         slot += np;
     }
     t.resize(t0);
+    t.insert(t.end(), whole.begin(), whole.end());
+    mid = (int64_t)t.size();
     t.insert(t.end(), pieces.begin(), pieces.end());
-    P->sdiag_cut[l] = (int64_t)t.size();
+    cut = (int64_t)t.size();
     t.insert(t.end(), sums.begin(), sums.end());
     return slot;
 }
@@ -294,6 +299,8 @@ void build_schedule(selinv_plan_s* P)
     P->sdiag_cut.assign(D, 0);
     P->panel_deep.assign(D, 0);
     P->zsd_slots = 0;
+    P->zgemm_cut.assign(D, 0);
+    P->zgemm_mid.assign(D, 0);
     // deterministic mode: no small-block kernels (their Schur updates use
     // atomics), no split contractions, no whole-contraction kernel variants
     const bool det = P->opts.deterministic != 0;
@@ -444,7 +451,13 @@ void build_schedule(selinv_plan_s* P)
             P->rs3_cuts[l] = {P->t_rs3.off[l], (int64_t)P->t_rs3.tasks.size()};
             P->sdiag_cut[l] = (int64_t)P->t_sdiag.tasks.size();
         }
-        if (P->opts.complex_values) P->zsd_slots = std::max(P->zsd_slots, zsdiag_split(P, l));
+        if (P->opts.complex_values) {
+            // the two launches run one after the other: they share the slots
+            int64_t mid = 0;
+            const int64_t a = zsplit_level(P, P->t_gemm, l, P->zgemm_mid[l], P->zgemm_cut[l]);
+            const int64_t b = zsplit_level(P, P->t_sdiag, l, mid, P->sdiag_cut[l]);
+            P->zsd_slots = std::max(P->zsd_slots, std::max(a, b));
+        }
         P->t_zero_off[l + 1] = (int64_t)P->t_zero.size();
         // diagonal blocks of the tiled path by width class (one launch each)
         const int64_t cls[] = {32, 64, 1 << 30};

@@ -11,10 +11,11 @@ constexpr int kDiagTile = 32;    // edge of a diagonal-block tile (pairs (I,J), 
 constexpr int kDiagTile64 = 64;  // the same on the per-level path (pipelined MFMA tile)
 constexpr int kLdsDiagMax = 128; // diagonal blocks swept in registers up to this width
 constexpr int kZMaxS = 64;       // widest block of the complex path (one 64-wide tile per diagonal step)
-// Complex diagonal step: a level with fewer than kZSplitFill / 2 blocks cuts
-// each block's contraction over C into pieces of at least kZSplitRows rows,
-// about kZSplitFill work-groups in all; a piece writes its 64 x 64 complex
-// partial product to a scratch slot of kZSlotDoubles doubles.
+// Complex gather-GEMM and diagonal step: a level with fewer than
+// kZSplitFill / 2 tasks cuts each task's contraction over C into pieces of
+// at least kZSplitRows rows, about kZSplitFill work-groups in all; a piece
+// writes its 64 x 64 complex partial product to a scratch slot of
+// kZSlotDoubles doubles.
 constexpr int kZSplitFill = 512;
 constexpr int kZSplitRows = 64;
 constexpr size_t kZSlotDoubles = 2 * (size_t)kZMaxS * kZMaxS;

@@ -358,10 +358,17 @@ __global__ __launch_bounds__(kThreads) void k_zschur(const Task* __restrict__ ta
 // Loads are unconditional (a padding element reads an in-bounds stand-in and
 // is zeroed by its mask at the LDS store), so no wait sits behind a branch.
 // Three work-groups per CU (registers capped at 168, a few spilled) measured
-// faster than two: 39.1 vs 39.8 ms for the 32-pole batch.
-__global__ __launch_bounds__(kThreads, 3) void k_zgemm(const Task* __restrict__ tasks, const BlockDesc* __restrict__ blk,
+// faster than two: 39.1 vs 39.8 ms for the 32-pole batch.  kPiece (kernel
+// k_zgemm_piece): the contraction runs over rows [kb, ke) of C (kb on a
+// 16-row chunk boundary) and the tile's G L_hat goes to scratch slot `pad`
+// (row-major 64 x 64 complex), for k_zgemm_sum to complete.  The two are
+// separate kernels: with the piece's extra argument and range the whole-tile
+// kernel spilled 13 registers instead of 3 and ran the batch 5 % slower.
+template <bool kPiece>
+__device__ __forceinline__ void zgemm_body(const Task* __restrict__ tasks, const BlockDesc* __restrict__ blk,
                                                     double* __restrict__ Ap, const double* __restrict__ Hp,
-                                                    const int64_t* __restrict__ cr2, const int32_t* __restrict__ rel)
+                                                    const int64_t* __restrict__ cr2, const int32_t* __restrict__ rel,
+                                                    double* __restrict__ Zs)
 {
     typedef int64_t i64v2 __attribute__((ext_vector_type(2)));
     const Task tk = tasks[blockIdx.x];
@@ -371,7 +378,8 @@ __global__ __launch_bounds__(kThreads, 3) void k_zgemm(const Task* __restrict__ 
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int wm0 = (wave & 1) * 32, wn0 = (wave >> 1) * 32;
     constexpr int NQ = (kZK * kZT) / kThreads;  // elements of each operand per thread and chunk
-    const int nch = (c + kZK - 1) / kZK;
+    // kb is a multiple of kZK: the chunks from ch0 on start at row kb
+    const int ke = kPiece ? tk.ke : c, ch0 = kPiece ? tk.kb / kZK : 0, nch = (ke + kZK - 1) / kZK;
     const double* Lh = Hp + 2 * d.hoff;
     auto along_of = [&](int ch) { return ch * kZK >= r0 + kZT; };
     // stage M: (cbase, rbase) of p and q (-1: padding); stage R: cbase and
@@ -389,7 +397,7 @@ __global__ __launch_bounds__(kThreads, 3) void k_zgemm(const Task* __restrict__ 
         for (int q = 0; q < NQ; ++q) {
             const int e = t + q * kThreads;
             const int k = ch * kZK + (al ? (e & 15) : (e >> 6)), i = r0 + (al ? (e >> 4) : (e & 63));
-            const bool ok = ch < nch && k < c && i < c;
+            const bool ok = ch < nch && k < ke && i < c;
             const int64_t p = d.coff + (ok ? (i >= k ? k : i) : 0);
             const i64v2 cr = *reinterpret_cast<const i64v2*>(cr2 + 2 * p);
             m_cb[q] = cr.x;
@@ -414,7 +422,7 @@ __global__ __launch_bounds__(kThreads, 3) void k_zgemm(const Task* __restrict__ 
             // L_hat(k, j) along k (contiguous), a stand-in past the ends
             const int e = t + q * kThreads;
             const int k = ch * kZK + (e & 15), j = e >> 4;
-            v_bok[q] = k < c && j < s;
+            v_bok[q] = k < ke && j < s;
             v_b[q] = zload(Lh, v_bok[q] ? k + (int64_t)j * c : 0);
         }
     };
@@ -433,14 +441,15 @@ __global__ __launch_bounds__(kThreads, 3) void k_zgemm(const Task* __restrict__ 
         }
     };
     ZAcc acc = {};
-    stage_m(0);
+    stage_m(ch0);
     stage_r();
-    stage_v(0);
-    stage_m(1);
+    stage_v(ch0);
+    stage_m(ch0 + 1);
     stage_r();
-    stage_m(2);
-    // registers now: values of chunk 0, rel entries of chunk 1, pairs of chunk 2
-    for (int ch = 0; ch < nch; ++ch) {
+    stage_m(ch0 + 2);
+    // registers now: values of the first chunk, rel entries of the second,
+    // pairs of the third
+    for (int ch = ch0; ch < nch; ++ch) {
         stage_store();
         __syncthreads();
         stage_v(ch + 1);
@@ -472,10 +481,53 @@ __global__ __launch_bounds__(kThreads, 3) void k_zgemm(const Task* __restrict__ 
     __builtin_amdgcn_sched_barrier(0);
     asm volatile("s_nop 15\n\ts_nop 15\n\ts_nop 15\n\ts_nop 15" ::: "memory");
     __builtin_amdgcn_sched_barrier(0);
-    zvisit(acc, [&](int ti, int j, z2 v) {
-        const int i = r0 + ti;
-        if (i < c && j < s) zstore(Ap, d.poff + s + i + (int64_t)j * ld, -v);
-    });
+    if constexpr (kPiece) {
+        double* z = Zs + (int64_t)tk.pad * kZSlotDoubles;
+        zvisit(acc, [&](int ti, int j, z2 v) { zstore(z, (int64_t)ti * kZT + j, v); });
+    } else {
+        zvisit(acc, [&](int ti, int j, z2 v) {
+            const int i = r0 + ti;
+            if (i < c && j < s) zstore(Ap, d.poff + s + i + (int64_t)j * ld, -v);
+        });
+    }
+}
+
+__global__ __launch_bounds__(kThreads, 3) void k_zgemm(const Task* __restrict__ tasks, const BlockDesc* __restrict__ blk,
+                                                    double* __restrict__ Ap, const double* __restrict__ Hp,
+                                                    const int64_t* __restrict__ cr2, const int32_t* __restrict__ rel)
+{
+    zgemm_body<false>(tasks, blk, Ap, Hp, cr2, rel, nullptr);
+}
+__global__ __launch_bounds__(kThreads, 3) void k_zgemm_piece(const Task* __restrict__ tasks, const BlockDesc* __restrict__ blk,
+                                                    double* __restrict__ Ap, const double* __restrict__ Hp,
+                                                    const int64_t* __restrict__ cr2, const int32_t* __restrict__ rel,
+                                                    double* __restrict__ Zs)
+{
+    zgemm_body<true>(tasks, blk, Ap, Hp, cr2, rel, Zs);
+}
+
+// A split gather-GEMM tile: the sum of its pieces' G L_hat (slots kb .. kb +
+// bn - 1, in that order), stored negated as Ainv(C,K) rows [r0, r0+64).
+__global__ __launch_bounds__(kThreads) void k_zgemm_sum(const Task* __restrict__ tasks,
+                                                        const BlockDesc* __restrict__ blk, double* __restrict__ Ap,
+                                                        const double* __restrict__ Zs)
+{
+    __shared__ z2 X[kZT][kZT + 1];
+    const Task tk = tasks[blockIdx.x];
+    const BlockDesc d = blk[tk.b];
+    const int s = d.s, c = d.c, r0 = tk.i0;
+    const int64_t ld = (int64_t)s + c;
+    const double* z0 = Zs + (int64_t)tk.kb * kZSlotDoubles;
+    for (int e = threadIdx.x; e < kZT * kZT; e += kThreads) {
+        z2 a = {0, 0};
+        for (int q = 0; q < tk.bn; q++) a += zload(z0 + (int64_t)q * kZSlotDoubles, e);
+        X[e / kZT][e % kZT] = a;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kZT * s; e += kThreads) {
+        const int ti = e % kZT, j = e / kZT, i = r0 + ti;
+        if (i < c) zstore(Ap, d.poff + s + i + (int64_t)j * ld, -X[ti][j]);
+    }
 }
 
 // Ainv(K,K) = T - (P + P^T) / 2 with P = L_hat^T Ainv(C,K) (lower triangle),
@@ -608,12 +660,18 @@ hipError_t launch_zfactor_level(const DevPtrs& D, int64_t diag0, int64_t ndiag, 
     return hipGetLastError();
 }
 
-hipError_t launch_zinvert_level(const DevPtrs& D, int64_t gemm0, int64_t ngemm, int64_t sdiag0, int64_t sdiag_cut,
+hipError_t launch_zinvert_level(const DevPtrs& D, const int64_t gemm[4], int64_t sdiag0, int64_t sdiag_cut,
                                 int64_t sdiag1, hipStream_t s)
 {
-    if (ngemm > 0)
-        hipLaunchKernelGGL(k_zgemm, dim3((unsigned)ngemm), dim3(kThreads), 0, s, D.t_gemm + gemm0, D.blocks, D.Ap,
-                           (const double*)D.Hp, D.cr2, D.rel);
+    if (gemm[1] > gemm[0])
+        hipLaunchKernelGGL(k_zgemm, dim3((unsigned)(gemm[1] - gemm[0])), dim3(kThreads), 0, s,
+                           D.t_gemm + gemm[0], D.blocks, D.Ap, (const double*)D.Hp, D.cr2, D.rel);
+    if (gemm[2] > gemm[1])
+        hipLaunchKernelGGL(k_zgemm_piece, dim3((unsigned)(gemm[2] - gemm[1])), dim3(kThreads), 0, s,
+                           D.t_gemm + gemm[1], D.blocks, D.Ap, (const double*)D.Hp, D.cr2, D.rel, D.Zs);
+    if (gemm[3] > gemm[2])
+        hipLaunchKernelGGL(k_zgemm_sum, dim3((unsigned)(gemm[3] - gemm[2])), dim3(kThreads), 0, s,
+                           D.t_gemm + gemm[2], D.blocks, D.Ap, (const double*)D.Zs);
     if (sdiag_cut > sdiag0)
         hipLaunchKernelGGL(k_zsdiag, dim3((unsigned)(sdiag_cut - sdiag0)), dim3(kThreads), 0, s, D.t_sdiag + sdiag0,
                            D.blocks, D.Ap, (const double*)D.Hp, (const double*)D.Tp, D.Zs);
