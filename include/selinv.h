@@ -110,7 +110,9 @@ typedef struct {
                              Hermitian); use selinv_factor_complex and
                              selinv_invert_complex.  Execution blocks are
                              then at most 64 columns wide and the schedule is
-                             the deterministic one.                         */
+                             atomic-free and bitwise repeatable (long
+                             contractions of sparse levels run as pieces
+                             summed in a fixed order).                      */
     int32_t pivoting;     /* 1: symmetric indefinite A: each diagonal block
                              F_KK is inverted with 1x1 or 2x2 pivots chosen
                              inside the block by the Bunch-Kaufman rule
