@@ -132,10 +132,16 @@ __device__ __forceinline__ void zvisit(const ZAcc& acc, F f)
 __device__ __forceinline__ z2 zload(const double* p, int64_t e) { return *reinterpret_cast<const z2*>(p + 2 * e); }
 __device__ __forceinline__ void zstore(double* p, int64_t e, z2 v) { *reinterpret_cast<z2*>(p + 2 * e) = v; }
 
+// 1 / b: the hardware reciprocal of |b|^2 refined by two Newton steps
+// (each doubles the correct bits of the ~23-bit estimate), then b's
+// conjugate scaled by it
 __device__ __forceinline__ z2 zrecip(z2 b)
 {
     const double den = b.x * b.x + b.y * b.y;
-    return z2{b.x / den, -b.y / den};
+    double r = __builtin_amdgcn_rcp(den);
+    r = fma(r, fma(-den, r, 1.0), r);
+    r = fma(r, fma(-den, r, 1.0), r);
+    return z2{b.x * r, -b.y * r};
 }
 
 // ---------------------------------------------------------------------------
@@ -147,8 +153,11 @@ __device__ __forceinline__ z2 zrecip(z2 b)
 // a >= b; a pivot's column goes through LDS (two alternating slots, one
 // barrier per pivot).  Row and column p are cleared by lane masks and the
 // pivot's own entries of the update vectors set to -1/d (rows) and -1
-// (columns), so one rank-1 pass also writes the new row and column p.  s <=
-// 64, one work-group per block; a zero or non-finite pivot latches its column.
+// (columns), so one rank-1 pass also writes the new row and column p.  Per
+// pivot the slots holding the next pivot's column are updated first and the
+// column published; the rest follow the barrier, while that column's LDS
+// reads are in flight.  s <= 64, one work-group per block; a zero or
+// non-finite pivot latches its column.
 // ---------------------------------------------------------------------------
 template <int N, class Fn>
 __device__ __forceinline__ void zfor(Fn&& f)
@@ -208,40 +217,66 @@ __global__ __launch_bounds__(kThreads) void k_zdiag(const Task* __restrict__ tas
     };
     if (s > 0) publish(0, cb[0]);
     __syncthreads();
-    int bad = -1;
-    for (int p = 0; p < s; ++p) {
+    // column p as read from LDS: rows tx + 16a, rows ty + 16b, the pivot
+    z2 ri[NB], rk[NB], dp;
+    auto read_col = [&](int p) {
         const z2* col = cb[p & 1];
-        z2 ri[NB], rk[NB];
 #pragma unroll
         for (int a = 0; a < NB; ++a) ri[a] = col[tx + 16 * a];
 #pragma unroll
         for (int b = 0; b < NB; ++b) rk[b] = col[ty + 16 * b];
-        const z2 dp = zuniform(col[p]);
+        dp = zuniform(col[p]);
+    };
+    if (s > 0) read_col(0);
+    int bad = -1;
+    for (int p = 0; p < s; ++p) {
         if (!((dp.x != 0.0 || dp.y != 0.0) && isfinite(dp.x) && isfinite(dp.y))) {
             bad = p;
             break;
         }
         const z2 inv = zrecip(dp);
         bool rz[NB], cz[NB];
+        z2 si[NB], sk[NB];
 #pragma unroll
         for (int a = 0; a < NB; ++a) {
             rz[a] = tx + 16 * a == p;
-            ri[a] = rz[a] ? -inv : zmul(ri[a], inv);
+            si[a] = rz[a] ? -inv : zmul(ri[a], inv);
         }
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             cz[b] = ty + 16 * b == p;
-            rk[b] = cz[b] ? z2{-1.0, 0.0} : rk[b];
+            sk[b] = cz[b] ? z2{-1.0, 0.0} : rk[b];
         }
+        auto upd = [&](int a, int b) {
+            const z2 m = (rz[a] || cz[b]) ? z2{0.0, 0.0} : M[slot(a, b)];
+            M[slot(a, b)] = m - zmul(si[a], sk[b]);
+        };
+        // the slots of the next pivot's sub-block column and row first, so
+        // that its column is published (and read) while the rest update
+        const int q = p + 1, qb = q >> 4;
+        if (qb >= NB) {  // the last pivot of a full block
 #pragma unroll
-        for (int a = 0; a < NB; ++a)
+            for (int a = 0; a < NB; ++a)
 #pragma unroll
-            for (int b = 0; b <= a; ++b) {
-                const z2 m = (rz[a] || cz[b]) ? z2{0.0, 0.0} : M[slot(a, b)];
-                M[slot(a, b)] = m - zmul(ri[a], rk[b]);
+                for (int b = 0; b <= a; ++b) upd(a, b);
+        }
+        zfor<NB>([&](auto cc) {
+            constexpr int b0 = decltype(cc)::value;
+            if (qb == b0) {
+#pragma unroll
+                for (int a = b0; a < NB; ++a) upd(a, b0);
+#pragma unroll
+                for (int b = 0; b < b0; ++b) upd(b0, b);
+                if (q < s) publish(q, cb[q & 1]);
+                __syncthreads();
+                if (q < s) read_col(q);
+#pragma unroll
+                for (int a = 0; a < NB; ++a)
+#pragma unroll
+                    for (int b = 0; b <= a; ++b)
+                        if (a != b0 && b != b0) upd(a, b);
             }
-        if (p + 1 < s) publish(p + 1, cb[(p + 1) & 1]);
-        __syncthreads();
+        });
     }
     if (bad >= 0) {  // every thread took the same branch
         if (tid == 0) atomicMin(status, (unsigned long long)(d.first + bad));
