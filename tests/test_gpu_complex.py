@@ -166,3 +166,33 @@ def test_complex_path_is_bitwise_repeatable():
     a = _gpu(p, vals)
     b = _gpu(p, vals)
     assert np.array_equal(a, b)
+
+
+def test_pole_batch_full_size_against_oracle():
+    """The pole workload the benchmark times, at full size: 32 poles of
+    n = 8000 in one batch, in the benchmark's launch configuration.  Poles 0,
+    15 and 31 of the batch, and pole 0 on a single-pole plan (every level of
+    which cuts its gather-GEMM and diagonal-step contractions into pieces),
+    against the oracle's complex tier to the C8 bar."""
+    _torch()
+    from paper_1404_0447_amd import selinv as S
+    from paper_1404_0447_amd import workloads as W
+    H, Sm = W.hamiltonian_overlap(side=10, dofs=8, seed=6)
+    z = W.poles(32, 0.0, 40.0)
+    print(f"[complex] pole batch n={H.n} x {len(z)}", flush=True)
+    p = S.Plan.poles(H, len(z)).bind()
+    got = _gpu(p, np.concatenate([W.pencil_values(H, Sm, zk) for zk in z]))
+    offs = [int(x) for x in p.nnzL_off]
+    del p
+    one = S.Plan.from_matrix(H, complex_values=True).bind()
+    got1 = _gpu(one, W.pencil_values(H, Sm, z[0]))
+    cp, ri, _ = one.pattern()
+    for k in (0, 15, 31):
+        print(f"[complex] oracle pole {k}", flush=True)
+        s, ref = _oracle(H, W.pencil_values(H, Sm, z[k]), 128)
+        assert np.array_equal(cp, s.colptrL) and np.array_equal(ri, s.rowindL)
+        e = _err(got[offs[k]:offs[k + 1]], ref, cp, ri)
+        assert e <= TOL, f"pole {k}: error {e:.3e}"
+        if k == 0:
+            e1 = _err(got1, ref, cp, ri)
+            assert e1 <= TOL, f"single-pole plan: error {e1:.3e}"
