@@ -194,3 +194,49 @@ def test_dense_indefinite_block_matches_library_inverse(s, zero_diag):
     osel, st, _ = o.factor_selinv_pivoted(m.vals)
     assert st == 0
     assert np.max(np.abs(sel - osel)) <= 1e-10 * scale
+
+
+def test_pivoted_full_size_against_oracle_and_sparse_lu():
+    """The indefinite workload the benchmark times, at full size (saddle-point
+    blocks on a jittered 16^3-atom lattice x 8, n = 32768, cap 128).  This
+    matrix has a 1-norm condition number of about 4.4e6, and with pivots
+    restricted to the diagonal blocks the oracle itself differs from an
+    independent sparse LU solve by up to about 1.5e-8 of the largest entry,
+    so the 1e-10 bar of the smaller cases (where the oracle matches a library
+    LU inverse) cannot hold here for any FP64 method.  The bar instead: on
+    the six columns where the GPU and the oracle differ most and on ten
+    random columns, the GPU's selected entries lie within 5x the oracle's own
+    distance from the sparse LU's column (floor 1e-9 of the largest entry);
+    over all entries, GPU and oracle agree to 1e-6 of the largest entry."""
+    _torch()
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as sla
+    from paper_1404_0447_amd import selinv as S
+    from paper_1404_0447_amd import workloads as W
+    from oracle import oracle as O
+    m = W.indefinite_molecular(side=16, dofs=8, seed=8)
+    n = m.n
+    print(f"[pivot] full size n={n}", flush=True)
+    p = S.Plan.from_matrix(m, max_super=128, pivoting=True).bind()
+    sel = _fwd(p, m.vals)
+    cp, ri, pm = p.pattern()
+    del p
+    o = O.symbolic(m, cap=128)
+    assert np.array_equal(cp, o.sym.colptrL) and np.array_equal(ri, o.sym.rowindL)
+    osel, st, _ = o.factor_selinv_pivoted(m.vals)
+    assert st == 0
+    scale = np.max(np.abs(osel))
+    d = np.abs(sel - osel)
+    assert np.max(d) <= 1e-6 * scale
+    cols = np.repeat(np.arange(n), np.diff(m.colptr))
+    A = sp.csc_matrix((m.vals, (m.rowind, cols)), shape=(n, n))
+    lu = sla.splu(sp.csc_matrix(A + sp.tril(A, -1).T))
+    worst = np.argsort(np.maximum.reduceat(d, cp[:-1]))[::-1][:6]
+    rand = np.random.default_rng(0).choice(n, 10, replace=False)
+    for j in list(worst) + list(rand):
+        e = np.zeros(n)
+        e[pm[j]] = 1.0
+        ref = lu.solve(e)[pm[ri[cp[j]:cp[j + 1]]]]
+        g = np.max(np.abs(sel[cp[j]:cp[j + 1]] - ref))
+        od = np.max(np.abs(osel[cp[j]:cp[j + 1]] - ref))
+        assert g <= 5 * max(od, 1e-9 * scale), f"column {j}: GPU {g / scale:.2e}, oracle {od / scale:.2e} from LU"
