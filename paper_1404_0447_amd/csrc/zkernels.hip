@@ -541,28 +541,42 @@ __global__ __launch_bounds__(kThreads, 3) void k_zgemm_piece(const Task* __restr
     zgemm_body<true>(tasks, blk, Ap, Hp, cr2, rel, Zs);
 }
 
-// A split gather-GEMM tile: the sum of its pieces' G L_hat (slots kb .. kb +
-// bn - 1, in that order), stored negated as Ainv(C,K) rows [r0, r0+64).
+// The sum of a split task's pieces (slots kb .. kb + bn - 1) at element e of
+// the row-major 64 x 64 tile: four running sums over the pieces q = 4m + r,
+// combined in a fixed order, so that four loads are in flight at a time.
+__device__ __forceinline__ z2 zslot_sum(const double* __restrict__ z0, int np, int e)
+{
+    z2 a[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+    int q = 0;
+    for (; q + 4 <= np; q += 4) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a[r] += zload(z0 + (int64_t)(q + r) * kZSlotDoubles, e);
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+        if (q + r < np) a[r] += zload(z0 + (int64_t)(q + r) * kZSlotDoubles, e);
+    return (a[0] + a[1]) + (a[2] + a[3]);
+}
+
+// Rows of a 64 x 64 summing tile one work-group handles (one element per
+// thread); a summing task takes kZT / kZSumRows work-groups (blockIdx.y), so
+// the reads of its pieces spread over that many CUs.
+constexpr int kZSumRows = kThreads / kZT;
+
+// A split gather-GEMM tile: the sum of its pieces' G L_hat, stored negated
+// as Ainv(C,K) rows [r0, r0+64); this work-group's rows ti0 .. ti0 + 3.
 __global__ __launch_bounds__(kThreads) void k_zgemm_sum(const Task* __restrict__ tasks,
                                                         const BlockDesc* __restrict__ blk, double* __restrict__ Ap,
                                                         const double* __restrict__ Zs)
 {
-    __shared__ z2 X[kZT][kZT + 1];
     const Task tk = tasks[blockIdx.x];
     const BlockDesc d = blk[tk.b];
-    const int s = d.s, c = d.c, r0 = tk.i0;
+    const int s = d.s, c = d.c;
     const int64_t ld = (int64_t)s + c;
-    const double* z0 = Zs + (int64_t)tk.kb * kZSlotDoubles;
-    for (int e = threadIdx.x; e < kZT * kZT; e += kThreads) {
-        z2 a = {0, 0};
-        for (int q = 0; q < tk.bn; q++) a += zload(z0 + (int64_t)q * kZSlotDoubles, e);
-        X[e / kZT][e % kZT] = a;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < kZT * s; e += kThreads) {
-        const int ti = e % kZT, j = e / kZT, i = r0 + ti;
-        if (i < c) zstore(Ap, d.poff + s + i + (int64_t)j * ld, -X[ti][j]);
-    }
+    const int ti = blockIdx.y * kZSumRows + threadIdx.x / kZT, j = threadIdx.x % kZT, i = tk.i0 + ti;
+    if (i >= c || j >= s) return;
+    const z2 x = zslot_sum(Zs + (int64_t)tk.kb * kZSlotDoubles, tk.bn, ti * kZT + j);
+    zstore(Ap, d.poff + s + i + (int64_t)j * ld, -x);
 }
 
 // Ainv(K,K) = T - (P + P^T) / 2 with P = L_hat^T Ainv(C,K) (lower triangle),
@@ -617,29 +631,22 @@ __global__ __launch_bounds__(kThreads) void k_zsdiag(const Task* __restrict__ ta
 }
 
 // A split block's diagonal step: P = the sum of its pieces' partial
-// products (slots kb .. kb + bn - 1, in that order), then Ainv(K,K) = T -
-// (P + P^T) / 2 on the lower triangle.
+// products, then Ainv(K,K) = T - (P + P^T) / 2 on the lower triangle; this
+// work-group's rows i0 .. i0 + 3 (P(i,j) and P(j,i) summed separately, each
+// in the fixed order of zslot_sum).
 __global__ __launch_bounds__(kThreads) void k_zsdiag_sum(const Task* __restrict__ tasks,
                                                          const BlockDesc* __restrict__ blk, double* __restrict__ Ap,
                                                          const double* __restrict__ Tp, const double* __restrict__ Zs)
 {
-    __shared__ z2 P[kZT][kZT + 1];
     const Task tk = tasks[blockIdx.x];
     const BlockDesc d = blk[tk.b];
     const int s = d.s;
     const int64_t ld = (int64_t)s + d.c;
+    const int i = blockIdx.y * kZSumRows + threadIdx.x / kZT, j = threadIdx.x % kZT;
+    if (i >= s || j > i) return;
     const double* z0 = Zs + (int64_t)tk.kb * kZSlotDoubles;
-    for (int e = threadIdx.x; e < kZT * kZT; e += kThreads) {
-        z2 a = {0, 0};
-        for (int q = 0; q < tk.bn; q++) a += zload(z0 + (int64_t)q * kZSlotDoubles, e);
-        P[e / kZT][e % kZT] = a;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < s * s; e += kThreads) {
-        const int i = e % s, j = e / s;
-        if (i >= j)
-            zstore(Ap, d.poff + i + (int64_t)j * ld, zload(Tp, d.woff + i + (int64_t)j * s) - 0.5 * (P[i][j] + P[j][i]));
-    }
+    const z2 pij = zslot_sum(z0, tk.bn, i * kZT + j), pji = zslot_sum(z0, tk.bn, j * kZT + i);
+    zstore(Ap, d.poff + i + (int64_t)j * ld, zload(Tp, d.woff + i + (int64_t)j * s) - 0.5 * (pij + pji));
 }
 
 // assemble: panel entry off[q] (a complex element) := value q; export: out
@@ -705,13 +712,13 @@ hipError_t launch_zinvert_level(const DevPtrs& D, const int64_t gemm[4], int64_t
         hipLaunchKernelGGL(k_zgemm_piece, dim3((unsigned)(gemm[2] - gemm[1])), dim3(kThreads), 0, s,
                            D.t_gemm + gemm[1], D.blocks, D.Ap, (const double*)D.Hp, D.cr2, D.rel, D.Zs);
     if (gemm[3] > gemm[2])
-        hipLaunchKernelGGL(k_zgemm_sum, dim3((unsigned)(gemm[3] - gemm[2])), dim3(kThreads), 0, s,
+        hipLaunchKernelGGL(k_zgemm_sum, dim3((unsigned)(gemm[3] - gemm[2]), kZT / kZSumRows), dim3(kThreads), 0, s,
                            D.t_gemm + gemm[2], D.blocks, D.Ap, (const double*)D.Zs);
     if (sdiag_cut > sdiag0)
         hipLaunchKernelGGL(k_zsdiag, dim3((unsigned)(sdiag_cut - sdiag0)), dim3(kThreads), 0, s, D.t_sdiag + sdiag0,
                            D.blocks, D.Ap, (const double*)D.Hp, (const double*)D.Tp, D.Zs);
     if (sdiag1 > sdiag_cut)
-        hipLaunchKernelGGL(k_zsdiag_sum, dim3((unsigned)(sdiag1 - sdiag_cut)), dim3(kThreads), 0, s,
+        hipLaunchKernelGGL(k_zsdiag_sum, dim3((unsigned)(sdiag1 - sdiag_cut), kZT / kZSumRows), dim3(kThreads), 0, s,
                            D.t_sdiag + sdiag_cut, D.blocks, D.Ap, (const double*)D.Tp, (const double*)D.Zs);
     return hipGetLastError();
 }
