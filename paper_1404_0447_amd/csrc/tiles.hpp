@@ -16,7 +16,7 @@ constexpr int kZMaxS = 64;       // widest block of the complex path (one 64-wid
 // at least kZSplitRows rows, about kZSplitFill work-groups in all; a piece
 // writes its 64 x 64 complex partial product to a scratch slot of
 // kZSlotDoubles doubles.
-constexpr int kZSplitFill = 512;
+constexpr int kZSplitFill = 2048;
 constexpr int kZSplitRows = 64;
 constexpr size_t kZSlotDoubles = 2 * (size_t)kZMaxS * kZMaxS;
 constexpr size_t kLdsDiagBytes = sizeof(double) * kLdsDiagMax * (kLdsDiagMax + 1);
