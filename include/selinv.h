@@ -455,7 +455,8 @@ selinv_status selinv_measure_peaks(void* d_buf, size_t bytes, double* fp64_mfma_
  * streams, other threads) race.  bad_col: NULL, or the call synchronises s
  * and reports a pivot failure as SELINV_EPIVOT with *bad_col = original
  * column (else -1).  SELINV_ENOMEM when selinv_workspace_size exceeds
- * SELINV_STATIC_SCRATCH_BYTES. */
+ * SELINV_STATIC_SCRATCH_BYTES; SELINV_EINVAL for a plan with complex
+ * values. */
 selinv_status selinv_factor_invert_static(selinv_plan p, const double* d_valsA, double* d_sel, int64_t* bad_col,
                                           hipStream_t s);
 

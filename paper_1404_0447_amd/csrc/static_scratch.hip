@@ -48,6 +48,8 @@ extern "C" selinv_status selinv_factor_invert_static(selinv_plan P, const double
     using namespace selinv;
     if (bad_col) *bad_col = -1;
     if (!P) return set_error(SELINV_EINVAL, "NULL plan");
+    if (P->opts.complex_values)
+        return set_error(SELINV_EINVAL, "the plan holds complex values (selinv_*_complex)");
     if ((P->nnzA > 0 && !d_valsA) || (P->colptrL.back() > 0 && !d_sel)) return set_error(SELINV_EINVAL, "NULL buffer");
     if (P->lay.total > kStaticBytes)
         return set_error(SELINV_ENOMEM, "the plan's workspace (" + std::to_string(P->lay.total) +

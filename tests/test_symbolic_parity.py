@@ -123,6 +123,19 @@ def test_device_calls_need_a_workspace():
     assert st == S.SELINV_ESTATE
 
 
+def test_real_entry_points_refuse_complex_plans():
+    """A complex plan's values and arenas are (re, im) pairs: every real
+    entry point, the allocation-free one included, refuses the plan before
+    it touches a pointer or the device."""
+    m = W.laplacian((4, 4))
+    p = S.Plan.from_matrix(m, complex_values=True)
+    L = S.lib()
+    assert L.selinv_factor_invert_static(p._h, None, None, None, None) == S.SELINV_EINVAL
+    assert b"complex" in L.selinv_last_error()
+    assert L.selinv_factor(p._h, None, None) == S.SELINV_EINVAL
+    assert b"complex" in L.selinv_last_error()
+
+
 @pytest.mark.parametrize("dims,cap", [((16, 16), 128), ((9, 8, 7), 16), ((12, 12, 12), 128)])
 def test_rim_last_parity(dims, cap):
     m = W.laplacian(dims, shift=0.1)
