@@ -304,7 +304,8 @@ selinv_status selinv_kernel_work(selinv_plan p, double* flops, double* bytes);
  * 2 L_hat(C,K) blocks, 3 scratch, 4 T_K blocks; after selinv_backward:
  * 5 the adjoint of the factor panels, 6 that of L_hat, 7 that of T_K.  The layout of
  * each execution block is given by selinv_get_blocks.  *count = number of
- * doubles; d_out (device, may be NULL) receives a copy on stream s. */
+ * doubles (a complex plan: two per entry, (re, im); which = 5..7 is then
+ * SELINV_EINVAL); d_out (device, may be NULL) receives a copy on stream s. */
 selinv_status selinv_get_arena(selinv_plan p, int32_t which, double* d_out, int64_t* count, hipStream_t s);
 
 /* Execution blocks (host copies, nblocks entries each; any may be NULL):

@@ -884,6 +884,11 @@ selinv_status selinv_get_arena(selinv_plan P, int32_t which, double* d_out, int6
         case 7: off = P->lay.tb; n = P->warena; transient = true; break;
         default: return fail(SELINV_EINVAL, "unknown arena");
     }
+    if (P->opts.complex_values) {
+        // (re, im) pairs; a complex plan has no adjoint arenas
+        if (which >= 5) return fail(SELINV_EINVAL, "a complex plan has no adjoint arenas");
+        n *= 2;
+    }
     if (count) *count = n;
     if (!d_out || n == 0) return SELINV_OK;
     if (!P->ws) return fail(SELINV_ESTATE, "no workspace bound");

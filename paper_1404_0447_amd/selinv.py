@@ -497,7 +497,9 @@ class Plan:
         return out
 
     def arena(self, which, stream=None):
-        """Copy of a device arena ("L", "Ainv", "Lhat", "W", "T") as a CUDA tensor."""
+        """Copy of a device arena ("L", "Ainv", "Lhat", "W", "T") as a CUDA
+        tensor of doubles (a complex plan's: (re, im) pairs, for a view as
+        complex128)."""
         import torch
         n = ct.c_int64()
         _check(lib().selinv_get_arena(self._h, ARENAS[which], None, ct.byref(n), None))

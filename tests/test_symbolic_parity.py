@@ -136,6 +136,23 @@ def test_real_entry_points_refuse_complex_plans():
     assert b"complex" in L.selinv_last_error()
 
 
+def test_complex_arenas_count_two_doubles_per_entry():
+    """A complex plan's arenas hold (re, im) pairs: their sizes are twice
+    those of a real plan with the same execution blocks (64 columns at
+    most), and the adjoint arenas, which a complex plan lacks, are refused."""
+    m = W.laplacian((6, 5, 4), shift=0.1)
+    real = S.Plan.from_matrix(m, exec_cap=64)
+    cx = S.Plan.from_matrix(m, complex_values=True)
+    L = S.lib()
+    for which in range(5):
+        a, b = ct.c_int64(-1), ct.c_int64(-1)
+        assert L.selinv_get_arena(real._h, which, None, ct.byref(a), None) == S.SELINV_OK
+        assert L.selinv_get_arena(cx._h, which, None, ct.byref(b), None) == S.SELINV_OK
+        assert b.value == 2 * a.value > 0 or (a.value == 0 and b.value == 0)
+    for which in (5, 6, 7):
+        assert L.selinv_get_arena(cx._h, which, None, None, None) == S.SELINV_EINVAL
+
+
 @pytest.mark.parametrize("dims,cap", [((16, 16), 128), ((9, 8, 7), 16), ((12, 12, 12), 128)])
 def test_rim_last_parity(dims, cap):
     m = W.laplacian(dims, shift=0.1)
