@@ -237,7 +237,8 @@ static void push_sb_groups(const std::vector<int>& small, int op, std::vector<Ta
 // Complex plans (deterministic schedule: every gather-GEMM tile and
 // diagonal-step task contracts over all of C): a level with fewer than
 // kZSplitFill / 2 tasks of one kind cuts each task's contraction into
-// pieces of at least kZSplitRows rows (boundaries on 16-row chunks), about
+// pieces of at least kZSplitRows rows (half that in a level of fewer than
+// kZSplitFewTasks tasks; boundaries on 16-row chunks), about
 // kZSplitFill pieces in all.  A piece (flags bit 5) writes its partial
 // product over its rows of C to scratch slot `pad`; after the pieces, one
 // task per split task (same block and tile origin, bn = pieces, kb = first
@@ -253,12 +254,14 @@ static int64_t zsplit_level(const selinv_plan_s* P, LevelTasks& lt, int l, int64
     mid = cut = (int64_t)t.size();
     if (n <= 0 || n >= kZSplitFill / 2) return 0;
     const int want = (int)((kZSplitFill + n - 1) / n);
+    // levels with very few tasks (a single pole's) take shorter pieces
+    const int rows = n < kZSplitFewTasks ? kZSplitRows / 2 : kZSplitRows;
     std::vector<Task> whole, pieces, sums;
     int64_t slot = 0;
     for (int64_t q = t0; q < (int64_t)t.size(); q++) {
         const Task k = t[q];
         const int c = P->blocks[k.b].c;
-        const int np = std::max(1, std::min(want, c / kZSplitRows));
+        const int np = std::max(1, std::min(want, c / rows));
         if (np == 1) {
             whole.push_back(k);
             continue;

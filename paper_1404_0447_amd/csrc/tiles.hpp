@@ -18,6 +18,10 @@ constexpr int kZMaxS = 64;       // widest block of the complex path (one 64-wid
 // kZSlotDoubles doubles.
 constexpr int kZSplitFill = 2048;
 constexpr int kZSplitRows = 64;
+// levels with fewer tasks than this (those of a single pole) cut pieces of
+// kZSplitRows / 2 rows: one pole 5.85 -> 5.67 ms, while 32-row pieces in the
+// batch's larger levels cost more in sums than they gained
+constexpr int kZSplitFewTasks = 64;
 constexpr size_t kZSlotDoubles = 2 * (size_t)kZMaxS * kZMaxS;
 constexpr size_t kLdsDiagBytes = sizeof(double) * kLdsDiagMax * (kLdsDiagMax + 1);
 constexpr bool kUseSweep = true;  // register Gauss-Jordan sweep for s <= kLdsDiagMax
